@@ -1,0 +1,105 @@
+/*
+ * CPU oracle for GraphGuess (Ramezani, Kandemir, Sivasubramaniam,
+ * "GraphGuess: Approximate Graph Processing System with Adaptive Correction",
+ * arXiv 2104.10039).
+ *
+ * TEST INFRASTRUCTURE ONLY. This is a plain, slow, single-threaded
+ * implementation of the exact and the sampled-plus-corrected vertex-centric
+ * iterations, used to check the GPU library. Only the tests, the smoke check
+ * and the benchmark's CPU-baseline leg may load it. The GPU library never
+ * links, includes or calls anything here, and nothing here comes from it.
+ *
+ * Graph: canonical in-CSR (pull model, Sec. 3.1). Row u holds the in-edges
+ * v -> u; edge id e is the position in the CSR.
+ *
+ * Values: PageRank in binary64; SSSP distances uint32 with INF = 0xFFFFFFFF;
+ * CC labels int32.
+ */
+#ifndef GG_ORACLE_H
+#define GG_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { GGO_PR = 0, GGO_SSSP = 1, GGO_CC = 2, GGO_PPR = 3 };
+/* Correction schemes: EXACT = accurate mode every iteration (the baseline of
+   Sec. 5); SP = sparsified only; SMS = static mode switch; GG = adaptive
+   correction with periodic supersteps (Sec. 3.4, Sec. 5.2). */
+enum { GGO_EXACT = 0, GGO_SP = 1, GGO_SMS = 2, GGO_GG = 3 };
+enum { GGO_STOP_FIXED_ITERS = 0, GGO_STOP_FIXED_POINT = 1 };
+enum { GGO_INFL_PREFIX = 0, GGO_INFL_TOTAL = 1 };
+enum { GGO_MASK_REPLACE = 0, GGO_MASK_UNION = 1 };
+enum { GGO_DANGLING_UNIFORM = 0, GGO_DANGLING_NONE = 1 };
+
+#define GGO_INF_U32 0xFFFFFFFFu
+
+typedef struct {
+  int32_t n;
+  int64_t m;
+  const int32_t* rowptr; /* n+1 */
+  const int32_t* col;    /* m: source of each in-edge */
+  const int32_t* weight; /* m or NULL; SSSP requires it, values in [0, 255] */
+} ggo_csr;
+
+typedef struct {
+  int32_t app;        /* GGO_PR / GGO_SSSP / GGO_CC / GGO_PPR */
+  double damping;     /* PR/PPR d */
+  int32_t iters;      /* T: iterations for PR/PPR and for FIXED_ITERS runs */
+  int32_t max_iters;  /* cap for fixed-point runs */
+  int32_t source;     /* SSSP/PPR source */
+  int32_t dangling;   /* GGO_DANGLING_* */
+} ggo_app_params;
+
+typedef struct {
+  int32_t kind;        /* GGO_EXACT / GGO_SP / GGO_SMS / GGO_GG */
+  int32_t alpha;       /* approximate window */
+  double theta;        /* influence threshold */
+  double sigma;        /* sparsification parameter (sampling ratio) */
+  uint64_t seed;       /* sampling seed */
+  int32_t influence;   /* GGO_INFL_* */
+  int32_t mask_update; /* GGO_MASK_* */
+  int32_t stop;        /* GGO_STOP_* (SSSP/CC) */
+} ggo_policy;
+
+typedef struct {
+  int32_t iter;        /* 1-based index of the iteration just executed */
+  int32_t accurate;    /* 1 if accurate mode */
+  int32_t superstep;   /* 1 if the edge flags were re-selected after it */
+  int64_t edges;       /* edges gathered */
+  int64_t changed;     /* vertices whose value changed */
+  int64_t active_edges;/* active edges after the iteration */
+} ggo_step_info;
+
+typedef struct ggo_run ggo_run;
+
+/* Philox4x64-10 (Salmon et al., SC'11), exposed for tests. */
+void ggo_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+/* The 32-bit sampling draw for edge e at epoch t under seed s. */
+uint32_t ggo_sample_draw(uint64_t seed, uint64_t epoch, int64_t e);
+/* Keep threshold for ratio sigma in [0, 1]: floor(sigma * 2^32 + 1/2). */
+uint64_t ggo_keep_threshold(double sigma);
+
+/* Returns NULL on invalid arguments (message via ggo_last_error). */
+ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy* pol);
+/* Executes one iteration. Returns 1 if executed, 0 if the run had ended. */
+int ggo_step(ggo_run* r, ggo_step_info* info);
+int ggo_done(const ggo_run* r);
+int32_t ggo_iterations(const ggo_run* r);
+int64_t ggo_edges_total(const ggo_run* r);
+/* PR/PPR: double[n]; SSSP: uint32[n]; CC: int32[n]. */
+void ggo_get_values(const ggo_run* r, void* out);
+/* One byte per edge: current active flag. */
+void ggo_get_mask(const ggo_run* r, uint8_t* out);
+/* Per-edge influence computed at the last superstep (PR: the ratio; SSSP:
+   relative improvement, 1 for the first finite candidate, -1 when not
+   assessable; CC: 1/0). */
+void ggo_get_influence(const ggo_run* r, double* out);
+void ggo_end(ggo_run* r);
+const char* ggo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
