@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark: GTEPS and HBM GB/s of exact vs approximate (GraphGuess) PageRank,
+SSSP and CC on one MI355X.
+
+Workload (default): R-MAT scale 22, edge factor 16 (a/b/c/d = .57/.19/.19/.05,
+seeded, self-loops removed, ~67.1M directed edges; the symmetrized graph for
+CC, ~134M arcs). One step runs, for PR, SSSP (int weights in [1, 255], one
+seeded source) and CC: the exact run, then the adaptive-correction run at
+sample ratios 0.1, 0.3, 0.5, 0.7, 0.9 (alpha = 4, theta = 0.05; SSSP/CC run
+the exact run's iteration count). Inputs are resident in HBM before timing;
+sampling and packing are inside the timed region.
+
+value = edges gathered per second over the timed steps (GTEPS, all runs).
+Printed as one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(graphs, source, budget_iters=3):
+    """The CPU oracle, single-threaded, on a bounded sample of the same workload:
+    `budget_iters` exact iterations of PR, SSSP and CC on the same graphs."""
+    import oracle
+    edges = 0
+    t0 = time.perf_counter()
+    for app in ("pr", "sssp", "cc"):
+        g = graphs[app]
+        kw = dict(iters=budget_iters, max_iters=budget_iters, source=source)
+        r = oracle.Run(g, app, "exact", **kw)
+        while r.step() is not None:
+            pass
+        edges += r.edges_total
+        r.close()
+    dt = time.perf_counter() - t0
+    return {"value": edges / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": "%d exact iterations each of PR, SSSP and CC on the benchmark graphs (%.1f s, %d edges)"
+                      % (budget_iters, dt, edges)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--edge-factor", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--sigmas", default="0.1,0.3,0.5,0.7,0.9")
+    ap.add_argument("--alpha", type=int, default=4)
+    ap.add_argument("--theta", type=float, default=0.05)
+    ap.add_argument("--apps", default="pr,sssp,cc")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_2104_10039_amd as P
+    from paper_2104_10039_amd import metrics
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    apps = args.apps.split(",")
+    sigmas = [float(x) for x in args.sigmas.split(",")]
+
+    t = time.perf_counter()
+    gw = gg.rmat(args.scale, args.edge_factor, seed=args.seed, weights=True)
+    graphs = {"pr": gw, "sssp": gw}
+    if "cc" in apps:
+        graphs["cc"] = gg.rmat(args.scale, args.edge_factor, seed=args.seed, symmetrize=True)
+    source = int(gg.pick_sources(gw, 1, args.seed)[0])
+    log("graphs ready in %.1f s: n=%d m=%d (sym m=%d), source %d" % (
+        time.perf_counter() - t, gw.n, gw.m, graphs["cc"].m if "cc" in graphs else 0, source))
+
+    G = {"pr": P.Graph.from_host(gw), "cc": P.Graph.from_host(graphs["cc"]) if "cc" in apps else None}
+    G["sssp"] = G["pr"]
+    torch.cuda.synchronize()
+
+    # Iteration counts of the exact runs (the approximate runs use the same count).
+    iters = {"pr": 20}
+    for app in ("sssp", "cc"):
+        if app in apps:
+            _, st = G[app].exact_run(app, source=source)
+            iters[app] = st.iterations
+    log("exact iteration counts:", iters)
+
+    outs = {}
+
+    def one_step(record):
+        stats = []
+        for app in apps:
+            out, st = G[app].exact_run(app, iters=iters[app], source=source)
+            stats.append((app, "exact", None, st))
+            if record:
+                outs[(app, "exact")] = out.clone()
+            for sg in sigmas:
+                out, st = G[app].approx_run(app, sg, "gg", alpha=args.alpha, theta=args.theta, seed=1,
+                                            iters=iters[app], source=source, stop="fixed_iters")
+                stats.append((app, "gg", sg, st))
+                if record:
+                    outs[(app, sg)] = out.clone()
+        return stats
+
+    for w in range(args.warmup):
+        one_step(record=(w == 0))
+        log("warmup step %d done" % (w + 1))
+    if args.warmup == 0:
+        one_step(record=True)
+
+    for app in apps:
+        G[app].set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_stats = []
+    for k in range(args.steps):
+        all_stats += one_step(record=False)
+        log("timed step %d done" % (k + 1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    edges_total = sum(st.edges_gathered for (_, _, _, st) in all_stats)
+    gteps = edges_total / elapsed / 1e9
+
+    # per-run summaries (device time from the library's events)
+    runs = {}
+    for (app, pol, sg, st) in all_stats:
+        key = "%s_%s" % (app, "exact" if pol == "exact" else "gg%.1f" % sg)
+        d = runs.setdefault(key, {"ms": [], "edges": st.edges_gathered, "iters": st.iterations})
+        d["ms"].append(st.device_ms)
+    m_eff = {"pr": gw.m, "sssp": gw.m, "cc": graphs["cc"].m if "cc" in graphs else 0}
+    summary = {}
+    for key, d in runs.items():
+        app = key.split("_")[0]
+        ms = float(np.mean(d["ms"]))
+        summary[key] = {"ms": round(ms, 3), "gteps_work": round(d["edges"] / ms / 1e6, 2),
+                        "gteps_eff": round(m_eff[app] * iters[app] / ms / 1e6, 2), "iters": d["iters"]}
+    for app in apps:
+        ex = summary["%s_exact" % app]["ms"]
+        exact_h = outs[(app, "exact")].cpu().numpy()
+        for sg in sigmas:
+            key = "%s_gg%.1f" % (app, sg)
+            ap_h = outs[(app, sg)].cpu().numpy()
+            if app == "pr":
+                err = metrics.topk_error(ap_h, exact_h, 1000)
+            elif app == "sssp":
+                err = metrics.stretch_error(ap_h.view(np.uint32), exact_h.view(np.uint32), source)
+            else:
+                err = metrics.label_mismatch(ap_h, exact_h)
+            summary[key]["speedup"] = round(ex / summary[key]["ms"], 3)
+            summary[key]["accuracy"] = round(metrics.accuracy(err), 3)
+
+    # roofline of the dominant kernel (largest total event time in the timed region)
+    best = None
+    for app in apps:
+        for kind in ("gather_exact", "gather_approx", "superstep"):
+            p = G[app].get_profile(kind, app)
+            if p["launches"] and (best is None or p["total_ms"] > best[2]["total_ms"]):
+                best = (app, kind, p)
+    app_b, kind_b, pb = best
+    avg_ms = pb["total_ms"] / pb["launches"]
+    bytes_per_launch = pb["alg_bytes"] / pb["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_gather<%s> (%s)" % (app_b.upper(), kind_b) if kind_b != "superstep"
+                else "k_super<%s>" % app_b.upper(),
+                "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(bytes_per_launch),
+                "launches": pb["launches"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(graphs, source, args.cpu_iters)
+
+    res = {
+        "metric": "GTEPS + HBM GB/s, approx vs exact PageRank/SSSP on 1 MI355X at <=1% error",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/u32",
+        "data": "synthetic",
+        "config": {"workload": "rmat%d_ef%d exact + GG(sigma %s, alpha %d, theta %g) for %s"
+                               % (args.scale, args.edge_factor, args.sigmas, args.alpha, args.theta, args.apps),
+                   "graph": "R-MAT a/b/c/d=.57/.19/.19/.05 seed %d" % args.seed, "n": gw.n, "m": gw.m,
+                   "m_sym": graphs["cc"].m if "cc" in graphs else None, "source": source},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "runs": summary,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,348 @@
+"""MI355X GraphGuess sweep: Python binding of the C ABI in include/gg.h.
+
+This module only marshals arguments: every step of the sweep runs in the HIP
+kernels of libgg.so. PyTorch provides device memory and streams. torch is
+imported before the library is loaded so that the process holds a single HIP
+runtime (torch's).
+
+If libgg.so is missing, loading fails with an error: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgg.so")
+
+APP = {"pr": 0, "sssp": 1, "cc": 2, "ppr": 3}
+POLICY = {"exact": 0, "sp": 1, "sms": 2, "gg": 3}
+STOP = {"fixed_iters": 0, "fixed_point": 1}
+INFLUENCE = {"prefix": 0, "total": 1}
+MASK = {"replace": 0, "union": 1}
+DANGLING = {"uniform": 0, "none": 1}
+CSR_DEVICE_PTRS = 0x1
+CSR_SKIP_VALIDATE = 0x2
+OUT_HOST = 0x1
+INF = 0xFFFFFFFF
+
+STATUS = {0: "GG_OK", -1: "GG_E_INVAL", -2: "GG_E_RANGE", -3: "GG_E_NOMEM", -4: "GG_E_DEVICE",
+          -5: "GG_E_UNSUPPORTED", -6: "GG_E_STATE"}
+
+
+class GGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(code, str(code)), msg))
+        self.code = code
+
+
+class CsrDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class AppParams(ctypes.Structure):
+    _fields_ = [("app", ctypes.c_int32), ("damping", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("source", ctypes.c_int32), ("dangling", ctypes.c_int32)]
+
+
+class Policy(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("alpha", ctypes.c_int32), ("theta", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("influence", ctypes.c_int32), ("mask_update", ctypes.c_int32),
+                ("stop", ctypes.c_int32)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("supersteps", ctypes.c_int32), ("edges_gathered", ctypes.c_int64),
+                ("active_edges", ctypes.c_int64), ("device_ms", ctypes.c_double)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int32), ("accurate", ctypes.c_int32), ("superstep", ctypes.c_int32),
+                ("edges", ctypes.c_int64), ("changed", ctypes.c_int64), ("active_edges", ctypes.c_int64)]
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+                ("edges", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("small_max", ctypes.c_int32), ("small_team", ctypes.c_int32), ("wave_max", ctypes.c_int32),
+                ("hub_chunk", ctypes.c_int32)]
+
+
+# Every symbol the header declares, with its ctypes signature.
+_VP = ctypes.c_void_p
+SIGNATURES = {
+    "gg_version": (ctypes.c_int, []),
+    "gg_last_error": (ctypes.c_char_p, []),
+    "gg_graph_load_csr": (ctypes.c_int, [ctypes.POINTER(CsrDesc), _VP, ctypes.POINTER(_VP)]),
+    "gg_graph_set_stream": (ctypes.c_int, [_VP, _VP]),
+    "gg_graph_free": (None, [_VP]),
+    "gg_exact_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), _VP, ctypes.c_uint32, ctypes.POINTER(RunStats)]),
+    "gg_approx_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_double, ctypes.POINTER(Policy), _VP,
+                                     ctypes.c_uint32, ctypes.POINTER(RunStats)]),
+    "gg_run_begin": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_double, ctypes.POINTER(Policy),
+                                    ctypes.POINTER(_VP)]),
+    "gg_run_step": (ctypes.c_int, [_VP, ctypes.POINTER(StepInfo)]),
+    "gg_run_values": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32]),
+    "gg_run_mask": (ctypes.c_int, [_VP, _VP]),
+    "gg_run_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(RunStats)]),
+    "gg_run_end": (None, [_VP]),
+    "gg_graph_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
+    "gg_graph_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
+    "gg_graph_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "gg_graph_get_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(KernelProfile)]),
+}
+
+PROFILE_KIND = {"gather_exact": 0, "gather_approx": 1, "superstep": 2}
+
+_lib = None
+
+
+def lib():
+    """Load libgg.so (built by __graft_entry__.build() / _build.py). Raises if missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgg.so is not built (%s); run paper_2104_10039_amd/_build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code < 0:
+        raise GGError(code, lib().gg_last_error().decode())
+    return code
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    return x.ctypes.data
+
+
+def _value_dtype(app: str):
+    return {"pr": torch.float32, "ppr": torch.float32, "sssp": torch.int32, "cc": torch.int32}[app]
+
+
+@dataclass
+class Stats:
+    iterations: int
+    supersteps: int
+    edges_gathered: int
+    active_edges: int
+    device_ms: float
+
+
+def _stats(s: RunStats) -> Stats:
+    return Stats(s.iterations, s.supersteps, s.edges_gathered, s.active_edges, s.device_ms)
+
+
+def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform"):
+    return AppParams(APP[app], damping, iters, max_iters, source, DANGLING[dangling])
+
+
+def _policy(policy="gg", alpha=4, theta=0.05, seed=1, influence="prefix", mask_update="replace",
+            stop="fixed_iters"):
+    return Policy(POLICY[policy], alpha, theta, seed, INFLUENCE[influence], MASK[mask_update], STOP[stop])
+
+
+class Graph:
+    """A graph loaded into the library (gg_graph_load_csr).
+
+    rowptr/col/weight may be numpy arrays (copied to the device) or int32
+    device tensors (borrowed: this object keeps them alive).
+    """
+
+    def __init__(self, n, rowptr, col, weight=None, stream=None, validate=True):
+        self._keep = (rowptr, col, weight)
+        dev = isinstance(rowptr, torch.Tensor) and rowptr.is_cuda
+        if dev:
+            for t in (rowptr, col) + ((weight,) if weight is not None else ()):
+                if t.dtype != torch.int32 or not t.is_contiguous():
+                    raise TypeError("device CSR arrays must be contiguous int32 tensors")
+        else:
+            rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            weight = None if weight is None else np.ascontiguousarray(weight, dtype=np.int32)
+            self._keep = (rowptr, col, weight)
+        self.n = int(n)
+        self.m = int(col.shape[0])
+        flags = (CSR_DEVICE_PTRS if dev else 0) | (0 if validate else CSR_SKIP_VALIDATE)
+        desc = CsrDesc(self.n, self.m, _ptr(rowptr), _ptr(col), _ptr(weight), flags)
+        h = ctypes.c_void_p()
+        self._stream = _stream_handle(stream)
+        _check(lib().gg_graph_load_csr(ctypes.byref(desc), self._stream, ctypes.byref(h)))
+        self._h = h
+        self.weighted = weight is not None
+
+    @classmethod
+    def from_host(cls, g, device=True, stream=None, validate=True):
+        """Load a graphgen.Graph-like object (n, rowptr, col, weight)."""
+        if device:
+            dev = torch.device("cuda")
+            rp = torch.from_numpy(np.ascontiguousarray(g.rowptr, dtype=np.int32)).to(dev)
+            cl = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).to(dev)
+            w = None if g.weight is None else torch.from_numpy(np.ascontiguousarray(g.weight, dtype=np.int32)).to(dev)
+            torch.cuda.synchronize()
+            return cls(g.n, rp, cl, w, stream=stream, validate=validate)
+        return cls(g.n, g.rowptr, g.col, g.weight, stream=stream, validate=validate)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gg_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream):
+        self._stream = _stream_handle(stream)
+        _check(lib().gg_graph_set_stream(self._h, self._stream))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().gg_graph_get_tuning(self._h, ctypes.byref(t)))
+        return {"small_max": t.small_max, "small_team": t.small_team, "wave_max": t.wave_max,
+                "hub_chunk": t.hub_chunk}
+
+    def set_tuning(self, small_max=None, small_team=None, wave_max=None, hub_chunk=None):
+        cur = self.get_tuning()
+        t = Tuning(small_max if small_max is not None else cur["small_max"],
+                   small_team if small_team is not None else cur["small_team"],
+                   wave_max if wave_max is not None else cur["wave_max"],
+                   hub_chunk if hub_chunk is not None else cur["hub_chunk"])
+        _check(lib().gg_graph_set_tuning(self._h, ctypes.byref(t)))
+
+    def set_profiling(self, enable=True):
+        _check(lib().gg_graph_set_profiling(self._h, 1 if enable else 0))
+
+    def get_profile(self, kind, app) -> dict:
+        p = KernelProfile()
+        _check(lib().gg_graph_get_profile(self._h, PROFILE_KIND[kind], APP[app], ctypes.byref(p)))
+        return {"launches": p.launches, "total_ms": p.total_ms, "alg_bytes": p.alg_bytes, "edges": p.edges}
+
+    def _out(self, app, out):
+        if out is None:
+            out = torch.empty(self.n, dtype=_value_dtype(app), device="cuda")
+        return out
+
+    def exact_run(self, app, out=None, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform"):
+        """gg_exact_run: returns (values tensor on the device, Stats)."""
+        out = self._out(app, out)
+        p = _app_params(app, damping, iters, max_iters, source, dangling)
+        st = RunStats()
+        _check(lib().gg_exact_run(self._h, ctypes.byref(p), out.data_ptr(), 0, ctypes.byref(st)))
+        return out, _stats(st)
+
+    def approx_run(self, app, sample_ratio, policy="gg", out=None, alpha=4, theta=0.05, seed=1,
+                   influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
+                   max_iters=1 << 20, source=0, dangling="uniform"):
+        """gg_approx_run: returns (values tensor on the device, Stats)."""
+        out = self._out(app, out)
+        p = _app_params(app, damping, iters, max_iters, source, dangling)
+        pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop)
+        st = RunStats()
+        _check(lib().gg_approx_run(self._h, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
+                                   out.data_ptr(), 0, ctypes.byref(st)))
+        return out, _stats(st)
+
+    def begin(self, app, sample_ratio=1.0, policy="exact", **kw) -> "Run":
+        return Run(self, app, sample_ratio, policy, **kw)
+
+
+class Run:
+    """Step API (gg_run_begin / gg_run_step / gg_run_values / gg_run_mask / gg_run_end)."""
+
+    def __init__(self, graph: Graph, app, sample_ratio=1.0, policy="exact", alpha=4, theta=0.05, seed=1,
+                 influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
+                 max_iters=1 << 20, source=0, dangling="uniform"):
+        self.graph = graph
+        self.app = app
+        p = _app_params(app, damping, iters, max_iters, source, dangling)
+        pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop)
+        h = ctypes.c_void_p()
+        _check(lib().gg_run_begin(graph.handle, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
+                                  ctypes.byref(h)))
+        self._h = h
+
+    def step(self) -> Optional[dict]:
+        info = StepInfo()
+        r = _check(lib().gg_run_step(self._h, ctypes.byref(info)))
+        if r == 0:
+            return None
+        return {"iter": info.iter, "accurate": bool(info.accurate), "superstep": bool(info.superstep),
+                "edges": info.edges, "changed": info.changed, "active_edges": info.active_edges}
+
+    def values(self, host=True):
+        dt = {"pr": np.float32, "ppr": np.float32, "sssp": np.uint32, "cc": np.int32}[self.app]
+        if host:
+            out = np.empty(max(self.graph.n, 1), dtype=dt)
+            _check(lib().gg_run_values(self._h, out.ctypes.data, OUT_HOST))
+            return out[: self.graph.n]
+        out = torch.empty(self.graph.n, dtype=_value_dtype(self.app), device="cuda")
+        _check(lib().gg_run_values(self._h, out.data_ptr(), 0))
+        return out
+
+    def mask_bits(self) -> np.ndarray:
+        nw = (self.graph.m + 31) // 32
+        out = np.zeros(max(nw, 1), dtype=np.uint32)
+        _check(lib().gg_run_mask(self._h, out.ctypes.data))
+        return out[:nw]
+
+    def mask(self) -> np.ndarray:
+        """Per-edge flags as uint8[m]."""
+        bits = self.mask_bits()
+        b = np.unpackbits(bits.view(np.uint8), bitorder="little")
+        return b[: self.graph.m].astype(np.uint8)
+
+    def stats(self) -> Stats:
+        st = RunStats()
+        _check(lib().gg_run_stats_get(self._h, ctypes.byref(st)))
+        return _stats(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gg_run_end(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

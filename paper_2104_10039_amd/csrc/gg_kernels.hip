@@ -1,0 +1,1113 @@
+// Device kernels of the GraphGuess sweep for CDNA4 (gfx950, wave64).
+//
+// The sweep is the pull-based vertex program of the paper [Sec. 3.1, Alg. 2]:
+// for every destination row, gather over its in-edges (all of them in
+// accurate mode, only the active ones in approximate mode [Sec. 3.3]), then
+// apply. A superstep is an accurate iteration that also computes each edge's
+// influence and re-selects the active edges against theta [Sec. 3.4].
+//
+// Work distribution is degree-binned: rows with few edges are handled by
+// teams of 4..32 lanes, medium rows by one wavefront, long rows by 256-thread
+// workgroups over fixed-size edge chunks whose partial results are combined
+// in a fixed order. Every reduction has a fixed shape, so results are
+// bitwise reproducible for a fixed tuning.
+//
+// The active edges of a row are kept packed at the front of the row's own
+// slot [rowptr[u], rowptr[u+1]) of a second edge array, with a per-row count;
+// the approximate gather streams only that prefix. A bitmap holds the flag of
+// every edge (bit e mod 32 of word e/32).
+#include "gg_internal.h"
+
+namespace ggk {
+
+// ---------------------------------------------------------------------------
+// Wavefront / team primitives
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t ld_stream(const uint32_t* p) { return __builtin_nontemporal_load(p); }
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor_t(T x, int m, int w) {
+  return __shfl_xor(x, m, w);
+}
+
+template <int TEAM>
+__device__ __forceinline__ double team_sum(double x) {
+#pragma unroll
+  for (int o = TEAM / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, TEAM);
+  return x;
+}
+
+template <int TEAM>
+__device__ __forceinline__ uint32_t team_min(uint32_t x) {
+#pragma unroll
+  for (int o = TEAM / 2; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o, TEAM));
+  return x;
+}
+
+// Inclusive scans inside a team of TEAM lanes (lt = lane index in the team).
+template <int TEAM>
+__device__ __forceinline__ double team_scan_add(double x, int lt) {
+#pragma unroll
+  for (int d = 1; d < TEAM; d <<= 1) {
+    double y = __shfl_up(x, d, TEAM);
+    if (lt >= d) x += y;
+  }
+  return x;
+}
+
+template <int TEAM>
+__device__ __forceinline__ uint32_t team_scan_min(uint32_t x, int lt) {
+#pragma unroll
+  for (int d = 1; d < TEAM; d <<= 1) {
+    uint32_t y = (uint32_t)__shfl_up((int)x, d, TEAM);
+    if (lt >= d) x = min(x, y);
+  }
+  return x;
+}
+
+// Per-app gather element, identity and combine.
+template <int APP>
+struct Tr;
+
+template <>
+struct Tr<kPR> {
+  using T = double;
+  static __device__ __forceinline__ T id() { return 0.0; }
+  static __device__ __forceinline__ T op(T a, T b) { return a + b; }
+  static __device__ __forceinline__ T elem(const Sweep& s, uint32_t e) { return (double)s.c_in[e]; }
+};
+template <>
+struct Tr<kPPR> : Tr<kPR> {};
+template <>
+struct Tr<kSSSP> {
+  using T = uint32_t;
+  static __device__ __forceinline__ T id() { return kInf; }
+  static __device__ __forceinline__ T op(T a, T b) { return min(a, b); }
+  // packed edge: source in the low 24 bits, weight in the high 8 bits
+  static __device__ __forceinline__ T elem(const Sweep& s, uint32_t e) {
+    uint32_t xv = s.x_in[e & 0xFFFFFFu];
+    return xv == kInf ? kInf : xv + (e >> 24);
+  }
+};
+template <>
+struct Tr<kCC> {
+  using T = uint32_t;
+  static __device__ __forceinline__ T id() { return kInf; }
+  static __device__ __forceinline__ T op(T a, T b) { return min(a, b); }
+  static __device__ __forceinline__ T elem(const Sweep& s, uint32_t e) { return s.x_in[e]; }
+};
+
+template <int TEAM>
+__device__ __forceinline__ double team_reduce(double x) { return team_sum<TEAM>(x); }
+template <int TEAM>
+__device__ __forceinline__ uint32_t team_reduce(uint32_t x) { return team_min<TEAM>(x); }
+
+// Block (256 threads = 4 waves) reductions in a fixed order; result valid in
+// every thread. lds must hold 4 elements.
+template <int APP>
+__device__ __forceinline__ typename Tr<APP>::T block_reduce(typename Tr<APP>::T x, typename Tr<APP>::T* lds) {
+  using T = typename Tr<APP>::T;
+  x = team_reduce<64>(x);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[wid] = x;
+  __syncthreads();
+  T r = Tr<APP>::op(Tr<APP>::op(lds[0], lds[1]), Tr<APP>::op(lds[2], lds[3]));
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int block_sum_int(int x, int* lds) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[wid] = x;
+  __syncthreads();
+  int r = lds[0] + lds[1] + lds[2] + lds[3];
+  __syncthreads();
+  return r;
+}
+
+// Exclusive rank of this thread among the block's threads with pred set.
+__device__ __forceinline__ int block_rank(bool pred, int* lds, int& total) {
+  const uint64_t bal = __ballot(pred);
+  const int lane = __lane_id();
+  const int wid = threadIdx.x >> 6;
+  const int r = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) lds[wid] = __popcll(bal);
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int c = lds[w];
+    off += (w < wid) ? c : 0;
+    tot += c;
+  }
+  __syncthreads();
+  total = tot;
+  return off + r;
+}
+
+__device__ __forceinline__ int row_len(const Sweep& s, int u, int b) {
+  return s.cnt ? s.cnt[u] : s.rowptr[u + 1] - b;
+}
+
+// Index of the hub row that owns chunk ch: the last h with hub_start[h] <= ch.
+__device__ __forceinline__ int find_hub(const int32_t* hub_start, int n_hub, int ch) {
+  int lo = 0, hi = n_hub - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (hub_start[mid] <= ch) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Apply [Alg. 2, GG-Apply]
+// ---------------------------------------------------------------------------
+
+template <int APP>
+__device__ __forceinline__ void apply(const Sweep& s, int u, typename Tr<APP>::T acc, int& nchanged) {
+  if constexpr (APP == kPR || APP == kPPR) {
+    const double D = *s.dangling;
+    double x;
+    if constexpr (APP == kPR) {
+      x = s.base + s.damping * (acc + D / (double)s.n);
+    } else {
+      const bool src = (u == s.source);
+      x = (src ? (1.0 - s.damping) : 0.0) + s.damping * (acc + (src ? D : 0.0));
+    }
+    const int od = s.outdeg[u];
+    s.c_out[u] = od > 0 ? (float)(x / (double)od) : (float)x;
+    if (s.x_out) s.x_out[u] = (float)x;
+  } else {
+    const uint32_t old = s.x_in[u];
+    const uint32_t nv = min(old, acc);
+    s.x_next[u] = nv;
+    nchanged += (nv != old);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plain gather-apply (exact and approximate iterations)
+// ---------------------------------------------------------------------------
+
+template <int APP, int TEAM>
+__device__ __forceinline__ void gather_team_rows(const Sweep& s, const int32_t* list, int count, int blk, int nblk,
+                                                 int& nchanged) {
+  using R = Tr<APP>;
+  using T = typename R::T;
+  const int lt = threadIdx.x & (TEAM - 1);
+  constexpr int TPB = kBlock / TEAM;
+  const int stride = nblk * TPB;
+  for (int t = blk * TPB + (int)threadIdx.x / TEAM; t < count; t += stride) {
+    const int u = list[t];
+    const int b = s.rowptr[u];
+    const int len = row_len(s, u, b);
+    const uint32_t* ed = s.edges + b;
+    T acc = R::id();
+    int k = lt;
+    for (; k + 3 * TEAM < len; k += 4 * TEAM) {
+      const uint32_t e0 = ld_stream(ed + k), e1 = ld_stream(ed + k + TEAM);
+      const uint32_t e2 = ld_stream(ed + k + 2 * TEAM), e3 = ld_stream(ed + k + 3 * TEAM);
+      const T v0 = R::elem(s, e0), v1 = R::elem(s, e1), v2 = R::elem(s, e2), v3 = R::elem(s, e3);
+      acc = R::op(acc, R::op(R::op(v0, v1), R::op(v2, v3)));
+    }
+    for (; k < len; k += TEAM) acc = R::op(acc, R::elem(s, ld_stream(ed + k)));
+    acc = team_reduce<TEAM>(acc);
+    if (lt == 0) apply<APP>(s, u, acc, nchanged);
+  }
+}
+
+// One 256-thread block reduces one chunk of a hub row. Rows with a single
+// chunk are applied directly; otherwise the partial goes to part[ch].
+template <int APP>
+__device__ __forceinline__ void gather_hub_chunk(const Sweep& s, int ch, bool always_partial, int& nchanged,
+                                                 typename Tr<APP>::T* lds) {
+  using R = Tr<APP>;
+  using T = typename R::T;
+  const int h = find_hub(s.hub_start, s.n_hub, ch);
+  const int u = s.list[s.n_small + s.n_wave + h];
+  const int j = ch - s.hub_start[h];
+  const int nch = s.hub_start[h + 1] - s.hub_start[h];
+  const int b = s.rowptr[u];
+  const int len = row_len(s, u, b);
+  const int e0 = j * s.hub_chunk;
+  const int e1 = min(len, e0 + s.hub_chunk);
+  const uint32_t* ed = s.edges + b;
+  T acc = R::id();
+  int k = e0 + (int)threadIdx.x;
+  for (; k + 3 * kBlock < e1; k += 4 * kBlock) {
+    const uint32_t a0 = ld_stream(ed + k), a1 = ld_stream(ed + k + kBlock);
+    const uint32_t a2 = ld_stream(ed + k + 2 * kBlock), a3 = ld_stream(ed + k + 3 * kBlock);
+    const T v0 = R::elem(s, a0), v1 = R::elem(s, a1), v2 = R::elem(s, a2), v3 = R::elem(s, a3);
+    acc = R::op(acc, R::op(R::op(v0, v1), R::op(v2, v3)));
+  }
+  for (; k < e1; k += kBlock) acc = R::op(acc, R::elem(s, ld_stream(ed + k)));
+  acc = block_reduce<APP>(acc, lds);
+  if (threadIdx.x == 0) {
+    if (nch == 1 && !always_partial) {
+      apply<APP>(s, u, acc, nchanged);
+    } else {
+      if constexpr (APP == kPR || APP == kPPR) s.part_f[ch] = acc;
+      else s.part_u[ch] = acc;
+    }
+  }
+}
+
+template <int APP>
+__device__ __forceinline__ void flush_changed(const Sweep& s, int nchanged, int* ilds) {
+  if constexpr (APP == kSSSP || APP == kCC) {
+    const int tot = block_sum_int(nchanged, ilds);
+    if (threadIdx.x == 0 && tot) atomicAdd(s.changed, tot);
+  }
+}
+
+// Blocks [0, gs): small rows; [gs, gs+gw): wavefront rows; the rest: one hub
+// chunk each.
+template <int APP, int TEAM>
+__global__ __launch_bounds__(kBlock) void k_gather(Sweep s, int gs, int gw) {
+  __shared__ typename Tr<APP>::T lds[4];
+  __shared__ int ilds[4];
+  int nchanged = 0;
+  const int bid = blockIdx.x;
+  if (bid < gs) {
+    gather_team_rows<APP, TEAM>(s, s.list, s.n_small, bid, gs, nchanged);
+  } else if (bid < gs + gw) {
+    gather_team_rows<APP, 64>(s, s.list + s.n_small, s.n_wave, bid - gs, gw, nchanged);
+  } else {
+    gather_hub_chunk<APP>(s, bid - gs - gw, false, nchanged, lds);
+  }
+  flush_changed<APP>(s, nchanged, ilds);
+}
+
+// Combine the chunk partials of multi-chunk hub rows in chunk order.
+template <int APP>
+__global__ __launch_bounds__(kBlock) void k_hub_combine(Sweep s) {
+  using R = Tr<APP>;
+  __shared__ int ilds[4];
+  int nchanged = 0;
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  if (h < s.n_hub) {
+    const int c0 = s.hub_start[h], nch = s.hub_start[h + 1] - c0;
+    if (nch > 1) {
+      typename R::T acc = R::id();
+      for (int j = 0; j < nch; ++j) {
+        if constexpr (APP == kPR || APP == kPPR) acc = R::op(acc, s.part_f[c0 + j]);
+        else acc = R::op(acc, s.part_u[c0 + j]);
+      }
+      apply<APP>(s, s.list[s.n_small + s.n_wave + h], acc, nchanged);
+    }
+  }
+  flush_changed<APP>(s, nchanged, ilds);
+}
+
+// ---------------------------------------------------------------------------
+// Superstep: accurate gather-apply + influence + GG-EStatus + repack
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t edge_bit(const uint32_t* bits, int e) { return (bits[e >> 5] >> (e & 31)) & 1u; }
+
+// Flag of one edge given the exclusive prefix (running value before it).
+// PR: influence = c / P with P the inclusive running sum. SSSP: relative
+// improvement of the running minimum; unreached sources keep their flag.
+// CC: the source label lowers the running minimum.
+template <int APP>
+struct Decide;
+
+template <>
+struct Decide<kPR> {
+  static __device__ __forceinline__ bool f(const Sweep& s, bool valid, double c, double P, uint32_t oldf) {
+    bool flag = valid && P > 0.0 && (c / P > s.theta);
+    return flag || (s.mask_union && oldf);
+  }
+};
+
+// Set the new flag bits of TEAM consecutive edges (edge e at team lane lt).
+template <int TEAM>
+__device__ __forceinline__ void write_bits(uint32_t* bits, uint64_t tm, int lt, int e, int remaining, bool valid) {
+  if (valid && (lt == 0 || (e & 31) == 0)) {
+    const int off = e & 31;
+    const int nb = min(32 - off, min(TEAM - lt, remaining));
+    const uint64_t sel = (tm >> lt) & ((1ull << nb) - 1ull);
+    const uint32_t word = (uint32_t)(sel << off);
+    if (word) atomicOr(&bits[e >> 5], word);
+  }
+}
+
+template <int APP, int TEAM>
+__device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* list, int count, int blk, int nblk,
+                                                int& nchanged) {
+  using R = Tr<APP>;
+  using T = typename R::T;
+  const int lt = threadIdx.x & (TEAM - 1);
+  const int lane = __lane_id();
+  const int team_base = lane & ~(TEAM - 1);
+  constexpr int TPB = kBlock / TEAM;
+  const int stride = nblk * TPB;
+  for (int t = blk * TPB + (int)threadIdx.x / TEAM; t < count; t += stride) {
+    const int u = list[t];
+    const int b = s.rowptr[u];
+    const int len = s.rowptr[u + 1] - b;
+    T carry = R::id();
+    int carry_cnt = 0;
+    for (int k0 = 0; k0 < len; k0 += TEAM) {
+      const int k = k0 + lt;
+      const bool valid = k < len;
+      const int e = b + k;
+      const uint32_t ev = valid ? ld_stream(s.edges + e) : 0u;
+      const uint32_t oldf = (valid && s.old_bits) ? edge_bit(s.old_bits, e) : 0u;
+      bool flag;
+      T chunk_total;
+      if constexpr (APP == kPR || APP == kPPR) {
+        const double c = valid ? (double)s.c_in[ev] : 0.0;
+        const double incl = team_scan_add<TEAM>(c, lt);
+        const double P = carry + incl;
+        flag = Decide<kPR>::f(s, valid, c, P, oldf);
+        chunk_total = __shfl(incl, TEAM - 1, TEAM);
+      } else if constexpr (APP == kSSSP) {
+        const uint32_t xv = valid ? s.x_in[ev & 0xFFFFFFu] : kInf;
+        const uint32_t cand = xv == kInf ? kInf : xv + (ev >> 24);
+        const uint32_t incl = team_scan_min<TEAM>(cand, lt);
+        uint32_t excl = (uint32_t)__shfl_up((int)incl, 1, TEAM);
+        if (lt == 0) excl = kInf;
+        const uint32_t rp = min(carry, excl);
+        const uint32_t nw = min(rp, cand);
+        const bool dec = (rp == kInf) || ((((uint64_t)(rp - nw)) << 16) > s.theta_q * (uint64_t)rp);
+        if (valid && xv != kInf) flag = dec || (s.mask_union && oldf);
+        else flag = oldf != 0u;
+        chunk_total = __shfl(incl, TEAM - 1, TEAM);
+      } else {  // CC
+        const uint32_t xv = valid ? s.x_in[ev] : kInf;
+        const uint32_t incl = team_scan_min<TEAM>(xv, lt);
+        uint32_t excl = (uint32_t)__shfl_up((int)incl, 1, TEAM);
+        if (lt == 0) excl = kInf;
+        const uint32_t rp = min(carry, excl);
+        flag = (valid && xv < rp) || (s.mask_union && oldf);
+        chunk_total = __shfl(incl, TEAM - 1, TEAM);
+      }
+      flag = flag && valid;
+      const uint64_t bal = __ballot(flag);
+      const uint64_t tm = TEAM == 64 ? bal : ((bal >> team_base) & ((1ull << (TEAM & 63)) - 1ull));
+      const int rank = __popcll(tm & ((1ull << lt) - 1ull));
+      if (flag) s.act_edges[b + carry_cnt + rank] = ev;
+      write_bits<TEAM>(s.new_bits, tm, lt, e, len - k, valid);
+      carry_cnt += __popcll(tm);
+      carry = R::op(carry, chunk_total);
+    }
+    if (lt == 0) {
+      apply<APP>(s, u, carry, nchanged);
+      s.act_cnt[u] = carry_cnt;
+    }
+  }
+}
+
+// Hub chunk of a superstep: prefix carried from the chunk totals computed
+// beforehand (part_f / part_u), flags and bits for the chunk, active count
+// to part_cnt[ch]. Chunk 0 applies the row with the total of all chunks.
+template <int APP>
+__device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nchanged, typename Tr<APP>::T* lds,
+                                                int* ilds) {
+  using R = Tr<APP>;
+  using T = typename R::T;
+  const int h = find_hub(s.hub_start, s.n_hub, ch);
+  const int u = s.list[s.n_small + s.n_wave + h];
+  const int c0 = s.hub_start[h];
+  const int j = ch - c0;
+  const int nch = s.hub_start[h + 1] - c0;
+  const int b = s.rowptr[u];
+  const int len = s.rowptr[u + 1] - b;
+  const int e0 = j * s.hub_chunk;
+  const int e1 = min(len, e0 + s.hub_chunk);
+  const int lane = __lane_id();
+  const int wid = threadIdx.x >> 6;
+
+  auto part = [&](int i) -> T {
+    if constexpr (APP == kPR || APP == kPPR) return s.part_f[i];
+    else return s.part_u[i];
+  };
+  T carry = R::id();
+  for (int i = 0; i < j; ++i) carry = R::op(carry, part(c0 + i));
+  int cnt = 0;
+  for (int sub = e0; sub < e1; sub += kBlock) {
+    const int k = sub + (int)threadIdx.x;
+    const bool valid = k < e1;
+    const int e = b + k;
+    const uint32_t ev = valid ? ld_stream(s.edges + e) : 0u;
+    const uint32_t oldf = (valid && s.old_bits) ? edge_bit(s.old_bits, e) : 0u;
+    bool flag;
+    T sub_total;
+    if constexpr (APP == kPR || APP == kPPR) {
+      const double c = valid ? (double)s.c_in[ev] : 0.0;
+      const double incl_w = team_scan_add<64>(c, lane);
+      if (lane == 63) lds[wid] = incl_w;
+      __syncthreads();
+      double before = 0.0;
+      for (int w = 0; w < wid; ++w) before += lds[w];
+      sub_total = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+      __syncthreads();
+      const double P = carry + (before + incl_w);
+      flag = Decide<kPR>::f(s, valid, c, P, oldf);
+    } else {
+      uint32_t val;
+      if constexpr (APP == kSSSP) {
+        const uint32_t xv = valid ? s.x_in[ev & 0xFFFFFFu] : kInf;
+        val = xv == kInf ? kInf : xv + (ev >> 24);
+      } else {
+        val = valid ? s.x_in[ev] : kInf;
+      }
+      const uint32_t incl_w = team_scan_min<64>(val, lane);
+      uint32_t excl_w = (uint32_t)__shfl_up((int)incl_w, 1, 64);
+      if (lane == 0) excl_w = kInf;
+      if (lane == 63) lds[wid] = incl_w;
+      __syncthreads();
+      uint32_t before = kInf;
+      for (int w = 0; w < wid; ++w) before = min(before, lds[w]);
+      sub_total = min(min(lds[0], lds[1]), min(lds[2], lds[3]));
+      __syncthreads();
+      const uint32_t rp = min(carry, min(before, excl_w));
+      if constexpr (APP == kSSSP) {
+        const uint32_t nw = min(rp, val);
+        const bool dec = (rp == kInf) || ((((uint64_t)(rp - nw)) << 16) > s.theta_q * (uint64_t)rp);
+        if (valid && val != kInf) flag = dec || (s.mask_union && oldf);
+        else flag = oldf != 0u;
+      } else {
+        flag = (valid && val < rp) || (s.mask_union && oldf);
+      }
+    }
+    flag = flag && valid;
+    const uint64_t bal = __ballot(flag);
+    write_bits<64>(s.new_bits, bal, lane, e, e1 - (sub + wid * 64) - lane, valid);
+    cnt += __popcll(bal);
+    carry = R::op(carry, sub_total);
+  }
+  // cnt is per wave; sum over the block
+  const int tot = block_sum_int((lane == 0) ? cnt : 0, ilds);
+  if (threadIdx.x == 0) {
+    s.part_cnt[ch] = tot;
+    if (j == 0) {
+      T all = R::id();
+      for (int i = 0; i < nch; ++i) all = R::op(all, part(c0 + i));
+      apply<APP>(s, u, all, nchanged);
+    }
+  }
+}
+
+template <int APP, int TEAM>
+__global__ __launch_bounds__(kBlock) void k_super(Sweep s, int gs, int gw) {
+  __shared__ typename Tr<APP>::T lds[4];
+  __shared__ int ilds[4];
+  int nchanged = 0;
+  const int bid = blockIdx.x;
+  if (bid < gs) {
+    super_team_rows<APP, TEAM>(s, s.list, s.n_small, bid, gs, nchanged);
+  } else if (bid < gs + gw) {
+    super_team_rows<APP, 64>(s, s.list + s.n_small, s.n_wave, bid - gs, gw, nchanged);
+  } else {
+    super_hub_chunk<APP>(s, bid - gs - gw, nchanged, lds, ilds);
+  }
+  flush_changed<APP>(s, nchanged, ilds);
+}
+
+// Chunk totals of hub rows before a superstep.
+template <int APP>
+__global__ __launch_bounds__(kBlock) void k_hub_totals(Sweep s) {
+  __shared__ typename Tr<APP>::T lds[4];
+  int dummy = 0;
+  gather_hub_chunk<APP>(s, blockIdx.x, true, dummy, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Packing of flagged edges (after the initial sampling, and the hub part of
+// a superstep)
+// ---------------------------------------------------------------------------
+
+template <int TEAM>
+__device__ __forceinline__ void pack_team_rows(const Sweep& s, const uint32_t* bits, const int32_t* list, int count,
+                                               int blk, int nblk) {
+  const int lt = threadIdx.x & (TEAM - 1);
+  const int lane = __lane_id();
+  const int team_base = lane & ~(TEAM - 1);
+  constexpr int TPB = kBlock / TEAM;
+  const int stride = nblk * TPB;
+  for (int t = blk * TPB + (int)threadIdx.x / TEAM; t < count; t += stride) {
+    const int u = list[t];
+    const int b = s.rowptr[u];
+    const int len = s.rowptr[u + 1] - b;
+    int carry_cnt = 0;
+    for (int k0 = 0; k0 < len; k0 += TEAM) {
+      const int k = k0 + lt;
+      const bool valid = k < len;
+      const int e = b + k;
+      const bool flag = valid && edge_bit(bits, e);
+      const uint64_t bal = __ballot(flag);
+      const uint64_t tm = TEAM == 64 ? bal : ((bal >> team_base) & ((1ull << (TEAM & 63)) - 1ull));
+      const int rank = __popcll(tm & ((1ull << lt) - 1ull));
+      if (flag) s.act_edges[b + carry_cnt + rank] = s.edges[e];
+      carry_cnt += __popcll(tm);
+    }
+    if (lt == 0) s.act_cnt[u] = carry_cnt;
+  }
+}
+
+// Count of flagged edges per hub chunk.
+__device__ __forceinline__ void hub_chunk_count(const Sweep& s, const uint32_t* bits, int ch, int* ilds) {
+  const int h = find_hub(s.hub_start, s.n_hub, ch);
+  const int u = s.list[s.n_small + s.n_wave + h];
+  const int j = ch - s.hub_start[h];
+  const int b = s.rowptr[u];
+  const int len = s.rowptr[u + 1] - b;
+  const int e0 = j * s.hub_chunk;
+  const int e1 = min(len, e0 + s.hub_chunk);
+  int c = 0;
+  for (int k = e0 + (int)threadIdx.x; k < e1; k += kBlock) c += (int)edge_bit(bits, b + k);
+  const int tot = block_sum_int(c, ilds);
+  if (threadIdx.x == 0) s.part_cnt[ch] = tot;
+}
+
+template <int TEAM>
+__global__ __launch_bounds__(kBlock) void k_pack(Sweep s, int gs, int gw) {
+  __shared__ int ilds[4];
+  const int bid = blockIdx.x;
+  if (bid < gs) {
+    pack_team_rows<TEAM>(s, s.old_bits, s.list, s.n_small, bid, gs);
+  } else if (bid < gs + gw) {
+    pack_team_rows<64>(s, s.old_bits, s.list + s.n_small, s.n_wave, bid - gs, gw);
+  } else {
+    hub_chunk_count(s, s.old_bits, bid - gs - gw, ilds);
+  }
+}
+
+// Write the flagged edges of one hub chunk at its rank inside the row; chunk
+// 0 writes the row's active count.
+__global__ __launch_bounds__(kBlock) void k_hub_pack(Sweep s, const uint32_t* bits) {
+  __shared__ int ilds[4];
+  const int ch = blockIdx.x;
+  const int h = find_hub(s.hub_start, s.n_hub, ch);
+  const int u = s.list[s.n_small + s.n_wave + h];
+  const int c0 = s.hub_start[h];
+  const int j = ch - c0;
+  const int nch = s.hub_start[h + 1] - c0;
+  const int b = s.rowptr[u];
+  const int len = s.rowptr[u + 1] - b;
+  const int e0 = j * s.hub_chunk;
+  const int e1 = min(len, e0 + s.hub_chunk);
+  int carry = 0;
+  for (int i = 0; i < j; ++i) carry += s.part_cnt[c0 + i];
+  for (int sub = e0; sub < e1; sub += kBlock) {
+    const int k = sub + (int)threadIdx.x;
+    const bool valid = k < e1;
+    const bool flag = valid && edge_bit(bits, b + k);
+    int tot;
+    const int rank = block_rank(flag, ilds, tot);
+    if (flag) s.act_edges[b + carry + rank] = s.edges[b + k];
+    carry += tot;
+  }
+  if (j == 0 && threadIdx.x == 0) {
+    int all = 0;
+    for (int i = 0; i < nch; ++i) all += s.part_cnt[c0 + i];
+    s.act_cnt[u] = all;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Degree binning (stable: every list keeps vertex order)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int bin_of(int len, int small_max, int wave_max) {
+  return len <= small_max ? 0 : (len <= wave_max ? 1 : 2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* rowptr, const int32_t* cnt, int n, int small_max,
+                                                      int wave_max, int32_t* blk, int64_t* blk_edges, int nblk) {
+  __shared__ int ilds[4];
+  __shared__ long long elds[4];
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  int len = 0, bin = -1;
+  if (u < n) {
+    len = cnt ? cnt[u] : rowptr[u + 1] - rowptr[u];
+    bin = bin_of(len, small_max, wave_max);
+  }
+  for (int q = 0; q < 3; ++q) {
+    int tot;
+    block_rank(bin == q, ilds, tot);
+    if (threadIdx.x == 0) blk[q * nblk + blockIdx.x] = tot;
+  }
+  long long e = len;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+  if ((threadIdx.x & 63) == 0) elds[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) blk_edges[blockIdx.x] = elds[0] + elds[1] + elds[2] + elds[3];
+}
+
+// Exclusive scan of a[0..count) in place by one 1024-thread block; returns
+// the total through *total.
+__device__ void block1024_exclusive_scan(int32_t* a, int count, int32_t* total) {
+  __shared__ int wsum[16];
+  __shared__ int carry_s;
+  const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+  if (tid == 0) carry_s = 0;
+  __syncthreads();
+  for (int base = 0; base < count; base += 1024) {
+    const int i = base + tid;
+    const int v = i < count ? a[i] : 0;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    int before = 0, tile = 0;
+    for (int w = 0; w < 16; ++w) {
+      before += (w < wid) ? wsum[w] : 0;
+      tile += wsum[w];
+    }
+    const int c = carry_s;
+    if (i < count) a[i] = c + before + x - v;
+    __syncthreads();
+    if (tid == 0) carry_s = c + tile;
+    __syncthreads();
+  }
+  if (tid == 0) *total = carry_s;
+}
+
+__global__ __launch_bounds__(1024) void k_bin_scan(int32_t* blk, const int64_t* blk_edges, int nblk, BinCounts* bc) {
+  __shared__ int32_t tot[3];
+  for (int q = 0; q < 3; ++q) {
+    block1024_exclusive_scan(blk + q * nblk, nblk, &tot[q]);
+    __syncthreads();
+  }
+  __shared__ long long es[16];
+  long long e = 0;
+  for (int i = threadIdx.x; i < nblk; i += 1024) e += blk_edges[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+  if ((threadIdx.x & 63) == 0) es[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < 16; ++w) t += es[w];
+    bc->small = tot[0];
+    bc->wave = tot[1];
+    bc->hub = tot[2];
+    bc->edges = t;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* rowptr, const int32_t* cnt, int n,
+                                                        int small_max, int wave_max, const int32_t* blk, int nblk,
+                                                        const BinCounts* bc, int32_t* list) {
+  __shared__ int ilds[4];
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  int bin = -1;
+  if (u < n) {
+    const int len = cnt ? cnt[u] : rowptr[u + 1] - rowptr[u];
+    bin = bin_of(len, small_max, wave_max);
+  }
+  const int base[3] = {0, bc->small, bc->small + bc->wave};
+  for (int q = 0; q < 3; ++q) {
+    int tot;
+    const int r = block_rank(bin == q, ilds, tot);
+    if (bin == q) list[base[q] + blk[q * nblk + blockIdx.x] + r] = u;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hub_nchunks(const int32_t* rowptr, const int32_t* cnt, const int32_t* list,
+                                                        const BinCounts* bc, int hub_chunk, int32_t* hub_start) {
+  const int h = blockIdx.x * kBlock + threadIdx.x;
+  if (h < bc->hub) {
+    const int u = list[bc->small + bc->wave + h];
+    const int len = cnt ? cnt[u] : rowptr[u + 1] - rowptr[u];
+    hub_start[h] = (len + hub_chunk - 1) / hub_chunk;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_hub_scan(int32_t* hub_start, BinCounts* bc) {
+  __shared__ int32_t tot;
+  const int nh = bc->hub;
+  block1024_exclusive_scan(hub_start, nh, &tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    hub_start[nh] = tot;
+    bc->chunks = tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sampling [Sec. 3.4]: Philox4x64-10 (Salmon et al., SC'11)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                              uint64_t k1, uint64_t out[4]) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// One thread per bitmap word (32 edges = 4 Philox blocks of 8 draws).
+__global__ __launch_bounds__(kBlock) void k_sample_bits(int64_t m, uint64_t seed, uint64_t epoch, uint64_t keep,
+                                                        uint32_t* bits) {
+  const int64_t nw = (m + 31) >> 5;
+  for (int64_t w = blockIdx.x * (int64_t)kBlock + threadIdx.x; w < nw; w += (int64_t)gridDim.x * kBlock) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint64_t o[4];
+      philox4x64_10((uint64_t)(w * 4 + q), epoch, 0, 0, seed, 0, o);
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const uint64_t word64 = o[h >> 1];
+        const uint32_t d = (h & 1) ? (uint32_t)(word64 >> 32) : (uint32_t)word64;
+        const int64_t e = w * 32 + q * 8 + h;
+        if (e < m && (uint64_t)d < keep) word |= 1u << (q * 8 + h);
+      }
+    }
+    bits[w] = word;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_outdeg(const int32_t* col, int64_t m, int32_t* outdeg) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&outdeg[col[i]], 1);
+}
+
+__global__ void k_pack_weights(const int32_t* col, const int32_t* w, int64_t m, uint32_t* packed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    packed[i] = ((uint32_t)w[i] << 24) | (uint32_t)col[i];
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_copy_u32(const uint32_t* a, uint32_t* b, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+__global__ void k_iota(int32_t* p, int32_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
+}
+
+__global__ void k_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, float* c) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double x;
+    if (app == kPR) x = 1.0 / (double)n;
+    else x = (i == source) ? 1.0 : 0.0;
+    const int od = outdeg[i];
+    c[i] = od > 0 ? (float)(x / (double)od) : (float)x;
+  }
+}
+
+__global__ void k_min_init(int app, int32_t n, int32_t source, uint32_t* x) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (app == kSSSP) x[i] = (i == source) ? 0u : kInf;
+    else x[i] = (uint32_t)i;
+  }
+}
+
+// Dangling list: stable compaction of the vertices with out-degree 0.
+__global__ __launch_bounds__(kBlock) void k_dang_count(const int32_t* outdeg, int n, int32_t* blk) {
+  __shared__ int ilds[4];
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  int tot;
+  block_rank(u < n && outdeg[u] == 0, ilds, tot);
+  if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan1(int32_t* a, int count, int32_t* total) {
+  __shared__ int32_t tot;
+  block1024_exclusive_scan(a, count, &tot);
+  __syncthreads();
+  if (threadIdx.x == 0) *total = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dang_scatter(const int32_t* outdeg, int n, const int32_t* blk,
+                                                         int32_t* list) {
+  __shared__ int ilds[4];
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  const bool d = u < n && outdeg[u] == 0;
+  int tot;
+  const int r = block_rank(d, ilds, tot);
+  if (d) list[blk[blockIdx.x] + r] = u;
+}
+
+constexpr int kDangBlocks = 256;
+
+__global__ __launch_bounds__(kBlock) void k_dsum_partial(const float* c, const int32_t* list, int count,
+                                                         double* partial) {
+  __shared__ double lds[4];
+  const int per = (count + kDangBlocks - 1) / kDangBlocks;
+  const int lo = blockIdx.x * per, hi = min(count, lo + per);
+  double acc = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) acc += (double)c[list[i]];
+  acc = block_reduce<kPR>(acc, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dsum_final(const double* partial, double* out) {
+  __shared__ double lds[4];
+  double acc = partial[threadIdx.x];
+  acc = block_reduce<kPR>(acc, lds);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static inline int grid_for(int64_t work, int per_block, int cap) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+hipError_t launch_outdeg(const int32_t* col, int64_t m, int32_t* outdeg, int32_t n, hipStream_t st) {
+  hipError_t e = launch_fill_u32((uint32_t*)outdeg, n, 0u, st);
+  if (e != hipSuccess || m == 0) return e;
+  hipLaunchKernelGGL(k_outdeg, dim3(grid_for(m, kBlock * 8, 1 << 16)), dim3(kBlock), 0, st, col, m, outdeg);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const int32_t* col, const int32_t* w, int64_t m, uint32_t* packed, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_weights, dim3(grid_for(m, kBlock * 8, 1 << 16)), dim3(kBlock), 0, st, col, w, m, packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, kBlock * 8, 1 << 16)), dim3(kBlock), 0, st, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_u32, dim3(grid_for(count, kBlock * 8, 1 << 16)), dim3(kBlock), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* p, int32_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n, kBlock * 8, 1 << 16)), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dangling_list(const int32_t* outdeg, int32_t n, int32_t* list, int32_t* count,
+                                int32_t* blk_scratch, hipStream_t st) {
+  const int nblk = (n + kBlock - 1) / kBlock;
+  if (n == 0) return launch_fill_u32((uint32_t*)count, 1, 0u, st);
+  hipLaunchKernelGGL(k_dang_count, dim3(nblk), dim3(kBlock), 0, st, outdeg, n, blk_scratch);
+  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, blk_scratch, nblk, count);
+  hipLaunchKernelGGL(k_dang_scatter, dim3(nblk), dim3(kBlock), 0, st, outdeg, n, blk_scratch, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_dangling_sum(const float* c, const int32_t* list, const int32_t* /*count_dev*/, int32_t count,
+                               double* partial, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dsum_partial, dim3(kDangBlocks), dim3(kBlock), 0, st, c, list, count, partial);
+  hipLaunchKernelGGL(k_dsum_final, dim3(1), dim3(kBlock), 0, st, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, int32_t small_max, int32_t wave_max,
+                        int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st) {
+  const int nblk = (n + kBlock - 1) / kBlock;
+  int32_t* blk = (int32_t*)blk_scratch;
+  int64_t* blk_edges = (int64_t*)(blk + 3 * (int64_t)nblk + ((3 * nblk) & 1));
+  if (n == 0) {
+    BinCounts z{};
+    hipError_t e = hipMemcpyAsync(bins.dcounts, &z, sizeof(z), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return launch_fill_u32((uint32_t*)bins.hub_start, 1, 0u, st);
+  }
+  hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(kBlock), 0, st, rowptr, cnt, n, small_max, wave_max, blk,
+                     blk_edges, nblk);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, blk, blk_edges, nblk, bins.dcounts);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(nblk), dim3(kBlock), 0, st, rowptr, cnt, n, small_max, wave_max, blk, nblk,
+                     bins.dcounts, bins.list);
+  hipLaunchKernelGGL(k_hub_nchunks, dim3(nblk), dim3(kBlock), 0, st, rowptr, cnt, bins.list, bins.dcounts, hub_chunk,
+                     bins.hub_start);
+  hipLaunchKernelGGL(k_hub_scan, dim3(1), dim3(1024), 0, st, bins.hub_start, bins.dcounts);
+  return hipGetLastError();
+}
+
+hipError_t launch_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, float* c, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pr_init, dim3(grid_for(n, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, app, outdeg, n, source,
+                     c);
+  return hipGetLastError();
+}
+
+hipError_t launch_min_init(int app, int32_t n, int32_t source, uint32_t* x, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_min_init, dim3(grid_for(n, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, app, n, source, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_bits(int64_t m, uint64_t seed, uint64_t epoch, uint64_t keep, uint32_t* bits,
+                              hipStream_t st) {
+  const int64_t nw = (m + 31) >> 5;
+  if (nw == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample_bits, dim3(grid_for(nw, kBlock, 1 << 16)), dim3(kBlock), 0, st, m, seed, epoch, keep,
+                     bits);
+  return hipGetLastError();
+}
+
+static constexpr int kTeamBlockCap = 16384;
+
+static void section_grids(const Sweep& s, int team, int& gs, int& gw) {
+  gs = s.n_small > 0 ? grid_for(s.n_small, kBlock / team, kTeamBlockCap) : 0;
+  gw = s.n_wave > 0 ? grid_for(s.n_wave, kBlock / 64, kTeamBlockCap) : 0;
+}
+
+static int hub_chunks(const Sweep& s) { return s.n_hub > 0 ? s.n_chunks : 0; }
+
+template <int APP, int TEAM>
+static hipError_t gather_t(const Sweep& s, int nchunks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  int gs, gw;
+  section_grids(s, TEAM, gs, gw);
+  const int total = gs + gw + nchunks;
+  if (ev0) (void)hipEventRecord(ev0, st);
+  if (total > 0) hipLaunchKernelGGL((k_gather<APP, TEAM>), dim3(total), dim3(kBlock), 0, st, s, gs, gw);
+  if (ev1) (void)hipEventRecord(ev1, st);
+  if (s.n_hub > 0) hipLaunchKernelGGL((k_hub_combine<APP>), dim3(grid_for(s.n_hub, kBlock, 1 << 20)), dim3(kBlock), 0,
+                                      st, s);
+  return hipGetLastError();
+}
+
+template <int APP, int TEAM>
+static hipError_t super_t(const Sweep& s, int nchunks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  int gs, gw;
+  section_grids(s, TEAM, gs, gw);
+  if (nchunks > 0) hipLaunchKernelGGL((k_hub_totals<APP>), dim3(nchunks), dim3(kBlock), 0, st, s);
+  const int total = gs + gw + nchunks;
+  if (ev0) (void)hipEventRecord(ev0, st);
+  if (total > 0) hipLaunchKernelGGL((k_super<APP, TEAM>), dim3(total), dim3(kBlock), 0, st, s, gs, gw);
+  if (ev1) (void)hipEventRecord(ev1, st);
+  if (nchunks > 0) hipLaunchKernelGGL(k_hub_pack, dim3(nchunks), dim3(kBlock), 0, st, s, (const uint32_t*)s.new_bits);
+  return hipGetLastError();
+}
+
+template <int TEAM>
+static hipError_t pack_t(const Sweep& s, int nchunks, hipStream_t st) {
+  int gs, gw;
+  section_grids(s, TEAM, gs, gw);
+  const int total = gs + gw + nchunks;
+  if (total > 0) hipLaunchKernelGGL((k_pack<TEAM>), dim3(total), dim3(kBlock), 0, st, s, gs, gw);
+  if (nchunks > 0) hipLaunchKernelGGL(k_hub_pack, dim3(nchunks), dim3(kBlock), 0, st, s, s.old_bits);
+  return hipGetLastError();
+}
+
+#define GG_DISPATCH_TEAM(FN, APP, team, ...)                      \
+  switch (team) {                                                 \
+    case 4: return FN<APP, 4>(__VA_ARGS__);                       \
+    case 8: return FN<APP, 8>(__VA_ARGS__);                       \
+    case 16: return FN<APP, 16>(__VA_ARGS__);                     \
+    case 32: return FN<APP, 32>(__VA_ARGS__);                     \
+    default: return hipErrorInvalidValue;                         \
+  }
+
+template <int APP>
+static hipError_t gather_app(int team, const Sweep& s, int nchunks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  GG_DISPATCH_TEAM(gather_t, APP, team, s, nchunks, st, ev0, ev1)
+}
+template <int APP>
+static hipError_t super_app(int team, const Sweep& s, int nchunks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  GG_DISPATCH_TEAM(super_t, APP, team, s, nchunks, st, ev0, ev1)
+}
+
+hipError_t launch_gather(int app, int team, const Sweep& s, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int nchunks = hub_chunks(s);
+  switch (app) {
+    case kPR: return gather_app<kPR>(team, s, nchunks, st, ev0, ev1);
+    case kPPR: return gather_app<kPPR>(team, s, nchunks, st, ev0, ev1);
+    case kSSSP: return gather_app<kSSSP>(team, s, nchunks, st, ev0, ev1);
+    case kCC: return gather_app<kCC>(team, s, nchunks, st, ev0, ev1);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_superstep(int app, int team, const Sweep& s, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int nchunks = hub_chunks(s);
+  switch (app) {
+    case kPR: return super_app<kPR>(team, s, nchunks, st, ev0, ev1);
+    case kPPR: return super_app<kPPR>(team, s, nchunks, st, ev0, ev1);
+    case kSSSP: return super_app<kSSSP>(team, s, nchunks, st, ev0, ev1);
+    case kCC: return super_app<kCC>(team, s, nchunks, st, ev0, ev1);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack(int team, const Sweep& s, hipStream_t st) {
+  const int nchunks = hub_chunks(s);
+  switch (team) {
+    case 4: return pack_t<4>(s, nchunks, st);
+    case 8: return pack_t<8>(s, nchunks, st);
+    case 16: return pack_t<16>(s, nchunks, st);
+    case 32: return pack_t<32>(s, nchunks, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ggk
+
+namespace ggk {
+
+// Structure check of an in-CSR: bit 0 rowptr ends, bit 1 rowptr decreasing,
+// bit 2 column out of range, bit 3 weight outside [0, 255].
+__global__ void k_validate(const int32_t* rowptr, const int32_t* col, const int32_t* w, int32_t n, int64_t m,
+                           int32_t* flags) {
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int f = 0;
+  if (tid == 0 && (rowptr[0] != 0 || (int64_t)rowptr[n] != m)) f |= 1;
+  for (int64_t u = tid; u < n; u += stride)
+    if (rowptr[u + 1] < rowptr[u]) f |= 2;
+  for (int64_t e = tid; e < m; e += stride) {
+    const int32_t v = col[e];
+    if (v < 0 || v >= n) f |= 4;
+    if (w && (w[e] < 0 || w[e] > 255)) f |= 8;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, const int32_t* w, int32_t n, int64_t m,
+                           int32_t* flags, hipStream_t st) {
+  hipError_t e = launch_fill_u32((uint32_t*)flags, 1, 0u, st);
+  if (e != hipSuccess) return e;
+  const int64_t work = m > n ? m : n;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(work + 1, kBlock * 8, 1 << 16)), dim3(kBlock), 0, st, rowptr, col, w,
+                     n, m, flags);
+  return hipGetLastError();
+}
+
+}  // namespace ggk

@@ -1,0 +1,760 @@
+// Host runtime and C ABI of the GraphGuess sweep library (see include/gg.h).
+//
+// A graph handle owns the device copy (or borrows the caller's device
+// arrays) of the in-CSR, its out-degrees, the dangling-vertex list, the
+// degree binning of the full rows, and a workspace reused by every run on
+// the graph: double-buffered vertex values, the edge-flag bitmaps, the
+// active edge array with its per-row counts and binning, and scratch for
+// hub partial results.
+//
+// A run follows the schedule of its correction scheme [Sec. 3.4, Sec. 5.2]:
+// iteration i (1-based) is accurate for EXACT always, for SMS from
+// i = alpha+1 on, for GG when i is a multiple of alpha+1; SP never. Each
+// accurate GG iteration is a superstep that re-selects the active edges.
+// Updates are synchronous: iteration i reads the values of iteration i-1.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gg.h"
+#include "gg_internal.h"
+
+using namespace ggk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define GG_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      if (e_ == hipErrorOutOfMemory) return fail(GG_E_NOMEM, std::string(#call) + ": out of device memory"); \
+      return fail(GG_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));            \
+    }                                                                                         \
+  } while (0)
+
+#define GG_TRY(x)            \
+  do {                       \
+    int r_ = (x);            \
+    if (r_ != GG_OK) return r_; \
+  } while (0)
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(GG_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  return GG_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct gg_graph {
+  int32_t n = 0;
+  int64_t m = 0;
+  hipStream_t stream = nullptr;
+  bool owns_csr = false;
+  int32_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  int32_t* weight = nullptr;   // owned copy (host input) or borrowed
+  uint32_t* wedges = nullptr;  // (weight << 24) | source, when weights exist
+  int32_t* outdeg = nullptr;
+  int32_t* dang = nullptr;
+  int32_t n_dang = 0;
+  int32_t* i32_scratch = nullptr;  // small device scalars: [0] dangling count, [1] validate flags
+  void* blk_scratch = nullptr;
+  gg_tuning tune{16, 8, 2048, 8192};
+  Bins full;         // binning of the full rows by in-degree
+  bool full_valid = false;
+  // workspace (allocated on first run)
+  bool ws = false;
+  float* c[2] = {nullptr, nullptr};
+  float* xout = nullptr;
+  uint32_t* xu[2] = {nullptr, nullptr};
+  uint32_t* bits[2] = {nullptr, nullptr};
+  uint32_t* act_edges = nullptr;
+  int32_t* act_cnt = nullptr;
+  Bins act;
+  double* part_f = nullptr;
+  uint32_t* part_u = nullptr;
+  int32_t* part_cnt = nullptr;
+  int64_t part_cap = 0;
+  double* dpartial = nullptr;  // 256 dangling partials + [256] = D
+  int32_t* changed = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  gg_run* active_run = nullptr;
+  // kernel profiling (gg_graph_set_profiling)
+  struct ProfRec {
+    int kind, app;
+    hipEvent_t e0, e1;
+    double bytes;
+    int64_t edges;
+  };
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+};
+
+struct gg_run {
+  gg_graph* g = nullptr;
+  gg_app_params p{};
+  gg_correction_policy pol{};
+  double sigma = 1.0;
+  int32_t iter = 0;
+  bool done = false;
+  int cur = 0;   // value buffer holding iteration `iter`
+  int bcur = 0;  // bitmap holding the current flags
+  bool x_valid = false;  // PR: xout holds the values of iteration `iter`
+  bool write_x_each_step = false;
+  int32_t supersteps = 0;
+  int64_t edges_total = 0;
+  bool timing = false;
+};
+
+namespace {
+
+int64_t max_chunks(const gg_graph* g) {
+  const int64_t m = g->m;
+  return m / g->tune.hub_chunk + m / ((int64_t)g->tune.wave_max + 1) + 2;
+}
+
+int sync_bins(gg_graph* g, Bins& b) {
+  GG_HIP(hipMemcpyAsync(&b.h, b.dcounts, sizeof(BinCounts), hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  return GG_OK;
+}
+
+int alloc_bins(Bins& b, int32_t n) {
+  GG_TRY(dalloc(&b.list, (size_t)n));
+  GG_TRY(dalloc(&b.hub_start, (size_t)n + 1));
+  GG_TRY(dalloc(&b.dcounts, 1));
+  return GG_OK;
+}
+
+void free_bins(Bins& b) {
+  dfree(b.list);
+  dfree(b.hub_start);
+  dfree(b.dcounts);
+}
+
+int rebin(gg_graph* g, Bins& b, const int32_t* cnt) {
+  GG_HIP(launch_rebin(g->rowptr, cnt, g->n, g->tune.small_max, g->tune.wave_max, g->tune.hub_chunk, b,
+                      g->blk_scratch, g->stream));
+  return sync_bins(g, b);
+}
+
+int ensure_parts(gg_graph* g) {
+  const int64_t need = max_chunks(g);
+  if (g->part_cap >= need) return GG_OK;
+  dfree(g->part_f);
+  dfree(g->part_u);
+  dfree(g->part_cnt);
+  g->part_cap = 0;
+  GG_TRY(dalloc(&g->part_f, (size_t)need));
+  GG_TRY(dalloc(&g->part_u, (size_t)need));
+  GG_TRY(dalloc(&g->part_cnt, (size_t)need));
+  g->part_cap = need;
+  return GG_OK;
+}
+
+int ensure_workspace(gg_graph* g) {
+  if (g->ws) return ensure_parts(g);
+  const size_t n = (size_t)g->n, m = (size_t)g->m, nw = (m + 31) / 32;
+  GG_TRY(dalloc(&g->c[0], n));
+  GG_TRY(dalloc(&g->c[1], n));
+  GG_TRY(dalloc(&g->xout, n));
+  GG_TRY(dalloc(&g->xu[0], n));
+  GG_TRY(dalloc(&g->xu[1], n));
+  GG_TRY(dalloc(&g->bits[0], nw));
+  GG_TRY(dalloc(&g->bits[1], nw));
+  GG_TRY(dalloc(&g->act_edges, m));
+  GG_TRY(dalloc(&g->act_cnt, n));
+  GG_TRY(alloc_bins(g->act, g->n));
+  GG_TRY(dalloc(&g->dpartial, 257));
+  GG_TRY(dalloc(&g->changed, 1));
+  GG_HIP(hipEventCreate(&g->ev0));
+  GG_HIP(hipEventCreate(&g->ev1));
+  g->ws = true;
+  return ensure_parts(g);
+}
+
+void free_graph(gg_graph* g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->owns_csr) {
+    dfree(g->rowptr);
+    dfree(g->col);
+    dfree(g->weight);
+  }
+  dfree(g->wedges);
+  dfree(g->outdeg);
+  dfree(g->dang);
+  dfree(g->i32_scratch);
+  if (g->blk_scratch) (void)hipFree(g->blk_scratch);
+  free_bins(g->full);
+  for (int i = 0; i < 2; ++i) {
+    dfree(g->c[i]);
+    dfree(g->xu[i]);
+    dfree(g->bits[i]);
+  }
+  dfree(g->xout);
+  dfree(g->act_edges);
+  dfree(g->act_cnt);
+  free_bins(g->act);
+  dfree(g->part_f);
+  dfree(g->part_u);
+  dfree(g->part_cnt);
+  dfree(g->dpartial);
+  dfree(g->changed);
+  for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
+  if (g->ev0) (void)hipEventDestroy(g->ev0);
+  if (g->ev1) (void)hipEventDestroy(g->ev1);
+  delete g;
+}
+
+bool valid_tuning(const gg_tuning& t) {
+  const bool team_ok = t.small_team == 4 || t.small_team == 8 || t.small_team == 16 || t.small_team == 32;
+  return team_ok && t.small_max >= 0 && t.wave_max >= t.small_max && t.wave_max >= 1 && t.hub_chunk >= kBlock &&
+         (t.hub_chunk % kBlock) == 0 && t.hub_chunk <= (1 << 24);
+}
+
+// ---- schedule -------------------------------------------------------------
+
+bool is_accurate(const gg_correction_policy& p, int32_t i) {
+  switch (p.kind) {
+    case GG_POLICY_EXACT: return true;
+    case GG_POLICY_SP: return false;
+    case GG_POLICY_SMS: return i >= p.alpha + 1;
+    case GG_POLICY_GG: return (i % (p.alpha + 1)) == 0;
+  }
+  return true;
+}
+
+bool is_superstep(const gg_correction_policy& p, int32_t i) { return p.kind == GG_POLICY_GG && is_accurate(p, i); }
+
+bool is_pr(int app) { return app == GG_APP_PR || app == GG_APP_PPR; }
+
+int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol) {
+  if (!p || !pol) return fail(GG_E_INVAL, "null params or policy");
+  if (p->app < GG_APP_PR || p->app > GG_APP_PPR) return fail(GG_E_INVAL, "unknown app");
+  if (pol->kind < GG_POLICY_EXACT || pol->kind > GG_POLICY_GG) return fail(GG_E_INVAL, "unknown policy kind");
+  if (!(sigma >= 0.0 && sigma <= 1.0)) return fail(GG_E_INVAL, "sample_ratio outside [0, 1]");
+  if (pol->alpha < 0) return fail(GG_E_INVAL, "alpha < 0");
+  if (!(pol->theta >= 0.0 && pol->theta < 65536.0)) return fail(GG_E_INVAL, "theta outside [0, 65536)");
+  if (pol->mask_update != GG_MASK_REPLACE && pol->mask_update != GG_MASK_UNION)
+    return fail(GG_E_INVAL, "unknown mask_update");
+  if (pol->stop != GG_STOP_FIXED_ITERS && pol->stop != GG_STOP_FIXED_POINT) return fail(GG_E_INVAL, "unknown stop");
+  if (pol->influence != GG_INFL_PREFIX && pol->influence != GG_INFL_TOTAL) return fail(GG_E_INVAL, "unknown influence");
+  if (pol->influence == GG_INFL_TOTAL) return fail(GG_E_UNSUPPORTED, "TOTAL influence is not implemented");
+  if (p->dangling != GG_DANGLING_UNIFORM && p->dangling != GG_DANGLING_NONE) return fail(GG_E_INVAL, "unknown dangling");
+  if (is_pr(p->app) && !(p->damping >= 0.0 && p->damping < 1.0)) return fail(GG_E_INVAL, "damping outside [0, 1)");
+  if ((p->app == GG_APP_SSSP || p->app == GG_APP_PPR) && (p->source < 0 || p->source >= g->n))
+    return fail(GG_E_INVAL, "source out of range");
+  if (p->app == GG_APP_SSSP && !g->wedges) return fail(GG_E_INVAL, "SSSP needs edge weights");
+  const bool fixed_iters = is_pr(p->app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
+  if (fixed_iters && p->iters < 0) return fail(GG_E_INVAL, "iters < 0");
+  if (!fixed_iters && p->max_iters <= 0) return fail(GG_E_INVAL, "max_iters must be > 0");
+  return GG_OK;
+}
+
+Sweep base_sweep(const gg_graph* g, const gg_run* r) {
+  Sweep s;
+  std::memset(&s, 0, sizeof(s));
+  s.n = g->n;
+  s.small_max = g->tune.small_max;
+  s.wave_max = g->tune.wave_max;
+  s.hub_chunk = g->tune.hub_chunk;
+  s.rowptr = g->rowptr;
+  s.outdeg = g->outdeg;
+  s.dangling = g->dpartial + 256;
+  s.damping = r->p.damping;
+  s.base = g->n > 0 ? (1.0 - r->p.damping) / (double)g->n : 0.0;
+  s.source = r->p.source;
+  s.changed = g->changed;
+  s.part_f = g->part_f;
+  s.part_u = g->part_u;
+  s.part_cnt = g->part_cnt;
+  s.theta = r->pol.theta;
+  s.theta_q = (uint64_t)std::floor(r->pol.theta * 65536.0 + 0.5);
+  s.mask_union = r->pol.mask_update == GG_MASK_UNION;
+  s.act_edges = g->act_edges;
+  s.act_cnt = g->act_cnt;
+  return s;
+}
+
+void set_bins(Sweep& s, const Bins& b) {
+  s.list = b.list;
+  s.hub_start = b.hub_start;
+  s.n_small = b.h.small;
+  s.n_wave = b.h.wave;
+  s.n_hub = b.h.hub;
+  s.n_chunks = b.h.chunks;
+}
+
+// Two events for one profiled launch (nullptr pair when profiling is off).
+int prof_events(gg_graph* g, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (!g->prof) return GG_OK;
+  while (g->pool.size() < g->pool_used + 2) {
+    hipEvent_t e;
+    GG_HIP(hipEventCreate(&e));
+    g->pool.push_back(e);
+  }
+  *e0 = g->pool[g->pool_used++];
+  *e1 = g->pool[g->pool_used++];
+  return GG_OK;
+}
+
+// Algorithmic bytes of one sweep launch: per gathered edge the edge word and
+// the gathered source value; per row its list entry, row offset, active count
+// (approximate mode), out-degree or own value, and the value written.
+double alg_bytes(int kind, int64_t rows, int64_t edges, bool x_out) {
+  const double per_row = 16.0 + (kind == 1 ? 4.0 : 0.0) + (kind == 2 ? 4.0 : 0.0) + (x_out ? 4.0 : 0.0);
+  return 8.0 * (double)edges + per_row * (double)rows;
+}
+
+const uint32_t* full_edges(const gg_graph* g, int app) {
+  return app == GG_APP_SSSP ? g->wedges : (const uint32_t*)g->col;
+}
+
+int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol, gg_run** out) {
+  GG_TRY(check_params(g, p, sigma, pol));
+  if (g->active_run) return fail(GG_E_STATE, "another run is active on this graph");
+  GG_TRY(ensure_workspace(g));
+  gg_run* r = new (std::nothrow) gg_run();
+  if (!r) return fail(GG_E_NOMEM, "host allocation failed");
+  r->g = g;
+  r->p = *p;
+  r->pol = *pol;
+  r->sigma = sigma;
+  const int app = p->app;
+  // initial values
+  if (is_pr(app)) {
+    GG_HIP(launch_pr_init(app, g->outdeg, g->n, p->source, g->c[0], g->stream));
+    if (p->dangling == GG_DANGLING_NONE) GG_HIP(launch_fill_u32((uint32_t*)(g->dpartial + 256), 2, 0u, g->stream));
+  } else {
+    GG_HIP(launch_min_init(app, g->n, p->source, g->xu[0], g->stream));
+  }
+  // initial sparsification [Sec. 3.4]
+  if (pol->kind != GG_POLICY_EXACT) {
+    const uint64_t keep = (uint64_t)std::floor(sigma * 4294967296.0 + 0.5);
+    GG_HIP(launch_sample_bits(g->m, pol->seed, 0, keep, g->bits[0], g->stream));
+    Sweep s = base_sweep(g, r);
+    set_bins(s, g->full);
+    s.edges = full_edges(g, app);
+    s.old_bits = g->bits[0];
+    GG_HIP(launch_pack(g->tune.small_team, s, g->stream));
+    int rc = rebin(g, g->act, g->act_cnt);
+    if (rc != GG_OK) {
+      delete r;
+      return rc;
+    }
+  }
+  const bool fixed_iters = is_pr(app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
+  if (fixed_iters && p->iters == 0) r->done = true;
+  g->active_run = r;
+  *out = r;
+  return GG_OK;
+}
+
+// One iteration. sync_changed: read the changed count back (needed for
+// fixed-point termination and for step info).
+int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
+  gg_graph* g = r->g;
+  if (r->done) return 0;
+  const int32_t i = r->iter + 1;
+  const int app = r->p.app;
+  const bool accurate = is_accurate(r->pol, i);
+  const bool superstep = is_superstep(r->pol, i);
+  const bool pr = is_pr(app);
+  const bool last_fixed = (pr || (r->pol.kind != GG_POLICY_EXACT && r->pol.stop == GG_STOP_FIXED_ITERS)) &&
+                          i >= r->p.iters;
+  Sweep s = base_sweep(g, r);
+  if (pr) {
+    if (r->p.dangling == GG_DANGLING_UNIFORM)
+      GG_HIP(launch_dangling_sum(g->c[r->cur], g->dang, nullptr, g->n_dang, g->dpartial, g->dpartial + 256,
+                                 g->stream));
+    s.c_in = g->c[r->cur];
+    s.c_out = g->c[1 - r->cur];
+    s.x_out = (r->write_x_each_step || last_fixed) ? g->xout : nullptr;
+  } else {
+    s.x_in = g->xu[r->cur];
+    s.x_next = g->xu[1 - r->cur];
+    GG_HIP(launch_fill_u32((uint32_t*)g->changed, 1, 0u, g->stream));
+  }
+  int64_t edges;
+  hipEvent_t pe0, pe1;
+  GG_TRY(prof_events(g, &pe0, &pe1));
+  int kind;
+  if (superstep) {
+    kind = 2;
+    GG_HIP(launch_fill_u32(g->bits[1 - r->bcur], (g->m + 31) / 32, 0u, g->stream));
+    set_bins(s, g->full);
+    s.edges = full_edges(g, app);
+    s.cnt = nullptr;
+    s.old_bits = g->bits[r->bcur];
+    s.new_bits = g->bits[1 - r->bcur];
+    GG_HIP(launch_superstep(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    r->bcur = 1 - r->bcur;
+    GG_TRY(rebin(g, g->act, g->act_cnt));
+    r->supersteps++;
+    edges = g->m;
+  } else if (accurate) {
+    kind = 0;
+    set_bins(s, g->full);
+    s.edges = full_edges(g, app);
+    s.cnt = nullptr;
+    GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    edges = g->m;
+  } else {
+    kind = 1;
+    set_bins(s, g->act);
+    s.edges = g->act_edges;
+    s.cnt = g->act_cnt;
+    GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    edges = g->act.h.edges;
+  }
+  if (g->prof) {
+    double bytes = alg_bytes(kind, g->n, edges, s.x_out != nullptr);
+    if (kind == 2) bytes += 4.0 * (double)g->act.h.edges + (double)((g->m + 31) / 32) * 4.0;
+    g->recs.push_back({kind, app, pe0, pe1, bytes, edges});
+  }
+  r->cur = 1 - r->cur;
+  r->iter = i;
+  r->x_valid = pr && s.x_out != nullptr;
+  r->edges_total += edges;
+  int64_t changed = -1;
+  if (!pr && sync_changed) {
+    int32_t hc = 0;
+    GG_HIP(hipMemcpyAsync(&hc, g->changed, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipStreamSynchronize(g->stream));
+    changed = hc;
+  }
+  // termination
+  if (pr) {
+    if (i >= r->p.iters) r->done = true;
+  } else if (r->pol.kind == GG_POLICY_EXACT) {
+    if (changed == 0 || i >= r->p.max_iters) r->done = true;
+  } else if (r->pol.stop == GG_STOP_FIXED_ITERS) {
+    if (i >= r->p.iters) r->done = true;
+  } else {
+    const bool final_kind = accurate || r->pol.kind == GG_POLICY_SP;
+    if ((changed == 0 && final_kind) || i >= r->p.max_iters) r->done = true;
+  }
+  if (info) {
+    info->iter = i;
+    info->accurate = accurate;
+    info->superstep = superstep;
+    info->edges = edges;
+    info->changed = changed;
+    info->active_edges = r->pol.kind == GG_POLICY_EXACT ? g->m : g->act.h.edges;
+  }
+  return 1;
+}
+
+int copy_out(gg_graph* g, const void* dsrc, void* out, size_t bytes, uint32_t flags) {
+  if (flags & GG_OUT_HOST) {
+    GG_HIP(hipMemcpyAsync(out, dsrc, bytes, hipMemcpyDeviceToHost, g->stream));
+  } else {
+    GG_HIP(hipMemcpyAsync(out, dsrc, bytes, hipMemcpyDeviceToDevice, g->stream));
+  }
+  GG_HIP(hipStreamSynchronize(g->stream));
+  return GG_OK;
+}
+
+// PR values before any iteration: the initial vector.
+int pr_initial_x(gg_run* r) {
+  gg_graph* g = r->g;
+  if (g->n == 0) return GG_OK;
+  float* h = new (std::nothrow) float[(size_t)g->n];
+  if (!h) return fail(GG_E_NOMEM, "host allocation failed");
+  for (int32_t u = 0; u < g->n; ++u)
+    h[u] = r->p.app == GG_APP_PR ? (float)(1.0 / (double)g->n) : (u == r->p.source ? 1.0f : 0.0f);
+  hipError_t e = hipMemcpyAsync(g->xout, h, sizeof(float) * (size_t)g->n, hipMemcpyHostToDevice, g->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+  delete[] h;
+  if (e != hipSuccess) return fail(GG_E_DEVICE, std::string("initial values: ") + hipGetErrorString(e));
+  r->x_valid = true;
+  return GG_OK;
+}
+
+int run_values(gg_run* r, void* out, uint32_t flags) {
+  gg_graph* g = r->g;
+  if (!out) return fail(GG_E_INVAL, "null output");
+  if (is_pr(r->p.app)) {
+    if (r->iter == 0) GG_TRY(pr_initial_x(r));
+    if (!r->x_valid) return fail(GG_E_STATE, "PR values of this iteration were not materialized");
+    return copy_out(g, g->xout, out, sizeof(float) * (size_t)g->n, flags);
+  }
+  return copy_out(g, g->xu[r->cur], out, sizeof(uint32_t) * (size_t)g->n, flags);
+}
+
+void end_run(gg_run* r) {
+  if (!r) return;
+  if (r->g && r->g->active_run == r) r->g->active_run = nullptr;
+  delete r;
+}
+
+int whole_run(gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol, void* out,
+              uint32_t flags, gg_run_stats* st) {
+  if (!g) return fail(GG_E_INVAL, "null graph");
+  if (!out) return fail(GG_E_INVAL, "null output");
+  gg_run* r = nullptr;
+  GG_TRY(ensure_workspace(g));
+  GG_HIP(hipEventRecord(g->ev0, g->stream));
+  GG_TRY(run_begin(g, p, sigma, pol, &r));
+  const bool need_changed = !is_pr(p->app) && (pol->kind == GG_POLICY_EXACT || pol->stop == GG_STOP_FIXED_POINT);
+  int rc = GG_OK;
+  while (!r->done) {
+    int s = run_step(r, nullptr, need_changed);
+    if (s < 0) {
+      rc = s;
+      break;
+    }
+    if (s == 0) break;
+  }
+  if (rc == GG_OK) {
+    hipError_t e = hipEventRecord(g->ev1, g->stream);
+    if (e != hipSuccess) rc = fail(GG_E_DEVICE, hipGetErrorString(e));
+  }
+  if (rc == GG_OK) rc = run_values(r, out, flags);
+  if (rc == GG_OK && st) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, g->ev0, g->ev1);
+    if (e != hipSuccess) rc = fail(GG_E_DEVICE, hipGetErrorString(e));
+    st->iterations = r->iter;
+    st->supersteps = r->supersteps;
+    st->edges_gathered = r->edges_total;
+    st->active_edges = pol->kind == GG_POLICY_EXACT ? g->m : g->act.h.edges;
+    st->device_ms = ms;
+  }
+  end_run(r);
+  return rc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int gg_version(void) { return GG_VERSION; }
+
+const char* gg_last_error(void) { return g_err.c_str(); }
+
+int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
+  if (!d || !out) return fail(GG_E_INVAL, "null argument");
+  *out = nullptr;
+  if (d->n < 0 || d->m < 0) return fail(GG_E_RANGE, "negative n or m");
+  if (d->m >= ((int64_t)1 << 31)) return fail(GG_E_RANGE, "m must be < 2^31");
+  if (d->n >= INT32_MAX) return fail(GG_E_RANGE, "n must be < 2^31 - 1");
+  if (!d->rowptr || (d->m > 0 && !d->col)) return fail(GG_E_INVAL, "null rowptr or col");
+  if (d->weight && d->n > (1 << 24)) return fail(GG_E_RANGE, "weighted graphs need n <= 2^24");
+  gg_graph* g = new (std::nothrow) gg_graph();
+  if (!g) return fail(GG_E_NOMEM, "host allocation failed");
+  g->n = d->n;
+  g->m = d->m;
+  g->stream = (hipStream_t)hip_stream;
+  const size_t n = (size_t)d->n, m = (size_t)d->m;
+  int rc = GG_OK;
+  auto bail = [&](int code) {
+    free_graph(g);
+    return code;
+  };
+  if (d->flags & GG_CSR_DEVICE_PTRS) {
+    g->owns_csr = false;
+    g->rowptr = const_cast<int32_t*>(d->rowptr);
+    g->col = const_cast<int32_t*>(d->col);
+    g->weight = const_cast<int32_t*>(d->weight);
+  } else {
+    g->owns_csr = true;
+    if ((rc = dalloc(&g->rowptr, n + 1)) != GG_OK) return bail(rc);
+    if ((rc = dalloc(&g->col, m)) != GG_OK) return bail(rc);
+    hipError_t e = hipMemcpyAsync(g->rowptr, d->rowptr, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess && m) e = hipMemcpyAsync(g->col, d->col, m * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess && d->weight) {
+      if ((rc = dalloc(&g->weight, m)) != GG_OK) return bail(rc);
+      if (m) e = hipMemcpyAsync(g->weight, d->weight, m * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+    }
+    if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("copy CSR: ") + hipGetErrorString(e)));
+  }
+  if ((rc = dalloc(&g->i32_scratch, 4)) != GG_OK) return bail(rc);
+  if (!(d->flags & GG_CSR_SKIP_VALIDATE)) {
+    hipError_t e = launch_validate(g->rowptr, g->col, g->weight, g->n, g->m, g->i32_scratch + 1, g->stream);
+    int32_t flags = 0;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&flags, g->i32_scratch + 1, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("validate: ") + hipGetErrorString(e)));
+    if (flags & 1) return bail(fail(GG_E_RANGE, "rowptr[0] != 0 or rowptr[n] != m"));
+    if (flags & 2) return bail(fail(GG_E_RANGE, "rowptr is not non-decreasing"));
+    if (flags & 4) return bail(fail(GG_E_RANGE, "column index out of [0, n)"));
+    if (flags & 8) return bail(fail(GG_E_RANGE, "weight outside [0, 255]"));
+  }
+  const int nblk = (d->n + kBlock - 1) / kBlock;
+  const size_t scratch_bytes = (size_t)(3 * nblk + 2) * sizeof(int32_t) + (size_t)(nblk + 1) * sizeof(int64_t);
+  if (hipMalloc(&g->blk_scratch, scratch_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(GG_E_NOMEM, "scratch allocation failed"));
+  }
+  if ((rc = dalloc(&g->outdeg, n)) != GG_OK) return bail(rc);
+  if ((rc = dalloc(&g->dang, n)) != GG_OK) return bail(rc);
+  hipError_t e = launch_outdeg(g->col, g->m, g->outdeg, g->n, g->stream);
+  if (e == hipSuccess) e = launch_dangling_list(g->outdeg, g->n, g->dang, g->i32_scratch, (int32_t*)g->blk_scratch,
+                                                 g->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&g->n_dang, g->i32_scratch, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
+  if (e == hipSuccess && d->weight) {
+    if ((rc = dalloc(&g->wedges, m)) != GG_OK) return bail(rc);
+    e = launch_pack_weights(g->col, g->weight, g->m, g->wedges, g->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+  if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("load: ") + hipGetErrorString(e)));
+  if ((rc = alloc_bins(g->full, g->n)) != GG_OK) return bail(rc);
+  if ((rc = rebin(g, g->full, nullptr)) != GG_OK) return bail(rc);
+  g->full_valid = true;
+  *out = g;
+  return GG_OK;
+}
+
+int gg_graph_set_stream(gg_graph* g, void* hip_stream) {
+  if (!g) return fail(GG_E_INVAL, "null graph");
+  if (g->stream) GG_HIP(hipStreamSynchronize(g->stream));
+  g->stream = (hipStream_t)hip_stream;
+  return GG_OK;
+}
+
+void gg_graph_free(gg_graph* g) {
+  if (!g) return;
+  if (g->active_run) end_run(g->active_run);
+  free_graph(g);
+}
+
+int gg_graph_get_tuning(const gg_graph* g, gg_tuning* out) {
+  if (!g || !out) return fail(GG_E_INVAL, "null argument");
+  *out = g->tune;
+  return GG_OK;
+}
+
+int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t) {
+  if (!g || !t) return fail(GG_E_INVAL, "null argument");
+  if (!valid_tuning(*t)) return fail(GG_E_INVAL, "invalid tuning");
+  if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+  g->tune = *t;
+  GG_TRY(rebin(g, g->full, nullptr));
+  if (g->ws) GG_TRY(ensure_parts(g));
+  return GG_OK;
+}
+
+int gg_graph_set_profiling(gg_graph* g, int enable) {
+  if (!g) return fail(GG_E_INVAL, "null graph");
+  if (g->stream) GG_HIP(hipStreamSynchronize(g->stream));
+  g->prof = enable != 0;
+  g->recs.clear();
+  g->pool_used = 0;
+  return GG_OK;
+}
+
+int gg_graph_get_profile(gg_graph* g, int kind, int app, gg_kernel_profile* out) {
+  if (!g || !out) return fail(GG_E_INVAL, "null argument");
+  if (kind < 0 || kind > 2 || app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "bad kind or app");
+  GG_HIP(hipStreamSynchronize(g->stream));
+  gg_kernel_profile p{0, 0.0, 0.0, 0};
+  for (const auto& r : g->recs) {
+    if (r.kind != kind || r.app != app) continue;
+    float ms = 0.f;
+    GG_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
+    p.launches++;
+    p.total_ms += ms;
+    p.alg_bytes += r.bytes;
+    p.edges += r.edges;
+  }
+  *out = p;
+  return GG_OK;
+}
+
+int gg_exact_run(gg_graph* g, const gg_app_params* params, void* out_values, uint32_t out_flags, gg_run_stats* st) {
+  gg_correction_policy pol;
+  std::memset(&pol, 0, sizeof(pol));
+  pol.kind = GG_POLICY_EXACT;
+  return whole_run(g, params, 1.0, &pol, out_values, out_flags, st);
+}
+
+int gg_approx_run(gg_graph* g, const gg_app_params* params, double sample_ratio, const gg_correction_policy* policy,
+                  void* out_values, uint32_t out_flags, gg_run_stats* st) {
+  return whole_run(g, params, sample_ratio, policy, out_values, out_flags, st);
+}
+
+int gg_run_begin(gg_graph* g, const gg_app_params* params, double sample_ratio, const gg_correction_policy* policy,
+                 gg_run** out) {
+  if (!g || !out) return fail(GG_E_INVAL, "null argument");
+  *out = nullptr;
+  gg_run* r = nullptr;
+  GG_TRY(run_begin(g, params, sample_ratio, policy, &r));
+  r->write_x_each_step = true;
+  *out = r;
+  return GG_OK;
+}
+
+int gg_run_step(gg_run* run, gg_step_info* info) {
+  if (!run) return fail(GG_E_INVAL, "null run");
+  return run_step(run, info, true);
+}
+
+int gg_run_values(gg_run* run, void* out_values, uint32_t out_flags) {
+  if (!run) return fail(GG_E_INVAL, "null run");
+  return run_values(run, out_values, out_flags);
+}
+
+int gg_run_mask(gg_run* run, uint32_t* out_bits_host) {
+  if (!run || !out_bits_host) return fail(GG_E_INVAL, "null argument");
+  gg_graph* g = run->g;
+  const size_t nw = (size_t)((g->m + 31) / 32);
+  if (run->pol.kind == GG_POLICY_EXACT) {
+    for (size_t w = 0; w < nw; ++w) {
+      const int64_t rem = g->m - (int64_t)w * 32;
+      out_bits_host[w] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+    }
+    return GG_OK;
+  }
+  if (nw == 0) return GG_OK;
+  return copy_out(g, g->bits[run->bcur], out_bits_host, nw * sizeof(uint32_t), GG_OUT_HOST);
+}
+
+int gg_run_stats_get(gg_run* run, gg_run_stats* st) {
+  if (!run || !st) return fail(GG_E_INVAL, "null argument");
+  st->iterations = run->iter;
+  st->supersteps = run->supersteps;
+  st->edges_gathered = run->edges_total;
+  st->active_edges = run->pol.kind == GG_POLICY_EXACT ? run->g->m : run->g->act.h.edges;
+  st->device_ms = 0.0;
+  return GG_OK;
+}
+
+void gg_run_end(gg_run* run) { end_run(run); }
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+"""Parity of the HIP library (called through the C ABI) with the CPU oracle.
+
+SSSP and CC must match bit for bit; PageRank within 1e-6 relative L1 (FP32
+values on the GPU against the FP64 oracle). Edge-flag decisions after every
+superstep must match exactly. Inputs are seeded synthetic graphs: the
+2^14-vertex R-MAT of the small PageRank workload, structured tiny graphs,
+and tunings that force every bin (team, wavefront, multi-chunk workgroup)
+to be used at small sizes.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from helpers import compare_values, device_values, graph_for, log, oracle_kw, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+TUNINGS = [
+    dict(small_max=16, small_team=8, wave_max=2048, hub_chunk=8192),  # default
+    dict(small_max=4, small_team=4, wave_max=32, hub_chunk=256),      # many multi-chunk hubs
+    dict(small_max=32, small_team=32, wave_max=64, hub_chunk=512),
+    dict(small_max=8, small_team=16, wave_max=128, hub_chunk=1024),
+]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_10039_amd as P
+    return P
+
+
+def load(P, g, tuning=None):
+    G = P.Graph.from_host(g)
+    if tuning:
+        G.set_tuning(**tuning)
+    return G
+
+
+def lib_run(G, app, policy, **kw):
+    if policy == "exact":
+        kw = {k: v for k, v in kw.items() if k in ("damping", "iters", "max_iters", "source", "dangling")}
+        out, st = G.exact_run(app, **kw)
+    else:
+        sr = kw.pop("sample_ratio")
+        out, st = G.approx_run(app, sr, policy, **kw)
+    return device_values(out, app), st
+
+
+def check_run(P, g, app, policy, tuning=None, ctx="", **kw):
+    log("case:", ctx, app, policy, kw, tuning)
+    G = load(P, g, tuning)
+    got, st = lib_run(G, app, policy, **dict(kw))
+    okw = oracle_kw(kw)
+    if policy == "exact":
+        okw.pop("sigma", None)
+    ref = oracle.run(g, app, policy, **okw)
+    compare_values(app, got, ref.values, ctx="%s %s %s" % (ctx, app, policy))
+    assert st.iterations == ref.iterations, (st.iterations, ref.iterations)
+    assert st.edges_gathered == ref.edges, (st.edges_gathered, ref.edges)
+    G.close()
+    return ref
+
+
+# ---------------------------------------------------------------------------
+# Exact (accurate-mode) runs
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("gi", range(len(gg.tiny_family())))
+def test_exact_tiny_family(P, gi):
+    g = gg.tiny_family()[gi]
+    check_run(P, g, "pr", "exact", ctx=g.name)
+    s = int(gg.pick_sources(g, 1, gi)[0]) if g.m else 0
+    check_run(P, g, "sssp", "exact", ctx=g.name, source=s)
+    check_run(P, g, "ppr", "exact", ctx=g.name, source=s)
+    gs = gg.from_edges(g.n, g.col, g.dst(), symmetrize=True, name=g.name + "_sym")
+    check_run(P, gs, "cc", "exact", ctx=gs.name)
+
+
+@pytest.mark.parametrize("ti", range(len(TUNINGS)))
+@pytest.mark.parametrize("app", ["pr", "sssp", "cc", "ppr"])
+def test_exact_rmat14(P, app, ti):
+    g = graph_for(app, 14, seed=1)
+    s = int(gg.pick_sources(g, 1, 1)[0])
+    check_run(P, g, app, "exact", tuning=TUNINGS[ti], ctx="rmat14", source=s)
+
+
+# ---------------------------------------------------------------------------
+# Approximate runs: whole-run outputs
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("policy", ["sp", "sms", "gg"])
+@pytest.mark.parametrize("sigma", [0.1, 0.5, 0.9])
+@pytest.mark.parametrize("app", ["sssp", "cc"])
+def test_approx_int_apps_rmat14(P, app, sigma, policy):
+    g = graph_for(app, 14, seed=1)
+    s = int(gg.pick_sources(g, 1, 1)[0])
+    L = oracle.run(g, app, "exact", source=s).iterations
+    for stop in ("fixed_iters", "fixed_point"):
+        check_run(P, g, app, policy, ctx="rmat14", sample_ratio=sigma, alpha=4, theta=0.05, seed=3, source=s,
+                  iters=L, stop=stop, max_iters=400)
+
+
+@pytest.mark.parametrize("ti", range(len(TUNINGS)))
+def test_approx_int_apps_tunings(P, ti):
+    for app in ("sssp", "cc"):
+        g = graph_for(app, 13, seed=5)
+        s = int(gg.pick_sources(g, 1, 5)[0])
+        check_run(P, g, app, "gg", tuning=TUNINGS[ti], ctx="rmat13", sample_ratio=0.3, alpha=2, theta=0.1,
+                  seed=9, source=s, iters=30, stop="fixed_iters")
+        check_run(P, g, app, "gg", tuning=TUNINGS[ti], ctx="rmat13-union", sample_ratio=0.3, alpha=2, theta=0.1,
+                  seed=9, source=s, iters=30, stop="fixed_iters", mask_update="union")
+
+
+# ---------------------------------------------------------------------------
+# Step-by-step parity with per-superstep flag comparison
+# ---------------------------------------------------------------------------
+
+def step_compare(P, g, app, policy, tuning=None, **kw):
+    """Run both sides one iteration at a time; compare values every iteration
+    and the edge flags after every superstep. Returns the worst PR error."""
+    G = load(P, g, tuning)
+    sr = kw.pop("sample_ratio", 1.0)
+    R = G.begin(app, sr, policy, **kw)
+    okw = oracle_kw(kw)
+    O = oracle.Run(g, app, policy, sigma=sr, **okw)
+    assert np.array_equal(R.mask(), O.mask()) or policy == "exact", "initial sample differs"
+    worst = 0.0
+    while True:
+        a = R.step()
+        b = O.step()
+        if a is None or b is None:
+            assert a is None and b is None, (a, b)
+            break
+        assert a["iter"] == b.iter and a["accurate"] == b.accurate and a["superstep"] == b.superstep
+        assert a["edges"] == b.edges, (a, b)
+        if app in ("sssp", "cc"):
+            assert a["changed"] == b.changed, (a, b)
+        if a["superstep"]:
+            gm, om = R.mask(), O.mask()
+            flips = np.nonzero(gm != om)[0]
+            if flips.size:
+                infl = O.influence()
+                log("flips at iter", b.iter, "edges", flips[:10].tolist(), "oracle influence",
+                    infl[flips[:10]].tolist(), "theta", kw.get("theta"))
+            assert flips.size == 0, "%d edge flags differ after superstep %d" % (flips.size, b.iter)
+            assert a["active_edges"] == b.active_edges
+        gv = R.values()
+        ov = O.values()
+        if app in ("pr", "ppr"):
+            worst = max(worst, rel_l1(gv, ov))
+        compare_values(app, gv, ov, ctx="iter %d" % b.iter)
+    R.close()
+    O.close()
+    G.close()
+    return worst
+
+
+@pytest.mark.parametrize("theta", [0.05, 0.2])
+@pytest.mark.parametrize("policy", ["gg", "sp", "sms"])
+def test_pr_steps_rmat14(P, policy, theta):
+    g = gg.rmat(14, 16, seed=1)
+    worst = step_compare(P, g, "pr", policy, sample_ratio=0.5, alpha=4, theta=theta, seed=1, iters=20)
+    log("PR %s theta %.2f worst rel L1 %.3e" % (policy, theta, worst))
+
+
+@pytest.mark.parametrize("ti", range(len(TUNINGS)))
+def test_pr_steps_tunings(P, ti):
+    g = gg.rmat(12, 16, seed=2)
+    step_compare(P, g, "pr", "gg", tuning=TUNINGS[ti], sample_ratio=0.5, alpha=2, theta=0.1, seed=4, iters=9)
+    s = int(gg.pick_sources(g, 1, 2)[0])
+    step_compare(P, g, "ppr", "gg", tuning=TUNINGS[ti], sample_ratio=0.5, alpha=2, theta=0.1, seed=4, iters=9,
+                 source=s)
+
+
+@pytest.mark.parametrize("app", ["sssp", "cc"])
+@pytest.mark.parametrize("ti", [0, 1])
+def test_int_steps_rmat14(P, app, ti):
+    g = graph_for(app, 14, seed=1)
+    s = int(gg.pick_sources(g, 1, 1)[0])
+    step_compare(P, g, app, "gg", tuning=TUNINGS[ti], sample_ratio=0.5, alpha=4, theta=0.05, seed=2, source=s,
+                 iters=25)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+
+def test_graph_without_edges(P):
+    g = gg.from_edges(5, [], [], [], name="empty5")
+    for app in ("pr", "cc", "sssp"):
+        check_run(P, g, app, "exact", ctx="empty", source=0)
+        check_run(P, g, app, "gg", ctx="empty", sample_ratio=0.5, alpha=1, theta=0.1, source=0, iters=3)
+
+
+def test_sigma_extremes_and_zero_iters(P):
+    g = gg.rmat(10, 8, seed=3, weights=True)
+    s = int(gg.pick_sources(g, 1, 3)[0])
+    for sr in (0.0, 1.0):
+        check_run(P, g, "pr", "gg", ctx="sigma", sample_ratio=sr, alpha=3, theta=0.1, iters=10)
+        check_run(P, g, "sssp", "sp", ctx="sigma", sample_ratio=sr, source=s, iters=12)
+    G = load(P, g)
+    out, st = G.exact_run("pr", iters=0)
+    assert st.iterations == 0
+    assert np.allclose(out.cpu().numpy(), 1.0 / g.n)
+
+
+def test_golden_examples_on_gpu(P):
+    """The hand-worked examples of tests/golden, run through the library."""
+    import json
+    import os
+    from fractions import Fraction
+    gdir = os.path.join(os.path.dirname(__file__), "golden")
+    fx = json.load(open(os.path.join(gdir, "sssp_superstep_4v.json")))
+    e = fx["graph"]["edges"]
+    g = gg.from_edges(4, [x[0] for x in e], [x[1] for x in e], [x[2] for x in e])
+    G = load(P, g)
+    R = G.begin("sssp", 0.0, "gg", alpha=1, theta=0.5, source=0, iters=6)
+    for it in range(1, 7):
+        R.step()
+        want = [0xFFFFFFFF if v == "INF" else int(v) for v in fx["expected"]["values_after"][str(it)]]
+        assert R.values().tolist() == want, it
+        if str(it) in fx["expected"]["mask_after"]:
+            assert R.mask().tolist() == fx["expected"]["mask_after"][str(it)], it
+    R.close()
+    fx = json.load(open(os.path.join(gdir, "pr_superstep_4v.json")))
+    e = fx["graph"]["edges"]
+    g = gg.from_edges(4, [x[0] for x in e], [x[1] for x in e])
+    G = load(P, g)
+    R = G.begin("pr", 1.0, "gg", alpha=1, theta=0.5, iters=3)
+    for it in range(1, 4):
+        R.step()
+        want = np.array([float(Fraction(v)) for v in fx["expected"]["values_after"][str(it)]])
+        assert np.max(np.abs(R.values() - want)) < 1e-7
+        if it == 2:
+            assert R.mask().tolist() == fx["expected"]["mask_after_superstep_2"]
+    R.close()
+
+
+def test_determinism(P):
+    g = gg.rmat(14, 16, seed=1)
+    G = load(P, g)
+    a, _ = G.approx_run("pr", 0.5, "gg", alpha=4, theta=0.05, seed=1)
+    a = a.cpu().numpy().copy()
+    b, _ = G.approx_run("pr", 0.5, "gg", alpha=4, theta=0.05, seed=1)
+    assert np.array_equal(a, b.cpu().numpy())
+
+
+def test_abi_errors(P):
+    import torch
+    g = gg.rmat(8, 4, seed=4)
+    # malformed CSR
+    bad = g.col.copy()
+    bad[3] = g.n + 5
+    with pytest.raises(P.GGError) as ei:
+        P.Graph(g.n, g.rowptr, bad)
+    assert ei.value.code == -2
+    rp = g.rowptr.copy()
+    rp[5], rp[6] = rp[6], rp[5] - 1
+    with pytest.raises(P.GGError) as ei:
+        P.Graph(g.n, rp, g.col)
+    assert ei.value.code == -2
+    G = P.Graph(g.n, g.rowptr, g.col)
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("pr", 1.5, "gg")
+    assert ei.value.code == -1
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("pr", 0.5, "gg", theta=-1)
+    assert ei.value.code == -1
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("pr", 0.5, "gg", alpha=-2)
+    assert ei.value.code == -1
+    with pytest.raises(P.GGError) as ei:
+        G.exact_run("sssp", source=0)  # no weights
+    assert ei.value.code == -1
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("pr", 0.5, "gg", influence="total")
+    assert ei.value.code == -5
+    # outputs untouched on failure
+    out = torch.full((g.n,), 7.0, device="cuda")
+    with pytest.raises(P.GGError):
+        G.approx_run("pr", 2.0, "gg", out=out)
+    assert torch.all(out == 7.0)
+    # one run at a time per graph
+    R = G.begin("pr", 0.5, "gg")
+    with pytest.raises(P.GGError) as ei:
+        G.begin("pr", 0.5, "gg")
+    assert ei.value.code == -6
+    R.close()
