@@ -201,14 +201,22 @@ void gg_run_end(gg_run* run);
  * rows of degree <= small_max are processed by teams of small_team lanes
  * (4, 8, 16 or 32); rows of degree <= wave_max by one 64-lane wavefront;
  * longer rows by 256-thread workgroups, split into chunks of hub_chunk edges
- * (a multiple of 256). Results do not depend on these knobs except for the
- * rounding order of PageRank sums.
+ * (a multiple of 256).
+ * With seg_enable, plain gathers over rows longer than small_max are split by
+ * source segment (seg_vertices consecutive source ids per segment; 0 = about
+ * 2 MiB of vertex values): each (row, segment) piece is reduced by blocks
+ * scheduled so that one GPU die works on one segment at a time, and the pieces
+ * are combined in segment order.
+ * Results do not depend on these knobs except for the rounding order of
+ * PageRank sums.
  */
 typedef struct {
   int32_t small_max;
   int32_t small_team;
   int32_t wave_max;
   int32_t hub_chunk;
+  int32_t seg_enable;
+  int32_t seg_vertices;
 } gg_tuning;
 
 int gg_graph_get_tuning(const gg_graph* g, gg_tuning* out);

@@ -74,7 +74,9 @@ class KernelProfile(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("small_max", ctypes.c_int32), ("small_team", ctypes.c_int32), ("wave_max", ctypes.c_int32),
-                ("hub_chunk", ctypes.c_int32)]
+                ("hub_chunk", ctypes.c_int32), ("seg_enable", ctypes.c_int32), ("seg_vertices", ctypes.c_int32)]
+
+TUNING_FIELDS = [f[0] for f in Tuning._fields_]
 
 
 # Every symbol the header declares, with its ctypes signature.
@@ -176,7 +178,7 @@ class Graph:
     device tensors (borrowed: this object keeps them alive).
     """
 
-    def __init__(self, n, rowptr, col, weight=None, stream=None, validate=True):
+    def __init__(self, n, rowptr, col, weight=None, stream=None, validate=True, m=None):
         self._keep = (rowptr, col, weight)
         dev = isinstance(rowptr, torch.Tensor) and rowptr.is_cuda
         if dev:
@@ -189,7 +191,7 @@ class Graph:
             weight = None if weight is None else np.ascontiguousarray(weight, dtype=np.int32)
             self._keep = (rowptr, col, weight)
         self.n = int(n)
-        self.m = int(col.shape[0])
+        self.m = int(col.shape[0]) if m is None else int(m)
         flags = (CSR_DEVICE_PTRS if dev else 0) | (0 if validate else CSR_SKIP_VALIDATE)
         desc = CsrDesc(self.n, self.m, _ptr(rowptr), _ptr(col), _ptr(weight), flags)
         h = ctypes.c_void_p()
@@ -201,13 +203,22 @@ class Graph:
     @classmethod
     def from_host(cls, g, device=True, stream=None, validate=True):
         """Load a graphgen.Graph-like object (n, rowptr, col, weight)."""
+        m = int(g.rowptr[-1])
         if device:
             dev = torch.device("cuda")
+
+            def up(a):
+                # at least one element, so that an empty array still has a non-null address
+                t = torch.zeros(max(m, 1), dtype=torch.int32, device=dev)
+                if m:
+                    t[:m].copy_(torch.from_numpy(np.ascontiguousarray(a[:m], dtype=np.int32)))
+                return t
+
             rp = torch.from_numpy(np.ascontiguousarray(g.rowptr, dtype=np.int32)).to(dev)
-            cl = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).to(dev)
-            w = None if g.weight is None else torch.from_numpy(np.ascontiguousarray(g.weight, dtype=np.int32)).to(dev)
+            cl = up(g.col)
+            w = None if g.weight is None else up(g.weight)
             torch.cuda.synchronize()
-            return cls(g.n, rp, cl, w, stream=stream, validate=validate)
+            return cls(g.n, rp, cl, w, stream=stream, validate=validate, m=m)
         return cls(g.n, g.rowptr, g.col, g.weight, stream=stream, validate=validate)
 
     def close(self):
@@ -232,15 +243,16 @@ class Graph:
     def get_tuning(self) -> dict:
         t = Tuning()
         _check(lib().gg_graph_get_tuning(self._h, ctypes.byref(t)))
-        return {"small_max": t.small_max, "small_team": t.small_team, "wave_max": t.wave_max,
-                "hub_chunk": t.hub_chunk}
+        return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
 
-    def set_tuning(self, small_max=None, small_team=None, wave_max=None, hub_chunk=None):
+    def set_tuning(self, **kw):
         cur = self.get_tuning()
-        t = Tuning(small_max if small_max is not None else cur["small_max"],
-                   small_team if small_team is not None else cur["small_team"],
-                   wave_max if wave_max is not None else cur["wave_max"],
-                   hub_chunk if hub_chunk is not None else cur["hub_chunk"])
+        for k, v in kw.items():
+            if k not in cur:
+                raise KeyError(k)
+            if v is not None:
+                cur[k] = int(v)
+        t = Tuning(*[cur[k] for k in TUNING_FIELDS])
         _check(lib().gg_graph_set_tuning(self._h, ctypes.byref(t)))
 
     def set_profiling(self, enable=True):

@@ -68,7 +68,19 @@ struct Sweep {
   double theta;
   uint64_t theta_q;
   int32_t mask_union;
+  // source-segmented gather of the long rows (list positions
+  // [n_small, n_small + n_wave + n_hub)): seg_off[s * nl + i] is the first edge
+  // of long row i whose source is >= s * seg_z, for s in [0, seg_s]
+  int32_t seg_s;
+  int32_t seg_z;
+  int32_t seg_qw;  // blocks per segment for the wavefront-bin long rows
+  const int32_t* seg_off;
+  double* seg_part_f;
+  uint32_t* seg_part_u;
 };
+
+// Segmented gather constants.
+constexpr int kSegRowsPerBlock = 64;  // wavefront-bin rows per (segment, batch) block
 
 // ---- launchers (gg_kernels.hip) -------------------------------------------
 hipError_t launch_outdeg(const int32_t* col, int64_t m, int32_t* outdeg, int32_t n, hipStream_t st);
@@ -108,5 +120,11 @@ hipError_t launch_superstep(int app, int team, const Sweep& s, hipStream_t st, h
                             hipEvent_t ev1 = nullptr);
 // Pack the active edges selected by s.old_bits (used after the initial sampling).
 hipError_t launch_pack(int team, const Sweep& s, hipStream_t st);
+// Segment offsets of the long rows of the binned edge set in s (source mask:
+// 0xFFFFFF for packed SSSP edge words, else all ones).
+hipError_t launch_seg_offsets(const Sweep& s, uint32_t src_mask, int32_t* seg_off, hipStream_t st);
+// Plain gather with the long rows split by source segment.
+hipError_t launch_gather_seg(int app, int team, const Sweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
 
 }  // namespace ggk

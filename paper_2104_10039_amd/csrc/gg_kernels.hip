@@ -1111,3 +1111,259 @@ hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, const int3
 }
 
 }  // namespace ggk
+
+// ===========================================================================
+// Source-segmented gather of long rows
+//
+// Rows longer than the small bin are sorted by source id, so the edges of a
+// row whose sources fall in segment s = [s*Z, (s+1)*Z) are contiguous. Each
+// (row, segment) piece is reduced separately; all pieces of one segment read
+// source values from a Z-vertex window that fits in one die's L2. Consecutive
+// block ids are dispatched to the eight dies in turn, so the block->piece map
+// keeps each die on one segment at a time. Pieces are combined per row in
+// segment order (fixed order: bitwise reproducible).
+// ===========================================================================
+namespace ggk {
+
+__device__ __forceinline__ void seg_map(int b, int S, int Q, int& seg, int& q) {
+  const int xcd = b & 7, k = b >> 3;
+  seg = xcd + 8 * (k / Q);
+  q = k % Q;
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_offsets(Sweep s, uint32_t src_mask, int32_t* seg_off) {
+  const int nl = s.n_wave + s.n_hub;
+  const int S = s.seg_s;
+  const int64_t total = (int64_t)(S + 1) * nl;
+  for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock) {
+    const int sg = (int)(t / nl);
+    const int i = (int)(t - (int64_t)sg * nl);
+    const int u = s.list[s.n_small + i];
+    const int b = s.rowptr[u];
+    const int len = row_len(s, u, b);
+    int off;
+    if (sg == 0) {
+      off = b;
+    } else if (sg == S) {
+      off = b + len;
+    } else {
+      const uint32_t key = (uint32_t)sg * (uint32_t)s.seg_z;
+      int lo = 0, hi = len;  // first position with source >= key
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((s.edges[b + mid] & src_mask) < key) lo = mid + 1;
+        else hi = mid;
+      }
+      off = b + lo;
+    }
+    seg_off[(int64_t)sg * nl + i] = off;
+  }
+}
+
+template <int APP>
+__device__ __forceinline__ void seg_store(const Sweep& s, int64_t idx, typename Tr<APP>::T v) {
+  if constexpr (APP == kPR || APP == kPPR) s.seg_part_f[idx] = v;
+  else s.seg_part_u[idx] = v;
+}
+
+// Value type a gathered edge contributes before the reduction (what LDS holds).
+template <int APP>
+struct GV {
+  using V = uint32_t;
+  static __device__ __forceinline__ V get(const Sweep& s, uint32_t e) { return Tr<APP>::elem(s, e); }
+  static __device__ __forceinline__ typename Tr<APP>::T widen(V v) { return v; }
+};
+template <>
+struct GV<kPR> {
+  using V = float;
+  static __device__ __forceinline__ V get(const Sweep& s, uint32_t e) { return s.c_in[e]; }
+  static __device__ __forceinline__ double widen(V v) { return (double)v; }
+};
+template <>
+struct GV<kPPR> : GV<kPR> {};
+
+constexpr int kFlatWin = 1024;   // edges gathered per round of a flattened batch
+
+
+// One block reduces a batch of P <= kBlock pieces [lo_p, hi_p) of the edge
+// array: every edge of the batch is gathered independently (kFlatWin per
+// round, all in flight together) into LDS, then the owner thread of each
+// piece sums its values in edge order. Returns the owner's result.
+template <int APP>
+__device__ __forceinline__ typename Tr<APP>::T flat_batch(const Sweep& s, int P, int my_lo, int my_len,
+                                                          typename GV<APP>::V* s_val, int* s_lo, int* s_scan,
+                                                          int* ilds) {
+  using R = Tr<APP>;
+  const int tid = threadIdx.x;
+  // exclusive scan of the piece lengths
+  const int len = tid < P ? my_len : 0;
+  int x = len;
+  const int lane = __lane_id(), wid = tid >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) ilds[wid] = x;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wid; ++w) before += ilds[w];
+  const int total = ilds[0] + ilds[1] + ilds[2] + ilds[3];
+  s_scan[tid] = before + x - len;
+  s_lo[tid] = my_lo;
+  if (tid == 0) s_scan[kBlock] = total;
+  __syncthreads();
+  typename R::T acc = R::id();
+  const int mine0 = s_scan[tid], mine1 = tid < P ? s_scan[tid] + len : s_scan[tid];
+  for (int base = 0; base < total; base += kFlatWin) {
+    const int lim = min(kFlatWin, total - base);
+#pragma unroll
+    for (int j = 0; j < kFlatWin / kBlock; ++j) {
+      const int k = j * kBlock + tid;
+      if (k < lim) {
+        const int kk = base + k;
+        int lo = 0, hi = P - 1;  // last piece whose start <= kk
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_scan[mid] <= kk) lo = mid;
+          else hi = mid - 1;
+        }
+        const int e = s_lo[lo] + (kk - s_scan[lo]);
+        s_val[k] = GV<APP>::get(s, ld_stream(s.edges + e));
+      }
+    }
+    __syncthreads();
+    const int a = max(mine0, base), b = min(mine1, base + lim);
+    for (int k = a; k < b; ++k) acc = R::op(acc, GV<APP>::widen(s_val[k - base]));
+    __syncthreads();
+  }
+  return acc;
+}
+
+template <int APP>
+__global__ __launch_bounds__(kBlock) void k_gather_seg(Sweep s, int gh, int gw, int gs) {
+  using R = Tr<APP>;
+  using T = typename R::T;
+  __shared__ T lds[4];
+  __shared__ int ilds[4];
+  __shared__ typename GV<APP>::V s_val[kFlatWin];
+  __shared__ int s_lo[kBlock];
+  __shared__ int s_scan[kBlock + 1];
+  int nchanged = 0;
+  const int bid = blockIdx.x;
+  const int nl = s.n_wave + s.n_hub;
+  if (bid < gh) {
+    // one block per (hub row, segment) piece
+    int sg, h;
+    seg_map(bid, s.seg_s, s.n_hub, sg, h);
+    const int i = s.n_wave + h;
+    const int lo = s.seg_off[(int64_t)sg * nl + i], hi = s.seg_off[(int64_t)(sg + 1) * nl + i];
+    T acc = R::id();
+    int k = lo + (int)threadIdx.x;
+    for (; k + 3 * kBlock < hi; k += 4 * kBlock) {
+      const uint32_t a0 = ld_stream(s.edges + k), a1 = ld_stream(s.edges + k + kBlock);
+      const uint32_t a2 = ld_stream(s.edges + k + 2 * kBlock), a3 = ld_stream(s.edges + k + 3 * kBlock);
+      const T v0 = R::elem(s, a0), v1 = R::elem(s, a1), v2 = R::elem(s, a2), v3 = R::elem(s, a3);
+      acc = R::op(acc, R::op(R::op(v0, v1), R::op(v2, v3)));
+    }
+    for (; k < hi; k += kBlock) acc = R::op(acc, R::elem(s, ld_stream(s.edges + k)));
+    acc = block_reduce<APP>(acc, lds);
+    if (threadIdx.x == 0) seg_store<APP>(s, (int64_t)sg * nl + i, acc);
+  } else if (bid < gh + gw) {
+    // (segment, batch of kSegRowsPerBlock wavefront-bin rows): flattened pieces
+    int sg, q;
+    seg_map(bid - gh, s.seg_s, s.seg_qw, sg, q);
+    const int i0 = q * kSegRowsPerBlock;
+    const int P = min(kSegRowsPerBlock, s.n_wave - i0);
+    int lo = 0, len = 0;
+    if ((int)threadIdx.x < P) {
+      const int i = i0 + threadIdx.x;
+      lo = s.seg_off[(int64_t)sg * nl + i];
+      len = s.seg_off[(int64_t)(sg + 1) * nl + i] - lo;
+    }
+    const T acc = flat_batch<APP>(s, P, lo, len, s_val, s_lo, s_scan, ilds);
+    if ((int)threadIdx.x < P) seg_store<APP>(s, (int64_t)sg * nl + i0 + threadIdx.x, acc);
+  } else {
+    // kBlock consecutive vertices: the short ones (length <= small_max) are
+    // gathered here, unsegmented, and applied; the long ones have length 0
+    // here (their pieces are combined by k_seg_combine)
+    const int u0 = (bid - gh - gw) * kBlock;
+    const int P = min(kBlock, s.n - u0);
+    const int u = u0 + (int)threadIdx.x;
+    int lo = 0, len = 0;
+    bool mine = false;
+    if ((int)threadIdx.x < P) {
+      lo = s.rowptr[u];
+      len = row_len(s, u, lo);
+      mine = len <= s.small_max;
+      if (!mine) len = 0;
+    }
+    const T acc = flat_batch<APP>(s, P, lo, len, s_val, s_lo, s_scan, ilds);
+    if (mine) apply<APP>(s, u, acc, nchanged);
+  }
+  flush_changed<APP>(s, nchanged, ilds);
+}
+
+// Combine the segment pieces of every long row in segment order and apply.
+template <int APP>
+__global__ __launch_bounds__(kBlock) void k_seg_combine(Sweep s) {
+  using R = Tr<APP>;
+  __shared__ int ilds[4];
+  int nchanged = 0;
+  const int nl = s.n_wave + s.n_hub;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nl) {
+    typename R::T acc = R::id();
+    for (int sg = 0; sg < s.seg_s; ++sg) {
+      if constexpr (APP == kPR || APP == kPPR) acc = R::op(acc, s.seg_part_f[(int64_t)sg * nl + i]);
+      else acc = R::op(acc, s.seg_part_u[(int64_t)sg * nl + i]);
+    }
+    apply<APP>(s, s.list[s.n_small + i], acc, nchanged);
+  }
+  flush_changed<APP>(s, nchanged, ilds);
+}
+
+hipError_t launch_seg_offsets(const Sweep& s, uint32_t src_mask, int32_t* seg_off, hipStream_t st) {
+  const int64_t total = (int64_t)(s.seg_s + 1) * (s.n_wave + s.n_hub);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_offsets, dim3(grid_for(total, kBlock, 1 << 16)), dim3(kBlock), 0, st, s, src_mask,
+                     seg_off);
+  return hipGetLastError();
+}
+
+template <int APP, int TEAM>
+static hipError_t gather_seg_t(const Sweep& s, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int gh = s.n_hub > 0 ? s.seg_s * s.n_hub : 0;
+  const int gw = s.n_wave > 0 ? s.seg_s * s.seg_qw : 0;
+  const int gs = (s.n + kBlock - 1) / kBlock;
+  const int total = gh + gw + gs;
+  if (ev0) (void)hipEventRecord(ev0, st);
+  if (total > 0) hipLaunchKernelGGL((k_gather_seg<APP>), dim3(total), dim3(kBlock), 0, st, s, gh, gw, gs);
+  if (ev1) (void)hipEventRecord(ev1, st);
+  const int nl = s.n_wave + s.n_hub;
+  if (nl > 0) hipLaunchKernelGGL((k_seg_combine<APP>), dim3(grid_for(nl, kBlock, 1 << 20)), dim3(kBlock), 0, st, s);
+  return hipGetLastError();
+}
+
+template <int APP>
+static hipError_t gather_seg_app(int team, const Sweep& s, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (team) {
+    case 4: return gather_seg_t<APP, 4>(s, st, ev0, ev1);
+    case 8: return gather_seg_t<APP, 8>(s, st, ev0, ev1);
+    case 16: return gather_seg_t<APP, 16>(s, st, ev0, ev1);
+    case 32: return gather_seg_t<APP, 32>(s, st, ev0, ev1);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gather_seg(int app, int team, const Sweep& s, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (app) {
+    case kPR: return gather_seg_app<kPR>(team, s, st, ev0, ev1);
+    case kPPR: return gather_seg_app<kPPR>(team, s, st, ev0, ev1);
+    case kSSSP: return gather_seg_app<kSSSP>(team, s, st, ev0, ev1);
+    case kCC: return gather_seg_app<kCC>(team, s, st, ev0, ev1);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ggk

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -85,7 +86,14 @@ struct gg_graph {
   int32_t n_dang = 0;
   int32_t* i32_scratch = nullptr;  // small device scalars: [0] dangling count, [1] validate flags
   void* blk_scratch = nullptr;
-  gg_tuning tune{16, 8, 2048, 8192};
+  gg_tuning tune{32, 4, 512, 2048, 1, 0};
+  // source segmentation of long rows (plain gathers)
+  int32_t seg_s = 8, seg_z = 1;
+  int32_t* seg_off_full = nullptr;
+  int32_t* seg_off_act = nullptr;
+  void* seg_part = nullptr;
+  int64_t seg_cap_off = 0;   // int32 entries of each offset array
+  int64_t seg_cap_part = 0;  // 8-byte entries of the partial array
   Bins full;         // binning of the full rows by in-degree
   bool full_valid = false;
   // workspace (allocated on first run)
@@ -166,6 +174,103 @@ int rebin(gg_graph* g, Bins& b, const int32_t* cnt) {
   return sync_bins(g, b);
 }
 
+// Segment count (a multiple of the 8 dies) and size for the current tuning.
+void seg_geometry(gg_graph* g) {
+  const int64_t target = g->tune.seg_vertices > 0 ? g->tune.seg_vertices : (int64_t)(2 << 20) / 4;
+  int64_t S = (g->n + target - 1) / target;
+  if (S < 1) S = 1;
+  S = (S + 7) / 8 * 8;
+  g->seg_s = (int32_t)S;
+  const int64_t z = ((int64_t)g->n + S - 1) / S;
+  g->seg_z = (int32_t)(z < 1 ? 1 : z);
+}
+
+// The offset arrays hold (S+1) entries and the partial array S entries per
+// long row of the full binning (an active binning never has more long rows).
+// Both depend on S as well as on the long-row count.
+int ensure_seg(gg_graph* g) {
+  const int64_t nl = (int64_t)g->full.h.wave + g->full.h.hub;
+  const int64_t rows = nl < 1 ? 1 : nl;
+  const int64_t need_off = ((int64_t)g->seg_s + 1) * rows;
+  const int64_t need_part = (int64_t)g->seg_s * rows;
+  if (g->seg_off_full && g->seg_cap_off >= need_off && g->seg_cap_part >= need_part) return GG_OK;
+  dfree(g->seg_off_full);
+  dfree(g->seg_off_act);
+  if (g->seg_part) (void)hipFree(g->seg_part);
+  g->seg_part = nullptr;
+  g->seg_cap_off = g->seg_cap_part = 0;
+  GG_TRY(dalloc(&g->seg_off_full, (size_t)need_off));
+  GG_TRY(dalloc(&g->seg_off_act, (size_t)need_off));
+  if (hipMalloc(&g->seg_part, (size_t)need_part * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    g->seg_part = nullptr;
+    return fail(GG_E_NOMEM, "segment partial allocation failed");
+  }
+  g->seg_cap_off = need_off;
+  g->seg_cap_part = need_part;
+  return GG_OK;
+}
+
+// Host-side capacity checks before launches that index sized scratch.
+int check_seg_capacity(const gg_graph* g, const Bins& b) {
+  const int64_t nl = (int64_t)b.h.wave + b.h.hub;
+  if (((int64_t)g->seg_s + 1) * nl > g->seg_cap_off || (int64_t)g->seg_s * nl > g->seg_cap_part)
+    return fail(GG_E_STATE, "segment arrays smaller than the binning requires");
+  return GG_OK;
+}
+
+int check_part_capacity(const gg_graph* g, const Bins& b) {
+  if ((int64_t)b.h.chunks > g->part_cap) return fail(GG_E_STATE, "hub partial array smaller than the chunk count");
+  return GG_OK;
+}
+
+void set_seg(const gg_graph* g, Sweep& s, const int32_t* off) {
+  s.seg_s = g->seg_s;
+  s.seg_z = g->seg_z;
+  s.seg_qw = (s.n_wave + kSegRowsPerBlock - 1) / kSegRowsPerBlock;
+  s.seg_off = off;
+  s.seg_part_f = (double*)g->seg_part;
+  s.seg_part_u = (uint32_t*)g->seg_part;
+}
+
+// Segment offsets of one binned view (edges: its edge array, cnt: active counts or null).
+int seg_offsets(gg_graph* g, const Bins& b, const uint32_t* edges, const int32_t* cnt, uint32_t src_mask,
+                int32_t* off) {
+  GG_TRY(check_seg_capacity(g, b));
+  Sweep s;
+  std::memset(&s, 0, sizeof(s));
+  s.n = g->n;
+  s.rowptr = g->rowptr;
+  s.cnt = cnt;
+  s.edges = edges;
+  s.list = b.list;
+  s.n_small = b.h.small;
+  s.n_wave = b.h.wave;
+  s.n_hub = b.h.hub;
+  s.seg_s = g->seg_s;
+  s.seg_z = g->seg_z;
+  GG_HIP(launch_seg_offsets(s, src_mask, off, g->stream));
+  return GG_OK;
+}
+
+// Binning of the full rows plus, with segmentation, their segment offsets.
+int rebin_full(gg_graph* g) {
+  GG_TRY(rebin(g, g->full, nullptr));
+  if (!g->tune.seg_enable) return GG_OK;
+  seg_geometry(g);
+  GG_TRY(ensure_seg(g));
+  return seg_offsets(g, g->full, (const uint32_t*)g->col, nullptr, 0xFFFFFFFFu, g->seg_off_full);
+}
+
+// Binning of the active rows plus, with segmentation, their segment offsets.
+int rebin_act(gg_graph* g, int app) {
+  GG_TRY(rebin(g, g->act, g->act_cnt));
+  if (!g->tune.seg_enable) return GG_OK;
+  GG_TRY(ensure_seg(g));
+  const uint32_t mask = app == GG_APP_SSSP ? 0xFFFFFFu : 0xFFFFFFFFu;
+  return seg_offsets(g, g->act, g->act_edges, g->act_cnt, mask, g->seg_off_act);
+}
+
 int ensure_parts(gg_graph* g) {
   const int64_t need = max_chunks(g);
   if (g->part_cap >= need) return GG_OK;
@@ -229,6 +334,9 @@ void free_graph(gg_graph* g) {
   dfree(g->part_cnt);
   dfree(g->dpartial);
   dfree(g->changed);
+  dfree(g->seg_off_full);
+  dfree(g->seg_off_act);
+  if (g->seg_part) (void)hipFree(g->seg_part);
   for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
@@ -238,7 +346,8 @@ void free_graph(gg_graph* g) {
 bool valid_tuning(const gg_tuning& t) {
   const bool team_ok = t.small_team == 4 || t.small_team == 8 || t.small_team == 16 || t.small_team == 32;
   return team_ok && t.small_max >= 0 && t.wave_max >= t.small_max && t.wave_max >= 1 && t.hub_chunk >= kBlock &&
-         (t.hub_chunk % kBlock) == 0 && t.hub_chunk <= (1 << 24);
+         (t.hub_chunk % kBlock) == 0 && t.hub_chunk <= (1 << 24) && (t.seg_enable == 0 || t.seg_enable == 1) &&
+         t.seg_vertices >= 0;
 }
 
 // ---- schedule -------------------------------------------------------------
@@ -344,7 +453,8 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
   GG_TRY(check_params(g, p, sigma, pol));
   if (g->active_run) return fail(GG_E_STATE, "another run is active on this graph");
   GG_TRY(ensure_workspace(g));
-  gg_run* r = new (std::nothrow) gg_run();
+  std::unique_ptr<gg_run> owner(new (std::nothrow) gg_run());
+  gg_run* r = owner.get();
   if (!r) return fail(GG_E_NOMEM, "host allocation failed");
   r->g = g;
   r->p = *p;
@@ -366,16 +476,13 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
     set_bins(s, g->full);
     s.edges = full_edges(g, app);
     s.old_bits = g->bits[0];
+    GG_TRY(check_part_capacity(g, g->full));
     GG_HIP(launch_pack(g->tune.small_team, s, g->stream));
-    int rc = rebin(g, g->act, g->act_cnt);
-    if (rc != GG_OK) {
-      delete r;
-      return rc;
-    }
+    GG_TRY(rebin_act(g, app));
   }
   const bool fixed_iters = is_pr(app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
   if (fixed_iters && p->iters == 0) r->done = true;
-  g->active_run = r;
+  g->active_run = owner.release();
   *out = r;
   return GG_OK;
 }
@@ -417,9 +524,10 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     s.cnt = nullptr;
     s.old_bits = g->bits[r->bcur];
     s.new_bits = g->bits[1 - r->bcur];
+    GG_TRY(check_part_capacity(g, g->full));
     GG_HIP(launch_superstep(app, g->tune.small_team, s, g->stream, pe0, pe1));
     r->bcur = 1 - r->bcur;
-    GG_TRY(rebin(g, g->act, g->act_cnt));
+    GG_TRY(rebin_act(g, app));
     r->supersteps++;
     edges = g->m;
   } else if (accurate) {
@@ -427,14 +535,28 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     set_bins(s, g->full);
     s.edges = full_edges(g, app);
     s.cnt = nullptr;
-    GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    GG_TRY(check_part_capacity(g, g->full));
+    if (g->tune.seg_enable) {
+      GG_TRY(check_seg_capacity(g, g->full));
+      set_seg(g, s, g->seg_off_full);
+      GG_HIP(launch_gather_seg(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    } else {
+      GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    }
     edges = g->m;
   } else {
     kind = 1;
     set_bins(s, g->act);
     s.edges = g->act_edges;
     s.cnt = g->act_cnt;
-    GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    GG_TRY(check_part_capacity(g, g->act));
+    if (g->tune.seg_enable) {
+      GG_TRY(check_seg_capacity(g, g->act));
+      set_seg(g, s, g->seg_off_act);
+      GG_HIP(launch_gather_seg(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    } else {
+      GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    }
     edges = g->act.h.edges;
   }
   if (g->prof) {
@@ -635,7 +757,7 @@ int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
   if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
   if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("load: ") + hipGetErrorString(e)));
   if ((rc = alloc_bins(g->full, g->n)) != GG_OK) return bail(rc);
-  if ((rc = rebin(g, g->full, nullptr)) != GG_OK) return bail(rc);
+  if ((rc = rebin_full(g)) != GG_OK) return bail(rc);
   g->full_valid = true;
   *out = g;
   return GG_OK;
@@ -665,7 +787,7 @@ int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t) {
   if (!valid_tuning(*t)) return fail(GG_E_INVAL, "invalid tuning");
   if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
   g->tune = *t;
-  GG_TRY(rebin(g, g->full, nullptr));
+  GG_TRY(rebin_full(g));
   if (g->ws) GG_TRY(ensure_parts(g));
   return GG_OK;
 }

@@ -17,10 +17,12 @@ from helpers import compare_values, device_values, graph_for, log, oracle_kw, re
 pytestmark = pytest.mark.gpu
 
 TUNINGS = [
-    dict(small_max=16, small_team=8, wave_max=2048, hub_chunk=8192),  # default
-    dict(small_max=4, small_team=4, wave_max=32, hub_chunk=256),      # many multi-chunk hubs
-    dict(small_max=32, small_team=32, wave_max=64, hub_chunk=512),
-    dict(small_max=8, small_team=16, wave_max=128, hub_chunk=1024),
+    dict(small_max=32, small_team=4, wave_max=512, hub_chunk=2048, seg_enable=1, seg_vertices=0),  # default
+    # many multi-chunk hubs, many source segments (several per die)
+    dict(small_max=4, small_team=4, wave_max=32, hub_chunk=256, seg_enable=1, seg_vertices=64),
+    dict(small_max=32, small_team=32, wave_max=64, hub_chunk=512, seg_enable=0, seg_vertices=0),
+    dict(small_max=8, small_team=16, wave_max=128, hub_chunk=1024, seg_enable=1, seg_vertices=1000),
+    dict(small_max=16, small_team=8, wave_max=2048, hub_chunk=8192, seg_enable=0, seg_vertices=0),
 ]
 
 
@@ -290,3 +292,30 @@ def test_abi_errors(P):
         G.begin("pr", 0.5, "gg")
     assert ei.value.code == -6
     R.close()
+
+
+def test_retune_same_graph(P):
+    """Regression: changing the tuning of a loaded graph (including the number
+    of source segments, up and down) re-sizes every scratch array."""
+    g = gg.rmat(13, 16, seed=6, weights=True)
+    s = int(gg.pick_sources(g, 1, 6)[0])
+    G = load(P, g)
+    ref_pr = oracle.run(g, "pr", "exact").values
+    ref_ss = oracle.run(g, "sssp", "exact", source=s).values
+    ref_gg = oracle.run(g, "sssp", "gg", sigma=0.4, alpha=2, theta=0.1, seed=5, source=s, iters=12).values
+    seq = [dict(seg_enable=1, seg_vertices=0, small_max=4),
+           dict(seg_enable=1, seg_vertices=1024, small_max=4),
+           dict(seg_enable=1, seg_vertices=128, small_max=4, wave_max=64, hub_chunk=256),
+           dict(seg_enable=0, seg_vertices=0, small_max=32),
+           dict(seg_enable=1, seg_vertices=64, small_max=2, wave_max=16, hub_chunk=256),
+           dict(seg_enable=1, seg_vertices=0, small_max=16, wave_max=2048, hub_chunk=8192)]
+    for t in seq:
+        log("retune", t)
+        G.set_tuning(**t)
+        out, _ = G.exact_run("pr")
+        compare_values("pr", device_values(out, "pr"), ref_pr, ctx=str(t))
+        out, _ = G.exact_run("sssp", source=s)
+        compare_values("sssp", device_values(out, "sssp"), ref_ss, ctx=str(t))
+        out, _ = G.approx_run("sssp", 0.4, "gg", alpha=2, theta=0.1, seed=5, source=s, iters=12)
+        compare_values("sssp", device_values(out, "sssp"), ref_gg, ctx=str(t))
+    G.close()
