@@ -131,6 +131,8 @@ typedef struct {
   int64_t edges_gathered;   /* sum over iterations of the edges gathered */
   int64_t active_edges;     /* active edges at the end of the run */
   double device_ms;         /* device time of the run (HIP events on the graph's stream) */
+  int64_t edges_processed;  /* edges actually read (frontier iterations read fewer) */
+  int32_t sparse_iterations;/* SSSP/CC iterations run as frontier pushes */
 } gg_run_stats;
 
 typedef struct {
@@ -140,6 +142,8 @@ typedef struct {
   int64_t edges;         /* edges gathered by it */
   int64_t changed;       /* SSSP/CC: vertices whose value changed; PR/PPR: -1 */
   int64_t active_edges;  /* active edges after it */
+  int64_t edges_processed; /* edges actually read by it */
+  int32_t sparse;        /* 1 if it ran as a frontier push (SSSP/CC) */
 } gg_step_info;
 
 typedef struct gg_graph gg_graph;
@@ -180,6 +184,25 @@ int gg_approx_run(gg_graph* g, const gg_app_params* params, double sample_ratio,
                   gg_run_stats* stats);
 
 /*
+ * Multi-query batch (project addition): n_queries runs of PPR or SSSP from
+ * sources_host[q] (host array, each in [0, n)) on this graph, iterated
+ * together so that every edge word is read once per iteration for all
+ * queries, with each query's values read as one contiguous run. Schemes:
+ * EXACT, and SP with one sampled edge set shared by all queries (ratio
+ * sample_ratio, policy->seed). PPR runs params->iters iterations, all
+ * captured in one HIP graph launched once; exact SSSP stops after the first
+ * iteration in which no query changed (at most params->max_iters), captured
+ * 32 iterations per graph launch with device-side early exit; SP SSSP runs
+ * params->iters iterations. Every query's result equals the corresponding
+ * single-query run. out_values: n * n_queries elements, row-major by vertex
+ * (out[u * n_queries + q]), float for PPR, uint32 for SSSP; host or device
+ * per out_flags. 1 <= n_queries <= 4096.
+ */
+int gg_batch_run(gg_graph* g, const gg_app_params* params, int32_t n_queries, const int32_t* sources_host,
+                 double sample_ratio, const gg_correction_policy* policy, void* out_values, uint32_t out_flags,
+                 gg_run_stats* stats);
+
+/*
  * Step API: the same computation as gg_approx_run (or gg_exact_run with
  * policy->kind = GG_POLICY_EXACT), one iteration per call, for tests,
  * traces and inspection. gg_run_step returns 1 when an iteration was
@@ -207,6 +230,11 @@ void gg_run_end(gg_run* run);
  * 2 MiB of vertex values): each (row, segment) piece is reduced by blocks
  * scheduled so that one GPU die works on one segment at a time, and the pieces
  * are combined in segment order.
+ * With frontier_enable, an SSSP/CC iteration whose edge set is contained in
+ * the previous iteration's runs as a push from the vertices that changed in
+ * the previous iteration (the active-vertex list of the vertex-centric model,
+ * Sec. 2.1) when their out-degree sum times frontier_div is at most m;
+ * otherwise it runs as a dense pull. Both give identical results.
  * Results do not depend on these knobs except for the rounding order of
  * PageRank sums.
  */
@@ -217,6 +245,8 @@ typedef struct {
   int32_t hub_chunk;
   int32_t seg_enable;
   int32_t seg_vertices;
+  int32_t frontier_enable;
+  int32_t frontier_div;
 } gg_tuning;
 
 int gg_graph_get_tuning(const gg_graph* g, gg_tuning* out);
@@ -228,7 +258,9 @@ int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t);
  * are counted: per gathered edge, the 4-byte edge word plus the 4-byte
  * source value; per processed row, its list entry, row offset, (active count
  * in approximate mode,) out-degree or own value, and the value written.
- * kind: 0 = accurate gather, 1 = approximate gather, 2 = superstep.
+ * kind: 0 = accurate gather, 1 = approximate gather, 2 = superstep,
+ * 3 = frontier push (SSSP/CC; per pushed edge: edge id, destination, weight
+ * and flag words and the atomic on the target).
  * gg_graph_set_profiling(g, 1) clears the counters. gg_graph_get_profile
  * synchronizes the stream and reports the totals for (kind, app).
  */

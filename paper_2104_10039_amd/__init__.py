@@ -59,12 +59,14 @@ class Policy(ctypes.Structure):
 
 class RunStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("supersteps", ctypes.c_int32), ("edges_gathered", ctypes.c_int64),
-                ("active_edges", ctypes.c_int64), ("device_ms", ctypes.c_double)]
+                ("active_edges", ctypes.c_int64), ("device_ms", ctypes.c_double), ("edges_processed", ctypes.c_int64),
+                ("sparse_iterations", ctypes.c_int32)]
 
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("accurate", ctypes.c_int32), ("superstep", ctypes.c_int32),
-                ("edges", ctypes.c_int64), ("changed", ctypes.c_int64), ("active_edges", ctypes.c_int64)]
+                ("edges", ctypes.c_int64), ("changed", ctypes.c_int64), ("active_edges", ctypes.c_int64),
+                ("edges_processed", ctypes.c_int64), ("sparse", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -74,7 +76,8 @@ class KernelProfile(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("small_max", ctypes.c_int32), ("small_team", ctypes.c_int32), ("wave_max", ctypes.c_int32),
-                ("hub_chunk", ctypes.c_int32), ("seg_enable", ctypes.c_int32), ("seg_vertices", ctypes.c_int32)]
+                ("hub_chunk", ctypes.c_int32), ("seg_enable", ctypes.c_int32), ("seg_vertices", ctypes.c_int32),
+                ("frontier_enable", ctypes.c_int32), ("frontier_div", ctypes.c_int32)]
 
 TUNING_FIELDS = [f[0] for f in Tuning._fields_]
 
@@ -99,11 +102,13 @@ SIGNATURES = {
     "gg_run_end": (None, [_VP]),
     "gg_graph_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "gg_graph_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
+    "gg_batch_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_int32, _VP, ctypes.c_double,
+                                    ctypes.POINTER(Policy), _VP, ctypes.c_uint32, ctypes.POINTER(RunStats)]),
     "gg_graph_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_graph_get_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(KernelProfile)]),
 }
 
-PROFILE_KIND = {"gather_exact": 0, "gather_approx": 1, "superstep": 2}
+PROFILE_KIND = {"gather_exact": 0, "gather_approx": 1, "superstep": 2, "push": 3}
 
 _lib = None
 
@@ -156,10 +161,13 @@ class Stats:
     edges_gathered: int
     active_edges: int
     device_ms: float
+    edges_processed: int
+    sparse_iterations: int
 
 
 def _stats(s: RunStats) -> Stats:
-    return Stats(s.iterations, s.supersteps, s.edges_gathered, s.active_edges, s.device_ms)
+    return Stats(s.iterations, s.supersteps, s.edges_gathered, s.active_edges, s.device_ms, s.edges_processed,
+                 s.sparse_iterations)
 
 
 def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform"):
@@ -288,6 +296,20 @@ class Graph:
                                    out.data_ptr(), 0, ctypes.byref(st)))
         return out, _stats(st)
 
+    def batch_run(self, app, sources, sample_ratio=1.0, policy="exact", out=None, seed=1, damping=0.85, iters=20,
+                  max_iters=1 << 20, dangling="uniform"):
+        """gg_batch_run: returns (values [n, Q] on the device, Stats)."""
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        q = int(src.shape[0])
+        if out is None:
+            out = torch.empty((self.n, q), dtype=_value_dtype(app), device="cuda")
+        p = _app_params(app, damping, iters, max_iters, 0, dangling)
+        pol = _policy(policy, 0, 0.0, seed)
+        st = RunStats()
+        _check(lib().gg_batch_run(self._h, ctypes.byref(p), q, src.ctypes.data, float(sample_ratio),
+                                  ctypes.byref(pol), out.data_ptr(), 0, ctypes.byref(st)))
+        return out, _stats(st)
+
     def begin(self, app, sample_ratio=1.0, policy="exact", **kw) -> "Run":
         return Run(self, app, sample_ratio, policy, **kw)
 
@@ -313,7 +335,8 @@ class Run:
         if r == 0:
             return None
         return {"iter": info.iter, "accurate": bool(info.accurate), "superstep": bool(info.superstep),
-                "edges": info.edges, "changed": info.changed, "active_edges": info.active_edges}
+                "edges": info.edges, "changed": info.changed, "active_edges": info.active_edges,
+                "edges_processed": info.edges_processed, "sparse": bool(info.sparse)}
 
     def values(self, host=True):
         dt = {"pr": np.float32, "ppr": np.float32, "sssp": np.uint32, "cc": np.int32}[self.app]

@@ -56,6 +56,7 @@ struct Sweep {
   const uint32_t* x_in;
   uint32_t* x_next;
   int32_t* changed;  // device counter
+  uint8_t* chg;      // nullable: per-vertex changed flag written by dense iterations
   // hub partial results (one per chunk)
   double* part_f;
   uint32_t* part_u;
@@ -81,6 +82,35 @@ struct Sweep {
 
 // Segmented gather constants.
 constexpr int kSegRowsPerBlock = 64;  // wavefront-bin rows per (segment, batch) block
+
+// Arguments of a multi-query batch launch (gg_batch.hip). Values are
+// vertex-major with padded query stride qp: value(u, q) = X[u * qp + q].
+struct BatchSweep {
+  int32_t n, qp, nslice;  // nslice = qp / 64
+  const int32_t* list;
+  const int32_t* hub_start;
+  int32_t n_small, n_wave, n_hub, n_chunks, hub_chunk;
+  const int32_t* rowptr;
+  const int32_t* cnt;
+  const uint32_t* edges;
+  // PPR
+  const float* c_in;
+  float* c_out;
+  float* x_out;  // nullable
+  const int32_t* outdeg;
+  const double* dang;  // per query dangling mass of the previous iteration
+  double damping;
+  const int32_t* src;  // qp sources (-1 for padding)
+  // SSSP
+  const uint32_t* x_in;
+  uint32_t* x_next;
+  int32_t* changed;
+  // hub partials (chunk-major, qp per chunk)
+  double* part_f;
+  uint32_t* part_u;
+  // early exit of captured SSSP loops (nullable)
+  const int32_t* done;
+};
 
 // ---- launchers (gg_kernels.hip) -------------------------------------------
 hipError_t launch_outdeg(const int32_t* col, int64_t m, int32_t* outdeg, int32_t n, hipStream_t st);
@@ -123,6 +153,42 @@ hipError_t launch_pack(int team, const Sweep& s, hipStream_t st);
 // Segment offsets of the long rows of the binned edge set in s (source mask:
 // 0xFFFFFF for packed SSSP edge words, else all ones).
 hipError_t launch_seg_offsets(const Sweep& s, uint32_t src_mask, int32_t* seg_off, hipStream_t st);
+// ---- frontier (SSSP / CC) ---------------------------------------------------
+// Counters of a frontier list: [0] count, [1] spare, [2..3] int64 sum of
+// out-degrees.
+struct FrontCounters {
+  int32_t count;
+  int32_t touched;
+  int64_t outdeg_sum;
+};
+// Exclusive scan of n int32 values (multi-block); scratch: ceil(n/1024)+1 int32.
+hipError_t launch_scan(const int32_t* in, int32_t* out, int32_t n, int32_t* total, int32_t* scratch,
+                       hipStream_t st);
+// Out-CSR structure of an in-CSR: orow[n+1] (from outdeg), oedge[m] = in-edge
+// id, odst[m] = destination row. cursor: n int32 of scratch.
+hipError_t launch_build_out(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, const int32_t* orow,
+                            int32_t* cursor, int32_t* oedge, int32_t* odst, hipStream_t st);
+// List of vertices whose chg flag is set (vertex order) with out-degree sum.
+hipError_t launch_compact_changed(const uint8_t* chg, const int32_t* outdeg, int32_t n, int32_t* list,
+                                  FrontCounters* fc, int32_t* blk_scratch, hipStream_t st);
+// Sparse push iteration from the frontier list `front` (count on the host):
+// x_next[v] = min(x_next[v], x_in[v]) for frontier v, then x_next[u] =
+// min(x_next[u], x_in[v] (+ w)) over the (active, when bits is non-null)
+// out-edges; touched destinations are appended to `touched` (stamp dedup),
+// then the changed ones (x_next < x_in) to `next`.
+hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nfront, const int32_t* orow,
+                       const int32_t* oedge, const int32_t* odst, const uint32_t* bits, uint32_t* stamp,
+                       uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc, hipStream_t st);
+
+// ---- multi-query batch (gg_batch.hip) -----------------------------------------
+hipError_t launch_batch_init(int app, int32_t n, int32_t qp, const int32_t* src, const int32_t* outdeg, float* c,
+                             uint32_t* x0, uint32_t* x1, hipStream_t st);
+hipError_t launch_batch_dangling(const BatchSweep& s, const int32_t* dlist, int32_t ndang, double* partial,
+                                 double* out, hipStream_t st);
+hipError_t launch_batch_gather(int app, const BatchSweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
+                               hipEvent_t ev1 = nullptr);
+hipError_t launch_batch_done(int32_t* changed, int32_t* done, int32_t* iters, hipStream_t st);
+
 // Plain gather with the long rows split by source segment.
 hipError_t launch_gather_seg(int app, int team, const Sweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);

@@ -186,6 +186,7 @@ __device__ __forceinline__ void apply(const Sweep& s, int u, typename Tr<APP>::T
     const uint32_t nv = min(old, acc);
     s.x_next[u] = nv;
     nchanged += (nv != old);
+    if (s.chg) s.chg[u] = (uint8_t)(nv != old);
   }
 }
 
@@ -1364,6 +1365,253 @@ hipError_t launch_gather_seg(int app, int team, const Sweep& s, hipStream_t st, 
     case kCC: return gather_seg_app<kCC>(team, s, st, ev0, ev1);
   }
   return hipErrorInvalidValue;
+}
+
+}  // namespace ggk
+
+// ===========================================================================
+// Frontier iterations for SSSP / CC (the active-vertex list of the vertex-
+// centric model): only vertices that changed in the previous iteration can
+// change their out-neighbours, provided the edge set did not grow. A sparse
+// iteration pushes from the changed vertices over their out-edges with
+// atomicMin into the next buffer, which reproduces the synchronous pull
+// result exactly (min is order-free).
+// ===========================================================================
+namespace ggk {
+
+// ---- generic multi-block exclusive scan ------------------------------------
+__global__ __launch_bounds__(1024) void k_scan_blocks(const int32_t* in, int32_t n, int32_t* blk) {
+  __shared__ int ws[16];
+  const int i = blockIdx.x * 1024 + threadIdx.x;
+  int v = i < n ? in[i] : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < 16; ++w) t += ws[w];
+    blk[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(const int32_t* in, int32_t* out, int32_t n, const int32_t* blk) {
+  __shared__ int ws[16];
+  const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
+  const int i = blockIdx.x * 1024 + tid;
+  const int v = i < n ? in[i] : 0;
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) ws[wid] = x;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wid; ++w) before += ws[w];
+  if (i < n) out[i] = blk[blockIdx.x] + before + x - v;
+}
+
+hipError_t launch_scan(const int32_t* in, int32_t* out, int32_t n, int32_t* total, int32_t* scratch,
+                       hipStream_t st) {
+  const int nb = (n + 1023) / 1024;
+  if (n == 0) return launch_fill_u32((uint32_t*)total, 1, 0u, st);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, st, in, n, scratch);
+  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, scratch, nb, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, in, out, n, scratch);
+  return hipGetLastError();
+}
+
+// ---- out-CSR structure -------------------------------------------------------
+__global__ void k_out_scatter(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, const int32_t* orow,
+                              int32_t* cursor, int32_t* oedge, int32_t* odst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = n - 1;  // the row holding edge e: last u with rowptr[u] <= e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rowptr[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    const int v = col[e];
+    const int pos = orow[v] + atomicAdd(&cursor[v], 1);
+    oedge[pos] = (int32_t)e;
+    odst[pos] = lo;
+  }
+}
+
+hipError_t launch_build_out(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, const int32_t* orow,
+                            int32_t* cursor, int32_t* oedge, int32_t* odst, hipStream_t st) {
+  hipError_t e = launch_fill_u32((uint32_t*)cursor, n, 0u, st);
+  if (e != hipSuccess || m == 0 || n == 0) return e;
+  hipLaunchKernelGGL(k_out_scatter, dim3(grid_for(m, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, rowptr, col, n, m,
+                     orow, cursor, oedge, odst);
+  return hipGetLastError();
+}
+
+// ---- changed list after a dense iteration ----------------------------------
+__global__ __launch_bounds__(kBlock) void k_chg_count(const uint8_t* chg, int n, int32_t* blk) {
+  __shared__ int ilds[4];
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  int tot;
+  block_rank(u < n && chg[u], ilds, tot);
+  if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chg_scatter(const uint8_t* chg, const int32_t* outdeg, int n,
+                                                        const int32_t* blk, int32_t* list, FrontCounters* fc) {
+  __shared__ int ilds[4];
+  __shared__ long long elds[4];
+  const int u = blockIdx.x * kBlock + threadIdx.x;
+  const bool c = u < n && chg[u];
+  int tot;
+  const int r = block_rank(c, ilds, tot);
+  if (c) list[blk[blockIdx.x] + r] = u;
+  long long d = c ? outdeg[u] : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+  if ((threadIdx.x & 63) == 0) elds[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long bsum = elds[0] + elds[1] + elds[2] + elds[3];
+    if (bsum) atomicAdd((unsigned long long*)&fc->outdeg_sum, (unsigned long long)bsum);
+  }
+}
+
+hipError_t launch_compact_changed(const uint8_t* chg, const int32_t* outdeg, int32_t n, int32_t* list,
+                                  FrontCounters* fc, int32_t* blk_scratch, hipStream_t st) {
+  hipError_t e = launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
+  if (e != hipSuccess || n == 0) return e;
+  const int nblk = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_chg_count, dim3(nblk), dim3(kBlock), 0, st, chg, n, blk_scratch);
+  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, blk_scratch, nblk, &fc->count);
+  hipLaunchKernelGGL(k_chg_scatter, dim3(nblk), dim3(kBlock), 0, st, chg, outdeg, n, blk_scratch, list, fc);
+  return hipGetLastError();
+}
+
+// ---- sparse push -----------------------------------------------------------
+// Append the lanes of this wave whose pred is set to list (one atomic per wave).
+__device__ __forceinline__ void wave_append(bool pred, int32_t val, int32_t* list, int32_t* counter) {
+  const uint64_t bal = __ballot(pred);
+  if (bal == 0) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)bal) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(bal));
+  base = __shfl(base, leader, 64);
+  if (pred) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = val;
+}
+
+template <int APP>
+__global__ __launch_bounds__(kBlock) void k_push(Sweep s, const int32_t* front, int32_t nfront, const int32_t* orow,
+                                                 const int32_t* oedge, const int32_t* odst, const uint32_t* bits,
+                                                 uint32_t* stamp, uint32_t epoch, int32_t* touched,
+                                                 FrontCounters* fc) {
+  __shared__ int ilds[4];
+  __shared__ int s_lo[kBlock];
+  __shared__ int s_scan[kBlock + 1];
+  __shared__ uint32_t s_x[kBlock];
+  const int tid = threadIdx.x;
+  const int f0 = blockIdx.x * kBlock;
+  const int P = min(kBlock, nfront - f0);
+  int lo = 0, len = 0;
+  uint32_t xv = kInf;
+  if (tid < P) {
+    const int v = front[f0 + tid];
+    lo = orow[v];
+    len = orow[v + 1] - lo;
+    xv = s.x_in[v];
+    atomicMin(&s.x_next[v], xv);  // the next buffer catches up with v's current value
+  }
+  // exclusive scan of out-degrees
+  int x = len;
+  const int lane = __lane_id(), wid = tid >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) ilds[wid] = x;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wid; ++w) before += ilds[w];
+  const int total = ilds[0] + ilds[1] + ilds[2] + ilds[3];
+  s_scan[tid] = before + x - len;
+  s_lo[tid] = lo;
+  s_x[tid] = xv;
+  __syncthreads();
+  for (int base = 0; base < total; base += kBlock) {
+    const int kk = base + tid;
+    bool newly = false;
+    int u = 0;
+    if (kk < total) {
+      int a = 0, b = P - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (s_scan[mid] <= kk) a = mid;
+        else b = mid - 1;
+      }
+      const int pos = s_lo[a] + (kk - s_scan[a]);
+      const int e = oedge[pos];
+      u = odst[pos];
+      const bool act = bits == nullptr || ((bits[e >> 5] >> (e & 31)) & 1u);
+      if (act) {
+        const uint32_t xs = s_x[a];
+        uint32_t cand;
+        if constexpr (APP == kSSSP) cand = xs == kInf ? kInf : xs + (s.edges[e] >> 24);
+        else cand = xs;
+        if (cand != kInf) {
+          const uint32_t old = atomicMin(&s.x_next[u], cand);
+          if (cand < old) newly = atomicExch(&stamp[u], epoch) != epoch;
+        }
+      }
+    }
+    wave_append(newly, u, touched, &fc->touched);
+  }
+}
+
+// Touched vertices whose value dropped below the previous iteration's form
+// the next frontier.
+__global__ __launch_bounds__(kBlock) void k_push_finalize(Sweep s, const int32_t* touched, int32_t* next,
+                                                          FrontCounters* fc) {
+  const int nt = fc->touched;
+  __shared__ long long elds[4];
+  long long dsum = 0;
+  for (int base = blockIdx.x * kBlock; base < nt; base += gridDim.x * kBlock) {
+    const int t = base + (int)threadIdx.x;
+    bool c = false;
+    int u = 0;
+    if (t < nt) {
+      u = touched[t];
+      c = s.x_next[u] < s.x_in[u];
+      if (c) dsum += s.outdeg[u];
+    }
+    wave_append(c, u, next, &fc->count);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
+  if ((threadIdx.x & 63) == 0) elds[threadIdx.x >> 6] = dsum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long b = elds[0] + elds[1] + elds[2] + elds[3];
+    if (b) atomicAdd((unsigned long long*)&fc->outdeg_sum, (unsigned long long)b);
+  }
+}
+
+hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nfront, const int32_t* orow,
+                       const int32_t* oedge, const int32_t* odst, const uint32_t* bits, uint32_t* stamp,
+                       uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc, hipStream_t st) {
+  hipError_t e = launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
+  if (e != hipSuccess || nfront == 0) return e;
+  const int g = (nfront + kBlock - 1) / kBlock;
+  if (app == kSSSP)
+    hipLaunchKernelGGL((k_push<kSSSP>), dim3(g), dim3(kBlock), 0, st, s, front, nfront, orow, oedge, odst, bits, stamp,
+                       epoch, touched, fc);
+  else
+    hipLaunchKernelGGL((k_push<kCC>), dim3(g), dim3(kBlock), 0, st, s, front, nfront, orow, oedge, odst, bits, stamp,
+                       epoch, touched, fc);
+  hipLaunchKernelGGL(k_push_finalize, dim3(1024), dim3(kBlock), 0, st, s, touched, next, fc);
+  return hipGetLastError();
 }
 
 }  // namespace ggk

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <memory>
 #include <new>
 #include <string>
@@ -86,7 +87,32 @@ struct gg_graph {
   int32_t n_dang = 0;
   int32_t* i32_scratch = nullptr;  // small device scalars: [0] dangling count, [1] validate flags
   void* blk_scratch = nullptr;
-  gg_tuning tune{32, 4, 512, 2048, 1, 0};
+  gg_tuning tune{32, 4, 512, 2048, 1, 0, 1, 16};
+  // frontier (SSSP / CC): out-CSR structure and lists, built on first use
+  bool out_built = false;
+  int32_t* orow = nullptr;
+  int32_t* oedge = nullptr;
+  int32_t* odst = nullptr;
+  uint8_t* chg = nullptr;
+  uint32_t* stamp = nullptr;
+  uint32_t epoch = 0;
+  int32_t* flist[2] = {nullptr, nullptr};
+  int32_t* touched = nullptr;
+  FrontCounters* fc = nullptr;
+  // multi-query batch workspace
+  struct Batch {
+    int64_t val_cap = 0;  // elements of each value buffer
+    void* buf[3] = {nullptr, nullptr, nullptr};
+    int64_t part_cap = 0;  // elements (chunks * qp) of the partial array
+    double* part = nullptr;
+    int32_t qp_cap = 0;
+    double* dpart = nullptr;  // 256 * qp dangling partials
+    double* dang = nullptr;   // qp
+    int32_t* src = nullptr;   // qp
+    int32_t* ctr = nullptr;   // [0] changed, [1] done, [2] iterations
+    hipStream_t cs = nullptr; // private capture stream (default priority)
+    hipEvent_t ea = nullptr, eb = nullptr, t0 = nullptr, t1 = nullptr;
+  } batch;
   // source segmentation of long rows (plain gathers)
   int32_t seg_s = 8, seg_z = 1;
   int32_t* seg_off_full = nullptr;
@@ -139,6 +165,13 @@ struct gg_run {
   bool write_x_each_step = false;
   int32_t supersteps = 0;
   int64_t edges_total = 0;
+  int64_t edges_processed = 0;
+  int32_t sparse_iters = 0;
+  // frontier state: list flist[fcur] holds the vertices changed by iteration
+  // `iter` (front_count < 0: unknown, the next iteration runs dense)
+  int fcur = 0;
+  int64_t front_count = -1;
+  int64_t front_outdeg = 0;
   bool timing = false;
 };
 
@@ -271,6 +304,33 @@ int rebin_act(gg_graph* g, int app) {
   return seg_offsets(g, g->act, g->act_edges, g->act_cnt, mask, g->seg_off_act);
 }
 
+// Out-CSR structure and frontier lists (first SSSP/CC run with the frontier on).
+int ensure_out(gg_graph* g) {
+  if (g->out_built) {
+    if (!g->orow || !g->oedge || !g->odst || !g->chg || !g->stamp || !g->flist[0] || !g->flist[1] || !g->touched ||
+        !g->fc)
+      return fail(GG_E_STATE, "frontier arrays missing");
+    return GG_OK;
+  }
+  const size_t n = (size_t)g->n, m = (size_t)g->m;
+  GG_TRY(dalloc(&g->orow, n + 1));
+  GG_TRY(dalloc(&g->oedge, m));
+  GG_TRY(dalloc(&g->odst, m));
+  GG_TRY(dalloc(&g->chg, n));
+  GG_TRY(dalloc(&g->stamp, n));
+  GG_TRY(dalloc(&g->flist[0], n));
+  GG_TRY(dalloc(&g->flist[1], n));
+  GG_TRY(dalloc(&g->touched, n));
+  GG_TRY(dalloc(&g->fc, 1));
+  GG_HIP(launch_fill_u32(g->stamp, g->n, 0u, g->stream));
+  GG_HIP(launch_scan(g->outdeg, g->orow, g->n, g->orow + g->n, (int32_t*)g->blk_scratch, g->stream));
+  // cursor scratch: the touched list is free at this point
+  GG_HIP(launch_build_out(g->rowptr, g->col, g->n, g->m, g->orow, g->touched, g->oedge, g->odst, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  g->out_built = true;
+  return GG_OK;
+}
+
 int ensure_parts(gg_graph* g) {
   const int64_t need = max_chunks(g);
   if (g->part_cap >= need) return GG_OK;
@@ -336,6 +396,25 @@ void free_graph(gg_graph* g) {
   dfree(g->changed);
   dfree(g->seg_off_full);
   dfree(g->seg_off_act);
+  dfree(g->orow);
+  dfree(g->oedge);
+  dfree(g->odst);
+  dfree(g->chg);
+  dfree(g->stamp);
+  dfree(g->flist[0]);
+  dfree(g->flist[1]);
+  dfree(g->touched);
+  dfree(g->fc);
+  for (int i = 0; i < 3; ++i)
+    if (g->batch.buf[i]) (void)hipFree(g->batch.buf[i]);
+  dfree(g->batch.part);
+  dfree(g->batch.dpart);
+  dfree(g->batch.dang);
+  dfree(g->batch.src);
+  dfree(g->batch.ctr);
+  if (g->batch.cs) (void)hipStreamDestroy(g->batch.cs);
+  for (hipEvent_t e : {g->batch.ea, g->batch.eb, g->batch.t0, g->batch.t1})
+    if (e) (void)hipEventDestroy(e);
   if (g->seg_part) (void)hipFree(g->seg_part);
   for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
@@ -347,7 +426,7 @@ bool valid_tuning(const gg_tuning& t) {
   const bool team_ok = t.small_team == 4 || t.small_team == 8 || t.small_team == 16 || t.small_team == 32;
   return team_ok && t.small_max >= 0 && t.wave_max >= t.small_max && t.wave_max >= 1 && t.hub_chunk >= kBlock &&
          (t.hub_chunk % kBlock) == 0 && t.hub_chunk <= (1 << 24) && (t.seg_enable == 0 || t.seg_enable == 1) &&
-         t.seg_vertices >= 0;
+         t.seg_vertices >= 0 && (t.frontier_enable == 0 || t.frontier_enable == 1) && t.frontier_div >= 1;
 }
 
 // ---- schedule -------------------------------------------------------------
@@ -449,6 +528,29 @@ const uint32_t* full_edges(const gg_graph* g, int app) {
   return app == GG_APP_SSSP ? g->wedges : (const uint32_t*)g->col;
 }
 
+// Initial sample of the edge flags into bits[0], the packed active edges and
+// their binning [Sec. 3.4].
+int sample_and_pack(gg_graph* g, int app, double sigma, uint64_t seed) {
+  const uint64_t keep = (uint64_t)std::floor(sigma * 4294967296.0 + 0.5);
+  GG_HIP(launch_sample_bits(g->m, seed, 0, keep, g->bits[0], g->stream));
+  Sweep s;
+  std::memset(&s, 0, sizeof(s));
+  s.n = g->n;
+  s.small_max = g->tune.small_max;
+  s.wave_max = g->tune.wave_max;
+  s.hub_chunk = g->tune.hub_chunk;
+  s.rowptr = g->rowptr;
+  s.part_cnt = g->part_cnt;
+  s.act_edges = g->act_edges;
+  s.act_cnt = g->act_cnt;
+  set_bins(s, g->full);
+  s.edges = full_edges(g, app);
+  s.old_bits = g->bits[0];
+  GG_TRY(check_part_capacity(g, g->full));
+  GG_HIP(launch_pack(g->tune.small_team, s, g->stream));
+  return rebin_act(g, app);
+}
+
 int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol, gg_run** out) {
   GG_TRY(check_params(g, p, sigma, pol));
   if (g->active_run) return fail(GG_E_STATE, "another run is active on this graph");
@@ -467,19 +569,29 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
     if (p->dangling == GG_DANGLING_NONE) GG_HIP(launch_fill_u32((uint32_t*)(g->dpartial + 256), 2, 0u, g->stream));
   } else {
     GG_HIP(launch_min_init(app, g->n, p->source, g->xu[0], g->stream));
+    GG_HIP(launch_min_init(app, g->n, p->source, g->xu[1], g->stream));
+    if (g->tune.frontier_enable) {
+      GG_TRY(ensure_out(g));
+      if (app == GG_APP_SSSP && g->n > 0) {
+        // the source is the only vertex whose value is new at iteration 0
+        const int32_t src = p->source;
+        int32_t od = 0;
+        GG_HIP(hipMemcpyAsync(g->flist[0], &src, sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
+        GG_HIP(hipMemcpyAsync(&od, g->outdeg + src, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+        GG_HIP(hipStreamSynchronize(g->stream));
+        r->fcur = 0;
+        r->front_count = 1;
+        r->front_outdeg = od;
+      } else {
+        // every label is new at iteration 0: no list is materialised, the first
+        // iteration runs dense (front_count < 0)
+        r->front_count = -1;
+        r->front_outdeg = 0;
+      }
+    }
   }
   // initial sparsification [Sec. 3.4]
-  if (pol->kind != GG_POLICY_EXACT) {
-    const uint64_t keep = (uint64_t)std::floor(sigma * 4294967296.0 + 0.5);
-    GG_HIP(launch_sample_bits(g->m, pol->seed, 0, keep, g->bits[0], g->stream));
-    Sweep s = base_sweep(g, r);
-    set_bins(s, g->full);
-    s.edges = full_edges(g, app);
-    s.old_bits = g->bits[0];
-    GG_TRY(check_part_capacity(g, g->full));
-    GG_HIP(launch_pack(g->tune.small_team, s, g->stream));
-    GG_TRY(rebin_act(g, app));
-  }
+  if (pol->kind != GG_POLICY_EXACT) GG_TRY(sample_and_pack(g, app, sigma, pol->seed));
   const bool fixed_iters = is_pr(app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
   if (fixed_iters && p->iters == 0) r->done = true;
   g->active_run = owner.release();
@@ -512,11 +624,35 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     s.x_next = g->xu[1 - r->cur];
     GG_HIP(launch_fill_u32((uint32_t*)g->changed, 1, 0u, g->stream));
   }
+  const bool frontier = !pr && g->tune.frontier_enable && g->out_built;
+  if (frontier) GG_TRY(ensure_out(g));
+  // A push from the changed vertices is exact when this iteration's edge set
+  // is contained in the previous one's: not at a superstep, not at a switch
+  // from approximate to accurate mode.
+  const bool grows = accurate && (i == 1 || !is_accurate(r->pol, i - 1)) && r->pol.kind != GG_POLICY_EXACT;
+  // front_count >= 0 only when flist[fcur] was written (source seed, dense
+  // compaction or push finalize)
+  const bool sparse = frontier && !superstep && !grows && r->front_count >= 0 && r->front_count <= g->n &&
+                      (double)r->front_outdeg * (double)g->tune.frontier_div <= (double)g->m;
+  if (frontier) s.chg = g->chg;
   int64_t edges;
+  int64_t processed;
   hipEvent_t pe0, pe1;
   GG_TRY(prof_events(g, &pe0, &pe1));
   int kind;
-  if (superstep) {
+  if (sparse) {
+    kind = accurate ? 0 : 1;
+    s.edges = full_edges(g, app);
+    const uint32_t* bits = accurate ? nullptr : g->bits[r->bcur];
+    g->epoch++;
+    if (pe0) GG_HIP(hipEventRecord(pe0, g->stream));
+    GG_HIP(launch_push(app, s, g->flist[r->fcur], (int32_t)r->front_count, g->orow, g->oedge, g->odst, bits,
+                       g->stamp, g->epoch, g->touched, g->flist[1 - r->fcur], g->fc, g->stream));
+    if (pe1) GG_HIP(hipEventRecord(pe1, g->stream));
+    edges = accurate ? g->m : g->act.h.edges;
+    processed = r->front_outdeg;
+    r->sparse_iters++;
+  } else if (superstep) {
     kind = 2;
     GG_HIP(launch_fill_u32(g->bits[1 - r->bcur], (g->m + 31) / 32, 0u, g->stream));
     set_bins(s, g->full);
@@ -530,6 +666,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     GG_TRY(rebin_act(g, app));
     r->supersteps++;
     edges = g->m;
+    processed = edges;
   } else if (accurate) {
     kind = 0;
     set_bins(s, g->full);
@@ -544,6 +681,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
       GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream, pe0, pe1));
     }
     edges = g->m;
+    processed = edges;
   } else {
     kind = 1;
     set_bins(s, g->act);
@@ -558,18 +696,38 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
       GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream, pe0, pe1));
     }
     edges = g->act.h.edges;
+    processed = edges;
   }
+  if (frontier && !sparse)
+    GG_HIP(launch_compact_changed(g->chg, g->outdeg, g->n, g->flist[1 - r->fcur], g->fc, (int32_t*)g->blk_scratch,
+                                  g->stream));
   if (g->prof) {
     double bytes = alg_bytes(kind, g->n, edges, s.x_out != nullptr);
     if (kind == 2) bytes += 4.0 * (double)g->act.h.edges + (double)((g->m + 31) / 32) * 4.0;
-    g->recs.push_back({kind, app, pe0, pe1, bytes, edges});
+    int pkind = kind;
+    if (sparse) {
+      // per pushed edge: edge id, destination, weight word, flag word (approx), atomic on the target;
+      // per frontier vertex: list entry, out-row offsets, value, sync
+      pkind = 3;
+      bytes = (accurate ? 16.0 : 20.0) * (double)processed + 16.0 * (double)r->front_count;
+    }
+    g->recs.push_back({pkind, app, pe0, pe1, bytes, processed});
   }
   r->cur = 1 - r->cur;
   r->iter = i;
   r->x_valid = pr && s.x_out != nullptr;
   r->edges_total += edges;
+  r->edges_processed += processed;
   int64_t changed = -1;
-  if (!pr && sync_changed) {
+  if (frontier) {
+    FrontCounters h;
+    GG_HIP(hipMemcpyAsync(&h, g->fc, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipStreamSynchronize(g->stream));
+    r->fcur = 1 - r->fcur;
+    r->front_count = h.count;
+    r->front_outdeg = h.outdeg_sum;
+    changed = h.count;
+  } else if (!pr && sync_changed) {
     int32_t hc = 0;
     GG_HIP(hipMemcpyAsync(&hc, g->changed, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
     GG_HIP(hipStreamSynchronize(g->stream));
@@ -593,6 +751,8 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     info->edges = edges;
     info->changed = changed;
     info->active_edges = r->pol.kind == GG_POLICY_EXACT ? g->m : g->act.h.edges;
+    info->edges_processed = processed;
+    info->sparse = sparse ? 1 : 0;
   }
   return 1;
 }
@@ -672,9 +832,219 @@ int whole_run(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
     st->edges_gathered = r->edges_total;
     st->active_edges = pol->kind == GG_POLICY_EXACT ? g->m : g->act.h.edges;
     st->device_ms = ms;
+    st->edges_processed = r->edges_processed;
+    st->sparse_iterations = r->sparse_iters;
   }
   end_run(r);
   return rc;
+}
+
+// ---- multi-query batch --------------------------------------------------------
+
+int ensure_batch(gg_graph* g, int32_t qp) {
+  auto& B = g->batch;
+  const int64_t need_val = (int64_t)g->n * qp;
+  if (B.val_cap < need_val) {
+    for (int i = 0; i < 3; ++i) {
+      if (B.buf[i]) (void)hipFree(B.buf[i]);
+      B.buf[i] = nullptr;
+    }
+    B.val_cap = 0;
+    for (int i = 0; i < 3; ++i) {
+      if (hipMalloc(&B.buf[i], (size_t)(need_val > 0 ? need_val : 1) * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GG_E_NOMEM, "batch value buffers");
+      }
+    }
+    B.val_cap = need_val;
+  }
+  const int64_t need_part = max_chunks(g) * (int64_t)qp;
+  if (B.part_cap < need_part) {
+    dfree(B.part);
+    B.part_cap = 0;
+    GG_TRY(dalloc(&B.part, (size_t)need_part));
+    B.part_cap = need_part;
+  }
+  if (B.qp_cap < qp) {
+    dfree(B.dpart);
+    dfree(B.dang);
+    dfree(B.src);
+    B.qp_cap = 0;
+    GG_TRY(dalloc(&B.dpart, (size_t)256 * qp));
+    GG_TRY(dalloc(&B.dang, (size_t)qp));
+    GG_TRY(dalloc(&B.src, (size_t)qp));
+    B.qp_cap = qp;
+  }
+  if (!B.ctr) GG_TRY(dalloc(&B.ctr, 4));
+  if (!B.cs) GG_HIP(hipStreamCreateWithFlags(&B.cs, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&B.ea, &B.eb, &B.t0, &B.t1})
+    if (!*e) GG_HIP(hipEventCreate(e));
+  return GG_OK;
+}
+
+// Capture `body` on the batch stream into a graph, instantiate and launch it.
+template <typename F>
+int capture_launch(gg_graph* g, F&& body) {
+  auto& B = g->batch;
+  GG_HIP(hipStreamBeginCapture(B.cs, hipStreamCaptureModeThreadLocal));
+  int rc = body(B.cs);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(B.cs, &graph);
+  if (rc != GG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(GG_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(exec, B.cs);
+  // the executable graph is destroyed only after its work has completed
+  const hipError_t es = hipStreamSynchronize(B.cs);
+  if (e == hipSuccess) e = es;
+  if (exec) (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(GG_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  return GG_OK;
+}
+
+int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* sources, double sigma,
+              const gg_correction_policy* pol, void* out, uint32_t flags, gg_run_stats* st) {
+  if (!g || !p || !pol || !sources || !out) return fail(GG_E_INVAL, "null argument");
+  if (p->app != GG_APP_PPR && p->app != GG_APP_SSSP) return fail(GG_E_UNSUPPORTED, "batch runs support PPR and SSSP");
+  if (pol->kind != GG_POLICY_EXACT && pol->kind != GG_POLICY_SP)
+    return fail(GG_E_UNSUPPORTED, "batch runs support the EXACT and SP schemes");
+  if (nq < 1 || nq > 4096) return fail(GG_E_INVAL, "n_queries outside [1, 4096]");
+  if (!(sigma >= 0.0 && sigma <= 1.0)) return fail(GG_E_INVAL, "sample_ratio outside [0, 1]");
+  if (p->app == GG_APP_SSSP && !g->wedges) return fail(GG_E_INVAL, "SSSP needs edge weights");
+  if (p->app == GG_APP_PPR && !(p->damping >= 0.0 && p->damping < 1.0)) return fail(GG_E_INVAL, "bad damping");
+  for (int32_t q = 0; q < nq; ++q)
+    if (sources[q] < 0 || sources[q] >= g->n) return fail(GG_E_INVAL, "source out of range");
+  const bool ppr = p->app == GG_APP_PPR;
+  const bool fixed = ppr || pol->kind != GG_POLICY_EXACT;
+  const int32_t T = fixed ? p->iters : p->max_iters;
+  if (T <= 0) return fail(GG_E_INVAL, "batch runs need at least one iteration");
+  if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+  const int32_t qp = (nq + 63) / 64 * 64;
+  GG_TRY(ensure_workspace(g));
+  GG_TRY(ensure_batch(g, qp));
+  auto& B = g->batch;
+  // stream order: graph stream -> batch stream
+  GG_HIP(hipEventRecord(B.ea, g->stream));
+  GG_HIP(hipStreamWaitEvent(B.cs, B.ea, 0));
+  GG_HIP(hipEventRecord(B.t0, B.cs));
+  std::vector<int32_t> hs(qp, -1);
+  for (int32_t q = 0; q < nq; ++q) hs[q] = sources[q];
+  GG_HIP(hipMemcpyAsync(B.src, hs.data(), sizeof(int32_t) * qp, hipMemcpyHostToDevice, B.cs));
+  GG_HIP(hipStreamSynchronize(B.cs));
+  const int app = p->app;
+  // shared edge set: all edges, or the sample of ratio sigma (one mask for all queries)
+  const bool approx = pol->kind != GG_POLICY_EXACT;
+  if (approx) {
+    hipStream_t keep = g->stream;
+    g->stream = B.cs;
+    int rc = sample_and_pack(g, app, sigma, pol->seed);
+    g->stream = keep;
+    GG_TRY(rc);
+  }
+  const Bins& bins = approx ? g->act : g->full;
+  if ((int64_t)bins.h.chunks * qp > B.part_cap) return fail(GG_E_STATE, "batch partial array too small");
+  BatchSweep s;
+  std::memset(&s, 0, sizeof(s));
+  s.n = g->n;
+  s.qp = qp;
+  s.nslice = qp / 64;
+  s.list = bins.list;
+  s.hub_start = bins.hub_start;
+  s.n_small = bins.h.small;
+  s.n_wave = bins.h.wave;
+  s.n_hub = bins.h.hub;
+  s.n_chunks = bins.h.chunks;
+  s.hub_chunk = g->tune.hub_chunk;
+  s.rowptr = g->rowptr;
+  s.cnt = approx ? g->act_cnt : nullptr;
+  s.edges = approx ? g->act_edges : full_edges(g, app);
+  s.outdeg = g->outdeg;
+  s.dang = B.dang;
+  s.damping = p->damping;
+  s.src = B.src;
+  s.changed = B.ctr;
+  s.part_f = B.part;
+  s.part_u = (uint32_t*)B.part;
+  float* C[2] = {(float*)B.buf[0], (float*)B.buf[1]};
+  float* X = (float*)B.buf[2];
+  uint32_t* U[2] = {(uint32_t*)B.buf[0], (uint32_t*)B.buf[1]};
+  GG_HIP(launch_batch_init(app, g->n, qp, B.src, g->outdeg, C[0], U[0], U[1], B.cs));
+  GG_HIP(launch_fill_u32((uint32_t*)B.ctr, 4, 0u, B.cs));
+  if (ppr && p->dangling == GG_DANGLING_NONE) GG_HIP(launch_fill_u32((uint32_t*)B.dang, 2 * (int64_t)qp, 0u, B.cs));
+  int32_t iters = 0;
+  if (ppr) {
+    // all T iterations in one captured graph
+    GG_TRY(capture_launch(g, [&](hipStream_t cs) -> int {
+      for (int32_t i = 1; i <= T; ++i) {
+        BatchSweep t = s;
+        t.c_in = C[(i - 1) & 1];
+        t.c_out = C[i & 1];
+        t.x_out = i == T ? X : nullptr;
+        if (p->dangling == GG_DANGLING_UNIFORM)
+          GG_HIP(launch_batch_dangling(t, g->dang, g->n_dang, B.dpart, B.dang, cs));
+        GG_HIP(launch_batch_gather(app, t, cs));
+      }
+      return GG_OK;
+    }));
+    iters = T;
+  } else {
+    // SSSP: chunks of K iterations; without a fixed count, every iteration
+    // exits early once an iteration changed nothing (device flag)
+    const int K = fixed ? (T > 0 ? T : 0) : 32;
+    int32_t done_iters = 0;
+    while (K > 0) {
+      const int32_t kk = fixed ? T : std::min(K, T - done_iters);
+      if (kk <= 0) break;
+      GG_TRY(capture_launch(g, [&](hipStream_t cs) -> int {
+        for (int32_t i = 0; i < kk; ++i) {
+          BatchSweep t = s;
+          t.x_in = U[(done_iters + i) & 1];
+          t.x_next = U[(done_iters + i + 1) & 1];
+          t.done = fixed ? nullptr : B.ctr + 1;
+          GG_HIP(launch_batch_gather(app, t, cs));
+          if (!fixed) GG_HIP(launch_batch_done(B.ctr, B.ctr + 1, B.ctr + 2, cs));
+        }
+        return GG_OK;
+      }));
+      if (fixed) {
+        iters = T;
+        break;
+      }
+      int32_t h[3];
+      GG_HIP(hipMemcpyAsync(h, B.ctr, sizeof(h), hipMemcpyDeviceToHost, B.cs));
+      GG_HIP(hipStreamSynchronize(B.cs));
+      done_iters += kk;
+      iters = h[2];
+      if (h[1] || done_iters >= T) break;
+    }
+  }
+  GG_HIP(hipEventRecord(B.t1, B.cs));
+  // values out: n rows of nq elements (drop the query padding)
+  const void* src_buf = ppr ? (const void*)X : (const void*)U[iters & 1];
+  const hipMemcpyKind kind = (flags & GG_OUT_HOST) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (g->n > 0)
+    GG_HIP(hipMemcpy2DAsync(out, (size_t)nq * 4, src_buf, (size_t)qp * 4, (size_t)nq * 4, (size_t)g->n, kind, B.cs));
+  GG_HIP(hipEventRecord(B.eb, B.cs));
+  GG_HIP(hipStreamWaitEvent(g->stream, B.eb, 0));
+  GG_HIP(hipStreamSynchronize(B.cs));
+  if (st) {
+    float ms = 0.f;
+    GG_HIP(hipEventElapsedTime(&ms, B.t0, B.t1));
+    const int64_t eset = approx ? bins.h.edges : g->m;
+    st->iterations = iters;
+    st->supersteps = 0;
+    st->edges_gathered = eset * (int64_t)iters * nq;
+    st->active_edges = eset;
+    st->device_ms = ms;
+    st->edges_processed = st->edges_gathered;
+    st->sparse_iterations = 0;
+  }
+  return GG_OK;
 }
 
 }  // namespace
@@ -803,7 +1173,7 @@ int gg_graph_set_profiling(gg_graph* g, int enable) {
 
 int gg_graph_get_profile(gg_graph* g, int kind, int app, gg_kernel_profile* out) {
   if (!g || !out) return fail(GG_E_INVAL, "null argument");
-  if (kind < 0 || kind > 2 || app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "bad kind or app");
+  if (kind < 0 || kind > 3 || app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "bad kind or app");
   GG_HIP(hipStreamSynchronize(g->stream));
   gg_kernel_profile p{0, 0.0, 0.0, 0};
   for (const auto& r : g->recs) {
@@ -817,6 +1187,12 @@ int gg_graph_get_profile(gg_graph* g, int kind, int app, gg_kernel_profile* out)
   }
   *out = p;
   return GG_OK;
+}
+
+int gg_batch_run(gg_graph* g, const gg_app_params* params, int32_t n_queries, const int32_t* sources_host,
+                 double sample_ratio, const gg_correction_policy* policy, void* out_values, uint32_t out_flags,
+                 gg_run_stats* stats) {
+  return batch_run(g, params, n_queries, sources_host, sample_ratio, policy, out_values, out_flags, stats);
 }
 
 int gg_exact_run(gg_graph* g, const gg_app_params* params, void* out_values, uint32_t out_flags, gg_run_stats* st) {
@@ -874,6 +1250,8 @@ int gg_run_stats_get(gg_run* run, gg_run_stats* st) {
   st->edges_gathered = run->edges_total;
   st->active_edges = run->pol.kind == GG_POLICY_EXACT ? run->g->m : run->g->act.h.edges;
   st->device_ms = 0.0;
+  st->edges_processed = run->edges_processed;
+  st->sparse_iterations = run->sparse_iters;
   return GG_OK;
 }
 

@@ -1,0 +1,94 @@
+"""Multi-query batch runs (many PPR / SSSP queries in one captured HIP graph):
+every query equals the single-query CPU oracle run from its source."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from helpers import compare_values, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_10039_amd as P
+    return P
+
+
+def check_batch(P, g, app, nq, policy="exact", sigma=1.0, tuning=None, n_check=6, **kw):
+    G = P.Graph.from_host(g)
+    if tuning:
+        G.set_tuning(**tuning)
+    srcs = gg.pick_sources(g, nq, 77 + nq)
+    log("batch case:", g.name, app, nq, policy, sigma, tuning)
+    out, st = G.batch_run(app, srcs, sample_ratio=sigma, policy=policy, seed=5, **kw)
+    got = out.cpu().numpy()
+    if app == "sssp":
+        got = got.view(np.uint32)
+    rng = np.random.default_rng(nq)
+    picks = sorted(set([0, nq - 1] + rng.integers(0, nq, size=n_check).tolist()))
+    iters = []
+    for q in picks:
+        okw = dict(source=int(srcs[q]), iters=kw.get("iters", 20))
+        if policy != "exact":
+            okw.update(sigma=sigma, seed=5)
+        ref = oracle.run(g, app, policy, **okw)
+        compare_values(app, got[:, q], ref.values, ctx="query %d" % q)
+        iters.append(ref.iterations)
+    if app == "sssp" and policy == "exact":
+        assert st.iterations >= max(iters)
+    G.close()
+    return st
+
+
+@pytest.mark.parametrize("nq", [1, 64, 70, 256])
+def test_batch_ppr_exact(P, nq):
+    g = gg.rmat(12, 16, seed=11)
+    st = check_batch(P, g, "ppr", nq, iters=20)
+    assert st.iterations == 20
+
+
+@pytest.mark.parametrize("nq", [1, 64, 130])
+def test_batch_sssp_exact(P, nq):
+    g = gg.rmat(12, 16, seed=12, weights=True)
+    check_batch(P, g, "sssp", nq)
+
+
+def test_batch_exact_sssp_stops_at_the_slowest_query(P):
+    g = gg.rmat(11, 8, seed=15, weights=True)
+    srcs = gg.pick_sources(g, 40, 3)
+    G = P.Graph.from_host(g)
+    out, st = G.batch_run("sssp", srcs)
+    L = max(oracle.run(g, "sssp", "exact", source=int(s)).iterations for s in srcs)
+    assert st.iterations == L
+
+
+@pytest.mark.parametrize("app", ["ppr", "sssp"])
+@pytest.mark.parametrize("sigma", [0.3, 0.8])
+def test_batch_sp(P, app, sigma):
+    g = gg.rmat(12, 16, seed=13, weights=True)
+    check_batch(P, g, app, 96, policy="sp", sigma=sigma, iters=15)
+
+
+@pytest.mark.parametrize("app", ["ppr", "sssp"])
+def test_batch_hub_chunks(P, app):
+    """Small hub chunks force the chunked path and its combine."""
+    g = gg.rmat(13, 16, seed=14, weights=True)
+    check_batch(P, g, app, 64, tuning=dict(small_max=4, wave_max=16, hub_chunk=256), iters=12)
+
+
+def test_batch_rejects_bad_input(P):
+    g = gg.rmat(8, 4, seed=16, weights=True)
+    G = P.Graph.from_host(g)
+    with pytest.raises(P.GGError):
+        G.batch_run("ppr", [g.n + 1])
+    with pytest.raises(P.GGError) as ei:
+        G.batch_run("cc", [0])
+    assert ei.value.code == -5
+    with pytest.raises(P.GGError) as ei:
+        G.batch_run("ppr", [0], policy="gg")
+    assert ei.value.code == -5

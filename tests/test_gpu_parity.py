@@ -17,12 +17,18 @@ from helpers import compare_values, device_values, graph_for, log, oracle_kw, re
 pytestmark = pytest.mark.gpu
 
 TUNINGS = [
-    dict(small_max=32, small_team=4, wave_max=512, hub_chunk=2048, seg_enable=1, seg_vertices=0),  # default
-    # many multi-chunk hubs, many source segments (several per die)
-    dict(small_max=4, small_team=4, wave_max=32, hub_chunk=256, seg_enable=1, seg_vertices=64),
-    dict(small_max=32, small_team=32, wave_max=64, hub_chunk=512, seg_enable=0, seg_vertices=0),
-    dict(small_max=8, small_team=16, wave_max=128, hub_chunk=1024, seg_enable=1, seg_vertices=1000),
-    dict(small_max=16, small_team=8, wave_max=2048, hub_chunk=8192, seg_enable=0, seg_vertices=0),
+    # default
+    dict(small_max=32, small_team=4, wave_max=512, hub_chunk=2048, seg_enable=1, seg_vertices=0,
+         frontier_enable=1, frontier_div=16),
+    # many multi-chunk hubs, many source segments (several per die), push whenever the frontier allows
+    dict(small_max=4, small_team=4, wave_max=32, hub_chunk=256, seg_enable=1, seg_vertices=64,
+         frontier_enable=1, frontier_div=1),
+    dict(small_max=32, small_team=32, wave_max=64, hub_chunk=512, seg_enable=0, seg_vertices=0,
+         frontier_enable=0, frontier_div=16),
+    dict(small_max=8, small_team=16, wave_max=128, hub_chunk=1024, seg_enable=1, seg_vertices=1000,
+         frontier_enable=1, frontier_div=4),
+    dict(small_max=16, small_team=8, wave_max=2048, hub_chunk=8192, seg_enable=0, seg_vertices=0,
+         frontier_enable=0, frontier_div=16),
 ]
 
 
@@ -139,6 +145,8 @@ def step_compare(P, g, app, policy, tuning=None, **kw):
             break
         assert a["iter"] == b.iter and a["accurate"] == b.accurate and a["superstep"] == b.superstep
         assert a["edges"] == b.edges, (a, b)
+        if a.get("sparse"):
+            log("iter", b.iter, "ran as a frontier push over", a["edges_processed"], "edges")
         if app in ("sssp", "cc"):
             assert a["changed"] == b.changed, (a, b)
         if a["superstep"]:
@@ -179,7 +187,7 @@ def test_pr_steps_tunings(P, ti):
 
 
 @pytest.mark.parametrize("app", ["sssp", "cc"])
-@pytest.mark.parametrize("ti", [0, 1])
+@pytest.mark.parametrize("ti", range(len(TUNINGS)))
 def test_int_steps_rmat14(P, app, ti):
     g = graph_for(app, 14, seed=1)
     s = int(gg.pick_sources(g, 1, 1)[0])
@@ -318,4 +326,23 @@ def test_retune_same_graph(P):
         compare_values("sssp", device_values(out, "sssp"), ref_ss, ctx=str(t))
         out, _ = G.approx_run("sssp", 0.4, "gg", alpha=2, theta=0.1, seed=5, source=s, iters=12)
         compare_values("sssp", device_values(out, "sssp"), ref_gg, ctx=str(t))
+    G.close()
+
+
+@pytest.mark.parametrize("app", ["sssp", "cc"])
+def test_frontier_push_used_and_exact(P, app):
+    """The frontier path runs (some iterations are pushes) and stays bit-exact,
+    for the exact baseline and for the sampled schemes."""
+    g = graph_for(app, 14, seed=8)
+    s = int(gg.pick_sources(g, 1, 8)[0])
+    G = load(P, g, dict(frontier_enable=1, frontier_div=4))
+    out, st = G.exact_run(app, source=s)
+    ref = oracle.run(g, app, "exact", source=s)
+    compare_values(app, device_values(out, app), ref.values, ctx="exact frontier")
+    assert st.sparse_iterations > 0 and st.edges_processed < st.edges_gathered
+    for pol in ("sp", "sms", "gg"):
+        out, st = G.approx_run(app, 0.5, pol, alpha=3, theta=0.1, seed=2, source=s, iters=ref.iterations + 5)
+        want = oracle.run(g, app, pol, sigma=0.5, alpha=3, theta=0.1, seed=2, source=s, iters=ref.iterations + 5)
+        compare_values(app, device_values(out, app), want.values, ctx=pol)
+        assert st.edges_gathered == want.edges
     G.close()
