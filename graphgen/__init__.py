@@ -266,3 +266,47 @@ def tiny_family():
     for s in range(8):
         gs.append(random_small(6 + s, 4 * (6 + s), seed=100 + s))
     return gs
+
+
+def union(graphs, name: str = "union"):
+    """Block-diagonal union of graphs: graph p's vertices are offset by the
+    vertex count of graphs 0..p-1. Returns (Graph, part_start) with
+    part_start[p] = first vertex of graph p and part_start[-1] = n."""
+    part_start = [0]
+    rowptrs, cols, weights = [], [], []
+    e_off = 0
+    for g in graphs:
+        rowptrs.append(np.asarray(g.rowptr[:-1], dtype=np.int64) + e_off)
+        cols.append(np.asarray(g.col, dtype=np.int64) + part_start[-1])
+        weights.append(g.weight)
+        e_off += g.m
+        part_start.append(part_start[-1] + g.n)
+    n = part_start[-1]
+    rowptr = np.concatenate(rowptrs + [np.array([e_off])]).astype(np.int32)
+    col = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
+    w = None
+    if all(x is not None for x in weights):
+        w = np.concatenate(weights).astype(np.int32)
+    return Graph(n=n, rowptr=rowptr, col=col, weight=w, name=name), np.array(part_start, dtype=np.int32)
+
+
+def part(g: Graph, part_start, p: int) -> Graph:
+    """Graph p of a block-diagonal union, with local vertex ids."""
+    v0, v1 = int(part_start[p]), int(part_start[p + 1])
+    e0, e1 = int(g.rowptr[v0]), int(g.rowptr[v1])
+    rowptr = (g.rowptr[v0:v1 + 1] - e0).astype(np.int32)
+    col = (g.col[e0:e1] - v0).astype(np.int32)
+    w = None if g.weight is None else g.weight[e0:e1].copy()
+    return Graph(n=v1 - v0, rowptr=rowptr, col=col, weight=w, name="%s[%d]" % (g.name, p))
+
+
+def rmat_family(count: int, scale_range=(10, 18), ef_range=(8, 32), seed0: int = 100, weights: bool = True,
+                symmetrize: bool = False):
+    """`count` independent R-MAT graphs with scale ~ U{scale_range} (log-uniform
+    vertex counts) and edge factor ~ U{ef_range}; graph g uses seed seed0 + g."""
+    out = []
+    for k in range(count):
+        sc = scale_range[0] + int(draw(seed0 + k, 0, 0) % (scale_range[1] - scale_range[0] + 1))
+        ef = ef_range[0] + int(draw(seed0 + k, 0, 1) % (ef_range[1] - ef_range[0] + 1))
+        out.append(rmat(sc, ef, seed=seed0 + k, weights=weights, symmetrize=symmetrize))
+    return out

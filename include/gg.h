@@ -203,6 +203,21 @@ int gg_batch_run(gg_graph* g, const gg_app_params* params, int32_t n_queries, co
                  gg_run_stats* stats);
 
 /*
+ * Independent parts (project addition, the multi-graph batch): declare the
+ * loaded graph a block-diagonal union of n_parts graphs, part p owning
+ * vertices [part_start_host[p], part_start_host[p+1]) (host array, starts at
+ * 0, ends at n, non-decreasing); no edge may cross parts (GG_E_RANGE). Every
+ * run then treats each part as its own graph, in the same launches: PageRank
+ * uses the part's vertex count and dangling mass; SSSP starts from
+ * part_sources_host[p] in every part (host array, required for SSSP,
+ * params->source is ignored); edge sampling draws part p's edges by their
+ * index inside the part with seed + p. PPR and batch runs are not supported
+ * on parts. n_parts = 0 removes the parts.
+ */
+int gg_graph_set_parts(gg_graph* g, int32_t n_parts, const int32_t* part_start_host,
+                       const int32_t* part_sources_host);
+
+/*
  * Step API: the same computation as gg_approx_run (or gg_exact_run with
  * policy->kind = GG_POLICY_EXACT), one iteration per call, for tests,
  * traces and inspection. gg_run_step returns 1 when an iteration was

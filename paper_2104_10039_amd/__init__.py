@@ -104,6 +104,7 @@ SIGNATURES = {
     "gg_graph_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "gg_batch_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_int32, _VP, ctypes.c_double,
                                     ctypes.POINTER(Policy), _VP, ctypes.c_uint32, ctypes.POINTER(RunStats)]),
+    "gg_graph_set_parts": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
     "gg_graph_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_graph_get_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(KernelProfile)]),
 }
@@ -262,6 +263,17 @@ class Graph:
                 cur[k] = int(v)
         t = Tuning(*[cur[k] for k in TUNING_FIELDS])
         _check(lib().gg_graph_set_tuning(self._h, ctypes.byref(t)))
+
+    def set_parts(self, part_start, part_sources=None):
+        """gg_graph_set_parts: part_start has n_parts + 1 entries (None or [] clears)."""
+        if part_start is None or len(part_start) == 0:
+            _check(lib().gg_graph_set_parts(self._h, 0, None, None))
+            return
+        ps = np.ascontiguousarray(part_start, dtype=np.int32)
+        src = None if part_sources is None else np.ascontiguousarray(part_sources, dtype=np.int32)
+        self._parts = (ps, src)
+        _check(lib().gg_graph_set_parts(self._h, int(ps.shape[0]) - 1, ps.ctypes.data,
+                                        None if src is None else src.ctypes.data))
 
     def set_profiling(self, enable=True):
         _check(lib().gg_graph_set_profiling(self._h, 1 if enable else 0))

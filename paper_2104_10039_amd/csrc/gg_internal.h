@@ -49,6 +49,11 @@ struct Sweep {
   float* x_out;  // nullable: PR value (written when non-null)
   const int32_t* outdeg;
   const double* dangling;  // device scalar: dangling mass of the previous iteration
+  // independent parts (block-diagonal union), nullable: PR uses each part's
+  // vertex count and dangling mass part_dang[p]
+  const int32_t* part_of;
+  const int32_t* part_start;
+  const double* part_dang;
   double damping;
   double base;  // (1 - d) / n for PR
   int32_t source;
@@ -133,7 +138,9 @@ hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, in
                         int32_t wave_max, int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st);
 
 // PR/PPR initial contributions.
-hipError_t launch_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, float* c, hipStream_t st);
+// part_of / part_start nullable (PR: 1/N per part when set).
+hipError_t launch_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, const int32_t* part_of,
+                          const int32_t* part_start, float* c, hipStream_t st);
 hipError_t launch_min_init(int app, int32_t n, int32_t source, uint32_t* x, hipStream_t st);
 
 // Initial sampling of the edge flags: bit (e mod 32) of word e/32 is set iff
@@ -148,6 +155,10 @@ hipError_t launch_gather(int app, int team, const Sweep& s, hipStream_t st, hipE
 // Superstep: accurate gather-apply plus influence, flags and repacking.
 hipError_t launch_superstep(int app, int team, const Sweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr);
+// Superstep with flattened batches for rows of degree <= wave_max (owner
+// threads walk each row in CSR order) and the chunked path for longer rows.
+hipError_t launch_superstep_flat(int app, const Sweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
+                                 hipEvent_t ev1 = nullptr);
 // Pack the active edges selected by s.old_bits (used after the initial sampling).
 hipError_t launch_pack(int team, const Sweep& s, hipStream_t st);
 // Segment offsets of the long rows of the binned edge set in s (source mask:
@@ -169,16 +180,39 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int32_t n, int32_t* tota
 hipError_t launch_build_out(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, const int32_t* orow,
                             int32_t* cursor, int32_t* oedge, int32_t* odst, hipStream_t st);
 // List of vertices whose chg flag is set (vertex order) with out-degree sum.
+// psum: int64 scratch of max(ceil(n / kBlock), 1024) entries.
 hipError_t launch_compact_changed(const uint8_t* chg, const int32_t* outdeg, int32_t n, int32_t* list,
-                                  FrontCounters* fc, int32_t* blk_scratch, hipStream_t st);
+                                  FrontCounters* fc, int32_t* blk_scratch, int64_t* psum, hipStream_t st);
 // Sparse push iteration from the frontier list `front` (count on the host):
 // x_next[v] = min(x_next[v], x_in[v]) for frontier v, then x_next[u] =
 // min(x_next[u], x_in[v] (+ w)) over the (active, when bits is non-null)
 // out-edges; touched destinations are appended to `touched` (stamp dedup),
 // then the changed ones (x_next < x_in) to `next`.
-hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nfront, const int32_t* orow,
-                       const int32_t* oedge, const int32_t* odst, const uint32_t* bits, uint32_t* stamp,
-                       uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc, hipStream_t st);
+// Edge-balanced: fdeg (n) and fscan (n + 1) hold the frontier out-degrees and
+// their scan; front_outdeg (host) sizes the grid.
+hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nfront, int64_t front_outdeg,
+                       const int32_t* orow, const int32_t* oedge, const int32_t* odst, const uint32_t* bits,
+                       uint32_t* stamp, uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc,
+                       int32_t* fdeg, int32_t* fscan, int32_t* scan_scratch, int64_t* psum, hipStream_t st);
+
+// ---- independent parts (block-diagonal union) ------------------------------
+// part_of[u] for every vertex; bad |= 1 if an edge crosses parts.
+hipError_t launch_parts_setup(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, int32_t np,
+                              const int32_t* part_start, int32_t* part_of, int32_t* bad, hipStream_t st);
+// Range of each part in the (vertex-sorted) dangling list: dstart[np+1].
+hipError_t launch_parts_dangling_ranges(const int32_t* dlist, int32_t ndang, int32_t np, const int32_t* part_start,
+                                        int32_t* dstart, hipStream_t st);
+// part_dang[p] = sum of c over part p's dangling vertices (fixed order).
+hipError_t launch_parts_dangling_sum(const float* c, const int32_t* dlist, int32_t np, const int32_t* dstart,
+                                     double* part_dang, hipStream_t st);
+// Sampling with part-local edge ids: edge e of part p draws with seed + p at
+// local index e - part_e0[p].
+hipError_t launch_sample_bits_parts(int64_t m, uint64_t seed, uint64_t epoch, uint64_t keep, int32_t np,
+                                    const int32_t* part_e0, uint32_t* bits, hipStream_t st);
+// out[i] = src[idx[i]]
+hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t count, int32_t* out, hipStream_t st);
+// x[src[p]] = 0 for every part source.
+hipError_t launch_set_sources(const int32_t* src, int32_t count, uint32_t* x, hipStream_t st);
 
 // ---- multi-query batch (gg_batch.hip) -----------------------------------------
 hipError_t launch_batch_init(int app, int32_t n, int32_t qp, const int32_t* src, const int32_t* outdeg, float* c,

@@ -173,7 +173,14 @@ __device__ __forceinline__ void apply(const Sweep& s, int u, typename Tr<APP>::T
     const double D = *s.dangling;
     double x;
     if constexpr (APP == kPR) {
-      x = s.base + s.damping * (acc + D / (double)s.n);
+      if (s.part_of) {
+        // a part of a block-diagonal union: its own vertex count and dangling mass
+        const int p = s.part_of[u];
+        const double np = (double)(s.part_start[p + 1] - s.part_start[p]);
+        x = (1.0 - s.damping) / np + s.damping * (acc + s.part_dang[p] / np);
+      } else {
+        x = s.base + s.damping * (acc + D / (double)s.n);
+      }
     } else {
       const bool src = (u == s.source);
       x = (src ? (1.0 - s.damping) : 0.0) + s.damping * (acc + (src ? D : 0.0));
@@ -317,10 +324,21 @@ __device__ __forceinline__ uint32_t edge_bit(const uint32_t* bits, int e) { retu
 template <int APP>
 struct Decide;
 
+// c / P > theta for c, P >= 0, identical to comparing the rounded quotient:
+// away from the threshold (relative margin 1e-12, far above the rounding of
+// theta * P) a product decides; only near-ties evaluate the division.
+__device__ __forceinline__ bool infl_above(double c, double P, double theta) {
+  if (!(P > 0.0)) return false;
+  const double tp = theta * P;
+  if (c > tp * (1.0 + 1e-12)) return true;
+  if (c < tp * (1.0 - 1e-12)) return false;
+  return c / P > theta;
+}
+
 template <>
 struct Decide<kPR> {
   static __device__ __forceinline__ bool f(const Sweep& s, bool valid, double c, double P, uint32_t oldf) {
-    bool flag = valid && P > 0.0 && (c / P > s.theta);
+    bool flag = valid && infl_above(c, P, s.theta);
     return flag || (s.mask_union && oldf);
   }
 };
@@ -817,11 +835,21 @@ __global__ void k_iota(int32_t* p, int32_t n) {
     p[i] = (int32_t)i;
 }
 
-__global__ void k_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, float* c) {
+__global__ void k_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, const int32_t* part_of,
+                          const int32_t* part_start, float* c) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double x;
-    if (app == kPR) x = 1.0 / (double)n;
-    else x = (i == source) ? 1.0 : 0.0;
+    if (app == kPR) {
+      // 1/N, with N the vertex count of the vertex's part when parts are set
+      double N = (double)n;
+      if (part_of) {
+        const int p = part_of[i];
+        N = (double)(part_start[p + 1] - part_start[p]);
+      }
+      x = 1.0 / N;
+    } else {
+      x = (i == source) ? 1.0 : 0.0;
+    }
     const int od = outdeg[i];
     c[i] = od > 0 ? (float)(x / (double)od) : (float)x;
   }
@@ -961,10 +989,11 @@ hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, in
   return hipGetLastError();
 }
 
-hipError_t launch_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, float* c, hipStream_t st) {
+hipError_t launch_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, const int32_t* part_of,
+                          const int32_t* part_start, float* c, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_pr_init, dim3(grid_for(n, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, app, outdeg, n, source,
-                     c);
+                     part_of, part_start, c);
   return hipGetLastError();
 }
 
@@ -1458,8 +1487,9 @@ __global__ __launch_bounds__(kBlock) void k_chg_count(const uint8_t* chg, int n,
   if (threadIdx.x == 0) blk[blockIdx.x] = tot;
 }
 
+// Per-block out-degree sums go to psum[block]; k_sum_i64 adds them.
 __global__ __launch_bounds__(kBlock) void k_chg_scatter(const uint8_t* chg, const int32_t* outdeg, int n,
-                                                        const int32_t* blk, int32_t* list, FrontCounters* fc) {
+                                                        const int32_t* blk, int32_t* list, int64_t* psum) {
   __shared__ int ilds[4];
   __shared__ long long elds[4];
   const int u = blockIdx.x * kBlock + threadIdx.x;
@@ -1472,58 +1502,360 @@ __global__ __launch_bounds__(kBlock) void k_chg_scatter(const uint8_t* chg, cons
   for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
   if ((threadIdx.x & 63) == 0) elds[threadIdx.x >> 6] = d;
   __syncthreads();
+  if (threadIdx.x == 0) psum[blockIdx.x] = elds[0] + elds[1] + elds[2] + elds[3];
+}
+
+__global__ __launch_bounds__(1024) void k_sum_i64(const int64_t* psum, int count, int64_t* out) {
+  __shared__ long long ws[16];
+  long long acc = 0;
+  for (int i = threadIdx.x; i < count; i += 1024) acc += psum[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const long long bsum = elds[0] + elds[1] + elds[2] + elds[3];
-    if (bsum) atomicAdd((unsigned long long*)&fc->outdeg_sum, (unsigned long long)bsum);
+    long long t = 0;
+    for (int w = 0; w < 16; ++w) t += ws[w];
+    *out = t;
   }
 }
 
 hipError_t launch_compact_changed(const uint8_t* chg, const int32_t* outdeg, int32_t n, int32_t* list,
-                                  FrontCounters* fc, int32_t* blk_scratch, hipStream_t st) {
+                                  FrontCounters* fc, int32_t* blk_scratch, int64_t* psum, hipStream_t st) {
   hipError_t e = launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
   if (e != hipSuccess || n == 0) return e;
   const int nblk = (n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_chg_count, dim3(nblk), dim3(kBlock), 0, st, chg, n, blk_scratch);
   hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, blk_scratch, nblk, &fc->count);
-  hipLaunchKernelGGL(k_chg_scatter, dim3(nblk), dim3(kBlock), 0, st, chg, outdeg, n, blk_scratch, list, fc);
+  hipLaunchKernelGGL(k_chg_scatter, dim3(nblk), dim3(kBlock), 0, st, chg, outdeg, n, blk_scratch, list, psum);
+  hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(1024), 0, st, psum, nblk, &fc->outdeg_sum);
   return hipGetLastError();
 }
 
 // ---- sparse push -----------------------------------------------------------
-// Append the lanes of this wave whose pred is set to list (one atomic per wave).
-__device__ __forceinline__ void wave_append(bool pred, int32_t val, int32_t* list, int32_t* counter) {
-  const uint64_t bal = __ballot(pred);
-  if (bal == 0) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((long long)bal) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(counter, __popcll(bal));
-  base = __shfl(base, leader, 64);
-  if (pred) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = val;
+// Append the block's threads whose pred is set to list (one atomic per block).
+__device__ __forceinline__ void block_append(bool pred, int32_t val, int32_t* list, int32_t* counter, int* ilds,
+                                             int* base_lds) {
+  int tot;
+  const int r = block_rank(pred, ilds, tot);
+  if (tot == 0) return;  // uniform: every thread sees the same total
+  if (threadIdx.x == 0) *base_lds = atomicAdd(counter, tot);
+  __syncthreads();
+  const int base = *base_lds;
+  if (pred) list[base + r] = val;
+  __syncthreads();
 }
 
+// Frontier vertices: out-degree for the edge-balanced push, and the next
+// buffer catches up with the vertex's current value.
+__global__ void k_front_prep(Sweep s, const int32_t* front, int32_t nfront, const int32_t* orow, int32_t* fdeg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nfront) {
+    const int v = front[i];
+    fdeg[i] = orow[v + 1] - orow[v];
+    atomicMin(&s.x_next[v], s.x_in[v]);
+  }
+}
+
+constexpr int kPushEdgesPerBlock = 1024;
+
+// Edge-balanced push: block b relaxes flattened out-edges
+// [b * kPushEdgesPerBlock, ...) of the whole frontier (fscan: exclusive scan
+// of the frontier out-degrees, fscan[nfront] = total).
 template <int APP>
-__global__ __launch_bounds__(kBlock) void k_push(Sweep s, const int32_t* front, int32_t nfront, const int32_t* orow,
-                                                 const int32_t* oedge, const int32_t* odst, const uint32_t* bits,
-                                                 uint32_t* stamp, uint32_t epoch, int32_t* touched,
-                                                 FrontCounters* fc) {
+__global__ __launch_bounds__(kBlock) void k_push(Sweep s, const int32_t* front, int32_t nfront, const int32_t* fscan,
+                                                 const int32_t* orow, const int32_t* oedge, const int32_t* odst,
+                                                 const uint32_t* bits, uint32_t* stamp, uint32_t epoch,
+                                                 int32_t* touched, FrontCounters* fc) {
   __shared__ int ilds[4];
+  __shared__ int base_lds;
+  const int total = fscan[nfront];
+  for (int64_t b0 = (int64_t)blockIdx.x * kPushEdgesPerBlock; b0 < total;
+       b0 += (int64_t)gridDim.x * kPushEdgesPerBlock) {
+#pragma unroll
+    for (int j = 0; j < kPushEdgesPerBlock / kBlock; ++j) {
+      const int64_t k = b0 + j * kBlock + threadIdx.x;
+      bool newly = false;
+      int u = 0;
+      if (k < total) {
+        int a = 0, hi = nfront - 1;  // last frontier entry whose first edge <= k
+        while (a < hi) {
+          const int mid = (a + hi + 1) >> 1;
+          if (fscan[mid] <= k) a = mid;
+          else hi = mid - 1;
+        }
+        const int v = front[a];
+        const int pos = orow[v] + (int)(k - fscan[a]);
+        const int e = oedge[pos];
+        u = odst[pos];
+        const bool act = bits == nullptr || ((bits[e >> 5] >> (e & 31)) & 1u);
+        if (act) {
+          const uint32_t xs = s.x_in[v];
+          uint32_t cand;
+          if constexpr (APP == kSSSP) cand = xs == kInf ? kInf : xs + (s.edges[e] >> 24);
+          else cand = xs;
+          if (cand != kInf) {
+            const uint32_t old = atomicMin(&s.x_next[u], cand);
+            if (cand < old) newly = atomicExch(&stamp[u], epoch) != epoch;
+          }
+        }
+      }
+      block_append(newly, u, touched, &fc->touched, ilds, &base_lds);
+    }
+  }
+}
+
+// Touched vertices whose value dropped below the previous iteration's form
+// the next frontier; per-block out-degree sums go to psum[block].
+__global__ __launch_bounds__(kBlock) void k_push_finalize(Sweep s, const int32_t* touched, int32_t* next,
+                                                          FrontCounters* fc, int64_t* psum) {
+  __shared__ int ilds[4];
+  __shared__ int base_lds;
+  __shared__ long long elds[4];
+  const int nt = fc->touched;
+  long long dsum = 0;
+  for (int base = blockIdx.x * kBlock; base < nt; base += gridDim.x * kBlock) {
+    const int t = base + (int)threadIdx.x;
+    bool c = false;
+    int u = 0;
+    if (t < nt) {
+      u = touched[t];
+      c = s.x_next[u] < s.x_in[u];
+      if (c) dsum += s.outdeg[u];
+    }
+    block_append(c, u, next, &fc->count, ilds, &base_lds);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
+  if ((threadIdx.x & 63) == 0) elds[threadIdx.x >> 6] = dsum;
+  __syncthreads();
+  if (threadIdx.x == 0) psum[blockIdx.x] = elds[0] + elds[1] + elds[2] + elds[3];
+}
+
+constexpr int kFinalizeBlocks = 1024;
+
+hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nfront, int64_t front_outdeg,
+                       const int32_t* orow, const int32_t* oedge, const int32_t* odst, const uint32_t* bits,
+                       uint32_t* stamp, uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc,
+                       int32_t* fdeg, int32_t* fscan, int32_t* scan_scratch, int64_t* psum, hipStream_t st) {
+  hipError_t e = launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
+  if (e != hipSuccess || nfront == 0) return e;
+  hipLaunchKernelGGL(k_front_prep, dim3((nfront + kBlock - 1) / kBlock), dim3(kBlock), 0, st, s, front, nfront, orow,
+                     fdeg);
+  e = launch_scan(fdeg, fscan, nfront, fscan + nfront, scan_scratch, st);
+  if (e != hipSuccess) return e;
+  const int g = grid_for(front_outdeg > 0 ? front_outdeg : 1, kPushEdgesPerBlock, 1 << 20);
+  if (app == kSSSP)
+    hipLaunchKernelGGL((k_push<kSSSP>), dim3(g), dim3(kBlock), 0, st, s, front, nfront, fscan, orow, oedge, odst,
+                       bits, stamp, epoch, touched, fc);
+  else
+    hipLaunchKernelGGL((k_push<kCC>), dim3(g), dim3(kBlock), 0, st, s, front, nfront, fscan, orow, oedge, odst,
+                       bits, stamp, epoch, touched, fc);
+  hipLaunchKernelGGL(k_push_finalize, dim3(kFinalizeBlocks), dim3(kBlock), 0, st, s, touched, next, fc, psum);
+  hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(1024), 0, st, psum, kFinalizeBlocks, &fc->outdeg_sum);
+  return hipGetLastError();
+}
+
+}  // namespace ggk
+
+
+// ===========================================================================
+// Independent parts: a block-diagonal union of graphs run as one graph
+// ===========================================================================
+namespace ggk {
+
+__global__ void k_part_of(int32_t n, int32_t np, const int32_t* part_start, int32_t* part_of) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = np - 1;  // last part whose start <= u
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (part_start[mid] <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    part_of[u] = lo;
+  }
+}
+
+__global__ void k_part_check(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, const int32_t* part_of,
+                             int32_t* bad) {
+  int f = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rowptr[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    if (part_of[lo] != part_of[col[e]]) f = 1;
+  }
+  if (f) atomicOr(bad, 1);
+}
+
+hipError_t launch_parts_setup(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, int32_t np,
+                              const int32_t* part_start, int32_t* part_of, int32_t* bad, hipStream_t st) {
+  hipError_t e = launch_fill_u32((uint32_t*)bad, 1, 0u, st);
+  if (e != hipSuccess || n == 0) return e;
+  hipLaunchKernelGGL(k_part_of, dim3(grid_for(n, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, n, np, part_start,
+                     part_of);
+  if (m > 0)
+    hipLaunchKernelGGL(k_part_check, dim3(grid_for(m, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, rowptr, col, n, m,
+                       part_of, bad);
+  return hipGetLastError();
+}
+
+__global__ void k_part_dranges(const int32_t* dlist, int32_t ndang, int32_t np, const int32_t* part_start,
+                               int32_t* dstart) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > np) return;
+  const int key = part_start[p];
+  int lo = 0, hi = ndang;  // first dangling vertex >= key
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (dlist[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  dstart[p] = lo;
+}
+
+hipError_t launch_parts_dangling_ranges(const int32_t* dlist, int32_t ndang, int32_t np, const int32_t* part_start,
+                                        int32_t* dstart, hipStream_t st) {
+  hipLaunchKernelGGL(k_part_dranges, dim3((np + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, dlist, ndang, np,
+                     part_start, dstart);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_part_dsum(const float* c, const int32_t* dlist, const int32_t* dstart,
+                                                      double* part_dang) {
+  __shared__ double lds[4];
+  const int p = blockIdx.x;
+  double acc = 0.0;
+  for (int i = dstart[p] + (int)threadIdx.x; i < dstart[p + 1]; i += kBlock) acc += (double)c[dlist[i]];
+  acc = block_reduce<kPR>(acc, lds);
+  if (threadIdx.x == 0) part_dang[p] = acc;
+}
+
+hipError_t launch_parts_dangling_sum(const float* c, const int32_t* dlist, int32_t np, const int32_t* dstart,
+                                     double* part_dang, hipStream_t st) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_part_dsum, dim3(np), dim3(kBlock), 0, st, c, dlist, dstart, part_dang);
+  return hipGetLastError();
+}
+
+// One thread per bitmap word; each edge finds its part and draws from the
+// Philox block of its part-local index.
+__global__ __launch_bounds__(kBlock) void k_sample_bits_parts(int64_t m, uint64_t seed, uint64_t epoch, uint64_t keep,
+                                                              int32_t np, const int32_t* part_e0, uint32_t* bits) {
+  const int64_t nw = (m + 31) >> 5;
+  for (int64_t w = blockIdx.x * (int64_t)kBlock + threadIdx.x; w < nw; w += (int64_t)gridDim.x * kBlock) {
+    uint32_t word = 0;
+    int64_t cached_block = -1;
+    int cached_part = -1;
+    uint64_t o[4] = {0, 0, 0, 0};
+    for (int h = 0; h < 32; ++h) {
+      const int64_t e = w * 32 + h;
+      if (e >= m) break;
+      int lo = 0, hi = np - 1;  // last part whose first edge <= e
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (part_e0[mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      const int64_t local = e - part_e0[lo];
+      if (lo != cached_part || (local >> 3) != cached_block) {
+        philox4x64_10((uint64_t)(local >> 3), epoch, 0, 0, seed + (uint64_t)lo, 0, o);
+        cached_part = lo;
+        cached_block = local >> 3;
+      }
+      const int j = (int)(local & 7);
+      const uint64_t w64 = o[j >> 1];
+      const uint32_t d = (j & 1) ? (uint32_t)(w64 >> 32) : (uint32_t)w64;
+      if ((uint64_t)d < keep) word |= 1u << h;
+    }
+    bits[w] = word;
+  }
+}
+
+hipError_t launch_sample_bits_parts(int64_t m, uint64_t seed, uint64_t epoch, uint64_t keep, int32_t np,
+                                    const int32_t* part_e0, uint32_t* bits, hipStream_t st) {
+  const int64_t nw = (m + 31) >> 5;
+  if (nw == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample_bits_parts, dim3(grid_for(nw, kBlock, 1 << 16)), dim3(kBlock), 0, st, m, seed, epoch,
+                     keep, np, part_e0, bits);
+  return hipGetLastError();
+}
+
+__global__ void k_set_sources(const int32_t* src, int32_t count, uint32_t* x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) x[src[i]] = 0u;
+}
+
+hipError_t launch_set_sources(const int32_t* src, int32_t count, uint32_t* x, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_sources, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, count, x);
+  return hipGetLastError();
+}
+
+}  // namespace ggk
+
+namespace ggk {
+__global__ void k_gather_i32(const int32_t* src, const int32_t* idx, int32_t count, int32_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = src[idx[i]];
+}
+hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t count, int32_t* out, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_i32, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, idx, count, out);
+  return hipGetLastError();
+}
+}  // namespace ggk
+
+// ===========================================================================
+// Superstep for short rows (degree <= small_max) as flattened batches: a block
+// takes kBlock consecutive vertices, gathers every edge of those rows into LDS
+// (all loads of a window in flight together), then the owner thread of each
+// row walks its values in CSR order: running sum / minimum, edge influence and
+// GG-EStatus [Alg. 2], flag bits, packed active edges, apply. Rows up to
+// wave_max use one wavefront each with shuffle scans; longer rows the chunked
+// hub path (k_hub_totals, super_hub_chunk, k_hub_pack).
+// ===========================================================================
+namespace ggk {
+
+template <int APP>
+__global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int gw) {
+  using R = Tr<APP>;
+  using T = typename R::T;
+  using V = typename GV<APP>::V;
+  __shared__ T lds[4];
+  __shared__ int ilds[4];
+  __shared__ V s_val[kFlatWin];
+  __shared__ uint32_t s_ev[kFlatWin];
   __shared__ int s_lo[kBlock];
   __shared__ int s_scan[kBlock + 1];
-  __shared__ uint32_t s_x[kBlock];
-  const int tid = threadIdx.x;
-  const int f0 = blockIdx.x * kBlock;
-  const int P = min(kBlock, nfront - f0);
-  int lo = 0, len = 0;
-  uint32_t xv = kInf;
-  if (tid < P) {
-    const int v = front[f0 + tid];
-    lo = orow[v];
-    len = orow[v + 1] - lo;
-    xv = s.x_in[v];
-    atomicMin(&s.x_next[v], xv);  // the next buffer catches up with v's current value
+  int nchanged = 0;
+  if ((int)blockIdx.x < nchunks) {
+    super_hub_chunk<APP>(s, blockIdx.x, nchanged, lds, ilds);
+    flush_changed<APP>(s, nchanged, ilds);
+    return;
   }
-  // exclusive scan of out-degrees
+  if ((int)blockIdx.x < nchunks + gw) {
+    // wavefront-bin rows: one wavefront per row, shuffle scans
+    super_team_rows<APP, 64>(s, s.list + s.n_small, s.n_wave, (int)blockIdx.x - nchunks, gw, nchanged);
+    flush_changed<APP>(s, nchanged, ilds);
+    return;
+  }
+  const int tid = threadIdx.x;
+  const int u0 = ((int)blockIdx.x - nchunks - gw) * kBlock;
+  const int P = min(kBlock, s.n - u0);
+  const int u = u0 + tid;
+  int lo = 0, len = 0;
+  bool mine = false;
+  if (tid < P) {
+    lo = s.rowptr[u];
+    len = s.rowptr[u + 1] - lo;
+    mine = len <= s.small_max;
+    if (!mine) len = 0;
+  }
+  // exclusive scan of the row lengths
   int x = len;
   const int lane = __lane_id(), wid = tid >> 6;
 #pragma unroll
@@ -1538,80 +1870,113 @@ __global__ __launch_bounds__(kBlock) void k_push(Sweep s, const int32_t* front, 
   const int total = ilds[0] + ilds[1] + ilds[2] + ilds[3];
   s_scan[tid] = before + x - len;
   s_lo[tid] = lo;
-  s_x[tid] = xv;
   __syncthreads();
-  for (int base = 0; base < total; base += kBlock) {
-    const int kk = base + tid;
-    bool newly = false;
-    int u = 0;
-    if (kk < total) {
-      int a = 0, b = P - 1;
-      while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (s_scan[mid] <= kk) a = mid;
-        else b = mid - 1;
-      }
-      const int pos = s_lo[a] + (kk - s_scan[a]);
-      const int e = oedge[pos];
-      u = odst[pos];
-      const bool act = bits == nullptr || ((bits[e >> 5] >> (e & 31)) & 1u);
-      if (act) {
-        const uint32_t xs = s_x[a];
-        uint32_t cand;
-        if constexpr (APP == kSSSP) cand = xs == kInf ? kInf : xs + (s.edges[e] >> 24);
-        else cand = xs;
-        if (cand != kInf) {
-          const uint32_t old = atomicMin(&s.x_next[u], cand);
-          if (cand < old) newly = atomicExch(&stamp[u], epoch) != epoch;
-        }
-      }
-    }
-    wave_append(newly, u, touched, &fc->touched);
-  }
-}
-
-// Touched vertices whose value dropped below the previous iteration's form
-// the next frontier.
-__global__ __launch_bounds__(kBlock) void k_push_finalize(Sweep s, const int32_t* touched, int32_t* next,
-                                                          FrontCounters* fc) {
-  const int nt = fc->touched;
-  __shared__ long long elds[4];
-  long long dsum = 0;
-  for (int base = blockIdx.x * kBlock; base < nt; base += gridDim.x * kBlock) {
-    const int t = base + (int)threadIdx.x;
-    bool c = false;
-    int u = 0;
-    if (t < nt) {
-      u = touched[t];
-      c = s.x_next[u] < s.x_in[u];
-      if (c) dsum += s.outdeg[u];
-    }
-    wave_append(c, u, next, &fc->count);
-  }
+  // owner state, carried across windows
+  const int mine0 = s_scan[tid], mine1 = s_scan[tid] + len;
+  double Psum = 0.0;            // PR: running sum of the row's contributions
+  uint32_t run = kInf;          // SSSP/CC: running minimum
+  int cnt = 0;                  // active edges written
+  int bw = -1;                  // current flag word
+  uint32_t bacc = 0;            // new bits of that word
+  int ow = -1;                  // cached old-flag word index
+  uint32_t oword = 0;
+  for (int base = 0; base < total; base += kFlatWin) {
+    const int lim = min(kFlatWin, total - base);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
-  if ((threadIdx.x & 63) == 0) elds[threadIdx.x >> 6] = dsum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const long long b = elds[0] + elds[1] + elds[2] + elds[3];
-    if (b) atomicAdd((unsigned long long*)&fc->outdeg_sum, (unsigned long long)b);
+    for (int j = 0; j < kFlatWin / kBlock; ++j) {
+      const int k = j * kBlock + tid;
+      if (k < lim) {
+        const int kk = base + k;
+        int a = 0, b = P - 1;
+        while (a < b) {
+          const int mid = (a + b + 1) >> 1;
+          if (s_scan[mid] <= kk) a = mid;
+          else b = mid - 1;
+        }
+        const int e = s_lo[a] + (kk - s_scan[a]);
+        const uint32_t ev = ld_stream(s.edges + e);
+        s_ev[k] = ev;
+        s_val[k] = GV<APP>::get(s, ev);
+      }
+    }
+    __syncthreads();
+    const int a0 = max(mine0, base), a1 = min(mine1, base + lim);
+    for (int k = a0; k < a1; ++k) {
+      const int e = lo + (k - mine0);
+      const V val = s_val[k - base];
+      uint32_t oldf = 0;
+      if (s.old_bits && (APP == kSSSP || s.mask_union)) {
+        if ((e >> 5) != ow) {
+          ow = e >> 5;
+          oword = s.old_bits[ow];
+        }
+        oldf = (oword >> (e & 31)) & 1u;
+      }
+      bool flag;
+      if constexpr (APP == kPR || APP == kPPR) {
+        const double c = (double)val;
+        Psum += c;
+        flag = infl_above(c, Psum, s.theta) || (s.mask_union && oldf);
+      } else if constexpr (APP == kSSSP) {
+        const uint32_t cand = val;  // INF iff the source is unreached
+        if (cand == kInf) {
+          flag = oldf != 0u;  // not assessable: keeps its flag
+        } else {
+          const uint32_t nw = min(run, cand);
+          const bool dec = (run == kInf) || ((((uint64_t)(run - nw)) << 16) > s.theta_q * (uint64_t)run);
+          flag = dec || (s.mask_union && oldf);
+          run = nw;
+        }
+      } else {
+        flag = (val < run) || (s.mask_union && oldf);
+        run = min(run, (uint32_t)val);
+      }
+      if ((e >> 5) != bw) {
+        if (bacc) atomicOr(&s.new_bits[bw], bacc);
+        bw = e >> 5;
+        bacc = 0;
+      }
+      if (flag) {
+        bacc |= 1u << (e & 31);
+        s.act_edges[lo + cnt] = s_ev[k - base];
+        ++cnt;
+      }
+    }
+    __syncthreads();
   }
+  if (mine) {
+    if (bacc) atomicOr(&s.new_bits[bw], bacc);
+    T acc;
+    if constexpr (APP == kPR || APP == kPPR) acc = Psum;
+    else acc = run;
+    apply<APP>(s, u, acc, nchanged);
+    s.act_cnt[u] = cnt;
+  }
+  flush_changed<APP>(s, nchanged, ilds);
 }
 
-hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nfront, const int32_t* orow,
-                       const int32_t* oedge, const int32_t* odst, const uint32_t* bits, uint32_t* stamp,
-                       uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc, hipStream_t st) {
-  hipError_t e = launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
-  if (e != hipSuccess || nfront == 0) return e;
-  const int g = (nfront + kBlock - 1) / kBlock;
-  if (app == kSSSP)
-    hipLaunchKernelGGL((k_push<kSSSP>), dim3(g), dim3(kBlock), 0, st, s, front, nfront, orow, oedge, odst, bits, stamp,
-                       epoch, touched, fc);
-  else
-    hipLaunchKernelGGL((k_push<kCC>), dim3(g), dim3(kBlock), 0, st, s, front, nfront, orow, oedge, odst, bits, stamp,
-                       epoch, touched, fc);
-  hipLaunchKernelGGL(k_push_finalize, dim3(1024), dim3(kBlock), 0, st, s, touched, next, fc);
+template <int APP>
+static hipError_t super_flat_t(const Sweep& s, int nchunks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (nchunks > 0) hipLaunchKernelGGL((k_hub_totals<APP>), dim3(nchunks), dim3(kBlock), 0, st, s);
+  const int gs = (s.n + kBlock - 1) / kBlock;
+  const int gw = s.n_wave > 0 ? grid_for(s.n_wave, kBlock / 64, kTeamBlockCap) : 0;
+  const int total = nchunks + gw + gs;
+  if (ev0) (void)hipEventRecord(ev0, st);
+  if (total > 0) hipLaunchKernelGGL((k_super_flat<APP>), dim3(total), dim3(kBlock), 0, st, s, nchunks, gw);
+  if (ev1) (void)hipEventRecord(ev1, st);
+  if (nchunks > 0) hipLaunchKernelGGL(k_hub_pack, dim3(nchunks), dim3(kBlock), 0, st, s, (const uint32_t*)s.new_bits);
   return hipGetLastError();
+}
+
+hipError_t launch_superstep_flat(int app, const Sweep& s, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int nchunks = s.n_hub > 0 ? s.n_chunks : 0;
+  switch (app) {
+    case kPR: return super_flat_t<kPR>(s, nchunks, st, ev0, ev1);
+    case kPPR: return super_flat_t<kPPR>(s, nchunks, st, ev0, ev1);
+    case kSSSP: return super_flat_t<kSSSP>(s, nchunks, st, ev0, ev1);
+    case kCC: return super_flat_t<kCC>(s, nchunks, st, ev0, ev1);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace ggk

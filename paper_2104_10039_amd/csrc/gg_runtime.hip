@@ -99,6 +99,17 @@ struct gg_graph {
   int32_t* flist[2] = {nullptr, nullptr};
   int32_t* touched = nullptr;
   FrontCounters* fc = nullptr;
+  int32_t* fdeg = nullptr;   // n
+  int32_t* fscan = nullptr;  // n + 1
+  int64_t* psum = nullptr;   // max(ceil(n / kBlock), 1024)
+  // independent parts (gg_graph_set_parts)
+  int32_t n_parts = 0;
+  int32_t* part_start = nullptr;  // np+1
+  int32_t* part_of = nullptr;     // n
+  int32_t* part_e0 = nullptr;     // np+1: first edge of each part
+  int32_t* part_dstart = nullptr; // np+1: range of each part in the dangling list
+  int32_t* part_src = nullptr;    // np or null
+  double* part_dang = nullptr;    // np
   // multi-query batch workspace
   struct Batch {
     int64_t val_cap = 0;  // elements of each value buffer
@@ -308,7 +319,7 @@ int rebin_act(gg_graph* g, int app) {
 int ensure_out(gg_graph* g) {
   if (g->out_built) {
     if (!g->orow || !g->oedge || !g->odst || !g->chg || !g->stamp || !g->flist[0] || !g->flist[1] || !g->touched ||
-        !g->fc)
+        !g->fc || !g->fdeg || !g->fscan || !g->psum)
       return fail(GG_E_STATE, "frontier arrays missing");
     return GG_OK;
   }
@@ -322,6 +333,10 @@ int ensure_out(gg_graph* g) {
   GG_TRY(dalloc(&g->flist[1], n));
   GG_TRY(dalloc(&g->touched, n));
   GG_TRY(dalloc(&g->fc, 1));
+  GG_TRY(dalloc(&g->fdeg, n));
+  GG_TRY(dalloc(&g->fscan, n + 1));
+  const size_t nblk = (n + kBlock - 1) / kBlock;
+  GG_TRY(dalloc(&g->psum, nblk > 1024 ? nblk : 1024));
   GG_HIP(launch_fill_u32(g->stamp, g->n, 0u, g->stream));
   GG_HIP(launch_scan(g->outdeg, g->orow, g->n, g->orow + g->n, (int32_t*)g->blk_scratch, g->stream));
   // cursor scratch: the touched list is free at this point
@@ -405,6 +420,15 @@ void free_graph(gg_graph* g) {
   dfree(g->flist[1]);
   dfree(g->touched);
   dfree(g->fc);
+  dfree(g->fdeg);
+  dfree(g->fscan);
+  dfree(g->psum);
+  dfree(g->part_start);
+  dfree(g->part_of);
+  dfree(g->part_e0);
+  dfree(g->part_dstart);
+  dfree(g->part_src);
+  dfree(g->part_dang);
   for (int i = 0; i < 3; ++i)
     if (g->batch.buf[i]) (void)hipFree(g->batch.buf[i]);
   dfree(g->batch.part);
@@ -459,8 +483,12 @@ int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const 
   if (pol->influence == GG_INFL_TOTAL) return fail(GG_E_UNSUPPORTED, "TOTAL influence is not implemented");
   if (p->dangling != GG_DANGLING_UNIFORM && p->dangling != GG_DANGLING_NONE) return fail(GG_E_INVAL, "unknown dangling");
   if (is_pr(p->app) && !(p->damping >= 0.0 && p->damping < 1.0)) return fail(GG_E_INVAL, "damping outside [0, 1)");
-  if ((p->app == GG_APP_SSSP || p->app == GG_APP_PPR) && (p->source < 0 || p->source >= g->n))
+  if (g->n_parts > 0) {
+    if (p->app == GG_APP_PPR) return fail(GG_E_UNSUPPORTED, "PPR on a graph with parts");
+    if (p->app == GG_APP_SSSP && !g->part_src) return fail(GG_E_INVAL, "SSSP on parts needs part sources");
+  } else if ((p->app == GG_APP_SSSP || p->app == GG_APP_PPR) && (p->source < 0 || p->source >= g->n)) {
     return fail(GG_E_INVAL, "source out of range");
+  }
   if (p->app == GG_APP_SSSP && !g->wedges) return fail(GG_E_INVAL, "SSSP needs edge weights");
   const bool fixed_iters = is_pr(p->app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
   if (fixed_iters && p->iters < 0) return fail(GG_E_INVAL, "iters < 0");
@@ -490,6 +518,11 @@ Sweep base_sweep(const gg_graph* g, const gg_run* r) {
   s.mask_union = r->pol.mask_update == GG_MASK_UNION;
   s.act_edges = g->act_edges;
   s.act_cnt = g->act_cnt;
+  if (g->n_parts > 0) {
+    s.part_of = g->part_of;
+    s.part_start = g->part_start;
+    s.part_dang = g->part_dang;
+  }
   return s;
 }
 
@@ -532,7 +565,10 @@ const uint32_t* full_edges(const gg_graph* g, int app) {
 // their binning [Sec. 3.4].
 int sample_and_pack(gg_graph* g, int app, double sigma, uint64_t seed) {
   const uint64_t keep = (uint64_t)std::floor(sigma * 4294967296.0 + 0.5);
-  GG_HIP(launch_sample_bits(g->m, seed, 0, keep, g->bits[0], g->stream));
+  if (g->n_parts > 0)
+    GG_HIP(launch_sample_bits_parts(g->m, seed, 0, keep, g->n_parts, g->part_e0, g->bits[0], g->stream));
+  else
+    GG_HIP(launch_sample_bits(g->m, seed, 0, keep, g->bits[0], g->stream));
   Sweep s;
   std::memset(&s, 0, sizeof(s));
   s.n = g->n;
@@ -564,15 +600,31 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
   r->sigma = sigma;
   const int app = p->app;
   // initial values
+  const bool parts = g->n_parts > 0;
   if (is_pr(app)) {
-    GG_HIP(launch_pr_init(app, g->outdeg, g->n, p->source, g->c[0], g->stream));
-    if (p->dangling == GG_DANGLING_NONE) GG_HIP(launch_fill_u32((uint32_t*)(g->dpartial + 256), 2, 0u, g->stream));
+    GG_HIP(launch_pr_init(app, g->outdeg, g->n, p->source, parts ? g->part_of : nullptr,
+                          parts ? g->part_start : nullptr, g->c[0], g->stream));
+    if (p->dangling == GG_DANGLING_NONE) {
+      GG_HIP(launch_fill_u32((uint32_t*)(g->dpartial + 256), 2, 0u, g->stream));
+      if (parts) GG_HIP(launch_fill_u32((uint32_t*)g->part_dang, 2 * (int64_t)g->n_parts, 0u, g->stream));
+    }
   } else {
-    GG_HIP(launch_min_init(app, g->n, p->source, g->xu[0], g->stream));
-    GG_HIP(launch_min_init(app, g->n, p->source, g->xu[1], g->stream));
+    const int32_t src0 = parts ? -1 : p->source;
+    GG_HIP(launch_min_init(app, g->n, src0, g->xu[0], g->stream));
+    GG_HIP(launch_min_init(app, g->n, src0, g->xu[1], g->stream));
+    if (parts && app == GG_APP_SSSP) {
+      GG_HIP(launch_set_sources(g->part_src, g->n_parts, g->xu[0], g->stream));
+      GG_HIP(launch_set_sources(g->part_src, g->n_parts, g->xu[1], g->stream));
+    }
     if (g->tune.frontier_enable) {
       GG_TRY(ensure_out(g));
-      if (app == GG_APP_SSSP && g->n > 0) {
+      if (parts && app == GG_APP_SSSP) {
+        // every part's source is new at iteration 0
+        GG_HIP(launch_copy_u32((const uint32_t*)g->part_src, (uint32_t*)g->flist[0], g->n_parts, g->stream));
+        r->fcur = 0;
+        r->front_count = g->n_parts;
+        r->front_outdeg = 0;
+      } else if (app == GG_APP_SSSP && g->n > 0) {
         // the source is the only vertex whose value is new at iteration 0
         const int32_t src = p->source;
         int32_t od = 0;
@@ -613,9 +665,13 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
                           i >= r->p.iters;
   Sweep s = base_sweep(g, r);
   if (pr) {
-    if (r->p.dangling == GG_DANGLING_UNIFORM)
-      GG_HIP(launch_dangling_sum(g->c[r->cur], g->dang, nullptr, g->n_dang, g->dpartial, g->dpartial + 256,
-                                 g->stream));
+    if (r->p.dangling == GG_DANGLING_UNIFORM) {
+      if (g->n_parts > 0)
+        GG_HIP(launch_parts_dangling_sum(g->c[r->cur], g->dang, g->n_parts, g->part_dstart, g->part_dang, g->stream));
+      else
+        GG_HIP(launch_dangling_sum(g->c[r->cur], g->dang, nullptr, g->n_dang, g->dpartial, g->dpartial + 256,
+                                   g->stream));
+    }
     s.c_in = g->c[r->cur];
     s.c_out = g->c[1 - r->cur];
     s.x_out = (r->write_x_each_step || last_fixed) ? g->xout : nullptr;
@@ -646,8 +702,9 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     const uint32_t* bits = accurate ? nullptr : g->bits[r->bcur];
     g->epoch++;
     if (pe0) GG_HIP(hipEventRecord(pe0, g->stream));
-    GG_HIP(launch_push(app, s, g->flist[r->fcur], (int32_t)r->front_count, g->orow, g->oedge, g->odst, bits,
-                       g->stamp, g->epoch, g->touched, g->flist[1 - r->fcur], g->fc, g->stream));
+    GG_HIP(launch_push(app, s, g->flist[r->fcur], (int32_t)r->front_count, r->front_outdeg, g->orow, g->oedge,
+                       g->odst, bits, g->stamp, g->epoch, g->touched, g->flist[1 - r->fcur], g->fc, g->fdeg, g->fscan,
+                       (int32_t*)g->blk_scratch, g->psum, g->stream));
     if (pe1) GG_HIP(hipEventRecord(pe1, g->stream));
     edges = accurate ? g->m : g->act.h.edges;
     processed = r->front_outdeg;
@@ -661,7 +718,10 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     s.old_bits = g->bits[r->bcur];
     s.new_bits = g->bits[1 - r->bcur];
     GG_TRY(check_part_capacity(g, g->full));
-    GG_HIP(launch_superstep(app, g->tune.small_team, s, g->stream, pe0, pe1));
+    if (g->tune.seg_enable)
+      GG_HIP(launch_superstep_flat(app, s, g->stream, pe0, pe1));
+    else
+      GG_HIP(launch_superstep(app, g->tune.small_team, s, g->stream, pe0, pe1));
     r->bcur = 1 - r->bcur;
     GG_TRY(rebin_act(g, app));
     r->supersteps++;
@@ -700,7 +760,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   }
   if (frontier && !sparse)
     GG_HIP(launch_compact_changed(g->chg, g->outdeg, g->n, g->flist[1 - r->fcur], g->fc, (int32_t*)g->blk_scratch,
-                                  g->stream));
+                                  g->psum, g->stream));
   if (g->prof) {
     double bytes = alg_bytes(kind, g->n, edges, s.x_out != nullptr);
     if (kind == 2) bytes += 4.0 * (double)g->act.h.edges + (double)((g->m + 31) / 32) * 4.0;
@@ -773,8 +833,23 @@ int pr_initial_x(gg_run* r) {
   if (g->n == 0) return GG_OK;
   float* h = new (std::nothrow) float[(size_t)g->n];
   if (!h) return fail(GG_E_NOMEM, "host allocation failed");
-  for (int32_t u = 0; u < g->n; ++u)
-    h[u] = r->p.app == GG_APP_PR ? (float)(1.0 / (double)g->n) : (u == r->p.source ? 1.0f : 0.0f);
+  std::vector<int32_t> ps;
+  if (g->n_parts > 0) {
+    ps.resize((size_t)g->n_parts + 1);
+    hipError_t e = hipMemcpy(ps.data(), g->part_start, sizeof(int32_t) * ps.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      delete[] h;
+      return fail(GG_E_DEVICE, std::string("initial values: ") + hipGetErrorString(e));
+    }
+  }
+  for (int32_t p = 0, u = 0; u < g->n; ++u) {
+    double N = (double)g->n;
+    if (!ps.empty()) {
+      while (u >= ps[p + 1]) ++p;
+      N = (double)(ps[p + 1] - ps[p]);
+    }
+    h[u] = r->p.app == GG_APP_PR ? (float)(1.0 / N) : (u == r->p.source ? 1.0f : 0.0f);
+  }
   hipError_t e = hipMemcpyAsync(g->xout, h, sizeof(float) * (size_t)g->n, hipMemcpyHostToDevice, g->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
   delete[] h;
@@ -914,6 +989,7 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
   if (pol->kind != GG_POLICY_EXACT && pol->kind != GG_POLICY_SP)
     return fail(GG_E_UNSUPPORTED, "batch runs support the EXACT and SP schemes");
   if (nq < 1 || nq > 4096) return fail(GG_E_INVAL, "n_queries outside [1, 4096]");
+  if (g->n_parts > 0) return fail(GG_E_UNSUPPORTED, "batch runs on a graph with parts");
   if (!(sigma >= 0.0 && sigma <= 1.0)) return fail(GG_E_INVAL, "sample_ratio outside [0, 1]");
   if (p->app == GG_APP_SSSP && !g->wedges) return fail(GG_E_INVAL, "SSSP needs edge weights");
   if (p->app == GG_APP_PPR && !(p->damping >= 0.0 && p->damping < 1.0)) return fail(GG_E_INVAL, "bad damping");
@@ -1144,6 +1220,58 @@ void gg_graph_free(gg_graph* g) {
   if (!g) return;
   if (g->active_run) end_run(g->active_run);
   free_graph(g);
+}
+
+int gg_graph_set_parts(gg_graph* g, int32_t n_parts, const int32_t* part_start_host,
+                       const int32_t* part_sources_host) {
+  if (!g) return fail(GG_E_INVAL, "null graph");
+  if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+  dfree(g->part_start);
+  dfree(g->part_of);
+  dfree(g->part_e0);
+  dfree(g->part_dstart);
+  dfree(g->part_src);
+  dfree(g->part_dang);
+  g->n_parts = 0;
+  if (n_parts == 0) return GG_OK;
+  if (n_parts < 0 || !part_start_host) return fail(GG_E_INVAL, "bad part description");
+  if (part_start_host[0] != 0 || part_start_host[n_parts] != g->n) return fail(GG_E_RANGE, "parts must cover [0, n)");
+  for (int32_t p = 0; p < n_parts; ++p) {
+    if (part_start_host[p + 1] < part_start_host[p]) return fail(GG_E_RANGE, "part starts must not decrease");
+    if (part_sources_host &&
+        (part_sources_host[p] < part_start_host[p] || part_sources_host[p] >= part_start_host[p + 1]))
+      return fail(GG_E_RANGE, "part source outside its part");
+  }
+  const size_t np = (size_t)n_parts;
+  GG_TRY(dalloc(&g->part_start, np + 1));
+  GG_TRY(dalloc(&g->part_of, (size_t)g->n));
+  GG_TRY(dalloc(&g->part_e0, np + 1));
+  GG_TRY(dalloc(&g->part_dstart, np + 1));
+  GG_TRY(dalloc(&g->part_dang, np));
+  GG_HIP(hipMemcpyAsync(g->part_start, part_start_host, sizeof(int32_t) * (np + 1), hipMemcpyHostToDevice,
+                        g->stream));
+  if (part_sources_host) {
+    GG_TRY(dalloc(&g->part_src, np));
+    GG_HIP(hipMemcpyAsync(g->part_src, part_sources_host, sizeof(int32_t) * np, hipMemcpyHostToDevice, g->stream));
+  }
+  GG_HIP(launch_gather_i32(g->rowptr, g->part_start, n_parts + 1, g->part_e0, g->stream));
+  GG_HIP(launch_parts_setup(g->rowptr, g->col, g->n, g->m, n_parts, g->part_start, g->part_of, g->i32_scratch + 2,
+                            g->stream));
+  GG_HIP(launch_parts_dangling_ranges(g->dang, g->n_dang, n_parts, g->part_start, g->part_dstart, g->stream));
+  int32_t bad = 0;
+  GG_HIP(hipMemcpyAsync(&bad, g->i32_scratch + 2, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  if (bad) {
+    dfree(g->part_start);
+    dfree(g->part_of);
+    dfree(g->part_e0);
+    dfree(g->part_dstart);
+    dfree(g->part_src);
+    dfree(g->part_dang);
+    return fail(GG_E_RANGE, "an edge crosses parts");
+  }
+  g->n_parts = n_parts;
+  return GG_OK;
 }
 
 int gg_graph_get_tuning(const gg_graph* g, gg_tuning* out) {
