@@ -14,6 +14,7 @@ value = edges gathered per second over the timed steps (GTEPS, all runs).
 Printed as one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SOURCES = ("paper_2104_10039_amd/csrc/gg_kernels.hip", "paper_2104_10039_amd/csrc/gg_internal.h")
 
 
 def log(*a):
@@ -49,6 +51,48 @@ def cpu_baseline(graphs, source, budget_iters=3):
                       % (budget_iters, dt, edges)}
 
 
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_<workload>_pmc.txt): FETCH_SIZE and WRITE_SIZE per
+    dispatch, each divided by what the counter reads per byte of a plain copy
+    kernel of known size. None when no summary exists or the kernel sources
+    changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_sha256") != kernel_source_sha():
+            return None
+        fetch = float(kv["kernel_FETCH_SIZE_KiB"]) / (float(kv["copy_FETCH_SIZE_KiB"]) * 1024.0 / float(kv["copy_bytes"]))
+        write = float(kv["kernel_WRITE_SIZE_KiB"]) / (float(kv["copy_WRITE_SIZE_KiB"]) * 1024.0 / float(kv["copy_bytes"]))
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+    return int(round((fetch + write) * 1024.0))
+
+
+def kernel_name(kind, app, seg):
+    a = app.upper()
+    if kind == "superstep":
+        return ("k_super_flat<%s>" if seg else "k_super<%s>") % a
+    if kind == "push":
+        return "k_push<%s>" % a
+    return ("k_gather_seg<%s>" if seg else "k_gather<%s>") % a
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +107,8 @@ def main():
     ap.add_argument("--apps", default="pr,sssp,cc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain copy kernel of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -78,6 +124,14 @@ def main():
     from paper_2104_10039_amd import metrics
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy_mib > 0:
+        # fp32 negation: reads and writes exactly calib_copy_mib MiB each
+        a = torch.ones(args.calib_copy_mib << 18, device="cuda")
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy of %d MiB done" % args.calib_copy_mib)
     apps = args.apps.split(",")
     sigmas = [float(x) for x in args.sigmas.split(",")]
 
@@ -169,7 +223,7 @@ def main():
     # roofline of the dominant kernel (largest total event time in the timed region)
     best = None
     for app in apps:
-        for kind in ("gather_exact", "gather_approx", "superstep"):
+        for kind in ("gather_exact", "gather_approx", "superstep", "push"):
             p = G[app].get_profile(kind, app)
             if p["launches"] and (best is None or p["total_ms"] > best[2]["total_ms"]):
                 best = (app, kind, p)
@@ -177,10 +231,12 @@ def main():
     avg_ms = pb["total_ms"] / pb["launches"]
     bytes_per_launch = pb["alg_bytes"] / pb["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kname = kernel_name(kind_b, app_b, G[app_b].get_tuning()["seg_enable"])
+    workload = "rmat%d_ef%d" % (args.scale, args.edge_factor)
+    traffic = measured_traffic(kname.replace("<", "_").replace(">", "").lower(), workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_gather<%s> (%s)" % (app_b.upper(), kind_b) if kind_b != "superstep"
-                else "k_super<%s>" % app_b.upper(),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kname, "kind": kind_b,
                 "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(bytes_per_launch),
                 "launches": pb["launches"]}
 
