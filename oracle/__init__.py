@@ -21,7 +21,17 @@ _HDR = os.path.join(_HERE, "oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PR, SSSP, CC, PPR = 0, 1, 2, 3
-EXACT, SP, SMS, GG = 0, 1, 2, 3
+EXACT, SP, SMS, GG, LEARNED = 0, 1, 2, 3, 4
+KIND_APPROX, KIND_ACCURATE, KIND_FULL, KIND_PARTIAL = 0, 1, 2, 3
+MLP_IN, MLP_HIDDEN = 8, 64
+MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + 2 * MLP_HIDDEN + 1
+# offsets of the parameter vector: W1 [8][64], b1, W2 [64][64], b2, w3, b3
+P_W1 = 0
+P_B1 = P_W1 + MLP_IN * MLP_HIDDEN
+P_W2 = P_B1 + MLP_HIDDEN
+P_B2 = P_W2 + MLP_HIDDEN * MLP_HIDDEN
+P_W3 = P_B2 + MLP_HIDDEN
+P_B3 = P_W3 + MLP_HIDDEN
 FIXED_ITERS, FIXED_POINT = 0, 1
 INFL_PREFIX, INFL_TOTAL = 0, 1
 MASK_REPLACE, MASK_UNION = 0, 1
@@ -29,7 +39,7 @@ DANGLING_UNIFORM, DANGLING_NONE = 0, 1
 INF = 0xFFFFFFFF
 
 APP_NAMES = {"pr": PR, "sssp": SSSP, "cc": CC, "ppr": PPR}
-POLICY_NAMES = {"exact": EXACT, "sp": SP, "sms": SMS, "gg": GG}
+POLICY_NAMES = {"exact": EXACT, "sp": SP, "sms": SMS, "gg": GG, "learned": LEARNED}
 
 
 def build(force: bool = False) -> str:
@@ -55,12 +65,15 @@ class _App(ctypes.Structure):
 class _Pol(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("alpha", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("influence", ctypes.c_int32),
-                ("mask_update", ctypes.c_int32), ("stop", ctypes.c_int32)]
+                ("mask_update", ctypes.c_int32), ("stop", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("tau", ctypes.c_double), ("rho", ctypes.c_double), ("fallback_k", ctypes.c_int32),
+                ("trace", ctypes.c_int32), ("label_eps", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("accurate", ctypes.c_int32), ("superstep", ctypes.c_int32),
-                ("edges", ctypes.c_int64), ("changed", ctypes.c_int64), ("active_edges", ctypes.c_int64)]
+                ("edges", ctypes.c_int64), ("changed", ctypes.c_int64), ("active_edges", ctypes.c_int64),
+                ("kind", ctypes.c_int32), ("selected", ctypes.c_int64)]
 
 
 @functools.lru_cache(maxsize=None)
@@ -85,6 +98,25 @@ def _lib():
     for f in ("ggo_get_values", "ggo_get_mask", "ggo_get_influence"):
         getattr(lib, f).argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.ggo_end.argtypes = [ctypes.c_void_p]
+    lib.ggo_get_features.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.ggo_get_selection.restype = ctypes.c_int
+    lib.ggo_get_selection.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.ggo_get_labels.restype = ctypes.c_int
+    lib.ggo_get_labels.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.ggo_bf16_bits.restype = ctypes.c_uint16
+    lib.ggo_bf16_bits.argtypes = [ctypes.c_float]
+    lib.ggo_bf16_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    lib.ggo_bf16_value.restype = ctypes.c_float
+    lib.ggo_bf16_value.argtypes = [ctypes.c_uint16]
+    lib.ggo_lg_feature.restype = ctypes.c_float
+    lib.ggo_lg_feature.argtypes = [ctypes.c_int64]
+    lib.ggo_delta_feature.restype = ctypes.c_float
+    lib.ggo_delta_feature.argtypes = [ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32]
+    lib.ggo_mlp_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+    lib.ggo_mlp_loss_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.ggo_adam_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int64, ctypes.c_double, ctypes.c_int64]
     lib.ggo_last_error.restype = ctypes.c_char_p
     return lib
 
@@ -113,6 +145,8 @@ class StepInfo:
     edges: int
     changed: int
     active_edges: int
+    kind: int = KIND_APPROX
+    selected: int = -1
 
 
 @dataclass
@@ -129,7 +163,8 @@ class Run:
 
     def __init__(self, g, app, policy="exact", sigma=1.0, alpha=4, theta=0.05, seed=1,
                  damping=0.85, iters=20, max_iters=100000, source=0, dangling=DANGLING_UNIFORM,
-                 influence=INFL_PREFIX, mask_update=MASK_REPLACE, stop=FIXED_ITERS):
+                 influence=INFL_PREFIX, mask_update=MASK_REPLACE, stop=FIXED_ITERS, mlp=None, tau=0.0,
+                 rho=1.0, fallback_k=0, trace=False, label_eps=1e-3):
         self._lib = _lib()
         self.app = APP_NAMES[app] if isinstance(app, str) else int(app)
         kind = POLICY_NAMES[policy] if isinstance(policy, str) else int(policy)
@@ -141,7 +176,12 @@ class Run:
         csr = _Csr(self.n, self.m, self._rowptr.ctypes.data, self._col.ctypes.data,
                    None if self._w is None else self._w.ctypes.data)
         ap = _App(self.app, damping, iters, max_iters, source, dangling)
-        po = _Pol(kind, alpha, theta, sigma, seed, influence, mask_update, stop)
+        self._mlp = None if mlp is None else np.ascontiguousarray(mlp, dtype=np.float64)
+        if self._mlp is not None and self._mlp.size != MLP_PARAMS:
+            raise ValueError("mlp needs %d parameters" % MLP_PARAMS)
+        po = _Pol(kind, alpha, theta, sigma, seed, influence, mask_update, stop,
+                  None if self._mlp is None else self._mlp.ctypes.data, tau, rho, fallback_k, int(bool(trace)),
+                  label_eps)
         self._h = self._lib.ggo_begin(ctypes.byref(csr), ctypes.byref(ap), ctypes.byref(po))
         if not self._h:
             raise ValueError("oracle: " + self._lib.ggo_last_error().decode())
@@ -151,7 +191,7 @@ class Run:
         if not self._lib.ggo_step(self._h, ctypes.byref(info)):
             return None
         return StepInfo(info.iter, bool(info.accurate), bool(info.superstep), info.edges, info.changed,
-                        info.active_edges)
+                        info.active_edges, info.kind, info.selected)
 
     @property
     def done(self) -> bool:
@@ -180,6 +220,27 @@ class Run:
         out = np.empty(max(self.m, 1), dtype=np.float64)
         self._lib.ggo_get_influence(self._h, out.ctypes.data)
         return out[: self.m]
+
+    def features(self) -> np.ndarray:
+        """[n, 8] bfloat16 bits of the features of the last correction or traced step."""
+        out = np.zeros((max(self.n, 1), MLP_IN), dtype=np.uint16)
+        self._lib.ggo_get_features(self._h, out.ctypes.data)
+        return out[: self.n]
+
+    def selection(self):
+        """(selected uint8 [n], logits float64 [n]) of this step, or None."""
+        sel = np.zeros(max(self.n, 1), dtype=np.uint8)
+        lg = np.zeros(max(self.n, 1), dtype=np.float64)
+        if not self._lib.ggo_get_selection(self._h, sel.ctypes.data, lg.ctypes.data):
+            return None
+        return sel[: self.n], lg[: self.n]
+
+    def labels(self):
+        """Drift labels uint8 [n] of this step (traced full superstep), or None."""
+        out = np.zeros(max(self.n, 1), dtype=np.uint8)
+        if not self._lib.ggo_get_labels(self._h, out.ctypes.data):
+            return None
+        return out[: self.n]
 
     def close(self):
         if self._h:
@@ -210,3 +271,62 @@ def run(g, app, policy="exact", **kw) -> Result:
         return r.run_to_end()
     finally:
         r.close()
+
+
+# ---------------------------------------------------------------------------
+# bfloat16 and the correction MLP
+# ---------------------------------------------------------------------------
+
+def bf16_bits(x) -> int:
+    return int(_lib().ggo_bf16_bits(float(x)))
+
+
+def bf16_array(x) -> np.ndarray:
+    """bfloat16 bits of a float32 array (round to nearest even)."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.empty(a.shape, dtype=np.uint16)
+    _lib().ggo_bf16_array(a.ctypes.data, out.ctypes.data, a.size)
+    return out
+
+
+def bf16_value(b) -> float:
+    return float(_lib().ggo_bf16_value(int(b)))
+
+
+def lg_feature(y) -> float:
+    return float(_lib().ggo_lg_feature(int(y)))
+
+
+def delta_feature(app, now, before) -> float:
+    a = APP_NAMES[app] if isinstance(app, str) else int(app)
+    return float(_lib().ggo_delta_feature(a, int(now) & 0xFFFFFFFF, int(before) & 0xFFFFFFFF))
+
+
+def mlp_forward(params, feat, rounding=True) -> np.ndarray:
+    """Logits of the samples in feat ([n, 8] bfloat16 bits)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    f = np.ascontiguousarray(feat, dtype=np.uint16).reshape(-1, MLP_IN)
+    out = np.zeros(max(len(f), 1), dtype=np.float64)
+    _lib().ggo_mlp_forward(p.ctypes.data, f.ctypes.data, len(f), int(bool(rounding)), out.ctypes.data)
+    return out[: len(f)]
+
+
+def mlp_loss_grad(params, feat, label, pos_weight=1.0, rounding=True):
+    """(mean loss, gradient [MLP_PARAMS]) of the weighted BCE-with-logits loss."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    f = np.ascontiguousarray(feat, dtype=np.uint16).reshape(-1, MLP_IN)
+    y = np.ascontiguousarray(label, dtype=np.float32)
+    g = np.zeros(MLP_PARAMS, dtype=np.float64)
+    loss = ctypes.c_double()
+    _lib().ggo_mlp_loss_grad(p.ctypes.data, f.ctypes.data, y.ctypes.data, len(f), float(pos_weight),
+                             int(bool(rounding)), g.ctypes.data, ctypes.byref(loss))
+    return loss.value, g
+
+
+def adam_step(params, m, v, grad, lr, t):
+    """In-place Adam step on float64 arrays."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    _lib().ggo_adam_step(params.ctypes.data, m.ctypes.data, v.ctypes.data, g.ctypes.data, params.size, float(lr),
+                         int(t))

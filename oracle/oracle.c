@@ -41,6 +41,15 @@
  *  - SSSP/CC exact runs stop after the first iteration that changes nothing;
  *    approximate runs either run a fixed number of iterations or stop after a
  *    no-change iteration that no later iteration can follow differently.
+ *
+ * Not in the paper (its automatic choice of control parameters is left to
+ * future work, Sec. 7): a LEARNED policy keeps GG's correction schedule but
+ * lets a small MLP pick the rows corrected at each correction step (a
+ * partial superstep), with GG's full superstep as fallback every k-th
+ * correction step or when the selection exceeds rho * n. Its features, the
+ * network, the loss and Adam are plain definitions written out below; the
+ * drift label of a traced full superstep compares the accurate update with
+ * the approximate one the flags alone would have given.
  */
 #include "oracle.h"
 
@@ -108,41 +117,247 @@ uint64_t ggo_keep_threshold(double sigma) {
   return (uint64_t)floor(sigma * 4294967296.0 + 0.5);
 }
 
+
+/* ---------------------------------------------------------------------------
+ * BF16 (bfloat16) rounding and the correction MLP. The MLP scores vertices
+ * for drift; it is not part of the paper's method (the paper leaves the
+ * automatic choice of its control parameters to future work, Sec. 7) and is
+ * written here as the plain definition of a 8-64-64-1 ReLU network.
+ * ------------------------------------------------------------------------- */
+
+/* Round-to-nearest-even from binary32 to bfloat16 bits (NaN -> 0x7FC0). */
+uint16_t ggo_bf16_bits(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return 0x7FC0;
+  const uint32_t lsb = (u >> 16) & 1u;
+  return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+void ggo_bf16_array(const float* in, uint16_t* out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = ggo_bf16_bits(in[i]);
+}
+
+float ggo_bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+/* binary64 -> binary32 -> bfloat16, the two roundings the GPU performs. */
+static double to_bf16(double v) { return (double)ggo_bf16_value(ggo_bf16_bits((float)v)); }
+static double to_f32(double v) { return (double)(float)v; }
+
+#define P_W1 0
+#define P_B1 (P_W1 + GGO_MLP_IN * GGO_MLP_HIDDEN)
+#define P_W2 (P_B1 + GGO_MLP_HIDDEN)
+#define P_B2 (P_W2 + GGO_MLP_HIDDEN * GGO_MLP_HIDDEN)
+#define P_W3 (P_B2 + GGO_MLP_HIDDEN)
+#define P_B3 (P_W3 + GGO_MLP_HIDDEN)
+
+/* Forward pass of one sample. rounding = 1 rounds where the GPU kernels do:
+   weights W1, W2, w3 to bfloat16, each pre-activation to binary32 before its
+   bias (binary32) is added, the hidden activations to bfloat16; rounding = 0
+   is plain binary64 throughout. Keeps z1, z2, h1, h2 for the backward pass. */
+typedef struct {
+  double z1[GGO_MLP_HIDDEN], h1[GGO_MLP_HIDDEN];
+  double z2[GGO_MLP_HIDDEN], h2[GGO_MLP_HIDDEN];
+  double z;
+} mlp_cache;
+
+static double wt(const double* p, int i, int rounding) { return rounding ? to_bf16(p[i]) : p[i]; }
+static double bs(const double* p, int i, int rounding) { return rounding ? to_f32(p[i]) : p[i]; }
+
+static double mlp_forward(const double* p, const double* x, int rounding, mlp_cache* c) {
+  for (int j = 0; j < GGO_MLP_HIDDEN; ++j) {
+    double a = 0.0;
+    for (int f = 0; f < GGO_MLP_IN; ++f) a += x[f] * wt(p, P_W1 + f * GGO_MLP_HIDDEN + j, rounding);
+    double z = rounding ? to_f32(to_f32(a) + bs(p, P_B1 + j, 1)) : a + p[P_B1 + j];
+    c->z1[j] = z;
+    c->h1[j] = z > 0.0 ? (rounding ? to_bf16(z) : z) : 0.0;
+  }
+  for (int j = 0; j < GGO_MLP_HIDDEN; ++j) {
+    double a = 0.0;
+    for (int k = 0; k < GGO_MLP_HIDDEN; ++k) a += c->h1[k] * wt(p, P_W2 + k * GGO_MLP_HIDDEN + j, rounding);
+    double z = rounding ? to_f32(to_f32(a) + bs(p, P_B2 + j, 1)) : a + p[P_B2 + j];
+    c->z2[j] = z;
+    c->h2[j] = z > 0.0 ? (rounding ? to_bf16(z) : z) : 0.0;
+  }
+  double a = 0.0;
+  for (int j = 0; j < GGO_MLP_HIDDEN; ++j) a += c->h2[j] * wt(p, P_W3 + j, rounding);
+  c->z = rounding ? to_f32(to_f32(a) + bs(p, P_B3, 1)) : a + p[P_B3];
+  return c->z;
+}
+
+static void feat_to_double(const uint16_t* f8, double* x) {
+  for (int f = 0; f < GGO_MLP_IN; ++f) x[f] = (double)ggo_bf16_value(f8[f]);
+}
+
+void ggo_mlp_forward(const double* params, const uint16_t* feat, int64_t n, int rounding, double* logits) {
+  mlp_cache c;
+  double x[GGO_MLP_IN];
+  for (int64_t i = 0; i < n; ++i) {
+    feat_to_double(feat + i * GGO_MLP_IN, x);
+    logits[i] = mlp_forward(params, x, rounding, &c);
+  }
+}
+
+/* Weighted binary cross-entropy on the logit, mean over the n samples:
+   L = (1/n) sum_i w_i (softplus(z_i) - y_i z_i), w_i = pos_weight for y_i = 1.
+   Gradient by the chain rule; with rounding = 1 the backward pass rounds the
+   pre-activation gradients that enter the W2, W1 and hidden-layer products to
+   bfloat16 (the GPU feeds them to matrix cores), and the ReLU gate reads the
+   rounded activation. */
+void ggo_mlp_loss_grad(const double* p, const uint16_t* feat, const float* label, int64_t n, double pos_weight,
+                       int rounding, double* grad, double* loss_out) {
+  memset(grad, 0, sizeof(double) * GGO_MLP_PARAMS);
+  double loss = 0.0;
+  mlp_cache c;
+  double x[GGO_MLP_IN], g2[GGO_MLP_HIDDEN], g2r[GGO_MLP_HIDDEN], g1[GGO_MLP_HIDDEN];
+  for (int64_t i = 0; i < n; ++i) {
+    feat_to_double(feat + i * GGO_MLP_IN, x);
+    const double z = mlp_forward(p, x, rounding, &c);
+    const double y = label[i];
+    const double w = y > 0.5 ? pos_weight : 1.0;
+    loss += w * ((z > 0.0 ? z : 0.0) - z * y + log1p(exp(-fabs(z))));
+    const double sig = 1.0 / (1.0 + exp(-z));
+    const double dz = w * (sig - y) / (double)n;
+    grad[P_B3] += dz;
+    for (int j = 0; j < GGO_MLP_HIDDEN; ++j) {
+      grad[P_W3 + j] += dz * c.h2[j];
+      g2[j] = c.h2[j] > 0.0 ? dz * wt(p, P_W3 + j, rounding) : 0.0;
+      g2r[j] = rounding ? to_bf16(g2[j]) : g2[j];
+      grad[P_B2 + j] += g2[j];
+    }
+    for (int k = 0; k < GGO_MLP_HIDDEN; ++k) {
+      double dh = 0.0;
+      for (int j = 0; j < GGO_MLP_HIDDEN; ++j) {
+        grad[P_W2 + k * GGO_MLP_HIDDEN + j] += c.h1[k] * g2r[j];
+        dh += g2r[j] * wt(p, P_W2 + k * GGO_MLP_HIDDEN + j, rounding);
+      }
+      g1[k] = c.h1[k] > 0.0 ? dh : 0.0;
+      grad[P_B1 + k] += g1[k];
+    }
+    for (int k = 0; k < GGO_MLP_HIDDEN; ++k) {
+      const double g = rounding ? to_bf16(g1[k]) : g1[k];
+      for (int f = 0; f < GGO_MLP_IN; ++f) grad[P_W1 + f * GGO_MLP_HIDDEN + k] += x[f] * g;
+    }
+  }
+  if (loss_out) *loss_out = n > 0 ? loss / (double)n : 0.0;
+}
+
+/* One Adam step (Kingma and Ba, ICLR'15) with beta1 = 0.9, beta2 = 0.999,
+   eps = 1e-8 and bias correction at step t >= 1. */
+void ggo_adam_step(double* p, double* m, double* v, const double* grad, int64_t count, double lr, int64_t t) {
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+  for (int64_t i = 0; i < count; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * grad[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * grad[i] * grad[i];
+    p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Per-vertex features of the learned policy, each computed in binary32 and
+ * rounded to bfloat16:
+ *   0: lg(1 + out-degree)   1: lg(1 + in-degree)
+ *   2: active in-edges / in-degree (0 without in-edges)
+ *   3: delta(x(i-1), x(i-2))   4: delta(x(i-2), x(i-3))   5-7: zero
+ * lg(y) = L + (y - 2^L) / 2^L with L = floor(log2 y), the piecewise-linear
+ * base-2 logarithm, exact at powers of two. delta compares a vertex's state
+ * in two consecutive iterations: PR/PPR the relative change of its binary32
+ * contribution, capped at 1; SSSP the relative decrease of the distance (1
+ * when it becomes finite, 0 while infinite); CC 1 iff the label changed.
+ * Deltas reaching before iteration 0 are 0.
+ * ------------------------------------------------------------------------- */
+float ggo_lg_feature(int64_t y) {
+  int L = 63 - __builtin_clzll((unsigned long long)y);
+  float t = (float)(y - ((int64_t)1 << L));
+  t = t / ldexpf(1.0f, L);
+  return (float)L + t;
+}
+
+static float word_float(uint32_t w) {
+  float f;
+  memcpy(&f, &w, 4);
+  return f;
+}
+
+float ggo_delta_feature(int32_t app, uint32_t now, uint32_t before) {
+  if (app == GGO_PR || app == GGO_PPR) {
+    const float cn = word_float(now), co = word_float(before);
+    if (!(cn > 0.0f)) return 0.0f;
+    const float r = fabsf(cn - co) / cn;
+    return r < 1.0f ? r : 1.0f;
+  }
+  if (app == GGO_SSSP) {
+    if (now == GGO_INF_U32) return 0.0f;
+    if (before == GGO_INF_U32) return 1.0f;
+    if (before == 0) return 0.0f;
+    return (float)(before - now) / (float)before;
+  }
+  return now != before ? 1.0f : 0.0f;
+}
+
 /* ------------------------------------------------------------------------- */
+
+/* Row modes of one iteration: APPROX gathers over the row's active in-edges,
+   ACCURATE over all of them, SUPER also re-selects their flags (GG-EStatus,
+   Alg. 2) from the influences of this gather. */
+enum { ROW_APPROX = 0, ROW_ACCURATE = 1, ROW_SUPER = 2 };
 
 struct ggo_run {
   ggo_csr g;
   ggo_app_params app;
   ggo_policy pol;
   int32_t* outdeg;
+  int32_t* indeg;
   uint8_t* active; /* edge flags */
   double* infl;    /* influence at the last superstep (diagnostics) */
-  /* values: x (current, iteration i-1) and xn (next) */
+  uint8_t* mode;   /* ROW_* of every row in this iteration */
+  /* values: x (current, iteration i-1), xn (next), sh (approximate shadow
+     pass of a traced superstep) */
   double* pr_x;
   double* pr_xn;
+  double* pr_sh;
   uint32_t* d_x;
   uint32_t* d_xn;
+  uint32_t* d_sh;
   int32_t* l_x;
   int32_t* l_xn;
+  int32_t* l_sh;
+  /* learned policy and traces */
+  uint32_t* hist[2]; /* state words of iterations i-2 and i-3 */
+  int32_t hist_n;    /* how many of them exist */
+  uint16_t* feat;    /* [n][8] features of the last correction step */
+  double* logit;
+  uint8_t* sel;
+  uint8_t* label;
+  int32_t corrections;
+  int32_t have_sel, have_label;
   int32_t iter;
   int32_t done;
   int64_t edges_total;
 };
 
-static int is_accurate(const ggo_policy* p, int32_t i) {
-  switch (p->kind) {
-    case GGO_EXACT: return 1;
-    case GGO_SP: return 0;
-    case GGO_SMS: return i >= p->alpha + 1;
-    case GGO_GG: return (i % (p->alpha + 1)) == 0;
+/* State word of vertex u for the delta features: PR/PPR the binary32
+   contribution x_u / outdeg_u (x_u without out-edges), SSSP the distance,
+   CC the label. */
+static uint32_t state_word(const ggo_run* r, int32_t u) {
+  switch (r->app.app) {
+    case GGO_PR:
+    case GGO_PPR: {
+      const int32_t od = r->outdeg[u];
+      const float c = od > 0 ? (float)(r->pr_x[u] / od) : (float)r->pr_x[u];
+      uint32_t w;
+      memcpy(&w, &c, 4);
+      return w;
+    }
+    case GGO_SSSP: return r->d_x[u];
+    default: return (uint32_t)r->l_x[u];
   }
-  return 1;
-}
-
-/* Edge flags are re-selected after an accurate iteration of GG only (for SMS
-   the flags are never read again after its switch). */
-static int is_superstep(const ggo_policy* p, int32_t i) {
-  return p->kind == GGO_GG && is_accurate(p, i);
 }
 
 ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy* pol) {
@@ -154,9 +369,13 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
   for (int64_t e = 0; e < g->m; ++e)
     if (g->col[e] < 0 || g->col[e] >= g->n) { set_err("col out of range"); return NULL; }
   if (app->app < GGO_PR || app->app > GGO_PPR) { set_err("bad app"); return NULL; }
-  if (pol->kind < GGO_EXACT || pol->kind > GGO_GG) { set_err("bad policy"); return NULL; }
+  if (pol->kind < GGO_EXACT || pol->kind > GGO_LEARNED) { set_err("bad policy"); return NULL; }
   if (pol->alpha < 0 || !(pol->theta >= 0) || !(pol->sigma >= 0 && pol->sigma <= 1)) {
     set_err("bad alpha/theta/sigma");
+    return NULL;
+  }
+  if (pol->kind == GGO_LEARNED && (!pol->mlp || pol->fallback_k < 0 || !(pol->rho >= 0))) {
+    set_err("LEARNED needs mlp, fallback_k >= 0, rho >= 0");
     return NULL;
   }
   if ((app->app == GGO_SSSP || app->app == GGO_PPR) && (app->source < 0 || app->source >= g->n)) {
@@ -181,9 +400,17 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
   int32_t n = g->n;
   int64_t m = g->m;
   r->outdeg = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  r->indeg = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
   for (int64_t e = 0; e < m; ++e) r->outdeg[g->col[e]]++;
+  for (int32_t u = 0; u < n; ++u) r->indeg[u] = g->rowptr[u + 1] - g->rowptr[u];
   r->active = (uint8_t*)calloc((size_t)m + 1, 1);
   r->infl = (double*)calloc((size_t)m + 1, sizeof(double));
+  r->mode = (uint8_t*)calloc((size_t)n + 1, 1);
+  for (int k = 0; k < 2; ++k) r->hist[k] = (uint32_t*)calloc((size_t)n + 1, sizeof(uint32_t));
+  r->feat = (uint16_t*)calloc(((size_t)n + 1) * GGO_MLP_IN, sizeof(uint16_t));
+  r->logit = (double*)calloc((size_t)n + 1, sizeof(double));
+  r->sel = (uint8_t*)calloc((size_t)n + 1, 1);
+  r->label = (uint8_t*)calloc((size_t)n + 1, 1);
 
   /* Initial sparsification [Sec. 3.4]: each edge kept iff its draw falls
      below floor(sigma * 2^32 + 1/2). The exact baseline ignores the flags. */
@@ -194,24 +421,26 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
   /* Initial values. */
   switch (app->app) {
     case GGO_PR:
-      r->pr_x = (double*)malloc(sizeof(double) * ((size_t)n + 1));
-      r->pr_xn = (double*)malloc(sizeof(double) * ((size_t)n + 1));
-      for (int32_t u = 0; u < n; ++u) r->pr_x[u] = 1.0 / n;
-      break;
     case GGO_PPR:
       r->pr_x = (double*)calloc((size_t)n + 1, sizeof(double));
       r->pr_xn = (double*)calloc((size_t)n + 1, sizeof(double));
-      r->pr_x[app->source] = 1.0;
+      r->pr_sh = (double*)calloc((size_t)n + 1, sizeof(double));
+      if (app->app == GGO_PR)
+        for (int32_t u = 0; u < n; ++u) r->pr_x[u] = 1.0 / n;
+      else
+        r->pr_x[app->source] = 1.0;
       break;
     case GGO_SSSP:
       r->d_x = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)n + 1));
       r->d_xn = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)n + 1));
+      r->d_sh = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)n + 1));
       for (int32_t u = 0; u < n; ++u) r->d_x[u] = GGO_INF_U32;
       r->d_x[app->source] = 0;
       break;
     case GGO_CC:
       r->l_x = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
       r->l_xn = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+      r->l_sh = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
       for (int32_t u = 0; u < n; ++u) r->l_x[u] = u;
       break;
   }
@@ -222,13 +451,13 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
 }
 
 /* ---------------------------------------------------------------------------
- * One PageRank / personalized PageRank iteration [Alg. 2]. Gather sums the
- * contributions x_v / outdeg_v over the row's edge set; Apply computes
+ * One PageRank / personalized PageRank pass [Alg. 2] into out[]. Gather sums
+ * the contributions x_v / outdeg_v over the row's edge set; Apply computes
  * (1-d)/N + d * (sum + D/N) (PPR: teleport and dangling mass go to the
- * source). On a superstep, each edge's influence is computed during the
- * gather from the running sum, and GG-EStatus sets its flag.
+ * source). For a SUPER row each edge's influence is computed from the
+ * running sum of the row, all in-edges in CSR order.
  * ------------------------------------------------------------------------- */
-static void step_pr(ggo_run* r, int accurate, int superstep, ggo_step_info* info) {
+static void pass_pr(ggo_run* r, const uint8_t* mode, double* out, int64_t* edges_out, int64_t* changed_out) {
   const ggo_csr* g = &r->g;
   const int32_t n = g->n;
   const double d = r->app.damping;
@@ -241,16 +470,16 @@ static void step_pr(ggo_run* r, int accurate, int superstep, ggo_step_info* info
 
   int64_t edges = 0, changed = 0;
   for (int32_t u = 0; u < n; ++u) {
-    double sum = 0.0;   /* gather accumulator */
-    double P = 0.0;     /* running sum of binary32 contributions (influence) */
+    double sum = 0.0; /* gather accumulator */
+    double P = 0.0;   /* running sum of binary32 contributions (influence) */
     const int32_t b = g->rowptr[u], e_end = g->rowptr[u + 1];
     for (int32_t e = b; e < e_end; ++e) {
-      if (!accurate && !r->active[e]) continue;
+      if (mode[u] == ROW_APPROX && !r->active[e]) continue;
       const int32_t v = g->col[e];
       sum += r->pr_x[v] / r->outdeg[v];
       ++edges;
     }
-    if (superstep) {
+    if (mode[u] == ROW_SUPER) {
       double rowsum32 = 0.0;
       if (r->pol.influence == GGO_INFL_TOTAL)
         for (int32_t e = b; e < e_end; ++e) {
@@ -275,22 +504,19 @@ static void step_pr(ggo_run* r, int accurate, int superstep, ggo_step_info* info
     else
       xn = (1.0 - d) / n + d * (sum + D / n);
     if (xn != r->pr_x[u]) ++changed;
-    r->pr_xn[u] = xn;
+    out[u] = xn;
   }
-  double* t = r->pr_x;
-  r->pr_x = r->pr_xn;
-  r->pr_xn = t;
-  info->edges = edges;
-  info->changed = changed;
+  *edges_out = edges;
+  *changed_out = changed;
 }
 
 /* ---------------------------------------------------------------------------
- * One SSSP iteration: x_u <- min(x_u, min over the edge set of x_v + w_e),
- * unreached sources (INF) contribute nothing. On a superstep the running
+ * One SSSP pass: x_u <- min(x_u, min over the edge set of x_v + w_e),
+ * unreached sources (INF) contribute nothing. For a SUPER row the running
  * minimum r over the row (starting at INF) gives each assessable edge its
  * influence.
  * ------------------------------------------------------------------------- */
-static void step_sssp(ggo_run* r, int accurate, int superstep, ggo_step_info* info) {
+static void pass_sssp(ggo_run* r, const uint8_t* mode, uint32_t* out, int64_t* edges_out, int64_t* changed_out) {
   const ggo_csr* g = &r->g;
   const int32_t n = g->n;
   int64_t edges = 0, changed = 0;
@@ -298,14 +524,14 @@ static void step_sssp(ggo_run* r, int accurate, int superstep, ggo_step_info* in
     uint32_t best = r->d_x[u];
     const int32_t b = g->rowptr[u], e_end = g->rowptr[u + 1];
     for (int32_t e = b; e < e_end; ++e) {
-      if (!accurate && !r->active[e]) continue;
+      if (mode[u] == ROW_APPROX && !r->active[e]) continue;
       ++edges;
       const uint32_t xv = r->d_x[g->col[e]];
       if (xv == GGO_INF_U32) continue;
       const uint64_t cand = (uint64_t)xv + (uint64_t)g->weight[e];
       if (cand < best) best = (uint32_t)cand;
     }
-    if (superstep) {
+    if (mode[u] == ROW_SUPER) {
       uint64_t run = GGO_INF_U32; /* running minimum, starts at INF */
       for (int32_t e = b; e < e_end; ++e) {
         const uint32_t xv = r->d_x[g->col[e]];
@@ -321,21 +547,18 @@ static void step_sssp(ggo_run* r, int accurate, int superstep, ggo_step_info* in
       }
     }
     if (best != r->d_x[u]) ++changed;
-    r->d_xn[u] = best;
+    out[u] = best;
   }
-  uint32_t* t = r->d_x;
-  r->d_x = r->d_xn;
-  r->d_xn = t;
-  info->edges = edges;
-  info->changed = changed;
+  *edges_out = edges;
+  *changed_out = changed;
 }
 
 /* ---------------------------------------------------------------------------
- * One CC (label propagation) iteration on the symmetrized graph:
- * x_u <- min(x_u, min over the edge set of x_v). Superstep influence is
- * binary: 1 iff x_v lowers the running minimum of the row.
+ * One CC (label propagation) pass on the symmetrized graph:
+ * x_u <- min(x_u, min over the edge set of x_v). For a SUPER row the
+ * influence is binary: 1 iff x_v lowers the running minimum of the row.
  * ------------------------------------------------------------------------- */
-static void step_cc(ggo_run* r, int accurate, int superstep, ggo_step_info* info) {
+static void pass_cc(ggo_run* r, const uint8_t* mode, int32_t* out, int64_t* edges_out, int64_t* changed_out) {
   const ggo_csr* g = &r->g;
   const int32_t n = g->n;
   int64_t edges = 0, changed = 0;
@@ -343,12 +566,12 @@ static void step_cc(ggo_run* r, int accurate, int superstep, ggo_step_info* info
     int32_t best = r->l_x[u];
     const int32_t b = g->rowptr[u], e_end = g->rowptr[u + 1];
     for (int32_t e = b; e < e_end; ++e) {
-      if (!accurate && !r->active[e]) continue;
+      if (mode[u] == ROW_APPROX && !r->active[e]) continue;
       ++edges;
       const int32_t xv = r->l_x[g->col[e]];
       if (xv < best) best = xv;
     }
-    if (superstep) {
+    if (mode[u] == ROW_SUPER) {
       int64_t run = INT64_MAX;
       for (int32_t e = b; e < e_end; ++e) {
         const int32_t xv = r->l_x[g->col[e]];
@@ -357,34 +580,39 @@ static void step_cc(ggo_run* r, int accurate, int superstep, ggo_step_info* info
       }
     }
     if (best != r->l_x[u]) ++changed;
-    r->l_xn[u] = best;
+    out[u] = best;
   }
-  int32_t* t = r->l_x;
-  r->l_x = r->l_xn;
-  r->l_xn = t;
-  info->edges = edges;
-  info->changed = changed;
+  *edges_out = edges;
+  *changed_out = changed;
 }
 
-/* GG-EStatus [Alg. 2] applied after a superstep: an assessed edge is active
-   iff its influence exceeds theta; every other edge is deactivated whether or
-   not it was active before [Sec. 3.4] (the UNION variant keeps old flags). */
+/* GG-EStatus [Alg. 2] for the SUPER rows after their pass: an assessed edge
+   is active iff its influence exceeds theta; every other edge of the row is
+   deactivated whether or not it was active before [Sec. 3.4] (the UNION
+   variant keeps old flags). */
 static void estatus(ggo_run* r) {
-  for (int64_t e = 0; e < r->g.m; ++e) {
-    const int flag = r->infl[e] > r->pol.theta;
-    r->active[e] = r->pol.mask_update == GGO_MASK_UNION ? (uint8_t)(r->active[e] | flag) : (uint8_t)flag;
+  const ggo_csr* g = &r->g;
+  for (int32_t u = 0; u < g->n; ++u) {
+    if (r->mode[u] != ROW_SUPER) continue;
+    for (int32_t e = g->rowptr[u]; e < g->rowptr[u + 1]; ++e) {
+      const int flag = r->infl[e] > r->pol.theta;
+      r->active[e] = r->pol.mask_update == GGO_MASK_UNION ? (uint8_t)(r->active[e] | flag) : (uint8_t)flag;
+    }
   }
 }
 
-/* SSSP EStatus needs the values the superstep gathered from (iteration i-1),
-   so it runs before the values are swapped; see ggo_step. */
-static void estatus_sssp(ggo_run* r, const uint32_t* x_prev) {
+/* SSSP EStatus compares integers on the values the pass gathered from
+   (iteration i-1): relative improvement (r - new) / r > theta as
+   (r - new) * 2^16 > theta_q * r; the first finite candidate is active; an
+   edge whose source is unreached is not assessed and keeps its flag. */
+static void estatus_sssp(ggo_run* r) {
   const ggo_csr* g = &r->g;
   const uint64_t theta_q = (uint64_t)floor(r->pol.theta * 65536.0 + 0.5);
   for (int32_t u = 0; u < g->n; ++u) {
+    if (r->mode[u] != ROW_SUPER) continue;
     uint64_t run = GGO_INF_U32;
     for (int32_t e = g->rowptr[u]; e < g->rowptr[u + 1]; ++e) {
-      const uint32_t xv = x_prev[g->col[e]];
+      const uint32_t xv = r->d_x[g->col[e]];
       if (xv == GGO_INF_U32) continue; /* not assessable: keeps its flag */
       const uint64_t cand = (uint64_t)xv + (uint64_t)g->weight[e];
       const uint64_t nw = cand < run ? cand : run;
@@ -399,52 +627,187 @@ static void estatus_sssp(ggo_run* r, const uint32_t* x_prev) {
   }
 }
 
+/* Features of every vertex before iteration i (state of iteration i-1 and
+   the two before it). */
+static void compute_features(ggo_run* r) {
+  const ggo_csr* g = &r->g;
+  for (int32_t u = 0; u < g->n; ++u) {
+    uint16_t* f = r->feat + (size_t)u * GGO_MLP_IN;
+    int64_t act = 0;
+    for (int32_t e = g->rowptr[u]; e < g->rowptr[u + 1]; ++e) act += r->active[e];
+    const int32_t id = r->indeg[u];
+    const uint32_t now = state_word(r, u);
+    const float d1 = r->hist_n >= 1 ? ggo_delta_feature(r->app.app, now, r->hist[0][u]) : 0.0f;
+    const float d2 = r->hist_n >= 2 ? ggo_delta_feature(r->app.app, r->hist[0][u], r->hist[1][u]) : 0.0f;
+    f[0] = ggo_bf16_bits(ggo_lg_feature(1 + (int64_t)r->outdeg[u]));
+    f[1] = ggo_bf16_bits(ggo_lg_feature(1 + (int64_t)id));
+    f[2] = ggo_bf16_bits(id > 0 ? (float)act / (float)id : 0.0f);
+    f[3] = ggo_bf16_bits(d1);
+    f[4] = ggo_bf16_bits(d2);
+    f[5] = f[6] = f[7] = 0;
+  }
+}
+
+/* Logits of the learned policy (rounding as on the GPU) and the selected set
+   S = { v : binary32(logit_v) > tau }. Returns |S|. */
+static int64_t select_rows(ggo_run* r) {
+  ggo_mlp_forward(r->pol.mlp, r->feat, r->g.n, 1, r->logit);
+  int64_t cnt = 0;
+  for (int32_t u = 0; u < r->g.n; ++u) {
+    r->sel[u] = (float)r->logit[u] > (float)r->pol.tau;
+    cnt += r->sel[u];
+  }
+  r->have_sel = 1;
+  return cnt;
+}
+
+static void run_pass(ggo_run* r, const uint8_t* mode, int shadow, int64_t* edges, int64_t* changed) {
+  switch (r->app.app) {
+    case GGO_PR:
+    case GGO_PPR: pass_pr(r, mode, shadow ? r->pr_sh : r->pr_xn, edges, changed); break;
+    case GGO_SSSP: pass_sssp(r, mode, shadow ? r->d_sh : r->d_xn, edges, changed); break;
+    case GGO_CC: pass_cc(r, mode, shadow ? r->l_sh : r->l_xn, edges, changed); break;
+  }
+}
+
+/* Drift labels of a traced full superstep: 1 where the approximate update
+   (shadow pass over the active edges) differs from the accurate one: PR/PPR
+   binary32 contributions differing by more than label_eps relative, SSSP a
+   shorter accurate distance, CC a smaller accurate label. */
+static void compute_labels(ggo_run* r) {
+  const int32_t n = r->g.n;
+  for (int32_t u = 0; u < n; ++u) {
+    int y;
+    switch (r->app.app) {
+      case GGO_PR:
+      case GGO_PPR: {
+        const int32_t od = r->outdeg[u];
+        const float ca = od > 0 ? (float)(r->pr_xn[u] / od) : (float)r->pr_xn[u];
+        const float cs = od > 0 ? (float)(r->pr_sh[u] / od) : (float)r->pr_sh[u];
+        y = fabsf(ca - cs) > (float)r->pol.label_eps * ca;
+        break;
+      }
+      case GGO_SSSP: y = r->d_xn[u] < r->d_sh[u]; break;
+      default: y = r->l_xn[u] < r->l_sh[u]; break;
+    }
+    r->label[u] = (uint8_t)y;
+  }
+  r->have_label = 1;
+}
+
 int ggo_step(ggo_run* r, ggo_step_info* info) {
   ggo_step_info tmp;
   if (!info) info = &tmp;
   memset(info, 0, sizeof(*info));
   if (r->done) return 0;
   const int32_t i = r->iter + 1;
-  const int accurate = is_accurate(&r->pol, i);
-  const int superstep = is_superstep(&r->pol, i);
-  info->iter = i;
-  info->accurate = accurate;
-  info->superstep = superstep;
-  switch (r->app.app) {
-    case GGO_PR:
-    case GGO_PPR:
-      step_pr(r, accurate, superstep, info);
-      if (superstep) estatus(r);
-      break;
-    case GGO_SSSP:
-      step_sssp(r, accurate, superstep, info);
-      if (superstep) estatus_sssp(r, r->d_xn); /* d_xn now holds iteration i-1 */
-      break;
-    case GGO_CC:
-      step_cc(r, accurate, superstep, info);
-      if (superstep) estatus(r);
+  const int32_t n = r->g.n;
+  const ggo_policy* p = &r->pol;
+  /* Kind of this iteration: every row alike, except the partial superstep
+     of the learned policy. */
+  int kind = GGO_KIND_APPROX;
+  int64_t selected = -1;
+  r->have_sel = 0;
+  r->have_label = 0;
+  switch (p->kind) {
+    case GGO_EXACT: kind = GGO_KIND_ACCURATE; break;
+    case GGO_SP: kind = GGO_KIND_APPROX; break;
+    case GGO_SMS: kind = i >= p->alpha + 1 ? GGO_KIND_ACCURATE : GGO_KIND_APPROX; break;
+    case GGO_GG: kind = (i % (p->alpha + 1)) == 0 ? GGO_KIND_FULL : GGO_KIND_APPROX; break;
+    case GGO_LEARNED:
+      if ((i % (p->alpha + 1)) == 0) {
+        const int32_t c = ++r->corrections;
+        compute_features(r);
+        selected = select_rows(r);
+        if ((p->fallback_k > 0 && c % p->fallback_k == 0) || (double)selected > p->rho * (double)n)
+          kind = GGO_KIND_FULL;
+        else
+          kind = GGO_KIND_PARTIAL;
+      }
       break;
   }
+  for (int32_t u = 0; u < n; ++u) {
+    switch (kind) {
+      case GGO_KIND_APPROX: r->mode[u] = ROW_APPROX; break;
+      case GGO_KIND_ACCURATE: r->mode[u] = ROW_ACCURATE; break;
+      case GGO_KIND_FULL: r->mode[u] = ROW_SUPER; break;
+      default: r->mode[u] = r->sel[u] ? ROW_SUPER : ROW_APPROX; break;
+    }
+  }
+  const int traced = p->trace && kind == GGO_KIND_FULL;
+  if (traced && p->kind != GGO_LEARNED) compute_features(r);
+  int64_t edges = 0, changed = 0;
+  if (traced) {
+    /* approximate shadow pass: the update the flags alone would give */
+    uint8_t* approx = (uint8_t*)calloc((size_t)n + 1, 1);
+    int64_t e2, c2;
+    run_pass(r, approx, 1, &e2, &c2);
+    free(approx);
+  }
+  run_pass(r, r->mode, 0, &edges, &changed);
+  if (traced) compute_labels(r);
+  if (kind == GGO_KIND_FULL || kind == GGO_KIND_PARTIAL) {
+    if (r->app.app == GGO_SSSP)
+      estatus_sssp(r); /* reads d_x, still iteration i-1 */
+    else
+      estatus(r);
+  }
+  /* history of state words for the delta features, then the swap */
+  {
+    uint32_t* t = r->hist[1];
+    r->hist[1] = r->hist[0];
+    r->hist[0] = t;
+    for (int32_t u = 0; u < n; ++u) r->hist[0][u] = state_word(r, u);
+    if (r->hist_n < 2) r->hist_n++;
+  }
+  switch (r->app.app) {
+    case GGO_PR:
+    case GGO_PPR: {
+      double* t = r->pr_x;
+      r->pr_x = r->pr_xn;
+      r->pr_xn = t;
+      break;
+    }
+    case GGO_SSSP: {
+      uint32_t* t = r->d_x;
+      r->d_x = r->d_xn;
+      r->d_xn = t;
+      break;
+    }
+    case GGO_CC: {
+      int32_t* t = r->l_x;
+      r->l_x = r->l_xn;
+      r->l_xn = t;
+      break;
+    }
+  }
+  info->iter = i;
+  info->kind = kind;
+  info->accurate = kind == GGO_KIND_ACCURATE || kind == GGO_KIND_FULL;
+  info->superstep = kind == GGO_KIND_FULL || kind == GGO_KIND_PARTIAL;
+  info->edges = edges;
+  info->changed = changed;
+  info->selected = selected;
   r->iter = i;
-  r->edges_total += info->edges;
+  r->edges_total += edges;
   int64_t act = 0;
   for (int64_t e = 0; e < r->g.m; ++e) act += r->active[e];
-  info->active_edges = r->pol.kind == GGO_EXACT ? r->g.m : act;
+  info->active_edges = p->kind == GGO_EXACT ? r->g.m : act;
 
   /* Termination. */
   const int app = r->app.app;
   if (app == GGO_PR || app == GGO_PPR) {
     if (i >= r->app.iters) r->done = 1;
-  } else if (r->pol.kind == GGO_EXACT) {
-    if (info->changed == 0 || i >= r->app.max_iters) r->done = 1;
-  } else if (r->pol.stop == GGO_STOP_FIXED_ITERS) {
+  } else if (p->kind == GGO_EXACT) {
+    if (changed == 0 || i >= r->app.max_iters) r->done = 1;
+  } else if (p->stop == GGO_STOP_FIXED_ITERS) {
     if (i >= r->app.iters) r->done = 1;
   } else {
     /* Fixed point: a no-change iteration ends the run when no later
-       iteration can differ from it (an accurate iteration, or any iteration
-       of SP, whose edge set never changes). */
-    const int final_kind = accurate || r->pol.kind == GGO_SP;
-    if ((info->changed == 0 && final_kind) || i >= r->app.max_iters) r->done = 1;
+       iteration can differ from it (an iteration over every edge, or any
+       iteration of SP, whose edge set never changes). */
+    const int final_kind = info->accurate || p->kind == GGO_SP;
+    if ((changed == 0 && final_kind) || i >= r->app.max_iters) r->done = 1;
   }
   return 1;
 }
@@ -469,16 +832,43 @@ void ggo_get_influence(const ggo_run* r, double* out) {
   memcpy(out, r->infl, (size_t)r->g.m * sizeof(double));
 }
 
+void ggo_get_features(const ggo_run* r, uint16_t* out) {
+  memcpy(out, r->feat, (size_t)r->g.n * GGO_MLP_IN * sizeof(uint16_t));
+}
+
+int ggo_get_selection(const ggo_run* r, uint8_t* sel, double* logits) {
+  if (!r->have_sel) return 0;
+  if (sel) memcpy(sel, r->sel, (size_t)r->g.n);
+  if (logits) memcpy(logits, r->logit, (size_t)r->g.n * sizeof(double));
+  return 1;
+}
+
+int ggo_get_labels(const ggo_run* r, uint8_t* out) {
+  if (!r->have_label) return 0;
+  memcpy(out, r->label, (size_t)r->g.n);
+  return 1;
+}
+
 void ggo_end(ggo_run* r) {
   if (!r) return;
   free(r->outdeg);
+  free(r->indeg);
   free(r->active);
   free(r->infl);
+  free(r->mode);
+  for (int k = 0; k < 2; ++k) free(r->hist[k]);
+  free(r->feat);
+  free(r->logit);
+  free(r->sel);
+  free(r->label);
   free(r->pr_x);
   free(r->pr_xn);
+  free(r->pr_sh);
   free(r->d_x);
   free(r->d_xn);
+  free(r->d_sh);
   free(r->l_x);
   free(r->l_xn);
+  free(r->l_sh);
   free(r);
 }

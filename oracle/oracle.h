@@ -27,7 +27,19 @@ enum { GGO_PR = 0, GGO_SSSP = 1, GGO_CC = 2, GGO_PPR = 3 };
 /* Correction schemes: EXACT = accurate mode every iteration (the baseline of
    Sec. 5); SP = sparsified only; SMS = static mode switch; GG = adaptive
    correction with periodic supersteps (Sec. 3.4, Sec. 5.2). */
-enum { GGO_EXACT = 0, GGO_SP = 1, GGO_SMS = 2, GGO_GG = 3 };
+enum { GGO_EXACT = 0, GGO_SP = 1, GGO_SMS = 2, GGO_GG = 3, GGO_LEARNED = 4 };
+/* LEARNED (not in the paper): GG's schedule, but at a correction step an MLP
+   over per-vertex features selects the rows S that are corrected (gathered
+   over all in-edges, flags re-selected); the other rows take an approximate
+   iteration. A full superstep replaces it every fallback_k-th correction
+   step (fallback_k > 0) and whenever |S| > rho * n. */
+/* Kind of an executed iteration. */
+enum { GGO_KIND_APPROX = 0, GGO_KIND_ACCURATE = 1, GGO_KIND_FULL = 2, GGO_KIND_PARTIAL = 3 };
+#define GGO_MLP_IN 8
+#define GGO_MLP_HIDDEN 64
+/* Parameter vector: W1 [8][64], b1 [64], W2 [64][64], b2 [64], w3 [64], b3. */
+#define GGO_MLP_PARAMS \
+  (GGO_MLP_IN * GGO_MLP_HIDDEN + GGO_MLP_HIDDEN + GGO_MLP_HIDDEN * GGO_MLP_HIDDEN + GGO_MLP_HIDDEN + GGO_MLP_HIDDEN + 1)
 enum { GGO_STOP_FIXED_ITERS = 0, GGO_STOP_FIXED_POINT = 1 };
 enum { GGO_INFL_PREFIX = 0, GGO_INFL_TOTAL = 1 };
 enum { GGO_MASK_REPLACE = 0, GGO_MASK_UNION = 1 };
@@ -53,7 +65,7 @@ typedef struct {
 } ggo_app_params;
 
 typedef struct {
-  int32_t kind;        /* GGO_EXACT / GGO_SP / GGO_SMS / GGO_GG */
+  int32_t kind;        /* GGO_EXACT / GGO_SP / GGO_SMS / GGO_GG / GGO_LEARNED */
   int32_t alpha;       /* approximate window */
   double theta;        /* influence threshold */
   double sigma;        /* sparsification parameter (sampling ratio) */
@@ -61,6 +73,12 @@ typedef struct {
   int32_t influence;   /* GGO_INFL_* */
   int32_t mask_update; /* GGO_MASK_* */
   int32_t stop;        /* GGO_STOP_* (SSSP/CC) */
+  const double* mlp;   /* LEARNED: GGO_MLP_PARAMS binary32 master values */
+  double tau;          /* LEARNED: select v iff binary32(logit_v) > binary32(tau) */
+  double rho;          /* LEARNED: full superstep when |S| > rho * n */
+  int32_t fallback_k;  /* LEARNED: every k-th correction step is full (0: never) */
+  int32_t trace;       /* 1: features and drift labels at every full superstep */
+  double label_eps;    /* PR/PPR drift label: relative contribution change */
 } ggo_policy;
 
 typedef struct {
@@ -70,6 +88,8 @@ typedef struct {
   int64_t edges;       /* edges gathered */
   int64_t changed;     /* vertices whose value changed */
   int64_t active_edges;/* active edges after the iteration */
+  int32_t kind;        /* GGO_KIND_* */
+  int64_t selected;    /* LEARNED correction steps: |S|; else -1 */
 } ggo_step_info;
 
 typedef struct ggo_run ggo_run;
@@ -96,7 +116,31 @@ void ggo_get_mask(const ggo_run* r, uint8_t* out);
    relative improvement, 1 for the first finite candidate, -1 when not
    assessable; CC: 1/0). */
 void ggo_get_influence(const ggo_run* r, double* out);
+/* Features [n][8] (bfloat16 bits) of the last correction or traced step. */
+void ggo_get_features(const ggo_run* r, uint16_t* out);
+/* Selection and logits of this step (LEARNED correction steps); 0 if none. */
+int ggo_get_selection(const ggo_run* r, uint8_t* sel, double* logits);
+/* Drift labels of this step (traced full supersteps); 0 if none. */
+int ggo_get_labels(const ggo_run* r, uint8_t* out);
 void ggo_end(ggo_run* r);
+
+/* bfloat16: round to nearest even from binary32 (NaN -> 0x7FC0), and back. */
+uint16_t ggo_bf16_bits(float f);
+float ggo_bf16_value(uint16_t b);
+void ggo_bf16_array(const float* in, uint16_t* out, int64_t n);
+/* Feature helpers (binary32): piecewise-linear log2 of y >= 1, and the delta
+   of two state words (PR/PPR: binary32 contribution bits; SSSP: distance;
+   CC: label). */
+float ggo_lg_feature(int64_t y);
+float ggo_delta_feature(int32_t app, uint32_t now, uint32_t before);
+/* MLP: logits of n samples (features [n][8] bfloat16 bits); rounding = 1
+   follows the GPU's rounding points, 0 is plain binary64. */
+void ggo_mlp_forward(const double* params, const uint16_t* feat, int64_t n, int rounding, double* logits);
+/* Mean weighted BCE-with-logits loss and its gradient (GGO_MLP_PARAMS). */
+void ggo_mlp_loss_grad(const double* params, const uint16_t* feat, const float* label, int64_t n,
+                       double pos_weight, int rounding, double* grad, double* loss);
+/* One Adam step at step number t >= 1 (beta1 0.9, beta2 0.999, eps 1e-8). */
+void ggo_adam_step(double* p, double* m, double* v, const double* grad, int64_t count, double lr, int64_t t);
 const char* ggo_last_error(void);
 
 #ifdef __cplusplus
