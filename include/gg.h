@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GG_VERSION 1
+#define GG_VERSION 2
 
 typedef enum {
   GG_OK = 0,
@@ -58,8 +58,25 @@ typedef enum { GG_APP_PR = 0, GG_APP_SSSP = 1, GG_APP_CC = 2, GG_APP_PPR = 3 } g
 
 /* Correction schemes: EXACT = accurate mode in every iteration (the baseline
    of Sec. 5); SP = sparsified for the whole run; SMS = approximate for alpha
-   iterations then accurate for the rest; GG = adaptive correction [Sec. 3.4]. */
-typedef enum { GG_POLICY_EXACT = 0, GG_POLICY_SP = 1, GG_POLICY_SMS = 2, GG_POLICY_GG = 3 } gg_policy_kind;
+   iterations then accurate for the rest; GG = adaptive correction [Sec. 3.4].
+   LEARNED (not in the paper; it addresses the automatic choice of control
+   parameters the paper leaves to future work, Sec. 7) keeps GG's schedule,
+   but at a correction step (iteration i with i mod (alpha+1) == 0) a network
+   scores every vertex; the selected rows S = { v : logit_v > tau } are
+   gathered over all in-edges and have their flags re-selected (a partial
+   superstep) while every other row takes an approximate iteration. Every
+   fallback_k-th correction step (fallback_k > 0), and every step with
+   |S| > rho * n, is GG's full superstep instead. */
+typedef enum {
+  GG_POLICY_EXACT = 0,
+  GG_POLICY_SP = 1,
+  GG_POLICY_SMS = 2,
+  GG_POLICY_GG = 3,
+  GG_POLICY_LEARNED = 4
+} gg_policy_kind;
+
+/* Kind of an executed iteration (gg_step_info.kind). */
+typedef enum { GG_STEP_APPROX = 0, GG_STEP_ACCURATE = 1, GG_STEP_FULL = 2, GG_STEP_PARTIAL = 3 } gg_step_kind;
 
 /* SSSP/CC termination for non-exact schemes: FIXED_ITERS runs exactly
    gg_app_params.iters iterations (the same count as the exact baseline,
@@ -115,6 +132,9 @@ typedef struct {
   int32_t dangling;  /* gg_dangling */
 } gg_app_params;
 
+typedef struct gg_mlp gg_mlp;
+typedef struct gg_trace gg_trace;
+
 typedef struct {
   int32_t kind;        /* gg_policy_kind */
   int32_t alpha;       /* approximate window, >= 0 [Sec. 3.4] */
@@ -123,6 +143,16 @@ typedef struct {
   int32_t influence;   /* gg_influence (PR/PPR) */
   int32_t mask_update; /* gg_mask_update */
   int32_t stop;        /* gg_stop (SSSP/CC) */
+  /* LEARNED only (zero otherwise) */
+  const gg_mlp* mlp;   /* the scoring network (on the graph's device) */
+  float tau;           /* selection threshold on the binary32 logit */
+  double rho;          /* full superstep when |S| > rho * n, rho >= 0 */
+  int32_t fallback_k;  /* every fallback_k-th correction step is full; 0 = never */
+  int32_t judge;       /* 1: at full supersteps, score the selection against the drift labels */
+  /* GG and LEARNED: optional trace (NULL = none). At every full superstep the
+     features of each vertex and its drift label are appended. */
+  gg_trace* trace;
+  float label_eps;     /* PR/PPR drift label: relative change of the contribution, > 0 */
 } gg_correction_policy;
 
 typedef struct {
@@ -133,6 +163,11 @@ typedef struct {
   double device_ms;         /* device time of the run (HIP events on the graph's stream) */
   int64_t edges_processed;  /* edges actually read (frontier iterations read fewer) */
   int32_t sparse_iterations;/* SSSP/CC iterations run as frontier pushes */
+  int32_t partial_supersteps; /* LEARNED: partial supersteps executed */
+  int64_t selected_total;   /* LEARNED: sum of |S| over correction steps */
+  int64_t judge_positives;  /* judged full supersteps: vertices that drifted */
+  int64_t judge_hits;       /* ... of which the network selected */
+  int64_t judge_selected;   /* ... vertices the network selected */
 } gg_run_stats;
 
 typedef struct {
@@ -144,6 +179,8 @@ typedef struct {
   int64_t active_edges;  /* active edges after it */
   int64_t edges_processed; /* edges actually read by it */
   int32_t sparse;        /* 1 if it ran as a frontier push (SSSP/CC) */
+  int32_t kind;          /* gg_step_kind */
+  int64_t selected;      /* LEARNED correction steps: |S|; otherwise -1 */
 } gg_step_info;
 
 typedef struct gg_graph gg_graph;
@@ -232,6 +269,14 @@ int gg_run_step(gg_run* run, gg_step_info* info);
 int gg_run_values(gg_run* run, void* out_values, uint32_t out_flags);
 int gg_run_mask(gg_run* run, uint32_t* out_bits_host);
 int gg_run_stats_get(gg_run* run, gg_run_stats* stats);
+/* Per-vertex state of the last correction step (LEARNED) or traced full
+   superstep, copied to host memory: features [n][8] bfloat16 bits; the
+   selection (1 byte per vertex) and binary32 logits of a LEARNED correction
+   step; the drift labels (1 byte per vertex) of a traced or judged full
+   superstep. GG_E_STATE when the last step produced no such data. */
+int gg_run_features(gg_run* run, uint16_t* feat_host);
+int gg_run_selection(gg_run* run, uint8_t* sel_host, float* logits_host);
+int gg_run_labels(gg_run* run, uint8_t* labels_host);
 void gg_run_end(gg_run* run);
 
 /*
@@ -275,7 +320,9 @@ int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t);
  * in approximate mode,) out-degree or own value, and the value written.
  * kind: 0 = accurate gather, 1 = approximate gather, 2 = superstep,
  * 3 = frontier push (SSSP/CC; per pushed edge: edge id, destination, weight
- * and flag words and the atomic on the target).
+ * and flag words and the atomic on the target), 4 = partial superstep of the
+ * learned policy (approximate gather of the unselected rows plus the
+ * superstep of the selected ones).
  * gg_graph_set_profiling(g, 1) clears the counters. gg_graph_get_profile
  * synchronizes the stream and reports the totals for (kind, app).
  */
@@ -288,6 +335,76 @@ typedef struct {
 
 int gg_graph_set_profiling(gg_graph* g, int enable);
 int gg_graph_get_profile(gg_graph* g, int kind, int app, gg_kernel_profile* out);
+
+/*
+ * Learned correction network (GG_POLICY_LEARNED). An 8-64-64-1 ReLU MLP over
+ * per-vertex features, all computed in binary32 and rounded to bfloat16
+ * (round to nearest even):
+ *   f0 = lg(1 + out-degree), f1 = lg(1 + in-degree), where lg(y) = L +
+ *        (y - 2^L) / 2^L with L = floor(log2 y);
+ *   f2 = active in-edges / in-degree (0 without in-edges);
+ *   f3 = delta of the vertex state between iterations i-1 and i-2, f4 the
+ *        same between i-2 and i-3 (0 before iteration 0); the state is the
+ *        binary32 contribution x_v / outdeg_v for PR/PPR (x_v without
+ *        out-edges; delta = relative change capped at 1), the distance for
+ *        SSSP (relative decrease; 1 when it becomes finite, 0 while
+ *        infinite), the label for CC (1 iff it changed);
+ *   f5..f7 = 0.
+ * Layers: h1 = bf16(relu(x W1 + b1)), h2 = bf16(relu(h1 W2 + b2)),
+ * logit = h2 w3 + b3, with bfloat16 W1, W2, w3 and binary32 biases and
+ * accumulation (matrix cores). Parameters in host order (GG_MLP_PARAMS
+ * binary32): W1 [8][64], b1 [64], W2 [64][64], b2 [64], w3 [64], b3.
+ *
+ * The drift label of a vertex at a full superstep is 1 when its accurate
+ * update differs from the approximate update its current flags would give:
+ * PR/PPR binary32 contributions differing by more than label_eps relative,
+ * SSSP a shorter distance, CC a smaller label.
+ *
+ * Training minimises the mean weighted binary cross-entropy on the logit
+ * (weight pos_weight on label-1 samples) with Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) on the binary32 master parameters; the bfloat16 copies are
+ * refreshed after every step.
+ *
+ * All MLP calls run on the network's stream (set at creation); pointers
+ * marked _dev are device pointers on that device. A gg_mlp may be used by a
+ * run on any graph of the same device; the run reads it on the graph's
+ * stream, so the caller orders the two streams (or uses one stream).
+ */
+#define GG_MLP_IN 8
+#define GG_MLP_HIDDEN 64
+#define GG_MLP_PARAMS 4801
+
+/* He-uniform initial weights from a SplitMix64 stream seeded by seed, zero
+   biases. */
+int gg_mlp_create(void* hip_stream, uint64_t seed, gg_mlp** out);
+void gg_mlp_free(gg_mlp* mlp);
+/* Host arrays of GG_MLP_PARAMS binary32 values; set resets Adam's state. */
+int gg_mlp_set_weights(gg_mlp* mlp, const float* params_host);
+int gg_mlp_get_weights(gg_mlp* mlp, float* params_host);
+/* Logits of n samples: feat_dev [n][8] bfloat16 bits, logits_dev float[n]. */
+int gg_mlp_forward(gg_mlp* mlp, const uint16_t* feat_dev, int64_t n, float* logits_dev);
+/* Gradient of the mean loss over n samples (labels 0/1 as float) into
+   grad_dev[0..GG_MLP_PARAMS), and the loss sum into grad_dev[GG_MLP_PARAMS]. */
+int gg_mlp_loss_grad(gg_mlp* mlp, const uint16_t* feat_dev, const float* label_dev, int64_t n, float pos_weight,
+                     float* grad_dev);
+/* One Adam step with the gradient in grad_dev (GG_MLP_PARAMS floats). */
+int gg_mlp_adam_step(gg_mlp* mlp, const float* grad_dev, float lr);
+/* epochs passes over the trace in mini-batches of `batch` consecutive
+   samples, batch order shuffled per epoch (SplitMix64 Fisher-Yates on seed);
+   epoch_loss_host (nullable) receives each epoch's mean loss. */
+int gg_mlp_train(gg_mlp* mlp, const gg_trace* trace, int32_t epochs, int32_t batch, float lr, float pos_weight,
+                 uint64_t seed, float* epoch_loss_host);
+
+/* A device-resident trace of (features, drift label) samples, on the current
+   device. Appends stop at capacity; the samples that did not fit are
+   counted as dropped. */
+int gg_trace_create(int64_t capacity, gg_trace** out);
+void gg_trace_free(gg_trace* trace);
+int gg_trace_clear(gg_trace* trace);
+int gg_trace_info(gg_trace* trace, int64_t* size, int64_t* positives, int64_t* dropped);
+/* Copies samples [first, first + count) to host: feat [count][8] bfloat16
+   bits, labels float [count] (either nullable). */
+int gg_trace_export(gg_trace* trace, int64_t first, int64_t count, uint16_t* feat_host, float* label_host);
 
 #ifdef __cplusplus
 }

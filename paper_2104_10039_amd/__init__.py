@@ -21,7 +21,9 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgg.so")
 
 APP = {"pr": 0, "sssp": 1, "cc": 2, "ppr": 3}
-POLICY = {"exact": 0, "sp": 1, "sms": 2, "gg": 3}
+POLICY = {"exact": 0, "sp": 1, "sms": 2, "gg": 3, "learned": 4}
+STEP_KIND = {0: "approx", 1: "accurate", 2: "full", 3: "partial"}
+MLP_IN, MLP_HIDDEN, MLP_PARAMS = 8, 64, 4801
 STOP = {"fixed_iters": 0, "fixed_point": 1}
 INFLUENCE = {"prefix": 0, "total": 1}
 MASK = {"replace": 0, "union": 1}
@@ -54,19 +56,24 @@ class AppParams(ctypes.Structure):
 class Policy(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("alpha", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("influence", ctypes.c_int32), ("mask_update", ctypes.c_int32),
-                ("stop", ctypes.c_int32)]
+                ("stop", ctypes.c_int32), ("mlp", ctypes.c_void_p), ("tau", ctypes.c_float), ("rho", ctypes.c_double),
+                ("fallback_k", ctypes.c_int32), ("judge", ctypes.c_int32), ("trace", ctypes.c_void_p),
+                ("label_eps", ctypes.c_float)]
 
 
 class RunStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("supersteps", ctypes.c_int32), ("edges_gathered", ctypes.c_int64),
                 ("active_edges", ctypes.c_int64), ("device_ms", ctypes.c_double), ("edges_processed", ctypes.c_int64),
-                ("sparse_iterations", ctypes.c_int32)]
+                ("sparse_iterations", ctypes.c_int32), ("partial_supersteps", ctypes.c_int32),
+                ("selected_total", ctypes.c_int64), ("judge_positives", ctypes.c_int64), ("judge_hits", ctypes.c_int64),
+                ("judge_selected", ctypes.c_int64)]
 
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("accurate", ctypes.c_int32), ("superstep", ctypes.c_int32),
                 ("edges", ctypes.c_int64), ("changed", ctypes.c_int64), ("active_edges", ctypes.c_int64),
-                ("edges_processed", ctypes.c_int64), ("sparse", ctypes.c_int32)]
+                ("edges_processed", ctypes.c_int64), ("sparse", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("selected", ctypes.c_int64)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -107,6 +114,23 @@ SIGNATURES = {
     "gg_graph_set_parts": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
     "gg_graph_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_graph_get_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(KernelProfile)]),
+    "gg_run_features": (ctypes.c_int, [_VP, _VP]),
+    "gg_run_selection": (ctypes.c_int, [_VP, _VP, _VP]),
+    "gg_run_labels": (ctypes.c_int, [_VP, _VP]),
+    "gg_mlp_create": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(_VP)]),
+    "gg_mlp_free": (None, [_VP]),
+    "gg_mlp_set_weights": (ctypes.c_int, [_VP, _VP]),
+    "gg_mlp_get_weights": (ctypes.c_int, [_VP, _VP]),
+    "gg_mlp_forward": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP]),
+    "gg_mlp_loss_grad": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, _VP]),
+    "gg_mlp_adam_step": (ctypes.c_int, [_VP, _VP, ctypes.c_float]),
+    "gg_mlp_train": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_uint64, _VP]),
+    "gg_trace_create": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(_VP)]),
+    "gg_trace_free": (None, [_VP]),
+    "gg_trace_clear": (ctypes.c_int, [_VP]),
+    "gg_trace_info": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "gg_trace_export": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP]),
 }
 
 PROFILE_KIND = {"gather_exact": 0, "gather_approx": 1, "superstep": 2, "push": 3}
@@ -164,11 +188,17 @@ class Stats:
     device_ms: float
     edges_processed: int
     sparse_iterations: int
+    partial_supersteps: int = 0
+    selected_total: int = 0
+    judge_positives: int = 0
+    judge_hits: int = 0
+    judge_selected: int = 0
 
 
 def _stats(s: RunStats) -> Stats:
     return Stats(s.iterations, s.supersteps, s.edges_gathered, s.active_edges, s.device_ms, s.edges_processed,
-                 s.sparse_iterations)
+                 s.sparse_iterations, s.partial_supersteps, s.selected_total, s.judge_positives, s.judge_hits,
+                 s.judge_selected)
 
 
 def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform"):
@@ -176,8 +206,13 @@ def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangli
 
 
 def _policy(policy="gg", alpha=4, theta=0.05, seed=1, influence="prefix", mask_update="replace",
-            stop="fixed_iters"):
-    return Policy(POLICY[policy], alpha, theta, seed, INFLUENCE[influence], MASK[mask_update], STOP[stop])
+            stop="fixed_iters", mlp=None, tau=0.0, rho=1.0, fallback_k=0, judge=False, trace=None, label_eps=1e-3):
+    return Policy(POLICY[policy], alpha, theta, seed, INFLUENCE[influence], MASK[mask_update], STOP[stop],
+                  None if mlp is None else mlp.handle.value, float(tau), float(rho), int(fallback_k), int(bool(judge)),
+                  None if trace is None else trace.handle.value, float(label_eps))
+
+
+LEARNED_KW = ("mlp", "tau", "rho", "fallback_k", "judge", "trace", "label_eps")
 
 
 class Graph:
@@ -298,11 +333,15 @@ class Graph:
 
     def approx_run(self, app, sample_ratio, policy="gg", out=None, alpha=4, theta=0.05, seed=1,
                    influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
-                   max_iters=1 << 20, source=0, dangling="uniform"):
-        """gg_approx_run: returns (values tensor on the device, Stats)."""
+                   max_iters=1 << 20, source=0, dangling="uniform", **learned):
+        """gg_approx_run: returns (values tensor on the device, Stats). Learned-policy
+        and trace arguments: mlp, tau, rho, fallback_k, judge, trace, label_eps."""
+        bad = set(learned) - set(LEARNED_KW)
+        if bad:
+            raise TypeError("unknown arguments %s" % sorted(bad))
         out = self._out(app, out)
         p = _app_params(app, damping, iters, max_iters, source, dangling)
-        pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop)
+        pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop, **learned)
         st = RunStats()
         _check(lib().gg_approx_run(self._h, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
                                    out.data_ptr(), 0, ctypes.byref(st)))
@@ -331,11 +370,15 @@ class Run:
 
     def __init__(self, graph: Graph, app, sample_ratio=1.0, policy="exact", alpha=4, theta=0.05, seed=1,
                  influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
-                 max_iters=1 << 20, source=0, dangling="uniform"):
+                 max_iters=1 << 20, source=0, dangling="uniform", **learned):
+        bad = set(learned) - set(LEARNED_KW)
+        if bad:
+            raise TypeError("unknown arguments %s" % sorted(bad))
         self.graph = graph
         self.app = app
+        self._keep = (learned.get("mlp"), learned.get("trace"))  # the run reads them until it ends
         p = _app_params(app, damping, iters, max_iters, source, dangling)
-        pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop)
+        pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop, **learned)
         h = ctypes.c_void_p()
         _check(lib().gg_run_begin(graph.handle, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
                                   ctypes.byref(h)))
@@ -348,7 +391,27 @@ class Run:
             return None
         return {"iter": info.iter, "accurate": bool(info.accurate), "superstep": bool(info.superstep),
                 "edges": info.edges, "changed": info.changed, "active_edges": info.active_edges,
-                "edges_processed": info.edges_processed, "sparse": bool(info.sparse)}
+                "edges_processed": info.edges_processed, "sparse": bool(info.sparse),
+                "kind": STEP_KIND[info.kind], "selected": info.selected}
+
+    def features(self) -> np.ndarray:
+        """[n, 8] bfloat16 bits of the last correction step's features."""
+        out = np.zeros((max(self.graph.n, 1), MLP_IN), dtype=np.uint16)
+        _check(lib().gg_run_features(self._h, out.ctypes.data))
+        return out[: self.graph.n]
+
+    def selection(self):
+        """(selected uint8 [n], logits float32 [n]) of the last LEARNED correction step."""
+        sel = np.zeros(max(self.graph.n, 1), dtype=np.uint8)
+        lg = np.zeros(max(self.graph.n, 1), dtype=np.float32)
+        _check(lib().gg_run_selection(self._h, sel.ctypes.data, lg.ctypes.data))
+        return sel[: self.graph.n], lg[: self.graph.n]
+
+    def labels(self) -> np.ndarray:
+        """Drift labels uint8 [n] of the last traced or judged full superstep."""
+        out = np.zeros(max(self.graph.n, 1), dtype=np.uint8)
+        _check(lib().gg_run_labels(self._h, out.ctypes.data))
+        return out[: self.graph.n]
 
     def values(self, host=True):
         dt = {"pr": np.float32, "ppr": np.float32, "sssp": np.uint32, "cc": np.int32}[self.app]
@@ -393,3 +456,102 @@ class Run:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Mlp:
+    """The learned-correction network (gg_mlp_*). Calls run on `stream`
+    (default: torch's current stream at creation)."""
+
+    def __init__(self, seed=1, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().gg_mlp_create(_stream_handle(stream), int(seed), ctypes.byref(h)))
+        self.handle = h
+
+    def set_weights(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError("expected %d parameters" % MLP_PARAMS)
+        _check(lib().gg_mlp_set_weights(self.handle, p.ctypes.data))
+
+    def get_weights(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(lib().gg_mlp_get_weights(self.handle, p.ctypes.data))
+        return p
+
+    def forward(self, feat: torch.Tensor) -> torch.Tensor:
+        """Logits of feat ([n, 8] bfloat16 bits as int16/uint16 on the device)."""
+        assert feat.is_cuda and feat.is_contiguous() and feat.shape[-1] == MLP_IN and feat.element_size() == 2
+        n = feat.shape[0]
+        out = torch.empty(max(n, 1), dtype=torch.float32, device=feat.device)
+        _check(lib().gg_mlp_forward(self.handle, feat.data_ptr(), n, out.data_ptr()))
+        return out[:n]
+
+    def loss_grad(self, feat: torch.Tensor, label: torch.Tensor, pos_weight=1.0) -> torch.Tensor:
+        """[MLP_PARAMS + 1] float32: the gradient of the mean loss, then the loss sum."""
+        assert feat.is_cuda and feat.is_contiguous() and feat.element_size() == 2
+        assert label.is_cuda and label.dtype == torch.float32 and label.is_contiguous()
+        out = torch.empty(MLP_PARAMS + 1, dtype=torch.float32, device=feat.device)
+        _check(lib().gg_mlp_loss_grad(self.handle, feat.data_ptr(), label.data_ptr(), feat.shape[0],
+                                      float(pos_weight), out.data_ptr()))
+        return out
+
+    def adam_step(self, grad: torch.Tensor, lr: float):
+        assert grad.is_cuda and grad.dtype == torch.float32 and grad.numel() >= MLP_PARAMS
+        _check(lib().gg_mlp_adam_step(self.handle, grad.data_ptr(), float(lr)))
+
+    def train(self, trace: "Trace", epochs=5, batch=4096, lr=1e-3, pos_weight=1.0, seed=1) -> np.ndarray:
+        """gg_mlp_train: returns the mean loss of every epoch."""
+        losses = np.zeros(epochs, dtype=np.float32)
+        _check(lib().gg_mlp_train(self.handle, trace.handle, int(epochs), int(batch), float(lr), float(pos_weight),
+                                  int(seed), losses.ctypes.data))
+        return losses
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().gg_mlp_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Trace:
+    """A device-resident trace of (features, drift label) samples (gg_trace_*)."""
+
+    def __init__(self, capacity):
+        h = ctypes.c_void_p()
+        _check(lib().gg_trace_create(int(capacity), ctypes.byref(h)))
+        self.handle = h
+
+    def clear(self):
+        _check(lib().gg_trace_clear(self.handle))
+
+    def info(self) -> dict:
+        size, pos, dropped = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gg_trace_info(self.handle, ctypes.byref(size), ctypes.byref(pos), ctypes.byref(dropped)))
+        return {"size": size.value, "positives": pos.value, "dropped": dropped.value}
+
+    def export(self, first=0, count=None):
+        """(features uint16 [count, 8], labels float32 [count]) on the host."""
+        if count is None:
+            count = self.info()["size"] - first
+        f = np.zeros((max(count, 1), MLP_IN), dtype=np.uint16)
+        y = np.zeros(max(count, 1), dtype=np.float32)
+        _check(lib().gg_trace_export(self.handle, int(first), int(count), f.ctypes.data, y.ctypes.data))
+        return f[:count], y[:count]
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().gg_trace_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

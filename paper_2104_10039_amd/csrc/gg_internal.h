@@ -135,7 +135,8 @@ hipError_t launch_dangling_sum(const float* c, const int32_t* list, const int32_
 
 // Degree binning. blk_scratch holds 3 * ceil(n / kBlock) int32 + ceil(n / kBlock) int64.
 hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, int32_t small_max,
-                        int32_t wave_max, int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st);
+                        int32_t wave_max, int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st, const uint8_t* rowsel = nullptr,
+                        int selwant = 0);
 
 // PR/PPR initial contributions.
 // part_of / part_start nullable (PR: 1/N per part when set).
@@ -226,5 +227,47 @@ hipError_t launch_batch_done(int32_t* changed, int32_t* done, int32_t* iters, hi
 // Plain gather with the long rows split by source segment.
 hipError_t launch_gather_seg(int app, int team, const Sweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);
+
+
+// ---- learned correction: features, MLP, labels ----------------------------
+constexpr int kMlpIn = 8;
+constexpr int kMlpHidden = 64;
+constexpr int kMlpW1 = 0;
+constexpr int kMlpB1 = kMlpW1 + kMlpIn * kMlpHidden;
+constexpr int kMlpW2 = kMlpB1 + kMlpHidden;
+constexpr int kMlpB2 = kMlpW2 + kMlpHidden * kMlpHidden;
+constexpr int kMlpW3 = kMlpB2 + kMlpHidden;
+constexpr int kMlpB3 = kMlpW3 + kMlpHidden;
+constexpr int kMlpParams = kMlpB3 + 1;
+
+// Device state of the network: binary32 master parameters with their Adam
+// moments, and the bfloat16 copies of the weight matrices the kernels use.
+struct MlpDev {
+  float* master;  // kMlpParams
+  float* m;
+  float* v;
+  uint16_t* w1b;  // [8][64]
+  uint16_t* w2b;  // [64][64]
+  uint16_t* w3b;  // [64]
+};
+
+hipError_t launch_mlp_forward(const MlpDev& w, const uint16_t* feat, int64_t n, float* logits, uint8_t* sel,
+                              float tau, int32_t* sel_count, hipStream_t st);
+// Partial-sum slots (floats) the gradient launch needs for n samples.
+int64_t mlp_grad_scratch(int64_t n);
+hipError_t launch_mlp_grad(const MlpDev& w, const uint16_t* feat, const float* label, int64_t n, float pos_weight,
+                           float* scratch, float* grad, hipStream_t st);
+hipError_t launch_mlp_adam(const MlpDev& w, const float* grad, float lr, float c1, float c2, hipStream_t st);
+hipError_t launch_mlp_sync_bf16(const MlpDev& w, hipStream_t st);
+hipError_t launch_feat_base(int32_t n, const int32_t* rowptr, const int32_t* outdeg, const int32_t* act_cnt,
+                            uint16_t* feat, hipStream_t st);
+hipError_t launch_feat_shift(int app, int32_t n, const uint32_t* now, const uint32_t* before, uint16_t* feat,
+                             hipStream_t st);
+hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t* apx, float eps, const uint8_t* sel,
+                         uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* judge,
+                         unsigned long long* trace_pos, hipStream_t st);
+hipError_t launch_add_f32(const float* src, float* dst, hipStream_t st);
+hipError_t launch_clear_rows(const int32_t* list, int32_t count, const int32_t* rowptr, uint32_t* bits,
+                             hipStream_t st);
 
 }  // namespace ggk

@@ -639,12 +639,13 @@ __device__ __forceinline__ int bin_of(int len, int small_max, int wave_max) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* rowptr, const int32_t* cnt, int n, int small_max,
-                                                      int wave_max, int32_t* blk, int64_t* blk_edges, int nblk) {
+                                                      int wave_max, int32_t* blk, int64_t* blk_edges, int nblk,
+                                                      const uint8_t* rowsel, int selwant) {
   __shared__ int ilds[4];
   __shared__ long long elds[4];
   const int u = blockIdx.x * kBlock + threadIdx.x;
   int len = 0, bin = -1;
-  if (u < n) {
+  if (u < n && (!rowsel || (rowsel[u] != 0) == (selwant != 0))) {
     len = cnt ? cnt[u] : rowptr[u + 1] - rowptr[u];
     bin = bin_of(len, small_max, wave_max);
   }
@@ -719,11 +720,12 @@ __global__ __launch_bounds__(1024) void k_bin_scan(int32_t* blk, const int64_t* 
 
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* rowptr, const int32_t* cnt, int n,
                                                         int small_max, int wave_max, const int32_t* blk, int nblk,
-                                                        const BinCounts* bc, int32_t* list) {
+                                                        const BinCounts* bc, int32_t* list, const uint8_t* rowsel,
+                                                        int selwant) {
   __shared__ int ilds[4];
   const int u = blockIdx.x * kBlock + threadIdx.x;
   int bin = -1;
-  if (u < n) {
+  if (u < n && (!rowsel || (rowsel[u] != 0) == (selwant != 0))) {
     const int len = cnt ? cnt[u] : rowptr[u + 1] - rowptr[u];
     bin = bin_of(len, small_max, wave_max);
   }
@@ -968,7 +970,8 @@ hipError_t launch_dangling_sum(const float* c, const int32_t* list, const int32_
 }
 
 hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, int32_t small_max, int32_t wave_max,
-                        int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st) {
+                        int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st, const uint8_t* rowsel,
+                        int selwant) {
   const int nblk = (n + kBlock - 1) / kBlock;
   int32_t* blk = (int32_t*)blk_scratch;
   int64_t* blk_edges = (int64_t*)(blk + 3 * (int64_t)nblk + ((3 * nblk) & 1));
@@ -979,10 +982,10 @@ hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, in
     return launch_fill_u32((uint32_t*)bins.hub_start, 1, 0u, st);
   }
   hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(kBlock), 0, st, rowptr, cnt, n, small_max, wave_max, blk,
-                     blk_edges, nblk);
+                     blk_edges, nblk, rowsel, selwant);
   hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, blk, blk_edges, nblk, bins.dcounts);
   hipLaunchKernelGGL(k_bin_scatter, dim3(nblk), dim3(kBlock), 0, st, rowptr, cnt, n, small_max, wave_max, blk, nblk,
-                     bins.dcounts, bins.list);
+                     bins.dcounts, bins.list, rowsel, selwant);
   hipLaunchKernelGGL(k_hub_nchunks, dim3(nblk), dim3(kBlock), 0, st, rowptr, cnt, bins.list, bins.dcounts, hub_chunk,
                      bins.hub_start);
   hipLaunchKernelGGL(k_hub_scan, dim3(1), dim3(1024), 0, st, bins.hub_start, bins.dcounts);

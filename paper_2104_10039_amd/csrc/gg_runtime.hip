@@ -11,6 +11,8 @@
 // iteration i (1-based) is accurate for EXACT always, for SMS from
 // i = alpha+1 on, for GG when i is a multiple of alpha+1; SP never. Each
 // accurate GG iteration is a superstep that re-selects the active edges.
+// LEARNED keeps GG's correction steps but lets a network pick the rows they
+// correct (a partial superstep), with GG's full superstep as fallback.
 // Updates are synchronous: iteration i reads the values of iteration i-1.
 #include <hip/hip_runtime.h>
 
@@ -133,6 +135,18 @@ struct gg_graph {
   int64_t seg_cap_part = 0;  // 8-byte entries of the partial array
   Bins full;         // binning of the full rows by in-degree
   bool full_valid = false;
+  // learned correction and traces (allocated on first use)
+  bool lws = false;
+  uint16_t* feat = nullptr;        // [n][8] bfloat16 features
+  uint8_t* sel = nullptr;          // n: selected rows of the last correction step
+  float* logits = nullptr;         // n
+  uint8_t* labels = nullptr;       // n: drift labels of the last traced / judged superstep
+  uint32_t* shadow = nullptr;      // n: approximate update of that superstep
+  int32_t* sel_count = nullptr;    // 1
+  unsigned long long* judge = nullptr;  // [0] drifted vertices, [1] of which selected
+  int32_t* dummy = nullptr;        // changed-counter sink of the shadow pass
+  Bins selb;                       // binning of the selected rows (full rows)
+  Bins nselb;                      // binning of the other rows (active edges)
   // workspace (allocated on first run)
   bool ws = false;
   float* c[2] = {nullptr, nullptr};
@@ -184,6 +198,30 @@ struct gg_run {
   int64_t front_count = -1;
   int64_t front_outdeg = 0;
   bool timing = false;
+  // learned correction
+  int32_t corrections = 0;
+  int32_t partials = 0;
+  int64_t selected_total = 0;
+  int64_t judge_selected = 0;
+  bool have_feat = false, have_sel = false, have_labels = false;
+};
+
+struct gg_mlp {
+  hipStream_t stream = nullptr;
+  ggk::MlpDev d{};
+  float* grad = nullptr;  // kMlpParams gradient + loss sum
+  float* scratch = nullptr;
+  int64_t scratch_cap = 0;
+  float* loss = nullptr;  // per-epoch loss sums
+  int64_t loss_cap = 0;
+  int64_t t = 0;          // Adam steps taken
+};
+
+struct gg_trace {
+  int64_t cap = 0, size = 0, dropped = 0;
+  uint16_t* feat = nullptr;  // [cap][8]
+  float* label = nullptr;    // cap
+  unsigned long long* pos = nullptr;  // positives recorded
 };
 
 namespace {
@@ -212,10 +250,27 @@ void free_bins(Bins& b) {
   dfree(b.dcounts);
 }
 
-int rebin(gg_graph* g, Bins& b, const int32_t* cnt) {
+int rebin(gg_graph* g, Bins& b, const int32_t* cnt, const uint8_t* rowsel = nullptr, int selwant = 0) {
   GG_HIP(launch_rebin(g->rowptr, cnt, g->n, g->tune.small_max, g->tune.wave_max, g->tune.hub_chunk, b,
-                      g->blk_scratch, g->stream));
+                      g->blk_scratch, g->stream, rowsel, selwant));
   return sync_bins(g, b);
+}
+
+int ensure_learned(gg_graph* g) {
+  if (g->lws) return GG_OK;
+  const size_t n = (size_t)g->n;
+  GG_TRY(dalloc(&g->feat, n * 8));
+  GG_TRY(dalloc(&g->sel, n));
+  GG_TRY(dalloc(&g->logits, n));
+  GG_TRY(dalloc(&g->labels, n));
+  GG_TRY(dalloc(&g->shadow, n));
+  GG_TRY(dalloc(&g->sel_count, 1));
+  GG_TRY(dalloc(&g->judge, 2));
+  GG_TRY(dalloc(&g->dummy, 1));
+  GG_TRY(alloc_bins(g->selb, g->n));
+  GG_TRY(alloc_bins(g->nselb, g->n));
+  g->lws = true;
+  return GG_OK;
 }
 
 // Segment count (a multiple of the 8 dies) and size for the current tuning.
@@ -440,6 +495,16 @@ void free_graph(gg_graph* g) {
   for (hipEvent_t e : {g->batch.ea, g->batch.eb, g->batch.t0, g->batch.t1})
     if (e) (void)hipEventDestroy(e);
   if (g->seg_part) (void)hipFree(g->seg_part);
+  dfree(g->feat);
+  dfree(g->sel);
+  dfree(g->logits);
+  dfree(g->labels);
+  dfree(g->shadow);
+  dfree(g->sel_count);
+  dfree(g->judge);
+  dfree(g->dummy);
+  free_bins(g->selb);
+  free_bins(g->nselb);
   for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
@@ -460,19 +525,39 @@ bool is_accurate(const gg_correction_policy& p, int32_t i) {
     case GG_POLICY_EXACT: return true;
     case GG_POLICY_SP: return false;
     case GG_POLICY_SMS: return i >= p.alpha + 1;
-    case GG_POLICY_GG: return (i % (p.alpha + 1)) == 0;
+    case GG_POLICY_GG:
+    case GG_POLICY_LEARNED: return (i % (p.alpha + 1)) == 0;
   }
   return true;
 }
 
-bool is_superstep(const gg_correction_policy& p, int32_t i) { return p.kind == GG_POLICY_GG && is_accurate(p, i); }
+// Kind of iteration i by the schedule alone (a LEARNED correction step may
+// become partial once its selection is known).
+int step_kind(const gg_correction_policy& p, int32_t i) {
+  switch (p.kind) {
+    case GG_POLICY_EXACT: return GG_STEP_ACCURATE;
+    case GG_POLICY_SP: return GG_STEP_APPROX;
+    case GG_POLICY_SMS: return i >= p.alpha + 1 ? GG_STEP_ACCURATE : GG_STEP_APPROX;
+    default: return (i % (p.alpha + 1)) == 0 ? GG_STEP_FULL : GG_STEP_APPROX;
+  }
+}
 
 bool is_pr(int app) { return app == GG_APP_PR || app == GG_APP_PPR; }
 
 int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol) {
   if (!p || !pol) return fail(GG_E_INVAL, "null params or policy");
   if (p->app < GG_APP_PR || p->app > GG_APP_PPR) return fail(GG_E_INVAL, "unknown app");
-  if (pol->kind < GG_POLICY_EXACT || pol->kind > GG_POLICY_GG) return fail(GG_E_INVAL, "unknown policy kind");
+  if (pol->kind < GG_POLICY_EXACT || pol->kind > GG_POLICY_LEARNED) return fail(GG_E_INVAL, "unknown policy kind");
+  if (pol->kind == GG_POLICY_LEARNED) {
+    if (!pol->mlp) return fail(GG_E_INVAL, "LEARNED needs a network");
+    if (!(pol->rho >= 0.0)) return fail(GG_E_INVAL, "rho < 0");
+    if (pol->fallback_k < 0) return fail(GG_E_INVAL, "fallback_k < 0");
+    if (std::isnan(pol->tau)) return fail(GG_E_INVAL, "tau is NaN");
+  }
+  if (pol->trace && pol->kind != GG_POLICY_GG && pol->kind != GG_POLICY_LEARNED)
+    return fail(GG_E_INVAL, "traces are recorded by GG and LEARNED runs");
+  if ((pol->trace || (pol->kind == GG_POLICY_LEARNED && pol->judge)) && is_pr(p->app) && !(pol->label_eps > 0.0f))
+    return fail(GG_E_INVAL, "label_eps must be > 0");
   if (!(sigma >= 0.0 && sigma <= 1.0)) return fail(GG_E_INVAL, "sample_ratio outside [0, 1]");
   if (pol->alpha < 0) return fail(GG_E_INVAL, "alpha < 0");
   if (!(pol->theta >= 0.0 && pol->theta < 65536.0)) return fail(GG_E_INVAL, "theta outside [0, 65536)");
@@ -644,10 +729,38 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
   }
   // initial sparsification [Sec. 3.4]
   if (pol->kind != GG_POLICY_EXACT) GG_TRY(sample_and_pack(g, app, sigma, pol->seed));
+  if (pol->kind == GG_POLICY_LEARNED || pol->trace) {
+    GG_TRY(ensure_learned(g));
+    // the delta features start at 0 (no iteration before iteration 0)
+    GG_HIP(launch_fill_u32((uint32_t*)g->feat, (int64_t)g->n * 4, 0u, g->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)g->judge, 4, 0u, g->stream));
+  }
   const bool fixed_iters = is_pr(app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
   if (fixed_iters && p->iters == 0) r->done = true;
   g->active_run = owner.release();
   *out = r;
+  return GG_OK;
+}
+
+// Features and selection of a LEARNED correction step; sets the step kind
+// (full when forced by the fallback schedule or when |S| > rho * n).
+int learned_select(gg_run* r, int* kind, int64_t* selected) {
+  gg_graph* g = r->g;
+  const int32_t c = ++r->corrections;
+  const bool forced = r->pol.fallback_k > 0 && c % r->pol.fallback_k == 0;
+  GG_HIP(launch_feat_base(g->n, g->rowptr, g->outdeg, g->act_cnt, g->feat, g->stream));
+  r->have_feat = true;
+  *kind = GG_STEP_FULL;
+  GG_HIP(launch_fill_u32((uint32_t*)g->sel_count, 1, 0u, g->stream));
+  GG_HIP(launch_mlp_forward(r->pol.mlp->d, g->feat, g->n, g->logits, g->sel, r->pol.tau, g->sel_count, g->stream));
+  int32_t cnt = 0;
+  GG_HIP(hipMemcpyAsync(&cnt, g->sel_count, sizeof(cnt), hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  r->have_sel = true;
+  *selected = cnt;
+  r->selected_total += cnt;
+  if (!forced && !((double)cnt > r->pol.rho * (double)g->n)) *kind = GG_STEP_PARTIAL;
+  if (*kind == GG_STEP_FULL && r->pol.judge) r->judge_selected += cnt;
   return GG_OK;
 }
 
@@ -658,9 +771,34 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   if (r->done) return 0;
   const int32_t i = r->iter + 1;
   const int app = r->p.app;
-  const bool accurate = is_accurate(r->pol, i);
-  const bool superstep = is_superstep(r->pol, i);
   const bool pr = is_pr(app);
+  const bool learned = r->pol.kind == GG_POLICY_LEARNED;
+  int kind = step_kind(r->pol, i);
+  int64_t selected = -1;
+  r->have_sel = false;
+  r->have_labels = false;
+  // Delta features of the next correction step c: at the start of iterations
+  // c-1 and c the buffers hold the states of iterations (c-2, c-3) and then
+  // (c-1, c-2); each shift moves f3 to f4 and writes the newer delta to f3.
+  if ((learned || r->pol.trace) && i >= 2 && g->n > 0) {
+    const int32_t a1 = r->pol.alpha + 1;
+    if (i % a1 == 0 || (i + 1) % a1 == 0) {
+      const uint32_t* now = pr ? (const uint32_t*)g->c[r->cur] : g->xu[r->cur];
+      const uint32_t* before = pr ? (const uint32_t*)g->c[1 - r->cur] : g->xu[1 - r->cur];
+      GG_HIP(launch_feat_shift(app, g->n, now, before, g->feat, g->stream));
+    }
+  }
+  if (learned && kind == GG_STEP_FULL) GG_TRY(learned_select(r, &kind, &selected));
+  const bool accurate = kind == GG_STEP_ACCURATE || kind == GG_STEP_FULL;
+  const bool superstep = kind == GG_STEP_FULL || kind == GG_STEP_PARTIAL;
+  // a traced or judged full superstep also computes the approximate update
+  // and labels every vertex by the difference
+  const bool traced = r->pol.trace != nullptr && kind == GG_STEP_FULL;
+  const bool judged = learned && r->pol.judge && kind == GG_STEP_FULL && r->have_sel;
+  if (traced && !learned) {
+    GG_HIP(launch_feat_base(g->n, g->rowptr, g->outdeg, g->act_cnt, g->feat, g->stream));
+    r->have_feat = true;
+  }
   const bool last_fixed = (pr || (r->pol.kind != GG_POLICY_EXACT && r->pol.stop == GG_STOP_FIXED_ITERS)) &&
                           i >= r->p.iters;
   Sweep s = base_sweep(g, r);
@@ -685,7 +823,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   // A push from the changed vertices is exact when this iteration's edge set
   // is contained in the previous one's: not at a superstep, not at a switch
   // from approximate to accurate mode.
-  const bool grows = accurate && (i == 1 || !is_accurate(r->pol, i - 1)) && r->pol.kind != GG_POLICY_EXACT;
+  const bool grows = accurate && (i == 1 || step_kind(r->pol, i - 1) == GG_STEP_APPROX) && r->pol.kind != GG_POLICY_EXACT;
   // front_count >= 0 only when flist[fcur] was written (source seed, dense
   // compaction or push finalize)
   const bool sparse = frontier && !superstep && !grows && r->front_count >= 0 && r->front_count <= g->n &&
@@ -695,9 +833,9 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   int64_t processed;
   hipEvent_t pe0, pe1;
   GG_TRY(prof_events(g, &pe0, &pe1));
-  int kind;
+  int pkind;
   if (sparse) {
-    kind = accurate ? 0 : 1;
+    pkind = accurate ? 0 : 1;
     s.edges = full_edges(g, app);
     const uint32_t* bits = accurate ? nullptr : g->bits[r->bcur];
     g->epoch++;
@@ -709,8 +847,55 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     edges = accurate ? g->m : g->act.h.edges;
     processed = r->front_outdeg;
     r->sparse_iters++;
+  } else if (kind == GG_STEP_PARTIAL) {
+    // Partial superstep: the selected rows S gather over all in-edges and
+    // re-select their flags; the other rows take an approximate iteration and
+    // keep theirs.
+    pkind = 4;
+    GG_TRY(rebin(g, g->selb, nullptr, g->sel, 1));
+    GG_TRY(rebin(g, g->nselb, g->act_cnt, g->sel, 0));
+    const int32_t ns = g->selb.h.small + g->selb.h.wave + g->selb.h.hub;
+    GG_HIP(launch_copy_u32(g->bits[r->bcur], g->bits[1 - r->bcur], (g->m + 31) / 32, g->stream));
+    GG_HIP(launch_clear_rows(g->selb.list, ns, g->rowptr, g->bits[1 - r->bcur], g->stream));
+    Sweep sa = s;
+    set_bins(sa, g->nselb);
+    sa.edges = g->act_edges;
+    sa.cnt = g->act_cnt;
+    GG_TRY(check_part_capacity(g, g->nselb));
+    GG_HIP(launch_gather(app, g->tune.small_team, sa, g->stream, pe0, nullptr));
+    Sweep sc = s;
+    set_bins(sc, g->selb);
+    sc.edges = full_edges(g, app);
+    sc.cnt = nullptr;
+    sc.old_bits = g->bits[r->bcur];
+    sc.new_bits = g->bits[1 - r->bcur];
+    GG_TRY(check_part_capacity(g, g->selb));
+    GG_HIP(launch_superstep(app, g->tune.small_team, sc, g->stream, nullptr, pe1));
+    r->bcur = 1 - r->bcur;
+    GG_TRY(rebin_act(g, app));
+    r->supersteps++;
+    r->partials++;
+    edges = g->nselb.h.edges + g->selb.h.edges;
+    processed = edges;
   } else if (superstep) {
-    kind = 2;
+    pkind = 2;
+    if (traced || judged) {
+      // approximate update from the same state, into the shadow buffer
+      Sweep sh = s;
+      set_bins(sh, g->act);
+      sh.edges = g->act_edges;
+      sh.cnt = g->act_cnt;
+      sh.chg = nullptr;
+      sh.x_out = nullptr;
+      if (pr) {
+        sh.c_out = (float*)g->shadow;
+      } else {
+        sh.x_next = g->shadow;
+        sh.changed = g->dummy;
+      }
+      GG_TRY(check_part_capacity(g, g->act));
+      GG_HIP(launch_gather(app, g->tune.small_team, sh, g->stream));
+    }
     GG_HIP(launch_fill_u32(g->bits[1 - r->bcur], (g->m + 31) / 32, 0u, g->stream));
     set_bins(s, g->full);
     s.edges = full_edges(g, app);
@@ -723,12 +908,34 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     else
       GG_HIP(launch_superstep(app, g->tune.small_team, s, g->stream, pe0, pe1));
     r->bcur = 1 - r->bcur;
+    if (traced || judged) {
+      const uint32_t* acc = pr ? (const uint32_t*)s.c_out : s.x_next;
+      float* lf = nullptr;
+      int32_t nf = 0;
+      unsigned long long* tpos = nullptr;
+      if (traced) {
+        gg_trace* T = r->pol.trace;
+        const int64_t room = T->cap - T->size;
+        nf = (int32_t)(room < (int64_t)g->n ? room : (int64_t)g->n);
+        if (nf > 0) {
+          GG_HIP(launch_copy_u32((const uint32_t*)g->feat, (uint32_t*)(T->feat + T->size * 8), (int64_t)nf * 4,
+                                 g->stream));
+          lf = T->label + T->size;
+          tpos = T->pos;
+        }
+        T->size += nf;
+        T->dropped += (int64_t)g->n - nf;
+      }
+      GG_HIP(launch_labels(app, g->n, acc, g->shadow, r->pol.label_eps, judged ? g->sel : nullptr, g->labels, lf, nf,
+                           judged ? g->judge : nullptr, tpos, g->stream));
+      r->have_labels = true;
+    }
     GG_TRY(rebin_act(g, app));
     r->supersteps++;
     edges = g->m;
     processed = edges;
   } else if (accurate) {
-    kind = 0;
+    pkind = 0;
     set_bins(s, g->full);
     s.edges = full_edges(g, app);
     s.cnt = nullptr;
@@ -743,7 +950,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     edges = g->m;
     processed = edges;
   } else {
-    kind = 1;
+    pkind = 1;
     set_bins(s, g->act);
     s.edges = g->act_edges;
     s.cnt = g->act_cnt;
@@ -762,9 +969,8 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     GG_HIP(launch_compact_changed(g->chg, g->outdeg, g->n, g->flist[1 - r->fcur], g->fc, (int32_t*)g->blk_scratch,
                                   g->psum, g->stream));
   if (g->prof) {
-    double bytes = alg_bytes(kind, g->n, edges, s.x_out != nullptr);
-    if (kind == 2) bytes += 4.0 * (double)g->act.h.edges + (double)((g->m + 31) / 32) * 4.0;
-    int pkind = kind;
+    double bytes = alg_bytes(pkind == 4 ? 2 : pkind, g->n, edges, s.x_out != nullptr);
+    if (pkind == 2) bytes += 4.0 * (double)g->act.h.edges + (double)((g->m + 31) / 32) * 4.0;
     if (sparse) {
       // per pushed edge: edge id, destination, weight word, flag word (approx), atomic on the target;
       // per frontier vertex: list entry, out-row offsets, value, sync
@@ -813,6 +1019,8 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     info->active_edges = r->pol.kind == GG_POLICY_EXACT ? g->m : g->act.h.edges;
     info->edges_processed = processed;
     info->sparse = sparse ? 1 : 0;
+    info->kind = kind;
+    info->selected = selected;
   }
   return 1;
 }
@@ -869,6 +1077,22 @@ int run_values(gg_run* r, void* out, uint32_t flags) {
   return copy_out(g, g->xu[r->cur], out, sizeof(uint32_t) * (size_t)g->n, flags);
 }
 
+// Learned-policy fields of the run statistics (reads the judge counters).
+int learned_stats(gg_run* r, gg_run_stats* st) {
+  st->partial_supersteps = r->partials;
+  st->selected_total = r->selected_total;
+  st->judge_positives = st->judge_hits = 0;
+  st->judge_selected = r->judge_selected;
+  if (r->g->lws && r->pol.kind == GG_POLICY_LEARNED && r->pol.judge) {
+    unsigned long long h[2] = {0, 0};
+    GG_HIP(hipMemcpyAsync(h, r->g->judge, sizeof(h), hipMemcpyDeviceToHost, r->g->stream));
+    GG_HIP(hipStreamSynchronize(r->g->stream));
+    st->judge_positives = (int64_t)h[0];
+    st->judge_hits = (int64_t)h[1];
+  }
+  return GG_OK;
+}
+
 void end_run(gg_run* r) {
   if (!r) return;
   if (r->g && r->g->active_run == r) r->g->active_run = nullptr;
@@ -909,6 +1133,7 @@ int whole_run(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
     st->device_ms = ms;
     st->edges_processed = r->edges_processed;
     st->sparse_iterations = r->sparse_iters;
+    if (rc == GG_OK) rc = learned_stats(r, st);
   }
   end_run(r);
   return rc;
@@ -1301,7 +1526,7 @@ int gg_graph_set_profiling(gg_graph* g, int enable) {
 
 int gg_graph_get_profile(gg_graph* g, int kind, int app, gg_kernel_profile* out) {
   if (!g || !out) return fail(GG_E_INVAL, "null argument");
-  if (kind < 0 || kind > 3 || app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "bad kind or app");
+  if (kind < 0 || kind > 4 || app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "bad kind or app");
   GG_HIP(hipStreamSynchronize(g->stream));
   gg_kernel_profile p{0, 0.0, 0.0, 0};
   for (const auto& r : g->recs) {
@@ -1380,9 +1605,265 @@ int gg_run_stats_get(gg_run* run, gg_run_stats* st) {
   st->device_ms = 0.0;
   st->edges_processed = run->edges_processed;
   st->sparse_iterations = run->sparse_iters;
+  return learned_stats(run, st);
+}
+
+int gg_run_features(gg_run* run, uint16_t* feat_host) {
+  if (!run || !feat_host) return fail(GG_E_INVAL, "null argument");
+  if (!run->have_feat) return fail(GG_E_STATE, "no features computed yet");
+  gg_graph* g = run->g;
+  GG_HIP(hipMemcpyAsync(feat_host, g->feat, (size_t)g->n * 16, hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  return GG_OK;
+}
+
+int gg_run_selection(gg_run* run, uint8_t* sel_host, float* logits_host) {
+  if (!run) return fail(GG_E_INVAL, "null run");
+  if (!run->have_sel) return fail(GG_E_STATE, "the last step made no selection");
+  gg_graph* g = run->g;
+  if (sel_host) GG_HIP(hipMemcpyAsync(sel_host, g->sel, (size_t)g->n, hipMemcpyDeviceToHost, g->stream));
+  if (logits_host)
+    GG_HIP(hipMemcpyAsync(logits_host, g->logits, (size_t)g->n * 4, hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  return GG_OK;
+}
+
+int gg_run_labels(gg_run* run, uint8_t* labels_host) {
+  if (!run || !labels_host) return fail(GG_E_INVAL, "null argument");
+  if (!run->have_labels) return fail(GG_E_STATE, "the last step computed no labels");
+  gg_graph* g = run->g;
+  GG_HIP(hipMemcpyAsync(labels_host, g->labels, (size_t)g->n, hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
   return GG_OK;
 }
 
 void gg_run_end(gg_run* run) { end_run(run); }
+
+// ---- learned correction network and traces ---------------------------------
+
+namespace {
+
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double unit(uint64_t& x) { return (double)(splitmix64(x) >> 11) * (1.0 / 9007199254740992.0); }
+
+int mlp_upload(gg_mlp* n, const float* host) {
+  GG_HIP(hipMemcpyAsync(n->d.master, host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, n->stream));
+  GG_HIP(launch_fill_u32((uint32_t*)n->d.m, kMlpParams, 0u, n->stream));
+  GG_HIP(launch_fill_u32((uint32_t*)n->d.v, kMlpParams, 0u, n->stream));
+  GG_HIP(launch_mlp_sync_bf16(n->d, n->stream));
+  GG_HIP(hipStreamSynchronize(n->stream));
+  n->t = 0;
+  return GG_OK;
+}
+
+void mlp_release(gg_mlp* n) {
+  if (!n) return;
+  if (n->stream) (void)hipStreamSynchronize(n->stream);
+  dfree(n->d.master);
+  dfree(n->d.m);
+  dfree(n->d.v);
+  dfree(n->d.w1b);
+  dfree(n->d.w2b);
+  dfree(n->d.w3b);
+  dfree(n->grad);
+  dfree(n->scratch);
+  dfree(n->loss);
+  delete n;
+}
+
+int mlp_scratch(gg_mlp* n, int64_t samples) {
+  const int64_t need = mlp_grad_scratch(samples);
+  if (n->scratch_cap >= need) return GG_OK;
+  dfree(n->scratch);
+  n->scratch_cap = 0;
+  GG_TRY(dalloc(&n->scratch, (size_t)need));
+  n->scratch_cap = need;
+  return GG_OK;
+}
+
+int mlp_adam(gg_mlp* n, const float* grad, float lr) {
+  n->t++;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)n->t));
+  const float c2 = (float)(1.0 - std::pow(0.999, (double)n->t));
+  GG_HIP(launch_mlp_adam(n->d, grad, lr, c1, c2, n->stream));
+  return GG_OK;
+}
+
+}  // namespace
+
+int gg_mlp_create(void* hip_stream, uint64_t seed, gg_mlp** out) {
+  if (!out) return fail(GG_E_INVAL, "null output");
+  *out = nullptr;
+  std::unique_ptr<gg_mlp, void (*)(gg_mlp*)> n(new (std::nothrow) gg_mlp(), mlp_release);
+  if (!n) return fail(GG_E_NOMEM, "host allocation failed");
+  n->stream = (hipStream_t)hip_stream;
+  GG_TRY(dalloc(&n->d.master, kMlpParams));
+  GG_TRY(dalloc(&n->d.m, kMlpParams));
+  GG_TRY(dalloc(&n->d.v, kMlpParams));
+  GG_TRY(dalloc(&n->d.w1b, kMlpIn * kMlpHidden));
+  GG_TRY(dalloc(&n->d.w2b, kMlpHidden * kMlpHidden));
+  GG_TRY(dalloc(&n->d.w3b, kMlpHidden));
+  GG_TRY(dalloc(&n->grad, kMlpParams + 1));
+  // He-uniform weights (bound sqrt(6 / fan_in)), zero biases
+  std::vector<float> h(kMlpParams, 0.0f);
+  uint64_t x = seed;
+  const double a1 = std::sqrt(6.0 / kMlpIn), a2 = std::sqrt(6.0 / kMlpHidden);
+  for (int i = 0; i < kMlpIn * kMlpHidden; ++i) h[kMlpW1 + i] = (float)((2.0 * unit(x) - 1.0) * a1);
+  for (int i = 0; i < kMlpHidden * kMlpHidden; ++i) h[kMlpW2 + i] = (float)((2.0 * unit(x) - 1.0) * a2);
+  for (int i = 0; i < kMlpHidden; ++i) h[kMlpW3 + i] = (float)((2.0 * unit(x) - 1.0) * a2);
+  GG_TRY(mlp_upload(n.get(), h.data()));
+  *out = n.release();
+  return GG_OK;
+}
+
+void gg_mlp_free(gg_mlp* mlp) { mlp_release(mlp); }
+
+int gg_mlp_set_weights(gg_mlp* mlp, const float* params_host) {
+  if (!mlp || !params_host) return fail(GG_E_INVAL, "null argument");
+  for (int i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(params_host[i])) return fail(GG_E_INVAL, "non-finite parameter");
+  return mlp_upload(mlp, params_host);
+}
+
+int gg_mlp_get_weights(gg_mlp* mlp, float* params_host) {
+  if (!mlp || !params_host) return fail(GG_E_INVAL, "null argument");
+  GG_HIP(hipMemcpyAsync(params_host, mlp->d.master, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, mlp->stream));
+  GG_HIP(hipStreamSynchronize(mlp->stream));
+  return GG_OK;
+}
+
+int gg_mlp_forward(gg_mlp* mlp, const uint16_t* feat_dev, int64_t n, float* logits_dev) {
+  if (!mlp || (n > 0 && (!feat_dev || !logits_dev))) return fail(GG_E_INVAL, "null argument");
+  if (n < 0) return fail(GG_E_INVAL, "n < 0");
+  GG_HIP(launch_mlp_forward(mlp->d, feat_dev, n, logits_dev, nullptr, 0.0f, nullptr, mlp->stream));
+  GG_HIP(hipStreamSynchronize(mlp->stream));
+  return GG_OK;
+}
+
+int gg_mlp_loss_grad(gg_mlp* mlp, const uint16_t* feat_dev, const float* label_dev, int64_t n, float pos_weight,
+                     float* grad_dev) {
+  if (!mlp || !grad_dev || (n > 0 && (!feat_dev || !label_dev))) return fail(GG_E_INVAL, "null argument");
+  if (n <= 0) return fail(GG_E_INVAL, "n <= 0");
+  if (!(pos_weight > 0.0f)) return fail(GG_E_INVAL, "pos_weight <= 0");
+  GG_TRY(mlp_scratch(mlp, n));
+  GG_HIP(launch_mlp_grad(mlp->d, feat_dev, label_dev, n, pos_weight, mlp->scratch, grad_dev, mlp->stream));
+  GG_HIP(hipStreamSynchronize(mlp->stream));
+  return GG_OK;
+}
+
+int gg_mlp_adam_step(gg_mlp* mlp, const float* grad_dev, float lr) {
+  if (!mlp || !grad_dev) return fail(GG_E_INVAL, "null argument");
+  if (!(lr > 0.0f)) return fail(GG_E_INVAL, "lr <= 0");
+  GG_TRY(mlp_adam(mlp, grad_dev, lr));
+  GG_HIP(hipStreamSynchronize(mlp->stream));
+  return GG_OK;
+}
+
+int gg_mlp_train(gg_mlp* mlp, const gg_trace* trace, int32_t epochs, int32_t batch, float lr, float pos_weight,
+                 uint64_t seed, float* epoch_loss_host) {
+  if (!mlp || !trace) return fail(GG_E_INVAL, "null argument");
+  if (epochs < 1 || batch < 16) return fail(GG_E_INVAL, "epochs < 1 or batch < 16");
+  if (!(lr > 0.0f) || !(pos_weight > 0.0f)) return fail(GG_E_INVAL, "lr and pos_weight must be > 0");
+  const int64_t size = trace->size;
+  if (size <= 0) return fail(GG_E_STATE, "empty trace");
+  // the trace was filled on a graph's stream
+  GG_HIP(hipDeviceSynchronize());
+  GG_TRY(mlp_scratch(mlp, batch));
+  if (mlp->loss_cap < epochs) {
+    dfree(mlp->loss);
+    mlp->loss_cap = 0;
+    GG_TRY(dalloc(&mlp->loss, (size_t)epochs));
+    mlp->loss_cap = epochs;
+  }
+  GG_HIP(launch_fill_u32((uint32_t*)mlp->loss, epochs, 0u, mlp->stream));
+  const int64_t nb = (size + batch - 1) / batch;
+  std::vector<int64_t> order((size_t)nb);
+  uint64_t x = seed;
+  for (int32_t e = 0; e < epochs; ++e) {
+    for (int64_t b = 0; b < nb; ++b) order[(size_t)b] = b;
+    for (int64_t b = nb - 1; b > 0; --b) {
+      const int64_t j = (int64_t)(splitmix64(x) % (uint64_t)(b + 1));
+      std::swap(order[(size_t)b], order[(size_t)j]);
+    }
+    for (int64_t k = 0; k < nb; ++k) {
+      const int64_t b0 = order[(size_t)k] * batch;
+      const int64_t bn = size - b0 < batch ? size - b0 : batch;
+      GG_HIP(launch_mlp_grad(mlp->d, trace->feat + b0 * 8, trace->label + b0, bn, pos_weight, mlp->scratch, mlp->grad,
+                             mlp->stream));
+      GG_TRY(mlp_adam(mlp, mlp->grad, lr));
+      GG_HIP(launch_add_f32(mlp->grad + kMlpParams, mlp->loss + e, mlp->stream));
+    }
+  }
+  std::vector<float> h((size_t)epochs);
+  GG_HIP(hipMemcpyAsync(h.data(), mlp->loss, sizeof(float) * epochs, hipMemcpyDeviceToHost, mlp->stream));
+  GG_HIP(hipStreamSynchronize(mlp->stream));
+  if (epoch_loss_host)
+    for (int32_t e = 0; e < epochs; ++e) epoch_loss_host[e] = h[(size_t)e] / (float)size;
+  return GG_OK;
+}
+
+int gg_trace_create(int64_t capacity, gg_trace** out) {
+  if (!out) return fail(GG_E_INVAL, "null output");
+  *out = nullptr;
+  if (capacity < 1 || capacity > ((int64_t)1 << 34)) return fail(GG_E_INVAL, "capacity outside [1, 2^34]");
+  gg_trace* t = new (std::nothrow) gg_trace();
+  if (!t) return fail(GG_E_NOMEM, "host allocation failed");
+  t->cap = capacity;
+  int rc = dalloc(&t->feat, (size_t)capacity * 8);
+  if (rc == GG_OK) rc = dalloc(&t->label, (size_t)capacity);
+  if (rc == GG_OK) rc = dalloc(&t->pos, 1);
+  if (rc == GG_OK && hipMemset(t->pos, 0, sizeof(unsigned long long)) != hipSuccess)
+    rc = fail(GG_E_DEVICE, "trace counter reset failed");
+  if (rc != GG_OK) {
+    gg_trace_free(t);
+    return rc;
+  }
+  *out = t;
+  return GG_OK;
+}
+
+void gg_trace_free(gg_trace* t) {
+  if (!t) return;
+  (void)hipDeviceSynchronize();
+  dfree(t->feat);
+  dfree(t->label);
+  dfree(t->pos);
+  delete t;
+}
+
+int gg_trace_clear(gg_trace* t) {
+  if (!t) return fail(GG_E_INVAL, "null trace");
+  GG_HIP(hipDeviceSynchronize());
+  GG_HIP(hipMemset(t->pos, 0, sizeof(unsigned long long)));
+  t->size = t->dropped = 0;
+  return GG_OK;
+}
+
+int gg_trace_info(gg_trace* t, int64_t* size, int64_t* positives, int64_t* dropped) {
+  if (!t) return fail(GG_E_INVAL, "null trace");
+  GG_HIP(hipDeviceSynchronize());
+  unsigned long long p = 0;
+  GG_HIP(hipMemcpy(&p, t->pos, sizeof(p), hipMemcpyDeviceToHost));
+  if (size) *size = t->size;
+  if (positives) *positives = (int64_t)p;
+  if (dropped) *dropped = t->dropped;
+  return GG_OK;
+}
+
+int gg_trace_export(gg_trace* t, int64_t first, int64_t count, uint16_t* feat_host, float* label_host) {
+  if (!t) return fail(GG_E_INVAL, "null trace");
+  if (first < 0 || count < 0 || first + count > t->size) return fail(GG_E_RANGE, "samples outside the trace");
+  GG_HIP(hipDeviceSynchronize());
+  if (count == 0) return GG_OK;
+  if (feat_host) GG_HIP(hipMemcpy(feat_host, t->feat + first * 8, (size_t)count * 16, hipMemcpyDeviceToHost));
+  if (label_host) GG_HIP(hipMemcpy(label_host, t->label + first, (size_t)count * 4, hipMemcpyDeviceToHost));
+  return GG_OK;
+}
 
 }  // extern "C"

@@ -72,3 +72,48 @@ def graph_for(app, scale, seed, ef=16):
     if app == "cc":
         return gg.rmat(scale, ef, seed=seed, symmetrize=True)
     return gg.rmat(scale, ef, seed=seed, weights=(app == "sssp"))
+
+
+# ---------------------------------------------------------------------------
+# MLP parameters and features for the learned-policy tests
+# ---------------------------------------------------------------------------
+
+def mlp_random_params(seed, scale=1.0):
+    """He-uniform weights, small biases; binary32 values in float64."""
+    import math
+    H, IN = oracle.MLP_HIDDEN, oracle.MLP_IN
+    rng = np.random.default_rng(seed)
+    p = np.zeros(oracle.MLP_PARAMS)
+    p[oracle.P_W1:oracle.P_B1] = rng.uniform(-1, 1, IN * H) * math.sqrt(6.0 / IN) * scale
+    p[oracle.P_B1:oracle.P_W2] = rng.uniform(-0.1, 0.1, H)
+    p[oracle.P_W2:oracle.P_B2] = rng.uniform(-1, 1, H * H) * math.sqrt(6.0 / H) * scale
+    p[oracle.P_B2:oracle.P_W3] = rng.uniform(-0.1, 0.1, H)
+    p[oracle.P_W3:oracle.P_B3] = rng.uniform(-1, 1, H) * math.sqrt(6.0 / H) * scale
+    p[oracle.P_B3] = 0.05
+    return p.astype(np.float32).astype(np.float64)
+
+
+def mlp_random_features(seed, n):
+    """bfloat16 bits [n, 8] spread like the policy's features."""
+    rng = np.random.default_rng(seed)
+    f = np.zeros((n, oracle.MLP_IN), dtype=np.float32)
+    f[:, 0] = rng.uniform(0, 12, n)
+    f[:, 1] = rng.uniform(0, 12, n)
+    f[:, 2] = rng.uniform(0, 1, n)
+    f[:, 3] = rng.uniform(0, 1, n) ** 3
+    f[:, 4] = rng.uniform(0, 1, n) ** 3
+    return oracle.bf16_array(f)
+
+
+def mlp_selector_params(feature, scale=1.0):
+    """logit = scale * feature_k, computed exactly: h1_0 = relu(f_k), h2_0 = relu(h1_0)."""
+    H = oracle.MLP_HIDDEN
+    p = np.zeros(oracle.MLP_PARAMS)
+    p[oracle.P_W1 + feature * H + 0] = 1.0
+    p[oracle.P_W2 + 0 * H + 0] = 1.0
+    p[oracle.P_W3 + 0] = scale
+    return p
+
+
+def bf16_to_f64(bits):
+    return (np.asarray(bits, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)

@@ -8,7 +8,6 @@ torch.optim.Adam; the policy against hand-worked examples and the special
 cases that reduce it to GG or SP.
 """
 import json
-import math
 import os
 
 import numpy as np
@@ -17,36 +16,14 @@ import torch
 
 import graphgen as gg
 import oracle
+from helpers import bf16_to_f64, mlp_random_features, mlp_random_params, mlp_selector_params
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 H, IN, NP = oracle.MLP_HIDDEN, oracle.MLP_IN, oracle.MLP_PARAMS
 
 
-def random_params(seed, scale=1.0):
-    rng = np.random.default_rng(seed)
-    p = np.zeros(NP)
-    p[oracle.P_W1:oracle.P_B1] = rng.uniform(-1, 1, IN * H) * math.sqrt(6.0 / IN) * scale
-    p[oracle.P_B1:oracle.P_W2] = rng.uniform(-0.1, 0.1, H)
-    p[oracle.P_W2:oracle.P_B2] = rng.uniform(-1, 1, H * H) * math.sqrt(6.0 / H) * scale
-    p[oracle.P_B2:oracle.P_W3] = rng.uniform(-0.1, 0.1, H)
-    p[oracle.P_W3:oracle.P_B3] = rng.uniform(-1, 1, H) * math.sqrt(6.0 / H) * scale
-    p[oracle.P_B3] = 0.05
-    return p.astype(np.float32).astype(np.float64)  # binary32 master values
-
-
-def random_features(seed, n):
-    rng = np.random.default_rng(seed)
-    f = np.zeros((n, IN), dtype=np.float32)
-    f[:, 0] = rng.uniform(0, 12, n)
-    f[:, 1] = rng.uniform(0, 12, n)
-    f[:, 2] = rng.uniform(0, 1, n)
-    f[:, 3] = rng.uniform(0, 1, n) ** 3
-    f[:, 4] = rng.uniform(0, 1, n) ** 3
-    return oracle.bf16_array(f)
-
-
-def bf16_to_f64(bits):
-    return (np.asarray(bits, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+random_params = mlp_random_params
+random_features = mlp_random_features
 
 
 # --------------------------------------------------------------------------
@@ -266,13 +243,7 @@ def test_adam_vs_torch():
 # LEARNED policy
 # --------------------------------------------------------------------------
 
-def selector_params(feature, scale=1.0):
-    """logit = scale * feature (exact): h1_0 = relu(f), h2_0 = relu(h1_0)."""
-    p = np.zeros(NP)
-    p[oracle.P_W1 + feature * H + 0] = 1.0
-    p[oracle.P_W2 + 0 * H + 0] = 1.0
-    p[oracle.P_W3 + 0] = scale
-    return p
+selector_params = mlp_selector_params
 
 
 def _graph_4v():
