@@ -267,6 +267,8 @@ hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
                          uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* judge,
                          unsigned long long* trace_pos, hipStream_t st);
 hipError_t launch_add_f32(const float* src, float* dst, hipStream_t st);
+hipError_t launch_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,
+                          const int32_t* act_cnt, int32_t* changed, unsigned long long* act_sum, hipStream_t st);
 hipError_t launch_clear_rows(const int32_t* list, int32_t count, const int32_t* rowptr, uint32_t* bits,
                              hipStream_t st);
 

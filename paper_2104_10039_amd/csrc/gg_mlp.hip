@@ -547,6 +547,29 @@ __global__ void k_clear_rows(const int32_t* list, int32_t count, const int32_t* 
   }
 }
 
+// Before the selected rows of a partial superstep are recomputed over all
+// in-edges: withdraw the change the approximate gather counted for them
+// (SSSP/CC, changed may be null) and add up their active edges.
+__global__ void k_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,
+                          const int32_t* act_cnt, int32_t* changed, unsigned long long* act_sum) {
+  int withdrawn = 0;
+  unsigned long long a = 0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+    const int u = list[t];
+    if (changed) withdrawn += x_next[u] != x_in[u];
+    a += (unsigned long long)act_cnt[u];
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    withdrawn += __shfl_xor(withdrawn, o, 64);
+    a += __shfl_xor(a, o, 64);
+  }
+  if (__lane_id() == 0) {
+    if (changed && withdrawn) atomicSub(changed, withdrawn);
+    if (a) atomicAdd(act_sum, a);
+  }
+}
+
 static int grid1d(int64_t n, int per) {
   int64_t g = (n + per - 1) / per;
   if (g < 1) g = 1;
@@ -574,6 +597,14 @@ hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_labels, dim3(grid1d(n, 1024)), dim3(256), 0, st, app, n, acc, apx, eps, sel, label_u8, label_f,
                      nf, judge, trace_pos);
+  return hipGetLastError();
+}
+
+hipError_t launch_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,
+                          const int32_t* act_cnt, int32_t* changed, unsigned long long* act_sum, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sel_fix, dim3(grid1d(count, 1024)), dim3(256), 0, st, list, count, x_in, x_next, act_cnt,
+                     changed, act_sum);
   return hipGetLastError();
 }
 

@@ -143,10 +143,9 @@ struct gg_graph {
   uint8_t* labels = nullptr;       // n: drift labels of the last traced / judged superstep
   uint32_t* shadow = nullptr;      // n: approximate update of that superstep
   int32_t* sel_count = nullptr;    // 1
-  unsigned long long* judge = nullptr;  // [0] drifted vertices, [1] of which selected
+  unsigned long long* judge = nullptr;  // [0] drifted vertices, [1] of which selected, [2] active edges of S
   int32_t* dummy = nullptr;        // changed-counter sink of the shadow pass
   Bins selb;                       // binning of the selected rows (full rows)
-  Bins nselb;                      // binning of the other rows (active edges)
   // workspace (allocated on first run)
   bool ws = false;
   float* c[2] = {nullptr, nullptr};
@@ -265,10 +264,9 @@ int ensure_learned(gg_graph* g) {
   GG_TRY(dalloc(&g->labels, n));
   GG_TRY(dalloc(&g->shadow, n));
   GG_TRY(dalloc(&g->sel_count, 1));
-  GG_TRY(dalloc(&g->judge, 2));
+  GG_TRY(dalloc(&g->judge, 3));
   GG_TRY(dalloc(&g->dummy, 1));
   GG_TRY(alloc_bins(g->selb, g->n));
-  GG_TRY(alloc_bins(g->nselb, g->n));
   g->lws = true;
   return GG_OK;
 }
@@ -504,7 +502,6 @@ void free_graph(gg_graph* g) {
   dfree(g->judge);
   dfree(g->dummy);
   free_bins(g->selb);
-  free_bins(g->nselb);
   for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
@@ -850,19 +847,30 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   } else if (kind == GG_STEP_PARTIAL) {
     // Partial superstep: the selected rows S gather over all in-edges and
     // re-select their flags; the other rows take an approximate iteration and
-    // keep theirs.
+    // keep theirs. The approximate gather runs over every row (the fast
+    // path); the superstep over S then overwrites S's results, after S's
+    // approximate change counts are withdrawn.
     pkind = 4;
     GG_TRY(rebin(g, g->selb, nullptr, g->sel, 1));
-    GG_TRY(rebin(g, g->nselb, g->act_cnt, g->sel, 0));
     const int32_t ns = g->selb.h.small + g->selb.h.wave + g->selb.h.hub;
     GG_HIP(launch_copy_u32(g->bits[r->bcur], g->bits[1 - r->bcur], (g->m + 31) / 32, g->stream));
     GG_HIP(launch_clear_rows(g->selb.list, ns, g->rowptr, g->bits[1 - r->bcur], g->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)(g->judge + 2), 2, 0u, g->stream));
     Sweep sa = s;
-    set_bins(sa, g->nselb);
+    set_bins(sa, g->act);
     sa.edges = g->act_edges;
     sa.cnt = g->act_cnt;
-    GG_TRY(check_part_capacity(g, g->nselb));
-    GG_HIP(launch_gather(app, g->tune.small_team, sa, g->stream, pe0, nullptr));
+    GG_TRY(check_part_capacity(g, g->act));
+    if (g->tune.seg_enable) {
+      GG_TRY(check_seg_capacity(g, g->act));
+      set_seg(g, sa, g->seg_off_act);
+      GG_HIP(launch_gather_seg(app, g->tune.small_team, sa, g->stream, pe0, nullptr));
+    } else {
+      GG_HIP(launch_gather(app, g->tune.small_team, sa, g->stream, pe0, nullptr));
+    }
+    GG_HIP(launch_sel_fix(g->selb.list, ns, pr ? nullptr : s.x_in, pr ? nullptr : s.x_next, g->act_cnt,
+                          pr ? nullptr : g->changed, g->judge + 2, g->stream));
+    const int64_t act_all = g->act.h.edges;
     Sweep sc = s;
     set_bins(sc, g->selb);
     sc.edges = full_edges(g, app);
@@ -871,12 +879,15 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     sc.new_bits = g->bits[1 - r->bcur];
     GG_TRY(check_part_capacity(g, g->selb));
     GG_HIP(launch_superstep(app, g->tune.small_team, sc, g->stream, nullptr, pe1));
+    unsigned long long act_s = 0;
+    GG_HIP(hipMemcpyAsync(&act_s, g->judge + 2, sizeof(act_s), hipMemcpyDeviceToHost, g->stream));
     r->bcur = 1 - r->bcur;
-    GG_TRY(rebin_act(g, app));
+    GG_TRY(rebin_act(g, app));  // synchronizes the stream
     r->supersteps++;
     r->partials++;
-    edges = g->nselb.h.edges + g->selb.h.edges;
-    processed = edges;
+    // algorithmic edges: S over all in-edges, the other rows over active ones
+    edges = act_all - (int64_t)act_s + g->selb.h.edges;
+    processed = act_all + g->selb.h.edges;
   } else if (superstep) {
     pkind = 2;
     if (traced || judged) {

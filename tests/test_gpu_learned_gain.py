@@ -1,0 +1,88 @@
+"""What the trained network gains over the method without it.
+
+Traces come from GG runs on one seeded R-MAT graph; the network is trained
+on them by the library's own kernels and then drives LEARNED runs on a
+different seeded graph of the same family. Against GG at the same sample
+ratio and alpha (the paper's full correction at every correction step) the
+learned policy must gather clearly fewer edges at no worse accuracy, and
+against GG at a larger alpha with a similar edge budget it must be more
+accurate. Accuracy is measured against the exact run on the same graph:
+CC by the fraction of wrong labels, PageRank by the top-1000 error.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from helpers import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_10039_amd as P
+    return P
+
+
+def _err(app, out, exact):
+    from paper_2104_10039_amd import metrics
+    o, e = out.cpu().numpy(), exact.cpu().numpy()
+    if app == "pr":
+        return metrics.topk_error(o, e, 1000)
+    return metrics.label_mismatch(o, e)
+
+
+def _iters(G, app):
+    """PR: 20 iterations; CC: the exact run's iteration count (its fixed point)."""
+    return 20 if app == "pr" else G.exact_run(app)[1].iterations
+
+
+def _train(P, app, g, eps):
+    G = P.Graph.from_host(g)
+    T = P.Trace(60 * g.n)
+    iters = _iters(G, app)
+    for sg in (0.1, 0.3, 0.5, 0.7, 0.9):
+        for a in (1, 4):
+            G.approx_run(app, sg, "gg", alpha=a, theta=0.05, seed=5, iters=iters, trace=T, label_eps=eps)
+    info = T.info()
+    net = P.Mlp(seed=7)
+    pw = (info["size"] - info["positives"]) / max(info["positives"], 1)
+    losses = net.train(T, epochs=8, batch=8192, lr=2e-3, pos_weight=pw, seed=8)
+    log(app, "trace", info, "epoch losses", [round(float(x), 4) for x in losses])
+    assert losses[-1] < losses[0]
+    T.close()
+    G.close()
+    return net
+
+
+@pytest.mark.parametrize("app,eps,tau", [("cc", 1e-3, -2.0), ("pr", 5e-2, 4.0)])
+def test_learned_gain_over_gg(P, app, eps, tau):
+    sym = app == "cc"
+    ga = gg.rmat(16, 16, seed=11, symmetrize=sym)
+    gb = gg.rmat(16, 16, seed=12, symmetrize=sym)
+    net = _train(P, app, ga, eps)
+    G = P.Graph.from_host(gb)
+    iters = _iters(G, app)
+    exact, sx = G.exact_run(app, iters=iters)
+    kw = dict(theta=0.05, seed=5, iters=iters, stop="fixed_iters")
+    res = {}
+    for name, pol, extra in (("gg4", "gg", dict(alpha=4)), ("gg8", "gg", dict(alpha=8)),
+                             ("sp", "sp", dict(alpha=4)),
+                             ("learned", "learned", dict(alpha=4, mlp=net, tau=tau, rho=0.6, fallback_k=0))):
+        out, st = G.approx_run(app, 0.3, pol, **kw, **extra)
+        res[name] = (st.edges_gathered / sx.edges_gathered, _err(app, out, exact), st.device_ms)
+        log(app, name, "edges %.3f of exact, error %.4f, %.3f ms" % res[name])
+    e_l, err_l, _ = res["learned"]
+    e_g4, err_g4, _ = res["gg4"]
+    e_g8, err_g8, _ = res["gg8"]
+    # fewer edges than GG at the same alpha, at no worse accuracy
+    assert e_l <= 0.93 * e_g4
+    assert err_l <= err_g4 + 0.005
+    # more accurate than GG at a similar edge budget (larger alpha)
+    assert e_l <= 1.10 * e_g8
+    assert err_l < err_g8
+    net.close()
+    G.close()
