@@ -11,6 +11,17 @@ the exact run's iteration count). Inputs are resident in HBM before timing;
 sampling and packing are inside the timed region.
 
 value = edges gathered per second over the timed steps (GTEPS, all runs).
+
+Two further sections are measured after the timed steps (they are not part
+of `value`):
+  batch    256 SSSP and 256 personalized-PageRank queries on R-MAT scale 20
+           (one captured HIP graph per kind), and 64 independent R-MAT graphs
+           of scale 10..18 and edge factor 8..32 run as one block-diagonal
+           union (PR, SSSP, CC);
+  learned  the correction network trained by the library's kernels on the
+           (features, drift label) traces of GG runs on the scale-22 graph at
+           every sample ratio, then LEARNED against GG and exact on R-MAT
+           scale 23 (seed 6) for PR and SSSP at sample ratio 0.3.
 Printed as one JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -49,6 +60,111 @@ def cpu_baseline(graphs, source, budget_iters=3):
     return {"value": edges / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": "%d exact iterations each of PR, SSSP and CC on the benchmark graphs (%.1f s, %d edges)"
                       % (budget_iters, dt, edges)}
+
+
+def bench_batch(P, gg, torch, seed):
+    """Batched queries on R-MAT scale 20 and a union of 64 uneven graphs."""
+    out = {}
+    t = time.perf_counter()
+    g = gg.rmat(20, 16, seed=seed, weights=True)
+    G = P.Graph.from_host(g)
+    srcs = gg.pick_sources(g, 256, seed + 1)
+    log("batch: rmat20 ready in %.1f s" % (time.perf_counter() - t))
+    for app, kw in (("sssp", dict(max_iters=1000)), ("ppr", dict(iters=20))):
+        G.batch_run(app, srcs, **kw)  # first call sizes the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = G.batch_run(app, srcs, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        q = len(srcs)
+        # per iteration: edge words (+ weights for SSSP), Q gathered values per
+        # edge, Q values read and written per vertex
+        per_it = g.m * (4.0 + (4.0 if app == "sssp" else 0.0) + 4.0 * q) + g.n * q * 8.0
+        out["rmat20_%s_q%d" % (app, q)] = {
+            "ms": round(dt * 1e3, 3), "device_ms": round(st.device_ms, 3), "iterations": st.iterations,
+            "gteps": round(st.edges_gathered / dt / 1e9, 2),
+            "alg_gbs": round(per_it * st.iterations / (st.device_ms * 1e-3) / 1e9, 1)}
+        log("batch:", app, out["rmat20_%s_q%d" % (app, q)])
+    G.close()
+    t = time.perf_counter()
+    for app in ("pr", "sssp", "cc"):
+        gs = gg.rmat_family(64, scale_range=(10, 18), ef_range=(8, 32), seed0=1000, weights=(app == "sssp"),
+                            symmetrize=(app == "cc"))
+        U, ps = gg.union(gs)
+        srcs = None
+        if app == "sssp":
+            srcs = [int(ps[k]) + int(gg.pick_sources(gs[k], 1, 50 + k)[0]) for k in range(len(gs))]
+        G = P.Graph.from_host(U)
+        G.set_parts(ps, srcs)
+        G.exact_run(app, iters=20, max_iters=1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = G.exact_run(app, iters=20, max_iters=1000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["union64_%s" % app] = {"n": U.n, "m": U.m, "ms": round(dt * 1e3, 3), "iterations": st.iterations,
+                                   "gteps": round(st.edges_gathered / dt / 1e9, 2)}
+        log("batch:", app, out["union64_%s" % app])
+        G.close()
+    log("batch: unions done in %.1f s" % (time.perf_counter() - t))
+    return out
+
+
+def bench_learned(P, gg, torch, np, metrics, G22, g22, source22, iters22, alpha, theta):
+    """Train on traces of GG runs on the scale-22 graph, evaluate on scale 23."""
+    out = {}
+    t = time.perf_counter()
+    g23 = gg.rmat(23, 16, seed=6, weights=True)
+    G23 = P.Graph.from_host(g23)
+    s23 = int(gg.pick_sources(g23, 1, 6)[0])
+    log("learned: rmat23 ready in %.1f s" % (time.perf_counter() - t))
+    # selection thresholds and drift-label tolerance per app
+    cfg = {"pr": (5e-2, 4.0), "sssp": (1e-3, 0.0)}
+    for app in ("pr", "sssp"):
+        eps, tau = cfg[app]
+        T = P.Trace(int(1.2 * g22.n * 5 * (iters22[app] // (alpha + 1) + 1)))
+        t0 = time.perf_counter()
+        for sg in (0.1, 0.3, 0.5, 0.7, 0.9):
+            G22.approx_run(app, sg, "gg", alpha=alpha, theta=theta, seed=1, iters=iters22[app], source=source22,
+                           trace=T, label_eps=eps)
+        info = T.info()
+        net = P.Mlp(seed=7)
+        pw = (info["size"] - info["positives"]) / max(info["positives"], 1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        losses = net.train(T, epochs=4, batch=65536, lr=2e-3, pos_weight=pw, seed=8)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t1
+        log("learned:", app, "trace", info, "traced in %.1f s, trained in %.2f s" % (t1 - t0, train_s),
+            "losses", [round(float(x), 4) for x in losses])
+        T.close()
+        it = 20
+        if app != "pr":
+            it = G23.exact_run(app, source=s23)[1].iterations
+        ex, sx = G23.exact_run(app, iters=it, source=s23)
+        exh = ex.cpu().numpy()
+        rec = {"trace_samples": info["size"], "trace_positives": info["positives"], "train_s": round(train_s, 3),
+               "epoch_loss": [round(float(x), 4) for x in losses], "tau": tau, "label_eps": eps,
+               "exact": {"ms": round(sx.device_ms, 3), "edges": sx.edges_gathered}}
+        kw = dict(alpha=alpha, theta=theta, seed=1, iters=it, source=s23, stop="fixed_iters")
+        for name, pol, extra in (("gg", "gg", {}), ("learned", "learned",
+                                                      dict(mlp=net, tau=tau, rho=0.6, fallback_k=0))):
+            G23.approx_run(app, 0.3, pol, **kw, **extra)  # warm
+            o, st = G23.approx_run(app, 0.3, pol, **kw, **extra)
+            oh = o.cpu().numpy()
+            if app == "pr":
+                err = metrics.topk_error(oh, exh, 1000)
+            else:
+                err = metrics.stretch_error(oh.view(np.uint32), exh.view(np.uint32), s23)
+            rec[name] = {"ms": round(st.device_ms, 3), "edges_vs_exact": round(st.edges_gathered / sx.edges_gathered, 4),
+                         "speedup": round(sx.device_ms / st.device_ms, 3), "accuracy": round(metrics.accuracy(err), 3),
+                         "partial_supersteps": st.partial_supersteps}
+        out["rmat23_%s_sigma0.3" % app] = rec
+        log("learned:", app, rec)
+        net.close()
+    G23.close()
+    return out
 
 
 def kernel_source_sha():
@@ -107,6 +223,8 @@ def main():
     ap.add_argument("--apps", default="pr,sssp,cc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-query section")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction section")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain copy kernel of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -240,6 +358,13 @@ def main():
                 "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(bytes_per_launch),
                 "launches": pb["launches"]}
 
+    batch = None
+    if not args.no_batch:
+        batch = bench_batch(P, gg, torch, args.seed)
+    learned = None
+    if not args.no_learned and "pr" in apps and "sssp" in apps:
+        learned = bench_learned(P, gg, torch, np, metrics, G["pr"], gw, source, iters, args.alpha, args.theta)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -265,6 +390,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "runs": summary,
+        "batch": batch,
+        "learned": learned,
     }
     print(json.dumps(res), flush=True)
 

@@ -83,6 +83,7 @@ struct Sweep {
   const int32_t* seg_off;
   double* seg_part_f;
   uint32_t* seg_part_u;
+  int32_t flat_list;  // flat superstep: short rows from list[0, n_small) instead of every vertex
 };
 
 // Segmented gather constants.
@@ -269,7 +270,7 @@ hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
 hipError_t launch_add_f32(const float* src, float* dst, hipStream_t st);
 hipError_t launch_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,
                           const int32_t* act_cnt, int32_t* changed, unsigned long long* act_sum, hipStream_t st);
-hipError_t launch_clear_rows(const int32_t* list, int32_t count, const int32_t* rowptr, uint32_t* bits,
-                             hipStream_t st);
+hipError_t launch_clear_rows(const int32_t* list, int32_t n_short, int32_t count, const int32_t* rowptr,
+                             uint32_t* bits, hipStream_t st);
 
 }  // namespace ggk

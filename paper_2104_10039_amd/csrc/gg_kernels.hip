@@ -1847,12 +1847,14 @@ __global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int
     return;
   }
   const int tid = threadIdx.x;
+  // natural order: every vertex, the short rows taken; listed: the small-bin
+  // rows list[0, n_small)
   const int u0 = ((int)blockIdx.x - nchunks - gw) * kBlock;
-  const int P = min(kBlock, s.n - u0);
-  const int u = u0 + tid;
-  int lo = 0, len = 0;
+  const int P = min(kBlock, (s.flat_list ? s.n_small : s.n) - u0);
+  int u = 0, lo = 0, len = 0;
   bool mine = false;
   if (tid < P) {
+    u = s.flat_list ? s.list[u0 + tid] : u0 + tid;
     lo = s.rowptr[u];
     len = s.rowptr[u + 1] - lo;
     mine = len <= s.small_max;
@@ -1961,7 +1963,7 @@ __global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int
 template <int APP>
 static hipError_t super_flat_t(const Sweep& s, int nchunks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (nchunks > 0) hipLaunchKernelGGL((k_hub_totals<APP>), dim3(nchunks), dim3(kBlock), 0, st, s);
-  const int gs = (s.n + kBlock - 1) / kBlock;
+  const int gs = ((s.flat_list ? s.n_small : s.n) + kBlock - 1) / kBlock;
   const int gw = s.n_wave > 0 ? grid_for(s.n_wave, kBlock / 64, kTeamBlockCap) : 0;
   const int total = nchunks + gw + gs;
   if (ev0) (void)hipEventRecord(ev0, st);

@@ -150,10 +150,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpDev w, const uint16_t* f
   const int wv = threadIdx.x >> 6;
   const int l = __lane_id(), g = l >> 4, c = l & 15;
   const int64_t ntiles = (n + 15) / 16;
+  int picked = 0;  // selected samples of this lane, over all its tiles
   for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
     Fwd F;
     forward_tile(sw, feat, n, tile * 16, h1[wv], F);
-    int picked = 0;
     if (c == 0) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -166,12 +166,19 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpDev w, const uint16_t* f
         }
       }
     }
-    if (sel_count) {
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) picked += __shfl_xor(picked, o, 64);
-      if (l == 0 && picked) atomicAdd(sel_count, picked);
-    }
     __builtin_amdgcn_wave_barrier();
+  }
+  if (sel_count) {
+    // one atomic per block
+    __shared__ int wsum[4];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) picked += __shfl_xor(picked, o, 64);
+    if (l == 0) wsum[wv] = picked;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+      if (t) atomicAdd(sel_count, t);
+    }
   }
 }
 
@@ -343,13 +350,21 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev w, const uint16_t* feat
   }
 }
 
-__global__ void k_mlp_reduce(const float* partial, int nwaves, float* grad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < kMlpParams + 1) {
-    float a = 0.f;
-    for (int b = 0; b < nwaves; ++b) a += partial[(int64_t)b * (kMlpParams + 1) + i];
-    grad[i] = a;
-  }
+// Sums the wave partials: a block takes 32 consecutive slots; lane group j
+// (8 groups) adds waves j, j+8, ... in order, then the 8 group sums are added
+// in a fixed tree, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float* partial, int nwaves, float* grad) {
+  __shared__ float red[8][33];
+  const int col = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int i = blockIdx.x * 32 + col;
+  float a = 0.f;
+  if (i < kMlpParams + 1)
+    for (int b = grp; b < nwaves; b += 8) a += partial[(int64_t)b * (kMlpParams + 1) + i];
+  red[grp][col] = a;
+  __syncthreads();
+  if (grp == 0 && i < kMlpParams + 1)
+    grad[i] = ((red[0][col] + red[1][col]) + (red[2][col] + red[3][col])) +
+              ((red[4][col] + red[5][col]) + (red[6][col] + red[7][col]));
 }
 
 // Adam on the FP32 master weights, then the BF16 copies.
@@ -404,7 +419,7 @@ hipError_t launch_mlp_grad(const MlpDev& w, const uint16_t* feat, const float* l
                            float* scratch, float* grad, hipStream_t st) {
   const int64_t nb = grad_blocks(n);
   hipLaunchKernelGGL(k_mlp_grad, dim3((int)nb), dim3(256), 0, st, w, feat, label, n, pos_weight, scratch);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, st, (const float*)scratch,
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + 31) / 32), dim3(256), 0, st, (const float*)scratch,
                      (int)(nb * 4), grad);
   return hipGetLastError();
 }
@@ -516,7 +531,18 @@ __global__ void k_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
     tp += __shfl_xor(tp, o, 64);
     fpos += __shfl_xor(fpos, o, 64);
   }
+  __shared__ unsigned long long ws[3][4];
+  const int wv = threadIdx.x >> 6;
   if (__lane_id() == 0) {
+    ws[0][wv] = pos;
+    ws[1][wv] = tp;
+    ws[2][wv] = fpos;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pos = ws[0][0] + ws[0][1] + ws[0][2] + ws[0][3];
+    tp = ws[1][0] + ws[1][1] + ws[1][2] + ws[1][3];
+    fpos = ws[2][0] + ws[2][1] + ws[2][2] + ws[2][3];
     if (judge && pos) atomicAdd(&judge[0], pos);
     if (judge && tp) atomicAdd(&judge[1], tp);
     if (trace_pos && fpos) atomicAdd(trace_pos, fpos);
@@ -527,23 +553,34 @@ __global__ void k_add_f32(const float* src, float* dst) {
   if (threadIdx.x == 0) *dst += *src;
 }
 
-// Clears the flag bits of the listed rows: one wave per row; words wholly
-// inside the row are stored, the two boundary words are masked atomically.
-__global__ void k_clear_rows(const int32_t* list, int32_t count, const int32_t* rowptr, uint32_t* bits) {
+// Clears the flag bits of edge range [b, e) in word k: words wholly inside
+// the range are stored, boundary words are masked atomically.
+__device__ __forceinline__ void clear_word(uint32_t* bits, int64_t k, int64_t b, int64_t e) {
+  const int64_t lo = (b > k * 32 ? b : k * 32) - k * 32;
+  const int64_t hi = (e < k * 32 + 32 ? e : k * 32 + 32) - k * 32;
+  const uint32_t m = hi - lo >= 32 ? 0xFFFFFFFFu : (((1u << (hi - lo)) - 1u) << lo);
+  if (m == 0xFFFFFFFFu) bits[k] = 0u;
+  else atomicAnd(&bits[k], ~m);
+}
+
+// Clears the flag bits of the listed rows: rows list[0, n_short) one thread
+// each (at most a few words), the rest one wave each.
+__global__ void k_clear_rows(const int32_t* list, int32_t n_short, int32_t count, const int32_t* rowptr,
+                             uint32_t* bits) {
+  const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = gtid; t < n_short; t += nthreads) {
+    const int u = list[t];
+    const int64_t b = rowptr[u], e = rowptr[u + 1];
+    if (b < e)
+      for (int64_t k = b >> 5; k <= ((e - 1) >> 5); ++k) clear_word(bits, k, b, e);
+  }
   const int lane = __lane_id();
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t t = wave; t < count; t += nwaves) {
+  for (int64_t t = n_short + (gtid >> 6); t < count; t += nthreads >> 6) {
     const int u = list[t];
     const int64_t b = rowptr[u], e = rowptr[u + 1];
     if (b >= e) continue;
-    for (int64_t k = (b >> 5) + lane; k <= ((e - 1) >> 5); k += 64) {
-      const int64_t lo = (b > k * 32 ? b : k * 32) - k * 32;
-      const int64_t hi = (e < k * 32 + 32 ? e : k * 32 + 32) - k * 32;
-      const uint32_t m = hi - lo >= 32 ? 0xFFFFFFFFu : (((1u << (hi - lo)) - 1u) << lo);
-      if (m == 0xFFFFFFFFu) bits[k] = 0u;
-      else atomicAnd(&bits[k], ~m);
-    }
+    for (int64_t k = (b >> 5) + lane; k <= ((e - 1) >> 5); k += 64) clear_word(bits, k, b, e);
   }
 }
 
@@ -564,7 +601,17 @@ __global__ void k_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_
     withdrawn += __shfl_xor(withdrawn, o, 64);
     a += __shfl_xor(a, o, 64);
   }
+  __shared__ int wsw[4];
+  __shared__ unsigned long long wsa[4];
+  const int wv = threadIdx.x >> 6;
   if (__lane_id() == 0) {
+    wsw[wv] = withdrawn;
+    wsa[wv] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    withdrawn = wsw[0] + wsw[1] + wsw[2] + wsw[3];
+    a = wsa[0] + wsa[1] + wsa[2] + wsa[3];
     if (changed && withdrawn) atomicSub(changed, withdrawn);
     if (a) atomicAdd(act_sum, a);
   }
@@ -595,7 +642,7 @@ hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
                          uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* judge,
                          unsigned long long* trace_pos, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_labels, dim3(grid1d(n, 1024)), dim3(256), 0, st, app, n, acc, apx, eps, sel, label_u8, label_f,
+  hipLaunchKernelGGL(k_labels, dim3(grid1d(n, 4096)), dim3(256), 0, st, app, n, acc, apx, eps, sel, label_u8, label_f,
                      nf, judge, trace_pos);
   return hipGetLastError();
 }
@@ -603,7 +650,7 @@ hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
 hipError_t launch_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,
                           const int32_t* act_cnt, int32_t* changed, unsigned long long* act_sum, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sel_fix, dim3(grid1d(count, 1024)), dim3(256), 0, st, list, count, x_in, x_next, act_cnt,
+  hipLaunchKernelGGL(k_sel_fix, dim3(grid1d(count, 4096)), dim3(256), 0, st, list, count, x_in, x_next, act_cnt,
                      changed, act_sum);
   return hipGetLastError();
 }
@@ -613,11 +660,11 @@ hipError_t launch_add_f32(const float* src, float* dst, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_clear_rows(const int32_t* list, int32_t count, const int32_t* rowptr, uint32_t* bits,
-                             hipStream_t st) {
+hipError_t launch_clear_rows(const int32_t* list, int32_t n_short, int32_t count, const int32_t* rowptr,
+                             uint32_t* bits, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_clear_rows, dim3(grid1d((int64_t)count * 64, 256)), dim3(256), 0, st, list, count, rowptr,
-                     bits);
+  const int64_t work = (int64_t)n_short + (int64_t)(count - n_short) * 64;
+  hipLaunchKernelGGL(k_clear_rows, dim3(grid1d(work, 256)), dim3(256), 0, st, list, n_short, count, rowptr, bits);
   return hipGetLastError();
 }
 

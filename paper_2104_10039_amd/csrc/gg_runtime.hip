@@ -854,7 +854,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     GG_TRY(rebin(g, g->selb, nullptr, g->sel, 1));
     const int32_t ns = g->selb.h.small + g->selb.h.wave + g->selb.h.hub;
     GG_HIP(launch_copy_u32(g->bits[r->bcur], g->bits[1 - r->bcur], (g->m + 31) / 32, g->stream));
-    GG_HIP(launch_clear_rows(g->selb.list, ns, g->rowptr, g->bits[1 - r->bcur], g->stream));
+    GG_HIP(launch_clear_rows(g->selb.list, g->selb.h.small, ns, g->rowptr, g->bits[1 - r->bcur], g->stream));
     GG_HIP(launch_fill_u32((uint32_t*)(g->judge + 2), 2, 0u, g->stream));
     Sweep sa = s;
     set_bins(sa, g->act);
@@ -878,7 +878,12 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     sc.old_bits = g->bits[r->bcur];
     sc.new_bits = g->bits[1 - r->bcur];
     GG_TRY(check_part_capacity(g, g->selb));
-    GG_HIP(launch_superstep(app, g->tune.small_team, sc, g->stream, nullptr, pe1));
+    if (g->tune.seg_enable) {
+      sc.flat_list = 1;
+      GG_HIP(launch_superstep_flat(app, sc, g->stream, nullptr, pe1));
+    } else {
+      GG_HIP(launch_superstep(app, g->tune.small_team, sc, g->stream, nullptr, pe1));
+    }
     unsigned long long act_s = 0;
     GG_HIP(hipMemcpyAsync(&act_s, g->judge + 2, sizeof(act_s), hipMemcpyDeviceToHost, g->stream));
     r->bcur = 1 - r->bcur;
