@@ -84,6 +84,7 @@ struct Sweep {
   double* seg_part_f;
   uint32_t* seg_part_u;
   int32_t flat_list;  // flat superstep: short rows from list[0, n_small) instead of every vertex
+  const int32_t* chunk_order;  // superstep hub chunks in source-segment order (null: natural order)
 };
 
 // Segmented gather constants.
@@ -159,6 +160,10 @@ hipError_t launch_superstep(int app, int team, const Sweep& s, hipStream_t st, h
                             hipEvent_t ev1 = nullptr);
 // Superstep with flattened batches for rows of degree <= wave_max (owner
 // threads walk each row in CSR order) and the chunked path for longer rows.
+// Order of the hub chunks of s's bins by the source segment (width z) of
+// their first edge; scratch holds nseg + n_chunks ints, order n_chunks.
+hipError_t launch_chunk_order(const Sweep& s, const int32_t* col, int32_t z, int32_t nseg, int32_t* scratch,
+                              int32_t* order, hipStream_t st);
 hipError_t launch_superstep_flat(int app, const Sweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
                                  hipEvent_t ev1 = nullptr);
 // Pack the active edges selected by s.old_bits (used after the initial sampling).

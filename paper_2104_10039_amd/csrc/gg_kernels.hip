@@ -371,23 +371,42 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
     const int len = s.rowptr[u + 1] - b;
     T carry = R::id();
     int carry_cnt = 0;
-    for (int k0 = 0; k0 < len; k0 += TEAM) {
+    // edge words and values of kPreT consecutive team-wide steps are loaded
+    // before the first step's scan
+    constexpr int kPreT = 4;
+    for (int g0 = 0; g0 < len; g0 += kPreT * TEAM) {
+    uint32_t evq[kPreT];
+    T vq[kPreT];
+#pragma unroll
+    for (int q = 0; q < kPreT; ++q) {
+      const int k = g0 + q * TEAM + lt;
+      evq[q] = k < len ? ld_stream(s.edges + b + k) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kPreT; ++q) {
+      const int k = g0 + q * TEAM + lt;
+      vq[q] = k < len ? R::elem(s, evq[q]) : R::id();
+    }
+#pragma unroll
+    for (int q = 0; q < kPreT; ++q) {
+      const int k0 = g0 + q * TEAM;
+      if (k0 >= len) break;  // uniform over the team
       const int k = k0 + lt;
       const bool valid = k < len;
       const int e = b + k;
-      const uint32_t ev = valid ? ld_stream(s.edges + e) : 0u;
+      const uint32_t ev = evq[q];
       const uint32_t oldf = (valid && s.old_bits) ? edge_bit(s.old_bits, e) : 0u;
       bool flag;
       T chunk_total;
       if constexpr (APP == kPR || APP == kPPR) {
-        const double c = valid ? (double)s.c_in[ev] : 0.0;
+        const double c = vq[q];
         const double incl = team_scan_add<TEAM>(c, lt);
         const double P = carry + incl;
         flag = Decide<kPR>::f(s, valid, c, P, oldf);
         chunk_total = __shfl(incl, TEAM - 1, TEAM);
       } else if constexpr (APP == kSSSP) {
-        const uint32_t xv = valid ? s.x_in[ev & 0xFFFFFFu] : kInf;
-        const uint32_t cand = xv == kInf ? kInf : xv + (ev >> 24);
+        const uint32_t cand = vq[q];  // INF exactly when the source is unreached
+        const uint32_t xv = cand;
         const uint32_t incl = team_scan_min<TEAM>(cand, lt);
         uint32_t excl = (uint32_t)__shfl_up((int)incl, 1, TEAM);
         if (lt == 0) excl = kInf;
@@ -398,7 +417,7 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
         else flag = oldf != 0u;
         chunk_total = __shfl(incl, TEAM - 1, TEAM);
       } else {  // CC
-        const uint32_t xv = valid ? s.x_in[ev] : kInf;
+        const uint32_t xv = vq[q];
         const uint32_t incl = team_scan_min<TEAM>(xv, lt);
         uint32_t excl = (uint32_t)__shfl_up((int)incl, 1, TEAM);
         if (lt == 0) excl = kInf;
@@ -414,6 +433,7 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
       write_bits<TEAM>(s.new_bits, tm, lt, e, len - k, valid);
       carry_cnt += __popcll(tm);
       carry = R::op(carry, chunk_total);
+    }
     }
     if (lt == 0) {
       apply<APP>(s, u, carry, nchanged);
@@ -449,16 +469,35 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
   T carry = R::id();
   for (int i = 0; i < j; ++i) carry = R::op(carry, part(c0 + i));
   int cnt = 0;
-  for (int sub = e0; sub < e1; sub += kBlock) {
+  // The edge words and gathered values of kPre consecutive 256-edge steps are
+  // loaded before the first step's scan, so one round trip to memory serves
+  // the whole group.
+  constexpr int kPre = 8;
+  for (int g0 = e0; g0 < e1; g0 += kPre * kBlock) {
+  uint32_t evq[kPre];
+  T vq[kPre];
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    const int k = g0 + q * kBlock + (int)threadIdx.x;
+    evq[q] = k < e1 ? ld_stream(s.edges + b + k) : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    const int k = g0 + q * kBlock + (int)threadIdx.x;
+    vq[q] = k < e1 ? R::elem(s, evq[q]) : R::id();
+  }
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) {
+    const int sub = g0 + q * kBlock;
+    if (sub >= e1) break;  // uniform over the block
     const int k = sub + (int)threadIdx.x;
     const bool valid = k < e1;
     const int e = b + k;
-    const uint32_t ev = valid ? ld_stream(s.edges + e) : 0u;
     const uint32_t oldf = (valid && s.old_bits) ? edge_bit(s.old_bits, e) : 0u;
     bool flag;
     T sub_total;
     if constexpr (APP == kPR || APP == kPPR) {
-      const double c = valid ? (double)s.c_in[ev] : 0.0;
+      const double c = vq[q];
       const double incl_w = team_scan_add<64>(c, lane);
       if (lane == 63) lds[wid] = incl_w;
       __syncthreads();
@@ -469,13 +508,7 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
       const double P = carry + (before + incl_w);
       flag = Decide<kPR>::f(s, valid, c, P, oldf);
     } else {
-      uint32_t val;
-      if constexpr (APP == kSSSP) {
-        const uint32_t xv = valid ? s.x_in[ev & 0xFFFFFFu] : kInf;
-        val = xv == kInf ? kInf : xv + (ev >> 24);
-      } else {
-        val = valid ? s.x_in[ev] : kInf;
-      }
+      const uint32_t val = vq[q];  // SSSP: INF exactly when the source is unreached
       const uint32_t incl_w = team_scan_min<64>(val, lane);
       uint32_t excl_w = (uint32_t)__shfl_up((int)incl_w, 1, 64);
       if (lane == 0) excl_w = kInf;
@@ -500,6 +533,7 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
     write_bits<64>(s.new_bits, bal, lane, e, e1 - (sub + wid * 64) - lane, valid);
     cnt += __popcll(bal);
     carry = R::op(carry, sub_total);
+  }
   }
   // cnt is per wave; sum over the block
   const int tot = block_sum_int((lane == 0) ? cnt : 0, ilds);
@@ -534,7 +568,7 @@ template <int APP>
 __global__ __launch_bounds__(kBlock) void k_hub_totals(Sweep s) {
   __shared__ typename Tr<APP>::T lds[4];
   int dummy = 0;
-  gather_hub_chunk<APP>(s, blockIdx.x, true, dummy, lds);
+  gather_hub_chunk<APP>(s, s.chunk_order ? s.chunk_order[blockIdx.x] : (int)blockIdx.x, true, dummy, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1836,7 +1870,7 @@ __global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int
   __shared__ int s_scan[kBlock + 1];
   int nchanged = 0;
   if ((int)blockIdx.x < nchunks) {
-    super_hub_chunk<APP>(s, blockIdx.x, nchanged, lds, ilds);
+    super_hub_chunk<APP>(s, s.chunk_order ? s.chunk_order[blockIdx.x] : (int)blockIdx.x, nchanged, lds, ilds);
     flush_changed<APP>(s, nchanged, ilds);
     return;
   }
@@ -1970,6 +2004,52 @@ static hipError_t super_flat_t(const Sweep& s, int nchunks, hipStream_t st, hipE
   if (total > 0) hipLaunchKernelGGL((k_super_flat<APP>), dim3(total), dim3(kBlock), 0, st, s, nchunks, gw);
   if (ev1) (void)hipEventRecord(ev1, st);
   if (nchunks > 0) hipLaunchKernelGGL(k_hub_pack, dim3(nchunks), dim3(kBlock), 0, st, s, (const uint32_t*)s.new_bits);
+  return hipGetLastError();
+}
+
+// Hub chunks ordered by the source segment of their first edge (rows are
+// sorted by source, so a chunk of a long row spans a narrow source range):
+// blocks dispatched together then gather from one window of the value array.
+__global__ void k_chunk_seg(Sweep s, const int32_t* col, int32_t z, int32_t nseg, int32_t* seg_of, int32_t* hist) {
+  for (int ch = blockIdx.x * blockDim.x + threadIdx.x; ch < s.n_chunks; ch += gridDim.x * blockDim.x) {
+    const int h = find_hub(s.hub_start, s.n_hub, ch);
+    const int u = s.list[s.n_small + s.n_wave + h];
+    const int j = ch - s.hub_start[h];
+    const int64_t e = (int64_t)s.rowptr[u] + (int64_t)j * s.hub_chunk;
+    const int sg = min(col[e] / z, nseg - 1);
+    seg_of[ch] = sg;
+    atomicAdd(&hist[sg], 1);
+  }
+}
+
+__global__ void k_chunk_cursor(int32_t* hist, int32_t nseg) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < nseg; ++i) {
+      const int c = hist[i];
+      hist[i] = run;
+      run += c;
+    }
+  }
+}
+
+__global__ void k_chunk_scatter(int32_t n_chunks, const int32_t* seg_of, int32_t* cursor, int32_t* order) {
+  for (int ch = blockIdx.x * blockDim.x + threadIdx.x; ch < n_chunks; ch += gridDim.x * blockDim.x)
+    order[atomicAdd(&cursor[seg_of[ch]], 1)] = ch;
+}
+
+hipError_t launch_chunk_order(const Sweep& s, const int32_t* col, int32_t z, int32_t nseg, int32_t* scratch,
+                              int32_t* order, hipStream_t st) {
+  if (s.n_chunks <= 0) return hipSuccess;
+  int32_t* hist = scratch;
+  int32_t* seg_of = scratch + nseg;
+  hipError_t e = launch_fill_u32((uint32_t*)hist, nseg, 0u, st);
+  if (e != hipSuccess) return e;
+  const int g = grid_for(s.n_chunks, kBlock, 4096);
+  hipLaunchKernelGGL(k_chunk_seg, dim3(g), dim3(kBlock), 0, st, s, col, z, nseg, seg_of, hist);
+  hipLaunchKernelGGL(k_chunk_cursor, dim3(1), dim3(64), 0, st, hist, nseg);
+  hipLaunchKernelGGL(k_chunk_scatter, dim3(g), dim3(kBlock), 0, st, s.n_chunks, (const int32_t*)seg_of, hist,
+                     order);
   return hipGetLastError();
 }
 

@@ -135,6 +135,9 @@ struct gg_graph {
   int64_t seg_cap_part = 0;  // 8-byte entries of the partial array
   Bins full;         // binning of the full rows by in-degree
   bool full_valid = false;
+  int32_t* chunk_order = nullptr;    // hub chunks of `full` in source-segment order
+  int32_t* chunk_scratch = nullptr;
+  int32_t chunk_cap = 0, chunk_order_n = 0;
   // learned correction and traces (allocated on first use)
   bool lws = false;
   uint16_t* feat = nullptr;        // [n][8] bfloat16 features
@@ -351,12 +354,35 @@ int seg_offsets(gg_graph* g, const Bins& b, const uint32_t* edges, const int32_t
 }
 
 // Binning of the full rows plus, with segmentation, their segment offsets.
+void set_bins(Sweep& s, const Bins& b);
+
 int rebin_full(gg_graph* g) {
   GG_TRY(rebin(g, g->full, nullptr));
+  g->chunk_order_n = 0;
   if (!g->tune.seg_enable) return GG_OK;
   seg_geometry(g);
   GG_TRY(ensure_seg(g));
-  return seg_offsets(g, g->full, (const uint32_t*)g->col, nullptr, 0xFFFFFFFFu, g->seg_off_full);
+  GG_TRY(seg_offsets(g, g->full, (const uint32_t*)g->col, nullptr, 0xFFFFFFFFu, g->seg_off_full));
+  // superstep hub chunks in source-segment order
+  const int32_t nch = g->full.h.hub > 0 ? g->full.h.chunks : 0;
+  if (nch == 0) return GG_OK;
+  if (g->chunk_cap < nch) {
+    dfree(g->chunk_order);
+    dfree(g->chunk_scratch);
+    g->chunk_cap = 0;
+    GG_TRY(dalloc(&g->chunk_order, (size_t)nch));
+    GG_TRY(dalloc(&g->chunk_scratch, (size_t)nch + (size_t)g->seg_s));
+    g->chunk_cap = nch;
+  }
+  Sweep s;
+  std::memset(&s, 0, sizeof(s));
+  s.n = g->n;
+  s.rowptr = g->rowptr;
+  s.hub_chunk = g->tune.hub_chunk;
+  set_bins(s, g->full);
+  GG_HIP(launch_chunk_order(s, g->col, g->seg_z, g->seg_s, g->chunk_scratch, g->chunk_order, g->stream));
+  g->chunk_order_n = nch;
+  return GG_OK;
 }
 
 // Binning of the active rows plus, with segmentation, their segment offsets.
@@ -448,6 +474,8 @@ void free_graph(gg_graph* g) {
   dfree(g->i32_scratch);
   if (g->blk_scratch) (void)hipFree(g->blk_scratch);
   free_bins(g->full);
+  dfree(g->chunk_order);
+  dfree(g->chunk_scratch);
   for (int i = 0; i < 2; ++i) {
     dfree(g->c[i]);
     dfree(g->xu[i]);
@@ -919,6 +947,8 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     s.old_bits = g->bits[r->bcur];
     s.new_bits = g->bits[1 - r->bcur];
     GG_TRY(check_part_capacity(g, g->full));
+    if (g->tune.seg_enable && g->chunk_order_n == g->full.h.chunks && g->full.h.hub > 0)
+      s.chunk_order = g->chunk_order;
     if (g->tune.seg_enable)
       GG_HIP(launch_superstep_flat(app, s, g->stream, pe0, pe1));
     else
