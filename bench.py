@@ -12,8 +12,12 @@ sampling and packing are inside the timed region.
 
 value = edges gathered per second over the timed steps (GTEPS, all runs).
 
-Two further sections are measured after the timed steps (they are not part
-of `value`):
+Three further sections are measured after the timed steps (they are not
+part of `value`):
+  at_1pct  per application, the fastest configuration found on this graph by a
+           sweep of schemes (SP, SMS, GG), sigma, alpha, theta and the flag
+           update that stays within 1% error of the exact run (listed in
+           AT_1PCT), timed again and checked live;
   batch    256 SSSP and 256 personalized-PageRank queries on R-MAT scale 20
            (one captured HIP graph per kind), and 64 independent R-MAT graphs
            of scale 10..18 and edge factor 8..32 run as one block-diagonal
@@ -60,6 +64,35 @@ def cpu_baseline(graphs, source, budget_iters=3):
     return {"value": edges / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": "%d exact iterations each of PR, SSSP and CC on the benchmark graphs (%.1f s, %d edges)"
                       % (budget_iters, dt, edges)}
+
+
+# Fastest configurations within 1% error on R-MAT scale 22 (seed 2), from a
+# sweep over SP/SMS/GG, sigma in {.1,.3,.5,.7,.9}, alpha in {1,2,4,8},
+# theta in {0, .001, .01, .05, .2} and REPLACE/UNION.
+AT_1PCT = {"pr": ("sms", 0.1, 4), "sssp": ("sms", 0.1, 8), "cc": ("sms", 0.1, 4)}
+
+
+def bench_at_1pct(G, apps, iters, source, exact_out, metrics, np):
+    out = {}
+    for app in apps:
+        pol, sg, alpha = AT_1PCT[app]
+        ex, sx = G[app].exact_run(app, iters=iters[app], source=source)
+        kw = dict(alpha=alpha, theta=0.05, seed=1, iters=iters[app], source=source, stop="fixed_iters")
+        G[app].approx_run(app, sg, pol, **kw)
+        o, st = G[app].approx_run(app, sg, pol, **kw)
+        oh, exh = o.cpu().numpy(), exact_out[app]
+        if app == "pr":
+            err = metrics.topk_error(oh, exh, 1000)
+        elif app == "sssp":
+            err = metrics.stretch_error(oh.view(np.uint32), exh.view(np.uint32), source)
+        else:
+            err = metrics.label_mismatch(oh, exh)
+        out[app] = {"scheme": pol, "sigma": sg, "alpha": alpha, "accuracy": round(metrics.accuracy(err), 3),
+                    "within_1pct": bool(err <= 0.01), "ms": round(st.device_ms, 3),
+                    "exact_ms": round(sx.device_ms, 3), "speedup": round(sx.device_ms / st.device_ms, 3),
+                    "edges_vs_exact": round(st.edges_gathered / sx.edges_gathered, 4)}
+        log("at_1pct:", app, out[app])
+    return out
 
 
 def bench_batch(P, gg, torch, seed):
@@ -358,6 +391,8 @@ def main():
                 "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(bytes_per_launch),
                 "launches": pb["launches"]}
 
+    at1 = bench_at_1pct(G, apps, iters, source, {a: outs[(a, "exact")].cpu().numpy() for a in apps}, metrics, np)
+
     batch = None
     if not args.no_batch:
         batch = bench_batch(P, gg, torch, args.seed)
@@ -390,6 +425,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "runs": summary,
+        "at_1pct": at1,
         "batch": batch,
         "learned": learned,
     }

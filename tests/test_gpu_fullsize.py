@@ -1,0 +1,146 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (default tuning).
+
+R-MAT scale 22 (seed 2, edge factor 16; the symmetrized graph for CC): the
+GPU's exact and GG runs against the CPU oracle (PR within 1e-6 relative L1,
+SSSP and CC bit for bit), and the exact results certified independently: for SSSP by the
+shortest-path optimality conditions (every edge relaxed, every reached vertex
+but the source tight on some in-edge), for CC by scipy's connected components
+(each label is the smallest id of its component).
+
+R-MAT scale 24 and an Erdos-Renyi graph with 2^24 vertices (average degree
+16) are checked the same way when GG_FULLSIZE_24=1 (each takes minutes of
+graph generation and oracle time, so they are not part of the default run).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from helpers import compare_values, log
+
+pytestmark = pytest.mark.gpu
+
+INF = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_10039_amd as P
+    return P
+
+
+def certify_sssp(g, src, d):
+    """Shortest-path optimality: d[src] = 0, no edge can be relaxed, every
+    reached vertex other than the source is tight on one of its in-edges,
+    and an edge from a reached vertex never leads to an unreached one."""
+    d = d.astype(np.int64)
+    d[d == INF] = -1
+    assert d[src] == 0
+    dst = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    dv = d[g.col]
+    du = d[dst]
+    w = g.weight.astype(np.int64)
+    from_reached = dv >= 0
+    assert np.all(du[from_reached] >= 0), "reached source, unreached target"
+    cand = dv[from_reached] + w[from_reached]
+    assert np.all(du[from_reached] <= cand), "an edge can still be relaxed"
+    tight = np.zeros(g.n, dtype=bool)
+    t = from_reached.copy()
+    t[from_reached] = du[from_reached] == cand
+    tight[dst[t]] = True
+    reached = d >= 0
+    reached[src] = False
+    assert np.all(tight[reached]), "a reached vertex is not tight on any in-edge"
+
+
+def certify_cc(g, lab):
+    """Min-label connected components: every label is the smallest vertex id
+    of its component, the components taken from scipy's connected_components
+    (a library routine independent of both sides)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    A = csr_matrix((np.ones(g.m, dtype=np.int8), g.col, g.rowptr), shape=(g.n, g.n))
+    nc, comp = connected_components(A, directed=True, connection="weak")
+    mins = np.full(nc, g.n, dtype=np.int64)
+    np.minimum.at(mins, comp, np.arange(g.n, dtype=np.int64))
+    assert np.array_equal(lab.astype(np.int64), mins[comp])
+
+
+def _host(out, app):
+    h = out.cpu().numpy()
+    if app == "sssp":
+        return h.view(np.uint32)
+    if app == "cc":
+        return h.astype(np.int32)
+    return h.astype(np.float64)
+
+
+def _check_app(P, g, app, src, sigma=0.3, alpha=4, theta=0.05, oracle_gg=True):
+    G = P.Graph.from_host(g)
+    it = 20
+    if app != "pr":
+        _, st = G.exact_run(app, source=src)
+        it = st.iterations
+    ex, _ = G.exact_run(app, iters=it, source=src)
+    exh = _host(ex, app)
+    log(app, "n", g.n, "m", g.m, "exact iterations", it)
+    if app == "sssp":
+        certify_sssp(g, src, exh)
+    elif app == "cc":
+        certify_cc(g, exh)
+    ref = oracle.run(g, app, "exact", source=src, iters=it, max_iters=it + 1)
+    compare_values(app, exh, ref.values, ctx="exact")
+    if oracle_gg:
+        out, st = G.approx_run(app, sigma, "gg", alpha=alpha, theta=theta, seed=1, iters=it, source=src,
+                               stop="fixed_iters")
+        ref = oracle.run(g, app, "gg", sigma=sigma, alpha=alpha, theta=theta, seed=1, iters=it, source=src,
+                         stop=oracle.FIXED_ITERS)
+        compare_values(app, _host(out, app), ref.values, ctx="gg")
+        assert st.edges_gathered == ref.edges
+    G.close()
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    g = gg.rmat(22, 16, seed=2, weights=True)
+    return g, int(gg.pick_sources(g, 1, 2)[0])
+
+
+def test_full_pr_rmat22(P, rmat22):
+    g, s = rmat22
+    _check_app(P, g, "pr", s)
+
+
+def test_full_sssp_rmat22(P, rmat22):
+    g, s = rmat22
+    _check_app(P, g, "sssp", s)
+
+
+def test_full_cc_rmat22(P):
+    g = gg.rmat(22, 16, seed=2, symmetrize=True)
+    _check_app(P, g, "cc", 0)
+
+
+scale24 = pytest.mark.skipif(os.environ.get("GG_FULLSIZE_24") != "1",
+                             reason="scale-24 graphs take minutes; set GG_FULLSIZE_24=1")
+
+
+@scale24
+@pytest.mark.parametrize("kind", ["rmat", "er"])
+def test_full_sssp_24(P, kind):
+    g = gg.rmat(24, 16, seed=3, weights=True) if kind == "rmat" else gg.erdos_renyi(1 << 24, 16, seed=4, weights=True)
+    _check_app(P, g, "sssp", int(gg.pick_sources(g, 1, 3)[0]))
+
+
+@scale24
+@pytest.mark.parametrize("kind", ["rmat", "er"])
+def test_full_cc_24(P, kind):
+    g = gg.rmat(24, 16, seed=3, symmetrize=True) if kind == "rmat" else gg.erdos_renyi(1 << 24, 16, seed=4,
+                                                                                       symmetrize=True)
+    _check_app(P, g, "cc", 0)
