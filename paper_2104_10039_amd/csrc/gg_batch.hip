@@ -92,9 +92,14 @@ __device__ __forceinline__ int bfind_hub(const int32_t* hub_start, int n_hub, in
 template <int APP>
 __device__ __forceinline__ void bflush(const BatchSweep& s, int nchanged) {
   if constexpr (APP == kSSSP) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) nchanged += __shfl_xor(nchanged, o, 64);
-    if (__lane_id() == 0 && nchanged) atomicAdd(s.changed, nchanged);
+    // Only whether anything changed is used (the captured loop stops on an
+    // iteration without change): a wave sets the flag only while it still
+    // reads clear, so the flag is written a handful of times per iteration
+    // instead of once per (row, slice).
+    const bool any = __ballot(nchanged != 0) != 0;
+    if (any && __lane_id() == 0 &&
+        __hip_atomic_load(s.changed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      atomicOr(s.changed, 1);
   }
 }
 
@@ -155,7 +160,6 @@ __global__ __launch_bounds__(kBlock) void k_bhub_combine(BatchSweep s) {
   bflush<APP>(s, nchanged);
 }
 
-constexpr int kBDangChunks = 256;
 
 // Per-query dangling mass: chunk c of the dangling list, one wave per
 // (chunk, slice), then a fixed-order sum over chunks.
@@ -167,15 +171,37 @@ __global__ __launch_bounds__(64) void k_bdang_partial(BatchSweep s, const int32_
   const int per = (ndang + kBDangChunks - 1) / kBDangChunks;
   const int lo = c * per, hi = min(ndang, lo + per);
   double acc = 0.0;
-  for (int i = lo; i < hi; ++i) acc += (double)s.c_in[(int64_t)dlist[i] * s.qp + q];
+  int i = lo;
+  // eight list entries and their values in flight, added in list order
+  for (; i + 8 <= hi; i += 8) {
+    int d[8];
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d[k] = dlist[i + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = s.c_in[(int64_t)d[k] * s.qp + q];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += (double)v[k];
+  }
+  for (; i < hi; ++i) acc += (double)s.c_in[(int64_t)dlist[i] * s.qp + q];
   partial[(int64_t)c * s.qp + q] = acc;
 }
 
-__global__ __launch_bounds__(64) void k_bdang_final(BatchSweep s, const double* partial, double* out) {
-  const int q = blockIdx.x * 64 + __lane_id();
+// Sum of the chunk partials of a 64-query slice: wave w adds chunks
+// w, w+16, ... in order, then the 16 wave sums are added in order.
+__global__ __launch_bounds__(1024) void k_bdang_final(BatchSweep s, const double* partial, double* out) {
+  __shared__ double red[16][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int q = blockIdx.x * 64 + l;
   double acc = 0.0;
-  for (int c = 0; c < kBDangChunks; ++c) acc += partial[(int64_t)c * s.qp + q];
-  out[q] = acc;
+  for (int c = w; c < kBDangChunks; c += 16) acc += partial[(int64_t)c * s.qp + q];
+  red[w][l] = acc;
+  __syncthreads();
+  if (w == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[k][l];
+    out[q] = t;
+  }
 }
 
 // Initial values: PPR contributions e_s / outdeg; SSSP distances 0 at the
@@ -223,7 +249,7 @@ hipError_t launch_batch_init(int app, int32_t n, int32_t qp, const int32_t* src,
 hipError_t launch_batch_dangling(const BatchSweep& s, const int32_t* dlist, int32_t ndang, double* partial,
                                  double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_bdang_partial, dim3(kBDangChunks * s.nslice), dim3(64), 0, st, s, dlist, ndang, partial);
-  hipLaunchKernelGGL(k_bdang_final, dim3(s.nslice), dim3(64), 0, st, s, partial, out);
+  hipLaunchKernelGGL(k_bdang_final, dim3(s.nslice), dim3(1024), 0, st, s, partial, out);
   return hipGetLastError();
 }
 

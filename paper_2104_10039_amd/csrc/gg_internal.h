@@ -222,6 +222,9 @@ hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t cou
 hipError_t launch_set_sources(const int32_t* src, int32_t count, uint32_t* x, hipStream_t st);
 
 // ---- multi-query batch (gg_batch.hip) -----------------------------------------
+// Chunks of the dangling list in a batched PPR iteration (partials of
+// kBDangChunks x query slots, added in a fixed order).
+constexpr int kBDangChunks = 1024;
 hipError_t launch_batch_init(int app, int32_t n, int32_t qp, const int32_t* src, const int32_t* outdeg, float* c,
                              uint32_t* x0, uint32_t* x1, hipStream_t st);
 hipError_t launch_batch_dangling(const BatchSweep& s, const int32_t* dlist, int32_t ndang, double* partial,

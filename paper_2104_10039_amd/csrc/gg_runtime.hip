@@ -119,7 +119,7 @@ struct gg_graph {
     int64_t part_cap = 0;  // elements (chunks * qp) of the partial array
     double* part = nullptr;
     int32_t qp_cap = 0;
-    double* dpart = nullptr;  // 256 * qp dangling partials
+    double* dpart = nullptr;  // kBDangChunks * qp dangling partials
     double* dang = nullptr;   // qp
     int32_t* src = nullptr;   // qp
     int32_t* ctr = nullptr;   // [0] changed, [1] done, [2] iterations
@@ -1216,7 +1216,7 @@ int ensure_batch(gg_graph* g, int32_t qp) {
     dfree(B.dang);
     dfree(B.src);
     B.qp_cap = 0;
-    GG_TRY(dalloc(&B.dpart, (size_t)256 * qp));
+    GG_TRY(dalloc(&B.dpart, (size_t)kBDangChunks * qp));
     GG_TRY(dalloc(&B.dang, (size_t)qp));
     GG_TRY(dalloc(&B.src, (size_t)qp));
     B.qp_cap = qp;

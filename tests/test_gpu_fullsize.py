@@ -81,6 +81,23 @@ def _host(out, app):
     return h.astype(np.float64)
 
 
+def _oracle(g, app, policy, **kw):
+    """oracle.run, stepped, with a line per iteration (large graphs take a
+    while per iteration on one CPU core)."""
+    import time
+    t0 = time.perf_counter()
+    r = oracle.Run(g, app, policy, **kw)
+    try:
+        while True:
+            info = r.step()
+            if info is None:
+                break
+            log("  oracle %s %s iteration %d, %.1f s" % (app, policy, info.iter, time.perf_counter() - t0))
+        return oracle.Result(values=r.values(), iterations=r.iterations, edges=r.edges_total)
+    finally:
+        r.close()
+
+
 def _check_app(P, g, app, src, sigma=0.3, alpha=4, theta=0.05, oracle_gg=True):
     G = P.Graph.from_host(g)
     it = 20
@@ -94,13 +111,14 @@ def _check_app(P, g, app, src, sigma=0.3, alpha=4, theta=0.05, oracle_gg=True):
         certify_sssp(g, src, exh)
     elif app == "cc":
         certify_cc(g, exh)
-    ref = oracle.run(g, app, "exact", source=src, iters=it, max_iters=it + 1)
+    log(app, "exact result certified")
+    ref = _oracle(g, app, "exact", source=src, iters=it, max_iters=it + 1)
     compare_values(app, exh, ref.values, ctx="exact")
     if oracle_gg:
         out, st = G.approx_run(app, sigma, "gg", alpha=alpha, theta=theta, seed=1, iters=it, source=src,
                                stop="fixed_iters")
-        ref = oracle.run(g, app, "gg", sigma=sigma, alpha=alpha, theta=theta, seed=1, iters=it, source=src,
-                         stop=oracle.FIXED_ITERS)
+        ref = _oracle(g, app, "gg", sigma=sigma, alpha=alpha, theta=theta, seed=1, iters=it, source=src,
+                      stop=oracle.FIXED_ITERS)
         compare_values(app, _host(out, app), ref.values, ctx="gg")
         assert st.edges_gathered == ref.edges
     G.close()
@@ -134,6 +152,7 @@ scale24 = pytest.mark.skipif(os.environ.get("GG_FULLSIZE_24") != "1",
 @scale24
 @pytest.mark.parametrize("kind", ["rmat", "er"])
 def test_full_sssp_24(P, kind):
+    log("generating", kind, "scale 24")
     g = gg.rmat(24, 16, seed=3, weights=True) if kind == "rmat" else gg.erdos_renyi(1 << 24, 16, seed=4, weights=True)
     _check_app(P, g, "sssp", int(gg.pick_sources(g, 1, 3)[0]))
 
@@ -141,6 +160,7 @@ def test_full_sssp_24(P, kind):
 @scale24
 @pytest.mark.parametrize("kind", ["rmat", "er"])
 def test_full_cc_24(P, kind):
+    log("generating", kind, "scale 24, symmetrized")
     g = gg.rmat(24, 16, seed=3, symmetrize=True) if kind == "rmat" else gg.erdos_renyi(1 << 24, 16, seed=4,
                                                                                        symmetrize=True)
     _check_app(P, g, "cc", 0)
