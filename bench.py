@@ -181,8 +181,11 @@ def bench_learned(P, gg, torch, np, metrics, G22, g22, source22, iters22, alpha,
                "epoch_loss": [round(float(x), 4) for x in losses], "tau": tau, "label_eps": eps,
                "exact": {"ms": round(sx.device_ms, 3), "edges": sx.edges_gathered}}
         kw = dict(alpha=alpha, theta=theta, seed=1, iters=it, source=s23, stop="fixed_iters")
-        for name, pol, extra in (("gg", "gg", {}), ("learned", "learned",
-                                                      dict(mlp=net, tau=tau, rho=0.6, fallback_k=0))):
+        # learned: the network's selection alone (rho = 1); learned_rho0.6: with
+        # the full superstep whenever the selected rows hold > 60% of the edges
+        for name, pol, extra in (("gg", "gg", {}),
+                                 ("learned", "learned", dict(mlp=net, tau=tau, rho=1.0, fallback_k=0)),
+                                 ("learned_rho0.6", "learned", dict(mlp=net, tau=tau, rho=0.6, fallback_k=0))):
             G23.approx_run(app, 0.3, pol, **kw, **extra)  # warm
             o, st = G23.approx_run(app, 0.3, pol, **kw, **extra)
             oh = o.cpu().numpy()

@@ -65,8 +65,9 @@ typedef enum { GG_APP_PR = 0, GG_APP_SSSP = 1, GG_APP_CC = 2, GG_APP_PPR = 3 } g
    scores every vertex; the selected rows S = { v : logit_v > tau } are
    gathered over all in-edges and have their flags re-selected (a partial
    superstep) while every other row takes an approximate iteration. Every
-   fallback_k-th correction step (fallback_k > 0), and every step with
-   |S| > rho * n, is GG's full superstep instead. */
+   fallback_k-th correction step (fallback_k > 0), and every step whose
+   selected rows hold more than rho * m in-edges, is GG's full superstep
+   instead. */
 typedef enum {
   GG_POLICY_EXACT = 0,
   GG_POLICY_SP = 1,
@@ -146,7 +147,7 @@ typedef struct {
   /* LEARNED only (zero otherwise) */
   const gg_mlp* mlp;   /* the scoring network (on the graph's device) */
   float tau;           /* selection threshold on the binary32 logit */
-  double rho;          /* full superstep when |S| > rho * n, rho >= 0 */
+  double rho;          /* full superstep when the rows of S hold > rho * m in-edges, rho >= 0 */
   int32_t fallback_k;  /* every fallback_k-th correction step is full; 0 = never */
   int32_t judge;       /* 1: at full supersteps, score the selection against the drift labels */
   /* GG and LEARNED: optional trace (NULL = none). At every full superstep the
@@ -381,7 +382,8 @@ void gg_mlp_free(gg_mlp* mlp);
 /* Host arrays of GG_MLP_PARAMS binary32 values; set resets Adam's state. */
 int gg_mlp_set_weights(gg_mlp* mlp, const float* params_host);
 int gg_mlp_get_weights(gg_mlp* mlp, float* params_host);
-/* Logits of n samples: feat_dev [n][8] bfloat16 bits, logits_dev float[n]. */
+/* Logits of n samples: feat_dev [n][8] bfloat16 bits (8-byte aligned, else
+   GG_E_INVAL), logits_dev float[n]. */
 int gg_mlp_forward(gg_mlp* mlp, const uint16_t* feat_dev, int64_t n, float* logits_dev);
 /* Gradient of the mean loss over n samples (labels 0/1 as float) into
    grad_dev[0..GG_MLP_PARAMS), and the loss sum into grad_dev[GG_MLP_PARAMS]. */

@@ -46,7 +46,7 @@
  * future work, Sec. 7): a LEARNED policy keeps GG's correction schedule but
  * lets a small MLP pick the rows corrected at each correction step (a
  * partial superstep), with GG's full superstep as fallback every k-th
- * correction step or when the selection exceeds rho * n. Its features, the
+ * correction step or when the selected rows hold more than rho * m in-edges. Its features, the
  * network, the loss and Adam are plain definitions written out below; the
  * drift label of a traced full superstep compares the accurate update with
  * the approximate one the flags alone would have given.
@@ -650,14 +650,18 @@ static void compute_features(ggo_run* r) {
 
 /* Logits of the learned policy (rounding as on the GPU) and the selected set
    S = { v : binary32(logit_v) > tau }. Returns |S|. */
-static int64_t select_rows(ggo_run* r) {
+/* S = { v : logit_v > tau } (binary32 comparison); returns |S| and, in
+   *sel_edges, the number of in-edges of the rows in S. */
+static int64_t select_rows(ggo_run* r, int64_t* sel_edges) {
   ggo_mlp_forward(r->pol.mlp, r->feat, r->g.n, 1, r->logit);
-  int64_t cnt = 0;
+  int64_t cnt = 0, edges = 0;
   for (int32_t u = 0; u < r->g.n; ++u) {
     r->sel[u] = (float)r->logit[u] > (float)r->pol.tau;
     cnt += r->sel[u];
+    if (r->sel[u]) edges += (int64_t)r->g.rowptr[u + 1] - r->g.rowptr[u];
   }
   r->have_sel = 1;
+  *sel_edges = edges;
   return cnt;
 }
 
@@ -718,8 +722,11 @@ int ggo_step(ggo_run* r, ggo_step_info* info) {
       if ((i % (p->alpha + 1)) == 0) {
         const int32_t c = ++r->corrections;
         compute_features(r);
-        selected = select_rows(r);
-        if ((p->fallback_k > 0 && c % p->fallback_k == 0) || (double)selected > p->rho * (double)n)
+        int64_t sel_edges = 0;
+        selected = select_rows(r, &sel_edges);
+        /* fallback: every fallback_k-th correction, and any selection whose
+           rows hold more than rho * m in-edges */
+        if ((p->fallback_k > 0 && c % p->fallback_k == 0) || (double)sel_edges > p->rho * (double)r->g.m)
           kind = GGO_KIND_FULL;
         else
           kind = GGO_KIND_PARTIAL;

@@ -32,7 +32,8 @@ enum { GGO_EXACT = 0, GGO_SP = 1, GGO_SMS = 2, GGO_GG = 3, GGO_LEARNED = 4 };
    over per-vertex features selects the rows S that are corrected (gathered
    over all in-edges, flags re-selected); the other rows take an approximate
    iteration. A full superstep replaces it every fallback_k-th correction
-   step (fallback_k > 0) and whenever |S| > rho * n. */
+   step (fallback_k > 0) and whenever the rows of S hold more than rho * m
+   in-edges (a partial superstep would then cost more than a full one). */
 /* Kind of an executed iteration. */
 enum { GGO_KIND_APPROX = 0, GGO_KIND_ACCURATE = 1, GGO_KIND_FULL = 2, GGO_KIND_PARTIAL = 3 };
 #define GGO_MLP_IN 8
@@ -75,7 +76,7 @@ typedef struct {
   int32_t stop;        /* GGO_STOP_* (SSSP/CC) */
   const double* mlp;   /* LEARNED: GGO_MLP_PARAMS binary32 master values */
   double tau;          /* LEARNED: select v iff binary32(logit_v) > binary32(tau) */
-  double rho;          /* LEARNED: full superstep when |S| > rho * n */
+  double rho;          /* LEARNED: full superstep when the rows of S hold > rho * m in-edges */
   int32_t fallback_k;  /* LEARNED: every k-th correction step is full (0: never) */
   int32_t trace;       /* 1: features and drift labels at every full superstep */
   double label_eps;    /* PR/PPR drift label: relative contribution change */

@@ -260,8 +260,11 @@ struct MlpDev {
   uint16_t* w3b;  // [64]
 };
 
+// With sel: sel[v] = logit > tau, *sel_count += |S| and, with rowptr,
+// *sel_edges += the in-edges of the rows in S.
 hipError_t launch_mlp_forward(const MlpDev& w, const uint16_t* feat, int64_t n, float* logits, uint8_t* sel,
-                              float tau, int32_t* sel_count, hipStream_t st);
+                              float tau, int32_t* sel_count, const int32_t* rowptr, unsigned long long* sel_edges,
+                              hipStream_t st);
 // Partial-sum slots (floats) the gradient launch needs for n samples.
 int64_t mlp_grad_scratch(int64_t n);
 hipError_t launch_mlp_grad(const MlpDev& w, const uint16_t* feat, const float* label, int64_t n, float pos_weight,

@@ -40,6 +40,30 @@ __device__ __forceinline__ short4v pack4(uint16_t a, uint16_t b, uint16_t c, uin
   return v;
 }
 
+// Inference helpers (16x16x32 bf16 MFMA: lane l holds A[l % 16][k in group
+// l / 16] and B[k in group l / 16][l % 16], eight k values per lane).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef unsigned uint4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4v mfma32(bf16x8 a, bf16x8 b, float4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// bf16(relu(a)) | bf16(relu(b)) << 16, round to nearest even (hardware
+// conversion); relu on the bfloat16 bits as a signed 16-bit max with 0.
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
+  const bf16x2 p = __builtin_convertvector((float2v){a, b}, bf16x2);
+  const short2v r = __builtin_elementwise_max(__builtin_bit_cast(short2v, p), (short2v){0, 0});
+  return __builtin_bit_cast(uint32_t, r);
+}
+
+__device__ __forceinline__ bf16x8 bf8(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  return __builtin_bit_cast(bf16x8, (uint4v){a, b, c, d});
+}
+
 // Weights staged in LDS by every block.
 struct SW {
   uint16_t w1[16 * 64];  // [k][j], k >= 8 zero
@@ -140,44 +164,130 @@ __device__ __forceinline__ void forward_tile(const SW& sw, const uint16_t* feat,
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Inference: logits (and selection logit > tau when sel is non-null)
+// Inference: logits (and selection logit > tau when sel is non-null).
+// Computed in transposed form: hidden units are the MFMA rows and the 16
+// samples of a tile its columns, so the D layout of one layer (lane holds
+// units 4g..4g+3 of sample c, g = lane / 16, c = lane % 16) feeds the B
+// operand of the next with no LDS round trip. Layers 2 and 3 use 16x16x32
+// MFMAs whose k slot j of lane group g stands for hidden unit
+//   u(q, g, j) = 32q + 4g + j (j < 4),  32q + 16 + 4g + (j - 4) (j >= 4)
+// in k slice q; A (weights) and B (activations) use the same map, so each
+// dot product is complete. Layer 3 replicates w3 over the 16 A rows. The
+// weights stay in registers for the whole kernel. Each pre-activation is the
+// binary32 product sum plus the bias in binary32, as in the reference
+// definition, so bfloat16 roundings of the activations agree with it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mlp_forward(MlpDev w, const uint16_t* feat, int64_t n, float* logits,
-                                                     uint8_t* sel, float tau, int32_t* sel_count) {
-  __shared__ SW sw;
-  __shared__ uint16_t h1[4][16 * 64];
-  stage_weights(w, sw);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_forward(
+    MlpDev w, const uint16_t* feat, int64_t n, float* logits, uint8_t* sel, float tau, int32_t* sel_count,
+    const int32_t* rowptr, unsigned long long* sel_edges) {
+  // b1, b2 by units: entry 4t+g holds units 16t+4g .. 16t+4g+3
+  __shared__ float4 sb1[16], sb2[16];
+  if (threadIdx.x < 64) {
+    ((float*)sb1)[threadIdx.x] = w.master[kMlpB1 + threadIdx.x];
+    ((float*)sb2)[threadIdx.x] = w.master[kMlpB2 + threadIdx.x];
+  }
   const int wv = threadIdx.x >> 6;
   const int l = __lane_id(), g = l >> 4, c = l & 15;
-  const int64_t ntiles = (n + 15) / 16;
-  int picked = 0;  // selected samples of this lane, over all its tiles
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    Fwd F;
-    forward_tile(sw, feat, n, tile * 16, h1[wv], F);
-    if (c == 0) {
+  auto unit = [&](int q, int j) { return 32 * q + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4)); };
+  auto pair = [](uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); };
+  short4v a1[4];     // [t]: A[row c][k 4g+i] = W1[4g+i][16t+c] (k >= 8 zero)
+  bf16x8 a2[4][2];   // [t][q]: A[row c][slot j] = W2[u(q, g, j)][16t+c]
+  bf16x8 a3[2];      // [q]: A[any row][slot j] = w3[u(q, g, j)]
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t si = tile * 16 + 4 * g + j;
-        if (si < n) {
-          if (logits) logits[si] = F.logit[j];
-          const bool on = F.logit[j] > tau;
-          if (sel) sel[si] = on ? 1 : 0;
-          picked += on;
-        }
-      }
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a1[t][i] = g < 2 ? (short)w.w1b[(4 * g + i) * 64 + 16 * t + c] : (short)0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      uint16_t e[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) e[j] = w.w2b[unit(q, j) * 64 + 16 * t + c];
+      a2[t][q] = bf8(pair(e[0], e[1]), pair(e[2], e[3]), pair(e[4], e[5]), pair(e[6], e[7]));
     }
-    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    uint16_t e[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) e[j] = w.w3b[unit(q, j)];
+    a3[q] = bf8(pair(e[0], e[1]), pair(e[2], e[3]), pair(e[4], e[5]), pair(e[6], e[7]));
+  }
+  const float b3 = w.master[kMlpB3];
+  __syncthreads();
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  // B of layer 1 for a tile: features 4g..4g+3 of sample c (k >= 8 and
+  // samples past n read as zero); kept two tiles ahead of the compute.
+  auto load = [&](int64_t tile) -> uint2 {
+    const int64_t si = tile * 16 + c;
+    uint2 v = make_uint2(0u, 0u);
+    if (tile < ntiles && g < 2 && si < n) v = *(const uint2*)(feat + si * 8 + 4 * g);
+    return v;
+  };
+  int picked = 0;               // selected samples of this lane, over all its tiles
+  unsigned long long pe = 0;    // and their in-edges
+  int64_t tile = (int64_t)blockIdx.x * 4 + wv;
+  uint2 f0 = load(tile), f1 = load(tile + stride);
+  for (; tile < ntiles; tile += stride) {
+    const uint2 v = f0;
+    f0 = f1;
+    f1 = load(tile + 2 * stride);
+    const short4v x = __builtin_bit_cast(short4v, v);
+    // pre-activations: the binary32 product sum, then the bias in binary32
+    float4v d1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float4 bb = sb1[4 * t + g];
+      d1[t] = mfma(a1[t], x, (float4v){0.f, 0.f, 0.f, 0.f}) + (float4v){bb.x, bb.y, bb.z, bb.w};
+    }
+    bf16x8 h1[2];  // [q]: B of layer 2
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      h1[q] = bf8(relu_bf16x2(d1[2 * q][0], d1[2 * q][1]), relu_bf16x2(d1[2 * q][2], d1[2 * q][3]),
+                  relu_bf16x2(d1[2 * q + 1][0], d1[2 * q + 1][1]), relu_bf16x2(d1[2 * q + 1][2], d1[2 * q + 1][3]));
+    float4v d2[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float4 bb = sb2[4 * t + g];
+      d2[t] = mfma32(a2[t][0], h1[0], (float4v){0.f, 0.f, 0.f, 0.f});
+      d2[t] = mfma32(a2[t][1], h1[1], d2[t]) + (float4v){bb.x, bb.y, bb.z, bb.w};
+    }
+    bf16x8 h2[2];  // [q]: B of layer 3
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      h2[q] = bf8(relu_bf16x2(d2[2 * q][0], d2[2 * q][1]), relu_bf16x2(d2[2 * q][2], d2[2 * q][3]),
+                  relu_bf16x2(d2[2 * q + 1][0], d2[2 * q + 1][1]), relu_bf16x2(d2[2 * q + 1][2], d2[2 * q + 1][3]));
+    float4v d3 = mfma32(a3[0], h2[0], (float4v){0.f, 0.f, 0.f, 0.f});
+    d3 = mfma32(a3[1], h2[1], d3);
+    const int64_t si = tile * 16 + c;
+    if (g == 0 && si < n) {
+      const float lg = d3[0] + b3;
+      if (logits) logits[si] = lg;
+      const bool on = lg > tau;
+      if (sel) sel[si] = on ? 1 : 0;
+      picked += on;
+      if (on && rowptr) pe += (unsigned long long)(rowptr[si + 1] - rowptr[si]);
+    }
   }
   if (sel_count) {
-    // one atomic per block
+    // one atomic per block (each)
     __shared__ int wsum[4];
+    __shared__ unsigned long long wes[4];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) picked += __shfl_xor(picked, o, 64);
-    if (l == 0) wsum[wv] = picked;
+    for (int o = 1; o < 64; o <<= 1) {
+      picked += __shfl_xor(picked, o, 64);
+      pe += __shfl_xor(pe, o, 64);
+    }
+    if (l == 0) {
+      wsum[wv] = picked;
+      wes[wv] = pe;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       const int t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
       if (t) atomicAdd(sel_count, t);
+      const unsigned long long te = wes[0] + wes[1] + wes[2] + wes[3];
+      if (te && sel_edges) atomicAdd(sel_edges, te);
     }
   }
 }
@@ -395,12 +505,14 @@ __global__ void k_mlp_sync_bf16(MlpDev w) {
 }
 
 hipError_t launch_mlp_forward(const MlpDev& w, const uint16_t* feat, int64_t n, float* logits, uint8_t* sel, float tau,
-                              int32_t* sel_count, hipStream_t st) {
+                              int32_t* sel_count, const int32_t* rowptr, unsigned long long* sel_edges,
+                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int64_t tiles = (n + 15) / 16;
   int64_t g = (tiles + 3) / 4;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_mlp_forward, dim3((int)g), dim3(256), 0, st, w, feat, n, logits, sel, tau, sel_count);
+  if (g > 1024) g = 1024;  // 4 waves per SIMD, resident at once; each loads the weights once
+  hipLaunchKernelGGL(k_mlp_forward, dim3((int)g), dim3(256), 0, st, w, feat, n, logits, sel, tau, sel_count, rowptr,
+                     sel_edges);
   return hipGetLastError();
 }
 

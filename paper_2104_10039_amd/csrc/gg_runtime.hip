@@ -145,7 +145,7 @@ struct gg_graph {
   float* logits = nullptr;         // n
   uint8_t* labels = nullptr;       // n: drift labels of the last traced / judged superstep
   uint32_t* shadow = nullptr;      // n: approximate update of that superstep
-  int32_t* sel_count = nullptr;    // 1
+  int32_t* sel_count = nullptr;    // 4: |S| (int32), pad, in-edges of S (uint64 at +2)
   unsigned long long* judge = nullptr;  // [0] drifted vertices, [1] of which selected, [2] active edges of S
   int32_t* dummy = nullptr;        // changed-counter sink of the shadow pass
   Bins selb;                       // binning of the selected rows (full rows)
@@ -266,7 +266,7 @@ int ensure_learned(gg_graph* g) {
   GG_TRY(dalloc(&g->logits, n));
   GG_TRY(dalloc(&g->labels, n));
   GG_TRY(dalloc(&g->shadow, n));
-  GG_TRY(dalloc(&g->sel_count, 1));
+  GG_TRY(dalloc(&g->sel_count, 4));
   GG_TRY(dalloc(&g->judge, 3));
   GG_TRY(dalloc(&g->dummy, 1));
   GG_TRY(alloc_bins(g->selb, g->n));
@@ -776,15 +776,21 @@ int learned_select(gg_run* r, int* kind, int64_t* selected) {
   GG_HIP(launch_feat_base(g->n, g->rowptr, g->outdeg, g->act_cnt, g->feat, g->stream));
   r->have_feat = true;
   *kind = GG_STEP_FULL;
-  GG_HIP(launch_fill_u32((uint32_t*)g->sel_count, 1, 0u, g->stream));
-  GG_HIP(launch_mlp_forward(r->pol.mlp->d, g->feat, g->n, g->logits, g->sel, r->pol.tau, g->sel_count, g->stream));
-  int32_t cnt = 0;
-  GG_HIP(hipMemcpyAsync(&cnt, g->sel_count, sizeof(cnt), hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(launch_fill_u32((uint32_t*)g->sel_count, 4, 0u, g->stream));
+  unsigned long long* sel_edges_dev = (unsigned long long*)(g->sel_count + 2);
+  GG_HIP(launch_mlp_forward(r->pol.mlp->d, g->feat, g->n, g->logits, g->sel, r->pol.tau, g->sel_count, g->rowptr,
+                            sel_edges_dev, g->stream));
+  int32_t h[4] = {0, 0, 0, 0};
+  GG_HIP(hipMemcpyAsync(h, g->sel_count, sizeof(h), hipMemcpyDeviceToHost, g->stream));
   GG_HIP(hipStreamSynchronize(g->stream));
+  const int32_t cnt = h[0];
+  unsigned long long sel_edges = 0;
+  memcpy(&sel_edges, h + 2, sizeof(sel_edges));
   r->have_sel = true;
   *selected = cnt;
   r->selected_total += cnt;
-  if (!forced && !((double)cnt > r->pol.rho * (double)g->n)) *kind = GG_STEP_PARTIAL;
+  // fallback when the selected rows hold more than rho * m in-edges
+  if (!forced && !((double)sel_edges > r->pol.rho * (double)g->m)) *kind = GG_STEP_PARTIAL;
   if (*kind == GG_STEP_FULL && r->pol.judge) r->judge_selected += cnt;
   return GG_OK;
 }
@@ -1787,7 +1793,8 @@ int gg_mlp_get_weights(gg_mlp* mlp, float* params_host) {
 int gg_mlp_forward(gg_mlp* mlp, const uint16_t* feat_dev, int64_t n, float* logits_dev) {
   if (!mlp || (n > 0 && (!feat_dev || !logits_dev))) return fail(GG_E_INVAL, "null argument");
   if (n < 0) return fail(GG_E_INVAL, "n < 0");
-  GG_HIP(launch_mlp_forward(mlp->d, feat_dev, n, logits_dev, nullptr, 0.0f, nullptr, mlp->stream));
+  if (((uintptr_t)feat_dev & 7) != 0) return fail(GG_E_INVAL, "feat_dev is not 8-byte aligned");
+  GG_HIP(launch_mlp_forward(mlp->d, feat_dev, n, logits_dev, nullptr, 0.0f, nullptr, nullptr, nullptr, mlp->stream));
   GG_HIP(hipStreamSynchronize(mlp->stream));
   return GG_OK;
 }

@@ -300,10 +300,22 @@ def test_learned_rho_and_empty_selection(P):
     s = int(gg.pick_sources(g, 1, 13)[0])
     kinds, _ = learned_step_compare(P, g, "sssp", mlp_selector_params(1), tau=-1.0, rho=0.5, sample_ratio=0.3,
                                     alpha=2, theta=0.05, seed=14, source=s, iters=9)
-    assert [k for k in kinds if k != "approx"] == ["full"] * 3  # everything selected > rho n
+    assert [k for k in kinds if k != "approx"] == ["full"] * 3  # every edge selected > rho m
     kinds, _ = learned_step_compare(P, g, "sssp", mlp_selector_params(1), tau=1e30, sample_ratio=0.3,
                                     alpha=2, theta=0.05, seed=14, source=s, iters=9)
     assert [k for k in kinds if k != "approx"] == ["partial"] * 3  # nothing selected
+
+
+def test_learned_rho_edge_share(P):
+    """The full-superstep fallback triggers on the in-edge share of the
+    selected rows (in-degree >= 32 here), on both sides alike."""
+    g = gg.rmat(12, 16, seed=24, weights=True)
+    indeg = np.diff(g.rowptr)
+    eshare = indeg[indeg >= 32].sum() / g.m
+    for rho, want in ((eshare - 0.01, "full"), (eshare + 0.01, "partial")):
+        kinds, _ = learned_step_compare(P, g, "sssp", mlp_selector_params(1), tau=5.0, rho=rho, sample_ratio=0.3,
+                                        alpha=2, theta=0.05, seed=4, source=0, iters=6)
+        assert [k for k in kinds if k != "approx"] == [want] * 2
 
 
 @pytest.mark.parametrize("app", ["sssp", "cc"])

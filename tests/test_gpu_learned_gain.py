@@ -71,7 +71,8 @@ def test_learned_gain_over_gg(P, app, eps, tau):
     res = {}
     for name, pol, extra in (("gg4", "gg", dict(alpha=4)), ("gg8", "gg", dict(alpha=8)),
                              ("sp", "sp", dict(alpha=4)),
-                             ("learned", "learned", dict(alpha=4, mlp=net, tau=tau, rho=0.6, fallback_k=0))):
+                             # rho = 1: the network's selection alone, no edge-share fallback
+                             ("learned", "learned", dict(alpha=4, mlp=net, tau=tau, rho=1.0, fallback_k=0))):
         out, st = G.approx_run(app, 0.3, pol, **kw, **extra)
         res[name] = (st.edges_gathered / sx.edges_gathered, _err(app, out, exact), st.device_ms)
         log(app, name, "edges %.3f of exact, error %.4f, %.3f ms" % res[name])

@@ -332,6 +332,29 @@ def test_learned_rho_forces_full():
     assert corr and all(s.kind == oracle.KIND_FULL and s.selected == g.n for s in corr)
 
 
+def _hub_share(g, min_indeg):
+    indeg = np.diff(g.rowptr)
+    sel = indeg >= min_indeg
+    return sel.sum() / g.n, indeg[sel].sum() / g.m
+
+
+def test_learned_rho_is_edge_share():
+    """The fallback compares the in-edges of the selected rows with rho * m.
+    The selector logit = lg(1 + in-degree) > 5 picks the rows of in-degree
+    >= 32: few vertices holding a large share of the edges, so a vertex-share
+    rule would take the opposite decision at both settings below."""
+    g = gg.rmat(12, 16, seed=24, weights=True)
+    vshare, eshare = _hub_share(g, 32)
+    assert vshare < 0.15 and eshare > 0.3
+    kw = dict(sigma=0.3, alpha=2, theta=0.05, seed=4, iters=6, source=0)
+    for rho, want in ((eshare - 0.01, oracle.KIND_FULL), (eshare + 0.01, oracle.KIND_PARTIAL)):
+        steps = oracle.Run(g, "sssp", "learned", mlp=mlp_selector_params(1), tau=5.0, rho=rho,
+                           **kw).run_to_end().steps
+        corr = [s for s in steps if s.iter % 3 == 0]
+        assert corr and all(s.kind == want for s in corr), (rho, [s.kind for s in corr])
+        assert all(s.selected == round(vshare * g.n) for s in corr)
+
+
 def test_learned_partial_rows_match_their_mode():
     """Brute force on a small graph: after a partial superstep every selected
     row holds the value of an accurate update and every other row that of an
