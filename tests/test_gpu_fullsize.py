@@ -10,7 +10,8 @@ but the source tight on some in-edge), for CC by scipy's connected components
 
 R-MAT scale 24 and an Erdos-Renyi graph with 2^24 vertices (average degree
 16) are checked the same way when GG_FULLSIZE_24=1 (each takes minutes of
-graph generation and oracle time, so they are not part of the default run).
+graph generation and oracle time, so they are not part of the default run;
+run them with a per-test time limit of about 15 minutes).
 """
 import os
 
