@@ -45,7 +45,8 @@ typedef enum {
   GG_E_INVAL = -1,       /* null pointer, unknown enum, sigma outside [0,1], theta < 0, alpha < 0, ... */
   GG_E_RANGE = -2,       /* malformed CSR, vertex id out of range, n or m too large, weight outside [0,255] */
   GG_E_NOMEM = -3,       /* device or host allocation failed */
-  GG_E_DEVICE = -4,      /* HIP runtime error; gg_last_error() holds its text */
+  GG_E_DEVICE = -4,      /* HIP runtime error, or a device-side wait of a superstep that gave up
+                            (the results since the last check are undefined); gg_last_error() holds its text */
   GG_E_UNSUPPORTED = -5, /* valid request that this build does not implement */
   GG_E_STATE = -6        /* call not valid in the current state of the handle */
 } gg_status;
@@ -196,6 +197,10 @@ const char* gg_last_error(void);
  * packed (weight << 24 | source) edge array. Host inputs are copied to device
  * memory; device inputs (GG_CSR_DEVICE_PTRS) are borrowed. The structure is
  * validated unless GG_CSR_SKIP_VALIDATE is set (GG_E_RANGE on failure).
+ * Validation also notes whether every row lists its sources in ascending
+ * order; if one does not, source segmentation stays off for this graph
+ * (gg_tuning.seg_enable reads 0 and setting it has no effect). With
+ * GG_CSR_SKIP_VALIDATE the rows are taken to be in ascending order.
  * hip_stream: a hipStream_t or NULL. On success *out owns a new handle.
  */
 int gg_graph_load_csr(const gg_csr_desc* desc, void* hip_stream, gg_graph** out);

@@ -9,6 +9,8 @@ namespace ggk {
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kBlock = 256;  // threads per workgroup of every sweep kernel
+constexpr int kHubPre = 8;   // 256-edge steps of a hub chunk whose loads are issued together
+constexpr int kHubSpinLimit = 1 << 20;  // polls before a single-pass hub chunk gives up waiting
 
 enum App : int { kPR = 0, kSSSP = 1, kCC = 2, kPPR = 3 };
 
@@ -85,6 +87,11 @@ struct Sweep {
   uint32_t* seg_part_u;
   int32_t flat_list;  // flat superstep: short rows from list[0, n_small) instead of every vertex
   const int32_t* chunk_order;  // superstep hub chunks in source-segment order (null: natural order)
+  // single-pass hub chunks of the flat superstep (null: two-pass), 3 *
+  // n_chunks + 2 words: [0] error word (a wait hit its spin limit), [1]
+  // ticket counter, [2, 2 + 2 n_chunks) chunk totals (64-bit), then the
+  // chunk counts (count + 1)
+  uint32_t* hub_sync;
 };
 
 // Segmented gather constants.
@@ -127,6 +134,9 @@ hipError_t launch_iota(int32_t* p, int32_t n, hipStream_t st);
 hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t count, hipStream_t st);
 hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, const int32_t* w, int32_t n, int64_t m,
                            int32_t* flags, hipStream_t st);
+// flags |= 16 when some row lists its sources out of ascending order (rowptr
+// must be valid).
+hipError_t launch_rows_sorted(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t* flags, hipStream_t st);
 
 // Dangling list of the graph (vertices without out-edges), in vertex order.
 hipError_t launch_dangling_list(const int32_t* outdeg, int32_t n, int32_t* list, int32_t* count,
@@ -160,10 +170,10 @@ hipError_t launch_superstep(int app, int team, const Sweep& s, hipStream_t st, h
                             hipEvent_t ev1 = nullptr);
 // Superstep with flattened batches for rows of degree <= wave_max (owner
 // threads walk each row in CSR order) and the chunked path for longer rows.
-// Order of the hub chunks of s's bins by the source segment (width z) of
-// their first edge; scratch holds nseg + n_chunks ints, order n_chunks.
-hipError_t launch_chunk_order(const Sweep& s, const int32_t* col, int32_t z, int32_t nseg, int32_t* scratch,
-                              int32_t* order, hipStream_t st);
+// Source segment (width z, nseg segments) of the first edge of each hub
+// chunk of s's bins: seg_of[0, n_chunks).
+hipError_t launch_chunk_seg(const Sweep& s, const int32_t* col, int32_t z, int32_t nseg, int32_t* seg_of,
+                            hipStream_t st);
 hipError_t launch_superstep_flat(int app, const Sweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
                                  hipEvent_t ev1 = nullptr);
 // Pack the active edges selected by s.old_bits (used after the initial sampling).

@@ -442,6 +442,61 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
   }
 }
 
+// One 256-edge step of a hub chunk in a superstep: edge b + k (k = sub + thread)
+// with gathered value v, the row prefix before the step in carry (advanced by
+// the step's total). Writes the new flag bits and returns this thread's flag.
+template <int APP>
+__device__ __forceinline__ bool hub_step(const Sweep& s, int b, int sub, int e1, typename Tr<APP>::T v,
+                                         typename Tr<APP>::T& carry, typename Tr<APP>::T* lds) {
+  using R = Tr<APP>;
+  using T = typename R::T;
+  const int lane = __lane_id();
+  const int wid = threadIdx.x >> 6;
+  const int k = sub + (int)threadIdx.x;
+  const bool valid = k < e1;
+  const int e = b + k;
+  const uint32_t oldf = (valid && s.old_bits) ? edge_bit(s.old_bits, e) : 0u;
+  bool flag;
+  T sub_total;
+  if constexpr (APP == kPR || APP == kPPR) {
+    const double c = v;
+    const double incl_w = team_scan_add<64>(c, lane);
+    if (lane == 63) lds[wid] = incl_w;
+    __syncthreads();
+    double before = 0.0;
+    for (int w = 0; w < wid; ++w) before += lds[w];
+    sub_total = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    __syncthreads();
+    const double P = carry + (before + incl_w);
+    flag = Decide<kPR>::f(s, valid, c, P, oldf);
+  } else {
+    const uint32_t val = v;  // SSSP: INF exactly when the source is unreached
+    const uint32_t incl_w = team_scan_min<64>(val, lane);
+    uint32_t excl_w = (uint32_t)__shfl_up((int)incl_w, 1, 64);
+    if (lane == 0) excl_w = kInf;
+    if (lane == 63) lds[wid] = incl_w;
+    __syncthreads();
+    uint32_t before = kInf;
+    for (int w = 0; w < wid; ++w) before = min(before, lds[w]);
+    sub_total = min(min(lds[0], lds[1]), min(lds[2], lds[3]));
+    __syncthreads();
+    const uint32_t rp = min(carry, min(before, excl_w));
+    if constexpr (APP == kSSSP) {
+      const uint32_t nw = min(rp, val);
+      const bool dec = (rp == kInf) || ((((uint64_t)(rp - nw)) << 16) > s.theta_q * (uint64_t)rp);
+      if (valid && val != kInf) flag = dec || (s.mask_union && oldf);
+      else flag = oldf != 0u;
+    } else {
+      flag = (valid && val < rp) || (s.mask_union && oldf);
+    }
+  }
+  flag = flag && valid;
+  const uint64_t bal = __ballot(flag);
+  write_bits<64>(s.new_bits, bal, lane, e, e1 - (sub + wid * 64) - lane, valid);
+  carry = R::op(carry, sub_total);
+  return flag;
+}
+
 // Hub chunk of a superstep: prefix carried from the chunk totals computed
 // beforehand (part_f / part_u), flags and bits for the chunk, active count
 // to part_cnt[ch]. Chunk 0 applies the row with the total of all chunks.
@@ -459,8 +514,6 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
   const int len = s.rowptr[u + 1] - b;
   const int e0 = j * s.hub_chunk;
   const int e1 = min(len, e0 + s.hub_chunk);
-  const int lane = __lane_id();
-  const int wid = threadIdx.x >> 6;
 
   auto part = [&](int i) -> T {
     if constexpr (APP == kPR || APP == kPPR) return s.part_f[i];
@@ -469,74 +522,32 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
   T carry = R::id();
   for (int i = 0; i < j; ++i) carry = R::op(carry, part(c0 + i));
   int cnt = 0;
-  // The edge words and gathered values of kPre consecutive 256-edge steps are
-  // loaded before the first step's scan, so one round trip to memory serves
-  // the whole group.
-  constexpr int kPre = 8;
-  for (int g0 = e0; g0 < e1; g0 += kPre * kBlock) {
-  uint32_t evq[kPre];
-  T vq[kPre];
+  // The edge words and gathered values of kHubPre consecutive 256-edge steps
+  // are loaded before the first step's scan, so one round trip to memory
+  // serves the whole group.
+  for (int g0 = e0; g0 < e1; g0 += kHubPre * kBlock) {
+  uint32_t evq[kHubPre];
+  T vq[kHubPre];
 #pragma unroll
-  for (int q = 0; q < kPre; ++q) {
+  for (int q = 0; q < kHubPre; ++q) {
     const int k = g0 + q * kBlock + (int)threadIdx.x;
     evq[q] = k < e1 ? ld_stream(s.edges + b + k) : 0u;
   }
 #pragma unroll
-  for (int q = 0; q < kPre; ++q) {
+  for (int q = 0; q < kHubPre; ++q) {
     const int k = g0 + q * kBlock + (int)threadIdx.x;
     vq[q] = k < e1 ? R::elem(s, evq[q]) : R::id();
   }
 #pragma unroll
-  for (int q = 0; q < kPre; ++q) {
+  for (int q = 0; q < kHubPre; ++q) {
     const int sub = g0 + q * kBlock;
     if (sub >= e1) break;  // uniform over the block
-    const int k = sub + (int)threadIdx.x;
-    const bool valid = k < e1;
-    const int e = b + k;
-    const uint32_t oldf = (valid && s.old_bits) ? edge_bit(s.old_bits, e) : 0u;
-    bool flag;
-    T sub_total;
-    if constexpr (APP == kPR || APP == kPPR) {
-      const double c = vq[q];
-      const double incl_w = team_scan_add<64>(c, lane);
-      if (lane == 63) lds[wid] = incl_w;
-      __syncthreads();
-      double before = 0.0;
-      for (int w = 0; w < wid; ++w) before += lds[w];
-      sub_total = (lds[0] + lds[1]) + (lds[2] + lds[3]);
-      __syncthreads();
-      const double P = carry + (before + incl_w);
-      flag = Decide<kPR>::f(s, valid, c, P, oldf);
-    } else {
-      const uint32_t val = vq[q];  // SSSP: INF exactly when the source is unreached
-      const uint32_t incl_w = team_scan_min<64>(val, lane);
-      uint32_t excl_w = (uint32_t)__shfl_up((int)incl_w, 1, 64);
-      if (lane == 0) excl_w = kInf;
-      if (lane == 63) lds[wid] = incl_w;
-      __syncthreads();
-      uint32_t before = kInf;
-      for (int w = 0; w < wid; ++w) before = min(before, lds[w]);
-      sub_total = min(min(lds[0], lds[1]), min(lds[2], lds[3]));
-      __syncthreads();
-      const uint32_t rp = min(carry, min(before, excl_w));
-      if constexpr (APP == kSSSP) {
-        const uint32_t nw = min(rp, val);
-        const bool dec = (rp == kInf) || ((((uint64_t)(rp - nw)) << 16) > s.theta_q * (uint64_t)rp);
-        if (valid && val != kInf) flag = dec || (s.mask_union && oldf);
-        else flag = oldf != 0u;
-      } else {
-        flag = (valid && val < rp) || (s.mask_union && oldf);
-      }
-    }
-    flag = flag && valid;
-    const uint64_t bal = __ballot(flag);
-    write_bits<64>(s.new_bits, bal, lane, e, e1 - (sub + wid * 64) - lane, valid);
-    cnt += __popcll(bal);
-    carry = R::op(carry, sub_total);
+    const bool flag = hub_step<APP>(s, b, sub, e1, vq[q], carry, lds);
+    cnt += __popcll(__ballot(flag));
   }
   }
   // cnt is per wave; sum over the block
-  const int tot = block_sum_int((lane == 0) ? cnt : 0, ilds);
+  const int tot = block_sum_int((__lane_id() == 0) ? cnt : 0, ilds);
   if (threadIdx.x == 0) {
     s.part_cnt[ch] = tot;
     if (j == 0) {
@@ -544,6 +555,142 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
       for (int i = 0; i < nch; ++i) all = R::op(all, part(c0 + i));
       apply<APP>(s, u, all, nchanged);
     }
+  }
+}
+
+// Chunk totals of the single-pass hub path travel in one 64-bit word that is
+// zero until written: PR/PPR the complemented bits of the binary64 total (a
+// finite total never complements to zero), SSSP/CC (1 << 32) | minimum.
+// Counts travel as count + 1 in a 32-bit word. Both are written and polled
+// with relaxed device-scope atomics, which stay coherent across the dies
+// without the cache-wide writeback or invalidation that release / acquire
+// ordering would cost on every poll.
+template <int APP>
+__device__ __forceinline__ uint64_t pack_total(typename Tr<APP>::T v) {
+  if constexpr (APP == kPR || APP == kPPR) return ~(uint64_t)__double_as_longlong(v);
+  else return (1ull << 32) | (uint64_t)v;
+}
+template <int APP>
+__device__ __forceinline__ typename Tr<APP>::T unpack_total(uint64_t w) {
+  if constexpr (APP == kPR || APP == kPPR) return __longlong_as_double((long long)~w);
+  else return (uint32_t)w;
+}
+
+// Poll a word until it is non-zero. Past the spin limit the wait gives up and
+// raises the error word err, which the host reports; the kernel still ends.
+template <typename W>
+__device__ __forceinline__ W wait_word(W* p, uint32_t* err) {
+  W v;
+  for (int it = 0; (v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0; ++it) {
+    if (it >= kHubSpinLimit) {
+      atomicOr(err, 1u);
+      return v;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return v;
+}
+
+// Hub chunk of a superstep in a single pass (hub_chunk <= kHubPre * kBlock).
+// Blocks take tickets in dispatch order and process the chunk at that position
+// of chunk_order (the natural order when null); the order keeps the chunks of
+// a row in row order. A chunk gathers its edges once, publishes its total,
+// and takes its row prefix from the totals of the row's earlier chunks,
+// summed in a fixed tree order. After its flags it publishes its active
+// count, and writes its active edges at the offset that the earlier chunks'
+// counts give. The row's last chunk applies the row and writes its active
+// count. A chunk waits only on chunks with smaller tickets, whose blocks are
+// already resident and publish before they wait, so every wait ends.
+template <int APP>
+__device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, typename Tr<APP>::T* lds, int* ilds) {
+  using R = Tr<APP>;
+  using T = typename R::T;
+  __shared__ int s_ch, s_cbase;
+  __shared__ T s_carry;
+  __shared__ int s_cnt[kHubPre][4];
+  uint32_t* const err = s.hub_sync;
+  uint64_t* const tot_w = (uint64_t*)(s.hub_sync + 2);             // [nchunks]
+  uint32_t* const cnt_w = s.hub_sync + 2 + 2 * (int64_t)nchunks;   // [nchunks]
+  const int lane = __lane_id();
+  const int wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) {
+    const int t = atomicAdd((int*)(s.hub_sync + 1), 1);
+    s_ch = s.chunk_order ? s.chunk_order[t] : t;
+  }
+  __syncthreads();
+  const int ch = s_ch;
+  const int h = find_hub(s.hub_start, s.n_hub, ch);
+  const int u = s.list[s.n_small + s.n_wave + h];
+  const int c0 = s.hub_start[h];
+  const int j = ch - c0;
+  const int nch = s.hub_start[h + 1] - c0;
+  const int b = s.rowptr[u];
+  const int len = s.rowptr[u + 1] - b;
+  const int e0 = j * s.hub_chunk;
+  const int e1 = min(len, e0 + s.hub_chunk);
+  // gather: every edge of the chunk, all loads in flight together
+  uint32_t evq[kHubPre];
+  T vq[kHubPre];
+#pragma unroll
+  for (int q = 0; q < kHubPre; ++q) {
+    const int k = e0 + q * kBlock + (int)threadIdx.x;
+    evq[q] = k < e1 ? ld_stream(s.edges + b + k) : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < kHubPre; ++q) {
+    const int k = e0 + q * kBlock + (int)threadIdx.x;
+    vq[q] = k < e1 ? R::elem(s, evq[q]) : R::id();
+  }
+  T acc = R::id();
+#pragma unroll
+  for (int q = 0; q < kHubPre; ++q) acc = R::op(acc, vq[q]);
+  acc = block_reduce<APP>(acc, lds);
+  if (threadIdx.x == 0) __hip_atomic_store(tot_w + ch, pack_total<APP>(acc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // row prefix: totals of chunks c0 .. ch-1, lane i takes i, i + 64, ...
+  if (wid == 0) {
+    T p = R::id();
+    for (int i = lane; i < j; i += 64) p = R::op(p, unpack_total<APP>(wait_word(tot_w + c0 + i, err)));
+    p = team_reduce<64>(p);
+    if (lane == 0) s_carry = p;
+  }
+  __syncthreads();
+  const T carry0 = s_carry;
+  T carry = carry0;
+  bool fq[kHubPre];
+#pragma unroll
+  for (int q = 0; q < kHubPre; ++q) {
+    const int sub = e0 + q * kBlock;
+    fq[q] = false;
+    if (sub < e1) fq[q] = hub_step<APP>(s, b, sub, e1, vq[q], carry, lds);  // uniform over the block
+    const int c = __popcll(__ballot(fq[q]));
+    if (lane == 0) s_cnt[q][wid] = c;
+  }
+  __syncthreads();
+  int ctot = 0;
+#pragma unroll
+  for (int q = 0; q < kHubPre; ++q) ctot += (s_cnt[q][0] + s_cnt[q][1]) + (s_cnt[q][2] + s_cnt[q][3]);
+  if (threadIdx.x == 0) __hip_atomic_store(cnt_w + ch, (uint32_t)ctot + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // offset of the chunk's active edges in the row
+  if (wid == 0) {
+    int cb = 0;
+    for (int i = lane; i < j; i += 64) cb += (int)wait_word(cnt_w + c0 + i, err) - 1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cb += __shfl_xor(cb, o, 64);
+    if (lane == 0) s_cbase = cb;
+  }
+  __syncthreads();
+  int off = s_cbase;
+#pragma unroll
+  for (int q = 0; q < kHubPre; ++q) {
+    int before = 0;
+    for (int w = 0; w < wid; ++w) before += s_cnt[q][w];
+    const uint64_t bal = __ballot(fq[q]);
+    if (fq[q]) s.act_edges[b + off + before + __popcll(bal & ((1ull << lane) - 1ull))] = evq[q];
+    off += (s_cnt[q][0] + s_cnt[q][1]) + (s_cnt[q][2] + s_cnt[q][3]);
+  }
+  if (j == nch - 1 && threadIdx.x == 0) {
+    apply<APP>(s, u, R::op(carry0, acc), nchanged);
+    s.act_cnt[u] = s_cbase + ctot;
   }
 }
 
@@ -1167,6 +1314,20 @@ __global__ void k_validate(const int32_t* rowptr, const int32_t* col, const int3
   if (f) atomicOr(flags, f);
 }
 
+// Bit 4: some row lists its sources out of ascending order. One wavefront
+// per row (rowptr already checked).
+__global__ void k_rows_sorted(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t* flags) {
+  const int lane = __lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  bool bad = false;
+  for (int64_t u = wave; u < n; u += nwaves) {
+    const int b = rowptr[u], e = rowptr[u + 1];
+    for (int k = b + 1 + lane; k < e; k += 64) bad |= col[k] < col[k - 1];
+  }
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(flags, 16);
+}
+
 hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, const int32_t* w, int32_t n, int64_t m,
                            int32_t* flags, hipStream_t st) {
   hipError_t e = launch_fill_u32((uint32_t*)flags, 1, 0u, st);
@@ -1174,6 +1335,13 @@ hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, const int3
   const int64_t work = m > n ? m : n;
   hipLaunchKernelGGL(k_validate, dim3(grid_for(work + 1, kBlock * 8, 1 << 16)), dim3(kBlock), 0, st, rowptr, col, w,
                      n, m, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_sorted(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t* flags, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_sorted, dim3(grid_for((int64_t)n * 64, kBlock, 1 << 14)), dim3(kBlock), 0, st, rowptr,
+                     col, n, flags);
   return hipGetLastError();
 }
 
@@ -1870,7 +2038,8 @@ __global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int
   __shared__ int s_scan[kBlock + 1];
   int nchanged = 0;
   if ((int)blockIdx.x < nchunks) {
-    super_hub_chunk<APP>(s, s.chunk_order ? s.chunk_order[blockIdx.x] : (int)blockIdx.x, nchanged, lds, ilds);
+    if (s.hub_sync) super_hub_chunk_1p<APP>(s, nchunks, nchanged, lds, ilds);
+    else super_hub_chunk<APP>(s, s.chunk_order ? s.chunk_order[blockIdx.x] : (int)blockIdx.x, nchanged, lds, ilds);
     flush_changed<APP>(s, nchanged, ilds);
     return;
   }
@@ -1994,62 +2163,50 @@ __global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int
   flush_changed<APP>(s, nchanged, ilds);
 }
 
+// With s.hub_sync (and hub_chunk <= kHubPre * kBlock) the hub chunks run in a
+// single pass inside k_super_flat; otherwise chunk totals come from
+// k_hub_totals before it and k_hub_pack writes the hub rows' active edges
+// after it. hub_sync[1 .. 2 + 3 * nchunks) (ticket, chunk totals and counts)
+// is cleared here.
 template <int APP>
-static hipError_t super_flat_t(const Sweep& s, int nchunks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (nchunks > 0) hipLaunchKernelGGL((k_hub_totals<APP>), dim3(nchunks), dim3(kBlock), 0, st, s);
+static hipError_t super_flat_t(Sweep s, int nchunks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const bool one_pass = s.hub_sync && nchunks > 0 && s.hub_chunk <= kHubPre * kBlock;
+  if (!one_pass) s.hub_sync = nullptr;
+  if (one_pass) {
+    const hipError_t e = launch_fill_u32(s.hub_sync + 1, 3 * (int64_t)nchunks + 1, 0u, st);
+    if (e != hipSuccess) return e;
+  } else if (nchunks > 0) {
+    hipLaunchKernelGGL((k_hub_totals<APP>), dim3(nchunks), dim3(kBlock), 0, st, s);
+  }
   const int gs = ((s.flat_list ? s.n_small : s.n) + kBlock - 1) / kBlock;
   const int gw = s.n_wave > 0 ? grid_for(s.n_wave, kBlock / 64, kTeamBlockCap) : 0;
   const int total = nchunks + gw + gs;
   if (ev0) (void)hipEventRecord(ev0, st);
   if (total > 0) hipLaunchKernelGGL((k_super_flat<APP>), dim3(total), dim3(kBlock), 0, st, s, nchunks, gw);
   if (ev1) (void)hipEventRecord(ev1, st);
-  if (nchunks > 0) hipLaunchKernelGGL(k_hub_pack, dim3(nchunks), dim3(kBlock), 0, st, s, (const uint32_t*)s.new_bits);
+  if (nchunks > 0 && !one_pass)
+    hipLaunchKernelGGL(k_hub_pack, dim3(nchunks), dim3(kBlock), 0, st, s, (const uint32_t*)s.new_bits);
   return hipGetLastError();
 }
 
-// Hub chunks ordered by the source segment of their first edge (rows are
-// sorted by source, so a chunk of a long row spans a narrow source range):
-// blocks dispatched together then gather from one window of the value array.
-__global__ void k_chunk_seg(Sweep s, const int32_t* col, int32_t z, int32_t nseg, int32_t* seg_of, int32_t* hist) {
+// Source segment of the first edge of every hub chunk (rows are sorted by
+// source, so a chunk of a long row spans a narrow source range). The host
+// orders the chunks by it, stably, for the superstep.
+__global__ void k_chunk_seg(Sweep s, const int32_t* col, int32_t z, int32_t nseg, int32_t* seg_of) {
   for (int ch = blockIdx.x * blockDim.x + threadIdx.x; ch < s.n_chunks; ch += gridDim.x * blockDim.x) {
     const int h = find_hub(s.hub_start, s.n_hub, ch);
     const int u = s.list[s.n_small + s.n_wave + h];
     const int j = ch - s.hub_start[h];
     const int64_t e = (int64_t)s.rowptr[u] + (int64_t)j * s.hub_chunk;
-    const int sg = min(col[e] / z, nseg - 1);
-    seg_of[ch] = sg;
-    atomicAdd(&hist[sg], 1);
+    seg_of[ch] = min(col[e] / z, nseg - 1);
   }
 }
 
-__global__ void k_chunk_cursor(int32_t* hist, int32_t nseg) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int run = 0;
-    for (int i = 0; i < nseg; ++i) {
-      const int c = hist[i];
-      hist[i] = run;
-      run += c;
-    }
-  }
-}
-
-__global__ void k_chunk_scatter(int32_t n_chunks, const int32_t* seg_of, int32_t* cursor, int32_t* order) {
-  for (int ch = blockIdx.x * blockDim.x + threadIdx.x; ch < n_chunks; ch += gridDim.x * blockDim.x)
-    order[atomicAdd(&cursor[seg_of[ch]], 1)] = ch;
-}
-
-hipError_t launch_chunk_order(const Sweep& s, const int32_t* col, int32_t z, int32_t nseg, int32_t* scratch,
-                              int32_t* order, hipStream_t st) {
+hipError_t launch_chunk_seg(const Sweep& s, const int32_t* col, int32_t z, int32_t nseg, int32_t* seg_of,
+                            hipStream_t st) {
   if (s.n_chunks <= 0) return hipSuccess;
-  int32_t* hist = scratch;
-  int32_t* seg_of = scratch + nseg;
-  hipError_t e = launch_fill_u32((uint32_t*)hist, nseg, 0u, st);
-  if (e != hipSuccess) return e;
-  const int g = grid_for(s.n_chunks, kBlock, 4096);
-  hipLaunchKernelGGL(k_chunk_seg, dim3(g), dim3(kBlock), 0, st, s, col, z, nseg, seg_of, hist);
-  hipLaunchKernelGGL(k_chunk_cursor, dim3(1), dim3(64), 0, st, hist, nseg);
-  hipLaunchKernelGGL(k_chunk_scatter, dim3(g), dim3(kBlock), 0, st, s.n_chunks, (const int32_t*)seg_of, hist,
-                     order);
+  hipLaunchKernelGGL(k_chunk_seg, dim3(grid_for(s.n_chunks, kBlock, 4096)), dim3(kBlock), 0, st, s, col, z, nseg,
+                     seg_of);
   return hipGetLastError();
 }
 

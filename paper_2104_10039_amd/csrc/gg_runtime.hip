@@ -90,6 +90,7 @@ struct gg_graph {
   int32_t* i32_scratch = nullptr;  // small device scalars: [0] dangling count, [1] validate flags
   void* blk_scratch = nullptr;
   gg_tuning tune{32, 4, 512, 2048, 1, 0, 1, 16};
+  bool rows_sorted = true;  // every row lists its sources in ascending order (else no segmentation)
   // frontier (SSSP / CC): out-CSR structure and lists, built on first use
   bool out_built = false;
   int32_t* orow = nullptr;
@@ -161,6 +162,7 @@ struct gg_graph {
   double* part_f = nullptr;
   uint32_t* part_u = nullptr;
   int32_t* part_cnt = nullptr;
+  uint32_t* hub_sync = nullptr;  // 3 * part_cap + 2: single-pass hub chunk sync (Sweep::hub_sync)
   int64_t part_cap = 0;
   double* dpartial = nullptr;  // 256 dangling partials + [256] = D
   int32_t* changed = nullptr;
@@ -371,7 +373,7 @@ int rebin_full(gg_graph* g) {
     dfree(g->chunk_scratch);
     g->chunk_cap = 0;
     GG_TRY(dalloc(&g->chunk_order, (size_t)nch));
-    GG_TRY(dalloc(&g->chunk_scratch, (size_t)nch + (size_t)g->seg_s));
+    GG_TRY(dalloc(&g->chunk_scratch, (size_t)nch));
     g->chunk_cap = nch;
   }
   Sweep s;
@@ -380,7 +382,22 @@ int rebin_full(gg_graph* g) {
   s.rowptr = g->rowptr;
   s.hub_chunk = g->tune.hub_chunk;
   set_bins(s, g->full);
-  GG_HIP(launch_chunk_order(s, g->col, g->seg_z, g->seg_s, g->chunk_scratch, g->chunk_order, g->stream));
+  GG_HIP(launch_chunk_seg(s, g->col, g->seg_z, g->seg_s, g->chunk_scratch, g->stream));
+  // stable counting sort by segment: the chunks of a row keep their order,
+  // which the single-pass superstep relies on
+  std::vector<int32_t> seg_of((size_t)nch), order((size_t)nch), cursor((size_t)g->seg_s + 1, 0);
+  GG_HIP(hipMemcpyAsync(seg_of.data(), g->chunk_scratch, sizeof(int32_t) * (size_t)nch, hipMemcpyDeviceToHost,
+                        g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  for (int32_t c = 0; c < nch; ++c) {
+    if (seg_of[c] < 0 || seg_of[c] >= g->seg_s) return fail(GG_E_DEVICE, "hub chunk segment out of range");
+    cursor[(size_t)seg_of[c] + 1]++;
+  }
+  for (int32_t k = 0; k < g->seg_s; ++k) cursor[(size_t)k + 1] += cursor[(size_t)k];
+  for (int32_t c = 0; c < nch; ++c) order[(size_t)cursor[(size_t)seg_of[c]]++] = c;
+  GG_HIP(hipMemcpyAsync(g->chunk_order, order.data(), sizeof(int32_t) * (size_t)nch, hipMemcpyHostToDevice,
+                        g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
   g->chunk_order_n = nch;
   return GG_OK;
 }
@@ -431,10 +448,13 @@ int ensure_parts(gg_graph* g) {
   dfree(g->part_f);
   dfree(g->part_u);
   dfree(g->part_cnt);
+  dfree(g->hub_sync);
   g->part_cap = 0;
   GG_TRY(dalloc(&g->part_f, (size_t)need));
   GG_TRY(dalloc(&g->part_u, (size_t)need));
   GG_TRY(dalloc(&g->part_cnt, (size_t)need));
+  GG_TRY(dalloc(&g->hub_sync, 3 * (size_t)need + 2));
+  GG_HIP(launch_fill_u32(g->hub_sync, 3 * need + 2, 0u, g->stream));
   g->part_cap = need;
   return GG_OK;
 }
@@ -488,6 +508,7 @@ void free_graph(gg_graph* g) {
   dfree(g->part_f);
   dfree(g->part_u);
   dfree(g->part_cnt);
+  dfree(g->hub_sync);
   dfree(g->dpartial);
   dfree(g->changed);
   dfree(g->seg_off_full);
@@ -623,6 +644,7 @@ Sweep base_sweep(const gg_graph* g, const gg_run* r) {
   s.part_f = g->part_f;
   s.part_u = g->part_u;
   s.part_cnt = g->part_cnt;
+  s.hub_sync = g->hub_sync;
   s.theta = r->pol.theta;
   s.theta_q = (uint64_t)std::floor(r->pol.theta * 65536.0 + 0.5);
   s.mask_union = r->pol.mask_update == GG_MASK_UNION;
@@ -1118,9 +1140,22 @@ int pr_initial_x(gg_run* r) {
   return GG_OK;
 }
 
+// Error word of the single-pass hub chunks: a wait that reached its spin
+// limit leaves the results of that superstep undefined.
+int check_hub_sync(gg_graph* g) {
+  if (!g->hub_sync) return GG_OK;
+  uint32_t e = 0;
+  GG_HIP(hipMemcpyAsync(&e, g->hub_sync, sizeof(e), hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  if (e == 0) return GG_OK;
+  GG_HIP(launch_fill_u32(g->hub_sync, 1, 0u, g->stream));
+  return fail(GG_E_DEVICE, "a superstep hub chunk gave up waiting for its row prefix");
+}
+
 int run_values(gg_run* r, void* out, uint32_t flags) {
   gg_graph* g = r->g;
   if (!out) return fail(GG_E_INVAL, "null output");
+  GG_TRY(check_hub_sync(g));
   if (is_pr(r->p.app)) {
     if (r->iter == 0) GG_TRY(pr_initial_x(r));
     if (!r->x_valid) return fail(GG_E_STATE, "PR values of this iteration were not materialized");
@@ -1460,6 +1495,16 @@ int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
     if (flags & 2) return bail(fail(GG_E_RANGE, "rowptr is not non-decreasing"));
     if (flags & 4) return bail(fail(GG_E_RANGE, "column index out of [0, n)"));
     if (flags & 8) return bail(fail(GG_E_RANGE, "weight outside [0, 255]"));
+    // the source-segmented kernels need every row's sources in ascending order
+    e = launch_rows_sorted(g->rowptr, g->col, g->n, g->i32_scratch + 1, g->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&flags, g->i32_scratch + 1, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("validate: ") + hipGetErrorString(e)));
+    if (flags & 16) {
+      g->rows_sorted = false;
+      g->tune.seg_enable = 0;
+    }
   }
   const int nblk = (d->n + kBlock - 1) / kBlock;
   const size_t scratch_bytes = (size_t)(3 * nblk + 2) * sizeof(int32_t) + (size_t)(nblk + 1) * sizeof(int64_t);
@@ -1562,6 +1607,7 @@ int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t) {
   if (!valid_tuning(*t)) return fail(GG_E_INVAL, "invalid tuning");
   if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
   g->tune = *t;
+  if (!g->rows_sorted) g->tune.seg_enable = 0;
   GG_TRY(rebin_full(g));
   if (g->ws) GG_TRY(ensure_parts(g));
   return GG_OK;

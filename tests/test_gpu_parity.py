@@ -302,6 +302,33 @@ def test_abi_errors(P):
     R.close()
 
 
+def test_unsorted_rows_disable_segmentation(P):
+    """Rows that list their sources out of ascending order: the graph loads
+    with source segmentation off (and it stays off when asked for), and runs
+    still match the oracle, which walks every row in CSR order."""
+    g0 = gg.rmat(12, 16, seed=9, weights=True)
+    rng = np.random.default_rng(9)
+    col, w = g0.col.copy(), g0.weight.copy()
+    for u in range(g0.n):
+        b, e = int(g0.rowptr[u]), int(g0.rowptr[u + 1])
+        if e - b > 1:
+            perm = b + rng.permutation(e - b)
+            col[b:e], w[b:e] = col[perm], w[perm]
+    g = gg.Graph(n=g0.n, rowptr=g0.rowptr, col=col, weight=w, name="rmat12_shuffled_rows")
+    assert np.any(np.diff(col)[np.diff(np.repeat(np.arange(g.n), np.diff(g.rowptr))) == 0] < 0)
+    G = load(P, g)
+    assert G.get_tuning()["seg_enable"] == 0
+    G.set_tuning(seg_enable=1)
+    assert G.get_tuning()["seg_enable"] == 0
+    G.close()
+    assert load(P, g0).get_tuning()["seg_enable"] == 1
+    s = int(gg.pick_sources(g, 1, 9)[0])
+    check_run(P, g, "pr", "exact", ctx="shuffled rows")
+    check_run(P, g, "pr", "gg", ctx="shuffled rows", sample_ratio=0.4, alpha=2, theta=0.05, seed=3, iters=12)
+    check_run(P, g, "sssp", "gg", ctx="shuffled rows", sample_ratio=0.4, alpha=2, theta=0.05, seed=3, source=s,
+              iters=12)
+
+
 def test_retune_same_graph(P):
     """Regression: changing the tuning of a loaded graph (including the number
     of source segments, up and down) re-sizes every scratch array."""
