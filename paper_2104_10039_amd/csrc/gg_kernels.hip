@@ -846,34 +846,56 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* rowptr, con
 // Exclusive scan of a[0..count) in place by one 1024-thread block; returns
 // the total through *total.
 __device__ void block1024_exclusive_scan(int32_t* a, int count, int32_t* total) {
+  // wave w owns the contiguous range [w * per, w * per + per), per a multiple
+  // of 64; it reads the range in coalesced slices of 16 x 64 with every load
+  // of a slice in flight, first to sum it, then to rewrite it through wave
+  // scans carried from the range's offset
   __shared__ int wsum[16];
-  __shared__ int carry_s;
   const int tid = threadIdx.x, lane = __lane_id(), wid = tid >> 6;
-  if (tid == 0) carry_s = 0;
-  __syncthreads();
-  for (int base = 0; base < count; base += 1024) {
-    const int i = base + tid;
-    const int v = i < count ? a[i] : 0;
-    int x = v;
+  const int per = ((count + 15) / 16 + 63) & ~63;
+  const int b = min(count, wid * per), e = min(count, b + per);
+  int sum = 0;
+  for (int i0 = b; i0 < e; i0 += 1024) {
+    int v[16];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int y = __shfl_up(x, d, 64);
-      if (lane >= d) x += y;
+    for (int k = 0; k < 16; ++k) {
+      const int i = i0 + k * 64 + lane;
+      v[k] = i < e ? a[i] : 0;
     }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    int before = 0, tile = 0;
-    for (int w = 0; w < 16; ++w) {
-      before += (w < wid) ? wsum[w] : 0;
-      tile += wsum[w];
-    }
-    const int c = carry_s;
-    if (i < count) a[i] = c + before + x - v;
-    __syncthreads();
-    if (tid == 0) carry_s = c + tile;
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sum += v[k];
   }
-  if (tid == 0) *total = carry_s;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (lane == 0) wsum[wid] = sum;
+  __syncthreads();
+  int carry = 0, all = 0;
+  for (int w = 0; w < 16; ++w) {
+    carry += (w < wid) ? wsum[w] : 0;
+    all += wsum[w];
+  }
+  for (int i0 = b; i0 < e; i0 += 1024) {
+    int v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = i0 + k * 64 + lane;
+      v[k] = i < e ? a[i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      int x = v[k];
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      const int i = i0 + k * 64 + lane;
+      if (i < e) a[i] = carry + x - v[k];
+      carry += __shfl(x, 63, 64);
+    }
+  }
+  if (tid == 0) *total = all;
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(1024) void k_bin_scan(int32_t* blk, const int64_t* blk_edges, int nblk, BinCounts* bc) {
@@ -1079,7 +1101,19 @@ __global__ __launch_bounds__(kBlock) void k_dsum_partial(const float* c, const i
   const int per = (count + kDangBlocks - 1) / kDangBlocks;
   const int lo = blockIdx.x * per, hi = min(count, lo + per);
   double acc = 0.0;
-  for (int i = lo + (int)threadIdx.x; i < hi; i += kBlock) acc += (double)c[list[i]];
+  // 8 index and value loads in flight per thread; added in index order
+  int i = lo + (int)threadIdx.x;
+  for (; i + 7 * kBlock < hi; i += 8 * kBlock) {
+    int id[8];
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) id[k] = list[i + k * kBlock];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = c[id[k]];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += (double)v[k];
+  }
+  for (; i < hi; i += kBlock) acc += (double)c[list[i]];
   acc = block_reduce<kPR>(acc, lds);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
