@@ -10,6 +10,7 @@ namespace ggk {
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kBlock = 256;  // threads per workgroup of every sweep kernel
 constexpr int kHubPre = 8;   // 256-edge steps of a hub chunk whose loads are issued together
+constexpr int kFlatWin = 1024;  // edges staged per round of a flattened batch of short rows
 constexpr int kHubSpinLimit = 1 << 20;  // polls before a single-pass hub chunk gives up waiting
 
 enum App : int { kPR = 0, kSSSP = 1, kCC = 2, kPPR = 3 };
@@ -177,7 +178,7 @@ hipError_t launch_chunk_seg(const Sweep& s, const int32_t* col, int32_t z, int32
 hipError_t launch_superstep_flat(int app, const Sweep& s, hipStream_t st, hipEvent_t ev0 = nullptr,
                                  hipEvent_t ev1 = nullptr);
 // Pack the active edges selected by s.old_bits (used after the initial sampling).
-hipError_t launch_pack(int team, const Sweep& s, hipStream_t st);
+hipError_t launch_pack(const Sweep& s, hipStream_t st);
 // Segment offsets of the long rows of the binned edge set in s (source mask:
 // 0xFFFFFF for packed SSSP edge words, else all ones).
 hipError_t launch_seg_offsets(const Sweep& s, uint32_t src_mask, int32_t* seg_off, hipStream_t st);

@@ -766,17 +766,89 @@ __device__ __forceinline__ void hub_chunk_count(const Sweep& s, const uint32_t* 
   if (threadIdx.x == 0) s.part_cnt[ch] = tot;
 }
 
-template <int TEAM>
-__global__ __launch_bounds__(kBlock) void k_pack(Sweep s, int gs, int gw) {
+// Packing of the edges flagged in s.old_bits (the initial sample). Blocks
+// [0, gw): wavefront-bin rows, one wavefront per row. [gw, gw + nchunks): the
+// flagged-edge count of each hub chunk (k_hub_pack writes their edges next).
+// The rest: short rows (degree <= small_max) as flattened batches: a block
+// takes kBlock consecutive vertices, stages the edge words of their short
+// rows in LDS (every load of a window in flight), then the owner thread of
+// each row walks it in CSR order and writes the flagged edges to the front of
+// the row's slot.
+__global__ __launch_bounds__(kBlock) void k_pack_flat(Sweep s, int gw, int nchunks) {
   __shared__ int ilds[4];
+  __shared__ uint32_t s_ev[kFlatWin];
+  __shared__ int s_lo[kBlock];
+  __shared__ int s_scan[kBlock + 1];
   const int bid = blockIdx.x;
-  if (bid < gs) {
-    pack_team_rows<TEAM>(s, s.old_bits, s.list, s.n_small, bid, gs);
-  } else if (bid < gs + gw) {
-    pack_team_rows<64>(s, s.old_bits, s.list + s.n_small, s.n_wave, bid - gs, gw);
-  } else {
-    hub_chunk_count(s, s.old_bits, bid - gs - gw, ilds);
+  if (bid < gw) {
+    pack_team_rows<64>(s, s.old_bits, s.list + s.n_small, s.n_wave, bid, gw);
+    return;
   }
+  if (bid < gw + nchunks) {
+    hub_chunk_count(s, s.old_bits, bid - gw, ilds);
+    return;
+  }
+  const int tid = threadIdx.x;
+  const int u0 = (bid - gw - nchunks) * kBlock;
+  const int P = min(kBlock, s.n - u0);
+  int u = 0, lo = 0, len = 0;
+  bool mine = false;
+  if (tid < P) {
+    u = u0 + tid;
+    lo = s.rowptr[u];
+    len = s.rowptr[u + 1] - lo;
+    mine = len <= s.small_max;
+    if (!mine) len = 0;
+  }
+  // exclusive scan of the row lengths
+  int x = len;
+  const int lane = __lane_id(), wid = tid >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) ilds[wid] = x;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wid; ++w) before += ilds[w];
+  const int total = ilds[0] + ilds[1] + ilds[2] + ilds[3];
+  s_scan[tid] = before + x - len;
+  s_lo[tid] = lo;
+  __syncthreads();
+  const int mine0 = s_scan[tid], mine1 = s_scan[tid] + len;
+  int cnt = 0;
+  int ow = -1;  // cached flag word
+  uint32_t oword = 0;
+  for (int base = 0; base < total; base += kFlatWin) {
+    const int lim = min(kFlatWin, total - base);
+#pragma unroll
+    for (int j = 0; j < kFlatWin / kBlock; ++j) {
+      const int k = j * kBlock + tid;
+      if (k < lim) {
+        const int kk = base + k;
+        int a = 0, b = P - 1;
+        while (a < b) {
+          const int mid = (a + b + 1) >> 1;
+          if (s_scan[mid] <= kk) a = mid;
+          else b = mid - 1;
+        }
+        s_ev[k] = ld_stream(s.edges + s_lo[a] + (kk - s_scan[a]));
+      }
+    }
+    __syncthreads();
+    const int a0 = max(mine0, base), a1 = min(mine1, base + lim);
+    for (int k = a0; k < a1; ++k) {
+      const int e = lo + (k - mine0);
+      if ((e >> 5) != ow) {
+        ow = e >> 5;
+        oword = s.old_bits[ow];
+      }
+      if ((oword >> (e & 31)) & 1u) s.act_edges[lo + cnt++] = s_ev[k - base];
+    }
+    __syncthreads();
+  }
+  if (mine) s.act_cnt[u] = cnt;
 }
 
 // Write the flagged edges of one hub chunk at its rank inside the row; chunk
@@ -1265,15 +1337,6 @@ static hipError_t super_t(const Sweep& s, int nchunks, hipStream_t st, hipEvent_
   return hipGetLastError();
 }
 
-template <int TEAM>
-static hipError_t pack_t(const Sweep& s, int nchunks, hipStream_t st) {
-  int gs, gw;
-  section_grids(s, TEAM, gs, gw);
-  const int total = gs + gw + nchunks;
-  if (total > 0) hipLaunchKernelGGL((k_pack<TEAM>), dim3(total), dim3(kBlock), 0, st, s, gs, gw);
-  if (nchunks > 0) hipLaunchKernelGGL(k_hub_pack, dim3(nchunks), dim3(kBlock), 0, st, s, s.old_bits);
-  return hipGetLastError();
-}
 
 #define GG_DISPATCH_TEAM(FN, APP, team, ...)                      \
   switch (team) {                                                 \
@@ -1315,15 +1378,14 @@ hipError_t launch_superstep(int app, int team, const Sweep& s, hipStream_t st, h
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_pack(int team, const Sweep& s, hipStream_t st) {
+hipError_t launch_pack(const Sweep& s, hipStream_t st) {
   const int nchunks = hub_chunks(s);
-  switch (team) {
-    case 4: return pack_t<4>(s, nchunks, st);
-    case 8: return pack_t<8>(s, nchunks, st);
-    case 16: return pack_t<16>(s, nchunks, st);
-    case 32: return pack_t<32>(s, nchunks, st);
-  }
-  return hipErrorInvalidValue;
+  const int gw = s.n_wave > 0 ? grid_for(s.n_wave, kBlock / 64, kTeamBlockCap) : 0;
+  const int gs = (s.n + kBlock - 1) / kBlock;
+  const int total = gw + nchunks + gs;
+  if (total > 0) hipLaunchKernelGGL(k_pack_flat, dim3(total), dim3(kBlock), 0, st, s, gw, nchunks);
+  if (nchunks > 0) hipLaunchKernelGGL(k_hub_pack, dim3(nchunks), dim3(kBlock), 0, st, s, s.old_bits);
+  return hipGetLastError();
 }
 
 }  // namespace ggk
@@ -1451,7 +1513,6 @@ struct GV<kPR> {
 template <>
 struct GV<kPPR> : GV<kPR> {};
 
-constexpr int kFlatWin = 1024;   // edges gathered per round of a flattened batch
 
 
 // One block reduces a batch of P <= kBlock pieces [lo_p, hi_p) of the edge

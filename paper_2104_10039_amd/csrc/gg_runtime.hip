@@ -715,7 +715,7 @@ int sample_and_pack(gg_graph* g, int app, double sigma, uint64_t seed) {
   s.edges = full_edges(g, app);
   s.old_bits = g->bits[0];
   GG_TRY(check_part_capacity(g, g->full));
-  GG_HIP(launch_pack(g->tune.small_team, s, g->stream));
+  GG_HIP(launch_pack(s, g->stream));
   return rebin_act(g, app);
 }
 
