@@ -103,6 +103,13 @@ def bench_batch(P, gg, torch, seed):
     G = P.Graph.from_host(g)
     srcs = gg.pick_sources(g, 256, seed + 1)
     log("batch: rmat20 ready in %.1f s" % (time.perf_counter() - t))
+    # bin thresholds and hub chunk chosen by the library's autotuner on a
+    # 3-iteration PPR batch of the same queries
+    t = time.perf_counter()
+    tuning, tune_ms = G.autotune("ppr", sources=srcs, iters=3, reps=1)
+    out["rmat20_autotune"] = {"seconds": round(time.perf_counter() - t, 2), "tuning": tuning,
+                              "ppr_3iter_ms": round(tune_ms, 3)}
+    log("batch: autotune", out["rmat20_autotune"])
     for app, kw in (("sssp", dict(max_iters=1000)), ("ppr", dict(iters=20))):
         G.batch_run(app, srcs, **kw)  # first call sizes the workspace
         torch.cuda.synchronize()
@@ -130,6 +137,7 @@ def bench_batch(P, gg, torch, seed):
             srcs = [int(ps[k]) + int(gg.pick_sources(gs[k], 1, 50 + k)[0]) for k in range(len(gs))]
         G = P.Graph.from_host(U)
         G.set_parts(ps, srcs)
+        tuning, _ = G.autotune(app, iters=3 if app == "pr" else 20, max_iters=1000, reps=1)
         G.exact_run(app, iters=20, max_iters=1000)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -137,7 +145,7 @@ def bench_batch(P, gg, torch, seed):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out["union64_%s" % app] = {"n": U.n, "m": U.m, "ms": round(dt * 1e3, 3), "iterations": st.iterations,
-                                   "gteps": round(st.edges_gathered / dt / 1e9, 2)}
+                                   "gteps": round(st.edges_gathered / dt / 1e9, 2), "tuning": tuning}
         log("batch:", app, out["union64_%s" % app])
         G.close()
     log("batch: unions done in %.1f s" % (time.perf_counter() - t))

@@ -286,7 +286,7 @@ int gg_run_labels(gg_run* run, uint8_t* labels_host);
 void gg_run_end(gg_run* run);
 
 /*
- * Tuning knobs of the degree-binned sweep (the autotuner sets them):
+ * Tuning knobs of the degree-binned sweep (set directly or by gg_graph_autotune):
  * rows of degree <= small_max are processed by teams of small_team lanes
  * (4, 8, 16 or 32); rows of degree <= wave_max by one 64-lane wavefront;
  * longer rows by 256-thread workgroups, split into chunks of hub_chunk edges
@@ -317,6 +317,25 @@ typedef struct {
 
 int gg_graph_get_tuning(const gg_graph* g, gg_tuning* out);
 int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t);
+
+/*
+ * Autotuner (project addition): picks the tuning knobs for one workload on
+ * this graph by timing that workload. With n_queries = 0 the workload is a
+ * single run (gg_exact_run when policy is NULL or EXACT, else gg_approx_run
+ * with sample_ratio and policy); with n_queries > 0 it is gg_batch_run over
+ * sources_host. Coordinate descent over small_max, small_team, wave_max,
+ * hub_chunk, seg_vertices and frontier_div (only the knobs the workload
+ * reads), two passes at most; each candidate is timed as the median device
+ * time of reps runs after one warm-up run (1 <= reps <= 64), and replaces
+ * the best one only when at least 1% faster. The best tuning is left set on
+ * the graph and returned in *out_best (*out_ms: its time, nullable). Keep
+ * params->iters small: every candidate runs the workload reps + 1 times.
+ * Results do not depend on the tuning except for the rounding order of
+ * PageRank sums. On error the graph keeps its previous tuning.
+ */
+int gg_graph_autotune(gg_graph* g, const gg_app_params* params, double sample_ratio,
+                      const gg_correction_policy* policy, int32_t n_queries, const int32_t* sources_host,
+                      int32_t reps, gg_tuning* out_best, double* out_ms);
 
 /*
  * Kernel profiling. When enabled, every launch of the sweep's main kernels is

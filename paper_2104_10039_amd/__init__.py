@@ -111,6 +111,9 @@ SIGNATURES = {
     "gg_graph_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "gg_batch_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_int32, _VP, ctypes.c_double,
                                     ctypes.POINTER(Policy), _VP, ctypes.c_uint32, ctypes.POINTER(RunStats)]),
+    "gg_graph_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_double, ctypes.POINTER(Policy),
+                                         ctypes.c_int32, _VP, ctypes.c_int32, ctypes.POINTER(Tuning),
+                                         ctypes.POINTER(ctypes.c_double)]),
     "gg_graph_set_parts": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
     "gg_graph_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_graph_get_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(KernelProfile)]),
@@ -360,6 +363,22 @@ class Graph:
         _check(lib().gg_batch_run(self._h, ctypes.byref(p), q, src.ctypes.data, float(sample_ratio),
                                   ctypes.byref(pol), out.data_ptr(), 0, ctypes.byref(st)))
         return out, _stats(st)
+
+    def autotune(self, app, sample_ratio=1.0, policy="exact", sources=None, reps=2, damping=0.85, iters=20,
+                 max_iters=1 << 20, source=0, dangling="uniform", **pol):
+        """gg_graph_autotune: times the workload (a single run, or a batch over
+        `sources`) under candidate tunings and keeps the fastest on the graph.
+        Returns (tuning dict, median ms of the chosen tuning)."""
+        p = _app_params(app, damping, iters, max_iters, source, dangling)
+        pc = _policy(policy, **pol)
+        src = None if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+        t = Tuning()
+        ms = ctypes.c_double(0.0)
+        _check(lib().gg_graph_autotune(self._h, ctypes.byref(p), float(sample_ratio), ctypes.byref(pc),
+                                       0 if src is None else int(src.shape[0]),
+                                       None if src is None else src.ctypes.data, int(reps), ctypes.byref(t),
+                                       ctypes.byref(ms)))
+        return {k: int(getattr(t, k)) for k in TUNING_FIELDS}, float(ms.value)
 
     def begin(self, app, sample_ratio=1.0, policy="exact", **kw) -> "Run":
         return Run(self, app, sample_ratio, policy, **kw)

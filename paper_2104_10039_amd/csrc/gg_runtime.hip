@@ -1646,6 +1646,100 @@ int gg_batch_run(gg_graph* g, const gg_app_params* params, int32_t n_queries, co
   return batch_run(g, params, n_queries, sources_host, sample_ratio, policy, out_values, out_flags, stats);
 }
 
+// Autotuner: coordinate descent over the tuning knobs that the workload
+// reads, timing the workload itself (median of reps runs after one warm-up,
+// device time from the library's own events). A candidate replaces the best
+// one only when it is at least 1% faster, so timing noise does not walk the
+// search away from the default.
+int gg_graph_autotune(gg_graph* g, const gg_app_params* params, double sample_ratio,
+                      const gg_correction_policy* policy, int32_t n_queries, const int32_t* sources_host,
+                      int32_t reps, gg_tuning* out_best, double* out_ms) {
+  if (!g || !params || !out_best) return fail(GG_E_INVAL, "null argument");
+  if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+  if (n_queries < 0 || (n_queries > 0 && !sources_host)) return fail(GG_E_INVAL, "bad queries");
+  if (reps < 1 || reps > 64) return fail(GG_E_INVAL, "reps outside [1, 64]");
+  gg_correction_policy exact;
+  std::memset(&exact, 0, sizeof(exact));
+  exact.kind = GG_POLICY_EXACT;
+  const gg_correction_policy* pol = policy ? policy : &exact;
+  const bool batch = n_queries > 0;
+  const size_t elems = (size_t)(g->n > 0 ? g->n : 1) * (size_t)(batch ? n_queries : 1);
+  void* out = nullptr;
+  if (hipMalloc(&out, elems * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GG_E_NOMEM, "autotune output buffer");
+  }
+  const gg_tuning start = g->tune;
+  auto measure = [&](const gg_tuning& t, double* ms) -> int {
+    GG_TRY(gg_graph_set_tuning(g, &t));
+    std::vector<double> v;
+    for (int32_t r = 0; r <= reps; ++r) {
+      gg_run_stats st;
+      std::memset(&st, 0, sizeof(st));
+      int rc;
+      if (batch)
+        rc = gg_batch_run(g, params, n_queries, sources_host, sample_ratio, pol, out, 0u, &st);
+      else
+        rc = whole_run(g, params, pol->kind == GG_POLICY_EXACT ? 1.0 : sample_ratio, pol, out, 0u, &st);
+      if (rc != GG_OK) return rc;
+      if (r > 0) v.push_back(st.device_ms);
+    }
+    std::sort(v.begin(), v.end());
+    *ms = v[v.size() / 2];
+    return GG_OK;
+  };
+  // knob value lists; a workload only varies the knobs it reads
+  const bool single = !batch;
+  const bool minapp = params->app == GG_APP_SSSP || params->app == GG_APP_CC;
+  struct Knob {
+    int32_t gg_tuning::*field;
+    std::vector<int32_t> values;
+    bool used;
+  };
+  const Knob knobs[] = {
+      {&gg_tuning::small_max, {8, 16, 32, 64}, true},
+      {&gg_tuning::small_team, {4, 8, 16, 32}, single},
+      {&gg_tuning::wave_max, {128, 256, 512, 1024, 2048}, true},
+      {&gg_tuning::hub_chunk, {512, 1024, 2048, 4096}, true},
+      {&gg_tuning::seg_vertices, {0, 1 << 17, 1 << 18, 1 << 20}, single && start.seg_enable != 0},
+      {&gg_tuning::frontier_div, {4, 16, 64}, single && minapp && start.frontier_enable != 0},
+  };
+  gg_tuning best = start;
+  double best_ms = 0.0;
+  int rc = measure(best, &best_ms);
+  for (int pass = 0; rc == GG_OK && pass < 2; ++pass) {
+    bool moved = false;
+    for (const Knob& k : knobs) {
+      if (!k.used) continue;
+      for (int32_t v : k.values) {
+        gg_tuning t = best;
+        t.*(k.field) = v;
+        if (t.*(k.field) == best.*(k.field) || !valid_tuning(t)) continue;
+        double ms = 0.0;
+        rc = measure(t, &ms);
+        if (rc != GG_OK) break;
+        if (ms < 0.99 * best_ms) {
+          best = t;
+          best_ms = ms;
+          moved = true;
+        }
+      }
+      if (rc != GG_OK) break;
+    }
+    if (!moved) break;
+  }
+  (void)hipFree(out);
+  if (rc != GG_OK) {
+    const std::string msg = gg_last_error();
+    (void)gg_graph_set_tuning(g, &start);
+    return fail(rc, "autotune: " + msg);
+  }
+  GG_TRY(gg_graph_set_tuning(g, &best));
+  *out_best = g->tune;
+  if (out_ms) *out_ms = best_ms;
+  return GG_OK;
+}
+
 int gg_exact_run(gg_graph* g, const gg_app_params* params, void* out_values, uint32_t out_flags, gg_run_stats* st) {
   gg_correction_policy pol;
   std::memset(&pol, 0, sizeof(pol));
