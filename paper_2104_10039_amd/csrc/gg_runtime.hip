@@ -1785,6 +1785,7 @@ int gg_run_mask(gg_run* run, uint32_t* out_bits_host) {
     return GG_OK;
   }
   if (nw == 0) return GG_OK;
+  GG_TRY(check_hub_sync(g));
   return copy_out(g, g->bits[run->bcur], out_bits_host, nw * sizeof(uint32_t), GG_OUT_HOST);
 }
 
