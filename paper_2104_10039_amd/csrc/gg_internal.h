@@ -63,7 +63,7 @@ struct Sweep {
   // SSSP / CC
   const uint32_t* x_in;
   uint32_t* x_next;
-  int32_t* changed;  // device counter
+  int32_t* changed;  // device counter of changed rows (nullable: not counted)
   uint8_t* chg;      // nullable: per-vertex changed flag written by dense iterations
   // hub partial results (one per chunk)
   double* part_f;

@@ -167,8 +167,17 @@ __device__ __forceinline__ int find_hub(const int32_t* hub_start, int n_hub, int
 // Apply [Alg. 2, GG-Apply]
 // ---------------------------------------------------------------------------
 
+// The per-row word the apply reads (PR/PPR: out-degree; SSSP/CC: the old
+// value), so that callers can issue its load before their gather.
 template <int APP>
-__device__ __forceinline__ void apply(const Sweep& s, int u, typename Tr<APP>::T acc, int& nchanged) {
+__device__ __forceinline__ uint32_t apply_word(const Sweep& s, int u) {
+  if constexpr (APP == kPR || APP == kPPR) return (uint32_t)s.outdeg[u];
+  else return s.x_in[u];
+}
+
+template <int APP>
+__device__ __forceinline__ void apply_with(const Sweep& s, int u, typename Tr<APP>::T acc, uint32_t word,
+                                           int& nchanged) {
   if constexpr (APP == kPR || APP == kPPR) {
     const double D = *s.dangling;
     double x;
@@ -185,16 +194,21 @@ __device__ __forceinline__ void apply(const Sweep& s, int u, typename Tr<APP>::T
       const bool src = (u == s.source);
       x = (src ? (1.0 - s.damping) : 0.0) + s.damping * (acc + (src ? D : 0.0));
     }
-    const int od = s.outdeg[u];
+    const int od = (int)word;
     s.c_out[u] = od > 0 ? (float)(x / (double)od) : (float)x;
     if (s.x_out) s.x_out[u] = (float)x;
   } else {
-    const uint32_t old = s.x_in[u];
+    const uint32_t old = word;
     const uint32_t nv = min(old, acc);
     s.x_next[u] = nv;
     nchanged += (nv != old);
     if (s.chg) s.chg[u] = (uint8_t)(nv != old);
   }
+}
+
+template <int APP>
+__device__ __forceinline__ void apply(const Sweep& s, int u, typename Tr<APP>::T acc, int& nchanged) {
+  apply_with<APP>(s, u, acc, apply_word<APP>(s, u), nchanged);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,6 +281,7 @@ __device__ __forceinline__ void gather_hub_chunk(const Sweep& s, int ch, bool al
 template <int APP>
 __device__ __forceinline__ void flush_changed(const Sweep& s, int nchanged, int* ilds) {
   if constexpr (APP == kSSSP || APP == kCC) {
+    if (!s.changed) return;  // counted elsewhere (the frontier's changed list)
     const int tot = block_sum_int(nchanged, ilds);
     if (threadIdx.x == 0 && tot) atomicAdd(s.changed, tot);
   }
@@ -1622,14 +1637,16 @@ __global__ __launch_bounds__(kBlock) void k_gather_seg(Sweep s, int gh, int gw, 
     const int u = u0 + (int)threadIdx.x;
     int lo = 0, len = 0;
     bool mine = false;
+    uint32_t word = 0;  // the apply's own read, issued before the gather
     if ((int)threadIdx.x < P) {
       lo = s.rowptr[u];
       len = row_len(s, u, lo);
+      word = apply_word<APP>(s, u);
       mine = len <= s.small_max;
       if (!mine) len = 0;
     }
     const T acc = flat_batch<APP>(s, P, lo, len, s_val, s_lo, s_scan, ilds);
-    if (mine) apply<APP>(s, u, acc, nchanged);
+    if (mine) apply_with<APP>(s, u, acc, word, nchanged);
   }
   flush_changed<APP>(s, nchanged, ilds);
 }
@@ -2151,10 +2168,12 @@ __global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int
   const int P = min(kBlock, (s.flat_list ? s.n_small : s.n) - u0);
   int u = 0, lo = 0, len = 0;
   bool mine = false;
+  uint32_t word = 0;  // the apply's own read, issued before the gather
   if (tid < P) {
     u = s.flat_list ? s.list[u0 + tid] : u0 + tid;
     lo = s.rowptr[u];
     len = s.rowptr[u + 1] - lo;
+    word = apply_word<APP>(s, u);
     mine = len <= s.small_max;
     if (!mine) len = 0;
   }
@@ -2252,7 +2271,7 @@ __global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int
     T acc;
     if constexpr (APP == kPR || APP == kPPR) acc = Psum;
     else acc = run;
-    apply<APP>(s, u, acc, nchanged);
+    apply_with<APP>(s, u, acc, word, nchanged);
     s.act_cnt[u] = cnt;
   }
   flush_changed<APP>(s, nchanged, ilds);

@@ -148,7 +148,6 @@ struct gg_graph {
   uint32_t* shadow = nullptr;      // n: approximate update of that superstep
   int32_t* sel_count = nullptr;    // 4: |S| (int32), pad, in-edges of S (uint64 at +2)
   unsigned long long* judge = nullptr;  // [0] drifted vertices, [1] of which selected, [2] active edges of S
-  int32_t* dummy = nullptr;        // changed-counter sink of the shadow pass
   Bins selb;                       // binning of the selected rows (full rows)
   // workspace (allocated on first run)
   bool ws = false;
@@ -270,7 +269,6 @@ int ensure_learned(gg_graph* g) {
   GG_TRY(dalloc(&g->shadow, n));
   GG_TRY(dalloc(&g->sel_count, 4));
   GG_TRY(dalloc(&g->judge, 3));
-  GG_TRY(dalloc(&g->dummy, 1));
   GG_TRY(alloc_bins(g->selb, g->n));
   g->lws = true;
   return GG_OK;
@@ -549,7 +547,6 @@ void free_graph(gg_graph* g) {
   dfree(g->shadow);
   dfree(g->sel_count);
   dfree(g->judge);
-  dfree(g->dummy);
   free_bins(g->selb);
   for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
@@ -881,7 +878,12 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   // compaction or push finalize)
   const bool sparse = frontier && !superstep && !grows && r->front_count >= 0 && r->front_count <= g->n &&
                       (double)r->front_outdeg * (double)g->tune.frontier_div <= (double)g->m;
-  if (frontier) s.chg = g->chg;
+  // with the frontier, the changed count comes from the compacted changed
+  // list, so the dense kernels skip their (contended) counter
+  if (frontier) {
+    s.chg = g->chg;
+    s.changed = nullptr;
+  }
   int64_t edges;
   int64_t processed;
   hipEvent_t pe0, pe1;
@@ -925,7 +927,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
       GG_HIP(launch_gather(app, g->tune.small_team, sa, g->stream, pe0, nullptr));
     }
     GG_HIP(launch_sel_fix(g->selb.list, ns, pr ? nullptr : s.x_in, pr ? nullptr : s.x_next, g->act_cnt,
-                          pr ? nullptr : g->changed, g->judge + 2, g->stream));
+                          (pr || frontier) ? nullptr : g->changed, g->judge + 2, g->stream));
     const int64_t act_all = g->act.h.edges;
     Sweep sc = s;
     set_bins(sc, g->selb);
@@ -963,7 +965,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
         sh.c_out = (float*)g->shadow;
       } else {
         sh.x_next = g->shadow;
-        sh.changed = g->dummy;
+        sh.changed = nullptr;  // the shadow pass counts nothing
       }
       GG_TRY(check_part_capacity(g, g->act));
       GG_HIP(launch_gather(app, g->tune.small_team, sh, g->stream));
