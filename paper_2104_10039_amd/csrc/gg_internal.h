@@ -10,7 +10,8 @@ namespace ggk {
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kBlock = 256;  // threads per workgroup of every sweep kernel
 constexpr int kHubPre = 8;   // 256-edge steps of a hub chunk whose loads are issued together
-constexpr int kFlatWin = 1024;  // edges staged per round of a flattened batch of short rows
+constexpr int kFlatWin = 1024;
+constexpr int kPartDangBlocks = 32;  // blocks per part of the per-part dangling sums  // edges staged per round of a flattened batch of short rows
 constexpr int kHubSpinLimit = 1 << 20;  // polls before a single-pass hub chunk gives up waiting
 
 enum App : int { kPR = 0, kSSSP = 1, kCC = 2, kPPR = 3 };
@@ -220,9 +221,10 @@ hipError_t launch_parts_setup(const int32_t* rowptr, const int32_t* col, int32_t
 // Range of each part in the (vertex-sorted) dangling list: dstart[np+1].
 hipError_t launch_parts_dangling_ranges(const int32_t* dlist, int32_t ndang, int32_t np, const int32_t* part_start,
                                         int32_t* dstart, hipStream_t st);
-// part_dang[p] = sum of c over part p's dangling vertices (fixed order).
+// part_dang[p] = sum of c over part p's dangling vertices (fixed order);
+// partial: np * kPartDangBlocks doubles of scratch.
 hipError_t launch_parts_dangling_sum(const float* c, const int32_t* dlist, int32_t np, const int32_t* dstart,
-                                     double* part_dang, hipStream_t st);
+                                     double* part_dang, double* partial, hipStream_t st);
 // Sampling with part-local edge ids: edge e of part p draws with seed + p at
 // local index e - part_e0[p].
 hipError_t launch_sample_bits_parts(int64_t m, uint64_t seed, uint64_t epoch, uint64_t keep, int32_t np,

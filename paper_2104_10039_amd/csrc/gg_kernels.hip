@@ -2041,20 +2041,45 @@ hipError_t launch_parts_dangling_ranges(const int32_t* dlist, int32_t ndang, int
   return hipGetLastError();
 }
 
+// Dangling mass of every part: kPartDangBlocks blocks per part take
+// interleaved slices of its dangling list (4 loads in flight per thread),
+// then one thread per part adds its partials in block order.
 __global__ __launch_bounds__(kBlock) void k_part_dsum(const float* c, const int32_t* dlist, const int32_t* dstart,
-                                                      double* part_dang) {
+                                                      double* partial) {
   __shared__ double lds[4];
-  const int p = blockIdx.x;
+  const int p = blockIdx.x / kPartDangBlocks, k = blockIdx.x % kPartDangBlocks;
+  const int hi = dstart[p + 1];
+  constexpr int kStride = kPartDangBlocks * kBlock;
   double acc = 0.0;
-  for (int i = dstart[p] + (int)threadIdx.x; i < dstart[p + 1]; i += kBlock) acc += (double)c[dlist[i]];
+  int i = dstart[p] + k * kBlock + (int)threadIdx.x;
+  for (; i + 3 * kStride < hi; i += 4 * kStride) {
+    const int a0 = dlist[i], a1 = dlist[i + kStride], a2 = dlist[i + 2 * kStride], a3 = dlist[i + 3 * kStride];
+    const float v0 = c[a0], v1 = c[a1], v2 = c[a2], v3 = c[a3];
+    acc += (double)v0;
+    acc += (double)v1;
+    acc += (double)v2;
+    acc += (double)v3;
+  }
+  for (; i < hi; i += kStride) acc += (double)c[dlist[i]];
   acc = block_reduce<kPR>(acc, lds);
-  if (threadIdx.x == 0) part_dang[p] = acc;
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ void k_part_dsum_final(const double* partial, int32_t np, double* part_dang) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) {
+    double acc = 0.0;
+    for (int k = 0; k < kPartDangBlocks; ++k) acc += partial[(int64_t)p * kPartDangBlocks + k];
+    part_dang[p] = acc;
+  }
 }
 
 hipError_t launch_parts_dangling_sum(const float* c, const int32_t* dlist, int32_t np, const int32_t* dstart,
-                                     double* part_dang, hipStream_t st) {
+                                     double* part_dang, double* partial, hipStream_t st) {
   if (np <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_part_dsum, dim3(np), dim3(kBlock), 0, st, c, dlist, dstart, part_dang);
+  hipLaunchKernelGGL(k_part_dsum, dim3(np * kPartDangBlocks), dim3(kBlock), 0, st, c, dlist, dstart, partial);
+  hipLaunchKernelGGL(k_part_dsum_final, dim3((np + kBlock - 1) / kBlock), dim3(kBlock), 0, st, partial, np,
+                     part_dang);
   return hipGetLastError();
 }
 

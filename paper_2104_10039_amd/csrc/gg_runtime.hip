@@ -112,7 +112,7 @@ struct gg_graph {
   int32_t* part_e0 = nullptr;     // np+1: first edge of each part
   int32_t* part_dstart = nullptr; // np+1: range of each part in the dangling list
   int32_t* part_src = nullptr;    // np or null
-  double* part_dang = nullptr;    // np
+  double* part_dang = nullptr;    // np, then np * kPartDangBlocks partials
   // multi-query batch workspace
   struct Batch {
     int64_t val_cap = 0;  // elements of each value buffer
@@ -855,7 +855,8 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   if (pr) {
     if (r->p.dangling == GG_DANGLING_UNIFORM) {
       if (g->n_parts > 0)
-        GG_HIP(launch_parts_dangling_sum(g->c[r->cur], g->dang, g->n_parts, g->part_dstart, g->part_dang, g->stream));
+        GG_HIP(launch_parts_dangling_sum(g->c[r->cur], g->dang, g->n_parts, g->part_dstart, g->part_dang,
+                                         g->part_dang + g->n_parts, g->stream));
       else
         GG_HIP(launch_dangling_sum(g->c[r->cur], g->dang, nullptr, g->n_dang, g->dpartial, g->dpartial + 256,
                                    g->stream));
@@ -1571,7 +1572,7 @@ int gg_graph_set_parts(gg_graph* g, int32_t n_parts, const int32_t* part_start_h
   GG_TRY(dalloc(&g->part_of, (size_t)g->n));
   GG_TRY(dalloc(&g->part_e0, np + 1));
   GG_TRY(dalloc(&g->part_dstart, np + 1));
-  GG_TRY(dalloc(&g->part_dang, np));
+  GG_TRY(dalloc(&g->part_dang, np * (1 + (size_t)kPartDangBlocks)));
   GG_HIP(hipMemcpyAsync(g->part_start, part_start_host, sizeof(int32_t) * (np + 1), hipMemcpyHostToDevice,
                         g->stream));
   if (part_sources_host) {
