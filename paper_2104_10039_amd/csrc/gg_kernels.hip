@@ -751,16 +751,28 @@ __device__ __forceinline__ void pack_team_rows(const Sweep& s, const uint32_t* b
     const int b = s.rowptr[u];
     const int len = s.rowptr[u + 1] - b;
     int carry_cnt = 0;
-    for (int k0 = 0; k0 < len; k0 += TEAM) {
-      const int k = k0 + lt;
-      const bool valid = k < len;
-      const int e = b + k;
-      const bool flag = valid && edge_bit(bits, e);
-      const uint64_t bal = __ballot(flag);
-      const uint64_t tm = TEAM == 64 ? bal : ((bal >> team_base) & ((1ull << (TEAM & 63)) - 1ull));
-      const int rank = __popcll(tm & ((1ull << lt) - 1ull));
-      if (flag) s.act_edges[b + carry_cnt + rank] = s.edges[e];
-      carry_cnt += __popcll(tm);
+    // the flag words and edge words of kPreP team-wide steps are loaded
+    // before the first step's ranks
+    constexpr int kPreP = 4;
+    for (int g0 = 0; g0 < len; g0 += kPreP * TEAM) {
+      uint32_t fw[kPreP], ev[kPreP];
+#pragma unroll
+      for (int q = 0; q < kPreP; ++q) {
+        const int k = g0 + q * TEAM + lt;
+        fw[q] = k < len ? bits[(b + k) >> 5] : 0u;
+        ev[q] = k < len ? ld_stream(s.edges + b + k) : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < kPreP; ++q) {
+        const int k = g0 + q * TEAM + lt;
+        const int e = b + k;
+        const bool flag = k < len && ((fw[q] >> (e & 31)) & 1u);
+        const uint64_t bal = __ballot(flag);
+        const uint64_t tm = TEAM == 64 ? bal : ((bal >> team_base) & ((1ull << (TEAM & 63)) - 1ull));
+        const int rank = __popcll(tm & ((1ull << lt) - 1ull));
+        if (flag) s.act_edges[b + carry_cnt + rank] = ev[q];
+        carry_cnt += __popcll(tm);
+      }
     }
     if (lt == 0) s.act_cnt[u] = carry_cnt;
   }
@@ -775,8 +787,16 @@ __device__ __forceinline__ void hub_chunk_count(const Sweep& s, const uint32_t* 
   const int len = s.rowptr[u + 1] - b;
   const int e0 = j * s.hub_chunk;
   const int e1 = min(len, e0 + s.hub_chunk);
+  // popcount over the flag words covering edges [b + e0, b + e1), the bits
+  // outside the range masked off
   int c = 0;
-  for (int k = e0 + (int)threadIdx.x; k < e1; k += kBlock) c += (int)edge_bit(bits, b + k);
+  const int lo = b + e0, hi = b + e1;  // hi > lo
+  for (int w = (lo >> 5) + (int)threadIdx.x; w <= ((hi - 1) >> 5); w += kBlock) {
+    uint32_t x = bits[w];
+    if (w == (lo >> 5)) x &= ~0u << (lo & 31);
+    if (w == ((hi - 1) >> 5) && (hi & 31)) x &= (1u << (hi & 31)) - 1u;
+    c += __popc(x);
+  }
   const int tot = block_sum_int(c, ilds);
   if (threadIdx.x == 0) s.part_cnt[ch] = tot;
 }
@@ -880,21 +900,49 @@ __global__ __launch_bounds__(kBlock) void k_hub_pack(Sweep s, const uint32_t* bi
   const int len = s.rowptr[u + 1] - b;
   const int e0 = j * s.hub_chunk;
   const int e1 = min(len, e0 + s.hub_chunk);
-  int carry = 0;
-  for (int i = 0; i < j; ++i) carry += s.part_cnt[c0 + i];
-  for (int sub = e0; sub < e1; sub += kBlock) {
-    const int k = sub + (int)threadIdx.x;
-    const bool valid = k < e1;
-    const bool flag = valid && edge_bit(bits, b + k);
-    int tot;
-    const int rank = block_rank(flag, ilds, tot);
-    if (flag) s.act_edges[b + carry + rank] = s.edges[b + k];
-    carry += tot;
+  // counts of the row's earlier chunks (and, for chunk 0, of all chunks),
+  // summed by the lanes of wave 0
+  __shared__ int s_base[2];
+  if (threadIdx.x < 64) {
+    int before = 0, all = 0;
+    for (int i = (int)threadIdx.x; i < nch; i += 64) {
+      const int c = s.part_cnt[c0 + i];
+      all += c;
+      before += i < j ? c : 0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      before += __shfl_xor(before, o, 64);
+      all += __shfl_xor(all, o, 64);
+    }
+    if (threadIdx.x == 0) {
+      s_base[0] = before;
+      s_base[1] = all;
+    }
   }
-  if (j == 0 && threadIdx.x == 0) {
-    int all = 0;
-    for (int i = 0; i < nch; ++i) all += s.part_cnt[c0 + i];
-    s.act_cnt[u] = all;
+  __syncthreads();
+  int carry = s_base[0];
+  if (j == 0 && threadIdx.x == 0) s.act_cnt[u] = s_base[1];
+  // flag words and edge words of kHubPre steps loaded before the ranks
+  for (int g0 = e0; g0 < e1; g0 += kHubPre * kBlock) {
+    uint32_t fw[kHubPre], ev[kHubPre];
+#pragma unroll
+    for (int q = 0; q < kHubPre; ++q) {
+      const int k = g0 + q * kBlock + (int)threadIdx.x;
+      fw[q] = k < e1 ? bits[(b + k) >> 5] : 0u;
+      ev[q] = k < e1 ? ld_stream(s.edges + b + k) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kHubPre; ++q) {
+      const int sub = g0 + q * kBlock;
+      if (sub >= e1) break;  // uniform over the block
+      const int k = sub + (int)threadIdx.x;
+      const bool flag = k < e1 && ((fw[q] >> ((b + k) & 31)) & 1u);
+      int tot;
+      const int rank = block_rank(flag, ilds, tot);
+      if (flag) s.act_edges[b + carry + rank] = ev[q];
+      carry += tot;
+    }
   }
 }
 
