@@ -69,7 +69,7 @@ def cpu_baseline(graphs, source, budget_iters=3):
 # Fastest configurations within 1% error on R-MAT scale 22 (seed 2), from a
 # sweep over SP/SMS/GG, sigma in {.1,.3,.5,.7,.9}, alpha in {1,2,4,8},
 # theta in {0, .001, .01, .05, .2} and REPLACE/UNION.
-AT_1PCT = {"pr": ("sms", 0.1, 4), "sssp": ("sms", 0.1, 8), "cc": ("sms", 0.1, 4)}
+AT_1PCT = {"pr": ("sms", 0.1, 6), "sssp": ("sms", 0.1, 8), "cc": ("sms", 0.1, 5)}
 
 
 def bench_at_1pct(G, apps, iters, source, exact_out, metrics, np):
