@@ -302,6 +302,32 @@ def test_abi_errors(P):
     R.close()
 
 
+def _giant_hub_graph(seed):
+    """2^16 vertices: vertex 0 has an in-edge from every other vertex (one
+    row of 65535 edges, sources ascending), plus 4 random in-edges per other
+    vertex."""
+    n = 1 << 16
+    rng = np.random.default_rng(seed)
+    src = np.concatenate([np.arange(1, n), rng.integers(0, n, size=4 * n)]).astype(np.int32)
+    dst = np.concatenate([np.zeros(n - 1, dtype=np.int64), rng.integers(1, n, size=4 * n)]).astype(np.int32)
+    w = rng.integers(1, 256, size=src.size).astype(np.int32)
+    return gg.from_edges(n, src, dst, w, name="giant_hub_%d" % seed)
+
+
+@pytest.mark.parametrize("app", ["pr", "sssp", "cc"])
+def test_giant_hub_many_chunks_per_segment(P, app):
+    """Single-pass hub chunks on one row of 65535 edges split into 256
+    chunks, about four per source segment (1024-vertex segments): the chunks
+    of the row must keep their order among equal segments. Supersteps every
+    third iteration match the oracle."""
+    g = _giant_hub_graph(31)
+    if app == "cc":
+        g = gg.from_edges(g.n, g.col, g.dst(), symmetrize=True, name=g.name + "_sym")
+    tuning = dict(small_max=8, small_team=4, wave_max=128, hub_chunk=256, seg_enable=1, seg_vertices=1024)
+    check_run(P, g, app, "gg", tuning=tuning, ctx="giant hub", sample_ratio=0.4, alpha=2, theta=0.02, seed=5,
+              source=1, iters=9)
+
+
 def test_unsorted_rows_disable_segmentation(P):
     """Rows that list their sources out of ascending order: the graph loads
     with source segmentation off (and it stays off when asked for), and runs
