@@ -1444,6 +1444,27 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
 // C ABI
 // ===========================================================================
 
+// Every entry point runs under guard(), so no C++ exception crosses the C
+// ABI: a failed host allocation returns GG_E_NOMEM.
+int fail_noexcept(int code, const char* msg) noexcept {
+  try {
+    g_err = msg;
+  } catch (...) {
+  }
+  return code;
+}
+
+template <typename F>
+int guard(F&& f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail_noexcept(GG_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail_noexcept(GG_E_DEVICE, "unexpected exception inside the library");
+  }
+}
+
 extern "C" {
 
 int gg_version(void) { return GG_VERSION; }
@@ -1451,202 +1472,221 @@ int gg_version(void) { return GG_VERSION; }
 const char* gg_last_error(void) { return g_err.c_str(); }
 
 int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
-  if (!d || !out) return fail(GG_E_INVAL, "null argument");
-  *out = nullptr;
-  if (d->n < 0 || d->m < 0) return fail(GG_E_RANGE, "negative n or m");
-  if (d->m >= ((int64_t)1 << 31)) return fail(GG_E_RANGE, "m must be < 2^31");
-  if (d->n >= INT32_MAX) return fail(GG_E_RANGE, "n must be < 2^31 - 1");
-  if (!d->rowptr || (d->m > 0 && !d->col)) return fail(GG_E_INVAL, "null rowptr or col");
-  if (d->weight && d->n > (1 << 24)) return fail(GG_E_RANGE, "weighted graphs need n <= 2^24");
-  gg_graph* g = new (std::nothrow) gg_graph();
-  if (!g) return fail(GG_E_NOMEM, "host allocation failed");
-  g->n = d->n;
-  g->m = d->m;
-  g->stream = (hipStream_t)hip_stream;
-  const size_t n = (size_t)d->n, m = (size_t)d->m;
-  int rc = GG_OK;
-  auto bail = [&](int code) {
-    free_graph(g);
-    return code;
-  };
-  if (d->flags & GG_CSR_DEVICE_PTRS) {
-    g->owns_csr = false;
-    g->rowptr = const_cast<int32_t*>(d->rowptr);
-    g->col = const_cast<int32_t*>(d->col);
-    g->weight = const_cast<int32_t*>(d->weight);
-  } else {
-    g->owns_csr = true;
-    if ((rc = dalloc(&g->rowptr, n + 1)) != GG_OK) return bail(rc);
-    if ((rc = dalloc(&g->col, m)) != GG_OK) return bail(rc);
-    hipError_t e = hipMemcpyAsync(g->rowptr, d->rowptr, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess && m) e = hipMemcpyAsync(g->col, d->col, m * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+  return guard([&]() -> int {
+    if (!d || !out) return fail(GG_E_INVAL, "null argument");
+    *out = nullptr;
+    if (d->n < 0 || d->m < 0) return fail(GG_E_RANGE, "negative n or m");
+    if (d->m >= ((int64_t)1 << 31)) return fail(GG_E_RANGE, "m must be < 2^31");
+    if (d->n >= INT32_MAX) return fail(GG_E_RANGE, "n must be < 2^31 - 1");
+    if (!d->rowptr || (d->m > 0 && !d->col)) return fail(GG_E_INVAL, "null rowptr or col");
+    if (d->weight && d->n > (1 << 24)) return fail(GG_E_RANGE, "weighted graphs need n <= 2^24");
+    gg_graph* g = new (std::nothrow) gg_graph();
+    if (!g) return fail(GG_E_NOMEM, "host allocation failed");
+    g->n = d->n;
+    g->m = d->m;
+    g->stream = (hipStream_t)hip_stream;
+    const size_t n = (size_t)d->n, m = (size_t)d->m;
+    int rc = GG_OK;
+    auto bail = [&](int code) {
+      free_graph(g);
+      return code;
+    };
+    if (d->flags & GG_CSR_DEVICE_PTRS) {
+      g->owns_csr = false;
+      g->rowptr = const_cast<int32_t*>(d->rowptr);
+      g->col = const_cast<int32_t*>(d->col);
+      g->weight = const_cast<int32_t*>(d->weight);
+    } else {
+      g->owns_csr = true;
+      if ((rc = dalloc(&g->rowptr, n + 1)) != GG_OK) return bail(rc);
+      if ((rc = dalloc(&g->col, m)) != GG_OK) return bail(rc);
+      hipError_t e = hipMemcpyAsync(g->rowptr, d->rowptr, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+      if (e == hipSuccess && m) e = hipMemcpyAsync(g->col, d->col, m * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+      if (e == hipSuccess && d->weight) {
+        if ((rc = dalloc(&g->weight, m)) != GG_OK) return bail(rc);
+        if (m) e = hipMemcpyAsync(g->weight, d->weight, m * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+      }
+      if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("copy CSR: ") + hipGetErrorString(e)));
+    }
+    if ((rc = dalloc(&g->i32_scratch, 4)) != GG_OK) return bail(rc);
+    if (!(d->flags & GG_CSR_SKIP_VALIDATE)) {
+      hipError_t e = launch_validate(g->rowptr, g->col, g->weight, g->n, g->m, g->i32_scratch + 1, g->stream);
+      int32_t flags = 0;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&flags, g->i32_scratch + 1, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+      if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("validate: ") + hipGetErrorString(e)));
+      if (flags & 1) return bail(fail(GG_E_RANGE, "rowptr[0] != 0 or rowptr[n] != m"));
+      if (flags & 2) return bail(fail(GG_E_RANGE, "rowptr is not non-decreasing"));
+      if (flags & 4) return bail(fail(GG_E_RANGE, "column index out of [0, n)"));
+      if (flags & 8) return bail(fail(GG_E_RANGE, "weight outside [0, 255]"));
+      // the source-segmented kernels need every row's sources in ascending order
+      e = launch_rows_sorted(g->rowptr, g->col, g->n, g->i32_scratch + 1, g->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&flags, g->i32_scratch + 1, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+      if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("validate: ") + hipGetErrorString(e)));
+      if (flags & 16) {
+        g->rows_sorted = false;
+        g->tune.seg_enable = 0;
+      }
+    }
+    const int nblk = (d->n + kBlock - 1) / kBlock;
+    const size_t scratch_bytes = (size_t)(3 * nblk + 2) * sizeof(int32_t) + (size_t)(nblk + 1) * sizeof(int64_t);
+    if (hipMalloc(&g->blk_scratch, scratch_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(GG_E_NOMEM, "scratch allocation failed"));
+    }
+    if ((rc = dalloc(&g->outdeg, n)) != GG_OK) return bail(rc);
+    if ((rc = dalloc(&g->dang, n)) != GG_OK) return bail(rc);
+    hipError_t e = launch_outdeg(g->col, g->m, g->outdeg, g->n, g->stream);
+    if (e == hipSuccess) e = launch_dangling_list(g->outdeg, g->n, g->dang, g->i32_scratch, (int32_t*)g->blk_scratch,
+                                                   g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&g->n_dang, g->i32_scratch, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess && d->weight) {
-      if ((rc = dalloc(&g->weight, m)) != GG_OK) return bail(rc);
-      if (m) e = hipMemcpyAsync(g->weight, d->weight, m * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
+      if ((rc = dalloc(&g->wedges, m)) != GG_OK) return bail(rc);
+      e = launch_pack_weights(g->col, g->weight, g->m, g->wedges, g->stream);
     }
-    if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("copy CSR: ") + hipGetErrorString(e)));
-  }
-  if ((rc = dalloc(&g->i32_scratch, 4)) != GG_OK) return bail(rc);
-  if (!(d->flags & GG_CSR_SKIP_VALIDATE)) {
-    hipError_t e = launch_validate(g->rowptr, g->col, g->weight, g->n, g->m, g->i32_scratch + 1, g->stream);
-    int32_t flags = 0;
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(&flags, g->i32_scratch + 1, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("validate: ") + hipGetErrorString(e)));
-    if (flags & 1) return bail(fail(GG_E_RANGE, "rowptr[0] != 0 or rowptr[n] != m"));
-    if (flags & 2) return bail(fail(GG_E_RANGE, "rowptr is not non-decreasing"));
-    if (flags & 4) return bail(fail(GG_E_RANGE, "column index out of [0, n)"));
-    if (flags & 8) return bail(fail(GG_E_RANGE, "weight outside [0, 255]"));
-    // the source-segmented kernels need every row's sources in ascending order
-    e = launch_rows_sorted(g->rowptr, g->col, g->n, g->i32_scratch + 1, g->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(&flags, g->i32_scratch + 1, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("validate: ") + hipGetErrorString(e)));
-    if (flags & 16) {
-      g->rows_sorted = false;
-      g->tune.seg_enable = 0;
-    }
-  }
-  const int nblk = (d->n + kBlock - 1) / kBlock;
-  const size_t scratch_bytes = (size_t)(3 * nblk + 2) * sizeof(int32_t) + (size_t)(nblk + 1) * sizeof(int64_t);
-  if (hipMalloc(&g->blk_scratch, scratch_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return bail(fail(GG_E_NOMEM, "scratch allocation failed"));
-  }
-  if ((rc = dalloc(&g->outdeg, n)) != GG_OK) return bail(rc);
-  if ((rc = dalloc(&g->dang, n)) != GG_OK) return bail(rc);
-  hipError_t e = launch_outdeg(g->col, g->m, g->outdeg, g->n, g->stream);
-  if (e == hipSuccess) e = launch_dangling_list(g->outdeg, g->n, g->dang, g->i32_scratch, (int32_t*)g->blk_scratch,
-                                                 g->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(&g->n_dang, g->i32_scratch, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
-  if (e == hipSuccess && d->weight) {
-    if ((rc = dalloc(&g->wedges, m)) != GG_OK) return bail(rc);
-    e = launch_pack_weights(g->col, g->weight, g->m, g->wedges, g->stream);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-  if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("load: ") + hipGetErrorString(e)));
-  if ((rc = alloc_bins(g->full, g->n)) != GG_OK) return bail(rc);
-  if ((rc = rebin_full(g)) != GG_OK) return bail(rc);
-  g->full_valid = true;
-  *out = g;
-  return GG_OK;
+    if (e != hipSuccess) return bail(fail(GG_E_DEVICE, std::string("load: ") + hipGetErrorString(e)));
+    if ((rc = alloc_bins(g->full, g->n)) != GG_OK) return bail(rc);
+    if ((rc = rebin_full(g)) != GG_OK) return bail(rc);
+    g->full_valid = true;
+    *out = g;
+    return GG_OK;
+  });
 }
 
 int gg_graph_set_stream(gg_graph* g, void* hip_stream) {
-  if (!g) return fail(GG_E_INVAL, "null graph");
-  if (g->stream) GG_HIP(hipStreamSynchronize(g->stream));
-  g->stream = (hipStream_t)hip_stream;
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!g) return fail(GG_E_INVAL, "null graph");
+    if (g->stream) GG_HIP(hipStreamSynchronize(g->stream));
+    g->stream = (hipStream_t)hip_stream;
+    return GG_OK;
+  });
 }
 
 void gg_graph_free(gg_graph* g) {
-  if (!g) return;
-  if (g->active_run) end_run(g->active_run);
-  free_graph(g);
+  try {
+    if (!g) return;
+    if (g->active_run) end_run(g->active_run);
+    free_graph(g);
+  } catch (...) {
+  }
 }
 
 int gg_graph_set_parts(gg_graph* g, int32_t n_parts, const int32_t* part_start_host,
                        const int32_t* part_sources_host) {
-  if (!g) return fail(GG_E_INVAL, "null graph");
-  if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
-  dfree(g->part_start);
-  dfree(g->part_of);
-  dfree(g->part_e0);
-  dfree(g->part_dstart);
-  dfree(g->part_src);
-  dfree(g->part_dang);
-  g->n_parts = 0;
-  if (n_parts == 0) return GG_OK;
-  if (n_parts < 0 || !part_start_host) return fail(GG_E_INVAL, "bad part description");
-  if (part_start_host[0] != 0 || part_start_host[n_parts] != g->n) return fail(GG_E_RANGE, "parts must cover [0, n)");
-  for (int32_t p = 0; p < n_parts; ++p) {
-    if (part_start_host[p + 1] < part_start_host[p]) return fail(GG_E_RANGE, "part starts must not decrease");
-    if (part_sources_host &&
-        (part_sources_host[p] < part_start_host[p] || part_sources_host[p] >= part_start_host[p + 1]))
-      return fail(GG_E_RANGE, "part source outside its part");
-  }
-  const size_t np = (size_t)n_parts;
-  GG_TRY(dalloc(&g->part_start, np + 1));
-  GG_TRY(dalloc(&g->part_of, (size_t)g->n));
-  GG_TRY(dalloc(&g->part_e0, np + 1));
-  GG_TRY(dalloc(&g->part_dstart, np + 1));
-  GG_TRY(dalloc(&g->part_dang, np * (1 + (size_t)kPartDangBlocks)));
-  GG_HIP(hipMemcpyAsync(g->part_start, part_start_host, sizeof(int32_t) * (np + 1), hipMemcpyHostToDevice,
-                        g->stream));
-  if (part_sources_host) {
-    GG_TRY(dalloc(&g->part_src, np));
-    GG_HIP(hipMemcpyAsync(g->part_src, part_sources_host, sizeof(int32_t) * np, hipMemcpyHostToDevice, g->stream));
-  }
-  GG_HIP(launch_gather_i32(g->rowptr, g->part_start, n_parts + 1, g->part_e0, g->stream));
-  GG_HIP(launch_parts_setup(g->rowptr, g->col, g->n, g->m, n_parts, g->part_start, g->part_of, g->i32_scratch + 2,
-                            g->stream));
-  GG_HIP(launch_parts_dangling_ranges(g->dang, g->n_dang, n_parts, g->part_start, g->part_dstart, g->stream));
-  int32_t bad = 0;
-  GG_HIP(hipMemcpyAsync(&bad, g->i32_scratch + 2, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
-  GG_HIP(hipStreamSynchronize(g->stream));
-  if (bad) {
+  return guard([&]() -> int {
+    if (!g) return fail(GG_E_INVAL, "null graph");
+    if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
     dfree(g->part_start);
     dfree(g->part_of);
     dfree(g->part_e0);
     dfree(g->part_dstart);
     dfree(g->part_src);
     dfree(g->part_dang);
-    return fail(GG_E_RANGE, "an edge crosses parts");
-  }
-  g->n_parts = n_parts;
-  return GG_OK;
+    g->n_parts = 0;
+    if (n_parts == 0) return GG_OK;
+    if (n_parts < 0 || !part_start_host) return fail(GG_E_INVAL, "bad part description");
+    if (part_start_host[0] != 0 || part_start_host[n_parts] != g->n) return fail(GG_E_RANGE, "parts must cover [0, n)");
+    for (int32_t p = 0; p < n_parts; ++p) {
+      if (part_start_host[p + 1] < part_start_host[p]) return fail(GG_E_RANGE, "part starts must not decrease");
+      if (part_sources_host &&
+          (part_sources_host[p] < part_start_host[p] || part_sources_host[p] >= part_start_host[p + 1]))
+        return fail(GG_E_RANGE, "part source outside its part");
+    }
+    const size_t np = (size_t)n_parts;
+    GG_TRY(dalloc(&g->part_start, np + 1));
+    GG_TRY(dalloc(&g->part_of, (size_t)g->n));
+    GG_TRY(dalloc(&g->part_e0, np + 1));
+    GG_TRY(dalloc(&g->part_dstart, np + 1));
+    GG_TRY(dalloc(&g->part_dang, np * (1 + (size_t)kPartDangBlocks)));
+    GG_HIP(hipMemcpyAsync(g->part_start, part_start_host, sizeof(int32_t) * (np + 1), hipMemcpyHostToDevice,
+                          g->stream));
+    if (part_sources_host) {
+      GG_TRY(dalloc(&g->part_src, np));
+      GG_HIP(hipMemcpyAsync(g->part_src, part_sources_host, sizeof(int32_t) * np, hipMemcpyHostToDevice, g->stream));
+    }
+    GG_HIP(launch_gather_i32(g->rowptr, g->part_start, n_parts + 1, g->part_e0, g->stream));
+    GG_HIP(launch_parts_setup(g->rowptr, g->col, g->n, g->m, n_parts, g->part_start, g->part_of, g->i32_scratch + 2,
+                              g->stream));
+    GG_HIP(launch_parts_dangling_ranges(g->dang, g->n_dang, n_parts, g->part_start, g->part_dstart, g->stream));
+    int32_t bad = 0;
+    GG_HIP(hipMemcpyAsync(&bad, g->i32_scratch + 2, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipStreamSynchronize(g->stream));
+    if (bad) {
+      dfree(g->part_start);
+      dfree(g->part_of);
+      dfree(g->part_e0);
+      dfree(g->part_dstart);
+      dfree(g->part_src);
+      dfree(g->part_dang);
+      return fail(GG_E_RANGE, "an edge crosses parts");
+    }
+    g->n_parts = n_parts;
+    return GG_OK;
+  });
 }
 
 int gg_graph_get_tuning(const gg_graph* g, gg_tuning* out) {
-  if (!g || !out) return fail(GG_E_INVAL, "null argument");
-  *out = g->tune;
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!g || !out) return fail(GG_E_INVAL, "null argument");
+    *out = g->tune;
+    return GG_OK;
+  });
 }
 
 int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t) {
-  if (!g || !t) return fail(GG_E_INVAL, "null argument");
-  if (!valid_tuning(*t)) return fail(GG_E_INVAL, "invalid tuning");
-  if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
-  g->tune = *t;
-  if (!g->rows_sorted) g->tune.seg_enable = 0;
-  GG_TRY(rebin_full(g));
-  if (g->ws) GG_TRY(ensure_parts(g));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!g || !t) return fail(GG_E_INVAL, "null argument");
+    if (!valid_tuning(*t)) return fail(GG_E_INVAL, "invalid tuning");
+    if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+    g->tune = *t;
+    if (!g->rows_sorted) g->tune.seg_enable = 0;
+    GG_TRY(rebin_full(g));
+    if (g->ws) GG_TRY(ensure_parts(g));
+    return GG_OK;
+  });
 }
 
 int gg_graph_set_profiling(gg_graph* g, int enable) {
-  if (!g) return fail(GG_E_INVAL, "null graph");
-  if (g->stream) GG_HIP(hipStreamSynchronize(g->stream));
-  g->prof = enable != 0;
-  g->recs.clear();
-  g->pool_used = 0;
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!g) return fail(GG_E_INVAL, "null graph");
+    if (g->stream) GG_HIP(hipStreamSynchronize(g->stream));
+    g->prof = enable != 0;
+    g->recs.clear();
+    g->pool_used = 0;
+    return GG_OK;
+  });
 }
 
 int gg_graph_get_profile(gg_graph* g, int kind, int app, gg_kernel_profile* out) {
-  if (!g || !out) return fail(GG_E_INVAL, "null argument");
-  if (kind < 0 || kind > 4 || app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "bad kind or app");
-  GG_HIP(hipStreamSynchronize(g->stream));
-  gg_kernel_profile p{0, 0.0, 0.0, 0};
-  for (const auto& r : g->recs) {
-    if (r.kind != kind || r.app != app) continue;
-    float ms = 0.f;
-    GG_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
-    p.launches++;
-    p.total_ms += ms;
-    p.alg_bytes += r.bytes;
-    p.edges += r.edges;
-  }
-  *out = p;
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!g || !out) return fail(GG_E_INVAL, "null argument");
+    if (kind < 0 || kind > 4 || app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "bad kind or app");
+    GG_HIP(hipStreamSynchronize(g->stream));
+    gg_kernel_profile p{0, 0.0, 0.0, 0};
+    for (const auto& r : g->recs) {
+      if (r.kind != kind || r.app != app) continue;
+      float ms = 0.f;
+      GG_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
+      p.launches++;
+      p.total_ms += ms;
+      p.alg_bytes += r.bytes;
+      p.edges += r.edges;
+    }
+    *out = p;
+    return GG_OK;
+  });
 }
 
 int gg_batch_run(gg_graph* g, const gg_app_params* params, int32_t n_queries, const int32_t* sources_host,
                  double sample_ratio, const gg_correction_policy* policy, void* out_values, uint32_t out_flags,
                  gg_run_stats* stats) {
-  return batch_run(g, params, n_queries, sources_host, sample_ratio, policy, out_values, out_flags, stats);
+  return guard([&]() -> int {
+    return batch_run(g, params, n_queries, sources_host, sample_ratio, policy, out_values, out_flags, stats);
+  });
 }
 
 // Autotuner: coordinate descent over the tuning knobs that the workload
@@ -1657,183 +1697,210 @@ int gg_batch_run(gg_graph* g, const gg_app_params* params, int32_t n_queries, co
 int gg_graph_autotune(gg_graph* g, const gg_app_params* params, double sample_ratio,
                       const gg_correction_policy* policy, int32_t n_queries, const int32_t* sources_host,
                       int32_t reps, gg_tuning* out_best, double* out_ms) {
-  if (!g || !params || !out_best) return fail(GG_E_INVAL, "null argument");
-  if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
-  if (n_queries < 0 || (n_queries > 0 && !sources_host)) return fail(GG_E_INVAL, "bad queries");
-  if (reps < 1 || reps > 64) return fail(GG_E_INVAL, "reps outside [1, 64]");
-  gg_correction_policy exact;
-  std::memset(&exact, 0, sizeof(exact));
-  exact.kind = GG_POLICY_EXACT;
-  const gg_correction_policy* pol = policy ? policy : &exact;
-  const bool batch = n_queries > 0;
-  const size_t elems = (size_t)(g->n > 0 ? g->n : 1) * (size_t)(batch ? n_queries : 1);
-  void* out = nullptr;
-  if (hipMalloc(&out, elems * 4) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(GG_E_NOMEM, "autotune output buffer");
-  }
-  const gg_tuning start = g->tune;
-  auto measure = [&](const gg_tuning& t, double* ms) -> int {
-    GG_TRY(gg_graph_set_tuning(g, &t));
-    std::vector<double> v;
-    for (int32_t r = 0; r <= reps; ++r) {
-      gg_run_stats st;
-      std::memset(&st, 0, sizeof(st));
-      int rc;
-      if (batch)
-        rc = gg_batch_run(g, params, n_queries, sources_host, sample_ratio, pol, out, 0u, &st);
-      else
-        rc = whole_run(g, params, pol->kind == GG_POLICY_EXACT ? 1.0 : sample_ratio, pol, out, 0u, &st);
-      if (rc != GG_OK) return rc;
-      if (r > 0) v.push_back(st.device_ms);
+  return guard([&]() -> int {
+    if (!g || !params || !out_best) return fail(GG_E_INVAL, "null argument");
+    if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+    if (n_queries < 0 || (n_queries > 0 && !sources_host)) return fail(GG_E_INVAL, "bad queries");
+    if (reps < 1 || reps > 64) return fail(GG_E_INVAL, "reps outside [1, 64]");
+    gg_correction_policy exact;
+    std::memset(&exact, 0, sizeof(exact));
+    exact.kind = GG_POLICY_EXACT;
+    const gg_correction_policy* pol = policy ? policy : &exact;
+    const bool batch = n_queries > 0;
+    const size_t elems = (size_t)(g->n > 0 ? g->n : 1) * (size_t)(batch ? n_queries : 1);
+    void* out = nullptr;
+    if (hipMalloc(&out, elems * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GG_E_NOMEM, "autotune output buffer");
     }
-    std::sort(v.begin(), v.end());
-    *ms = v[v.size() / 2];
-    return GG_OK;
-  };
-  // knob value lists; a workload only varies the knobs it reads
-  const bool single = !batch;
-  const bool minapp = params->app == GG_APP_SSSP || params->app == GG_APP_CC;
-  struct Knob {
-    int32_t gg_tuning::*field;
-    std::vector<int32_t> values;
-    bool used;
-  };
-  const Knob knobs[] = {
-      {&gg_tuning::small_max, {8, 16, 32, 64}, true},
-      {&gg_tuning::small_team, {4, 8, 16, 32}, single},
-      {&gg_tuning::wave_max, {128, 256, 512, 1024, 2048}, true},
-      {&gg_tuning::hub_chunk, {512, 1024, 2048, 4096}, true},
-      {&gg_tuning::seg_vertices, {0, 1 << 17, 1 << 18, 1 << 20}, single && start.seg_enable != 0},
-      {&gg_tuning::frontier_div, {4, 16, 64}, single && minapp && start.frontier_enable != 0},
-  };
-  gg_tuning best = start;
-  double best_ms = 0.0;
-  int rc = measure(best, &best_ms);
-  for (int pass = 0; rc == GG_OK && pass < 2; ++pass) {
-    bool moved = false;
-    for (const Knob& k : knobs) {
-      if (!k.used) continue;
-      for (int32_t v : k.values) {
-        gg_tuning t = best;
-        t.*(k.field) = v;
-        if (t.*(k.field) == best.*(k.field) || !valid_tuning(t)) continue;
-        double ms = 0.0;
-        rc = measure(t, &ms);
-        if (rc != GG_OK) break;
-        if (ms < 0.99 * best_ms) {
-          best = t;
-          best_ms = ms;
-          moved = true;
-        }
+    const gg_tuning start = g->tune;
+    auto measure = [&](const gg_tuning& t, double* ms) -> int {
+      GG_TRY(gg_graph_set_tuning(g, &t));
+      std::vector<double> v;
+      for (int32_t r = 0; r <= reps; ++r) {
+        gg_run_stats st;
+        std::memset(&st, 0, sizeof(st));
+        int rc;
+        if (batch)
+          rc = gg_batch_run(g, params, n_queries, sources_host, sample_ratio, pol, out, 0u, &st);
+        else
+          rc = whole_run(g, params, pol->kind == GG_POLICY_EXACT ? 1.0 : sample_ratio, pol, out, 0u, &st);
+        if (rc != GG_OK) return rc;
+        if (r > 0) v.push_back(st.device_ms);
       }
-      if (rc != GG_OK) break;
+      std::sort(v.begin(), v.end());
+      *ms = v[v.size() / 2];
+      return GG_OK;
+    };
+    // knob value lists; a workload only varies the knobs it reads
+    const bool single = !batch;
+    const bool minapp = params->app == GG_APP_SSSP || params->app == GG_APP_CC;
+    struct Knob {
+      int32_t gg_tuning::*field;
+      std::vector<int32_t> values;
+      bool used;
+    };
+    const Knob knobs[] = {
+        {&gg_tuning::small_max, {8, 16, 32, 64}, true},
+        {&gg_tuning::small_team, {4, 8, 16, 32}, single},
+        {&gg_tuning::wave_max, {128, 256, 512, 1024, 2048}, true},
+        {&gg_tuning::hub_chunk, {512, 1024, 2048, 4096}, true},
+        {&gg_tuning::seg_vertices, {0, 1 << 17, 1 << 18, 1 << 20}, single && start.seg_enable != 0},
+        {&gg_tuning::frontier_div, {4, 16, 64}, single && minapp && start.frontier_enable != 0},
+    };
+    gg_tuning best = start;
+    double best_ms = 0.0;
+    int rc = measure(best, &best_ms);
+    for (int pass = 0; rc == GG_OK && pass < 2; ++pass) {
+      bool moved = false;
+      for (const Knob& k : knobs) {
+        if (!k.used) continue;
+        for (int32_t v : k.values) {
+          gg_tuning t = best;
+          t.*(k.field) = v;
+          if (t.*(k.field) == best.*(k.field) || !valid_tuning(t)) continue;
+          double ms = 0.0;
+          rc = measure(t, &ms);
+          if (rc != GG_OK) break;
+          if (ms < 0.99 * best_ms) {
+            best = t;
+            best_ms = ms;
+            moved = true;
+          }
+        }
+        if (rc != GG_OK) break;
+      }
+      if (!moved) break;
     }
-    if (!moved) break;
-  }
-  (void)hipFree(out);
-  if (rc != GG_OK) {
-    const std::string msg = gg_last_error();
-    (void)gg_graph_set_tuning(g, &start);
-    return fail(rc, "autotune: " + msg);
-  }
-  GG_TRY(gg_graph_set_tuning(g, &best));
-  *out_best = g->tune;
-  if (out_ms) *out_ms = best_ms;
-  return GG_OK;
+    (void)hipFree(out);
+    if (rc != GG_OK) {
+      const std::string msg = gg_last_error();
+      (void)gg_graph_set_tuning(g, &start);
+      return fail(rc, "autotune: " + msg);
+    }
+    GG_TRY(gg_graph_set_tuning(g, &best));
+    *out_best = g->tune;
+    if (out_ms) *out_ms = best_ms;
+    return GG_OK;
+  });
 }
 
 int gg_exact_run(gg_graph* g, const gg_app_params* params, void* out_values, uint32_t out_flags, gg_run_stats* st) {
-  gg_correction_policy pol;
-  std::memset(&pol, 0, sizeof(pol));
-  pol.kind = GG_POLICY_EXACT;
-  return whole_run(g, params, 1.0, &pol, out_values, out_flags, st);
+  return guard([&]() -> int {
+    gg_correction_policy pol;
+    std::memset(&pol, 0, sizeof(pol));
+    pol.kind = GG_POLICY_EXACT;
+    return whole_run(g, params, 1.0, &pol, out_values, out_flags, st);
+  });
 }
 
 int gg_approx_run(gg_graph* g, const gg_app_params* params, double sample_ratio, const gg_correction_policy* policy,
                   void* out_values, uint32_t out_flags, gg_run_stats* st) {
-  return whole_run(g, params, sample_ratio, policy, out_values, out_flags, st);
+  return guard([&]() -> int {
+    return whole_run(g, params, sample_ratio, policy, out_values, out_flags, st);
+  });
 }
 
 int gg_run_begin(gg_graph* g, const gg_app_params* params, double sample_ratio, const gg_correction_policy* policy,
                  gg_run** out) {
-  if (!g || !out) return fail(GG_E_INVAL, "null argument");
-  *out = nullptr;
-  gg_run* r = nullptr;
-  GG_TRY(run_begin(g, params, sample_ratio, policy, &r));
-  r->write_x_each_step = true;
-  *out = r;
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!g || !out) return fail(GG_E_INVAL, "null argument");
+    *out = nullptr;
+    gg_run* r = nullptr;
+    GG_TRY(run_begin(g, params, sample_ratio, policy, &r));
+    r->write_x_each_step = true;
+    *out = r;
+    return GG_OK;
+  });
 }
 
 int gg_run_step(gg_run* run, gg_step_info* info) {
-  if (!run) return fail(GG_E_INVAL, "null run");
-  return run_step(run, info, true);
+  return guard([&]() -> int {
+    if (!run) return fail(GG_E_INVAL, "null run");
+    return run_step(run, info, true);
+  });
 }
 
 int gg_run_values(gg_run* run, void* out_values, uint32_t out_flags) {
-  if (!run) return fail(GG_E_INVAL, "null run");
-  return run_values(run, out_values, out_flags);
+  return guard([&]() -> int {
+    if (!run) return fail(GG_E_INVAL, "null run");
+    return run_values(run, out_values, out_flags);
+  });
 }
 
 int gg_run_mask(gg_run* run, uint32_t* out_bits_host) {
-  if (!run || !out_bits_host) return fail(GG_E_INVAL, "null argument");
-  gg_graph* g = run->g;
-  const size_t nw = (size_t)((g->m + 31) / 32);
-  if (run->pol.kind == GG_POLICY_EXACT) {
-    for (size_t w = 0; w < nw; ++w) {
-      const int64_t rem = g->m - (int64_t)w * 32;
-      out_bits_host[w] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+  return guard([&]() -> int {
+    if (!run || !out_bits_host) return fail(GG_E_INVAL, "null argument");
+    gg_graph* g = run->g;
+    const size_t nw = (size_t)((g->m + 31) / 32);
+    if (run->pol.kind == GG_POLICY_EXACT) {
+      for (size_t w = 0; w < nw; ++w) {
+        const int64_t rem = g->m - (int64_t)w * 32;
+        out_bits_host[w] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+      }
+      return GG_OK;
     }
-    return GG_OK;
-  }
-  if (nw == 0) return GG_OK;
-  GG_TRY(check_hub_sync(g));
-  return copy_out(g, g->bits[run->bcur], out_bits_host, nw * sizeof(uint32_t), GG_OUT_HOST);
+    if (nw == 0) return GG_OK;
+    GG_TRY(check_hub_sync(g));
+    return copy_out(g, g->bits[run->bcur], out_bits_host, nw * sizeof(uint32_t), GG_OUT_HOST);
+  });
 }
 
 int gg_run_stats_get(gg_run* run, gg_run_stats* st) {
-  if (!run || !st) return fail(GG_E_INVAL, "null argument");
-  st->iterations = run->iter;
-  st->supersteps = run->supersteps;
-  st->edges_gathered = run->edges_total;
-  st->active_edges = run->pol.kind == GG_POLICY_EXACT ? run->g->m : run->g->act.h.edges;
-  st->device_ms = 0.0;
-  st->edges_processed = run->edges_processed;
-  st->sparse_iterations = run->sparse_iters;
-  return learned_stats(run, st);
+  return guard([&]() -> int {
+    if (!run || !st) return fail(GG_E_INVAL, "null argument");
+    st->iterations = run->iter;
+    st->supersteps = run->supersteps;
+    st->edges_gathered = run->edges_total;
+    st->active_edges = run->pol.kind == GG_POLICY_EXACT ? run->g->m : run->g->act.h.edges;
+    st->device_ms = 0.0;
+    st->edges_processed = run->edges_processed;
+    st->sparse_iterations = run->sparse_iters;
+    return learned_stats(run, st);
+  });
 }
 
 int gg_run_features(gg_run* run, uint16_t* feat_host) {
-  if (!run || !feat_host) return fail(GG_E_INVAL, "null argument");
-  if (!run->have_feat) return fail(GG_E_STATE, "no features computed yet");
-  gg_graph* g = run->g;
-  GG_HIP(hipMemcpyAsync(feat_host, g->feat, (size_t)g->n * 16, hipMemcpyDeviceToHost, g->stream));
-  GG_HIP(hipStreamSynchronize(g->stream));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!run || !feat_host) return fail(GG_E_INVAL, "null argument");
+    if (!run->have_feat) return fail(GG_E_STATE, "no features computed yet");
+    gg_graph* g = run->g;
+    GG_HIP(hipMemcpyAsync(feat_host, g->feat, (size_t)g->n * 16, hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipStreamSynchronize(g->stream));
+    return GG_OK;
+  });
 }
 
 int gg_run_selection(gg_run* run, uint8_t* sel_host, float* logits_host) {
-  if (!run) return fail(GG_E_INVAL, "null run");
-  if (!run->have_sel) return fail(GG_E_STATE, "the last step made no selection");
-  gg_graph* g = run->g;
-  if (sel_host) GG_HIP(hipMemcpyAsync(sel_host, g->sel, (size_t)g->n, hipMemcpyDeviceToHost, g->stream));
-  if (logits_host)
-    GG_HIP(hipMemcpyAsync(logits_host, g->logits, (size_t)g->n * 4, hipMemcpyDeviceToHost, g->stream));
-  GG_HIP(hipStreamSynchronize(g->stream));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!run) return fail(GG_E_INVAL, "null run");
+    if (!run->have_sel) return fail(GG_E_STATE, "the last step made no selection");
+    gg_graph* g = run->g;
+    if (sel_host) GG_HIP(hipMemcpyAsync(sel_host, g->sel, (size_t)g->n, hipMemcpyDeviceToHost, g->stream));
+    if (logits_host)
+      GG_HIP(hipMemcpyAsync(logits_host, g->logits, (size_t)g->n * 4, hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipStreamSynchronize(g->stream));
+    return GG_OK;
+  });
 }
 
 int gg_run_labels(gg_run* run, uint8_t* labels_host) {
-  if (!run || !labels_host) return fail(GG_E_INVAL, "null argument");
-  if (!run->have_labels) return fail(GG_E_STATE, "the last step computed no labels");
-  gg_graph* g = run->g;
-  GG_HIP(hipMemcpyAsync(labels_host, g->labels, (size_t)g->n, hipMemcpyDeviceToHost, g->stream));
-  GG_HIP(hipStreamSynchronize(g->stream));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!run || !labels_host) return fail(GG_E_INVAL, "null argument");
+    if (!run->have_labels) return fail(GG_E_STATE, "the last step computed no labels");
+    gg_graph* g = run->g;
+    GG_HIP(hipMemcpyAsync(labels_host, g->labels, (size_t)g->n, hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipStreamSynchronize(g->stream));
+    return GG_OK;
+  });
 }
 
-void gg_run_end(gg_run* run) { end_run(run); }
+void gg_run_end(gg_run* run) {
+  try {
+    end_run(run);
+  } catch (...) {
+  }
+}
 
 // ---- learned correction network and traces ---------------------------------
 
@@ -1894,173 +1961,203 @@ int mlp_adam(gg_mlp* n, const float* grad, float lr) {
 }  // namespace
 
 int gg_mlp_create(void* hip_stream, uint64_t seed, gg_mlp** out) {
-  if (!out) return fail(GG_E_INVAL, "null output");
-  *out = nullptr;
-  std::unique_ptr<gg_mlp, void (*)(gg_mlp*)> n(new (std::nothrow) gg_mlp(), mlp_release);
-  if (!n) return fail(GG_E_NOMEM, "host allocation failed");
-  n->stream = (hipStream_t)hip_stream;
-  GG_TRY(dalloc(&n->d.master, kMlpParams));
-  GG_TRY(dalloc(&n->d.m, kMlpParams));
-  GG_TRY(dalloc(&n->d.v, kMlpParams));
-  GG_TRY(dalloc(&n->d.w1b, kMlpIn * kMlpHidden));
-  GG_TRY(dalloc(&n->d.w2b, kMlpHidden * kMlpHidden));
-  GG_TRY(dalloc(&n->d.w3b, kMlpHidden));
-  GG_TRY(dalloc(&n->grad, kMlpParams + 1));
-  // He-uniform weights (bound sqrt(6 / fan_in)), zero biases
-  std::vector<float> h(kMlpParams, 0.0f);
-  uint64_t x = seed;
-  const double a1 = std::sqrt(6.0 / kMlpIn), a2 = std::sqrt(6.0 / kMlpHidden);
-  for (int i = 0; i < kMlpIn * kMlpHidden; ++i) h[kMlpW1 + i] = (float)((2.0 * unit(x) - 1.0) * a1);
-  for (int i = 0; i < kMlpHidden * kMlpHidden; ++i) h[kMlpW2 + i] = (float)((2.0 * unit(x) - 1.0) * a2);
-  for (int i = 0; i < kMlpHidden; ++i) h[kMlpW3 + i] = (float)((2.0 * unit(x) - 1.0) * a2);
-  GG_TRY(mlp_upload(n.get(), h.data()));
-  *out = n.release();
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!out) return fail(GG_E_INVAL, "null output");
+    *out = nullptr;
+    std::unique_ptr<gg_mlp, void (*)(gg_mlp*)> n(new (std::nothrow) gg_mlp(), mlp_release);
+    if (!n) return fail(GG_E_NOMEM, "host allocation failed");
+    n->stream = (hipStream_t)hip_stream;
+    GG_TRY(dalloc(&n->d.master, kMlpParams));
+    GG_TRY(dalloc(&n->d.m, kMlpParams));
+    GG_TRY(dalloc(&n->d.v, kMlpParams));
+    GG_TRY(dalloc(&n->d.w1b, kMlpIn * kMlpHidden));
+    GG_TRY(dalloc(&n->d.w2b, kMlpHidden * kMlpHidden));
+    GG_TRY(dalloc(&n->d.w3b, kMlpHidden));
+    GG_TRY(dalloc(&n->grad, kMlpParams + 1));
+    // He-uniform weights (bound sqrt(6 / fan_in)), zero biases
+    std::vector<float> h(kMlpParams, 0.0f);
+    uint64_t x = seed;
+    const double a1 = std::sqrt(6.0 / kMlpIn), a2 = std::sqrt(6.0 / kMlpHidden);
+    for (int i = 0; i < kMlpIn * kMlpHidden; ++i) h[kMlpW1 + i] = (float)((2.0 * unit(x) - 1.0) * a1);
+    for (int i = 0; i < kMlpHidden * kMlpHidden; ++i) h[kMlpW2 + i] = (float)((2.0 * unit(x) - 1.0) * a2);
+    for (int i = 0; i < kMlpHidden; ++i) h[kMlpW3 + i] = (float)((2.0 * unit(x) - 1.0) * a2);
+    GG_TRY(mlp_upload(n.get(), h.data()));
+    *out = n.release();
+    return GG_OK;
+  });
 }
 
-void gg_mlp_free(gg_mlp* mlp) { mlp_release(mlp); }
+void gg_mlp_free(gg_mlp* mlp) {
+  try {
+    mlp_release(mlp);
+  } catch (...) {
+  }
+}
 
 int gg_mlp_set_weights(gg_mlp* mlp, const float* params_host) {
-  if (!mlp || !params_host) return fail(GG_E_INVAL, "null argument");
-  for (int i = 0; i < kMlpParams; ++i)
-    if (!std::isfinite(params_host[i])) return fail(GG_E_INVAL, "non-finite parameter");
-  return mlp_upload(mlp, params_host);
+  return guard([&]() -> int {
+    if (!mlp || !params_host) return fail(GG_E_INVAL, "null argument");
+    for (int i = 0; i < kMlpParams; ++i)
+      if (!std::isfinite(params_host[i])) return fail(GG_E_INVAL, "non-finite parameter");
+    return mlp_upload(mlp, params_host);
+  });
 }
 
 int gg_mlp_get_weights(gg_mlp* mlp, float* params_host) {
-  if (!mlp || !params_host) return fail(GG_E_INVAL, "null argument");
-  GG_HIP(hipMemcpyAsync(params_host, mlp->d.master, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, mlp->stream));
-  GG_HIP(hipStreamSynchronize(mlp->stream));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!mlp || !params_host) return fail(GG_E_INVAL, "null argument");
+    GG_HIP(hipMemcpyAsync(params_host, mlp->d.master, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, mlp->stream));
+    GG_HIP(hipStreamSynchronize(mlp->stream));
+    return GG_OK;
+  });
 }
 
 int gg_mlp_forward(gg_mlp* mlp, const uint16_t* feat_dev, int64_t n, float* logits_dev) {
-  if (!mlp || (n > 0 && (!feat_dev || !logits_dev))) return fail(GG_E_INVAL, "null argument");
-  if (n < 0) return fail(GG_E_INVAL, "n < 0");
-  if (((uintptr_t)feat_dev & 7) != 0) return fail(GG_E_INVAL, "feat_dev is not 8-byte aligned");
-  GG_HIP(launch_mlp_forward(mlp->d, feat_dev, n, logits_dev, nullptr, 0.0f, nullptr, nullptr, nullptr, mlp->stream));
-  GG_HIP(hipStreamSynchronize(mlp->stream));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!mlp || (n > 0 && (!feat_dev || !logits_dev))) return fail(GG_E_INVAL, "null argument");
+    if (n < 0) return fail(GG_E_INVAL, "n < 0");
+    if (((uintptr_t)feat_dev & 7) != 0) return fail(GG_E_INVAL, "feat_dev is not 8-byte aligned");
+    GG_HIP(launch_mlp_forward(mlp->d, feat_dev, n, logits_dev, nullptr, 0.0f, nullptr, nullptr, nullptr, mlp->stream));
+    GG_HIP(hipStreamSynchronize(mlp->stream));
+    return GG_OK;
+  });
 }
 
 int gg_mlp_loss_grad(gg_mlp* mlp, const uint16_t* feat_dev, const float* label_dev, int64_t n, float pos_weight,
                      float* grad_dev) {
-  if (!mlp || !grad_dev || (n > 0 && (!feat_dev || !label_dev))) return fail(GG_E_INVAL, "null argument");
-  if (n <= 0) return fail(GG_E_INVAL, "n <= 0");
-  if (!(pos_weight > 0.0f)) return fail(GG_E_INVAL, "pos_weight <= 0");
-  GG_TRY(mlp_scratch(mlp, n));
-  GG_HIP(launch_mlp_grad(mlp->d, feat_dev, label_dev, n, pos_weight, mlp->scratch, grad_dev, mlp->stream));
-  GG_HIP(hipStreamSynchronize(mlp->stream));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!mlp || !grad_dev || (n > 0 && (!feat_dev || !label_dev))) return fail(GG_E_INVAL, "null argument");
+    if (n <= 0) return fail(GG_E_INVAL, "n <= 0");
+    if (!(pos_weight > 0.0f)) return fail(GG_E_INVAL, "pos_weight <= 0");
+    GG_TRY(mlp_scratch(mlp, n));
+    GG_HIP(launch_mlp_grad(mlp->d, feat_dev, label_dev, n, pos_weight, mlp->scratch, grad_dev, mlp->stream));
+    GG_HIP(hipStreamSynchronize(mlp->stream));
+    return GG_OK;
+  });
 }
 
 int gg_mlp_adam_step(gg_mlp* mlp, const float* grad_dev, float lr) {
-  if (!mlp || !grad_dev) return fail(GG_E_INVAL, "null argument");
-  if (!(lr > 0.0f)) return fail(GG_E_INVAL, "lr <= 0");
-  GG_TRY(mlp_adam(mlp, grad_dev, lr));
-  GG_HIP(hipStreamSynchronize(mlp->stream));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!mlp || !grad_dev) return fail(GG_E_INVAL, "null argument");
+    if (!(lr > 0.0f)) return fail(GG_E_INVAL, "lr <= 0");
+    GG_TRY(mlp_adam(mlp, grad_dev, lr));
+    GG_HIP(hipStreamSynchronize(mlp->stream));
+    return GG_OK;
+  });
 }
 
 int gg_mlp_train(gg_mlp* mlp, const gg_trace* trace, int32_t epochs, int32_t batch, float lr, float pos_weight,
                  uint64_t seed, float* epoch_loss_host) {
-  if (!mlp || !trace) return fail(GG_E_INVAL, "null argument");
-  if (epochs < 1 || batch < 16) return fail(GG_E_INVAL, "epochs < 1 or batch < 16");
-  if (!(lr > 0.0f) || !(pos_weight > 0.0f)) return fail(GG_E_INVAL, "lr and pos_weight must be > 0");
-  const int64_t size = trace->size;
-  if (size <= 0) return fail(GG_E_STATE, "empty trace");
-  // the trace was filled on a graph's stream
-  GG_HIP(hipDeviceSynchronize());
-  GG_TRY(mlp_scratch(mlp, batch));
-  if (mlp->loss_cap < epochs) {
-    dfree(mlp->loss);
-    mlp->loss_cap = 0;
-    GG_TRY(dalloc(&mlp->loss, (size_t)epochs));
-    mlp->loss_cap = epochs;
-  }
-  GG_HIP(launch_fill_u32((uint32_t*)mlp->loss, epochs, 0u, mlp->stream));
-  const int64_t nb = (size + batch - 1) / batch;
-  std::vector<int64_t> order((size_t)nb);
-  uint64_t x = seed;
-  for (int32_t e = 0; e < epochs; ++e) {
-    for (int64_t b = 0; b < nb; ++b) order[(size_t)b] = b;
-    for (int64_t b = nb - 1; b > 0; --b) {
-      const int64_t j = (int64_t)(splitmix64(x) % (uint64_t)(b + 1));
-      std::swap(order[(size_t)b], order[(size_t)j]);
+  return guard([&]() -> int {
+    if (!mlp || !trace) return fail(GG_E_INVAL, "null argument");
+    if (epochs < 1 || batch < 16) return fail(GG_E_INVAL, "epochs < 1 or batch < 16");
+    if (!(lr > 0.0f) || !(pos_weight > 0.0f)) return fail(GG_E_INVAL, "lr and pos_weight must be > 0");
+    const int64_t size = trace->size;
+    if (size <= 0) return fail(GG_E_STATE, "empty trace");
+    // the trace was filled on a graph's stream
+    GG_HIP(hipDeviceSynchronize());
+    GG_TRY(mlp_scratch(mlp, batch));
+    if (mlp->loss_cap < epochs) {
+      dfree(mlp->loss);
+      mlp->loss_cap = 0;
+      GG_TRY(dalloc(&mlp->loss, (size_t)epochs));
+      mlp->loss_cap = epochs;
     }
-    for (int64_t k = 0; k < nb; ++k) {
-      const int64_t b0 = order[(size_t)k] * batch;
-      const int64_t bn = size - b0 < batch ? size - b0 : batch;
-      GG_HIP(launch_mlp_grad(mlp->d, trace->feat + b0 * 8, trace->label + b0, bn, pos_weight, mlp->scratch, mlp->grad,
-                             mlp->stream));
-      GG_TRY(mlp_adam(mlp, mlp->grad, lr));
-      GG_HIP(launch_add_f32(mlp->grad + kMlpParams, mlp->loss + e, mlp->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)mlp->loss, epochs, 0u, mlp->stream));
+    const int64_t nb = (size + batch - 1) / batch;
+    std::vector<int64_t> order((size_t)nb);
+    uint64_t x = seed;
+    for (int32_t e = 0; e < epochs; ++e) {
+      for (int64_t b = 0; b < nb; ++b) order[(size_t)b] = b;
+      for (int64_t b = nb - 1; b > 0; --b) {
+        const int64_t j = (int64_t)(splitmix64(x) % (uint64_t)(b + 1));
+        std::swap(order[(size_t)b], order[(size_t)j]);
+      }
+      for (int64_t k = 0; k < nb; ++k) {
+        const int64_t b0 = order[(size_t)k] * batch;
+        const int64_t bn = size - b0 < batch ? size - b0 : batch;
+        GG_HIP(launch_mlp_grad(mlp->d, trace->feat + b0 * 8, trace->label + b0, bn, pos_weight, mlp->scratch, mlp->grad,
+                               mlp->stream));
+        GG_TRY(mlp_adam(mlp, mlp->grad, lr));
+        GG_HIP(launch_add_f32(mlp->grad + kMlpParams, mlp->loss + e, mlp->stream));
+      }
     }
-  }
-  std::vector<float> h((size_t)epochs);
-  GG_HIP(hipMemcpyAsync(h.data(), mlp->loss, sizeof(float) * epochs, hipMemcpyDeviceToHost, mlp->stream));
-  GG_HIP(hipStreamSynchronize(mlp->stream));
-  if (epoch_loss_host)
-    for (int32_t e = 0; e < epochs; ++e) epoch_loss_host[e] = h[(size_t)e] / (float)size;
-  return GG_OK;
+    std::vector<float> h((size_t)epochs);
+    GG_HIP(hipMemcpyAsync(h.data(), mlp->loss, sizeof(float) * epochs, hipMemcpyDeviceToHost, mlp->stream));
+    GG_HIP(hipStreamSynchronize(mlp->stream));
+    if (epoch_loss_host)
+      for (int32_t e = 0; e < epochs; ++e) epoch_loss_host[e] = h[(size_t)e] / (float)size;
+    return GG_OK;
+  });
 }
 
 int gg_trace_create(int64_t capacity, gg_trace** out) {
-  if (!out) return fail(GG_E_INVAL, "null output");
-  *out = nullptr;
-  if (capacity < 1 || capacity > ((int64_t)1 << 34)) return fail(GG_E_INVAL, "capacity outside [1, 2^34]");
-  gg_trace* t = new (std::nothrow) gg_trace();
-  if (!t) return fail(GG_E_NOMEM, "host allocation failed");
-  t->cap = capacity;
-  int rc = dalloc(&t->feat, (size_t)capacity * 8);
-  if (rc == GG_OK) rc = dalloc(&t->label, (size_t)capacity);
-  if (rc == GG_OK) rc = dalloc(&t->pos, 1);
-  if (rc == GG_OK && hipMemset(t->pos, 0, sizeof(unsigned long long)) != hipSuccess)
-    rc = fail(GG_E_DEVICE, "trace counter reset failed");
-  if (rc != GG_OK) {
-    gg_trace_free(t);
-    return rc;
-  }
-  *out = t;
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!out) return fail(GG_E_INVAL, "null output");
+    *out = nullptr;
+    if (capacity < 1 || capacity > ((int64_t)1 << 34)) return fail(GG_E_INVAL, "capacity outside [1, 2^34]");
+    gg_trace* t = new (std::nothrow) gg_trace();
+    if (!t) return fail(GG_E_NOMEM, "host allocation failed");
+    t->cap = capacity;
+    int rc = dalloc(&t->feat, (size_t)capacity * 8);
+    if (rc == GG_OK) rc = dalloc(&t->label, (size_t)capacity);
+    if (rc == GG_OK) rc = dalloc(&t->pos, 1);
+    if (rc == GG_OK && hipMemset(t->pos, 0, sizeof(unsigned long long)) != hipSuccess)
+      rc = fail(GG_E_DEVICE, "trace counter reset failed");
+    if (rc != GG_OK) {
+      gg_trace_free(t);
+      return rc;
+    }
+    *out = t;
+    return GG_OK;
+  });
 }
 
 void gg_trace_free(gg_trace* t) {
-  if (!t) return;
-  (void)hipDeviceSynchronize();
-  dfree(t->feat);
-  dfree(t->label);
-  dfree(t->pos);
-  delete t;
+  try {
+    if (!t) return;
+    (void)hipDeviceSynchronize();
+    dfree(t->feat);
+    dfree(t->label);
+    dfree(t->pos);
+    delete t;
+  } catch (...) {
+  }
 }
 
 int gg_trace_clear(gg_trace* t) {
-  if (!t) return fail(GG_E_INVAL, "null trace");
-  GG_HIP(hipDeviceSynchronize());
-  GG_HIP(hipMemset(t->pos, 0, sizeof(unsigned long long)));
-  t->size = t->dropped = 0;
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!t) return fail(GG_E_INVAL, "null trace");
+    GG_HIP(hipDeviceSynchronize());
+    GG_HIP(hipMemset(t->pos, 0, sizeof(unsigned long long)));
+    t->size = t->dropped = 0;
+    return GG_OK;
+  });
 }
 
 int gg_trace_info(gg_trace* t, int64_t* size, int64_t* positives, int64_t* dropped) {
-  if (!t) return fail(GG_E_INVAL, "null trace");
-  GG_HIP(hipDeviceSynchronize());
-  unsigned long long p = 0;
-  GG_HIP(hipMemcpy(&p, t->pos, sizeof(p), hipMemcpyDeviceToHost));
-  if (size) *size = t->size;
-  if (positives) *positives = (int64_t)p;
-  if (dropped) *dropped = t->dropped;
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!t) return fail(GG_E_INVAL, "null trace");
+    GG_HIP(hipDeviceSynchronize());
+    unsigned long long p = 0;
+    GG_HIP(hipMemcpy(&p, t->pos, sizeof(p), hipMemcpyDeviceToHost));
+    if (size) *size = t->size;
+    if (positives) *positives = (int64_t)p;
+    if (dropped) *dropped = t->dropped;
+    return GG_OK;
+  });
 }
 
 int gg_trace_export(gg_trace* t, int64_t first, int64_t count, uint16_t* feat_host, float* label_host) {
-  if (!t) return fail(GG_E_INVAL, "null trace");
-  if (first < 0 || count < 0 || first + count > t->size) return fail(GG_E_RANGE, "samples outside the trace");
-  GG_HIP(hipDeviceSynchronize());
-  if (count == 0) return GG_OK;
-  if (feat_host) GG_HIP(hipMemcpy(feat_host, t->feat + first * 8, (size_t)count * 16, hipMemcpyDeviceToHost));
-  if (label_host) GG_HIP(hipMemcpy(label_host, t->label + first, (size_t)count * 4, hipMemcpyDeviceToHost));
-  return GG_OK;
+  return guard([&]() -> int {
+    if (!t) return fail(GG_E_INVAL, "null trace");
+    if (first < 0 || count < 0 || first + count > t->size) return fail(GG_E_RANGE, "samples outside the trace");
+    GG_HIP(hipDeviceSynchronize());
+    if (count == 0) return GG_OK;
+    if (feat_host) GG_HIP(hipMemcpy(feat_host, t->feat + first * 8, (size_t)count * 16, hipMemcpyDeviceToHost));
+    if (label_host) GG_HIP(hipMemcpy(label_host, t->label + first, (size_t)count * 4, hipMemcpyDeviceToHost));
+    return GG_OK;
+  });
 }
 
 }  // extern "C"
