@@ -1844,12 +1844,15 @@ hipError_t launch_build_out(const int32_t* rowptr, const int32_t* col, int32_t n
 }
 
 // ---- changed list after a dense iteration ----------------------------------
-__global__ __launch_bounds__(kBlock) void k_chg_count(const uint8_t* chg, int n, int32_t* blk) {
+// Per-block counts of changed vertices; block 0 also clears the touched
+// counter (the count and the out-degree sum are written by later kernels).
+__global__ __launch_bounds__(kBlock) void k_chg_count(const uint8_t* chg, int n, int32_t* blk, FrontCounters* fc) {
   __shared__ int ilds[4];
   const int u = blockIdx.x * kBlock + threadIdx.x;
   int tot;
   block_rank(u < n && chg[u], ilds, tot);
   if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) fc->touched = 0;
 }
 
 // Per-block out-degree sums go to psum[block]; k_sum_i64 adds them.
@@ -1887,10 +1890,9 @@ __global__ __launch_bounds__(1024) void k_sum_i64(const int64_t* psum, int count
 
 hipError_t launch_compact_changed(const uint8_t* chg, const int32_t* outdeg, int32_t n, int32_t* list,
                                   FrontCounters* fc, int32_t* blk_scratch, int64_t* psum, hipStream_t st) {
-  hipError_t e = launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
-  if (e != hipSuccess || n == 0) return e;
+  if (n == 0) return launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
   const int nblk = (n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_chg_count, dim3(nblk), dim3(kBlock), 0, st, chg, n, blk_scratch);
+  hipLaunchKernelGGL(k_chg_count, dim3(nblk), dim3(kBlock), 0, st, chg, n, blk_scratch, fc);
   hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, blk_scratch, nblk, &fc->count);
   hipLaunchKernelGGL(k_chg_scatter, dim3(nblk), dim3(kBlock), 0, st, chg, outdeg, n, blk_scratch, list, psum);
   hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(1024), 0, st, psum, nblk, &fc->outdeg_sum);
@@ -1920,6 +1922,30 @@ __global__ void k_front_prep(Sweep s, const int32_t* front, int32_t nfront, cons
     fdeg[i] = orow[v + 1] - orow[v];
     atomicMin(&s.x_next[v], s.x_in[v]);
   }
+}
+
+// Frontiers up to this size are prepared and scanned by one 1024-thread
+// block (one launch instead of four).
+constexpr int kFrontOneBlock = 16384;
+
+// One-block form of the push preparation: clears the counters, writes the
+// frontier out-degrees to fscan, lets the next buffer catch up with each
+// frontier vertex's current value, and scans fscan in place (fscan[nfront] =
+// total).
+__global__ __launch_bounds__(1024) void k_front_prep_scan(Sweep s, const int32_t* front, int32_t nfront,
+                                                          const int32_t* orow, int32_t* fscan, FrontCounters* fc) {
+  if (threadIdx.x == 0) {
+    fc->count = 0;
+    fc->touched = 0;
+    fc->outdeg_sum = 0;
+  }
+  for (int i = threadIdx.x; i < nfront; i += 1024) {
+    const int v = front[i];
+    fscan[i] = orow[v + 1] - orow[v];
+    atomicMin(&s.x_next[v], s.x_in[v]);
+  }
+  __syncthreads();
+  block1024_exclusive_scan(fscan, nfront, fscan + nfront);
 }
 
 constexpr int kPushEdgesPerBlock = 1024;
@@ -2003,12 +2029,18 @@ hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nf
                        const int32_t* orow, const int32_t* oedge, const int32_t* odst, const uint32_t* bits,
                        uint32_t* stamp, uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc,
                        int32_t* fdeg, int32_t* fscan, int32_t* scan_scratch, int64_t* psum, hipStream_t st) {
-  hipError_t e = launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
-  if (e != hipSuccess || nfront == 0) return e;
-  hipLaunchKernelGGL(k_front_prep, dim3((nfront + kBlock - 1) / kBlock), dim3(kBlock), 0, st, s, front, nfront, orow,
-                     fdeg);
-  e = launch_scan(fdeg, fscan, nfront, fscan + nfront, scan_scratch, st);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (nfront == 0) return launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
+  if (nfront <= kFrontOneBlock) {
+    hipLaunchKernelGGL(k_front_prep_scan, dim3(1), dim3(1024), 0, st, s, front, nfront, orow, fscan, fc);
+  } else {
+    e = launch_fill_u32((uint32_t*)fc, sizeof(FrontCounters) / 4, 0u, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_front_prep, dim3((nfront + kBlock - 1) / kBlock), dim3(kBlock), 0, st, s, front, nfront,
+                       orow, fdeg);
+    e = launch_scan(fdeg, fscan, nfront, fscan + nfront, scan_scratch, st);
+    if (e != hipSuccess) return e;
+  }
   const int g = grid_for(front_outdeg > 0 ? front_outdeg : 1, kPushEdgesPerBlock, 1 << 20);
   if (app == kSSSP)
     hipLaunchKernelGGL((k_push<kSSSP>), dim3(g), dim3(kBlock), 0, st, s, front, nfront, fscan, orow, oedge, odst,
@@ -2016,8 +2048,17 @@ hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nf
   else
     hipLaunchKernelGGL((k_push<kCC>), dim3(g), dim3(kBlock), 0, st, s, front, nfront, fscan, orow, oedge, odst,
                        bits, stamp, epoch, touched, fc);
-  hipLaunchKernelGGL(k_push_finalize, dim3(kFinalizeBlocks), dim3(kBlock), 0, st, s, touched, next, fc, psum);
-  hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(1024), 0, st, psum, kFinalizeBlocks, &fc->outdeg_sum);
+  // at most one touched vertex per pushed edge: a frontier of few out-edges
+  // is finalized by one block, which writes the out-degree sum itself
+  const int64_t fin = (front_outdeg + kBlock - 1) / kBlock;
+  const int gf = (int)std::max<int64_t>(1, std::min<int64_t>(kFinalizeBlocks, fin));
+  if (gf == 1) {
+    hipLaunchKernelGGL(k_push_finalize, dim3(1), dim3(kBlock), 0, st, s, touched, next, fc,
+                       (int64_t*)&fc->outdeg_sum);
+  } else {
+    hipLaunchKernelGGL(k_push_finalize, dim3(gf), dim3(kBlock), 0, st, s, touched, next, fc, psum);
+    hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(1024), 0, st, psum, gf, &fc->outdeg_sum);
+  }
   return hipGetLastError();
 }
 

@@ -867,9 +867,11 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   } else {
     s.x_in = g->xu[r->cur];
     s.x_next = g->xu[1 - r->cur];
-    GG_HIP(launch_fill_u32((uint32_t*)g->changed, 1, 0u, g->stream));
   }
   const bool frontier = !pr && g->tune.frontier_enable && g->out_built;
+  // with the frontier the changed count comes from the compacted list and
+  // the counter is never read
+  if (!pr && !frontier) GG_HIP(launch_fill_u32((uint32_t*)g->changed, 1, 0u, g->stream));
   if (frontier) GG_TRY(ensure_out(g));
   // A push from the changed vertices is exact when this iteration's edge set
   // is contained in the previous one's: not at a superstep, not at a switch
