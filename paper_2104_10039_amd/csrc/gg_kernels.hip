@@ -410,7 +410,9 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
       const bool valid = k < len;
       const int e = b + k;
       const uint32_t ev = evq[q];
-      const uint32_t oldf = (valid && s.old_bits) ? edge_bit(s.old_bits, e) : 0u;
+      // the old flag matters only for SSSP (unassessable edges) and UNION
+      const uint32_t oldf =
+          (valid && s.old_bits && (APP == kSSSP || s.mask_union)) ? edge_bit(s.old_bits, e) : 0u;
       bool flag;
       T chunk_total;
       if constexpr (APP == kPR || APP == kPPR) {
@@ -470,7 +472,7 @@ __device__ __forceinline__ bool hub_step(const Sweep& s, int b, int sub, int e1,
   const int k = sub + (int)threadIdx.x;
   const bool valid = k < e1;
   const int e = b + k;
-  const uint32_t oldf = (valid && s.old_bits) ? edge_bit(s.old_bits, e) : 0u;
+  const uint32_t oldf = (valid && s.old_bits && (APP == kSSSP || s.mask_union)) ? edge_bit(s.old_bits, e) : 0u;
   bool flag;
   T sub_total;
   if constexpr (APP == kPR || APP == kPPR) {

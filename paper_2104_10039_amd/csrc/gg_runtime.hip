@@ -887,21 +887,28 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     s.chg = g->chg;
     s.changed = nullptr;
   }
+  // A push from an empty frontier changes nothing (both value buffers already
+  // hold the current values), so such an iteration launches no work at all:
+  // an approximate run whose sampled edges have converged idles this way
+  // until its next superstep.
+  const bool idle = sparse && r->front_count == 0;
   int64_t edges;
   int64_t processed;
-  hipEvent_t pe0, pe1;
-  GG_TRY(prof_events(g, &pe0, &pe1));
+  hipEvent_t pe0 = nullptr, pe1 = nullptr;
+  if (!idle) GG_TRY(prof_events(g, &pe0, &pe1));
   int pkind;
   if (sparse) {
     pkind = accurate ? 0 : 1;
-    s.edges = full_edges(g, app);
-    const uint32_t* bits = accurate ? nullptr : g->bits[r->bcur];
-    g->epoch++;
-    if (pe0) GG_HIP(hipEventRecord(pe0, g->stream));
-    GG_HIP(launch_push(app, s, g->flist[r->fcur], (int32_t)r->front_count, r->front_outdeg, g->orow, g->oedge,
-                       g->odst, bits, g->stamp, g->epoch, g->touched, g->flist[1 - r->fcur], g->fc, g->fdeg, g->fscan,
-                       (int32_t*)g->blk_scratch, g->psum, g->stream));
-    if (pe1) GG_HIP(hipEventRecord(pe1, g->stream));
+    if (!idle) {
+      s.edges = full_edges(g, app);
+      const uint32_t* bits = accurate ? nullptr : g->bits[r->bcur];
+      g->epoch++;
+      if (pe0) GG_HIP(hipEventRecord(pe0, g->stream));
+      GG_HIP(launch_push(app, s, g->flist[r->fcur], (int32_t)r->front_count, r->front_outdeg, g->orow, g->oedge,
+                         g->odst, bits, g->stamp, g->epoch, g->touched, g->flist[1 - r->fcur], g->fc, g->fdeg,
+                         g->fscan, (int32_t*)g->blk_scratch, g->psum, g->stream));
+      if (pe1) GG_HIP(hipEventRecord(pe1, g->stream));
+    }
     edges = accurate ? g->m : g->act.h.edges;
     processed = r->front_outdeg;
     r->sparse_iters++;
@@ -1047,7 +1054,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   if (frontier && !sparse)
     GG_HIP(launch_compact_changed(g->chg, g->outdeg, g->n, g->flist[1 - r->fcur], g->fc, (int32_t*)g->blk_scratch,
                                   g->psum, g->stream));
-  if (g->prof) {
+  if (g->prof && !idle) {
     double bytes = alg_bytes(pkind == 4 ? 2 : pkind, g->n, edges, s.x_out != nullptr);
     if (pkind == 2) bytes += 4.0 * (double)g->act.h.edges + (double)((g->m + 31) / 32) * 4.0;
     if (sparse) {
@@ -1065,9 +1072,11 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   r->edges_processed += processed;
   int64_t changed = -1;
   if (frontier) {
-    FrontCounters h;
-    GG_HIP(hipMemcpyAsync(&h, g->fc, sizeof(h), hipMemcpyDeviceToHost, g->stream));
-    GG_HIP(hipStreamSynchronize(g->stream));
+    FrontCounters h = {0, 0, 0};
+    if (!idle) {
+      GG_HIP(hipMemcpyAsync(&h, g->fc, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+      GG_HIP(hipStreamSynchronize(g->stream));
+    }
     r->fcur = 1 - r->fcur;
     r->front_count = h.count;
     r->front_outdeg = h.outdeg_sum;

@@ -127,9 +127,11 @@ def test_approx_int_apps_tunings(P, ti):
 # Step-by-step parity with per-superstep flag comparison
 # ---------------------------------------------------------------------------
 
-def step_compare(P, g, app, policy, tuning=None, **kw):
+def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
     """Run both sides one iteration at a time; compare values every iteration
-    and the edge flags after every superstep. Returns the worst PR error."""
+    and the edge flags after every superstep. Returns the worst PR error.
+    `stats` (a dict), when given, receives the number of idle iterations (a
+    push from an empty frontier) and of supersteps that followed one."""
     G = load(P, g, tuning)
     sr = kw.pop("sample_ratio", 1.0)
     R = G.begin(app, sr, policy, **kw)
@@ -147,6 +149,13 @@ def step_compare(P, g, app, policy, tuning=None, **kw):
         assert a["edges"] == b.edges, (a, b)
         if a.get("sparse"):
             log("iter", b.iter, "ran as a frontier push over", a["edges_processed"], "edges")
+        if stats is not None:
+            if a["sparse"] and a["edges_processed"] == 0:
+                stats["idle"] = stats.get("idle", 0) + 1
+                stats["pending"] = True
+            elif a["superstep"] and stats.get("pending"):
+                stats["super_after_idle"] = stats.get("super_after_idle", 0) + 1
+                stats["pending"] = False
         if app in ("sssp", "cc"):
             assert a["changed"] == b.changed, (a, b)
         if a["superstep"]:
@@ -380,6 +389,22 @@ def test_retune_same_graph(P):
         out, _ = G.approx_run("sssp", 0.4, "gg", alpha=2, theta=0.1, seed=5, source=s, iters=12)
         compare_values("sssp", device_values(out, "sssp"), ref_gg, ctx=str(t))
     G.close()
+
+
+@pytest.mark.parametrize("app", ["sssp", "cc"])
+def test_idle_iterations_then_superstep(P, app):
+    """Approximate iterations after the sampled edges have converged push from
+    an empty frontier and launch nothing; the supersteps that follow still
+    match the oracle step by step (values, flags, changed counts)."""
+    g = graph_for(app, 14, seed=9)
+    s = int(gg.pick_sources(g, 1, 9)[0])
+    st = {}
+    # windows of 14 approximate iterations: longer than the sampled graph
+    # needs to converge on this input
+    step_compare(P, g, app, "gg", tuning=dict(frontier_enable=1, frontier_div=1), stats=st, sample_ratio=0.3,
+                 alpha=14, theta=0.05, seed=4, source=s, iters=45)
+    log(app, "idle iterations", st)
+    assert st.get("idle", 0) > 0 and st.get("super_after_idle", 0) > 0
 
 
 @pytest.mark.parametrize("app", ["sssp", "cc"])
