@@ -608,6 +608,10 @@ __device__ __forceinline__ W wait_word(W* p, uint32_t* err) {
   return v;
 }
 
+// Gathered value in its stored width (defined with the flat batches below).
+template <int APP>
+struct GV;
+
 // Hub chunk of a superstep in a single pass (hub_chunk <= kHubPre * kBlock).
 // Blocks take tickets in dispatch order and process the chunk at that position
 // of chunk_order (the natural order when null); the order keeps the chunks of
@@ -645,9 +649,11 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
   const int len = s.rowptr[u + 1] - b;
   const int e0 = j * s.hub_chunk;
   const int e1 = min(len, e0 + s.hub_chunk);
-  // gather: every edge of the chunk, all loads in flight together
+  // gather: every edge of the chunk, all loads in flight together, values
+  // held in their stored width (binary32 contributions for PR)
+  using V = typename GV<APP>::V;
   uint32_t evq[kHubPre];
-  T vq[kHubPre];
+  V vq[kHubPre];
 #pragma unroll
   for (int q = 0; q < kHubPre; ++q) {
     const int k = e0 + q * kBlock + (int)threadIdx.x;
@@ -656,11 +662,11 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
 #pragma unroll
   for (int q = 0; q < kHubPre; ++q) {
     const int k = e0 + q * kBlock + (int)threadIdx.x;
-    vq[q] = k < e1 ? R::elem(s, evq[q]) : R::id();
+    vq[q] = k < e1 ? GV<APP>::get(s, evq[q]) : (V)R::id();
   }
   T acc = R::id();
 #pragma unroll
-  for (int q = 0; q < kHubPre; ++q) acc = R::op(acc, vq[q]);
+  for (int q = 0; q < kHubPre; ++q) acc = R::op(acc, GV<APP>::widen(vq[q]));
   acc = block_reduce<APP>(acc, lds);
   if (threadIdx.x == 0) __hip_atomic_store(tot_w + ch, pack_total<APP>(acc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // row prefix: totals of chunks c0 .. ch-1, lane i takes i, i + 64, ...
@@ -678,7 +684,7 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
   for (int q = 0; q < kHubPre; ++q) {
     const int sub = e0 + q * kBlock;
     fq[q] = false;
-    if (sub < e1) fq[q] = hub_step<APP>(s, b, sub, e1, vq[q], carry, lds);  // uniform over the block
+    if (sub < e1) fq[q] = hub_step<APP>(s, b, sub, e1, GV<APP>::widen(vq[q]), carry, lds);  // uniform over the block
     const int c = __popcll(__ballot(fq[q]));
     if (lane == 0) s_cnt[q][wid] = c;
   }
@@ -2253,8 +2259,11 @@ hipError_t launch_gather_i32(const int32_t* src, const int32_t* idx, int32_t cou
 // ===========================================================================
 namespace ggk {
 
+// Seven waves per SIMD: the hub section otherwise holds the PR instance at six
+// (SSSP and CC reach eight).
 template <int APP>
-__global__ __launch_bounds__(kBlock) void k_super_flat(Sweep s, int nchunks, int gw) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_super_flat(Sweep s, int nchunks,
+                                                                                              int gw) {
   using R = Tr<APP>;
   using T = typename R::T;
   using V = typename GV<APP>::V;

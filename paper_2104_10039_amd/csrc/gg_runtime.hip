@@ -89,7 +89,7 @@ struct gg_graph {
   int32_t n_dang = 0;
   int32_t* i32_scratch = nullptr;  // small device scalars: [0] dangling count, [1] validate flags
   void* blk_scratch = nullptr;
-  gg_tuning tune{32, 4, 512, 2048, 1, 0, 1, 16};
+  gg_tuning tune{32, 4, 1024, 2048, 1, 0, 1, 16};
   bool rows_sorted = true;  // every row lists its sources in ascending order (else no segmentation)
   // frontier (SSSP / CC): out-CSR structure and lists, built on first use
   bool out_built = false;

@@ -18,6 +18,9 @@ pytestmark = pytest.mark.gpu
 
 TUNINGS = [
     # default
+    dict(small_max=32, small_team=4, wave_max=1024, hub_chunk=2048, seg_enable=1, seg_vertices=0,
+         frontier_enable=1, frontier_div=16),
+    # the earlier default
     dict(small_max=32, small_team=4, wave_max=512, hub_chunk=2048, seg_enable=1, seg_vertices=0,
          frontier_enable=1, frontier_div=16),
     # many multi-chunk hubs, many source segments (several per die), push whenever the frontier allows
