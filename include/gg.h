@@ -47,7 +47,7 @@ typedef enum {
   GG_E_NOMEM = -3,       /* device or host allocation failed */
   GG_E_DEVICE = -4,      /* HIP runtime error, or a device-side wait of a superstep that gave up
                             (the results since the last check are undefined); gg_last_error() holds its text */
-  GG_E_UNSUPPORTED = -5, /* valid request that this build does not implement */
+  GG_E_UNSUPPORTED = -5, /* valid request that the library does not implement */
   GG_E_STATE = -6        /* call not valid in the current state of the handle */
 } gg_status;
 
@@ -150,7 +150,7 @@ typedef struct {
   float tau;           /* selection threshold on the binary32 logit */
   double rho;          /* full superstep when the rows of S hold > rho * m in-edges, rho >= 0 */
   int32_t fallback_k;  /* every fallback_k-th correction step is full; 0 = never */
-  int32_t judge;       /* 1: at full supersteps, score the selection against the drift labels */
+  int32_t audit;       /* 1: at full supersteps, score the selection against the drift labels */
   /* GG and LEARNED: optional trace (NULL = none). At every full superstep the
      features of each vertex and its drift label are appended. */
   gg_trace* trace;
@@ -167,9 +167,9 @@ typedef struct {
   int32_t sparse_iterations;/* SSSP/CC iterations run as frontier pushes */
   int32_t partial_supersteps; /* LEARNED: partial supersteps executed */
   int64_t selected_total;   /* LEARNED: sum of |S| over correction steps */
-  int64_t judge_positives;  /* judged full supersteps: vertices that drifted */
-  int64_t judge_hits;       /* ... of which the network selected */
-  int64_t judge_selected;   /* ... vertices the network selected */
+  int64_t audit_positives;  /* audited full supersteps: vertices that drifted */
+  int64_t audit_hits;       /* ... of which the network selected */
+  int64_t audit_selected;   /* ... vertices the network selected */
 } gg_run_stats;
 
 typedef struct {
@@ -278,7 +278,7 @@ int gg_run_stats_get(gg_run* run, gg_run_stats* stats);
 /* Per-vertex state of the last correction step (LEARNED) or traced full
    superstep, copied to host memory: features [n][8] bfloat16 bits; the
    selection (1 byte per vertex) and binary32 logits of a LEARNED correction
-   step; the drift labels (1 byte per vertex) of a traced or judged full
+   step; the drift labels (1 byte per vertex) of a traced or audited full
    superstep. GG_E_STATE when the last step produced no such data. */
 int gg_run_features(gg_run* run, uint16_t* feat_host);
 int gg_run_selection(gg_run* run, uint8_t* sel_host, float* logits_host);

@@ -57,7 +57,7 @@ class Policy(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("alpha", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("influence", ctypes.c_int32), ("mask_update", ctypes.c_int32),
                 ("stop", ctypes.c_int32), ("mlp", ctypes.c_void_p), ("tau", ctypes.c_float), ("rho", ctypes.c_double),
-                ("fallback_k", ctypes.c_int32), ("judge", ctypes.c_int32), ("trace", ctypes.c_void_p),
+                ("fallback_k", ctypes.c_int32), ("audit", ctypes.c_int32), ("trace", ctypes.c_void_p),
                 ("label_eps", ctypes.c_float)]
 
 
@@ -65,8 +65,8 @@ class RunStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("supersteps", ctypes.c_int32), ("edges_gathered", ctypes.c_int64),
                 ("active_edges", ctypes.c_int64), ("device_ms", ctypes.c_double), ("edges_processed", ctypes.c_int64),
                 ("sparse_iterations", ctypes.c_int32), ("partial_supersteps", ctypes.c_int32),
-                ("selected_total", ctypes.c_int64), ("judge_positives", ctypes.c_int64), ("judge_hits", ctypes.c_int64),
-                ("judge_selected", ctypes.c_int64)]
+                ("selected_total", ctypes.c_int64), ("audit_positives", ctypes.c_int64), ("audit_hits", ctypes.c_int64),
+                ("audit_selected", ctypes.c_int64)]
 
 
 class StepInfo(ctypes.Structure):
@@ -193,15 +193,15 @@ class Stats:
     sparse_iterations: int
     partial_supersteps: int = 0
     selected_total: int = 0
-    judge_positives: int = 0
-    judge_hits: int = 0
-    judge_selected: int = 0
+    audit_positives: int = 0
+    audit_hits: int = 0
+    audit_selected: int = 0
 
 
 def _stats(s: RunStats) -> Stats:
     return Stats(s.iterations, s.supersteps, s.edges_gathered, s.active_edges, s.device_ms, s.edges_processed,
-                 s.sparse_iterations, s.partial_supersteps, s.selected_total, s.judge_positives, s.judge_hits,
-                 s.judge_selected)
+                 s.sparse_iterations, s.partial_supersteps, s.selected_total, s.audit_positives, s.audit_hits,
+                 s.audit_selected)
 
 
 def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform"):
@@ -209,13 +209,13 @@ def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangli
 
 
 def _policy(policy="gg", alpha=4, theta=0.05, seed=1, influence="prefix", mask_update="replace",
-            stop="fixed_iters", mlp=None, tau=0.0, rho=1.0, fallback_k=0, judge=False, trace=None, label_eps=1e-3):
+            stop="fixed_iters", mlp=None, tau=0.0, rho=1.0, fallback_k=0, audit=False, trace=None, label_eps=1e-3):
     return Policy(POLICY[policy], alpha, theta, seed, INFLUENCE[influence], MASK[mask_update], STOP[stop],
-                  None if mlp is None else mlp.handle.value, float(tau), float(rho), int(fallback_k), int(bool(judge)),
+                  None if mlp is None else mlp.handle.value, float(tau), float(rho), int(fallback_k), int(bool(audit)),
                   None if trace is None else trace.handle.value, float(label_eps))
 
 
-LEARNED_KW = ("mlp", "tau", "rho", "fallback_k", "judge", "trace", "label_eps")
+LEARNED_KW = ("mlp", "tau", "rho", "fallback_k", "audit", "trace", "label_eps")
 
 
 class Graph:
@@ -338,7 +338,7 @@ class Graph:
                    influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
                    max_iters=1 << 20, source=0, dangling="uniform", **learned):
         """gg_approx_run: returns (values tensor on the device, Stats). Learned-policy
-        and trace arguments: mlp, tau, rho, fallback_k, judge, trace, label_eps."""
+        and trace arguments: mlp, tau, rho, fallback_k, audit, trace, label_eps."""
         bad = set(learned) - set(LEARNED_KW)
         if bad:
             raise TypeError("unknown arguments %s" % sorted(bad))
@@ -427,7 +427,7 @@ class Run:
         return sel[: self.graph.n], lg[: self.graph.n]
 
     def labels(self) -> np.ndarray:
-        """Drift labels uint8 [n] of the last traced or judged full superstep."""
+        """Drift labels uint8 [n] of the last traced or audited full superstep."""
         out = np.zeros(max(self.graph.n, 1), dtype=np.uint8)
         _check(lib().gg_run_labels(self._h, out.ctypes.data))
         return out[: self.graph.n]

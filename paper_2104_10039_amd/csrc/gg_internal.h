@@ -289,7 +289,7 @@ hipError_t launch_feat_base(int32_t n, const int32_t* rowptr, const int32_t* out
 hipError_t launch_feat_shift(int app, int32_t n, const uint32_t* now, const uint32_t* before, uint16_t* feat,
                              hipStream_t st);
 hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t* apx, float eps, const uint8_t* sel,
-                         uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* judge,
+                         uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* audit,
                          unsigned long long* trace_pos, hipStream_t st);
 hipError_t launch_add_f32(const float* src, float* dst, hipStream_t st);
 hipError_t launch_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,

@@ -615,10 +615,10 @@ __global__ void k_feat_shift(int app, int32_t n, const uint32_t* now, const uint
 // Drift labels of a full superstep: acc = accurate update, apx = the
 // approximate update from the same state. PR/PPR (binary32 contributions):
 // |acc - apx| > eps * acc; SSSP/CC: acc < apx. label_u8 gets every label,
-// label_f the first nf (a trace's free room); judge[0] += positives and
-// judge[1] += positives that sel marks; trace_pos += positives among the first nf.
+// label_f the first nf (a trace's free room); audit[0] += positives and
+// audit[1] += positives that sel marks; trace_pos += positives among the first nf.
 __global__ void k_labels(int app, int32_t n, const uint32_t* acc, const uint32_t* apx, float eps, const uint8_t* sel,
-                         uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* judge,
+                         uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* audit,
                          unsigned long long* trace_pos) {
   unsigned long long pos = 0, tp = 0, fpos = 0;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
@@ -655,8 +655,8 @@ __global__ void k_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
     pos = ws[0][0] + ws[0][1] + ws[0][2] + ws[0][3];
     tp = ws[1][0] + ws[1][1] + ws[1][2] + ws[1][3];
     fpos = ws[2][0] + ws[2][1] + ws[2][2] + ws[2][3];
-    if (judge && pos) atomicAdd(&judge[0], pos);
-    if (judge && tp) atomicAdd(&judge[1], tp);
+    if (audit && pos) atomicAdd(&audit[0], pos);
+    if (audit && tp) atomicAdd(&audit[1], tp);
     if (trace_pos && fpos) atomicAdd(trace_pos, fpos);
   }
 }
@@ -751,11 +751,11 @@ hipError_t launch_feat_shift(int app, int32_t n, const uint32_t* now, const uint
 }
 
 hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t* apx, float eps, const uint8_t* sel,
-                         uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* judge,
+                         uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* audit,
                          unsigned long long* trace_pos, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_labels, dim3(grid1d(n, 4096)), dim3(256), 0, st, app, n, acc, apx, eps, sel, label_u8, label_f,
-                     nf, judge, trace_pos);
+                     nf, audit, trace_pos);
   return hipGetLastError();
 }
 

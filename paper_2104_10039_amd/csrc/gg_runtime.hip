@@ -144,10 +144,10 @@ struct gg_graph {
   uint16_t* feat = nullptr;        // [n][8] bfloat16 features
   uint8_t* sel = nullptr;          // n: selected rows of the last correction step
   float* logits = nullptr;         // n
-  uint8_t* labels = nullptr;       // n: drift labels of the last traced / judged superstep
+  uint8_t* labels = nullptr;       // n: drift labels of the last traced / audited superstep
   uint32_t* shadow = nullptr;      // n: approximate update of that superstep
   int32_t* sel_count = nullptr;    // 4: |S| (int32), pad, in-edges of S (uint64 at +2)
-  unsigned long long* judge = nullptr;  // [0] drifted vertices, [1] of which selected, [2] active edges of S
+  unsigned long long* audit = nullptr;  // [0] drifted vertices, [1] of which selected, [2] active edges of S
   Bins selb;                       // binning of the selected rows (full rows)
   // workspace (allocated on first run)
   bool ws = false;
@@ -205,7 +205,7 @@ struct gg_run {
   int32_t corrections = 0;
   int32_t partials = 0;
   int64_t selected_total = 0;
-  int64_t judge_selected = 0;
+  int64_t audit_selected = 0;
   bool have_feat = false, have_sel = false, have_labels = false;
 };
 
@@ -268,7 +268,7 @@ int ensure_learned(gg_graph* g) {
   GG_TRY(dalloc(&g->labels, n));
   GG_TRY(dalloc(&g->shadow, n));
   GG_TRY(dalloc(&g->sel_count, 4));
-  GG_TRY(dalloc(&g->judge, 3));
+  GG_TRY(dalloc(&g->audit, 3));
   GG_TRY(alloc_bins(g->selb, g->n));
   g->lws = true;
   return GG_OK;
@@ -546,7 +546,7 @@ void free_graph(gg_graph* g) {
   dfree(g->labels);
   dfree(g->shadow);
   dfree(g->sel_count);
-  dfree(g->judge);
+  dfree(g->audit);
   free_bins(g->selb);
   for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
@@ -599,7 +599,7 @@ int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const 
   }
   if (pol->trace && pol->kind != GG_POLICY_GG && pol->kind != GG_POLICY_LEARNED)
     return fail(GG_E_INVAL, "traces are recorded by GG and LEARNED runs");
-  if ((pol->trace || (pol->kind == GG_POLICY_LEARNED && pol->judge)) && is_pr(p->app) && !(pol->label_eps > 0.0f))
+  if ((pol->trace || (pol->kind == GG_POLICY_LEARNED && pol->audit)) && is_pr(p->app) && !(pol->label_eps > 0.0f))
     return fail(GG_E_INVAL, "label_eps must be > 0");
   if (!(sigma >= 0.0 && sigma <= 1.0)) return fail(GG_E_INVAL, "sample_ratio outside [0, 1]");
   if (pol->alpha < 0) return fail(GG_E_INVAL, "alpha < 0");
@@ -777,7 +777,7 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
     GG_TRY(ensure_learned(g));
     // the delta features start at 0 (no iteration before iteration 0)
     GG_HIP(launch_fill_u32((uint32_t*)g->feat, (int64_t)g->n * 4, 0u, g->stream));
-    GG_HIP(launch_fill_u32((uint32_t*)g->judge, 4, 0u, g->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)g->audit, 4, 0u, g->stream));
   }
   const bool fixed_iters = is_pr(app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
   if (fixed_iters && p->iters == 0) r->done = true;
@@ -810,7 +810,7 @@ int learned_select(gg_run* r, int* kind, int64_t* selected) {
   r->selected_total += cnt;
   // fallback when the selected rows hold more than rho * m in-edges
   if (!forced && !((double)sel_edges > r->pol.rho * (double)g->m)) *kind = GG_STEP_PARTIAL;
-  if (*kind == GG_STEP_FULL && r->pol.judge) r->judge_selected += cnt;
+  if (*kind == GG_STEP_FULL && r->pol.audit) r->audit_selected += cnt;
   return GG_OK;
 }
 
@@ -841,10 +841,10 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   if (learned && kind == GG_STEP_FULL) GG_TRY(learned_select(r, &kind, &selected));
   const bool accurate = kind == GG_STEP_ACCURATE || kind == GG_STEP_FULL;
   const bool superstep = kind == GG_STEP_FULL || kind == GG_STEP_PARTIAL;
-  // a traced or judged full superstep also computes the approximate update
+  // a traced or audited full superstep also computes the approximate update
   // and labels every vertex by the difference
   const bool traced = r->pol.trace != nullptr && kind == GG_STEP_FULL;
-  const bool judged = learned && r->pol.judge && kind == GG_STEP_FULL && r->have_sel;
+  const bool audited = learned && r->pol.audit && kind == GG_STEP_FULL && r->have_sel;
   if (traced && !learned) {
     GG_HIP(launch_feat_base(g->n, g->rowptr, g->outdeg, g->act_cnt, g->feat, g->stream));
     r->have_feat = true;
@@ -923,7 +923,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     const int32_t ns = g->selb.h.small + g->selb.h.wave + g->selb.h.hub;
     GG_HIP(launch_copy_u32(g->bits[r->bcur], g->bits[1 - r->bcur], (g->m + 31) / 32, g->stream));
     GG_HIP(launch_clear_rows(g->selb.list, g->selb.h.small, ns, g->rowptr, g->bits[1 - r->bcur], g->stream));
-    GG_HIP(launch_fill_u32((uint32_t*)(g->judge + 2), 2, 0u, g->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)(g->audit + 2), 2, 0u, g->stream));
     Sweep sa = s;
     set_bins(sa, g->act);
     sa.edges = g->act_edges;
@@ -937,7 +937,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
       GG_HIP(launch_gather(app, g->tune.small_team, sa, g->stream, pe0, nullptr));
     }
     GG_HIP(launch_sel_fix(g->selb.list, ns, pr ? nullptr : s.x_in, pr ? nullptr : s.x_next, g->act_cnt,
-                          (pr || frontier) ? nullptr : g->changed, g->judge + 2, g->stream));
+                          (pr || frontier) ? nullptr : g->changed, g->audit + 2, g->stream));
     const int64_t act_all = g->act.h.edges;
     Sweep sc = s;
     set_bins(sc, g->selb);
@@ -953,7 +953,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
       GG_HIP(launch_superstep(app, g->tune.small_team, sc, g->stream, nullptr, pe1));
     }
     unsigned long long act_s = 0;
-    GG_HIP(hipMemcpyAsync(&act_s, g->judge + 2, sizeof(act_s), hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipMemcpyAsync(&act_s, g->audit + 2, sizeof(act_s), hipMemcpyDeviceToHost, g->stream));
     r->bcur = 1 - r->bcur;
     GG_TRY(rebin_act(g, app));  // synchronizes the stream
     r->supersteps++;
@@ -963,7 +963,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     processed = act_all + g->selb.h.edges;
   } else if (superstep) {
     pkind = 2;
-    if (traced || judged) {
+    if (traced || audited) {
       // approximate update from the same state, into the shadow buffer
       Sweep sh = s;
       set_bins(sh, g->act);
@@ -994,7 +994,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     else
       GG_HIP(launch_superstep(app, g->tune.small_team, s, g->stream, pe0, pe1));
     r->bcur = 1 - r->bcur;
-    if (traced || judged) {
+    if (traced || audited) {
       const uint32_t* acc = pr ? (const uint32_t*)s.c_out : s.x_next;
       float* lf = nullptr;
       int32_t nf = 0;
@@ -1012,8 +1012,8 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
         T->size += nf;
         T->dropped += (int64_t)g->n - nf;
       }
-      GG_HIP(launch_labels(app, g->n, acc, g->shadow, r->pol.label_eps, judged ? g->sel : nullptr, g->labels, lf, nf,
-                           judged ? g->judge : nullptr, tpos, g->stream));
+      GG_HIP(launch_labels(app, g->n, acc, g->shadow, r->pol.label_eps, audited ? g->sel : nullptr, g->labels, lf, nf,
+                           audited ? g->audit : nullptr, tpos, g->stream));
       r->have_labels = true;
     }
     GG_TRY(rebin_act(g, app));
@@ -1178,18 +1178,18 @@ int run_values(gg_run* r, void* out, uint32_t flags) {
   return copy_out(g, g->xu[r->cur], out, sizeof(uint32_t) * (size_t)g->n, flags);
 }
 
-// Learned-policy fields of the run statistics (reads the judge counters).
+// Learned-policy fields of the run statistics (reads the audit counters).
 int learned_stats(gg_run* r, gg_run_stats* st) {
   st->partial_supersteps = r->partials;
   st->selected_total = r->selected_total;
-  st->judge_positives = st->judge_hits = 0;
-  st->judge_selected = r->judge_selected;
-  if (r->g->lws && r->pol.kind == GG_POLICY_LEARNED && r->pol.judge) {
+  st->audit_positives = st->audit_hits = 0;
+  st->audit_selected = r->audit_selected;
+  if (r->g->lws && r->pol.kind == GG_POLICY_LEARNED && r->pol.audit) {
     unsigned long long h[2] = {0, 0};
-    GG_HIP(hipMemcpyAsync(h, r->g->judge, sizeof(h), hipMemcpyDeviceToHost, r->g->stream));
+    GG_HIP(hipMemcpyAsync(h, r->g->audit, sizeof(h), hipMemcpyDeviceToHost, r->g->stream));
     GG_HIP(hipStreamSynchronize(r->g->stream));
-    st->judge_positives = (int64_t)h[0];
-    st->judge_hits = (int64_t)h[1];
+    st->audit_positives = (int64_t)h[0];
+    st->audit_hits = (int64_t)h[1];
   }
   return GG_OK;
 }

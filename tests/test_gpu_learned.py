@@ -227,16 +227,16 @@ def test_trace_capacity_drops(P):
 # LEARNED runs
 # --------------------------------------------------------------------------
 
-def learned_step_compare(P, g, app, params, tau, rho=1.0, fallback_k=0, judge=False, **kw):
+def learned_step_compare(P, g, app, params, tau, rho=1.0, fallback_k=0, audit=False, **kw):
     """Both sides step by step; selections, step kinds, edges, values and
     (after every correction) the flags must agree."""
     net = P.Mlp()
     net.set_weights(params.astype(np.float32))
     G = P.Graph.from_host(g)
     sr = kw.pop("sample_ratio")
-    R = G.begin(app, sr, "learned", mlp=net, tau=tau, rho=rho, fallback_k=fallback_k, judge=judge, **kw)
+    R = G.begin(app, sr, "learned", mlp=net, tau=tau, rho=rho, fallback_k=fallback_k, audit=audit, **kw)
     O = oracle.Run(g, app, "learned", sigma=sr, mlp=params, tau=tau, rho=rho, fallback_k=fallback_k,
-                   trace=judge, **oracle_kw(kw))
+                   trace=audit, **oracle_kw(kw))
     kinds = []
     hits = pos = 0
     while True:
@@ -256,14 +256,14 @@ def learned_step_compare(P, g, app, params, tau, rho=1.0, fallback_k=0, judge=Fa
             assert np.array_equal(gs, os_)
         if a["superstep"]:
             assert np.array_equal(R.mask(), O.mask()), "flags after iteration %d" % b.iter
-        if judge and a["kind"] == "full" and a["selected"] >= 0:
+        if audit and a["kind"] == "full" and a["selected"] >= 0:
             ol = O.labels()
             pos += int(ol.sum())
             hits += int((ol & O.selection()[0]).sum())
         compare_values(app, R.values(), O.values(), ctx="iter %d" % b.iter)
     st = R.stats()
-    if judge:
-        assert st.judge_positives == pos and st.judge_hits == hits
+    if audit:
+        assert st.audit_positives == pos and st.audit_hits == hits
     R.close()
     G.close()
     net.close()
@@ -291,7 +291,7 @@ def test_learned_selector_dynamic(P, app):
     s = int(gg.pick_sources(g, 1, 10)[0])
     for params, tau in ((mlp_selector_params(2, -1.0), -0.5), (mlp_selector_params(3, 1.0), 0.0)):
         for stop in ("fixed_iters", "fixed_point"):
-            learned_step_compare(P, g, app, params, tau=tau, fallback_k=4, judge=True, sample_ratio=0.3, alpha=1,
+            learned_step_compare(P, g, app, params, tau=tau, fallback_k=4, audit=True, sample_ratio=0.3, alpha=1,
                                  theta=0.05, seed=11, source=s, iters=20, stop=stop, max_iters=200)
 
 
