@@ -283,6 +283,30 @@ int gg_run_stats_get(gg_run* run, gg_run_stats* stats);
 int gg_run_features(gg_run* run, uint16_t* feat_host);
 int gg_run_selection(gg_run* run, uint8_t* sel_host, float* logits_host);
 int gg_run_labels(gg_run* run, uint8_t* labels_host);
+/*
+ * Checkpoint and resume of a step-API run (not in the paper, whose runs are
+ * never interrupted; a project addition). The state after the last executed
+ * iteration is the values that the next iteration reads, the edge flags (for
+ * every scheme but EXACT) and the run's counters; packed active edges, bins
+ * and frontier lists are rebuilt from them. The blob is opaque host memory,
+ * owned by the caller, valid only for this library version.
+ *   gg_run_state_size    bytes the blob of the run's current state needs
+ *   gg_run_export_state  writes it to state_host (bytes must equal the size)
+ *   gg_run_import_state  loads it into a run that has executed no iteration,
+ *                        begun on a graph of the same shape (n, m, parts)
+ *                        with the same app, parameters, sample ratio and
+ *                        policy (GG_E_INVAL otherwise; GG_E_STATE once the
+ *                        run has stepped); the caller supplies the same
+ *                        graph, which is not checked edge by edge.
+ * A resumed run continues bit for bit as the uninterrupted run would. Its
+ * first SSSP/CC iteration runs dense (the frontier restarts unknown), so
+ * edges_processed and sparse_iterations may differ; no value does.
+ * LEARNED and traced runs: GG_E_UNSUPPORTED (their delta features span two
+ * iterations).
+ */
+int gg_run_state_size(gg_run* run, int64_t* bytes);
+int gg_run_export_state(gg_run* run, void* state_host, int64_t bytes);
+int gg_run_import_state(gg_run* run, const void* state_host, int64_t bytes);
 void gg_run_end(gg_run* run);
 
 /*

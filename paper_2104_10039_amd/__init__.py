@@ -120,6 +120,9 @@ SIGNATURES = {
     "gg_run_features": (ctypes.c_int, [_VP, _VP]),
     "gg_run_selection": (ctypes.c_int, [_VP, _VP, _VP]),
     "gg_run_labels": (ctypes.c_int, [_VP, _VP]),
+    "gg_run_state_size": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
+    "gg_run_export_state": (ctypes.c_int, [_VP, _VP, ctypes.c_int64]),
+    "gg_run_import_state": (ctypes.c_int, [_VP, _VP, ctypes.c_int64]),
     "gg_mlp_create": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(_VP)]),
     "gg_mlp_free": (None, [_VP]),
     "gg_mlp_set_weights": (ctypes.c_int, [_VP, _VP]),
@@ -385,7 +388,8 @@ class Graph:
 
 
 class Run:
-    """Step API (gg_run_begin / gg_run_step / gg_run_values / gg_run_mask / gg_run_end)."""
+    """Step API (gg_run_begin / gg_run_step / gg_run_values / gg_run_mask /
+    gg_run_export_state / gg_run_import_state / gg_run_end)."""
 
     def __init__(self, graph: Graph, app, sample_ratio=1.0, policy="exact", alpha=4, theta=0.05, seed=1,
                  influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
@@ -458,6 +462,19 @@ class Run:
         st = RunStats()
         _check(lib().gg_run_stats_get(self._h, ctypes.byref(st)))
         return _stats(st)
+
+    def export_state(self) -> np.ndarray:
+        """gg_run_export_state: the run's state after its last iteration, as host bytes."""
+        size = ctypes.c_int64()
+        _check(lib().gg_run_state_size(self._h, ctypes.byref(size)))
+        out = np.zeros(size.value, dtype=np.uint8)
+        _check(lib().gg_run_export_state(self._h, out.ctypes.data, size.value))
+        return out
+
+    def import_state(self, state) -> None:
+        """gg_run_import_state: continue from a state that export_state returned."""
+        buf = np.ascontiguousarray(state, dtype=np.uint8)
+        _check(lib().gg_run_import_state(self._h, buf.ctypes.data, buf.size))
 
     def close(self):
         if getattr(self, "_h", None):

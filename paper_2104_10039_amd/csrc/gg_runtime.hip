@@ -690,6 +690,8 @@ const uint32_t* full_edges(const gg_graph* g, int app) {
   return app == GG_APP_SSSP ? g->wedges : (const uint32_t*)g->col;
 }
 
+int pack_from_bits0(gg_graph* g, int app);
+
 // Initial sample of the edge flags into bits[0], the packed active edges and
 // their binning [Sec. 3.4].
 int sample_and_pack(gg_graph* g, int app, double sigma, uint64_t seed) {
@@ -698,6 +700,12 @@ int sample_and_pack(gg_graph* g, int app, double sigma, uint64_t seed) {
     GG_HIP(launch_sample_bits_parts(g->m, seed, 0, keep, g->n_parts, g->part_e0, g->bits[0], g->stream));
   else
     GG_HIP(launch_sample_bits(g->m, seed, 0, keep, g->bits[0], g->stream));
+  return pack_from_bits0(g, app);
+}
+
+// Packed active edges (flag set in bits[0], CSR order within each row) and
+// their binning.
+int pack_from_bits0(gg_graph* g, int app) {
   Sweep s;
   std::memset(&s, 0, sizeof(s));
   s.n = g->n;
@@ -1191,6 +1199,156 @@ int learned_stats(gg_run* r, gg_run_stats* st) {
     st->audit_positives = (int64_t)h[0];
     st->audit_hits = (int64_t)h[1];
   }
+  return GG_OK;
+}
+
+// ---- run state (checkpoint / resume) --------------------------------------
+//
+// Blob layout: StateHeader, then the values of iteration `iter` (PR/PPR: the
+// binary32 contributions the next iteration gathers, then the binary32
+// values when they were materialised; SSSP/CC: the uint32 values), then the
+// edge flags as ceil(m/32) words when the scheme has flags. Everything else a
+// run carries (packed active edges, bins, frontier lists) is derived from
+// these on import; the frontier restarts as unknown, so the first resumed
+// SSSP/CC iteration runs dense, which changes no value.
+struct StateHeader {
+  uint32_t magic, version;
+  int32_t app, kind, n, n_parts;
+  int64_t m;
+  int32_t iter, done, has_x, has_bits;
+  double sigma, theta, damping;
+  uint64_t seed;
+  int32_t alpha, influence, mask_update, stop, iters, max_iters, source, dangling;
+  int32_t supersteps, sparse_iters;
+  int64_t edges_total, edges_processed;
+};
+constexpr uint32_t kStateMagic = 0x53524747u;  // "GGRS"
+constexpr uint32_t kStateVersion = 1;
+
+int state_check_kind(const gg_run* r) {
+  if (r->pol.kind == GG_POLICY_LEARNED || r->pol.trace)
+    return fail(GG_E_UNSUPPORTED, "run state of LEARNED or traced runs (their delta features span two iterations)");
+  return GG_OK;
+}
+
+int64_t state_bytes(const gg_run* r, bool has_x) {
+  const gg_graph* g = r->g;
+  int64_t b = (int64_t)sizeof(StateHeader) + 4 * (int64_t)g->n;
+  if (has_x) b += 4 * (int64_t)g->n;
+  if (r->pol.kind != GG_POLICY_EXACT) b += 4 * ((g->m + 31) / 32);
+  return b;
+}
+
+bool state_has_x(const gg_run* r) { return is_pr(r->p.app) && r->iter > 0 && r->x_valid; }
+
+int run_state_size(gg_run* r, int64_t* bytes) {
+  GG_TRY(state_check_kind(r));
+  *bytes = state_bytes(r, state_has_x(r));
+  return GG_OK;
+}
+
+int run_export_state(gg_run* r, void* buf, int64_t bytes) {
+  GG_TRY(state_check_kind(r));
+  gg_graph* g = r->g;
+  const bool has_x = state_has_x(r);
+  if (bytes != state_bytes(r, has_x)) return fail(GG_E_INVAL, "state buffer size differs from gg_run_state_size");
+  GG_TRY(check_hub_sync(g));
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = kStateMagic;
+  h.version = kStateVersion;
+  h.app = r->p.app;
+  h.kind = r->pol.kind;
+  h.n = g->n;
+  h.n_parts = g->n_parts;
+  h.m = g->m;
+  h.iter = r->iter;
+  h.done = r->done ? 1 : 0;
+  h.has_x = has_x ? 1 : 0;
+  h.has_bits = r->pol.kind != GG_POLICY_EXACT ? 1 : 0;
+  h.sigma = r->sigma;
+  h.theta = r->pol.theta;
+  h.damping = r->p.damping;
+  h.seed = r->pol.seed;
+  h.alpha = r->pol.alpha;
+  h.influence = r->pol.influence;
+  h.mask_update = r->pol.mask_update;
+  h.stop = r->pol.stop;
+  h.iters = r->p.iters;
+  h.max_iters = r->p.max_iters;
+  h.source = r->p.source;
+  h.dangling = r->p.dangling;
+  h.supersteps = r->supersteps;
+  h.sparse_iters = r->sparse_iters;
+  h.edges_total = r->edges_total;
+  h.edges_processed = r->edges_processed;
+  char* p = (char*)buf;
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  const size_t vb = 4 * (size_t)g->n;
+  const void* vals = is_pr(r->p.app) ? (const void*)g->c[r->cur] : (const void*)g->xu[r->cur];
+  if (vb) GG_HIP(hipMemcpyAsync(p, vals, vb, hipMemcpyDeviceToHost, g->stream));
+  p += vb;
+  if (has_x && vb) GG_HIP(hipMemcpyAsync(p, g->xout, vb, hipMemcpyDeviceToHost, g->stream));
+  if (has_x) p += vb;
+  const size_t wb = 4 * (size_t)((g->m + 31) / 32);
+  if (h.has_bits && wb) GG_HIP(hipMemcpyAsync(p, g->bits[r->bcur], wb, hipMemcpyDeviceToHost, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+  return GG_OK;
+}
+
+int run_import_state(gg_run* r, const void* buf, int64_t bytes) {
+  GG_TRY(state_check_kind(r));
+  gg_graph* g = r->g;
+  if (r->iter != 0) return fail(GG_E_STATE, "state can only be imported into a run that has executed no iteration");
+  if (bytes < (int64_t)sizeof(StateHeader)) return fail(GG_E_INVAL, "state buffer shorter than its header");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kStateMagic || h.version != kStateVersion) return fail(GG_E_INVAL, "not a run state of this library version");
+  const bool same = h.app == r->p.app && h.kind == r->pol.kind && h.n == g->n && h.n_parts == g->n_parts &&
+                    h.m == g->m && h.sigma == r->sigma && h.theta == r->pol.theta && h.damping == r->p.damping &&
+                    h.seed == r->pol.seed && h.alpha == r->pol.alpha && h.influence == r->pol.influence &&
+                    h.mask_update == r->pol.mask_update && h.stop == r->pol.stop && h.iters == r->p.iters &&
+                    h.max_iters == r->p.max_iters && h.source == r->p.source && h.dangling == r->p.dangling;
+  if (!same) return fail(GG_E_INVAL, "state was exported from a run with another graph shape, app, parameters or policy");
+  const bool has_x = h.has_x != 0;
+  if (has_x && !is_pr(r->p.app)) return fail(GG_E_INVAL, "state holds PR values for a min-type app");
+  if (h.has_bits != (r->pol.kind != GG_POLICY_EXACT ? 1 : 0)) return fail(GG_E_INVAL, "state flag section mismatch");
+  if (bytes != state_bytes(r, has_x)) return fail(GG_E_INVAL, "state buffer size does not match its header");
+  if (h.iter < 0 || (h.iter == 0 && has_x)) return fail(GG_E_INVAL, "state iteration out of range");
+  const char* p = (const char*)buf + sizeof(h);
+  const size_t vb = 4 * (size_t)g->n;
+  if (is_pr(r->p.app)) {
+    if (vb) GG_HIP(hipMemcpyAsync(g->c[0], p, vb, hipMemcpyHostToDevice, g->stream));
+    p += vb;
+    if (has_x && vb) GG_HIP(hipMemcpyAsync(g->xout, p, vb, hipMemcpyHostToDevice, g->stream));
+    if (has_x) p += vb;
+  } else {
+    // both buffers hold the values, as at the start of a run
+    if (vb) {
+      GG_HIP(hipMemcpyAsync(g->xu[0], p, vb, hipMemcpyHostToDevice, g->stream));
+      GG_HIP(hipMemcpyAsync(g->xu[1], p, vb, hipMemcpyHostToDevice, g->stream));
+    }
+    p += vb;
+  }
+  if (h.has_bits) {
+    const size_t wb = 4 * (size_t)((g->m + 31) / 32);
+    if (wb) GG_HIP(hipMemcpyAsync(g->bits[0], p, wb, hipMemcpyHostToDevice, g->stream));
+    GG_TRY(pack_from_bits0(g, r->p.app));
+  }
+  GG_HIP(hipStreamSynchronize(g->stream));
+  r->cur = 0;
+  r->bcur = 0;
+  r->iter = h.iter;
+  r->done = h.done != 0;
+  r->x_valid = has_x;
+  r->supersteps = h.supersteps;
+  r->sparse_iters = h.sparse_iters;
+  r->edges_total = h.edges_total;
+  r->edges_processed = h.edges_processed;
+  r->fcur = 0;
+  r->front_count = -1;
+  r->front_outdeg = 0;
   return GG_OK;
 }
 
@@ -1903,6 +2061,27 @@ int gg_run_labels(gg_run* run, uint8_t* labels_host) {
     GG_HIP(hipMemcpyAsync(labels_host, g->labels, (size_t)g->n, hipMemcpyDeviceToHost, g->stream));
     GG_HIP(hipStreamSynchronize(g->stream));
     return GG_OK;
+  });
+}
+
+int gg_run_state_size(gg_run* run, int64_t* bytes) {
+  return guard([&]() -> int {
+    if (!run || !bytes) return fail(GG_E_INVAL, "null argument");
+    return run_state_size(run, bytes);
+  });
+}
+
+int gg_run_export_state(gg_run* run, void* state_host, int64_t bytes) {
+  return guard([&]() -> int {
+    if (!run || !state_host) return fail(GG_E_INVAL, "null argument");
+    return run_export_state(run, state_host, bytes);
+  });
+}
+
+int gg_run_import_state(gg_run* run, const void* state_host, int64_t bytes) {
+  return guard([&]() -> int {
+    if (!run || !state_host) return fail(GG_E_INVAL, "null argument");
+    return run_import_state(run, state_host, bytes);
   });
 }
 
