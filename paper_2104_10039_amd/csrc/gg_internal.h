@@ -10,8 +10,9 @@ namespace ggk {
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr int kBlock = 256;  // threads per workgroup of every sweep kernel
 constexpr int kHubPre = 8;   // 256-edge steps of a hub chunk whose loads are issued together
-constexpr int kFlatWin = 1024;
-constexpr int kPartDangBlocks = 32;  // blocks per part of the per-part dangling sums  // edges staged per round of a flattened batch of short rows
+constexpr int kFlatWin = 1024;  // edges staged per round of a flattened batch of short rows
+constexpr int kSegWin = 2048;  // edges gathered per window of a segmented gather's flattened batch
+constexpr int kPartDangBlocks = 32;  // blocks per part of the per-part dangling sums
 constexpr int kHubSpinLimit = 1 << 20;  // polls before a single-pass hub chunk gives up waiting
 
 enum App : int { kPR = 0, kSSSP = 1, kCC = 2, kPPR = 3 };

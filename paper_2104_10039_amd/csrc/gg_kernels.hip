@@ -1587,9 +1587,11 @@ struct GV<kPPR> : GV<kPR> {};
 
 
 // One block reduces a batch of P <= kBlock pieces [lo_p, hi_p) of the edge
-// array: every edge of the batch is gathered independently (kFlatWin per
-// round, all in flight together) into LDS, then the owner thread of each
-// piece sums its values in edge order. Returns the owner's result.
+// array: every edge of the batch is gathered independently (kSegWin per
+// round) into LDS, then the owner thread of each piece sums its values in
+// edge order. Returns the owner's result. A round runs in phases (positions,
+// edge words, values, LDS stores) so that all of a thread's edge-word loads,
+// and then all of its value loads, are in flight together.
 template <int APP>
 __device__ __forceinline__ typename Tr<APP>::T flat_batch(const Sweep& s, int P, int my_lo, int my_len,
                                                           typename GV<APP>::V* s_val, int* s_lo, int* s_scan,
@@ -1616,11 +1618,14 @@ __device__ __forceinline__ typename Tr<APP>::T flat_batch(const Sweep& s, int P,
   __syncthreads();
   typename R::T acc = R::id();
   const int mine0 = s_scan[tid], mine1 = tid < P ? s_scan[tid] + len : s_scan[tid];
-  for (int base = 0; base < total; base += kFlatWin) {
-    const int lim = min(kFlatWin, total - base);
+  for (int base = 0; base < total; base += kSegWin) {
+    const int lim = min(kSegWin, total - base);
+    constexpr int J = kSegWin / kBlock;
+    int pos[J];
 #pragma unroll
-    for (int j = 0; j < kFlatWin / kBlock; ++j) {
+    for (int j = 0; j < J; ++j) {
       const int k = j * kBlock + tid;
+      pos[j] = -1;
       if (k < lim) {
         const int kk = base + k;
         int lo = 0, hi = P - 1;  // last piece whose start <= kk
@@ -1629,10 +1634,18 @@ __device__ __forceinline__ typename Tr<APP>::T flat_batch(const Sweep& s, int P,
           if (s_scan[mid] <= kk) lo = mid;
           else hi = mid - 1;
         }
-        const int e = s_lo[lo] + (kk - s_scan[lo]);
-        s_val[k] = GV<APP>::get(s, ld_stream(s.edges + e));
+        pos[j] = s_lo[lo] + (kk - s_scan[lo]);
       }
     }
+    uint32_t ev[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) ev[j] = pos[j] >= 0 ? ld_stream(s.edges + pos[j]) : 0u;
+    typename GV<APP>::V val[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) val[j] = pos[j] >= 0 ? GV<APP>::get(s, ev[j]) : typename GV<APP>::V(0);
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      if (pos[j] >= 0) s_val[j * kBlock + tid] = val[j];
     __syncthreads();
     const int a = max(mine0, base), b = min(mine1, base + lim);
     for (int k = a; k < b; ++k) acc = R::op(acc, GV<APP>::widen(s_val[k - base]));
@@ -1647,7 +1660,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_seg(Sweep s, int gh, int gw, 
   using T = typename R::T;
   __shared__ T lds[4];
   __shared__ int ilds[4];
-  __shared__ typename GV<APP>::V s_val[kFlatWin];
+  __shared__ typename GV<APP>::V s_val[kSegWin];
   __shared__ int s_lo[kBlock];
   __shared__ int s_scan[kBlock + 1];
   int nchanged = 0;
