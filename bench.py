@@ -429,6 +429,14 @@ def main():
                 d[f] += p[f]
             d["kinds"].append(kind)
     kname, pb = max(per_kernel.items(), key=lambda kv: kv[1]["total_ms"])
+    # every sweep kernel of the timed region, largest total time first
+    by_kernel = []
+    for kn, d in sorted(per_kernel.items(), key=lambda kv: -kv[1]["total_ms"]):
+        avg = d["total_ms"] / d["launches"]
+        ach = d["alg_bytes"] / d["launches"] / (avg * 1e-3) / 1e9
+        by_kernel.append({"kernel": kn, "kind": "+".join(d["kinds"]), "launches": d["launches"],
+                          "total_ms": round(d["total_ms"], 3), "avg_launch_ms": round(avg, 4),
+                          "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)})
     kind_b = "+".join(pb["kinds"])
     avg_ms = pb["total_ms"] / pb["launches"]
     bytes_per_launch = pb["alg_bytes"] / pb["launches"]
@@ -439,7 +447,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "kind": kind_b,
                 "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": int(bytes_per_launch),
-                "launches": pb["launches"]}
+                "launches": pb["launches"], "kernels": by_kernel}
 
     at1 = bench_at_1pct(G, apps, iters, source, {a: outs[(a, "exact")].cpu().numpy() for a in apps}, metrics, np)
 
