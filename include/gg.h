@@ -231,12 +231,13 @@ int gg_approx_run(gg_graph* g, const gg_app_params* params, double sample_ratio,
  * sources_host[q] (host array, each in [0, n)) on this graph, iterated
  * together so that every edge word is read once per iteration for all
  * queries, with each query's values read as one contiguous run. Schemes:
- * EXACT, and SP with one sampled edge set shared by all queries (ratio
- * sample_ratio, policy->seed). PPR runs params->iters iterations, all
- * captured in one HIP graph launched once; exact SSSP stops after the first
- * iteration in which no query changed (at most params->max_iters), captured
- * 32 iterations per graph launch with device-side early exit; SP SSSP runs
- * params->iters iterations. Every query's result equals the corresponding
+ * EXACT; SP with one sampled edge set shared by all queries (ratio
+ * sample_ratio, policy->seed); SMS [Sec. 5.2], that sample for iterations
+ * 1..policy->alpha and every edge after. PPR runs params->iters iterations,
+ * all captured in one HIP graph launched once; exact SSSP stops after the
+ * first iteration in which no query changed (at most params->max_iters),
+ * captured 32 iterations per graph launch with device-side early exit; SP
+ * and SMS SSSP run params->iters iterations. Every query's result equals the corresponding
  * single-query run. out_values: n * n_queries elements, row-major by vertex
  * (out[u * n_queries + q]), float for PPR, uint32 for SSSP; host or device
  * per out_flags. 1 <= n_queries <= 4096.

@@ -1470,8 +1470,9 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
               const gg_correction_policy* pol, void* out, uint32_t flags, gg_run_stats* st) {
   if (!g || !p || !pol || !sources || !out) return fail(GG_E_INVAL, "null argument");
   if (p->app != GG_APP_PPR && p->app != GG_APP_SSSP) return fail(GG_E_UNSUPPORTED, "batch runs support PPR and SSSP");
-  if (pol->kind != GG_POLICY_EXACT && pol->kind != GG_POLICY_SP)
-    return fail(GG_E_UNSUPPORTED, "batch runs support the EXACT and SP schemes");
+  if (pol->kind != GG_POLICY_EXACT && pol->kind != GG_POLICY_SP && pol->kind != GG_POLICY_SMS)
+    return fail(GG_E_UNSUPPORTED, "batch runs support the EXACT, SP and SMS schemes");
+  if (pol->kind == GG_POLICY_SMS && pol->alpha < 0) return fail(GG_E_INVAL, "alpha < 0");
   if (nq < 1 || nq > 4096) return fail(GG_E_INVAL, "n_queries outside [1, 4096]");
   if (g->n_parts > 0) return fail(GG_E_UNSUPPORTED, "batch runs on a graph with parts");
   if (!(sigma >= 0.0 && sigma <= 1.0)) return fail(GG_E_INVAL, "sample_ratio outside [0, 1]");
@@ -1506,8 +1507,11 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
     g->stream = keep;
     GG_TRY(rc);
   }
+  // SMS: approximate iterations 1..alpha over the sample, accurate ones after
+  const bool sms = pol->kind == GG_POLICY_SMS;
   const Bins& bins = approx ? g->act : g->full;
-  if ((int64_t)bins.h.chunks * qp > B.part_cap) return fail(GG_E_STATE, "batch partial array too small");
+  if ((int64_t)bins.h.chunks * qp > B.part_cap || (int64_t)g->full.h.chunks * qp > B.part_cap)
+    return fail(GG_E_STATE, "batch partial array too small");
   BatchSweep s;
   std::memset(&s, 0, sizeof(s));
   s.n = g->n;
@@ -1530,6 +1534,17 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
   s.changed = B.ctr;
   s.part_f = B.part;
   s.part_u = (uint32_t*)B.part;
+  // the accurate-mode sweep of an SMS run
+  BatchSweep sf = s;
+  sf.list = g->full.list;
+  sf.hub_start = g->full.hub_start;
+  sf.n_small = g->full.h.small;
+  sf.n_wave = g->full.h.wave;
+  sf.n_hub = g->full.h.hub;
+  sf.n_chunks = g->full.h.chunks;
+  sf.cnt = nullptr;
+  sf.edges = full_edges(g, app);
+  auto sweep_for = [&](int32_t i) -> const BatchSweep& { return (sms && i >= pol->alpha + 1) ? sf : s; };
   float* C[2] = {(float*)B.buf[0], (float*)B.buf[1]};
   float* X = (float*)B.buf[2];
   uint32_t* U[2] = {(uint32_t*)B.buf[0], (uint32_t*)B.buf[1]};
@@ -1541,7 +1556,7 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
     // all T iterations in one captured graph
     GG_TRY(capture_launch(g, [&](hipStream_t cs) -> int {
       for (int32_t i = 1; i <= T; ++i) {
-        BatchSweep t = s;
+        BatchSweep t = sweep_for(i);
         t.c_in = C[(i - 1) & 1];
         t.c_out = C[i & 1];
         t.x_out = i == T ? X : nullptr;
@@ -1562,7 +1577,7 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
       if (kk <= 0) break;
       GG_TRY(capture_launch(g, [&](hipStream_t cs) -> int {
         for (int32_t i = 0; i < kk; ++i) {
-          BatchSweep t = s;
+          BatchSweep t = sweep_for(done_iters + i + 1);
           t.x_in = U[(done_iters + i) & 1];
           t.x_next = U[(done_iters + i + 1) & 1];
           t.done = fixed ? nullptr : B.ctr + 1;
@@ -1596,10 +1611,11 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
     float ms = 0.f;
     GG_HIP(hipEventElapsedTime(&ms, B.t0, B.t1));
     const int64_t eset = approx ? bins.h.edges : g->m;
+    const int64_t n_approx = sms ? std::min<int64_t>(iters, pol->alpha) : (approx ? iters : 0);
     st->iterations = iters;
     st->supersteps = 0;
-    st->edges_gathered = eset * (int64_t)iters * nq;
-    st->active_edges = eset;
+    st->edges_gathered = (eset * n_approx + g->m * ((int64_t)iters - n_approx)) * nq;
+    st->active_edges = sms && iters > pol->alpha ? g->m : eset;
     st->device_ms = ms;
     st->edges_processed = st->edges_gathered;
     st->sparse_iterations = 0;

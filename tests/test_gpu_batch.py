@@ -36,6 +36,8 @@ def check_batch(P, g, app, nq, policy="exact", sigma=1.0, tuning=None, n_check=6
         okw = dict(source=int(srcs[q]), iters=kw.get("iters", 20))
         if policy != "exact":
             okw.update(sigma=sigma, seed=5)
+        if "alpha" in kw:
+            okw["alpha"] = kw["alpha"]
         ref = oracle.run(g, app, policy, **okw)
         compare_values(app, got[:, q], ref.values, ctx="query %d" % q)
         iters.append(ref.iterations)
@@ -72,6 +74,25 @@ def test_batch_exact_sssp_stops_at_the_slowest_query(P):
 def test_batch_sp(P, app, sigma):
     g = gg.rmat(12, 16, seed=13, weights=True)
     check_batch(P, g, app, 96, policy="sp", sigma=sigma, iters=15)
+
+
+@pytest.mark.parametrize("app", ["ppr", "sssp"])
+@pytest.mark.parametrize("alpha", [0, 3, 20])
+def test_batch_sms(P, app, alpha):
+    """SMS: the shared sample for alpha iterations, every edge after (alpha
+    = 0 is exact, alpha >= iters is SP); small hub chunks put hub rows in
+    both edge sets."""
+    g = gg.rmat(13, 16, seed=17, weights=True)
+    st = check_batch(P, g, app, 80, policy="sms", sigma=0.3, alpha=alpha, iters=12,
+                     tuning=dict(small_max=8, wave_max=64, hub_chunk=512))
+    assert st.iterations == 12
+    m = int(g.rowptr[-1])
+    if alpha == 0:
+        assert st.edges_gathered == 80 * 12 * m
+    elif alpha >= 12:
+        assert st.edges_gathered == 80 * 12 * st.active_edges < 80 * 12 * m
+    else:
+        assert 80 * (12 - alpha) * m < st.edges_gathered < 80 * 12 * m
 
 
 @pytest.mark.parametrize("app", ["ppr", "sssp"])
