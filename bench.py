@@ -71,8 +71,11 @@ def cpu_baseline(graphs, source, budget_iters=3):
 
 # Fastest configurations within 1% error on R-MAT scale 22 (seed 2), from a
 # sweep over SP/SMS/GG, sigma in {.1,.3,.5,.7,.9}, alpha in {1,2,4,8},
-# theta in {0, .001, .01, .05, .2} and REPLACE/UNION.
-AT_1PCT = {"pr": ("sms", 0.1, 6), "sssp": ("sms", 0.1, 8), "cc": ("sms", 0.1, 5)}
+# theta in {0, .001, .01, .05, .2} and REPLACE/UNION, and a second sweep of
+# SMS and GG over every alpha up to the iteration count. Each stays within 1%
+# for every sampling seed 1..5, not only on average (CC at sigma 0.1 and
+# alpha 5 reaches 100% with seed 1 but 43% with another).
+AT_1PCT = {"pr": ("sms", 0.1, 6), "sssp": ("sms", 0.1, 8), "cc": ("sms", 0.2, 4)}
 
 # Batched SSSP (256 queries, R-MAT scale 20) within 1% error: the largest alpha
 # of SMS whose mean stretch accuracy stays >= 99%, from a sweep over sigma in
@@ -88,6 +91,18 @@ LEARNED_1PCT = {"pr": dict(sigma=0.1, alpha=6, theta=0.0, tau=0.0, rho=0.6, stop
                 "sssp": dict(sigma=0.3, alpha=4, theta=0.0, tau=2.0, rho=0.6, stop="fixed_point")}
 
 
+SEEDS = (1, 2, 3, 4, 5)
+
+
+def app_error(metrics, np, app, approx_h, exact_h, source):
+    """The paper's error metric of one approximate result [Sec. 4.2]."""
+    if app == "pr":
+        return metrics.topk_error(approx_h, exact_h, 1000)
+    if app == "sssp":
+        return metrics.stretch_error(approx_h.view(np.uint32), exact_h.view(np.uint32), source)
+    return metrics.label_mismatch(approx_h, exact_h)
+
+
 def bench_at_1pct(G, apps, iters, source, exact_out, metrics, np):
     out = {}
     for app in apps:
@@ -99,15 +114,15 @@ def bench_at_1pct(G, apps, iters, source, exact_out, metrics, np):
         ap_runs = [G[app].approx_run(app, sg, pol, **kw) for _ in range(3)]
         sx = sorted(ex_runs, key=lambda r: r.device_ms)[1]
         o, st = sorted(ap_runs, key=lambda r: r[1].device_ms)[1]
-        oh, exh = o.cpu().numpy(), exact_out[app]
-        if app == "pr":
-            err = metrics.topk_error(oh, exh, 1000)
-        elif app == "sssp":
-            err = metrics.stretch_error(oh.view(np.uint32), exh.view(np.uint32), source)
-        else:
-            err = metrics.label_mismatch(oh, exh)
+        exh = exact_out[app]
+        errs = [app_error(metrics, np, app, o.cpu().numpy(), exh, source)]
+        for sd in SEEDS[1:]:  # the other sampling seeds, untimed
+            o2, _ = G[app].approx_run(app, sg, pol, **dict(kw, seed=sd))
+            errs.append(app_error(metrics, np, app, o2.cpu().numpy(), exh, source))
+        err = float(np.mean(errs))
         out[app] = {"scheme": pol, "sigma": sg, "alpha": alpha, "accuracy": round(metrics.accuracy(err), 3),
-                    "within_1pct": bool(err <= 0.01), "ms": round(st.device_ms, 3),
+                    "accuracy_min": round(metrics.accuracy(float(np.max(errs))), 3),
+                    "within_1pct": bool(max(errs) <= 0.01), "ms": round(st.device_ms, 3),
                     "exact_ms": round(sx.device_ms, 3), "speedup": round(sx.device_ms / st.device_ms, 3),
                     "edges_vs_exact": round(st.edges_gathered / sx.edges_gathered, 4)}
         log("at_1pct:", app, out[app])
@@ -147,22 +162,28 @@ def bench_batch(P, gg, torch, seed, np, metrics):
         log("batch:", app, out["rmat20_%s_q%d" % (app, q)])
     # batched SSSP within 1% error: SMS over one shared sample, the same
     # iteration count as the exact batch, stretch accuracy averaged over
-    # every 8th query
+    # every 8th query, for each sampling seed
     sg, alpha = BATCH_SMS_1PCT
     ex, sx = G.batch_run("sssp", srcs, max_iters=1000)
     it = sx.iterations
     kw = dict(sample_ratio=sg, policy="sms", alpha=alpha, iters=it, seed=1)
     G.batch_run("sssp", srcs, **kw)
     o, st = G.batch_run("sssp", srcs, **kw)
-    exh, oh = ex.cpu().numpy().view(np.uint32), o.cpu().numpy().view(np.uint32)
-    errs = [metrics.stretch_error(oh[:, k], exh[:, k], int(srcs[k])) for k in range(0, len(srcs), 8)]
+    exh = ex.cpu().numpy().view(np.uint32)
+    seed_errs = []
+    for sd in SEEDS:  # every sampling seed; the timed run is seed 1
+        oh = (o if sd == 1 else G.batch_run("sssp", srcs, **dict(kw, seed=sd))[0]).cpu().numpy().view(np.uint32)
+        seed_errs.append(float(np.mean([metrics.stretch_error(oh[:, k], exh[:, k], int(srcs[k]))
+                                        for k in range(0, len(srcs), 8)])))
+    errs = seed_errs
     q = len(srcs)
     alg = st.edges_gathered * 4.0 + st.edges_gathered / q * 8.0 + it * g.n * q * 8.0
     out["rmat20_sssp_q%d_sms" % q] = {
         "sigma": sg, "alpha": alpha, "iterations": it, "device_ms": round(st.device_ms, 3),
         "exact_device_ms": round(sx.device_ms, 3), "speedup": round(sx.device_ms / st.device_ms, 3),
         "accuracy": round(metrics.accuracy(float(np.mean(errs))), 3),
-        "within_1pct": bool(np.mean(errs) <= 0.01), "alg_gbs": round(alg / (st.device_ms * 1e-3) / 1e9, 1)}
+        "accuracy_min": round(metrics.accuracy(float(np.max(errs))), 3),
+        "within_1pct": bool(np.max(errs) <= 0.01), "alg_gbs": round(alg / (st.device_ms * 1e-3) / 1e9, 1)}
     log("batch: sssp sms", out["rmat20_sssp_q%d_sms" % q])
     G.close()
     t = time.perf_counter()
@@ -377,7 +398,7 @@ def main():
 
     outs = {}
 
-    def one_step(record):
+    def one_step(record, seed=1):
         stats = []
         for app in apps:
             out, st = G[app].exact_run(app, iters=iters[app], source=source)
@@ -385,7 +406,7 @@ def main():
             if record:
                 outs[(app, "exact")] = out.clone()
             for sg in sigmas:
-                out, st = G[app].approx_run(app, sg, "gg", alpha=args.alpha, theta=args.theta, seed=1,
+                out, st = G[app].approx_run(app, sg, "gg", alpha=args.alpha, theta=args.theta, seed=seed,
                                             iters=iters[app], source=source, stop="fixed_iters")
                 stats.append((app, "gg", sg, st))
                 if record:
@@ -404,7 +425,8 @@ def main():
     t0 = time.perf_counter()
     all_stats = []
     for k in range(args.steps):
-        all_stats += one_step(record=False)
+        # sampling seeds 1..5 in turn, as the paper averages runs over seeds
+        all_stats += one_step(record=False, seed=SEEDS[k % len(SEEDS)])
         log("timed step %d done" % (k + 1))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -415,29 +437,33 @@ def main():
     runs = {}
     for (app, pol, sg, st) in all_stats:
         key = "%s_%s" % (app, "exact" if pol == "exact" else "gg%.1f" % sg)
-        d = runs.setdefault(key, {"ms": [], "edges": st.edges_gathered, "iters": st.iterations})
+        d = runs.setdefault(key, {"ms": [], "edges": [], "iters": st.iterations})
         d["ms"].append(st.device_ms)
+        d["edges"].append(st.edges_gathered)
     m_eff = {"pr": gw.m, "sssp": gw.m, "cc": graphs["cc"].m if "cc" in graphs else 0}
     summary = {}
     for key, d in runs.items():
         app = key.split("_")[0]
         ms = float(np.mean(d["ms"]))
-        summary[key] = {"ms": round(ms, 3), "gteps_work": round(d["edges"] / ms / 1e6, 2),
+        summary[key] = {"ms": round(ms, 3), "gteps_work": round(float(np.mean(d["edges"])) / ms / 1e6, 2),
                         "gteps_eff": round(m_eff[app] * iters[app] / ms / 1e6, 2), "iters": d["iters"]}
     for app in apps:
         ex = summary["%s_exact" % app]["ms"]
         exact_h = outs[(app, "exact")].cpu().numpy()
         for sg in sigmas:
             key = "%s_gg%.1f" % (app, sg)
-            ap_h = outs[(app, sg)].cpu().numpy()
-            if app == "pr":
-                err = metrics.topk_error(ap_h, exact_h, 1000)
-            elif app == "sssp":
-                err = metrics.stretch_error(ap_h.view(np.uint32), exact_h.view(np.uint32), source)
-            else:
-                err = metrics.label_mismatch(ap_h, exact_h)
+            accs = []
+            for sd in SEEDS:
+                if sd == 1:
+                    ap_h = outs[(app, sg)].cpu().numpy()
+                else:  # untimed run with this seed
+                    o, _ = G[app].approx_run(app, sg, "gg", alpha=args.alpha, theta=args.theta, seed=sd,
+                                             iters=iters[app], source=source, stop="fixed_iters")
+                    ap_h = o.cpu().numpy()
+                accs.append(metrics.accuracy(app_error(metrics, np, app, ap_h, exact_h, source)))
             summary[key]["speedup"] = round(ex / summary[key]["ms"], 3)
-            summary[key]["accuracy"] = round(metrics.accuracy(err), 3)
+            summary[key]["accuracy"] = round(float(np.mean(accs)), 3)
+            summary[key]["accuracy_min"] = round(float(np.min(accs)), 3)
 
     # roofline of the dominant kernel (largest total event time in the timed
     # region); the exact and the approximate gathers are one kernel, so their

@@ -19,11 +19,17 @@ INF = 0xFFFFFFFF
 
 
 def top_k(values, k: int) -> np.ndarray:
+    """Ids of the k largest values, ties broken by the lower id, in rank
+    order. Only the candidates at or above the k-th largest value are
+    sorted."""
     v = np.asarray(values, dtype=np.float64)
     k = min(k, v.shape[0])
-    ids = np.arange(v.shape[0])
-    order = np.lexsort((ids, -v))
-    return order[:k]
+    if k <= 0:
+        return np.zeros(0, dtype=np.int64)
+    kth = np.partition(v, v.shape[0] - k)[v.shape[0] - k]
+    cand = np.nonzero(v >= kth)[0]
+    order = np.lexsort((cand, -v[cand]))
+    return cand[order[:k]]
 
 
 def topk_error(approx, exact, k: int = 1000) -> float:
