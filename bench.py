@@ -433,6 +433,26 @@ def main():
     edges_total = sum(st.edges_gathered for (_, _, _, st) in all_stats)
     gteps = edges_total / elapsed / 1e9
 
+    # roofline of the dominant kernel (largest total event time in the timed
+    # region); the exact and the approximate gathers are one kernel, so their
+    # launches are pooled
+    per_kernel = {}
+    for app in apps:
+        seg = G[app].get_tuning()["seg_enable"]
+        for kind in ("gather_exact", "gather_approx", "superstep", "push"):
+            p = G[app].get_profile(kind, app)
+            if not p["launches"]:
+                continue
+            kn = kernel_name(kind, app, seg)
+            d = per_kernel.setdefault(kn, {"launches": 0, "total_ms": 0.0, "alg_bytes": 0.0, "kinds": []})
+            for f in ("launches", "total_ms", "alg_bytes"):
+                d[f] += p[f]
+            d["kinds"].append(kind)
+    # the profiles hold the timed steps only: profiling stops before any
+    # further (untimed) run
+    for app in apps:
+        G[app].set_profiling(False)
+
     # per-run summaries (device time from the library's events)
     runs = {}
     for (app, pol, sg, st) in all_stats:
@@ -465,21 +485,6 @@ def main():
             summary[key]["accuracy"] = round(float(np.mean(accs)), 3)
             summary[key]["accuracy_min"] = round(float(np.min(accs)), 3)
 
-    # roofline of the dominant kernel (largest total event time in the timed
-    # region); the exact and the approximate gathers are one kernel, so their
-    # launches are pooled
-    per_kernel = {}
-    for app in apps:
-        seg = G[app].get_tuning()["seg_enable"]
-        for kind in ("gather_exact", "gather_approx", "superstep", "push"):
-            p = G[app].get_profile(kind, app)
-            if not p["launches"]:
-                continue
-            kn = kernel_name(kind, app, seg)
-            d = per_kernel.setdefault(kn, {"launches": 0, "total_ms": 0.0, "alg_bytes": 0.0, "kinds": []})
-            for f in ("launches", "total_ms", "alg_bytes"):
-                d[f] += p[f]
-            d["kinds"].append(kind)
     kname, pb = max(per_kernel.items(), key=lambda kv: kv[1]["total_ms"])
     # every sweep kernel of the timed region, largest total time first
     by_kernel = []
