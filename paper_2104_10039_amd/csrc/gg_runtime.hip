@@ -79,6 +79,7 @@ struct gg_graph {
   int32_t n = 0;
   int64_t m = 0;
   hipStream_t stream = nullptr;
+  void* pin = nullptr;  // kPinBytes of pinned host memory for small readbacks
   bool owns_csr = false;
   int32_t* rowptr = nullptr;
   int32_t* col = nullptr;
@@ -234,11 +235,23 @@ int64_t max_chunks(const gg_graph* g) {
   return m / g->tune.hub_chunk + m / ((int64_t)g->tune.wave_max + 1) + 2;
 }
 
-int sync_bins(gg_graph* g, Bins& b) {
-  GG_HIP(hipMemcpyAsync(&b.h, b.dcounts, sizeof(BinCounts), hipMemcpyDeviceToHost, g->stream));
-  GG_HIP(hipStreamSynchronize(g->stream));
+// Small device-to-host readback that the host waits for: through the graph's
+// pinned buffer when it fits (a direct DMA, no staging copy).
+constexpr size_t kPinBytes = 256;
+
+int readback(gg_graph* g, void* dst, const void* src, size_t bytes) {
+  if (g->pin && bytes <= kPinBytes) {
+    GG_HIP(hipMemcpyAsync(g->pin, src, bytes, hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipStreamSynchronize(g->stream));
+    std::memcpy(dst, g->pin, bytes);
+  } else {
+    GG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, g->stream));
+    GG_HIP(hipStreamSynchronize(g->stream));
+  }
   return GG_OK;
 }
+
+int sync_bins(gg_graph* g, Bins& b) { return readback(g, &b.h, b.dcounts, sizeof(BinCounts)); }
 
 int alloc_bins(Bins& b, int32_t n) {
   GG_TRY(dalloc(&b.list, (size_t)n));
@@ -551,6 +564,7 @@ void free_graph(gg_graph* g) {
   for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
+  if (g->pin) (void)hipHostFree(g->pin);
   delete g;
 }
 
@@ -766,8 +780,7 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
         const int32_t src = p->source;
         int32_t od = 0;
         GG_HIP(hipMemcpyAsync(g->flist[0], &src, sizeof(int32_t), hipMemcpyHostToDevice, g->stream));
-        GG_HIP(hipMemcpyAsync(&od, g->outdeg + src, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
-        GG_HIP(hipStreamSynchronize(g->stream));
+        GG_TRY(readback(g, &od, g->outdeg + src, sizeof(int32_t)));
         r->fcur = 0;
         r->front_count = 1;
         r->front_outdeg = od;
@@ -1081,18 +1094,14 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   int64_t changed = -1;
   if (frontier) {
     FrontCounters h = {0, 0, 0};
-    if (!idle) {
-      GG_HIP(hipMemcpyAsync(&h, g->fc, sizeof(h), hipMemcpyDeviceToHost, g->stream));
-      GG_HIP(hipStreamSynchronize(g->stream));
-    }
+    if (!idle) GG_TRY(readback(g, &h, g->fc, sizeof(h)));
     r->fcur = 1 - r->fcur;
     r->front_count = h.count;
     r->front_outdeg = h.outdeg_sum;
     changed = h.count;
   } else if (!pr && sync_changed) {
     int32_t hc = 0;
-    GG_HIP(hipMemcpyAsync(&hc, g->changed, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
-    GG_HIP(hipStreamSynchronize(g->stream));
+    GG_TRY(readback(g, &hc, g->changed, sizeof(int32_t)));
     changed = hc;
   }
   // termination
@@ -1167,8 +1176,7 @@ int pr_initial_x(gg_run* r) {
 int check_hub_sync(gg_graph* g) {
   if (!g->hub_sync) return GG_OK;
   uint32_t e = 0;
-  GG_HIP(hipMemcpyAsync(&e, g->hub_sync, sizeof(e), hipMemcpyDeviceToHost, g->stream));
-  GG_HIP(hipStreamSynchronize(g->stream));
+  GG_TRY(readback(g, &e, g->hub_sync, sizeof(e)));
   if (e == 0) return GG_OK;
   GG_HIP(launch_fill_u32(g->hub_sync, 1, 0u, g->stream));
   return fail(GG_E_DEVICE, "a superstep hub chunk gave up waiting for its row prefix");
@@ -1676,6 +1684,11 @@ int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
       free_graph(g);
       return code;
     };
+    if (hipHostMalloc(&g->pin, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      g->pin = nullptr;
+      return bail(fail(GG_E_NOMEM, "pinned readback buffer"));
+    }
     if (d->flags & GG_CSR_DEVICE_PTRS) {
       g->owns_csr = false;
       g->rowptr = const_cast<int32_t*>(d->rowptr);
