@@ -180,3 +180,35 @@ def test_learned_state_unsupported(P, graphs):
     assert e.value.code == E_UNSUPPORTED
     R.close()
     net.close()
+
+
+@pytest.mark.parametrize("app", ["pr", "sssp", "cc"])
+def test_resume_on_a_union_of_graphs(P, app):
+    """Resume on a block-diagonal union (per-part vertex counts, dangling
+    masses, sources and sampling seeds) continues as the uninterrupted run."""
+    import graphgen as gg
+    gs = gg.rmat_family(8, scale_range=(6, 11), ef_range=(4, 16), seed0=500, weights=(app == "sssp"),
+                        symmetrize=(app == "cc"))
+    U, ps = gg.union(gs)
+    srcs = None
+    if app == "sssp":
+        srcs = np.array([ps[p] + int(gg.pick_sources(gs[p], 1, 60 + p)[0]) for p in range(len(gs))], np.int32)
+    G = P.Graph.from_host(U)
+    G.set_parts(ps, srcs)
+    kw = dict(alpha=2, theta=0.1, seed=3, iters=12)
+    log("case: resume on parts", app)
+    R = G.begin(app, 0.4, "gg", **kw)
+    full = trail(R, app)
+    R.close()
+    for j in (1, 5, len(full) - 1):
+        R = G.begin(app, 0.4, "gg", **kw)
+        for _ in range(j):
+            R.step()
+        state = R.export_state()
+        R.close()
+        R2 = G.begin(app, 0.4, "gg", **kw)
+        R2.import_state(state)
+        rest = trail(R2, app)
+        R2.close()
+        assert_same_trail(rest, full[j:], "parts %s j=%d" % (app, j))
+    G.close()
