@@ -1093,12 +1093,20 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   r->edges_processed += processed;
   int64_t changed = -1;
   if (frontier) {
+    // The counters decide whether the next iteration may push. The host need
+    // not wait for them when that iteration runs dense anyway (a superstep, or
+    // the switch to accurate mode) or when a fixed-count run ends here, unless
+    // the caller wants the changed count; the frontier is then left unknown.
+    const int nk = step_kind(r->pol, i + 1);
+    const bool next_dense = nk == GG_STEP_FULL || (nk == GG_STEP_ACCURATE && step_kind(r->pol, i) == GG_STEP_APPROX &&
+                                                   r->pol.kind != GG_POLICY_EXACT);
+    const bool known = idle || sync_changed || !(last_fixed || next_dense);
     FrontCounters h = {0, 0, 0};
-    if (!idle) GG_TRY(readback(g, &h, g->fc, sizeof(h)));
+    if (!idle && known) GG_TRY(readback(g, &h, g->fc, sizeof(h)));
     r->fcur = 1 - r->fcur;
-    r->front_count = h.count;
-    r->front_outdeg = h.outdeg_sum;
-    changed = h.count;
+    r->front_count = known ? h.count : -1;
+    r->front_outdeg = known ? h.outdeg_sum : 0;
+    changed = known ? h.count : -1;
   } else if (!pr && sync_changed) {
     int32_t hc = 0;
     GG_TRY(readback(g, &hc, g->changed, sizeof(int32_t)));
