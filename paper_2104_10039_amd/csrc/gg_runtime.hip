@@ -1193,7 +1193,8 @@ int check_hub_sync(gg_graph* g) {
 int run_values(gg_run* r, void* out, uint32_t flags) {
   gg_graph* g = r->g;
   if (!out) return fail(GG_E_INVAL, "null output");
-  GG_TRY(check_hub_sync(g));
+  // only a superstep can raise the hub error word
+  if (r->supersteps > 0) GG_TRY(check_hub_sync(g));
   if (is_pr(r->p.app)) {
     if (r->iter == 0) GG_TRY(pr_initial_x(r));
     if (!r->x_valid) return fail(GG_E_STATE, "PR values of this iteration were not materialized");
