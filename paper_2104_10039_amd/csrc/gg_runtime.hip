@@ -238,6 +238,8 @@ int64_t max_chunks(const gg_graph* g) {
 // Small device-to-host readback that the host waits for: through the graph's
 // pinned buffer when it fits (a direct DMA, no staging copy).
 constexpr size_t kPinBytes = 256;
+static_assert(sizeof(BinCounts) <= kPinBytes && sizeof(FrontCounters) <= kPinBytes,
+              "the per-iteration readbacks fit the pinned buffer");
 
 int readback(gg_graph* g, void* dst, const void* src, size_t bytes) {
   if (g->pin && bytes <= kPinBytes) {
