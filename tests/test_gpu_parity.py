@@ -306,6 +306,22 @@ def test_abi_errors(P):
     with pytest.raises(P.GGError):
         G.approx_run("pr", 2.0, "gg", out=out)
     assert torch.all(out == 7.0)
+    # weighted graphs: n <= 2^24 (distances then fit uint32), one more vertex is rejected
+    for n_w, code in (((1 << 24) + 1, -2), (1 << 24, 0)):
+        rp_w = np.zeros(n_w + 1, dtype=np.int32)
+        rp_w[1:] = 1  # row 0 holds one in-edge, from vertex 1
+        col_w = np.array([1], dtype=np.int32)
+        w_w = np.array([7], dtype=np.int32)
+        if code:
+            with pytest.raises(P.GGError) as ei:
+                P.Graph(n_w, rp_w, col_w, w_w)
+            assert ei.value.code == code
+        else:
+            Gw = P.Graph(n_w, rp_w, col_w, w_w)
+            d, _ = Gw.exact_run("sssp", source=1)
+            d = d.cpu().numpy().view(np.uint32)
+            assert d[1] == 0 and d[0] == 7 and d[2] == 0xFFFFFFFF
+            Gw.close()
     # one run at a time per graph
     R = G.begin("pr", 0.5, "gg")
     with pytest.raises(P.GGError) as ei:
