@@ -19,6 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _HDR = os.path.join(_HERE, "oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A prebuilt oracle library to load instead (the mutation tests point this at
+# copies of the oracle with one planted mistake); build() leaves it alone.
+_LIB_OVERRIDE = os.environ.get("GGO_ORACLE_LIB")
 
 PR, SSSP, CC, PPR = 0, 1, 2, 3
 EXACT, SP, SMS, GG, LEARNED = 0, 1, 2, 3, 4
@@ -44,6 +47,8 @@ POLICY_NAMES = {"exact": EXACT, "sp": SP, "sms": SMS, "gg": GG, "learned": LEARN
 
 def build(force: bool = False) -> str:
     """Compile the oracle: plain single-threaded C at -O2."""
+    if _LIB_OVERRIDE:
+        return _LIB_OVERRIDE
     newest = max(os.path.getmtime(_SRC), os.path.getmtime(_HDR))
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
@@ -78,8 +83,7 @@ class _Info(ctypes.Structure):
 
 @functools.lru_cache(maxsize=None)
 def _lib():
-    build()
-    lib = ctypes.CDLL(_LIB)
+    lib = ctypes.CDLL(build())
     lib.ggo_philox4x64_10.argtypes = [ctypes.POINTER(ctypes.c_uint64)] * 3
     lib.ggo_sample_draw.restype = ctypes.c_uint32
     lib.ggo_sample_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64]

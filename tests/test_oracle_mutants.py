@@ -1,0 +1,74 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a temporary copy of oracle/oracle.c (a
+dropped term, a wrong index or operand, an off-by-one), builds that copy,
+and runs the pin suite (tests/test_oracle_pins.py) against it in a child
+process; at least one pin must fail. The oracle itself is never modified.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+
+# name: (text of oracle.c, its replacement)
+MUTANTS = {
+    # Alg. 2 GG-Apply without the dangling-mass term
+    "pr_apply_drops_dangling": ("xn = (1.0 - d) / n + d * (sum + D / n);", "xn = (1.0 - d) / n + d * (sum);"),
+    # Alg. 2 GG-Gather without the division by the out-degree
+    "pr_gather_no_outdeg": ("sum += r->pr_x[v] / r->outdeg[v];", "sum += r->pr_x[v];"),
+    # PREFIX influence over the running sum before the edge's own contribution
+    "pr_prefix_exclusive": ("        P += c;\n        double influence;",
+                            "        double influence;\n        P += 0.0;"),
+    # SSSP relaxation with an off-by-one weight
+    "sssp_weight_off_by_one": ("const uint64_t cand = (uint64_t)xv + (uint64_t)g->weight[e];\n      if (cand < best)",
+                               "const uint64_t cand = (uint64_t)xv + (uint64_t)g->weight[e] + 1u;\n      if (cand < best)"),
+    # CC gather reading the destination's label instead of the source's
+    "cc_reads_destination": ("      const int32_t xv = r->l_x[g->col[e]];\n      if (xv < best) best = xv;",
+                             "      const int32_t xv = r->l_x[u];\n      if (xv < best) best = xv;"),
+    # GG schedule with the wrong period
+    "gg_period_off_by_one": ("case GGO_GG: kind = (i % (p->alpha + 1)) == 0",
+                             "case GGO_GG: kind = (i % (p->alpha + 2)) == 0"),
+    # CC influence relative to the row's first label only (running minimum never updated)
+    "cc_influence_no_running_min": ("        r->infl[e] = xv < run ? 1.0 : 0.0;\n        if (xv < run) run = xv;",
+                                    "        r->infl[e] = xv < run ? 1.0 : 0.0;"),
+}
+
+
+def run_pins_against(tmp_path, src):
+    """Build `src` as an oracle library in tmp_path and run the pin suite
+    against it in a child process; returns pytest's exit code."""
+    with open(tmp_path / "oracle.c", "w") as f:
+        f.write(src)
+    shutil.copy(os.path.join(ORACLE, "oracle.h"), tmp_path / "oracle.h")
+    lib = str(tmp_path / "liboracle_copy.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", lib, str(tmp_path / "oracle.c"), "-lm"])
+    env = dict(os.environ, GGO_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode, r.stdout
+
+
+def oracle_source():
+    with open(os.path.join(ORACLE, "oracle.c")) as f:
+        return f.read()
+
+
+def test_unmodified_copy_passes_the_pins(tmp_path):
+    code, out = run_pins_against(tmp_path, oracle_source())
+    assert code == 0, out[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = oracle_source()
+    assert src.count(old) == 1, "the mutant's target text must occur exactly once"
+    code, out = run_pins_against(tmp_path, src.replace(old, new))
+    # exit code 1: tests ran and at least one failed (not a crash or an error)
+    assert code == 1, "no pin failed for mutant %s:\n%s" % (name, out[-2000:])
