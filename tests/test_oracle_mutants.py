@@ -1,7 +1,8 @@
 """The oracle's pins catch plausible mistakes.
 
 Each case plants one mistake in a temporary copy of oracle/oracle.c (a
-dropped term, a wrong index or operand, an off-by-one), builds that copy,
+dropped term, a wrong index or operand, an off-by-one, a non-strict
+comparison), builds that copy,
 and runs the pin suite (tests/test_oracle_pins.py) against it in a child
 process; at least one pin must fail. The oracle itself is never modified.
 """
@@ -33,6 +34,18 @@ MUTANTS = {
     # GG schedule with the wrong period
     "gg_period_off_by_one": ("case GGO_GG: kind = (i % (p->alpha + 1)) == 0",
                              "case GGO_GG: kind = (i % (p->alpha + 2)) == 0"),
+    # SSSP EStatus: improvement measured against the new minimum instead of the old one
+    "sssp_estatus_wrong_denominator": ("flag = ((run - nw) << 16) > theta_q * run;",
+                                       "flag = ((run - nw) << 16) > theta_q * nw;"),
+    # SSSP EStatus deactivating the arcs of unreached sources
+    "sssp_unreached_deactivated": ("if (xv == GGO_INF_U32) continue; /* not assessable: keeps its flag */",
+                                   "if (xv == GGO_INF_U32) { r->active[e] = 0; continue; }"),
+    # EStatus with >= instead of the strict > of Alg. 2
+    "estatus_not_strict": ("const int flag = r->infl[e] > r->pol.theta;",
+                           "const int flag = r->infl[e] >= r->pol.theta;"),
+    # PPR teleporting to every vertex instead of the source
+    "ppr_teleport_everywhere": ("xn = (u == s ? (1.0 - d) : 0.0) + d * (sum + (u == s ? D : 0.0));",
+                                "xn = (1.0 - d) / n + d * (sum + (u == s ? D : 0.0));"),
     # CC influence relative to the row's first label only (running minimum never updated)
     "cc_influence_no_running_min": ("        r->infl[e] = xv < run ? 1.0 : 0.0;\n        if (xv < run) run = xv;",
                                     "        r->infl[e] = xv < run ? 1.0 : 0.0;"),

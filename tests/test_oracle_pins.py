@@ -517,3 +517,56 @@ def test_invalid_arguments_rejected():
     gnw = gg.rmat(6, 4, seed=85)
     with pytest.raises(ValueError):
         oracle.Run(gnw, "sssp", "exact", source=0)
+
+
+# ---------------------------------------------------------------------------
+# EStatus decisions on hand-built rows (values worked out by hand)
+# ---------------------------------------------------------------------------
+
+def _eid(g, s, d):
+    """Edge id of the arc s -> d in the canonical in-CSR (first occurrence)."""
+    row = g.col[g.rowptr[d]:g.rowptr[d + 1]]
+    return int(g.rowptr[d] + int(np.nonzero(row == s)[0][0]))
+
+
+def test_sssp_estatus_improvement_is_relative_to_the_old_minimum():
+    """Row 3 sees candidates 100 (via 1) then 95 (via 2) at the superstep of
+    iteration 2. The improvement (100 - 95) / 100 = 0.05 does not exceed
+    theta = 0.05 (strict, compared as 5 * 2^16 = 327680 against
+    round(0.05 * 2^16) * 100 = 327700), so the arc 2 -> 3 is deactivated; the
+    first finite candidate is always active [Alg. 2, GG-EStatus; reading 10]."""
+    g = gg.from_edges(4, [0, 0, 1, 2], [1, 2, 3, 3], [50, 45, 50, 50], name="sssp_rel")
+    r = oracle.Run(g, "sssp", "gg", sigma=1.0, alpha=1, theta=0.05, seed=1, iters=2, source=0)
+    r.step()
+    r.step()
+    mask = r.mask()
+    assert mask[_eid(g, 1, 3)] == 1 and mask[_eid(g, 2, 3)] == 0
+    assert list(r.values()) == [0, 50, 45, 95]
+    r.close()
+
+
+def test_sssp_unreached_source_keeps_its_flag():
+    """Path 0 -> 1 -> 2 -> 3: at the superstep of iteration 2 vertex 2 is
+    still unreached, so the arc 2 -> 3 cannot be assessed and keeps its flag
+    (active, sigma = 1); the assessed arcs stay active as first finite
+    candidates [Sec. 3.4; reading 11]."""
+    g = gg.from_edges(4, [0, 1, 2], [1, 2, 3], [1, 1, 1], name="sssp_path")
+    r = oracle.Run(g, "sssp", "gg", sigma=1.0, alpha=1, theta=0.05, seed=1, iters=2, source=0)
+    r.step()
+    r.step()
+    assert list(r.mask()) == [1, 1, 1]
+    r.close()
+
+
+def test_estatus_is_strict_for_binary_cc_influence():
+    """Triangle 0-1-2 (both directions), every iteration a superstep
+    (alpha = 0), theta = 0: row 2 reads label 0 (via 0, influence 1) then
+    label 1 (via 1, influence 0); 0 > 0 is false, so the arc 1 -> 2 is
+    deactivated [Alg. 2, GG-EStatus: active iff influence > threshold]."""
+    g = gg.from_edges(3, [0, 1, 0, 2, 1, 2], [1, 0, 2, 0, 2, 1], None, name="triangle")
+    r = oracle.Run(g, "cc", "gg", sigma=1.0, alpha=0, theta=0.0, seed=1, iters=1)
+    r.step()
+    mask = r.mask()
+    assert mask[_eid(g, 0, 2)] == 1 and mask[_eid(g, 1, 2)] == 0
+    assert mask[_eid(g, 0, 1)] == 1 and mask[_eid(g, 2, 1)] == 0
+    r.close()
