@@ -443,3 +443,33 @@ def test_frontier_push_used_and_exact(P, app):
         compare_values(app, device_values(out, app), want.values, ctx=pol)
         assert st.edges_gathered == want.edges
     G.close()
+
+
+@pytest.mark.parametrize("case", ["sssp_tie", "sssp_unreached", "cc_strict"])
+def test_estatus_edge_cases_on_gpu(P, case):
+    """Hand-built rows where EStatus sits on its boundary (an SSSP improvement
+    that ties theta, an unassessable arc, a zero CC influence at theta = 0):
+    the library's flags and values equal the oracle's after every step."""
+    if case == "sssp_tie":
+        g = gg.from_edges(4, [0, 0, 1, 2], [1, 2, 3, 3], [50, 45, 50, 50], name=case)
+        app, kw = "sssp", dict(alpha=1, theta=0.05, iters=2, source=0)
+    elif case == "sssp_unreached":
+        g = gg.from_edges(4, [0, 1, 2], [1, 2, 3], [1, 1, 1], name=case)
+        app, kw = "sssp", dict(alpha=1, theta=0.05, iters=2, source=0)
+    else:
+        g = gg.from_edges(3, [0, 1, 0, 2, 1, 2], [1, 0, 2, 0, 2, 1], None, name=case)
+        app, kw = "cc", dict(alpha=0, theta=0.0, iters=1)
+    log("case:", case)
+    G = P.Graph.from_host(g)
+    R = G.begin(app, 1.0, "gg", seed=1, **kw)
+    ref = oracle.Run(g, app, "gg", sigma=1.0, seed=1, **kw)
+    while True:
+        a, b = R.step(), ref.step()
+        assert (a is None) == (b is None)
+        if a is None:
+            break
+        assert np.array_equal(R.mask(), ref.mask()), case
+        compare_values(app, device_values(R.values(host=False), app), ref.values(), ctx=case)
+    R.close()
+    ref.close()
+    G.close()
