@@ -344,6 +344,20 @@ int gg_graph_get_tuning(const gg_graph* g, gg_tuning* out);
 int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t);
 
 /*
+ * Bounded waits of the superstep (project addition, no counterpart in the
+ * paper). The workgroups that share one long row take their row prefix and
+ * write offset from the row's earlier chunks, polling words those chunks
+ * publish; every such wait ends by construction. A wait that still reaches
+ * `polls` polls gives up: the chunk writes no active edge and no active
+ * count, and the step that ran the superstep returns GG_E_DEVICE with its
+ * results undefined (the next run on the graph starts clean). The default is
+ * 2^20 polls; polls <= 0 makes every such wait give up at once, so that
+ * callers can test their handling of that failure. GG_E_STATE while a run is
+ * active on the graph.
+ */
+int gg_graph_set_wait_limit(gg_graph* g, int32_t polls);
+
+/*
  * Autotuner (project addition): picks the tuning knobs for one workload on
  * this graph by timing that workload. With n_queries = 0 the workload is a
  * single run (gg_exact_run when policy is NULL or EXACT, else gg_approx_run

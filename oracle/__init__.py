@@ -39,6 +39,8 @@ FIXED_ITERS, FIXED_POINT = 0, 1
 INFL_PREFIX, INFL_TOTAL = 0, 1
 MASK_REPLACE, MASK_UNION = 0, 1
 DANGLING_UNIFORM, DANGLING_NONE = 0, 1
+DEGREE_FULL, DEGREE_ACTIVE = 0, 1
+VSTATUS_NONE, VSTATUS_ABS, VSTATUS_REL = 0, 1, 2
 INF = 0xFFFFFFFF
 
 APP_NAMES = {"pr": PR, "sssp": SSSP, "cc": CC, "ppr": PPR}
@@ -64,7 +66,8 @@ class _Csr(ctypes.Structure):
 
 class _App(ctypes.Structure):
     _fields_ = [("app", ctypes.c_int32), ("damping", ctypes.c_double), ("iters", ctypes.c_int32),
-                ("max_iters", ctypes.c_int32), ("source", ctypes.c_int32), ("dangling", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("source", ctypes.c_int32), ("dangling", ctypes.c_int32),
+                ("pr_degree", ctypes.c_int32)]
 
 
 class _Pol(ctypes.Structure):
@@ -72,7 +75,9 @@ class _Pol(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("influence", ctypes.c_int32),
                 ("mask_update", ctypes.c_int32), ("stop", ctypes.c_int32), ("mlp", ctypes.c_void_p),
                 ("tau", ctypes.c_double), ("rho", ctypes.c_double), ("fallback_k", ctypes.c_int32),
-                ("trace", ctypes.c_int32), ("label_eps", ctypes.c_double)]
+                ("trace", ctypes.c_int32), ("label_eps", ctypes.c_double), ("decoupled", ctypes.c_int32),
+                ("alpha0", ctypes.c_int32), ("theta0", ctypes.c_double), ("vstatus", ctypes.c_int32),
+                ("eps", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -99,7 +104,8 @@ def _lib():
     lib.ggo_iterations.argtypes = [ctypes.c_void_p]
     lib.ggo_edges_total.restype = ctypes.c_int64
     lib.ggo_edges_total.argtypes = [ctypes.c_void_p]
-    for f in ("ggo_get_values", "ggo_get_mask", "ggo_get_influence"):
+    for f in ("ggo_get_values", "ggo_get_mask", "ggo_get_influence", "ggo_set_mask", "ggo_get_vactive",
+              "ggo_set_vactive"):
         getattr(lib, f).argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.ggo_end.argtypes = [ctypes.c_void_p]
     lib.ggo_get_features.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -168,7 +174,8 @@ class Run:
     def __init__(self, g, app, policy="exact", sigma=1.0, alpha=4, theta=0.05, seed=1,
                  damping=0.85, iters=20, max_iters=100000, source=0, dangling=DANGLING_UNIFORM,
                  influence=INFL_PREFIX, mask_update=MASK_REPLACE, stop=FIXED_ITERS, mlp=None, tau=0.0,
-                 rho=1.0, fallback_k=0, trace=False, label_eps=1e-3):
+                 rho=1.0, fallback_k=0, trace=False, label_eps=1e-3, pr_degree=DEGREE_FULL, alpha0=None,
+                 theta0=None, vstatus=VSTATUS_NONE, eps=0.0):
         self._lib = _lib()
         self.app = APP_NAMES[app] if isinstance(app, str) else int(app)
         kind = POLICY_NAMES[policy] if isinstance(policy, str) else int(policy)
@@ -179,13 +186,14 @@ class Run:
         self._w = None if g.weight is None else np.ascontiguousarray(g.weight, dtype=np.int32)
         csr = _Csr(self.n, self.m, self._rowptr.ctypes.data, self._col.ctypes.data,
                    None if self._w is None else self._w.ctypes.data)
-        ap = _App(self.app, damping, iters, max_iters, source, dangling)
+        ap = _App(self.app, damping, iters, max_iters, source, dangling, pr_degree)
         self._mlp = None if mlp is None else np.ascontiguousarray(mlp, dtype=np.float64)
         if self._mlp is not None and self._mlp.size != MLP_PARAMS:
             raise ValueError("mlp needs %d parameters" % MLP_PARAMS)
         po = _Pol(kind, alpha, theta, sigma, seed, influence, mask_update, stop,
                   None if self._mlp is None else self._mlp.ctypes.data, tau, rho, fallback_k, int(bool(trace)),
-                  label_eps)
+                  label_eps, int(alpha0 is not None or theta0 is not None),
+                  alpha if alpha0 is None else alpha0, theta if theta0 is None else theta0, vstatus, eps)
         self._h = self._lib.ggo_begin(ctypes.byref(csr), ctypes.byref(ap), ctypes.byref(po))
         if not self._h:
             raise ValueError("oracle: " + self._lib.ggo_last_error().decode())
@@ -219,6 +227,24 @@ class Run:
         out = np.empty(max(self.m, 1), dtype=np.uint8)
         self._lib.ggo_get_mask(self._h, out.ctypes.data)
         return out[: self.m]
+
+    def set_mask(self, mask):
+        """Adopt another side's edge flags (one value per edge, nonzero = active)."""
+        a = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+        if a.size != self.m:
+            raise ValueError("mask needs %d entries" % self.m)
+        self._lib.ggo_set_mask(self._h, a.ctypes.data if self.m else None)
+
+    def vactive(self) -> np.ndarray:
+        out = np.empty(max(self.n, 1), dtype=np.uint8)
+        self._lib.ggo_get_vactive(self._h, out.ctypes.data)
+        return out[: self.n]
+
+    def set_vactive(self, act):
+        a = np.ascontiguousarray(np.asarray(act) != 0, dtype=np.uint8)
+        if a.size != self.n:
+            raise ValueError("vertex status needs %d entries" % self.n)
+        self._lib.ggo_set_vactive(self._h, a.ctypes.data if self.n else None)
 
     def influence(self) -> np.ndarray:
         out = np.empty(max(self.m, 1), dtype=np.float64)

@@ -42,14 +42,27 @@
  *    approximate runs either run a fixed number of iterations or stop after a
  *    no-change iteration that no later iteration can follow differently.
  *
- * Not in the paper (its automatic choice of control parameters is left to
- * future work, Sec. 7): a LEARNED policy keeps GG's correction schedule but
- * lets a small MLP pick the rows corrected at each correction step (a
- * partial superstep), with GG's full superstep as fallback every k-th
- * correction step or when the selected rows hold more than rho * m in-edges. Its features, the
- * network, the loss and Adam are plain definitions written out below; the
- * drift label of a traced full superstep compares the accurate update with
- * the approximate one the flags alone would have given.
+ * Variants the paper mentions without fixing them (each a flag):
+ *  - Decoupled parameters: the first superstep after alpha0 approximate
+ *    iterations with threshold theta0, later ones every alpha+1 iterations
+ *    with theta [Sec. 3.4, last paragraph].
+ *  - ACTIVE out-degree: in approximate iterations PageRank divides by the
+ *    count of active out-edges and treats vertices without one as dangling,
+ *    i.e. it is PageRank of the sparsified graph [Alg. 2 reads v.degree].
+ *  - GG-VStatus with epsilon > 0 [Alg. 2]: approximate PageRank iterations
+ *    after the first recompute only rows with an active in-edge from a
+ *    vertex whose value moved by more than epsilon (absolute, or relative to
+ *    its old value) in the previous iteration; the active-vertex list of
+ *    Sec. 2.1, which starts with every vertex.
+ *
+ * A project addition, not part of the paper: a LEARNED policy keeps GG's
+ * correction schedule but lets a small MLP pick the rows corrected at each
+ * correction step (a partial superstep), with GG's full superstep as
+ * fallback every k-th correction step or when the selected rows hold more
+ * than rho * m in-edges. Its features, the network, the loss and Adam are
+ * plain definitions written out below; the drift label of a traced full
+ * superstep compares the accurate update with the approximate one the flags
+ * alone would have given.
  */
 #include "oracle.h"
 
@@ -120,9 +133,8 @@ uint64_t ggo_keep_threshold(double sigma) {
 
 /* ---------------------------------------------------------------------------
  * BF16 (bfloat16) rounding and the correction MLP. The MLP scores vertices
- * for drift; it is not part of the paper's method (the paper leaves the
- * automatic choice of its control parameters to future work, Sec. 7) and is
- * written here as the plain definition of a 8-64-64-1 ReLU network.
+ * for drift; it is a project addition, not part of the paper's method, and
+ * is written here as the plain definition of a 8-64-64-1 ReLU network.
  * ------------------------------------------------------------------------- */
 
 /* Round-to-nearest-even from binary32 to bfloat16 bits (NaN -> 0x7FC0). */
@@ -340,7 +352,27 @@ struct ggo_run {
   int32_t iter;
   int32_t done;
   int64_t edges_total;
+  /* variants */
+  int32_t* odeg_act; /* ACTIVE: active out-degree of the current flags */
+  uint8_t* vact;     /* vertex status after the last iteration (GG-VStatus) */
+  uint8_t* skip;     /* rows not recomputed in this iteration (GG-VStatus) */
+  double theta_now;  /* threshold of this iteration's superstep */
 };
+
+/* Superstep (correction step) of GG and LEARNED at iteration i, 1-based:
+   every (alpha+1)-th iteration; with decoupled parameters the first comes
+   after alpha0 approximate iterations and the later ones every alpha+1
+   iterations after it [Sec. 3.4]. */
+static int is_correction(const ggo_policy* p, int32_t i) {
+  if (!p->decoupled) return i % (p->alpha + 1) == 0;
+  const int32_t first = p->alpha0 + 1;
+  return i == first || (i > first && (i - first) % (p->alpha + 1) == 0);
+}
+
+/* Influence threshold of the superstep at iteration i. */
+static double theta_at(const ggo_policy* p, int32_t i) {
+  return (p->decoupled && i == p->alpha0 + 1) ? p->theta0 : p->theta;
+}
 
 /* State word of vertex u for the delta features: PR/PPR the binary32
    contribution x_u / outdeg_u (x_u without out-edges), SSSP the distance,
@@ -392,6 +424,18 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
     set_err("TOTAL influence is defined for PR/PPR only");
     return NULL;
   }
+  const int pr_app = app->app == GGO_PR || app->app == GGO_PPR;
+  if (app->pr_degree != GGO_DEGREE_FULL && app->pr_degree != GGO_DEGREE_ACTIVE) { set_err("bad pr_degree"); return NULL; }
+  if (app->pr_degree == GGO_DEGREE_ACTIVE && (!pr_app || pol->kind == GGO_LEARNED || pol->trace)) {
+    set_err("ACTIVE degree: PR/PPR under EXACT, SP, SMS or GG without traces");
+    return NULL;
+  }
+  if (pol->decoupled && (pol->alpha0 < 0 || !(pol->theta0 >= 0))) { set_err("bad alpha0/theta0"); return NULL; }
+  if (pol->vstatus < GGO_VSTATUS_NONE || pol->vstatus > GGO_VSTATUS_REL) { set_err("bad vstatus"); return NULL; }
+  if (pol->vstatus != GGO_VSTATUS_NONE && (!pr_app || !(pol->eps >= 0) || pol->kind == GGO_LEARNED || pol->trace)) {
+    set_err("VStatus: PR/PPR, eps >= 0, not LEARNED, no traces");
+    return NULL;
+  }
 
   ggo_run* r = (ggo_run*)calloc(1, sizeof(ggo_run));
   r->g = *g;
@@ -411,6 +455,11 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
   r->logit = (double*)calloc((size_t)n + 1, sizeof(double));
   r->sel = (uint8_t*)calloc((size_t)n + 1, 1);
   r->label = (uint8_t*)calloc((size_t)n + 1, 1);
+  r->odeg_act = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  r->vact = (uint8_t*)malloc((size_t)n + 1);
+  memset(r->vact, 1, (size_t)n + 1); /* every vertex starts active */
+  r->skip = (uint8_t*)calloc((size_t)n + 1, 1);
+  r->theta_now = pol->theta;
 
   /* Initial sparsification [Sec. 3.4]: each edge kept iff its draw falls
      below floor(sigma * 2^32 + 1/2). The exact baseline ignores the flags. */
@@ -457,26 +506,34 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
  * source). For a SUPER row each edge's influence is computed from the
  * running sum of the row, all in-edges in CSR order.
  * ------------------------------------------------------------------------- */
-static void pass_pr(ggo_run* r, const uint8_t* mode, double* out, int64_t* edges_out, int64_t* changed_out) {
+static void pass_pr(ggo_run* r, const uint8_t* mode, const int32_t* deg, const uint8_t* skip, double* out,
+                    int64_t* edges_out, int64_t* changed_out) {
   const ggo_csr* g = &r->g;
   const int32_t n = g->n;
   const double d = r->app.damping;
   const int ppr = r->app.app == GGO_PPR;
   const int32_t s = r->app.source;
+  /* deg: the out-degree this iteration divides by; vertices with none are
+     dangling */
   double D = 0.0;
   if (r->app.dangling == GGO_DANGLING_UNIFORM)
     for (int32_t v = 0; v < n; ++v)
-      if (r->outdeg[v] == 0) D += r->pr_x[v];
+      if (deg[v] == 0) D += r->pr_x[v];
 
   int64_t edges = 0, changed = 0;
   for (int32_t u = 0; u < n; ++u) {
+    if (skip && skip[u]) {
+      /* not recomputed: keeps its value (GG-VStatus) */
+      out[u] = r->pr_x[u];
+      continue;
+    }
     double sum = 0.0; /* gather accumulator */
     double P = 0.0;   /* running sum of binary32 contributions (influence) */
     const int32_t b = g->rowptr[u], e_end = g->rowptr[u + 1];
     for (int32_t e = b; e < e_end; ++e) {
       if (mode[u] == ROW_APPROX && !r->active[e]) continue;
       const int32_t v = g->col[e];
-      sum += r->pr_x[v] / r->outdeg[v];
+      sum += r->pr_x[v] / deg[v];
       ++edges;
     }
     if (mode[u] == ROW_SUPER) {
@@ -595,7 +652,7 @@ static void estatus(ggo_run* r) {
   for (int32_t u = 0; u < g->n; ++u) {
     if (r->mode[u] != ROW_SUPER) continue;
     for (int32_t e = g->rowptr[u]; e < g->rowptr[u + 1]; ++e) {
-      const int flag = r->infl[e] > r->pol.theta;
+      const int flag = r->infl[e] > r->theta_now;
       r->active[e] = r->pol.mask_update == GGO_MASK_UNION ? (uint8_t)(r->active[e] | flag) : (uint8_t)flag;
     }
   }
@@ -607,7 +664,7 @@ static void estatus(ggo_run* r) {
    edge whose source is unreached is not assessed and keeps its flag. */
 static void estatus_sssp(ggo_run* r) {
   const ggo_csr* g = &r->g;
-  const uint64_t theta_q = (uint64_t)floor(r->pol.theta * 65536.0 + 0.5);
+  const uint64_t theta_q = (uint64_t)floor(r->theta_now * 65536.0 + 0.5);
   for (int32_t u = 0; u < g->n; ++u) {
     if (r->mode[u] != ROW_SUPER) continue;
     uint64_t run = GGO_INF_U32;
@@ -668,7 +725,7 @@ static int64_t select_rows(ggo_run* r, int64_t* sel_edges) {
 static void run_pass(ggo_run* r, const uint8_t* mode, int shadow, int64_t* edges, int64_t* changed) {
   switch (r->app.app) {
     case GGO_PR:
-    case GGO_PPR: pass_pr(r, mode, shadow ? r->pr_sh : r->pr_xn, edges, changed); break;
+    case GGO_PPR: pass_pr(r, mode, r->outdeg, NULL, shadow ? r->pr_sh : r->pr_xn, edges, changed); break;
     case GGO_SSSP: pass_sssp(r, mode, shadow ? r->d_sh : r->d_xn, edges, changed); break;
     case GGO_CC: pass_cc(r, mode, shadow ? r->l_sh : r->l_xn, edges, changed); break;
   }
@@ -717,9 +774,9 @@ int ggo_step(ggo_run* r, ggo_step_info* info) {
     case GGO_EXACT: kind = GGO_KIND_ACCURATE; break;
     case GGO_SP: kind = GGO_KIND_APPROX; break;
     case GGO_SMS: kind = i >= p->alpha + 1 ? GGO_KIND_ACCURATE : GGO_KIND_APPROX; break;
-    case GGO_GG: kind = (i % (p->alpha + 1)) == 0 ? GGO_KIND_FULL : GGO_KIND_APPROX; break;
+    case GGO_GG: kind = is_correction(p, i) ? GGO_KIND_FULL : GGO_KIND_APPROX; break;
     case GGO_LEARNED:
-      if ((i % (p->alpha + 1)) == 0) {
+      if (is_correction(p, i)) {
         const int32_t c = ++r->corrections;
         compute_features(r);
         int64_t sel_edges = 0;
@@ -741,6 +798,7 @@ int ggo_step(ggo_run* r, ggo_step_info* info) {
       default: r->mode[u] = r->sel[u] ? ROW_SUPER : ROW_APPROX; break;
     }
   }
+  r->theta_now = theta_at(p, i);
   const int traced = p->trace && kind == GGO_KIND_FULL;
   if (traced && p->kind != GGO_LEARNED) compute_features(r);
   int64_t edges = 0, changed = 0;
@@ -751,7 +809,42 @@ int ggo_step(ggo_run* r, ggo_step_info* info) {
     run_pass(r, approx, 1, &e2, &c2);
     free(approx);
   }
-  run_pass(r, r->mode, 0, &edges, &changed);
+  const int pr_app = r->app.app == GGO_PR || r->app.app == GGO_PPR;
+  if (pr_app && kind == GGO_KIND_APPROX &&
+      (r->app.pr_degree == GGO_DEGREE_ACTIVE || p->vstatus != GGO_VSTATUS_NONE)) {
+    const int32_t* deg = r->outdeg;
+    if (r->app.pr_degree == GGO_DEGREE_ACTIVE) {
+      /* active out-degree of the current flags */
+      memset(r->odeg_act, 0, sizeof(int32_t) * (size_t)n);
+      for (int64_t e = 0; e < r->g.m; ++e)
+        if (r->active[e]) r->odeg_act[r->g.col[e]]++;
+      deg = r->odeg_act;
+    }
+    const uint8_t* skip = NULL;
+    if (p->vstatus != GGO_VSTATUS_NONE && i > 1) {
+      /* every vertex is on the active list of iteration 1; later a row is
+         recomputed iff one of its active in-edges comes from a vertex that
+         was active after the previous iteration */
+      for (int32_t u = 0; u < n; ++u) {
+        int any = 0;
+        for (int32_t e = r->g.rowptr[u]; e < r->g.rowptr[u + 1] && !any; ++e)
+          any = r->active[e] && r->vact[r->g.col[e]];
+        r->skip[u] = (uint8_t)!any;
+      }
+      skip = r->skip;
+    }
+    pass_pr(r, r->mode, deg, skip, r->pr_xn, &edges, &changed);
+  } else {
+    run_pass(r, r->mode, 0, &edges, &changed);
+  }
+  if (pr_app && p->vstatus != GGO_VSTATUS_NONE) {
+    /* GG-VStatus [Alg. 2]: active iff the value moved by more than eps */
+    for (int32_t u = 0; u < n; ++u) {
+      const double delta = fabs(r->pr_xn[u] - r->pr_x[u]);
+      const double bound = p->vstatus == GGO_VSTATUS_ABS ? p->eps : p->eps * fabs(r->pr_x[u]);
+      r->vact[u] = (uint8_t)(delta > bound);
+    }
+  }
   if (traced) compute_labels(r);
   if (kind == GGO_KIND_FULL || kind == GGO_KIND_PARTIAL) {
     if (r->app.app == GGO_SSSP)
@@ -835,6 +928,16 @@ void ggo_get_values(const ggo_run* r, void* out) {
 
 void ggo_get_mask(const ggo_run* r, uint8_t* out) { memcpy(out, r->active, (size_t)r->g.m); }
 
+void ggo_set_mask(ggo_run* r, const uint8_t* mask) {
+  for (int64_t e = 0; e < r->g.m; ++e) r->active[e] = mask[e] != 0;
+}
+
+void ggo_get_vactive(const ggo_run* r, uint8_t* out) { memcpy(out, r->vact, (size_t)r->g.n); }
+
+void ggo_set_vactive(ggo_run* r, const uint8_t* in) {
+  for (int32_t u = 0; u < r->g.n; ++u) r->vact[u] = in[u] != 0;
+}
+
 void ggo_get_influence(const ggo_run* r, double* out) {
   memcpy(out, r->infl, (size_t)r->g.m * sizeof(double));
 }
@@ -868,6 +971,9 @@ void ggo_end(ggo_run* r) {
   free(r->logit);
   free(r->sel);
   free(r->label);
+  free(r->odeg_act);
+  free(r->vact);
+  free(r->skip);
   free(r->pr_x);
   free(r->pr_xn);
   free(r->pr_sh);

@@ -45,6 +45,19 @@ enum { GGO_STOP_FIXED_ITERS = 0, GGO_STOP_FIXED_POINT = 1 };
 enum { GGO_INFL_PREFIX = 0, GGO_INFL_TOTAL = 1 };
 enum { GGO_MASK_REPLACE = 0, GGO_MASK_UNION = 1 };
 enum { GGO_DANGLING_UNIFORM = 0, GGO_DANGLING_NONE = 1 };
+/* PR/PPR out-degree in approximate iterations: the full graph's (FULL) or
+   the count of active out-edges (ACTIVE: PageRank of the sparsified graph,
+   whose vertices without active out-edges are dangling). */
+enum { GGO_DEGREE_FULL = 0, GGO_DEGREE_ACTIVE = 1 };
+/* Vertex status (GG-VStatus, Alg. 2) for PR/PPR: NONE = every vertex is
+   processed in every iteration; ABS = a vertex is active after an iteration
+   iff its value moved by more than eps; REL = by more than eps times its
+   previous value. Approximate iterations after the first recompute only
+   the rows with an active in-edge from an active vertex (the active-vertex
+   list of the vertex-centric model, Sec. 2.1, which starts with every
+   vertex); the others keep their value. Accurate iterations recompute
+   every row. */
+enum { GGO_VSTATUS_NONE = 0, GGO_VSTATUS_ABS = 1, GGO_VSTATUS_REL = 2 };
 
 #define GGO_INF_U32 0xFFFFFFFFu
 
@@ -63,6 +76,7 @@ typedef struct {
   int32_t max_iters;  /* cap for fixed-point runs */
   int32_t source;     /* SSSP/PPR source */
   int32_t dangling;   /* GGO_DANGLING_* */
+  int32_t pr_degree;  /* GGO_DEGREE_* (PR/PPR) */
 } ggo_app_params;
 
 typedef struct {
@@ -80,6 +94,15 @@ typedef struct {
   int32_t fallback_k;  /* LEARNED: every k-th correction step is full (0: never) */
   int32_t trace;       /* 1: features and drift labels at every full superstep */
   double label_eps;    /* PR/PPR drift label: relative contribution change */
+  /* GG / LEARNED with decoupled = 1: the first superstep follows alpha0
+     approximate iterations and uses threshold theta0; later ones recur
+     every alpha+1 iterations after it with theta (Sec. 3.4, last
+     paragraph). decoupled = 0: alpha and theta throughout. */
+  int32_t decoupled;
+  int32_t alpha0;
+  double theta0;
+  int32_t vstatus;     /* GGO_VSTATUS_* (PR/PPR) */
+  double eps;          /* its epsilon, >= 0 */
 } ggo_policy;
 
 typedef struct {
@@ -117,6 +140,15 @@ void ggo_get_mask(const ggo_run* r, uint8_t* out);
    relative improvement, 1 for the first finite candidate, -1 when not
    assessable; CC: 1/0). */
 void ggo_get_influence(const ggo_run* r, double* out);
+/* Replace the current edge flags (one byte per edge, nonzero = active), for
+   the replay check: after a superstep whose floating-point decisions the
+   GPU took differently within rounding, the oracle continues from the GPU's
+   flags. */
+void ggo_set_mask(ggo_run* r, const uint8_t* mask);
+/* Vertex status after the last iteration (one byte per vertex; all 1 before
+   the first), and its replacement for the replay check. */
+void ggo_get_vactive(const ggo_run* r, uint8_t* out);
+void ggo_set_vactive(ggo_run* r, const uint8_t* in);
 /* Features [n][8] (bfloat16 bits) of the last correction or traced step. */
 void ggo_get_features(const ggo_run* r, uint16_t* out);
 /* Selection and logits of this step (LEARNED correction steps); 0 if none. */

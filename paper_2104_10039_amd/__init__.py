@@ -115,6 +115,7 @@ SIGNATURES = {
                                          ctypes.c_int32, _VP, ctypes.c_int32, ctypes.POINTER(Tuning),
                                          ctypes.POINTER(ctypes.c_double)]),
     "gg_graph_set_parts": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
+    "gg_graph_set_wait_limit": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "gg_graph_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_graph_get_profile": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.POINTER(KernelProfile)]),
     "gg_run_features": (ctypes.c_int, [_VP, _VP]),
@@ -304,6 +305,10 @@ class Graph:
                 cur[k] = int(v)
         t = Tuning(*[cur[k] for k in TUNING_FIELDS])
         _check(lib().gg_graph_set_tuning(self._h, ctypes.byref(t)))
+
+    def set_wait_limit(self, polls):
+        """gg_graph_set_wait_limit: polls before a superstep's bounded wait gives up."""
+        _check(lib().gg_graph_set_wait_limit(self._h, int(polls)))
 
     def set_parts(self, part_start, part_sources=None):
         """gg_graph_set_parts: part_start has n_parts + 1 entries (None or [] clears)."""

@@ -13,7 +13,7 @@ constexpr int kHubPre = 8;   // 256-edge steps of a hub chunk whose loads are is
 constexpr int kFlatWin = 1024;  // edges staged per round of a flattened batch of short rows
 constexpr int kSegWin = 2048;  // edges gathered per window of a segmented gather's flattened batch
 constexpr int kPartDangBlocks = 32;  // blocks per part of the per-part dangling sums
-constexpr int kHubSpinLimit = 1 << 20;  // polls before a single-pass hub chunk gives up waiting
+constexpr int kHubSpinLimit = 1 << 20;  // default polls before a single-pass hub chunk gives up waiting
 
 enum App : int { kPR = 0, kSSSP = 1, kCC = 2, kPPR = 3 };
 
@@ -25,6 +25,8 @@ struct BinCounts {
   int32_t hub;     // rows processed by workgroups, chunked
   int32_t chunks;  // total hub chunks
   int64_t edges;   // total row length (edges in the binned edge set)
+  uint32_t hub_err;  // copy of a superstep's hub error word (0 unless asked for)
+  uint32_t pad;
 };
 
 // A degree binning of the rows: one list, partitioned [small | wave | hub].
@@ -95,6 +97,7 @@ struct Sweep {
   // ticket counter, [2, 2 + 2 n_chunks) chunk totals (64-bit), then the
   // chunk counts (count + 1)
   uint32_t* hub_sync;
+  int32_t hub_spin;  // polls before a hub chunk's wait gives up (<= 0: at once)
 };
 
 // Segmented gather constants.
@@ -151,7 +154,7 @@ hipError_t launch_dangling_sum(const float* c, const int32_t* list, const int32_
 // Degree binning. blk_scratch holds 3 * ceil(n / kBlock) int32 + ceil(n / kBlock) int64.
 hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, int32_t small_max,
                         int32_t wave_max, int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st, const uint8_t* rowsel = nullptr,
-                        int selwant = 0);
+                        int selwant = 0, const uint32_t* hub_err = nullptr);
 
 // PR/PPR initial contributions.
 // part_of / part_start nullable (PR: 1/N per part when set).

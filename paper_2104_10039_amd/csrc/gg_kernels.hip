@@ -593,19 +593,23 @@ __device__ __forceinline__ typename Tr<APP>::T unpack_total(uint64_t w) {
   else return (uint32_t)w;
 }
 
-// Poll a word until it is non-zero. Past the spin limit the wait gives up and
-// raises the error word err, which the host reports; the kernel still ends.
+// Poll a word until it is non-zero. Past `limit` polls the wait gives up: it
+// sets gave_up, raises the error word err (which the host reads back after
+// the superstep) and returns 0; the kernel still ends. limit <= 0 gives up
+// without polling, which exercises that path on purpose.
 template <typename W>
-__device__ __forceinline__ W wait_word(W* p, uint32_t* err) {
-  W v;
-  for (int it = 0; (v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0; ++it) {
-    if (it >= kHubSpinLimit) {
-      atomicOr(err, 1u);
-      return v;
+__device__ __forceinline__ W wait_word(W* p, uint32_t* err, int limit, bool& gave_up) {
+  W v = 0;
+  if (limit > 0) {
+    for (int it = 0; (v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0; ++it) {
+      if (it >= limit) break;
+      __builtin_amdgcn_s_sleep(2);
     }
-    __builtin_amdgcn_s_sleep(2);
+    if (v != 0) return v;
   }
-  return v;
+  atomicOr(err, 1u);
+  gave_up = true;
+  return 0;
 }
 
 // Gathered value in its stored width (defined with the flat batches below).
@@ -621,12 +625,15 @@ struct GV;
 // count, and writes its active edges at the offset that the earlier chunks'
 // counts give. The row's last chunk applies the row and writes its active
 // count. A chunk waits only on chunks with smaller tickets, whose blocks are
-// already resident and publish before they wait, so every wait ends.
+// already resident and publish before they wait, so every wait ends. If a
+// wait gives up anyway, the chunk writes no active edge and no active count:
+// its offsets would be wrong, and the row keeps the count of its previous
+// packing, which still bounds edges written in every packing since.
 template <int APP>
 __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, typename Tr<APP>::T* lds, int* ilds) {
   using R = Tr<APP>;
   using T = typename R::T;
-  __shared__ int s_ch, s_cbase;
+  __shared__ int s_ch, s_cbase, s_bad;
   __shared__ T s_carry;
   __shared__ int s_cnt[kHubPre][4];
   uint32_t* const err = s.hub_sync;
@@ -637,6 +644,7 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
   if (threadIdx.x == 0) {
     const int t = atomicAdd((int*)(s.hub_sync + 1), 1);
     s_ch = s.chunk_order ? s.chunk_order[t] : t;
+    s_bad = 0;
   }
   __syncthreads();
   const int ch = s_ch;
@@ -672,8 +680,10 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
   // row prefix: totals of chunks c0 .. ch-1, lane i takes i, i + 64, ...
   if (wid == 0) {
     T p = R::id();
-    for (int i = lane; i < j; i += 64) p = R::op(p, unpack_total<APP>(wait_word(tot_w + c0 + i, err)));
+    bool bad = false;
+    for (int i = lane; i < j; i += 64) p = R::op(p, unpack_total<APP>(wait_word(tot_w + c0 + i, err, s.hub_spin, bad)));
     p = team_reduce<64>(p);
+    if (bad) s_bad = 1;
     if (lane == 0) s_carry = p;
   }
   __syncthreads();
@@ -696,12 +706,23 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
   // offset of the chunk's active edges in the row
   if (wid == 0) {
     int cb = 0;
-    for (int i = lane; i < j; i += 64) cb += (int)wait_word(cnt_w + c0 + i, err) - 1;
+    bool bad = false;
+    for (int i = lane; i < j; i += 64) {
+      const uint32_t w = wait_word(cnt_w + c0 + i, err, s.hub_spin, bad);
+      cb += w != 0u ? (int)w - 1 : 0;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) cb += __shfl_xor(cb, o, 64);
+    if (bad) s_bad = 1;
     if (lane == 0) s_cbase = cb;
   }
   __syncthreads();
+  if (s_bad) {
+    // a wait gave up: the carry or the offset is unknown (reported by the
+    // error word); write nothing that the offset or count would place
+    if (j == nch - 1 && threadIdx.x == 0) apply<APP>(s, u, R::op(carry0, acc), nchanged);
+    return;
+  }
   int off = s_cbase;
 #pragma unroll
   for (int q = 0; q < kHubPre; ++q) {
@@ -1093,7 +1114,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_nchunks(const int32_t* rowptr, c
   }
 }
 
-__global__ __launch_bounds__(1024) void k_hub_scan(int32_t* hub_start, BinCounts* bc) {
+__global__ __launch_bounds__(1024) void k_hub_scan(int32_t* hub_start, BinCounts* bc, const uint32_t* hub_err) {
   __shared__ int32_t tot;
   const int nh = bc->hub;
   block1024_exclusive_scan(hub_start, nh, &tot);
@@ -1101,6 +1122,7 @@ __global__ __launch_bounds__(1024) void k_hub_scan(int32_t* hub_start, BinCounts
   if (threadIdx.x == 0) {
     hub_start[nh] = tot;
     bc->chunks = tot;
+    bc->hub_err = hub_err ? *hub_err : 0u;
   }
 }
 
@@ -1329,7 +1351,7 @@ hipError_t launch_dangling_sum(const float* c, const int32_t* list, const int32_
 
 hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, int32_t small_max, int32_t wave_max,
                         int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st, const uint8_t* rowsel,
-                        int selwant) {
+                        int selwant, const uint32_t* hub_err) {
   const int nblk = (n + kBlock - 1) / kBlock;
   int32_t* blk = (int32_t*)blk_scratch;
   int64_t* blk_edges = (int64_t*)(blk + 3 * (int64_t)nblk + ((3 * nblk) & 1));
@@ -1346,7 +1368,7 @@ hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, in
                      bins.dcounts, bins.list, rowsel, selwant);
   hipLaunchKernelGGL(k_hub_nchunks, dim3(nblk), dim3(kBlock), 0, st, rowptr, cnt, bins.list, bins.dcounts, hub_chunk,
                      bins.hub_start);
-  hipLaunchKernelGGL(k_hub_scan, dim3(1), dim3(1024), 0, st, bins.hub_start, bins.dcounts);
+  hipLaunchKernelGGL(k_hub_scan, dim3(1), dim3(1024), 0, st, bins.hub_start, bins.dcounts, hub_err);
   return hipGetLastError();
 }
 

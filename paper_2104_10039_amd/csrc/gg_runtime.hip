@@ -91,6 +91,7 @@ struct gg_graph {
   int32_t* i32_scratch = nullptr;  // small device scalars: [0] dangling count, [1] validate flags
   void* blk_scratch = nullptr;
   gg_tuning tune{32, 4, 1024, 2048, 1, 0, 1, 16};
+  int32_t hub_spin = kHubSpinLimit;  // gg_graph_set_wait_limit
   bool rows_sorted = true;  // every row lists its sources in ascending order (else no segmentation)
   // frontier (SSSP / CC): out-CSR structure and lists, built on first use
   bool out_built = false;
@@ -268,10 +269,20 @@ void free_bins(Bins& b) {
   dfree(b.dcounts);
 }
 
-int rebin(gg_graph* g, Bins& b, const int32_t* cnt, const uint8_t* rowsel = nullptr, int selwant = 0) {
+int rebin(gg_graph* g, Bins& b, const int32_t* cnt, const uint8_t* rowsel = nullptr, int selwant = 0,
+          bool hub_check = false) {
+  const uint32_t* err = hub_check ? g->hub_sync : nullptr;
   GG_HIP(launch_rebin(g->rowptr, cnt, g->n, g->tune.small_max, g->tune.wave_max, g->tune.hub_chunk, b,
-                      g->blk_scratch, g->stream, rowsel, selwant));
-  return sync_bins(g, b);
+                      g->blk_scratch, g->stream, rowsel, selwant, err));
+  GG_TRY(sync_bins(g, b));
+  if (b.h.hub_err != 0) {
+    // a hub chunk of the superstep before this rebin gave up waiting: its
+    // results are undefined (its memory writes stayed inside its row)
+    b.h.hub_err = 0;
+    GG_HIP(launch_fill_u32(g->hub_sync, 1, 0u, g->stream));
+    return fail(GG_E_DEVICE, "a superstep hub chunk gave up waiting for its row prefix");
+  }
+  return GG_OK;
 }
 
 int ensure_learned(gg_graph* g) {
@@ -416,8 +427,8 @@ int rebin_full(gg_graph* g) {
 }
 
 // Binning of the active rows plus, with segmentation, their segment offsets.
-int rebin_act(gg_graph* g, int app) {
-  GG_TRY(rebin(g, g->act, g->act_cnt));
+int rebin_act(gg_graph* g, int app, bool after_superstep = false) {
+  GG_TRY(rebin(g, g->act, g->act_cnt, nullptr, 0, after_superstep));
   if (!g->tune.seg_enable) return GG_OK;
   GG_TRY(ensure_seg(g));
   const uint32_t mask = app == GG_APP_SSSP ? 0xFFFFFFu : 0xFFFFFFFFu;
@@ -658,6 +669,7 @@ Sweep base_sweep(const gg_graph* g, const gg_run* r) {
   s.part_u = g->part_u;
   s.part_cnt = g->part_cnt;
   s.hub_sync = g->hub_sync;
+  s.hub_spin = g->hub_spin;
   s.theta = r->pol.theta;
   s.theta_q = (uint64_t)std::floor(r->pol.theta * 65536.0 + 0.5);
   s.mask_union = r->pol.mask_update == GG_MASK_UNION;
@@ -978,7 +990,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     unsigned long long act_s = 0;
     GG_HIP(hipMemcpyAsync(&act_s, g->audit + 2, sizeof(act_s), hipMemcpyDeviceToHost, g->stream));
     r->bcur = 1 - r->bcur;
-    GG_TRY(rebin_act(g, app));  // synchronizes the stream
+    GG_TRY(rebin_act(g, app, true));  // synchronizes the stream, reads the hub error word
     r->supersteps++;
     r->partials++;
     // algorithmic edges: S over all in-edges, the other rows over active ones
@@ -1039,7 +1051,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
                            audited ? g->audit : nullptr, tpos, g->stream));
       r->have_labels = true;
     }
-    GG_TRY(rebin_act(g, app));
+    GG_TRY(rebin_act(g, app, true));  // reads the hub error word too
     r->supersteps++;
     edges = g->m;
     processed = edges;
@@ -1855,6 +1867,15 @@ int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t) {
     if (!g->rows_sorted) g->tune.seg_enable = 0;
     GG_TRY(rebin_full(g));
     if (g->ws) GG_TRY(ensure_parts(g));
+    return GG_OK;
+  });
+}
+
+int gg_graph_set_wait_limit(gg_graph* g, int32_t polls) {
+  return guard([&]() -> int {
+    if (!g) return fail(GG_E_INVAL, "null graph");
+    if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+    g->hub_spin = polls;
     return GG_OK;
   });
 }

@@ -8,6 +8,13 @@ import graphgen as gg
 import oracle
 
 PR_TOL = 1e-6  # relative L1, FP32 GPU against the FP64 oracle
+# Replay band: a PageRank edge flag may differ between the two sides only
+# when the oracle's influence lies within this relative distance of theta.
+# The GPU decides on binary32 contributions of its own binary32 iterate,
+# summed in binary64 in another order; the oracle on binary32 roundings of
+# its binary64 iterate. Contributions then differ by about one binary32 ulp
+# (6e-8 relative), far inside the band.
+REPLAY_BAND = 1e-4
 
 
 def log(*a):
@@ -63,6 +70,10 @@ def oracle_kw(kw):
     o["mask_update"] = oracle.MASK_UNION if mu == "union" else oracle.MASK_REPLACE
     dg = o.pop("dangling", "uniform")
     o["dangling"] = oracle.DANGLING_NONE if dg == "none" else oracle.DANGLING_UNIFORM
+    o["influence"] = oracle.INFL_TOTAL if o.pop("influence", "prefix") == "total" else oracle.INFL_PREFIX
+    o["pr_degree"] = oracle.DEGREE_ACTIVE if o.pop("pr_degree", "full") == "active" else oracle.DEGREE_FULL
+    o["vstatus"] = {"none": oracle.VSTATUS_NONE, "abs": oracle.VSTATUS_ABS,
+                    "rel": oracle.VSTATUS_REL}[o.pop("vstatus", "none")]
     if "sample_ratio" in o:
         o["sigma"] = o.pop("sample_ratio")
     return o
@@ -117,3 +128,76 @@ def mlp_selector_params(feature, scale=1.0):
 
 def bf16_to_f64(bits):
     return (np.asarray(bits, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def load(P, g, tuning=None):
+    G = P.Graph.from_host(g)
+    if tuning:
+        G.set_tuning(**tuning)
+    return G
+
+
+def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
+    """Run both sides one iteration at a time; compare values every iteration
+    and the edge flags after every superstep. Returns the worst PR error.
+
+    SSSP/CC flags must be equal. PageRank flags follow the replay protocol:
+    every flag that differs must belong to an edge whose oracle influence is
+    within REPLAY_BAND * theta of theta; the oracle then adopts the GPU's
+    flags and both continue from the same edge set. `stats` (a dict), when
+    given, receives the number of such flips ("flips"), of idle iterations (a
+    push from an empty frontier) and of supersteps that followed one."""
+    G = load(P, g, tuning)
+    sr = kw.pop("sample_ratio", 1.0)
+    R = G.begin(app, sr, policy, **kw)
+    okw = oracle_kw(kw)
+    O = oracle.Run(g, app, policy, sigma=sr, **okw)
+    assert np.array_equal(R.mask(), O.mask()) or policy == "exact", "initial sample differs"
+    worst = 0.0
+    flips_total = 0
+    while True:
+        a = R.step()
+        b = O.step()
+        if a is None or b is None:
+            assert a is None and b is None, (a, b)
+            break
+        assert a["iter"] == b.iter and a["accurate"] == b.accurate and a["superstep"] == b.superstep
+        assert a["edges"] == b.edges, (a, b)
+        if a.get("sparse"):
+            log("iter", b.iter, "ran as a frontier push over", a["edges_processed"], "edges")
+        if stats is not None:
+            if a["sparse"] and a["edges_processed"] == 0:
+                stats["idle"] = stats.get("idle", 0) + 1
+                stats["pending"] = True
+            elif a["superstep"] and stats.get("pending"):
+                stats["super_after_idle"] = stats.get("super_after_idle", 0) + 1
+                stats["pending"] = False
+        if app in ("sssp", "cc"):
+            assert a["changed"] == b.changed, (a, b)
+        if a["superstep"]:
+            gm, om = R.mask(), O.mask()
+            flips = np.nonzero(gm != om)[0]
+            if flips.size:
+                infl = O.influence()
+                theta = kw.get("theta0", kw.get("theta")) if b.iter == kw.get("alpha0", -2) + 1 else kw.get("theta")
+                log("flips at iter", b.iter, ":", flips.size, "edges, first", flips[:5].tolist(), "oracle influence",
+                    infl[flips[:5]].tolist(), "theta", theta)
+                assert app in ("pr", "ppr"), "%d SSSP/CC edge flags differ after superstep %d" % (flips.size, b.iter)
+                dist = np.abs(infl[flips] - theta)
+                assert np.all(dist <= REPLAY_BAND * theta), \
+                    "flag differs away from theta: influence %r" % infl[flips[dist > REPLAY_BAND * theta][:5]].tolist()
+                O.set_mask(gm)
+                flips_total += int(flips.size)
+            assert a["active_edges"] == int(gm.sum())
+        gv = R.values()
+        ov = O.values()
+        if app in ("pr", "ppr"):
+            worst = max(worst, rel_l1(gv, ov))
+        compare_values(app, gv, ov, ctx="iter %d" % b.iter)
+    log("replay: %d PageRank flags adopted from the GPU over the run" % flips_total)
+    if stats is not None:
+        stats["flips"] = flips_total
+    R.close()
+    O.close()
+    G.close()
+    return worst

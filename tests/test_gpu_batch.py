@@ -113,3 +113,47 @@ def test_batch_rejects_bad_input(P):
     with pytest.raises(P.GGError) as ei:
         G.batch_run("ppr", [0], policy="gg")
     assert ei.value.code == -5
+
+
+C4_SEED = 5  # R-MAT scale 20 of the batched workload; sources from seed 6
+
+
+def test_c4_rmat20_batches_full_size(P):
+    """The batched workload at full size, in the launch configuration the
+    benchmark times (tuning picked by the autotuner on a 3-iteration PPR
+    batch): R-MAT 20 with 256 PPR and 256 SSSP queries from the same seeded
+    sources, exact and SSSP under SMS (sigma 0.05, alpha 10, the exact
+    batch's iteration count). A seeded subset of 32 queries of each exact
+    batch, and 8 of the SMS batch, equal single-query oracle runs (PPR within
+    1e-6 relative L1, SSSP bit for bit)."""
+    g = gg.rmat(20, 16, seed=C4_SEED, weights=True)
+    srcs = gg.pick_sources(g, 256, C4_SEED + 1)
+    G = P.Graph.from_host(g)
+    tuning, _ = G.autotune("ppr", sources=srcs, iters=3, reps=1)
+    log("C4 tuning", tuning)
+    rng = np.random.default_rng(2024)
+    picks = sorted(rng.choice(256, size=32, replace=False).tolist())
+    out, st = G.batch_run("ppr", srcs, iters=20)
+    got = out.cpu().numpy()
+    assert st.iterations == 20
+    for q in picks:
+        log("C4 PPR query", q, "source", int(srcs[q]))
+        ref = oracle.run(g, "ppr", "exact", source=int(srcs[q]), iters=20)
+        compare_values("ppr", got[:, q], ref.values, ctx="ppr query %d" % q)
+    out, st = G.batch_run("sssp", srcs, max_iters=1000)
+    got = out.cpu().numpy().view(np.uint32)
+    L = st.iterations
+    iters = []
+    for q in picks:
+        log("C4 SSSP query", q, "source", int(srcs[q]))
+        ref = oracle.run(g, "sssp", "exact", source=int(srcs[q]))
+        compare_values("sssp", got[:, q], ref.values, ctx="sssp query %d" % q)
+        iters.append(ref.iterations)
+    assert L >= max(iters)
+    out, st = G.batch_run("sssp", srcs, sample_ratio=0.05, policy="sms", alpha=10, iters=L, seed=1)
+    got = out.cpu().numpy().view(np.uint32)
+    for q in picks[:8]:
+        log("C4 SSSP SMS query", q)
+        ref = oracle.run(g, "sssp", "sms", source=int(srcs[q]), sigma=0.05, alpha=10, iters=L, seed=1)
+        compare_values("sssp", got[:, q], ref.values, ctx="sms query %d" % q)
+    G.close()

@@ -8,19 +8,20 @@ shortest-path optimality conditions (every edge relaxed, every reached vertex
 but the source tight on some in-edge), for CC by scipy's connected components
 (each label is the smallest id of its component).
 
-R-MAT scale 24 and an Erdos-Renyi graph with 2^24 vertices (average degree
-16) are checked the same way when GG_FULLSIZE_24=1 (each takes minutes of
-graph generation and oracle time, so they are not part of the default run;
-run them with a per-test time limit of about 15 minutes).
-"""
-import os
+GG runs at every sample ratio the benchmark times (0.1 to 0.9) are checked
+against the oracle on R-MAT 22, and the PageRank GG run step by step with the
+replay check of its edge flags.
 
+R-MAT scale 24 and an Erdos-Renyi graph with 2^24 vertices (average degree
+16) are checked the same way for SSSP and CC (each takes a few minutes of
+graph generation and single-core oracle time).
+"""
 import numpy as np
 import pytest
 
 import graphgen as gg
 import oracle
-from helpers import compare_values, log
+from helpers import compare_values, log, step_compare
 
 pytestmark = pytest.mark.gpu
 
@@ -136,21 +137,55 @@ def test_full_pr_rmat22(P, rmat22):
     _check_app(P, g, "pr", s)
 
 
+def test_pr_gg_steps_rmat22_replay(P, rmat22):
+    """The PageRank GG run of the benchmark (sigma 0.3, alpha 4, theta 0.05)
+    compared with the oracle after every iteration: values within 1e-6
+    relative L1, edge flags after every superstep equal except flags whose
+    oracle influence lies within the replay band around theta, which the
+    oracle adopts from the GPU (their count is printed)."""
+    g, _ = rmat22
+    st = {}
+    worst = step_compare(P, g, "pr", "gg", stats=st, sample_ratio=0.3, alpha=4, theta=0.05, seed=1, iters=20)
+    log("R-MAT 22 PageRank GG step by step: worst relative L1 %.3e, flags adopted from the GPU: %d of %d edges"
+        % (worst, st["flips"], g.m))
+
+
+@pytest.fixture(scope="module")
+def rmat22_sym():
+    return gg.rmat(22, 16, seed=2, symmetrize=True)
+
+
+@pytest.mark.parametrize("sigma", [0.1, 0.5, 0.7, 0.9])
+@pytest.mark.parametrize("app", ["pr", "sssp", "cc"])
+def test_full_gg_sample_ratios_rmat22(P, rmat22, rmat22_sym, app, sigma):
+    """GG (alpha 4, theta 0.05) at the other sample ratios the benchmark
+    times, against the oracle at the exact run's iteration count."""
+    g, s = rmat22
+    if app == "cc":
+        g, s = rmat22_sym, 0
+    G = P.Graph.from_host(g)
+    it = 20
+    if app != "pr":
+        _, st = G.exact_run(app, source=s)
+        it = st.iterations
+    log("case: R-MAT 22", app, "GG sigma", sigma, "iterations", it)
+    out, st = G.approx_run(app, sigma, "gg", alpha=4, theta=0.05, seed=1, iters=it, source=s, stop="fixed_iters")
+    ref = _oracle(g, app, "gg", sigma=sigma, alpha=4, theta=0.05, seed=1, iters=it, source=s,
+                  stop=oracle.FIXED_ITERS)
+    compare_values(app, _host(out, app), ref.values, ctx="gg sigma %.1f" % sigma)
+    assert st.edges_gathered == ref.edges
+    G.close()
+
+
 def test_full_sssp_rmat22(P, rmat22):
     g, s = rmat22
     _check_app(P, g, "sssp", s)
 
 
-def test_full_cc_rmat22(P):
-    g = gg.rmat(22, 16, seed=2, symmetrize=True)
-    _check_app(P, g, "cc", 0)
+def test_full_cc_rmat22(P, rmat22_sym):
+    _check_app(P, rmat22_sym, "cc", 0)
 
 
-scale24 = pytest.mark.skipif(os.environ.get("GG_FULLSIZE_24") != "1",
-                             reason="scale-24 graphs take minutes; set GG_FULLSIZE_24=1")
-
-
-@scale24
 @pytest.mark.parametrize("kind", ["rmat", "er"])
 def test_full_sssp_24(P, kind):
     log("generating", kind, "scale 24")
@@ -158,7 +193,6 @@ def test_full_sssp_24(P, kind):
     _check_app(P, g, "sssp", int(gg.pick_sources(g, 1, 3)[0]))
 
 
-@scale24
 @pytest.mark.parametrize("kind", ["rmat", "er"])
 def test_full_cc_24(P, kind):
     log("generating", kind, "scale 24, symmetrized")

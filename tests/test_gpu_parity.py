@@ -12,7 +12,7 @@ import pytest
 
 import graphgen as gg
 import oracle
-from helpers import compare_values, device_values, graph_for, log, oracle_kw, rel_l1
+from helpers import compare_values, device_values, graph_for, load, log, oracle_kw, rel_l1, step_compare
 
 pytestmark = pytest.mark.gpu
 
@@ -42,13 +42,6 @@ def P():
         pytest.skip("no GPU")
     import paper_2104_10039_amd as P
     return P
-
-
-def load(P, g, tuning=None):
-    G = P.Graph.from_host(g)
-    if tuning:
-        G.set_tuning(**tuning)
-    return G
 
 
 def lib_run(G, app, policy, **kw):
@@ -129,57 +122,6 @@ def test_approx_int_apps_tunings(P, ti):
 # ---------------------------------------------------------------------------
 # Step-by-step parity with per-superstep flag comparison
 # ---------------------------------------------------------------------------
-
-def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
-    """Run both sides one iteration at a time; compare values every iteration
-    and the edge flags after every superstep. Returns the worst PR error.
-    `stats` (a dict), when given, receives the number of idle iterations (a
-    push from an empty frontier) and of supersteps that followed one."""
-    G = load(P, g, tuning)
-    sr = kw.pop("sample_ratio", 1.0)
-    R = G.begin(app, sr, policy, **kw)
-    okw = oracle_kw(kw)
-    O = oracle.Run(g, app, policy, sigma=sr, **okw)
-    assert np.array_equal(R.mask(), O.mask()) or policy == "exact", "initial sample differs"
-    worst = 0.0
-    while True:
-        a = R.step()
-        b = O.step()
-        if a is None or b is None:
-            assert a is None and b is None, (a, b)
-            break
-        assert a["iter"] == b.iter and a["accurate"] == b.accurate and a["superstep"] == b.superstep
-        assert a["edges"] == b.edges, (a, b)
-        if a.get("sparse"):
-            log("iter", b.iter, "ran as a frontier push over", a["edges_processed"], "edges")
-        if stats is not None:
-            if a["sparse"] and a["edges_processed"] == 0:
-                stats["idle"] = stats.get("idle", 0) + 1
-                stats["pending"] = True
-            elif a["superstep"] and stats.get("pending"):
-                stats["super_after_idle"] = stats.get("super_after_idle", 0) + 1
-                stats["pending"] = False
-        if app in ("sssp", "cc"):
-            assert a["changed"] == b.changed, (a, b)
-        if a["superstep"]:
-            gm, om = R.mask(), O.mask()
-            flips = np.nonzero(gm != om)[0]
-            if flips.size:
-                infl = O.influence()
-                log("flips at iter", b.iter, "edges", flips[:10].tolist(), "oracle influence",
-                    infl[flips[:10]].tolist(), "theta", kw.get("theta"))
-            assert flips.size == 0, "%d edge flags differ after superstep %d" % (flips.size, b.iter)
-            assert a["active_edges"] == b.active_edges
-        gv = R.values()
-        ov = O.values()
-        if app in ("pr", "ppr"):
-            worst = max(worst, rel_l1(gv, ov))
-        compare_values(app, gv, ov, ctx="iter %d" % b.iter)
-    R.close()
-    O.close()
-    G.close()
-    return worst
-
 
 @pytest.mark.parametrize("theta", [0.05, 0.2])
 @pytest.mark.parametrize("policy", ["gg", "sp", "sms"])
@@ -354,6 +296,34 @@ def test_giant_hub_many_chunks_per_segment(P, app):
     tuning = dict(small_max=8, small_team=4, wave_max=128, hub_chunk=256, seg_enable=1, seg_vertices=1024)
     check_run(P, g, app, "gg", tuning=tuning, ctx="giant hub", sample_ratio=0.4, alpha=2, theta=0.02, seed=5,
               source=1, iters=9)
+
+
+@pytest.mark.parametrize("app", ["pr", "sssp"])
+def test_superstep_wait_give_up_is_reported(P, app):
+    """Every bounded wait of the single-pass hub chunks forced to give up at
+    once (wait limit 0, set from the host; no kernel is made to hang): the
+    step that ran the superstep returns GG_E_DEVICE, every kernel exits (the
+    next run on the same graph completes), and with the default limit back
+    that run matches the oracle bit for bit (SSSP) or within tolerance (PR)."""
+    g = _giant_hub_graph(31)
+    tuning = dict(small_max=8, small_team=4, wave_max=128, hub_chunk=256, seg_enable=1, seg_vertices=1024)
+    kw = dict(alpha=1, theta=0.02, seed=5, source=1, iters=4)
+    log("case: forced give-up", app, kw)
+    G = load(P, g, tuning)
+    G.set_wait_limit(0)
+    R = G.begin(app, 0.4, "gg", **kw)
+    info = R.step()
+    assert info is not None and not info["superstep"]
+    with pytest.raises(P.GGError) as ei:
+        R.step()
+    assert ei.value.code == -4 and "gave up" in str(ei.value)
+    R.close()
+    G.set_wait_limit(1 << 20)
+    got, st = lib_run(G, app, "gg", sample_ratio=0.4, **kw)
+    ref = oracle.run(g, app, "gg", sigma=0.4, **kw)
+    compare_values(app, got, ref.values, ctx="after give-up")
+    assert st.edges_gathered == ref.edges
+    G.close()
 
 
 def test_unsorted_rows_disable_segmentation(P):

@@ -77,3 +77,35 @@ def test_parts_reject_crossing_edge(P):
     G.set_parts(None)
     with pytest.raises(P.GGError):
         G.set_parts(np.array([0, 5, U.n + 1], np.int32))
+
+
+@pytest.mark.parametrize("app", ["pr", "sssp", "cc"])
+def test_union64_full_size(P, app):
+    """The multi-graph workload at full size, as the benchmark runs it (tuning
+    from the autotuner): 64 R-MAT graphs of scale 10..18 and edge factor
+    8..32 (seeds 100 + g) as one block-diagonal union, exact for 20 PR
+    iterations (SSSP and CC until no part changes), every part checked
+    against the oracle run on that graph alone."""
+    gs = gg.rmat_family(64, scale_range=(10, 18), ef_range=(8, 32), seed0=100, weights=(app == "sssp"),
+                        symmetrize=(app == "cc"))
+    U, ps = gg.union(gs)
+    srcs = None
+    if app == "sssp":
+        srcs = np.array([ps[k] + int(gg.pick_sources(gs[k], 1, 50 + k)[0]) for k in range(len(gs))], np.int32)
+    G = P.Graph.from_host(U)
+    G.set_parts(ps, srcs)
+    tuning, _ = G.autotune(app, iters=3 if app == "pr" else 20, max_iters=1000, reps=1)
+    log("union64", app, "n", U.n, "m", U.m, "tuning", tuning)
+    out, st = G.exact_run(app, iters=20, max_iters=1000)
+    got = device_values(out, app)
+    iters = []
+    for p, g in enumerate(gs):
+        sl = slice(int(ps[p]), int(ps[p + 1]))
+        kw = dict(source=0 if srcs is None else int(srcs[p] - ps[p]), iters=20)
+        ref = oracle.run(g, app, "exact", **kw)
+        want = ref.values + (ps[p] if app == "cc" else 0)
+        compare_values(app, got[sl], want, ctx="part %d (n %d, m %d)" % (p, g.n, g.m))
+        iters.append(ref.iterations)
+    if app != "pr":
+        assert st.iterations == max(iters)
+    G.close()

@@ -21,7 +21,7 @@ MUTANTS = {
     # Alg. 2 GG-Apply without the dangling-mass term
     "pr_apply_drops_dangling": ("xn = (1.0 - d) / n + d * (sum + D / n);", "xn = (1.0 - d) / n + d * (sum);"),
     # Alg. 2 GG-Gather without the division by the out-degree
-    "pr_gather_no_outdeg": ("sum += r->pr_x[v] / r->outdeg[v];", "sum += r->pr_x[v];"),
+    "pr_gather_no_outdeg": ("sum += r->pr_x[v] / deg[v];", "sum += r->pr_x[v];"),
     # PREFIX influence over the running sum before the edge's own contribution
     "pr_prefix_exclusive": ("        P += c;\n        double influence;",
                             "        double influence;\n        P += 0.0;"),
@@ -32,8 +32,29 @@ MUTANTS = {
     "cc_reads_destination": ("      const int32_t xv = r->l_x[g->col[e]];\n      if (xv < best) best = xv;",
                              "      const int32_t xv = r->l_x[u];\n      if (xv < best) best = xv;"),
     # GG schedule with the wrong period
-    "gg_period_off_by_one": ("case GGO_GG: kind = (i % (p->alpha + 1)) == 0",
-                             "case GGO_GG: kind = (i % (p->alpha + 2)) == 0"),
+    "gg_period_off_by_one": ("if (!p->decoupled) return i % (p->alpha + 1) == 0;",
+                             "if (!p->decoupled) return i % (p->alpha + 2) == 0;"),
+    # the NONE dangling reading still spreading the dangling mass
+    "dangling_none_ignored": ("  if (r->app.dangling == GGO_DANGLING_UNIFORM)\n    for (int32_t v = 0; v < n; ++v)\n      if (deg[v] == 0)",
+                              "  if (1)\n    for (int32_t v = 0; v < n; ++v)\n      if (deg[v] == 0)"),
+    # TOTAL influence taken over the running sum (the PREFIX reading)
+    "total_uses_running_sum": ("influence = rowsum32 > 0.0 ? c / rowsum32 : 0.0;",
+                               "influence = P > 0.0 ? c / P : 0.0;"),
+    # ACTIVE degree with the dangling set of the full graph
+    "active_degree_full_dangling_set": ("      if (deg[v] == 0) D += r->pr_x[v];",
+                                        "      if (r->outdeg[v] == 0) D += r->pr_x[v];"),
+    # ACTIVE degree counted over every out-edge instead of the active ones
+    "active_degree_counts_all_edges": ("        if (r->active[e]) r->odeg_act[r->g.col[e]]++;",
+                                       "        r->odeg_act[r->g.col[e]]++;"),
+    # decoupled schedule: first superstep one iteration early
+    "decoupled_first_off_by_one": ("  const int32_t first = p->alpha0 + 1;", "  const int32_t first = p->alpha0;"),
+    # decoupled schedule: theta0 never used
+    "decoupled_theta0_ignored": ("return (p->decoupled && i == p->alpha0 + 1) ? p->theta0 : p->theta;",
+                                 "return p->theta;"),
+    # GG-VStatus: the destination's status instead of the source's
+    "vstatus_reads_destination": ("any = r->active[e] && r->vact[r->g.col[e]];", "any = r->active[e] && r->vact[u];"),
+    # GG-VStatus: non-strict comparison with epsilon
+    "vstatus_not_strict": ("r->vact[u] = (uint8_t)(delta > bound);", "r->vact[u] = (uint8_t)(delta >= bound);"),
     # SSSP EStatus: improvement measured against the new minimum instead of the old one
     "sssp_estatus_wrong_denominator": ("flag = ((run - nw) << 16) > theta_q * run;",
                                        "flag = ((run - nw) << 16) > theta_q * nw;"),
@@ -41,8 +62,8 @@ MUTANTS = {
     "sssp_unreached_deactivated": ("if (xv == GGO_INF_U32) continue; /* not assessable: keeps its flag */",
                                    "if (xv == GGO_INF_U32) { r->active[e] = 0; continue; }"),
     # EStatus with >= instead of the strict > of Alg. 2
-    "estatus_not_strict": ("const int flag = r->infl[e] > r->pol.theta;",
-                           "const int flag = r->infl[e] >= r->pol.theta;"),
+    "estatus_not_strict": ("const int flag = r->infl[e] > r->theta_now;",
+                           "const int flag = r->infl[e] >= r->theta_now;"),
     # PPR teleporting to every vertex instead of the source
     "ppr_teleport_everywhere": ("xn = (u == s ? (1.0 - d) : 0.0) + d * (sum + (u == s ? D : 0.0));",
                                 "xn = (1.0 - d) / n + d * (sum + (u == s ? D : 0.0));"),

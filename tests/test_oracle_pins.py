@@ -570,3 +570,173 @@ def test_estatus_is_strict_for_binary_cc_influence():
     assert mask[_eid(g, 0, 2)] == 1 and mask[_eid(g, 1, 2)] == 0
     assert mask[_eid(g, 0, 1)] == 1 and mask[_eid(g, 2, 1)] == 0
     r.close()
+
+
+# --------------------------------------------------------------------------
+# Variants: dangling mass dropped, TOTAL influence, ACTIVE out-degree,
+# decoupled first-superstep parameters, GG-VStatus, the replay hooks
+# --------------------------------------------------------------------------
+
+def test_pr_dangling_none_linear_solve():
+    """Dropping the dangling mass (the literal Alg. 2 apply) is the linear
+    iteration x = (1-d)/N + d W x, whose fixed point a dense solve gives; PPR
+    likewise with the teleport to the source."""
+    g = gg.random_small(24, 40, seed=62)
+    assert np.sum(g.outdeg() == 0) >= 3, "the pin needs dangling vertices"
+    r = oracle.run(g, "pr", "exact", iters=400, dangling=oracle.DANGLING_NONE)
+    want = pr_linear_solve(g, dangling=False)
+    assert np.max(np.abs(r.values - want)) <= 1e-12
+    assert r.values.sum() < 1.0 - 1e-3  # mass leaks through the dangling vertices
+    s = int(np.nonzero(g.outdeg() > 0)[0][0])
+    r = oracle.run(g, "ppr", "exact", iters=400, source=s, dangling=oracle.DANGLING_NONE)
+    assert np.max(np.abs(r.values - pr_linear_solve(g, dangling=False, source=s))) <= 1e-12
+
+
+def _golden_graph(fx):
+    edges = fx["graph"]["edges"]
+    return gg.from_edges(fx["graph"]["n"], [e[0] for e in edges], [e[1] for e in edges])
+
+
+def _fr(vals):
+    return np.array([float(Fraction(v)) for v in vals])
+
+
+def test_golden_pr_total_influence():
+    fx = _load("pr_total_influence_4v.json")
+    g, p = _golden_graph(fx), fx["params"]
+    r = oracle.Run(g, "pr", "gg", sigma=p["sigma"], alpha=p["alpha"], theta=p["theta"], iters=p["iters"],
+                   influence=oracle.INFL_TOTAL)
+    for it in range(1, p["iters"] + 1):
+        st = r.step()
+        assert np.max(np.abs(r.values() - _fr(fx["expected"]["values_after"][str(it)]))) <= 1e-15, it
+        if it == 2:
+            assert st.superstep
+            assert list(r.mask()) == fx["expected"]["mask_after_superstep_2"]
+            assert np.max(np.abs(r.influence() - _fr(fx["expected"]["influence_at_superstep_2"]))) <= 1e-7
+    # PREFIX keeps every edge at this threshold: the two readings differ here
+    q = oracle.run(g, "pr", "gg", sigma=1.0, alpha=1, theta=p["theta"], iters=2)
+    assert list(q.mask) == [1] * 6
+
+
+def test_golden_pr_active_degree():
+    fx = _load("pr_active_degree_4v.json")
+    g, p = _golden_graph(fx), fx["params"]
+    r = oracle.Run(g, "pr", "gg", sigma=p["sigma"], alpha=p["alpha"], theta=p["theta"], iters=p["iters"],
+                   pr_degree=oracle.DEGREE_ACTIVE)
+    for it in range(1, p["iters"] + 1):
+        r.step()
+        assert np.max(np.abs(r.values() - _fr(fx["expected"]["values_after"][str(it)]))) <= 1e-15, it
+        if it == 2:
+            assert list(r.mask()) == fx["expected"]["mask_after_superstep_2"]
+    assert abs(r.values().sum() - 1.0) <= 1e-15
+
+
+def test_active_degree_sp_is_pagerank_of_the_sampled_graph():
+    """SP with the ACTIVE out-degree run to its fixed point is textbook
+    PageRank (uniform dangling mass) of the materialised sampled subgraph,
+    solved densely; with sigma = 1 it equals the full-degree run bit for bit."""
+    g = gg.random_small(30, 110, seed=77)
+    r = oracle.run(g, "pr", "sp", sigma=0.55, seed=5, iters=500, pr_degree=oracle.DEGREE_ACTIVE)
+    keep = r.mask.astype(bool)
+    sub = gg.from_edges(g.n, g.col[keep], g.dst()[keep])
+    want = pr_linear_solve(sub)
+    assert np.max(np.abs(r.values - want)) <= 1e-12
+    assert abs(r.values.sum() - 1.0) <= 1e-12
+    a = oracle.run(g, "pr", "gg", sigma=1.0, alpha=2, theta=0.0, iters=9, pr_degree=oracle.DEGREE_ACTIVE)
+    b = oracle.run(g, "pr", "gg", sigma=1.0, alpha=2, theta=0.0, iters=9)
+    assert np.array_equal(a.values, b.values)
+
+
+def test_golden_pr_decoupled_parameters():
+    fx = _load("pr_decoupled_4v.json")
+    g, p = _golden_graph(fx), fx["params"]
+    r = oracle.Run(g, "pr", "gg", sigma=p["sigma"], alpha=p["alpha"], theta=p["theta"], alpha0=p["alpha0"],
+                   theta0=p["theta0"], iters=p["iters"])
+    supers = []
+    for it in range(1, p["iters"] + 1):
+        st = r.step()
+        if st.superstep:
+            supers.append(it)
+        assert np.max(np.abs(r.values() - _fr(fx["expected"]["values_after"][str(it)]))) <= 1e-15, it
+        if str(it) in fx["expected"]["mask_after"]:
+            assert list(r.mask()) == fx["expected"]["mask_after"][str(it)], it
+    assert supers == fx["expected"]["supersteps"]
+
+
+@pytest.mark.parametrize("app", ["pr", "sssp", "cc"])
+def test_decoupled_with_equal_parameters_is_gg(app):
+    """alpha0 = alpha and theta0 = theta reduce the decoupled schedule to GG's."""
+    g = gg.rmat(8, 8, seed=21, weights=(app == "sssp"), symmetrize=(app == "cc"))
+    kw = dict(sigma=0.4, alpha=3, theta=0.1, seed=2, iters=14, source=int(gg.pick_sources(g, 1, 2)[0]))
+    a = oracle.run(g, app, "gg", alpha0=3, theta0=0.1, **kw)
+    b = oracle.run(g, app, "gg", **kw)
+    assert np.array_equal(a.values, b.values) and np.array_equal(a.mask, b.mask) and a.edges == b.edges
+
+
+def test_decoupled_schedule():
+    """Supersteps at alpha0 + 1 and then every alpha + 1 iterations."""
+    g = gg.rmat(7, 8, seed=23)
+    for a0, a in ((0, 3), (5, 1), (2, 2), (6, 0)):
+        r = oracle.run(g, "pr", "gg", sigma=0.5, alpha=a, theta=0.1, alpha0=a0, theta0=0.3, iters=20)
+        got = [s.iter for s in r.steps if s.superstep]
+        want = [i for i in range(1, 21) if i == a0 + 1 or (i > a0 + 1 and (i - a0 - 1) % (a + 1) == 0)]
+        assert got == want, (a0, a)
+
+
+def test_golden_pr_vstatus():
+    fx = _load("pr_vstatus_3v.json")
+    g, p = _golden_graph(fx), fx["params"]
+    r = oracle.Run(g, "pr", "sp", sigma=p["sigma"], iters=p["iters"], vstatus=oracle.VSTATUS_ABS, eps=p["eps"])
+    for it in range(1, p["iters"] + 1):
+        st = r.step()
+        assert np.max(np.abs(r.values() - _fr(fx["expected"]["values_after"][str(it)]))) <= 1e-15, it
+        assert st.edges == fx["expected"]["edges_gathered"][str(it)], it
+        if str(it) in fx["expected"]["active_after"]:
+            assert list(r.vactive()) == fx["expected"]["active_after"][str(it)], it
+    # strict comparison: with eps = 0, vertex 2 (1/3 before and after the
+    # first iteration) is inactive
+    r = oracle.Run(g, "pr", "sp", sigma=1.0, iters=2, vstatus=oracle.VSTATUS_ABS, eps=0.0)
+    r.step()
+    assert list(r.vactive()) == [1, 1, 0]
+
+
+def test_vstatus_extremes():
+    """A huge epsilon freezes every value after the first iteration (which
+    processes every vertex); with epsilon = 0 in accurate iterations nothing
+    is skipped, so an exact run is unchanged."""
+    g = gg.rmat(9, 8, seed=25)
+    one = oracle.run(g, "pr", "exact", iters=1).values
+    r = oracle.run(g, "pr", "sp", sigma=0.7, seed=3, iters=8, vstatus=oracle.VSTATUS_ABS, eps=1e9)
+    first = oracle.run(g, "pr", "sp", sigma=0.7, seed=3, iters=1)
+    assert np.array_equal(r.values, first.values)
+    assert r.edges == first.edges
+    assert not np.array_equal(first.values, one)  # the first sampled iteration is not the exact one
+    a = oracle.run(g, "pr", "exact", iters=6, vstatus=oracle.VSTATUS_REL, eps=0.5)
+    b = oracle.run(g, "pr", "exact", iters=6)
+    assert np.array_equal(a.values, b.values)
+
+
+def test_set_mask_replays_flags():
+    """Adopting the run's own flags changes nothing; adopting all-ones makes
+    the next SP iteration gather every edge and equal an exact iteration."""
+    g = gg.rmat(8, 8, seed=27)
+    a = oracle.Run(g, "pr", "sp", sigma=0.3, seed=4, iters=3)
+    b = oracle.Run(g, "pr", "sp", sigma=0.3, seed=4, iters=3)
+    a.step()
+    b.step()
+    b.set_mask(b.mask())
+    sa, sb = a.step(), b.step()
+    assert np.array_equal(a.values(), b.values()) and sa.edges == sb.edges
+    b.set_mask(np.ones(g.m))
+    x = b.values()
+    st = b.step()
+    assert st.edges == g.m
+    e = oracle.Run(g, "pr", "exact", iters=3)
+    e.step()
+    e.step()
+    # one exact iteration from the same state: compare through a fresh exact step on b's input
+    outdeg = g.outdeg().astype(np.float64)
+    dang = x[outdeg == 0].sum()
+    want = np.full(g.n, 0.15 / g.n) + 0.85 * (np.bincount(g.dst(), weights=x[g.col] / outdeg[g.col],
+                                                          minlength=g.n) + dang / g.n)
+    assert np.max(np.abs(b.values() - want)) <= 1e-15
