@@ -10,7 +10,10 @@ sample ratios 0.1, 0.3, 0.5, 0.7, 0.9 (alpha = 4, theta = 0.05; SSSP/CC run
 the exact run's iteration count). Inputs are resident in HBM before timing;
 sampling and packing are inside the timed region.
 
-value = edges gathered per second over the timed steps (GTEPS, all runs).
+value = edges actually read per second over the timed steps (GTEPS_work, all
+runs): a frontier-push SSSP/CC iteration counts the out-edges it pushed, not
+the edge set it stands for. Each run also reports GTEPS_eff = E * L / time
+(L = the exact run's iteration count), which is comparable across schemes.
 
 Three further sections are measured after the timed steps (they are not
 part of `value`):
@@ -66,7 +69,20 @@ def cpu_baseline(graphs, source, budget_iters=3):
     dt = time.perf_counter() - t0
     return {"value": edges / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": "%d exact iterations each of PR, SSSP and CC on the benchmark graphs (%.1f s, %d edges)"
-                      % (budget_iters, dt, edges)}
+                      % (budget_iters, dt, edges),
+            "host_nproc": os.cpu_count(), "host_affinity": len(os.sched_getaffinity(0)), "host_cpu": cpu_model()}
+
+
+def cpu_model():
+    """CPU model name of the host, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 # Fastest configurations within 1% error on R-MAT scale 22 (seed 2), from a
@@ -125,7 +141,10 @@ def bench_at_1pct(G, apps, iters, source, exact_out, metrics, np):
                     "accuracy_min": round(metrics.accuracy(float(np.max(errs))), 3),
                     "within_1pct": bool(max(errs) <= 0.01), "ms": round(st.device_ms, 3),
                     "exact_ms": round(sx.device_ms, 3), "speedup": round(sx.device_ms / st.device_ms, 3),
-                    "edges_vs_exact": round(st.edges_gathered / sx.edges_gathered, 4)}
+                    "edges_vs_exact": round(st.edges_gathered / sx.edges_gathered, 4),
+                    "gteps_work": round(st.edges_processed / st.device_ms / 1e6, 2),
+                    "gteps_eff": round(G[app].m * iters[app] / st.device_ms / 1e6, 2),
+                    "exact_gteps_work": round(sx.edges_processed / sx.device_ms / 1e6, 2)}
         log("at_1pct:", app, out[app])
     return out
 
@@ -205,7 +224,7 @@ def bench_batch(P, gg, torch, seed, np, metrics):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out["union64_%s" % app] = {"n": U.n, "m": U.m, "ms": round(dt * 1e3, 3), "iterations": st.iterations,
-                                   "gteps": round(st.edges_gathered / dt / 1e9, 2), "tuning": tuning}
+                                   "gteps": round(st.edges_processed / dt / 1e9, 2), "tuning": tuning}
         log("batch:", app, out["union64_%s" % app])
         G.close()
     log("batch: unions done in %.1f s" % (time.perf_counter() - t))
@@ -431,8 +450,9 @@ def main():
         log("timed step %d done" % (k + 1))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    edges_total = sum(st.edges_gathered for (_, _, _, st) in all_stats)
+    edges_total = sum(st.edges_processed for (_, _, _, st) in all_stats)
     gteps = edges_total / elapsed / 1e9
+    eff_total = sum((graphs[app].m * iters[app]) for (app, _, _, _) in all_stats)
 
     # roofline of the dominant kernel (largest total event time in the timed
     # region); the exact and the approximate gathers are one kernel, so their
@@ -460,7 +480,7 @@ def main():
         key = "%s_%s" % (app, "exact" if pol == "exact" else "gg%.1f" % sg)
         d = runs.setdefault(key, {"ms": [], "edges": [], "iters": st.iterations})
         d["ms"].append(st.device_ms)
-        d["edges"].append(st.edges_gathered)
+        d["edges"].append(st.edges_processed)
     m_eff = {"pr": gw.m, "sssp": gw.m, "cc": graphs["cc"].m if "cc" in graphs else 0}
     summary = {}
     for key, d in runs.items():
@@ -525,6 +545,7 @@ def main():
         "metric": "GTEPS + HBM GB/s, approx vs exact PageRank/SSSP on 1 MI355X at <=1% error",
         "value": round(gteps, 3),
         "unit": "GTEPS",
+        "gteps_eff": round(eff_total / elapsed / 1e9, 3),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,

@@ -60,8 +60,8 @@ typedef enum { GG_APP_PR = 0, GG_APP_SSSP = 1, GG_APP_CC = 2, GG_APP_PPR = 3 } g
 /* Correction schemes: EXACT = accurate mode in every iteration (the baseline
    of Sec. 5); SP = sparsified for the whole run; SMS = approximate for alpha
    iterations then accurate for the rest; GG = adaptive correction [Sec. 3.4].
-   LEARNED (not in the paper; it addresses the automatic choice of control
-   parameters the paper leaves to future work, Sec. 7) keeps GG's schedule,
+   LEARNED (a project addition, not in the paper: a network trained on the
+   method's own error traces picks where to correct) keeps GG's schedule,
    but at a correction step (iteration i with i mod (alpha+1) == 0) a network
    scores every vertex; the selected rows S = { v : logit_v > tau } are
    gathered over all in-edges and have their flags re-selected (a partial

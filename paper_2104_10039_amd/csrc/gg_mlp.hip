@@ -1,5 +1,4 @@
-// Learned correction policy (not in the paper, whose automatic choice of
-// control parameters is left to future work, Sec. 7): per-vertex features,
+// Learned correction policy (a project addition, not in the paper): per-vertex features,
 // a small MLP (8 -> 64 -> 64 -> 1, ReLU) that scores each vertex for drift,
 // drift labels, and the kernels that train the network. BF16 weights and
 // activations, FP32 accumulation on MFMA (v_mfma_f32_16x16x16_bf16), FP32
