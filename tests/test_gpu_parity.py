@@ -172,6 +172,25 @@ def test_sigma_extremes_and_zero_iters(P):
     assert np.allclose(out.cpu().numpy(), 1.0 / g.n)
 
 
+@pytest.mark.parametrize("app", ["pr", "ppr"])
+@pytest.mark.parametrize("policy", ["exact", "gg"])
+def test_dangling_none(P, app, policy):
+    """The literal GG-Apply (mass of vertices without out-edges dropped, not
+    spread): exact runs and GG step by step against the oracle on R-MAT 14,
+    where about half the vertices have no out-edge, and exact runs on the
+    tiny family."""
+    g = graph_for(app, 14, seed=3)
+    s = int(gg.pick_sources(g, 1, 3)[0])
+    if policy == "exact":
+        check_run(P, g, app, "exact", ctx="rmat14 dangling none", source=s, dangling="none", iters=20)
+        for tg in gg.tiny_family():
+            ts = int(gg.pick_sources(tg, 1, 3)[0]) if tg.m else 0
+            check_run(P, tg, app, "exact", ctx=tg.name + " dangling none", source=ts, dangling="none", iters=20)
+    else:
+        step_compare(P, g, app, "gg", sample_ratio=0.5, alpha=4, theta=0.05, seed=2, iters=20, source=s,
+                     dangling="none")
+
+
 def test_golden_examples_on_gpu(P):
     """The hand-worked examples of tests/golden, run through the library."""
     import json
