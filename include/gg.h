@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GG_VERSION 2
+#define GG_VERSION 3
 
 typedef enum {
   GG_OK = 0,
@@ -216,6 +216,38 @@ void gg_graph_free(gg_graph* g);
  */
 int gg_exact_run(gg_graph* g, const gg_app_params* params, void* out_values, uint32_t out_flags,
                  gg_run_stats* stats);
+
+/*
+ * Exact run that allocates nothing, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation. It runs the same gather kernels as gg_exact_run, with
+ * its per-run state (two value buffers, the dangling partial sums, the hub
+ * and source-segment partials) in one static array the library holds on
+ * each device, 64 MiB, allocated with the library's code at load (about
+ * n * 8 bytes + 8 bytes per source segment of every row longer than the
+ * short-row bound: R-MAT scale 22 fits, scale 23 does not). Every call on a
+ * device shares that device's array, so calls that overlap on one device
+ * (on any streams, from any threads) race; the array keeps the last call's
+ * contents, none of which a later call reads before writing it.
+ *   - Runs exactly params->iters (>= 1) iterations of every app: PR/PPR as
+ *     gg_exact_run; SSSP/CC dense, with no frontier pushes and no readback
+ *     of a changed count, so their values equal gg_exact_run's once iters
+ *     reaches that run's iteration count (further iterations change
+ *     nothing). params->max_iters is ignored.
+ *   - Only enqueues work on the graph's stream and returns (no host wait):
+ *     out_values_dev (device, n elements of the app's value type, as for
+ *     gg_exact_run) holds the result once the stream reaches that point.
+ *     The call launches kernels only, so it can be captured into a HIP graph.
+ *   - stats (nullable): iterations, edges_gathered = edges_processed =
+ *     iters * m, active_edges = m; device_ms and the rest 0.
+ * The graph (loaded with gg_graph_load_csr, which allocates) must be current
+ * on the calling thread's device. GG_E_INVAL (null argument, iters < 1, bad
+ * parameters as for gg_exact_run), GG_E_RANGE (the run needs more scratch
+ * than the array holds), GG_E_STATE (a step-API run is active on the graph,
+ * or another device is current), GG_E_UNSUPPORTED (graphs with parts). No
+ * work is enqueued when an error is returned.
+ */
+int gg_exact_run_noalloc(gg_graph* g, const gg_app_params* params, void* out_values_dev, gg_run_stats* stats);
 
 /*
  * The approximate run (the "approx_run(app, sample_ratio, correction_policy)"

@@ -98,6 +98,7 @@ SIGNATURES = {
     "gg_graph_set_stream": (ctypes.c_int, [_VP, _VP]),
     "gg_graph_free": (None, [_VP]),
     "gg_exact_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), _VP, ctypes.c_uint32, ctypes.POINTER(RunStats)]),
+    "gg_exact_run_noalloc": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), _VP, ctypes.POINTER(RunStats)]),
     "gg_approx_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_double, ctypes.POINTER(Policy), _VP,
                                      ctypes.c_uint32, ctypes.POINTER(RunStats)]),
     "gg_run_begin": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_double, ctypes.POINTER(Policy),
@@ -340,6 +341,16 @@ class Graph:
         p = _app_params(app, damping, iters, max_iters, source, dangling)
         st = RunStats()
         _check(lib().gg_exact_run(self._h, ctypes.byref(p), out.data_ptr(), 0, ctypes.byref(st)))
+        return out, _stats(st)
+
+    def exact_run_noalloc(self, app, out, damping=0.85, iters=20, source=0, dangling="uniform"):
+        """gg_exact_run_noalloc into a caller-allocated device tensor `out`;
+        enqueues on the graph's stream without waiting. Returns (out, Stats)."""
+        if not (out.is_cuda and out.dtype == _value_dtype(app) and out.is_contiguous() and out.numel() >= self.n):
+            raise ValueError("out must be a contiguous device tensor of %d %s values" % (self.n, _value_dtype(app)))
+        p = _app_params(app, damping, iters, 1, source, dangling)
+        st = RunStats()
+        _check(lib().gg_exact_run_noalloc(self._h, ctypes.byref(p), out.data_ptr(), ctypes.byref(st)))
         return out, _stats(st)
 
     def approx_run(self, app, sample_ratio, policy="gg", out=None, alpha=4, theta=0.05, seed=1,

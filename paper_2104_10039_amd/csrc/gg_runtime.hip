@@ -21,6 +21,7 @@
 #include <cstring>
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -91,6 +92,7 @@ struct gg_graph {
   int32_t* i32_scratch = nullptr;  // small device scalars: [0] dangling count, [1] validate flags
   void* blk_scratch = nullptr;
   gg_tuning tune{32, 4, 1024, 2048, 1, 0, 1, 16};
+  int device = 0;  // the device current at load
   int32_t hub_spin = kHubSpinLimit;  // gg_graph_set_wait_limit
   bool rows_sorted = true;  // every row lists its sources in ascending order (else no segmentation)
   // frontier (SSSP / CC): out-CSR structure and lists, built on first use
@@ -1429,6 +1431,153 @@ int whole_run(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
   return rc;
 }
 
+// ---- exact runs that allocate nothing -----------------------------------------
+// Scratch of gg_exact_run_noalloc: the double-buffered vertex values, the
+// dangling partial sums, the hub chunk partials and the source-segment
+// partials of the gather, in one array per device that the device holds
+// until the process ends. In host code the array's name is only a stand-in:
+// every use goes through the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(GG_E_RANGE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    GG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(GG_E_DEVICE, "no device address for the scratch array");
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GG_OK;
+}
+
+// Byte offsets of the scratch regions of one run (each 256-byte aligned).
+struct NoAllocLayout {
+  size_t val[2], dpart, part_f, part_u, part_cnt, seg_part, total;
+};
+
+NoAllocLayout noalloc_layout(const gg_graph* g) {
+  NoAllocLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += ((bytes > 0 ? bytes : 1) + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t n = (size_t)g->n;
+  const size_t chunks = (size_t)(g->full.h.chunks > 0 ? g->full.h.chunks : 1);
+  const size_t nl = (size_t)g->full.h.wave + (size_t)g->full.h.hub;
+  L.val[0] = take(n * 4);
+  L.val[1] = take(n * 4);
+  L.dpart = take(257 * sizeof(double));
+  L.part_f = take(chunks * sizeof(double));
+  L.part_u = take(chunks * sizeof(uint32_t));
+  L.part_cnt = take(chunks * sizeof(int32_t));
+  L.seg_part = take(g->tune.seg_enable ? (size_t)g->seg_s * (nl > 0 ? nl : 1) * sizeof(double) : 0);
+  L.total = off;
+  return L;
+}
+
+// Exact run of p->iters iterations over the graph's full binning, its
+// per-run state in the scratch array; only enqueues work on the graph's
+// stream. Nothing in the scratch needs to start at zero: every region is
+// written before it is read, in every iteration.
+int exact_noalloc(gg_graph* g, const gg_app_params* p, void* out, gg_run_stats* st) {
+  if (!g || !p || !out) return fail(GG_E_INVAL, "null argument");
+  const int app = p->app;
+  if (app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "unknown app");
+  if (p->iters < 1) return fail(GG_E_INVAL, "iters must be >= 1");
+  const bool pr = is_pr(app);
+  if (pr && !(p->damping >= 0.0 && p->damping < 1.0)) return fail(GG_E_INVAL, "damping outside [0, 1)");
+  if (p->dangling != GG_DANGLING_UNIFORM && p->dangling != GG_DANGLING_NONE) return fail(GG_E_INVAL, "unknown dangling");
+  if ((app == GG_APP_SSSP || app == GG_APP_PPR) && (p->source < 0 || p->source >= g->n))
+    return fail(GG_E_INVAL, "source out of range");
+  if (app == GG_APP_SSSP && !g->wedges) return fail(GG_E_INVAL, "SSSP needs edge weights");
+  if (g->n_parts > 0) return fail(GG_E_UNSUPPORTED, "graphs with parts");
+  if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+  if (!g->full_valid) return fail(GG_E_STATE, "the graph has no binning");
+  const NoAllocLayout L = noalloc_layout(g);
+  if (L.total > kNoAllocScratchBytes)
+    return fail(GG_E_RANGE, "the run needs " + std::to_string(L.total) + " bytes of scratch, more than the " +
+                                std::to_string(kNoAllocScratchBytes) + " the library holds");
+  if (g->tune.seg_enable) GG_TRY(check_seg_capacity(g, g->full));
+  int dev = -1;
+  GG_HIP(hipGetDevice(&dev));
+  if (dev != g->device) return fail(GG_E_STATE, "the current device is not the graph's device");
+  unsigned char* sp = nullptr;
+  GG_TRY(scratch_address(dev, &sp));
+  if (st) std::memset(st, 0, sizeof(*st));
+  if (g->n > 0) {
+    Sweep s;
+    std::memset(&s, 0, sizeof(s));
+    s.n = g->n;
+    s.small_max = g->tune.small_max;
+    s.wave_max = g->tune.wave_max;
+    s.hub_chunk = g->tune.hub_chunk;
+    s.rowptr = g->rowptr;
+    s.outdeg = g->outdeg;
+    double* dpart = (double*)(sp + L.dpart);
+    s.dangling = dpart + 256;
+    s.damping = p->damping;
+    s.base = (1.0 - p->damping) / (double)g->n;
+    s.source = p->source;
+    s.part_f = (double*)(sp + L.part_f);
+    s.part_u = (uint32_t*)(sp + L.part_u);
+    s.part_cnt = (int32_t*)(sp + L.part_cnt);
+    set_bins(s, g->full);
+    s.edges = full_edges(g, app);
+    if (g->tune.seg_enable) {
+      set_seg(g, s, g->seg_off_full);
+      s.seg_part_f = (double*)(sp + L.seg_part);
+      s.seg_part_u = (uint32_t*)(sp + L.seg_part);
+    }
+    float* c[2] = {(float*)(sp + L.val[0]), (float*)(sp + L.val[1])};
+    uint32_t* x[2] = {(uint32_t*)(sp + L.val[0]), (uint32_t*)(sp + L.val[1])};
+    if (pr) {
+      GG_HIP(launch_pr_init(app, g->outdeg, g->n, p->source, nullptr, nullptr, c[0], g->stream));
+      if (p->dangling == GG_DANGLING_NONE) GG_HIP(launch_fill_u32((uint32_t*)(dpart + 256), 2, 0u, g->stream));
+    } else {
+      GG_HIP(launch_min_init(app, g->n, p->source, x[0], g->stream));
+    }
+    for (int32_t i = 1; i <= p->iters; ++i) {
+      const int cur = (i - 1) & 1;
+      const bool last = i == p->iters;
+      if (pr) {
+        if (p->dangling == GG_DANGLING_UNIFORM)
+          GG_HIP(launch_dangling_sum(c[cur], g->dang, nullptr, g->n_dang, dpart, dpart + 256, g->stream));
+        s.c_in = c[cur];
+        s.c_out = c[1 - cur];
+        s.x_out = last ? (float*)out : nullptr;
+      } else {
+        s.x_in = x[cur];
+        s.x_next = last ? (uint32_t*)out : x[1 - cur];
+      }
+      if (g->tune.seg_enable)
+        GG_HIP(launch_gather_seg(app, g->tune.small_team, s, g->stream));
+      else
+        GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream));
+    }
+  }
+  if (st) {
+    st->iterations = p->iters;
+    st->edges_gathered = (int64_t)p->iters * g->m;
+    st->edges_processed = st->edges_gathered;
+    st->active_edges = g->m;
+  }
+  return GG_OK;
+}
+
+}  // namespace
+
 // ---- multi-query batch --------------------------------------------------------
 
 int ensure_batch(gg_graph* g, int32_t qp) {
@@ -1701,6 +1850,11 @@ int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
     g->n = d->n;
     g->m = d->m;
     g->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+      (void)hipGetLastError();
+      delete g;
+      return fail(GG_E_DEVICE, "no current device");
+    }
     const size_t n = (size_t)d->n, m = (size_t)d->m;
     int rc = GG_OK;
     auto bail = [&](int code) {
@@ -2022,6 +2176,10 @@ int gg_exact_run(gg_graph* g, const gg_app_params* params, void* out_values, uin
     pol.kind = GG_POLICY_EXACT;
     return whole_run(g, params, 1.0, &pol, out_values, out_flags, st);
   });
+}
+
+int gg_exact_run_noalloc(gg_graph* g, const gg_app_params* params, void* out_values_dev, gg_run_stats* st) {
+  return guard([&]() -> int { return exact_noalloc(g, params, out_values_dev, st); });
 }
 
 int gg_approx_run(gg_graph* g, const gg_app_params* params, double sample_ratio, const gg_correction_policy* policy,
