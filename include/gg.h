@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GG_VERSION 3
+#define GG_VERSION 4
 
 typedef enum {
   GG_OK = 0,
@@ -190,6 +190,30 @@ typedef struct gg_run gg_run;
 
 int gg_version(void);
 const char* gg_last_error(void);
+
+/*
+ * Device memory of the library's own objects (project addition; the paper
+ * has no memory manager). Graph workspaces, networks and traces allocate
+ * through alloc(bytes, ctx), which returns device memory on the current
+ * device, aligned to 256 bytes, or NULL when it cannot (the library then
+ * fails with GG_E_NOMEM and leaves the caller's outputs untouched; blocks
+ * that an object already holds stay with it until it is freed). They free
+ * through free(ptr, ctx). The library synchronizes the device after each
+ * successful alloc and before each free, as hipMalloc / hipFree do, so a
+ * block changes owner with no work pending on it. Both NULL restores
+ * hipMalloc / hipFree, the default. The pinned host buffer of a graph and
+ * the static array of gg_exact_run_noalloc do not use it. The allocator may
+ * change only while no graph, network or trace exists (GG_E_STATE
+ * otherwise), so every block is freed by the allocator that made it;
+ * GG_E_INVAL when exactly one function is NULL. Not thread-safe against
+ * concurrent object creation.
+ */
+typedef void* (*gg_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*gg_free_fn)(void* ptr, void* ctx);
+int gg_set_allocator(gg_alloc_fn alloc, gg_free_fn free_fn, void* ctx);
+
+/* Graphs, networks and traces currently alive (for leak checks). */
+int64_t gg_live_objects(void);
 
 /*
  * Load a graph (the "graph_load_csr" step). The library computes the

@@ -1,7 +1,8 @@
 """MI355X GraphGuess sweep: Python binding of the C ABI in include/gg.h.
 
 This module only marshals arguments: every step of the sweep runs in the HIP
-kernels of libgg.so. PyTorch provides device memory and streams. torch is
+kernels of libgg.so. PyTorch provides device memory (the library allocates
+through torch's caching allocator, gg_set_allocator) and streams. torch is
 imported before the library is loaded so that the process holds a single HIP
 runtime (torch's).
 
@@ -9,8 +10,10 @@ If libgg.so is missing, loading fails with an error: there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Optional
 
@@ -93,6 +96,8 @@ TUNING_FIELDS = [f[0] for f in Tuning._fields_]
 _VP = ctypes.c_void_p
 SIGNATURES = {
     "gg_version": (ctypes.c_int, []),
+    "gg_set_allocator": (ctypes.c_int, [_VP, _VP, _VP]),
+    "gg_live_objects": (ctypes.c_int64, []),
     "gg_last_error": (ctypes.c_char_p, []),
     "gg_graph_load_csr": (ctypes.c_int, [ctypes.POINTER(CsrDesc), _VP, ctypes.POINTER(_VP)]),
     "gg_graph_set_stream": (ctypes.c_int, [_VP, _VP]),
@@ -145,9 +150,71 @@ PROFILE_KIND = {"gather_exact": 0, "gather_approx": 1, "superstep": 2, "push": 3
 
 _lib = None
 
+# Device allocator callbacks (gg_set_allocator): C function pointers made
+# from Python functions; the module keeps them alive.
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator = None  # (ALLOC_FN, FREE_FN) installed, or None for hipMalloc
+
+
+def _torch_alloc(nbytes, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+    except Exception:  # out of memory: the library reports GG_E_NOMEM
+        return None
+
+
+def _torch_free(ptr, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(ptr)
+    except Exception:
+        pass
+
+
+def set_allocator(alloc=None, free=None):
+    """gg_set_allocator with Python callables alloc(nbytes) -> int address
+    (0 or None on failure) and free(address); both None restores hipMalloc.
+    "torch" for alloc selects torch's caching allocator (the default once the
+    library is loaded). Only while no graph, network or trace exists."""
+    global _allocator
+    if alloc == "torch":
+        pair = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
+    elif alloc is None and free is None:
+        pair = None
+    else:
+        pair = (ALLOC_FN(lambda nb, ctx: alloc(int(nb)) or None), FREE_FN(lambda p, ctx: free(int(p))))
+    if pair is None:
+        _check(lib().gg_set_allocator(None, None, None))
+    else:
+        _check(lib().gg_set_allocator(ctypes.cast(pair[0], _VP), ctypes.cast(pair[1], _VP), None))
+    _allocator = pair
+
+
+def live_objects():
+    """gg_live_objects: graphs, networks and traces the library holds."""
+    return int(lib().gg_live_objects())
+
+
+# Objects that hold library handles, closed at interpreter exit while torch
+# (whose allocator frees their memory) is still alive.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    objs = list(_live)
+    # step-API runs first: freeing a graph also ends its run
+    for obj in sorted(objs, key=lambda o: not isinstance(o, Run)):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
 
 def lib():
-    """Load libgg.so (built by __graft_entry__.build() / _build.py). Raises if missing."""
+    """Load libgg.so (built by __graft_entry__.build() / _build.py). Raises if
+    missing. Device memory of the library's objects then comes from torch's
+    caching allocator."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -158,6 +225,7 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        set_allocator("torch")
     return _lib
 
 
@@ -250,6 +318,7 @@ class Graph:
         self._stream = _stream_handle(stream)
         _check(lib().gg_graph_load_csr(ctypes.byref(desc), self._stream, ctypes.byref(h)))
         self._h = h
+        _live.add(self)
         self.weighted = weight is not None
 
     @classmethod
@@ -422,6 +491,7 @@ class Run:
         _check(lib().gg_run_begin(graph.handle, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
                                   ctypes.byref(h)))
         self._h = h
+        _live.add(self)
 
     def step(self) -> Optional[dict]:
         info = StepInfo()
@@ -494,7 +564,9 @@ class Run:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().gg_run_end(self._h)
+            # a graph that was freed first has already ended its run
+            if getattr(self.graph, "_h", None):
+                lib().gg_run_end(self._h)
             self._h = None
 
     def __del__(self):
@@ -520,6 +592,7 @@ class Mlp:
         h = ctypes.c_void_p()
         _check(lib().gg_mlp_create(_stream_handle(stream), int(seed), ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
 
     def set_weights(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
@@ -579,6 +652,7 @@ class Trace:
         h = ctypes.c_void_p()
         _check(lib().gg_trace_create(int(capacity), ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
 
     def clear(self):
         _check(lib().gg_trace_clear(self.handle))

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -55,28 +56,75 @@ int fail(int code, const std::string& msg) {
     if (r_ != GG_OK) return r_; \
   } while (0)
 
+// Device memory of the library's objects comes from the caller's allocator
+// (gg_set_allocator) or, when none is set, from hipMalloc / hipFree. The
+// allocator can change only while no graph, network or trace exists, so
+// every block is freed by the allocator that made it. Around the caller's
+// functions the device is synchronized, as hipMalloc / hipFree do: a block
+// handed back is idle on every stream, and a block received carries no
+// work still pending from its previous owner.
+gg_alloc_fn g_alloc_fn = nullptr;
+gg_free_fn g_free_fn = nullptr;
+void* g_alloc_ctx = nullptr;
+std::atomic<int64_t> g_live_objects{0};
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (g_alloc_fn) {
+    void* p = g_alloc_fn(bytes, g_alloc_ctx);
+    if (p) (void)hipDeviceSynchronize();
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_free_fn) {
+    (void)hipDeviceSynchronize();
+    g_free_fn(p, g_alloc_ctx);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+// Allocates count elements into *p. A block already held there (left by an
+// earlier set-up step that failed part way) is freed first, so a retry
+// leaks nothing.
 template <typename T>
 int dalloc(T** p, size_t count) {
+  if (*p) dev_free((void*)*p);
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(GG_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-  }
+  void* q = dev_alloc(count * sizeof(T));
+  if (!q) return fail(GG_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  *p = (T*)q;
   return GG_OK;
 }
 
 template <typename T>
 void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+  dev_free((void*)p);
   p = nullptr;
 }
+
+// Member of every graph, network and trace: keeps the count of live objects.
+struct LiveObject {
+  LiveObject() { g_live_objects.fetch_add(1); }
+  ~LiveObject() { g_live_objects.fetch_sub(1); }
+  LiveObject(const LiveObject&) = delete;
+  LiveObject& operator=(const LiveObject&) = delete;
+};
 
 }  // namespace
 
 struct gg_graph {
+  LiveObject live;
   int32_t n = 0;
   int64_t m = 0;
   hipStream_t stream = nullptr;
@@ -90,7 +138,7 @@ struct gg_graph {
   int32_t* dang = nullptr;
   int32_t n_dang = 0;
   int32_t* i32_scratch = nullptr;  // small device scalars: [0] dangling count, [1] validate flags
-  void* blk_scratch = nullptr;
+  int64_t* blk_scratch = nullptr;  // block-level scan scratch (8-byte units)
   gg_tuning tune{32, 4, 1024, 2048, 1, 0, 1, 16};
   int device = 0;  // the device current at load
   int32_t hub_spin = kHubSpinLimit;  // gg_graph_set_wait_limit
@@ -120,7 +168,7 @@ struct gg_graph {
   // multi-query batch workspace
   struct Batch {
     int64_t val_cap = 0;  // elements of each value buffer
-    void* buf[3] = {nullptr, nullptr, nullptr};
+    uint32_t* buf[3] = {nullptr, nullptr, nullptr};  // 4-byte values
     int64_t part_cap = 0;  // elements (chunks * qp) of the partial array
     double* part = nullptr;
     int32_t qp_cap = 0;
@@ -135,7 +183,7 @@ struct gg_graph {
   int32_t seg_s = 8, seg_z = 1;
   int32_t* seg_off_full = nullptr;
   int32_t* seg_off_act = nullptr;
-  void* seg_part = nullptr;
+  double* seg_part = nullptr;  // 8-byte partials (double for PR, uint32 in the low half otherwise)
   int64_t seg_cap_off = 0;   // int32 entries of each offset array
   int64_t seg_cap_part = 0;  // 8-byte entries of the partial array
   Bins full;         // binning of the full rows by in-degree
@@ -214,6 +262,7 @@ struct gg_run {
 };
 
 struct gg_mlp {
+  LiveObject live;
   hipStream_t stream = nullptr;
   ggk::MlpDev d{};
   float* grad = nullptr;  // kMlpParams gradient + loss sum
@@ -225,6 +274,7 @@ struct gg_mlp {
 };
 
 struct gg_trace {
+  LiveObject live;
   int64_t cap = 0, size = 0, dropped = 0;
   uint16_t* feat = nullptr;  // [cap][8]
   float* label = nullptr;    // cap
@@ -324,16 +374,11 @@ int ensure_seg(gg_graph* g) {
   if (g->seg_off_full && g->seg_cap_off >= need_off && g->seg_cap_part >= need_part) return GG_OK;
   dfree(g->seg_off_full);
   dfree(g->seg_off_act);
-  if (g->seg_part) (void)hipFree(g->seg_part);
-  g->seg_part = nullptr;
+  dfree(g->seg_part);
   g->seg_cap_off = g->seg_cap_part = 0;
   GG_TRY(dalloc(&g->seg_off_full, (size_t)need_off));
   GG_TRY(dalloc(&g->seg_off_act, (size_t)need_off));
-  if (hipMalloc(&g->seg_part, (size_t)need_part * sizeof(double)) != hipSuccess) {
-    (void)hipGetLastError();
-    g->seg_part = nullptr;
-    return fail(GG_E_NOMEM, "segment partial allocation failed");
-  }
+  GG_TRY(dalloc(&g->seg_part, (size_t)need_part));
   g->seg_cap_off = need_off;
   g->seg_cap_part = need_part;
   return GG_OK;
@@ -500,8 +545,8 @@ int ensure_workspace(gg_graph* g) {
   GG_TRY(alloc_bins(g->act, g->n));
   GG_TRY(dalloc(&g->dpartial, 257));
   GG_TRY(dalloc(&g->changed, 1));
-  GG_HIP(hipEventCreate(&g->ev0));
-  GG_HIP(hipEventCreate(&g->ev1));
+  if (!g->ev0) GG_HIP(hipEventCreate(&g->ev0));
+  if (!g->ev1) GG_HIP(hipEventCreate(&g->ev1));
   g->ws = true;
   return ensure_parts(g);
 }
@@ -518,7 +563,7 @@ void free_graph(gg_graph* g) {
   dfree(g->outdeg);
   dfree(g->dang);
   dfree(g->i32_scratch);
-  if (g->blk_scratch) (void)hipFree(g->blk_scratch);
+  dfree(g->blk_scratch);
   free_bins(g->full);
   dfree(g->chunk_order);
   dfree(g->chunk_scratch);
@@ -557,8 +602,7 @@ void free_graph(gg_graph* g) {
   dfree(g->part_dstart);
   dfree(g->part_src);
   dfree(g->part_dang);
-  for (int i = 0; i < 3; ++i)
-    if (g->batch.buf[i]) (void)hipFree(g->batch.buf[i]);
+  for (int i = 0; i < 3; ++i) dfree(g->batch.buf[i]);
   dfree(g->batch.part);
   dfree(g->batch.dpart);
   dfree(g->batch.dang);
@@ -567,7 +611,7 @@ void free_graph(gg_graph* g) {
   if (g->batch.cs) (void)hipStreamDestroy(g->batch.cs);
   for (hipEvent_t e : {g->batch.ea, g->batch.eb, g->batch.t0, g->batch.t1})
     if (e) (void)hipEventDestroy(e);
-  if (g->seg_part) (void)hipFree(g->seg_part);
+  dfree(g->seg_part);
   dfree(g->feat);
   dfree(g->sel);
   dfree(g->logits);
@@ -1584,17 +1628,9 @@ int ensure_batch(gg_graph* g, int32_t qp) {
   auto& B = g->batch;
   const int64_t need_val = (int64_t)g->n * qp;
   if (B.val_cap < need_val) {
-    for (int i = 0; i < 3; ++i) {
-      if (B.buf[i]) (void)hipFree(B.buf[i]);
-      B.buf[i] = nullptr;
-    }
+    for (int i = 0; i < 3; ++i) dfree(B.buf[i]);
     B.val_cap = 0;
-    for (int i = 0; i < 3; ++i) {
-      if (hipMalloc(&B.buf[i], (size_t)(need_val > 0 ? need_val : 1) * 4) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(GG_E_NOMEM, "batch value buffers");
-      }
-    }
+    for (int i = 0; i < 3; ++i) GG_TRY(dalloc(&B.buf[i], (size_t)(need_val > 0 ? need_val : 1)));
     B.val_cap = need_val;
   }
   const int64_t need_part = max_chunks(g) * (int64_t)qp;
@@ -1834,6 +1870,19 @@ extern "C" {
 
 int gg_version(void) { return GG_VERSION; }
 
+int gg_set_allocator(gg_alloc_fn alloc, gg_free_fn free_fn, void* ctx) {
+  return guard([&]() -> int {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(GG_E_INVAL, "alloc and free must both be set or both null");
+    if (g_live_objects.load() > 0) return fail(GG_E_STATE, "graphs, networks or traces exist");
+    g_alloc_fn = alloc;
+    g_free_fn = free_fn;
+    g_alloc_ctx = ctx;
+    return GG_OK;
+  });
+}
+
+int64_t gg_live_objects(void) { return g_live_objects.load(); }
+
 const char* gg_last_error(void) { return g_err.c_str(); }
 
 int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
@@ -1908,10 +1957,7 @@ int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
     }
     const int nblk = (d->n + kBlock - 1) / kBlock;
     const size_t scratch_bytes = (size_t)(3 * nblk + 2) * sizeof(int32_t) + (size_t)(nblk + 1) * sizeof(int64_t);
-    if (hipMalloc(&g->blk_scratch, scratch_bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      return bail(fail(GG_E_NOMEM, "scratch allocation failed"));
-    }
+    if ((rc = dalloc(&g->blk_scratch, (scratch_bytes + 7) / 8)) != GG_OK) return bail(rc);
     if ((rc = dalloc(&g->outdeg, n)) != GG_OK) return bail(rc);
     if ((rc = dalloc(&g->dang, n)) != GG_OK) return bail(rc);
     hipError_t e = launch_outdeg(g->col, g->m, g->outdeg, g->n, g->stream);
@@ -2092,11 +2138,8 @@ int gg_graph_autotune(gg_graph* g, const gg_app_params* params, double sample_ra
     const gg_correction_policy* pol = policy ? policy : &exact;
     const bool batch = n_queries > 0;
     const size_t elems = (size_t)(g->n > 0 ? g->n : 1) * (size_t)(batch ? n_queries : 1);
-    void* out = nullptr;
-    if (hipMalloc(&out, elems * 4) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(GG_E_NOMEM, "autotune output buffer");
-    }
+    uint32_t* out = nullptr;
+    GG_TRY(dalloc(&out, elems));
     const gg_tuning start = g->tune;
     auto measure = [&](const gg_tuning& t, double* ms) -> int {
       GG_TRY(gg_graph_set_tuning(g, &t));
@@ -2156,7 +2199,7 @@ int gg_graph_autotune(gg_graph* g, const gg_app_params* params, double sample_ra
       }
       if (!moved) break;
     }
-    (void)hipFree(out);
+    dfree(out);
     if (rc != GG_OK) {
       const std::string msg = gg_last_error();
       (void)gg_graph_set_tuning(g, &start);
