@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GG_VERSION 4
+#define GG_VERSION 7
 
 typedef enum {
   GG_OK = 0,
@@ -88,7 +88,9 @@ typedef enum { GG_STEP_APPROX = 0, GG_STEP_ACCURATE = 1, GG_STEP_FULL = 2, GG_ST
 typedef enum { GG_STOP_FIXED_ITERS = 0, GG_STOP_FIXED_POINT = 1 } gg_stop;
 
 /* PageRank edge influence [Alg. 2, GG-Gather]: PREFIX = contribution over the
-   running sum of the row in CSR order; TOTAL = contribution over the row sum. */
+   running sum of the row in CSR order; TOTAL = contribution over the row sum
+   (PR/PPR; its supersteps gather every edge twice, once for the row sums;
+   not with LEARNED: GG_E_UNSUPPORTED). */
 typedef enum { GG_INFL_PREFIX = 0, GG_INFL_TOTAL = 1 } gg_influence;
 
 /* Flag update at a superstep: REPLACE deactivates every edge that does not
@@ -98,6 +100,15 @@ typedef enum { GG_MASK_REPLACE = 0, GG_MASK_UNION = 1 } gg_mask_update;
 /* PageRank mass of vertices without out-edges: spread over all vertices
    (UNIFORM; sent to the source for PPR) or dropped (NONE). */
 typedef enum { GG_DANGLING_UNIFORM = 0, GG_DANGLING_NONE = 1 } gg_dangling;
+
+/* Out-degree PageRank divides by in approximate iterations [Alg. 2,
+   GG-Gather reads v.degree]: the graph's (FULL), or the count of the
+   vertex's active out-edges under the current flags (ACTIVE: PageRank of
+   the sparsified graph, whose vertices without an active out-edge are
+   dangling). Accurate iterations and supersteps always use FULL. ACTIVE is
+   not available with LEARNED, traces, vertex status or graphs with parts
+   (GG_E_UNSUPPORTED). */
+typedef enum { GG_DEGREE_FULL = 0, GG_DEGREE_ACTIVE = 1 } gg_pr_degree;
 
 /* gg_csr_desc.flags */
 #define GG_CSR_DEVICE_PTRS 0x1u /* rowptr/col/weight are device pointers, borrowed (must outlive the graph) */
@@ -132,6 +143,7 @@ typedef struct {
   int32_t max_iters; /* SSSP/CC fixed-point runs: cap on iterations (> 0) */
   int32_t source;    /* SSSP/PPR source vertex */
   int32_t dangling;  /* gg_dangling */
+  int32_t pr_degree; /* gg_pr_degree (PR/PPR) */
 } gg_app_params;
 
 typedef struct gg_mlp gg_mlp;
@@ -155,7 +167,29 @@ typedef struct {
      features of each vertex and its drift label are appended. */
   gg_trace* trace;
   float label_eps;     /* PR/PPR drift label: relative change of the contribution, > 0 */
+  /* GG and LEARNED: decoupled parameters of the first superstep [Sec. 3.4,
+     last paragraph]. decoupled = 1: the first superstep follows alpha0 >= 0
+     approximate iterations (iteration alpha0 + 1) and selects with theta0
+     in [0, 65536); the later ones recur every alpha + 1 iterations after it
+     and select with theta. decoupled = 0: alpha and theta throughout, alpha0
+     and theta0 ignored. Other schemes: decoupled must be 0. */
+  int32_t decoupled;
+  int32_t alpha0;
+  double theta0;
+  /* PR/PPR vertex status [Alg. 2, GG-VStatus] (not with LEARNED, traces or
+     graphs with parts): GG_VSTATUS_NONE processes every row in every
+     iteration; with ABS (REL) a vertex is active after an iteration iff its
+     value moved by more than eps (eps times its previous value), every
+     vertex being active before the first. Approximate iterations after the
+     first then recompute only the rows that an active in-edge from an active
+     vertex reaches (the active-vertex list of the vertex-centric model,
+     Sec. 2.1); the other rows keep their values. Accurate iterations
+     recompute every row. eps >= 0. */
+  int32_t vstatus;
+  double eps;
 } gg_correction_policy;
+
+enum { GG_VSTATUS_NONE = 0, GG_VSTATUS_ABS = 1, GG_VSTATUS_REL = 2 };
 
 typedef struct {
   int32_t iterations;       /* iterations executed */
@@ -331,6 +365,13 @@ int gg_run_begin(gg_graph* g, const gg_app_params* params, double sample_ratio,
 int gg_run_step(gg_run* run, gg_step_info* info);
 int gg_run_values(gg_run* run, void* out_values, uint32_t out_flags);
 int gg_run_mask(gg_run* run, uint32_t* out_bits_host);
+
+/*
+ * Vertex status after the last iteration (GG-VStatus runs; all ones before
+ * the first): one byte per vertex (1 = active) into out_host (n bytes).
+ * GG_E_STATE for runs without vertex status.
+ */
+int gg_run_vstatus(gg_run* run, uint8_t* out_host);
 int gg_run_stats_get(gg_run* run, gg_run_stats* stats);
 /* Per-vertex state of the last correction step (LEARNED) or traced full
    superstep, copied to host memory: features [n][8] bfloat16 bits; the

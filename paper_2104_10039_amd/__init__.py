@@ -53,7 +53,8 @@ class CsrDesc(ctypes.Structure):
 
 class AppParams(ctypes.Structure):
     _fields_ = [("app", ctypes.c_int32), ("damping", ctypes.c_double), ("iters", ctypes.c_int32),
-                ("max_iters", ctypes.c_int32), ("source", ctypes.c_int32), ("dangling", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("source", ctypes.c_int32), ("dangling", ctypes.c_int32),
+                ("pr_degree", ctypes.c_int32)]
 
 
 class Policy(ctypes.Structure):
@@ -61,7 +62,8 @@ class Policy(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("influence", ctypes.c_int32), ("mask_update", ctypes.c_int32),
                 ("stop", ctypes.c_int32), ("mlp", ctypes.c_void_p), ("tau", ctypes.c_float), ("rho", ctypes.c_double),
                 ("fallback_k", ctypes.c_int32), ("audit", ctypes.c_int32), ("trace", ctypes.c_void_p),
-                ("label_eps", ctypes.c_float)]
+                ("label_eps", ctypes.c_float), ("decoupled", ctypes.c_int32), ("alpha0", ctypes.c_int32),
+                ("theta0", ctypes.c_double), ("vstatus", ctypes.c_int32), ("eps", ctypes.c_double)]
 
 
 class RunStats(ctypes.Structure):
@@ -111,6 +113,7 @@ SIGNATURES = {
     "gg_run_step": (ctypes.c_int, [_VP, ctypes.POINTER(StepInfo)]),
     "gg_run_values": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32]),
     "gg_run_mask": (ctypes.c_int, [_VP, _VP]),
+    "gg_run_vstatus": (ctypes.c_int, [_VP, _VP]),
     "gg_run_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(RunStats)]),
     "gg_run_end": (None, [_VP]),
     "gg_graph_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
@@ -277,18 +280,29 @@ def _stats(s: RunStats) -> Stats:
                  s.audit_selected)
 
 
-def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform"):
-    return AppParams(APP[app], damping, iters, max_iters, source, DANGLING[dangling])
+PR_DEGREE = {"full": 0, "active": 1}
+
+
+def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full"):
+    return AppParams(APP[app], damping, iters, max_iters, source, DANGLING[dangling], PR_DEGREE[pr_degree])
 
 
 def _policy(policy="gg", alpha=4, theta=0.05, seed=1, influence="prefix", mask_update="replace",
-            stop="fixed_iters", mlp=None, tau=0.0, rho=1.0, fallback_k=0, audit=False, trace=None, label_eps=1e-3):
+            stop="fixed_iters", mlp=None, tau=0.0, rho=1.0, fallback_k=0, audit=False, trace=None, label_eps=1e-3,
+            alpha0=None, theta0=None, vstatus="none", eps=0.0):
+    """alpha0 / theta0 (either one given): decoupled first-superstep parameters,
+    the other defaulting to alpha / theta. vstatus ("none", "abs", "rel") and
+    eps: GG-VStatus of PR/PPR."""
+    dec = alpha0 is not None or theta0 is not None
     return Policy(POLICY[policy], alpha, theta, seed, INFLUENCE[influence], MASK[mask_update], STOP[stop],
                   None if mlp is None else mlp.handle.value, float(tau), float(rho), int(fallback_k), int(bool(audit)),
-                  None if trace is None else trace.handle.value, float(label_eps))
+                  None if trace is None else trace.handle.value, float(label_eps), int(dec),
+                  int(alpha if alpha0 is None else alpha0), float(theta if theta0 is None else theta0),
+                  VSTATUS[vstatus], float(eps))
 
 
-LEARNED_KW = ("mlp", "tau", "rho", "fallback_k", "audit", "trace", "label_eps")
+VSTATUS = {"none": 0, "abs": 1, "rel": 2}
+POLICY_KW = ("mlp", "tau", "rho", "fallback_k", "audit", "trace", "label_eps", "alpha0", "theta0", "vstatus", "eps")
 
 
 class Graph:
@@ -424,14 +438,16 @@ class Graph:
 
     def approx_run(self, app, sample_ratio, policy="gg", out=None, alpha=4, theta=0.05, seed=1,
                    influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
-                   max_iters=1 << 20, source=0, dangling="uniform", **learned):
+                   max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full", **learned):
         """gg_approx_run: returns (values tensor on the device, Stats). Learned-policy
-        and trace arguments: mlp, tau, rho, fallback_k, audit, trace, label_eps."""
-        bad = set(learned) - set(LEARNED_KW)
+        and trace arguments: mlp, tau, rho, fallback_k, audit, trace, label_eps;
+        decoupled first superstep: alpha0, theta0; vertex status: vstatus, eps;
+        pr_degree "full" or "active"."""
+        bad = set(learned) - set(POLICY_KW)
         if bad:
             raise TypeError("unknown arguments %s" % sorted(bad))
         out = self._out(app, out)
-        p = _app_params(app, damping, iters, max_iters, source, dangling)
+        p = _app_params(app, damping, iters, max_iters, source, dangling, pr_degree)
         pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop, **learned)
         st = RunStats()
         _check(lib().gg_approx_run(self._h, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
@@ -478,14 +494,14 @@ class Run:
 
     def __init__(self, graph: Graph, app, sample_ratio=1.0, policy="exact", alpha=4, theta=0.05, seed=1,
                  influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
-                 max_iters=1 << 20, source=0, dangling="uniform", **learned):
-        bad = set(learned) - set(LEARNED_KW)
+                 max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full", **learned):
+        bad = set(learned) - set(POLICY_KW)
         if bad:
             raise TypeError("unknown arguments %s" % sorted(bad))
         self.graph = graph
         self.app = app
         self._keep = (learned.get("mlp"), learned.get("trace"))  # the run reads them until it ends
-        p = _app_params(app, damping, iters, max_iters, source, dangling)
+        p = _app_params(app, damping, iters, max_iters, source, dangling, pr_degree)
         pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop, **learned)
         h = ctypes.c_void_p()
         _check(lib().gg_run_begin(graph.handle, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
@@ -502,6 +518,12 @@ class Run:
                 "edges": info.edges, "changed": info.changed, "active_edges": info.active_edges,
                 "edges_processed": info.edges_processed, "sparse": bool(info.sparse),
                 "kind": STEP_KIND[info.kind], "selected": info.selected}
+
+    def vstatus(self) -> np.ndarray:
+        """gg_run_vstatus: uint8 [n], 1 for the vertices active after the last iteration."""
+        out = np.zeros(max(self.graph.n, 1), dtype=np.uint8)
+        _check(lib().gg_run_vstatus(self._h, out.ctypes.data))
+        return out[: self.graph.n]
 
     def features(self) -> np.ndarray:
         """[n, 8] bfloat16 bits of the last correction step's features."""

@@ -98,6 +98,17 @@ struct Sweep {
   // chunk counts (count + 1)
   uint32_t* hub_sync;
   int32_t hub_spin;  // polls before a hub chunk's wait gives up (<= 0: at once)
+  // PR/PPR TOTAL influence: row sums of the superstep's contributions (null:
+  // PREFIX, the running sum); sum_out (nullable) receives each applied row's sum
+  const double* row_total;
+  double* sum_out;
+  // PR/PPR GG-VStatus (nullable): the apply compares each row's new value
+  // with x_prev (the previous one, binary32, updated in place) and sets
+  // vact[u] = |x - x_prev| > (vs_rel ? vs_eps * |x_prev| : vs_eps)
+  uint8_t* vact;
+  float* x_prev;
+  double vs_eps;
+  int32_t vs_rel;
 };
 
 // Segmented gather constants.
@@ -217,6 +228,22 @@ hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nf
                        const int32_t* orow, const int32_t* oedge, const int32_t* odst, const uint32_t* bits,
                        uint32_t* stamp, uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc,
                        int32_t* fdeg, int32_t* fscan, int32_t* scan_scratch, int64_t* psum, hipStream_t st);
+
+// GG-VStatus active-vertex list [Alg. 2; Sec. 2.1]: dirty[u] = 1 for every
+// row u that an active in-edge (bit set in bits) from a vertex of front
+// reaches, edge-balanced over the list's out-edges (front_outdeg of them;
+// fdeg: nfront int32, fscan: nfront + 1 int32, scan_scratch as for
+// launch_scan). dirty is not cleared here.
+hipError_t launch_vs_mark(const int32_t* front, int32_t nfront, int64_t front_outdeg, const int32_t* orow,
+                          const int32_t* oedge, const int32_t* odst, const uint32_t* bits, int32_t* fdeg,
+                          int32_t* fscan, int32_t* scan_scratch, uint8_t* dirty, hipStream_t st);
+
+// ACTIVE out-degree of PageRank: odeg[v] = flags set among v's out-edges
+// (edge e's source is col[e]; PR/PPR edge words are the sources).
+hipError_t launch_active_degree(const int32_t* col, int64_t m, const uint32_t* bits, int32_t n, int32_t* odeg,
+                                hipStream_t st);
+// c[v] = x[v] / deg[v] (x[v] when deg[v] = 0), from binary32 values.
+hipError_t launch_recontrib(const float* x, const int32_t* deg, int32_t n, float* c, hipStream_t st);
 
 // ---- independent parts (block-diagonal union) ------------------------------
 // part_of[u] for every vertex; bad |= 1 if an edge crosses parts.

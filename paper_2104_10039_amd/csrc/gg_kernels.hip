@@ -197,6 +197,14 @@ __device__ __forceinline__ void apply_with(const Sweep& s, int u, typename Tr<AP
     const int od = (int)word;
     s.c_out[u] = od > 0 ? (float)(x / (double)od) : (float)x;
     if (s.x_out) s.x_out[u] = (float)x;
+    if (s.sum_out) s.sum_out[u] = acc;
+    if (s.vact) {
+      // GG-VStatus [Alg. 2]: active iff the value moved by more than eps
+      const double xo = (double)s.x_prev[u];
+      const double bound = s.vs_rel ? s.vs_eps * fabs(xo) : s.vs_eps;
+      s.vact[u] = (uint8_t)(fabs(x - xo) > bound);
+      s.x_prev[u] = (float)x;
+    }
   } else {
     const uint32_t old = word;
     const uint32_t nv = min(old, acc);
@@ -384,6 +392,8 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
     const int u = list[t];
     const int b = s.rowptr[u];
     const int len = s.rowptr[u + 1] - b;
+    // TOTAL influence compares with the row sum, PREFIX with the running sum
+    const double rtot = ((APP == kPR || APP == kPPR) && s.row_total) ? s.row_total[u] : -1.0;
     T carry = R::id();
     int carry_cnt = 0;
     // edge words and values of kPreT consecutive team-wide steps are loaded
@@ -419,7 +429,7 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
         const double c = vq[q];
         const double incl = team_scan_add<TEAM>(c, lt);
         const double P = carry + incl;
-        flag = Decide<kPR>::f(s, valid, c, P, oldf);
+        flag = Decide<kPR>::f(s, valid, c, rtot >= 0.0 ? rtot : P, oldf);
         chunk_total = __shfl(incl, TEAM - 1, TEAM);
       } else if constexpr (APP == kSSSP) {
         const uint32_t cand = vq[q];  // INF exactly when the source is unreached
@@ -464,7 +474,7 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
 // the step's total). Writes the new flag bits and returns this thread's flag.
 template <int APP>
 __device__ __forceinline__ bool hub_step(const Sweep& s, int b, int sub, int e1, typename Tr<APP>::T v,
-                                         typename Tr<APP>::T& carry, typename Tr<APP>::T* lds) {
+                                         typename Tr<APP>::T& carry, typename Tr<APP>::T* lds, double rtot) {
   using R = Tr<APP>;
   using T = typename R::T;
   const int lane = __lane_id();
@@ -485,7 +495,7 @@ __device__ __forceinline__ bool hub_step(const Sweep& s, int b, int sub, int e1,
     sub_total = (lds[0] + lds[1]) + (lds[2] + lds[3]);
     __syncthreads();
     const double P = carry + (before + incl_w);
-    flag = Decide<kPR>::f(s, valid, c, P, oldf);
+    flag = Decide<kPR>::f(s, valid, c, rtot >= 0.0 ? rtot : P, oldf);
   } else {
     const uint32_t val = v;  // SSSP: INF exactly when the source is unreached
     const uint32_t incl_w = team_scan_min<64>(val, lane);
@@ -531,6 +541,7 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
   const int len = s.rowptr[u + 1] - b;
   const int e0 = j * s.hub_chunk;
   const int e1 = min(len, e0 + s.hub_chunk);
+  const double rtot = ((APP == kPR || APP == kPPR) && s.row_total) ? s.row_total[u] : -1.0;
 
   auto part = [&](int i) -> T {
     if constexpr (APP == kPR || APP == kPPR) return s.part_f[i];
@@ -559,7 +570,7 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
   for (int q = 0; q < kHubPre; ++q) {
     const int sub = g0 + q * kBlock;
     if (sub >= e1) break;  // uniform over the block
-    const bool flag = hub_step<APP>(s, b, sub, e1, vq[q], carry, lds);
+    const bool flag = hub_step<APP>(s, b, sub, e1, vq[q], carry, lds, rtot);
     cnt += __popcll(__ballot(flag));
   }
   }
@@ -657,6 +668,7 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
   const int len = s.rowptr[u + 1] - b;
   const int e0 = j * s.hub_chunk;
   const int e1 = min(len, e0 + s.hub_chunk);
+  const double rtot = ((APP == kPR || APP == kPPR) && s.row_total) ? s.row_total[u] : -1.0;
   // gather: every edge of the chunk, all loads in flight together, values
   // held in their stored width (binary32 contributions for PR)
   using V = typename GV<APP>::V;
@@ -694,7 +706,7 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
   for (int q = 0; q < kHubPre; ++q) {
     const int sub = e0 + q * kBlock;
     fq[q] = false;
-    if (sub < e1) fq[q] = hub_step<APP>(s, b, sub, e1, GV<APP>::widen(vq[q]), carry, lds);  // uniform over the block
+    if (sub < e1) fq[q] = hub_step<APP>(s, b, sub, e1, GV<APP>::widen(vq[q]), carry, lds, rtot);  // uniform over the block
     const int c = __popcll(__ballot(fq[q]));
     if (lane == 0) s_cnt[q][wid] = c;
   }
@@ -2068,6 +2080,78 @@ __global__ __launch_bounds__(kBlock) void k_push_finalize(Sweep s, const int32_t
 
 constexpr int kFinalizeBlocks = 1024;
 
+// ACTIVE out-degree: odeg[col[e]] += 1 for every edge whose flag is set
+// (odeg cleared beforehand).
+__global__ void k_odeg_act(const int32_t* col, int64_t m, const uint32_t* bits, int32_t* odeg) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    if ((bits[e >> 5] >> (e & 31)) & 1u) atomicAdd(&odeg[col[e]], 1);
+}
+
+// Contributions from binary32 values: c[v] = x[v] / deg[v], or x[v] when deg[v] = 0.
+__global__ void k_recontrib(const float* x, const int32_t* deg, int32_t n, float* c) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) {
+    const int d = deg[v];
+    c[v] = d > 0 ? (float)((double)x[v] / (double)d) : x[v];
+  }
+}
+
+hipError_t launch_active_degree(const int32_t* col, int64_t m, const uint32_t* bits, int32_t n, int32_t* odeg,
+                                hipStream_t st) {
+  hipError_t e = launch_fill_u32((uint32_t*)odeg, n, 0u, st);
+  if (e != hipSuccess || m == 0) return e;
+  const int64_t blocks = (m + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_odeg_act, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kBlock), 0, st, col, m,
+                     bits, odeg);
+  return hipGetLastError();
+}
+
+hipError_t launch_recontrib(const float* x, const int32_t* deg, int32_t n, float* c, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_recontrib, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, x, deg, n, c);
+  return hipGetLastError();
+}
+
+__global__ void k_vs_deg(const int32_t* front, int32_t nfront, const int32_t* orow, int32_t* fdeg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nfront) {
+    const int v = front[i];
+    fdeg[i] = orow[v + 1] - orow[v];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vs_mark(const int32_t* front, int32_t nfront, const int32_t* fscan,
+                                                    const int32_t* orow, const int32_t* oedge, const int32_t* odst,
+                                                    const uint32_t* bits, uint8_t* dirty) {
+  const int64_t total = fscan[nfront];
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < total; k += (int64_t)gridDim.x * kBlock) {
+    int a = 0, hi = nfront - 1;  // last list entry whose first out-edge <= k
+    while (a < hi) {
+      const int mid = (a + hi + 1) >> 1;
+      if (fscan[mid] <= k) a = mid;
+      else hi = mid - 1;
+    }
+    const int v = front[a];
+    const int pos = orow[v] + (int)(k - fscan[a]);
+    const int e = oedge[pos];
+    if ((bits[e >> 5] >> (e & 31)) & 1u) dirty[odst[pos]] = 1;
+  }
+}
+
+hipError_t launch_vs_mark(const int32_t* front, int32_t nfront, int64_t front_outdeg, const int32_t* orow,
+                          const int32_t* oedge, const int32_t* odst, const uint32_t* bits, int32_t* fdeg,
+                          int32_t* fscan, int32_t* scan_scratch, uint8_t* dirty, hipStream_t st) {
+  if (nfront <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vs_deg, dim3((nfront + kBlock - 1) / kBlock), dim3(kBlock), 0, st, front, nfront, orow, fdeg);
+  const hipError_t e = launch_scan(fdeg, fscan, nfront, fscan + nfront, scan_scratch, st);
+  if (e != hipSuccess) return e;
+  if (front_outdeg <= 0) return hipGetLastError();
+  const int64_t blocks = (front_outdeg + kBlock - 1) / kBlock;
+  const int grid = (int)(blocks < 65536 ? blocks : 65536);
+  hipLaunchKernelGGL(k_vs_mark, dim3(grid), dim3(kBlock), 0, st, front, nfront, fscan, orow, oedge, odst, bits, dirty);
+  return hipGetLastError();
+}
+
 hipError_t launch_push(int app, const Sweep& s, const int32_t* front, int32_t nfront, int64_t front_outdeg,
                        const int32_t* orow, const int32_t* oedge, const int32_t* odst, const uint32_t* bits,
                        uint32_t* stamp, uint32_t epoch, int32_t* touched, int32_t* next, FrontCounters* fc,
@@ -2329,6 +2413,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
   int u = 0, lo = 0, len = 0;
   bool mine = false;
   uint32_t word = 0;  // the apply's own read, issued before the gather
+  double rtot = -1.0;  // TOTAL influence: the row sum
   if (tid < P) {
     u = s.flat_list ? s.list[u0 + tid] : u0 + tid;
     lo = s.rowptr[u];
@@ -2336,6 +2421,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
     word = apply_word<APP>(s, u);
     mine = len <= s.small_max;
     if (!mine) len = 0;
+    if ((APP == kPR || APP == kPPR) && s.row_total && mine) rtot = s.row_total[u];
   }
   // exclusive scan of the row lengths
   int x = len;
@@ -2398,7 +2484,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
       if constexpr (APP == kPR || APP == kPPR) {
         const double c = (double)val;
         Psum += c;
-        flag = infl_above(c, Psum, s.theta) || (s.mask_union && oldf);
+        flag = infl_above(c, rtot >= 0.0 ? rtot : Psum, s.theta) || (s.mask_union && oldf);
       } else if constexpr (APP == kSSSP) {
         const uint32_t cand = val;  // INF iff the source is unreached
         if (cand == kInf) {

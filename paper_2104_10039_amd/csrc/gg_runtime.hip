@@ -216,6 +216,16 @@ struct gg_graph {
   uint32_t* hub_sync = nullptr;  // 3 * part_cap + 2: single-pass hub chunk sync (Sweep::hub_sync)
   int64_t part_cap = 0;
   double* dpartial = nullptr;  // 256 dangling partials + [256] = D
+  double* row_sum = nullptr;   // n: row sums for TOTAL influence (first use)
+  // GG-VStatus (first use): vertex status, rows to recompute, previous values
+  uint8_t* vact = nullptr;     // n (+ padding to whole words)
+  uint8_t* vdirty = nullptr;   // n (+ padding)
+  float* x_prev = nullptr;     // n
+  // ACTIVE out-degree (first use): active out-edges per vertex, and the
+  // vertices without one
+  int32_t* odeg_act = nullptr;
+  int32_t* dang_act = nullptr;
+  int32_t n_dang_act = 0;
   int32_t* changed = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   gg_run* active_run = nullptr;
@@ -334,6 +344,11 @@ int rebin(gg_graph* g, Bins& b, const int32_t* cnt, const uint8_t* rowsel = null
     GG_HIP(launch_fill_u32(g->hub_sync, 1, 0u, g->stream));
     return fail(GG_E_DEVICE, "a superstep hub chunk gave up waiting for its row prefix");
   }
+  return GG_OK;
+}
+
+int ensure_selb(gg_graph* g) {
+  if (!g->selb.list) GG_TRY(alloc_bins(g->selb, g->n));
   return GG_OK;
 }
 
@@ -581,6 +596,12 @@ void free_graph(gg_graph* g) {
   dfree(g->part_cnt);
   dfree(g->hub_sync);
   dfree(g->dpartial);
+  dfree(g->row_sum);
+  dfree(g->vact);
+  dfree(g->vdirty);
+  dfree(g->x_prev);
+  dfree(g->odeg_act);
+  dfree(g->dang_act);
   dfree(g->changed);
   dfree(g->seg_off_full);
   dfree(g->seg_off_act);
@@ -636,15 +657,19 @@ bool valid_tuning(const gg_tuning& t) {
 
 // ---- schedule -------------------------------------------------------------
 
-bool is_accurate(const gg_correction_policy& p, int32_t i) {
-  switch (p.kind) {
-    case GG_POLICY_EXACT: return true;
-    case GG_POLICY_SP: return false;
-    case GG_POLICY_SMS: return i >= p.alpha + 1;
-    case GG_POLICY_GG:
-    case GG_POLICY_LEARNED: return (i % (p.alpha + 1)) == 0;
-  }
-  return true;
+// Correction step (superstep) of GG and LEARNED at iteration i, 1-based:
+// every (alpha+1)-th iteration; with decoupled parameters the first is
+// iteration alpha0 + 1 and the later ones recur every alpha+1 iterations
+// after it [Sec. 3.4].
+bool is_correction(const gg_correction_policy& p, int32_t i) {
+  if (!p.decoupled) return (i % (p.alpha + 1)) == 0;
+  const int32_t first = p.alpha0 + 1;
+  return i == first || (i > first && (i - first) % (p.alpha + 1) == 0);
+}
+
+// Influence threshold of the superstep at iteration i.
+double theta_at(const gg_correction_policy& p, int32_t i) {
+  return (p.decoupled && i == p.alpha0 + 1) ? p.theta0 : p.theta;
 }
 
 // Kind of iteration i by the schedule alone (a LEARNED correction step may
@@ -654,7 +679,7 @@ int step_kind(const gg_correction_policy& p, int32_t i) {
     case GG_POLICY_EXACT: return GG_STEP_ACCURATE;
     case GG_POLICY_SP: return GG_STEP_APPROX;
     case GG_POLICY_SMS: return i >= p.alpha + 1 ? GG_STEP_ACCURATE : GG_STEP_APPROX;
-    default: return (i % (p.alpha + 1)) == 0 ? GG_STEP_FULL : GG_STEP_APPROX;
+    default: return is_correction(p, i) ? GG_STEP_FULL : GG_STEP_APPROX;
   }
 }
 
@@ -676,12 +701,35 @@ int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const 
     return fail(GG_E_INVAL, "label_eps must be > 0");
   if (!(sigma >= 0.0 && sigma <= 1.0)) return fail(GG_E_INVAL, "sample_ratio outside [0, 1]");
   if (pol->alpha < 0) return fail(GG_E_INVAL, "alpha < 0");
+  if (pol->decoupled != 0 && pol->decoupled != 1) return fail(GG_E_INVAL, "decoupled must be 0 or 1");
+  if (pol->decoupled) {
+    if (pol->kind != GG_POLICY_GG && pol->kind != GG_POLICY_LEARNED)
+      return fail(GG_E_INVAL, "decoupled parameters belong to GG and LEARNED");
+    if (pol->alpha0 < 0) return fail(GG_E_INVAL, "alpha0 < 0");
+    if (!(pol->theta0 >= 0.0 && pol->theta0 < 65536.0)) return fail(GG_E_INVAL, "theta0 outside [0, 65536)");
+  }
   if (!(pol->theta >= 0.0 && pol->theta < 65536.0)) return fail(GG_E_INVAL, "theta outside [0, 65536)");
   if (pol->mask_update != GG_MASK_REPLACE && pol->mask_update != GG_MASK_UNION)
     return fail(GG_E_INVAL, "unknown mask_update");
   if (pol->stop != GG_STOP_FIXED_ITERS && pol->stop != GG_STOP_FIXED_POINT) return fail(GG_E_INVAL, "unknown stop");
   if (pol->influence != GG_INFL_PREFIX && pol->influence != GG_INFL_TOTAL) return fail(GG_E_INVAL, "unknown influence");
-  if (pol->influence == GG_INFL_TOTAL) return fail(GG_E_UNSUPPORTED, "TOTAL influence is not implemented");
+  if (p->pr_degree != GG_DEGREE_FULL && p->pr_degree != GG_DEGREE_ACTIVE) return fail(GG_E_INVAL, "unknown pr_degree");
+  if (p->pr_degree == GG_DEGREE_ACTIVE) {
+    if (!is_pr(p->app)) return fail(GG_E_INVAL, "the ACTIVE out-degree is defined for PR and PPR");
+    if (pol->kind == GG_POLICY_LEARNED || pol->trace || pol->vstatus != GG_VSTATUS_NONE || g->n_parts > 0)
+      return fail(GG_E_UNSUPPORTED, "ACTIVE out-degree with LEARNED, traces, vertex status or parts");
+  }
+  if (pol->vstatus < GG_VSTATUS_NONE || pol->vstatus > GG_VSTATUS_REL) return fail(GG_E_INVAL, "unknown vstatus");
+  if (pol->vstatus != GG_VSTATUS_NONE) {
+    if (!is_pr(p->app)) return fail(GG_E_INVAL, "vertex status is defined for PR and PPR");
+    if (!(pol->eps >= 0.0) || !std::isfinite(pol->eps)) return fail(GG_E_INVAL, "eps must be finite and >= 0");
+    if (pol->kind == GG_POLICY_LEARNED || pol->trace) return fail(GG_E_UNSUPPORTED, "vertex status with LEARNED or traces");
+    if (g->n_parts > 0) return fail(GG_E_UNSUPPORTED, "vertex status on a graph with parts");
+  }
+  if (pol->influence == GG_INFL_TOTAL) {
+    if (!is_pr(p->app)) return fail(GG_E_INVAL, "TOTAL influence is defined for PR and PPR");
+    if (pol->kind == GG_POLICY_LEARNED) return fail(GG_E_UNSUPPORTED, "TOTAL influence with LEARNED");
+  }
   if (p->dangling != GG_DANGLING_UNIFORM && p->dangling != GG_DANGLING_NONE) return fail(GG_E_INVAL, "unknown dangling");
   if (is_pr(p->app) && !(p->damping >= 0.0 && p->damping < 1.0)) return fail(GG_E_INVAL, "damping outside [0, 1)");
   if (g->n_parts > 0) {
@@ -697,7 +745,7 @@ int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const 
   return GG_OK;
 }
 
-Sweep base_sweep(const gg_graph* g, const gg_run* r) {
+Sweep base_sweep(const gg_graph* g, const gg_run* r, int32_t i) {
   Sweep s;
   std::memset(&s, 0, sizeof(s));
   s.n = g->n;
@@ -716,11 +764,17 @@ Sweep base_sweep(const gg_graph* g, const gg_run* r) {
   s.part_cnt = g->part_cnt;
   s.hub_sync = g->hub_sync;
   s.hub_spin = g->hub_spin;
-  s.theta = r->pol.theta;
-  s.theta_q = (uint64_t)std::floor(r->pol.theta * 65536.0 + 0.5);
+  s.theta = theta_at(r->pol, i);
+  s.theta_q = (uint64_t)std::floor(s.theta * 65536.0 + 0.5);
   s.mask_union = r->pol.mask_update == GG_MASK_UNION;
   s.act_edges = g->act_edges;
   s.act_cnt = g->act_cnt;
+  if (r->pol.vstatus != GG_VSTATUS_NONE) {
+    s.vact = g->vact;
+    s.x_prev = g->x_prev;
+    s.vs_eps = r->pol.eps;
+    s.vs_rel = r->pol.vstatus == GG_VSTATUS_REL;
+  }
   if (g->n_parts > 0) {
     s.part_of = g->part_of;
     s.part_start = g->part_start;
@@ -798,6 +852,26 @@ int pack_from_bits0(gg_graph* g, int app) {
   return rebin_act(g, app);
 }
 
+// PR with the ACTIVE out-degree: approximate iterations divide by it
+bool active_degree_run(const gg_run* r) {
+  return is_pr(r->p.app) && r->p.pr_degree == GG_DEGREE_ACTIVE && r->pol.kind != GG_POLICY_EXACT;
+}
+
+// Active out-degree of the flags in bits[b] and the list of vertices without
+// an active out-edge (the dangling set of the sparsified graph).
+int active_degree(gg_graph* g, int b) {
+  if (!g->odeg_act) GG_TRY(dalloc(&g->odeg_act, (size_t)g->n));
+  if (!g->dang_act) GG_TRY(dalloc(&g->dang_act, (size_t)g->n));
+  if (g->n == 0) {
+    g->n_dang_act = 0;
+    return GG_OK;
+  }
+  GG_HIP(launch_active_degree(g->col, g->m, g->bits[b], g->n, g->odeg_act, g->stream));
+  GG_HIP(launch_dangling_list(g->odeg_act, g->n, g->dang_act, g->i32_scratch + 3, (int32_t*)g->blk_scratch,
+                              g->stream));
+  return readback(g, &g->n_dang_act, g->i32_scratch + 3, sizeof(int32_t));
+}
+
 int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol, gg_run** out) {
   GG_TRY(check_params(g, p, sigma, pol));
   if (g->active_run) return fail(GG_E_STATE, "another run is active on this graph");
@@ -852,8 +926,33 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
       }
     }
   }
+  if (pol->vstatus != GG_VSTATUS_NONE && g->n > 0) {
+    // every vertex is active before the first iteration; previous values x0
+    const size_t words = ((size_t)g->n + 3) / 4;
+    if (!g->vact) GG_TRY(dalloc(&g->vact, words * 4));
+    if (!g->vdirty) GG_TRY(dalloc(&g->vdirty, words * 4));
+    if (!g->x_prev) GG_TRY(dalloc(&g->x_prev, (size_t)g->n));
+    GG_TRY(ensure_out(g));
+    GG_HIP(launch_fill_u32((uint32_t*)g->vact, (int64_t)words, 0x01010101u, g->stream));
+    float x0 = p->app == GG_APP_PR ? (float)(1.0 / (double)g->n) : 0.0f;
+    uint32_t bits0;
+    std::memcpy(&bits0, &x0, 4);
+    GG_HIP(launch_fill_u32((uint32_t*)g->x_prev, g->n, bits0, g->stream));
+    if (p->app == GG_APP_PPR) {
+      const float one = 1.0f;
+      uint32_t b1;
+      std::memcpy(&b1, &one, 4);
+      GG_HIP(launch_fill_u32((uint32_t*)g->x_prev + p->source, 1, b1, g->stream));
+    }
+  }
   // initial sparsification [Sec. 3.4]
   if (pol->kind != GG_POLICY_EXACT) GG_TRY(sample_and_pack(g, app, sigma, pol->seed));
+  if (active_degree_run(r)) {
+    // the first iteration's contributions divide by the active out-degree
+    GG_TRY(active_degree(g, 0));
+    if (step_kind(*pol, 1) == GG_STEP_APPROX)
+      GG_HIP(launch_pr_init(app, g->odeg_act, g->n, p->source, nullptr, nullptr, g->c[0], g->stream));
+  }
   if (pol->kind == GG_POLICY_LEARNED || pol->trace) {
     GG_TRY(ensure_learned(g));
     // the delta features start at 0 (no iteration before iteration 0)
@@ -912,8 +1011,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   // c-1 and c the buffers hold the states of iterations (c-2, c-3) and then
   // (c-1, c-2); each shift moves f3 to f4 and writes the newer delta to f3.
   if ((learned || r->pol.trace) && i >= 2 && g->n > 0) {
-    const int32_t a1 = r->pol.alpha + 1;
-    if (i % a1 == 0 || (i + 1) % a1 == 0) {
+    if (is_correction(r->pol, i) || is_correction(r->pol, i + 1)) {
       const uint32_t* now = pr ? (const uint32_t*)g->c[r->cur] : g->xu[r->cur];
       const uint32_t* before = pr ? (const uint32_t*)g->c[1 - r->cur] : g->xu[1 - r->cur];
       GG_HIP(launch_feat_shift(app, g->n, now, before, g->feat, g->stream));
@@ -932,19 +1030,28 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   }
   const bool last_fixed = (pr || (r->pol.kind != GG_POLICY_EXACT && r->pol.stop == GG_STOP_FIXED_ITERS)) &&
                           i >= r->p.iters;
-  Sweep s = base_sweep(g, r);
+  Sweep s = base_sweep(g, r, i);
+  const bool act_deg = active_degree_run(r);
   if (pr) {
     if (r->p.dangling == GG_DANGLING_UNIFORM) {
+      // with the ACTIVE out-degree an approximate iteration's dangling set is
+      // the vertices without an active out-edge
+      const bool ad = act_deg && kind == GG_STEP_APPROX;
       if (g->n_parts > 0)
         GG_HIP(launch_parts_dangling_sum(g->c[r->cur], g->dang, g->n_parts, g->part_dstart, g->part_dang,
                                          g->part_dang + g->n_parts, g->stream));
       else
-        GG_HIP(launch_dangling_sum(g->c[r->cur], g->dang, nullptr, g->n_dang, g->dpartial, g->dpartial + 256,
-                                   g->stream));
+        GG_HIP(launch_dangling_sum(g->c[r->cur], ad ? g->dang_act : g->dang, nullptr, ad ? g->n_dang_act : g->n_dang,
+                                   g->dpartial, g->dpartial + 256, g->stream));
     }
+    // the apply writes the contributions the next iteration gathers: over the
+    // active out-degree when that iteration is approximate (after a superstep
+    // they are recomputed once the new flags are known)
+    if (act_deg && !superstep && step_kind(r->pol, i + 1) == GG_STEP_APPROX) s.outdeg = g->odeg_act;
     s.c_in = g->c[r->cur];
     s.c_out = g->c[1 - r->cur];
     s.x_out = (r->write_x_each_step || last_fixed) ? g->xout : nullptr;
+    if (act_deg && superstep && step_kind(r->pol, i + 1) == GG_STEP_APPROX) s.x_out = g->xout;
   } else {
     s.x_in = g->xu[r->cur];
     s.x_next = g->xu[1 - r->cur];
@@ -1065,6 +1172,22 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     set_bins(s, g->full);
     s.edges = full_edges(g, app);
     s.cnt = nullptr;
+    if (pr && r->pol.influence == GG_INFL_TOTAL) {
+      // TOTAL influence [Alg. 2, GG-Gather variant]: each edge's contribution
+      // over its row's sum, from an accurate gather before the superstep
+      if (!g->row_sum) GG_TRY(dalloc(&g->row_sum, (size_t)g->n));
+      Sweep st = s;
+      st.sum_out = g->row_sum;
+      GG_TRY(check_part_capacity(g, g->full));
+      if (g->tune.seg_enable) {
+        GG_TRY(check_seg_capacity(g, g->full));
+        set_seg(g, st, g->seg_off_full);
+        GG_HIP(launch_gather_seg(app, g->tune.small_team, st, g->stream));
+      } else {
+        GG_HIP(launch_gather(app, g->tune.small_team, st, g->stream));
+      }
+      s.row_total = g->row_sum;
+    }
     s.old_bits = g->bits[r->bcur];
     s.new_bits = g->bits[1 - r->bcur];
     GG_TRY(check_part_capacity(g, g->full));
@@ -1098,9 +1221,14 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
       r->have_labels = true;
     }
     GG_TRY(rebin_act(g, app, true));  // reads the hub error word too
+    if (act_deg && step_kind(r->pol, i + 1) == GG_STEP_APPROX) {
+      // the next iteration divides by the active out-degree of the new flags
+      GG_TRY(active_degree(g, r->bcur));
+      GG_HIP(launch_recontrib(g->xout, g->odeg_act, g->n, g->c[1 - r->cur], g->stream));
+    }
     r->supersteps++;
     edges = g->m;
-    processed = edges;
+    processed = s.row_total ? 2 * edges : edges;
   } else if (accurate) {
     pkind = 0;
     set_bins(s, g->full);
@@ -1116,6 +1244,33 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     }
     edges = g->m;
     processed = edges;
+  } else if (r->pol.vstatus != GG_VSTATUS_NONE && i > 1 && g->n > 0) {
+    // GG-VStatus [Alg. 2; Sec. 2.1]: only the rows that an active in-edge from
+    // an active vertex reaches are recomputed; the others keep their values
+    // (and become inactive)
+    pkind = 1;
+    GG_HIP(launch_compact_changed(g->vact, g->outdeg, g->n, g->flist[0], g->fc, (int32_t*)g->blk_scratch, g->psum,
+                                  g->stream));
+    FrontCounters h = {0, 0, 0};
+    GG_TRY(readback(g, &h, g->fc, sizeof(h)));
+    const int64_t words = ((int64_t)g->n + 3) / 4;
+    GG_HIP(launch_fill_u32((uint32_t*)g->vdirty, words, 0u, g->stream));
+    GG_HIP(launch_vs_mark(g->flist[0], h.count, h.outdeg_sum, g->orow, g->oedge, g->odst, g->bits[r->bcur], g->fdeg,
+                          g->fscan, (int32_t*)g->blk_scratch, g->vdirty, g->stream));
+    GG_TRY(ensure_selb(g));
+    GG_TRY(rebin(g, g->selb, g->act_cnt, g->vdirty, 1));
+    GG_HIP(launch_copy_u32((const uint32_t*)s.c_in, (uint32_t*)s.c_out, g->n, g->stream));
+    if (s.x_out) GG_HIP(launch_copy_u32((const uint32_t*)g->x_prev, (uint32_t*)s.x_out, g->n, g->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)g->vact, words, 0u, g->stream));
+    set_bins(s, g->selb);
+    s.edges = g->act_edges;
+    s.cnt = g->act_cnt;
+    GG_TRY(check_part_capacity(g, g->selb));
+    if (pe0) GG_HIP(hipEventRecord(pe0, g->stream));
+    GG_HIP(launch_gather(app, g->tune.small_team, s, g->stream));
+    if (pe1) GG_HIP(hipEventRecord(pe1, g->stream));
+    edges = g->selb.h.edges;
+    processed = edges + h.outdeg_sum;
   } else {
     pkind = 1;
     set_bins(s, g->act);
@@ -1298,13 +1453,18 @@ struct StateHeader {
   int32_t alpha, influence, mask_update, stop, iters, max_iters, source, dangling;
   int32_t supersteps, sparse_iters;
   int64_t edges_total, edges_processed;
+  int32_t decoupled, alpha0;
+  double theta0;
 };
 constexpr uint32_t kStateMagic = 0x53524747u;  // "GGRS"
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 
 int state_check_kind(const gg_run* r) {
   if (r->pol.kind == GG_POLICY_LEARNED || r->pol.trace)
     return fail(GG_E_UNSUPPORTED, "run state of LEARNED or traced runs (their delta features span two iterations)");
+  if (r->pol.vstatus != GG_VSTATUS_NONE)
+    return fail(GG_E_UNSUPPORTED, "run state of runs with vertex status (it spans two iterations)");
+  if (active_degree_run(r)) return fail(GG_E_UNSUPPORTED, "run state of runs with the ACTIVE out-degree");
   return GG_OK;
 }
 
@@ -1359,6 +1519,9 @@ int run_export_state(gg_run* r, void* buf, int64_t bytes) {
   h.sparse_iters = r->sparse_iters;
   h.edges_total = r->edges_total;
   h.edges_processed = r->edges_processed;
+  h.decoupled = r->pol.decoupled;
+  h.alpha0 = r->pol.alpha0;
+  h.theta0 = r->pol.theta0;
   char* p = (char*)buf;
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
@@ -1386,7 +1549,9 @@ int run_import_state(gg_run* r, const void* buf, int64_t bytes) {
                     h.m == g->m && h.sigma == r->sigma && h.theta == r->pol.theta && h.damping == r->p.damping &&
                     h.seed == r->pol.seed && h.alpha == r->pol.alpha && h.influence == r->pol.influence &&
                     h.mask_update == r->pol.mask_update && h.stop == r->pol.stop && h.iters == r->p.iters &&
-                    h.max_iters == r->p.max_iters && h.source == r->p.source && h.dangling == r->p.dangling;
+                    h.max_iters == r->p.max_iters && h.source == r->p.source && h.dangling == r->p.dangling &&
+                    h.decoupled == r->pol.decoupled &&
+                    (!h.decoupled || (h.alpha0 == r->pol.alpha0 && h.theta0 == r->pol.theta0));
   if (!same) return fail(GG_E_INVAL, "state was exported from a run with another graph shape, app, parameters or policy");
   const bool has_x = h.has_x != 0;
   if (has_x && !is_pr(r->p.app)) return fail(GG_E_INVAL, "state holds PR values for a min-type app");
@@ -1686,6 +1851,7 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
               const gg_correction_policy* pol, void* out, uint32_t flags, gg_run_stats* st) {
   if (!g || !p || !pol || !sources || !out) return fail(GG_E_INVAL, "null argument");
   if (p->app != GG_APP_PPR && p->app != GG_APP_SSSP) return fail(GG_E_UNSUPPORTED, "batch runs support PPR and SSSP");
+  if (pol->decoupled) return fail(GG_E_INVAL, "decoupled parameters belong to GG and LEARNED");
   if (pol->kind != GG_POLICY_EXACT && pol->kind != GG_POLICY_SP && pol->kind != GG_POLICY_SMS)
     return fail(GG_E_UNSUPPORTED, "batch runs support the EXACT, SP and SMS schemes");
   if (pol->kind == GG_POLICY_SMS && pol->alpha < 0) return fail(GG_E_INVAL, "alpha < 0");
@@ -2274,6 +2440,16 @@ int gg_run_mask(gg_run* run, uint32_t* out_bits_host) {
     if (nw == 0) return GG_OK;
     GG_TRY(check_hub_sync(g));
     return copy_out(g, g->bits[run->bcur], out_bits_host, nw * sizeof(uint32_t), GG_OUT_HOST);
+  });
+}
+
+int gg_run_vstatus(gg_run* run, uint8_t* out_host) {
+  return guard([&]() -> int {
+    if (!run || !out_host) return fail(GG_E_INVAL, "null argument");
+    if (run->pol.vstatus == GG_VSTATUS_NONE) return fail(GG_E_STATE, "the run has no vertex status");
+    gg_graph* g = run->g;
+    if (g->n == 0) return GG_OK;
+    return copy_out(g, g->vact, out_host, (size_t)g->n, GG_OUT_HOST);
   });
 }
 

@@ -15,6 +15,10 @@ PR_TOL = 1e-6  # relative L1, FP32 GPU against the FP64 oracle
 # its binary64 iterate. Contributions then differ by about one binary32 ulp
 # (6e-8 relative), far inside the band.
 REPLAY_BAND = 1e-4
+# Vertex-status replay band (GG-VStatus): a vertex's status may differ only
+# when the oracle's |x_new - x_old| lies within this many times the larger of
+# the two values of the bound; the GPU's iterate is binary32 (6e-8 relative).
+VSTATUS_BAND = 1e-6
 
 
 def log(*a):
@@ -155,6 +159,9 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
     assert np.array_equal(R.mask(), O.mask()) or policy == "exact", "initial sample differs"
     worst = 0.0
     flips_total = 0
+    vflips_total = 0
+    vs = kw.get("vstatus", "none")
+    ov_prev = O.values() if vs != "none" else None
     while True:
         a = R.step()
         b = O.step()
@@ -194,9 +201,28 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
         if app in ("pr", "ppr"):
             worst = max(worst, rel_l1(gv, ov))
         compare_values(app, gv, ov, ctx="iter %d" % b.iter)
+        if vs != "none":
+            # vertex status: equal except within the band of its bound, where
+            # the oracle adopts the GPU's status (replay)
+            ga, oa = R.vstatus(), O.vactive()
+            diff = np.nonzero(ga != oa)[0]
+            if diff.size:
+                eps = kw.get("eps", 0.0)
+                delta = np.abs(ov - ov_prev)
+                bound = eps if vs == "abs" else eps * np.abs(ov_prev)
+                bound = np.broadcast_to(bound, delta.shape)
+                scale = np.maximum(np.abs(ov), np.abs(ov_prev))
+                far = diff[np.abs(delta[diff] - bound[diff]) > VSTATUS_BAND * scale[diff]]
+                assert far.size == 0, "vertex status differs away from its bound at %s" % far[:5].tolist()
+                O.set_vactive(ga)
+                vflips_total += int(diff.size)
+            ov_prev = ov
     log("replay: %d PageRank flags adopted from the GPU over the run" % flips_total)
+    if vs != "none":
+        log("replay: %d vertex statuses adopted from the GPU over the run" % vflips_total)
     if stats is not None:
         stats["flips"] = flips_total
+        stats["vflips"] = vflips_total
     R.close()
     O.close()
     G.close()

@@ -149,6 +149,127 @@ def test_int_steps_rmat14(P, app, ti):
                  iters=25)
 
 
+@pytest.mark.parametrize("ti", [0, 2, 3])
+@pytest.mark.parametrize("app", ["pr", "ppr", "sssp", "cc"])
+def test_decoupled_first_superstep_steps(P, app, ti):
+    """Decoupled parameters [Sec. 3.4, last paragraph]: the first superstep
+    after alpha0 approximate iterations with theta0, later ones every alpha+1
+    iterations with theta; compared with the oracle after every iteration."""
+    g = graph_for(app if app != "ppr" else "pr", 14, seed=5)
+    s = int(gg.pick_sources(g, 1, 5)[0])
+    if app in ("pr", "ppr"):
+        kw = dict(alpha=3, theta=0.2, alpha0=1, theta0=0.01, iters=20)
+    else:
+        kw = dict(alpha=4, theta=0.05, alpha0=2, theta0=0.5, iters=25)
+    step_compare(P, g, app, "gg", tuning=TUNINGS[ti], sample_ratio=0.3, seed=3, source=s, **kw)
+
+
+@pytest.mark.parametrize("ti", [0, 2, 3])
+@pytest.mark.parametrize("app", ["pr", "ppr"])
+def test_total_influence_steps(P, app, ti):
+    """TOTAL influence (each edge's contribution over its row's sum) step by
+    step against the oracle, flags with the replay check."""
+    g = graph_for("pr", 14, seed=6)
+    s = int(gg.pick_sources(g, 1, 6)[0])
+    st = {}
+    step_compare(P, g, app, "gg", tuning=TUNINGS[ti], stats=st, sample_ratio=0.3, alpha=3, theta=0.02, seed=2,
+                 source=s, iters=20, influence="total")
+    log("TOTAL %s tuning %d: %d flags adopted" % (app, ti, st["flips"]))
+
+
+def test_total_influence_unsupported_with_learned(P):
+    g = graph_for("pr", 8, seed=6)
+    G = P.Graph.from_host(g)
+    net = P.Mlp()
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("pr", 0.5, "learned", influence="total", mlp=net, tau=0.0)
+    assert ei.value.code == -5
+    net.close()
+    G.close()
+
+
+@pytest.mark.parametrize("policy,vs,eps", [("gg", "abs", 1e-7), ("gg", "rel", 0.01), ("sp", "rel", 0.03),
+                                            ("sms", "abs", 2e-8)])
+@pytest.mark.parametrize("app", ["pr", "ppr"])
+def test_vstatus_steps(P, app, policy, vs, eps):
+    """GG-VStatus [Alg. 2]: approximate iterations after the first recompute
+    only rows reached by an active in-edge from an active vertex; step by
+    step against the oracle, vertex statuses and edge flags with the replay
+    check (R-MAT 14, n = 16384: 1/n = 6.1e-5)."""
+    g = graph_for("pr", 14, seed=7)
+    s = int(gg.pick_sources(g, 1, 7)[0])
+    st = {}
+    step_compare(P, g, app, policy, stats=st, sample_ratio=0.4, alpha=3, theta=0.05, seed=4, source=s, iters=20,
+                 vstatus=vs, eps=eps)
+    # the rows skipped by the vertex status show in the edges gathered
+    G = P.Graph.from_host(g)
+    kw = dict(alpha=3, theta=0.05, seed=4, source=s, iters=20)
+    _, with_vs = G.approx_run(app, 0.4, policy, vstatus=vs, eps=eps, **kw)
+    _, without = G.approx_run(app, 0.4, policy, **kw)
+    G.close()
+    log("VStatus %s %s %s eps %g: %d statuses, %d flags adopted; edges %d of %d" % (
+        app, policy, vs, eps, st["vflips"], st["flips"], with_vs.edges_gathered, without.edges_gathered))
+    assert with_vs.edges_gathered < without.edges_gathered
+
+
+def test_vstatus_rejects(P):
+    g = graph_for("sssp", 8, seed=7)
+    G = P.Graph.from_host(g)
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("sssp", 0.5, "gg", source=1, vstatus="abs", eps=1.0)
+    assert ei.value.code == -1
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("pr", 0.5, "gg", vstatus="rel", eps=-1.0)
+    assert ei.value.code == -1
+    net = P.Mlp()
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("pr", 0.5, "learned", mlp=net, vstatus="abs", eps=1e-6)
+    assert ei.value.code == -5
+    net.close()
+    R = G.begin("pr", 0.5, "gg")
+    with pytest.raises(P.GGError) as ei:
+        R.vstatus()
+    assert ei.value.code == -6
+    R.close()
+    G.close()
+
+
+@pytest.mark.parametrize("ti", [0, 3])
+@pytest.mark.parametrize("policy,dangling", [("gg", "uniform"), ("sp", "uniform"), ("sms", "none")])
+@pytest.mark.parametrize("app", ["pr", "ppr"])
+def test_active_degree_steps(P, app, policy, dangling, ti):
+    """ACTIVE out-degree (PageRank of the sparsified graph in approximate
+    iterations, vertices without an active out-edge dangling) step by step
+    against the oracle."""
+    g = graph_for("pr", 14, seed=8)
+    s = int(gg.pick_sources(g, 1, 8)[0])
+    step_compare(P, g, app, policy, tuning=TUNINGS[ti], sample_ratio=0.3, alpha=3, theta=0.05, seed=5, source=s,
+                 iters=16, pr_degree="active", dangling=dangling)
+
+
+def test_active_degree_rejects(P):
+    g = graph_for("sssp", 8, seed=8)
+    G = P.Graph.from_host(g)
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("sssp", 0.5, "gg", source=1, pr_degree="active")
+    assert ei.value.code == -1
+    with pytest.raises(P.GGError) as ei:
+        G.approx_run("pr", 0.5, "gg", pr_degree="active", vstatus="abs", eps=1e-6)
+    assert ei.value.code == -5
+    G.close()
+
+
+def test_decoupled_rejects_bad_parameters(P):
+    g = graph_for("pr", 8, seed=5)
+    G = P.Graph.from_host(g)
+    for kw in (dict(alpha0=-1), dict(theta0=-0.5), dict(theta0=70000.0)):
+        with pytest.raises(P.GGError):
+            G.approx_run("pr", 0.5, "gg", **kw)
+    with pytest.raises(P.GGError):
+        G.approx_run("pr", 0.5, "sms", alpha0=2)  # decoupled parameters belong to GG and LEARNED
+    G.close()
+
+
 # ---------------------------------------------------------------------------
 # Edge cases
 # ---------------------------------------------------------------------------
@@ -260,8 +381,8 @@ def test_abi_errors(P):
         G.exact_run("sssp", source=0)  # no weights
     assert ei.value.code == -1
     with pytest.raises(P.GGError) as ei:
-        G.approx_run("pr", 0.5, "gg", influence="total")
-    assert ei.value.code == -5
+        G.approx_run("cc", 0.5, "gg", influence="total")  # TOTAL is a PageRank influence
+    assert ei.value.code == -1
     # outputs untouched on failure
     out = torch.full((g.n,), 7.0, device="cuda")
     with pytest.raises(P.GGError):
