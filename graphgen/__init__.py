@@ -43,6 +43,8 @@ def _lib():
     i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
     lib.graphgen_draw.restype = ctypes.c_uint64
     lib.graphgen_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
+    lib.graphgen_draws.restype = None
+    lib.graphgen_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_void_p]
     lib.graphgen_rmat_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_uint64, i32p, i32p]
     lib.graphgen_er_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, i32p, i32p]
@@ -200,6 +202,23 @@ def pick_sources(g: Graph, count: int, seed: int) -> np.ndarray:
     if got < count:
         raise ValueError("graph has no vertex with out-degree > 0")
     return out[:count].copy()
+
+
+def bp_prior(n: int, seed: int, labeled: float = 0.1) -> np.ndarray:
+    """Prior log-odds of a belief-propagation workload, float32 [n]: a
+    fraction `labeled` of the vertices carries evidence (probability 0.9 or
+    0.1 of state 1, equally likely), the others a nearly uninformative
+    probability in [0.45, 0.55]. Uses the generator's own counter-based
+    draws: vertex u takes draw(seed, u, 0) and draw(seed, u, 1)."""
+    u1 = np.empty(max(n, 1), dtype=np.uint64)
+    u2 = np.empty(max(n, 1), dtype=np.uint64)
+    _lib().graphgen_draws(seed, 0, n, u1.ctypes.data)
+    _lib().graphgen_draws(seed, 1, n, u2.ctypes.data)
+    u1, u2 = u1[:n], u2[:n]
+    a = (u1 >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    b = (u2 >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    p = np.where(a < labeled, np.where(b < 0.5, 0.9, 0.1), 0.45 + 0.1 * b)
+    return (np.log(p) - np.log1p(-p)).astype(np.float32)
 
 
 def draw(seed: int, k: int, l: int = 0) -> int:

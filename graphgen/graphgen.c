@@ -45,6 +45,11 @@ static inline uint64_t mulshift(uint64_t x, uint64_t n) {
 
 uint64_t graphgen_draw(uint64_t seed, uint64_t k, uint32_t l) { return draw(seed, k, l); }
 
+/* out[k] = draw(seed, k, l) for k in [0, count). */
+void graphgen_draws(uint64_t seed, uint32_t l, int64_t count, uint64_t* out) {
+  for (int64_t k = 0; k < count; ++k) out[k] = draw(seed, (uint64_t)k, l);
+}
+
 /* R-MAT edge list: m pairs on n = 2^scale vertices (ids before permutation). */
 void graphgen_rmat_edges(int32_t scale, int64_t m, double a, double b, double c, uint64_t seed,
                          int32_t* src, int32_t* dst) {

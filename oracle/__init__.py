@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # copies of the oracle with one planted mistake); build() leaves it alone.
 _LIB_OVERRIDE = os.environ.get("GGO_ORACLE_LIB")
 
-PR, SSSP, CC, PPR = 0, 1, 2, 3
+PR, SSSP, CC, PPR, BP = 0, 1, 2, 3, 4
 EXACT, SP, SMS, GG, LEARNED = 0, 1, 2, 3, 4
 KIND_APPROX, KIND_ACCURATE, KIND_FULL, KIND_PARTIAL = 0, 1, 2, 3
 MLP_IN, MLP_HIDDEN = 8, 64
@@ -43,7 +43,7 @@ DEGREE_FULL, DEGREE_ACTIVE = 0, 1
 VSTATUS_NONE, VSTATUS_ABS, VSTATUS_REL = 0, 1, 2
 INF = 0xFFFFFFFF
 
-APP_NAMES = {"pr": PR, "sssp": SSSP, "cc": CC, "ppr": PPR}
+APP_NAMES = {"pr": PR, "sssp": SSSP, "cc": CC, "ppr": PPR, "bp": BP}
 POLICY_NAMES = {"exact": EXACT, "sp": SP, "sms": SMS, "gg": GG, "learned": LEARNED}
 
 
@@ -67,7 +67,7 @@ class _Csr(ctypes.Structure):
 class _App(ctypes.Structure):
     _fields_ = [("app", ctypes.c_int32), ("damping", ctypes.c_double), ("iters", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("source", ctypes.c_int32), ("dangling", ctypes.c_int32),
-                ("pr_degree", ctypes.c_int32)]
+                ("pr_degree", ctypes.c_int32), ("coupling", ctypes.c_double), ("prior", ctypes.c_void_p)]
 
 
 class _Pol(ctypes.Structure):
@@ -118,6 +118,8 @@ def _lib():
     lib.ggo_bf16_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
     lib.ggo_bf16_value.restype = ctypes.c_float
     lib.ggo_bf16_value.argtypes = [ctypes.c_uint16]
+    lib.ggo_bp_message.restype = ctypes.c_double
+    lib.ggo_bp_message.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.ggo_lg_feature.restype = ctypes.c_float
     lib.ggo_lg_feature.argtypes = [ctypes.c_int64]
     lib.ggo_delta_feature.restype = ctypes.c_float
@@ -175,7 +177,7 @@ class Run:
                  damping=0.85, iters=20, max_iters=100000, source=0, dangling=DANGLING_UNIFORM,
                  influence=INFL_PREFIX, mask_update=MASK_REPLACE, stop=FIXED_ITERS, mlp=None, tau=0.0,
                  rho=1.0, fallback_k=0, trace=False, label_eps=1e-3, pr_degree=DEGREE_FULL, alpha0=None,
-                 theta0=None, vstatus=VSTATUS_NONE, eps=0.0):
+                 theta0=None, vstatus=VSTATUS_NONE, eps=0.0, coupling=0.0, prior=None):
         self._lib = _lib()
         self.app = APP_NAMES[app] if isinstance(app, str) else int(app)
         kind = POLICY_NAMES[policy] if isinstance(policy, str) else int(policy)
@@ -186,7 +188,12 @@ class Run:
         self._w = None if g.weight is None else np.ascontiguousarray(g.weight, dtype=np.int32)
         csr = _Csr(self.n, self.m, self._rowptr.ctypes.data, self._col.ctypes.data,
                    None if self._w is None else self._w.ctypes.data)
-        ap = _App(self.app, damping, iters, max_iters, source, dangling, pr_degree)
+        # BP: prior log-odds (binary64, one per vertex) and edge coupling
+        self._prior = None if prior is None else np.ascontiguousarray(prior, dtype=np.float64)
+        if self._prior is not None and self._prior.size != self.n:
+            raise ValueError("prior needs %d entries" % self.n)
+        ap = _App(self.app, damping, iters, max_iters, source, dangling, pr_degree, coupling,
+                  None if self._prior is None or self.n == 0 else self._prior.ctypes.data)
         self._mlp = None if mlp is None else np.ascontiguousarray(mlp, dtype=np.float64)
         if self._mlp is not None and self._mlp.size != MLP_PARAMS:
             raise ValueError("mlp needs %d parameters" % MLP_PARAMS)
@@ -218,7 +225,7 @@ class Run:
         return int(self._lib.ggo_edges_total(self._h))
 
     def values(self) -> np.ndarray:
-        dt = {PR: np.float64, PPR: np.float64, SSSP: np.uint32, CC: np.int32}[self.app]
+        dt = {PR: np.float64, PPR: np.float64, BP: np.float64, SSSP: np.uint32, CC: np.int32}[self.app]
         out = np.empty(self.n, dtype=dt)
         self._lib.ggo_get_values(self._h, out.ctypes.data)
         return out
@@ -360,3 +367,8 @@ def adam_step(params, m, v, grad, lr, t):
     g = np.ascontiguousarray(grad, dtype=np.float64)
     _lib().ggo_adam_step(params.ctypes.data, m.ctypes.data, v.ctypes.data, g.ctypes.data, params.size, float(lr),
                          int(t))
+
+
+def bp_message(L, coupling):
+    """The oracle's BP message log-ratio of a sender with log-odds L."""
+    return float(_lib().ggo_bp_message(float(L), float(coupling)))

@@ -42,6 +42,17 @@
  *    approximate runs either run a fixed number of iterations or stop after a
  *    no-change iteration that no later iteration can follow differently.
  *
+ * Belief propagation [Sec. 4.1 lists it; the paper defines neither its
+ * potentials nor its messages]: the reading taken is a binary pairwise
+ * Markov random field with a homophily coupling and per-vertex priors.
+ * A vertex's value is the log-odds of its belief; each iteration every
+ * in-neighbour v sends the message m(x) = sum_y psi(x, y) b_v(y), built from
+ * v's current belief, and the new log-odds are the prior plus the sum of
+ * the log-ratios log(m(1) / m(0)) over the row's edge set. Influence of an
+ * edge at a superstep: the magnitude of its (binary32-rounded) log-ratio
+ * over the magnitude of the row's running sum, in CSR order [Alg. 2 with
+ * magnitudes, since log-ratios take both signs].
+ *
  * Variants the paper mentions without fixing them (each a flag):
  *  - Decoupled parameters: the first superstep after alpha0 approximate
  *    iterations with threshold theta0, later ones every alpha+1 iterations
@@ -387,6 +398,12 @@ static uint32_t state_word(const ggo_run* r, int32_t u) {
       memcpy(&w, &c, 4);
       return w;
     }
+    case GGO_BP: {
+      const float c = (float)ggo_bp_message(r->pr_x[u], r->app.coupling);
+      uint32_t w;
+      memcpy(&w, &c, 4);
+      return w;
+    }
     case GGO_SSSP: return r->d_x[u];
     default: return (uint32_t)r->l_x[u];
   }
@@ -400,7 +417,18 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
     if (g->rowptr[u + 1] < g->rowptr[u]) { set_err("rowptr not monotone"); return NULL; }
   for (int64_t e = 0; e < g->m; ++e)
     if (g->col[e] < 0 || g->col[e] >= g->n) { set_err("col out of range"); return NULL; }
-  if (app->app < GGO_PR || app->app > GGO_PPR) { set_err("bad app"); return NULL; }
+  if (app->app < GGO_PR || app->app > GGO_BP) { set_err("bad app"); return NULL; }
+  if (app->app == GGO_BP) {
+    if (!app->prior || !(app->coupling >= 0.0 && app->coupling < 1.0)) {
+      set_err("BP needs priors and a coupling in [0, 1)");
+      return NULL;
+    }
+    if (pol->kind == GGO_LEARNED || pol->trace || pol->vstatus != GGO_VSTATUS_NONE ||
+        app->pr_degree != GGO_DEGREE_FULL) {
+      set_err("BP runs EXACT, SP, SMS or GG without traces, vertex status or ACTIVE degree");
+      return NULL;
+    }
+  }
   if (pol->kind < GGO_EXACT || pol->kind > GGO_LEARNED) { set_err("bad policy"); return NULL; }
   if (pol->alpha < 0 || !(pol->theta >= 0) || !(pol->sigma >= 0 && pol->sigma <= 1)) {
     set_err("bad alpha/theta/sigma");
@@ -479,6 +507,13 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
       else
         r->pr_x[app->source] = 1.0;
       break;
+    case GGO_BP:
+      /* every belief starts at its prior */
+      r->pr_x = (double*)calloc((size_t)n + 1, sizeof(double));
+      r->pr_xn = (double*)calloc((size_t)n + 1, sizeof(double));
+      r->pr_sh = (double*)calloc((size_t)n + 1, sizeof(double));
+      for (int32_t u = 0; u < n; ++u) r->pr_x[u] = app->prior[u];
+      break;
     case GGO_SSSP:
       r->d_x = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)n + 1));
       r->d_xn = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)n + 1));
@@ -494,7 +529,7 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
       break;
   }
   r->iter = 0;
-  r->done = (app->app == GGO_PR || app->app == GGO_PPR || pol->stop == GGO_STOP_FIXED_ITERS) &&
+  r->done = (app->app == GGO_PR || app->app == GGO_PPR || app->app == GGO_BP || pol->stop == GGO_STOP_FIXED_ITERS) &&
             app->iters <= 0;
   return r;
 }
@@ -560,6 +595,53 @@ static void pass_pr(ggo_run* r, const uint8_t* mode, const int32_t* deg, const u
       xn = (u == s ? (1.0 - d) : 0.0) + d * (sum + (u == s ? D : 0.0));
     else
       xn = (1.0 - d) / n + d * (sum + D / n);
+    if (xn != r->pr_x[u]) ++changed;
+    out[u] = xn;
+  }
+  *edges_out = edges;
+  *changed_out = changed;
+}
+
+/* BP message log-ratio of a sender with log-odds L: its belief is
+   b(1) = 1 / (1 + e^-L), b(0) = 1 / (1 + e^L), and the message
+   m(x) = psi(x, 1) b(1) + psi(x, 0) b(0). */
+double ggo_bp_message(double L, double coupling) {
+  const double b1 = 1.0 / (1.0 + exp(-L));
+  const double b0 = 1.0 / (1.0 + exp(L));
+  const double same = (1.0 + coupling) / 2.0, diff = (1.0 - coupling) / 2.0;
+  const double m1 = same * b1 + diff * b0;
+  const double m0 = diff * b1 + same * b0;
+  return log(m1) - log(m0);
+}
+
+/* ---------------------------------------------------------------------------
+ * One BP pass: new log-odds = prior + sum over the edge set of the senders'
+ * message log-ratios. For a SUPER row the influence of each edge is the
+ * magnitude of its binary32-rounded log-ratio over the magnitude of the
+ * running sum (in CSR order, including the edge).
+ * ------------------------------------------------------------------------- */
+static void pass_bp(ggo_run* r, const uint8_t* mode, double* out, int64_t* edges_out, int64_t* changed_out) {
+  const ggo_csr* g = &r->g;
+  const int32_t n = g->n;
+  const double kappa = r->app.coupling;
+  int64_t edges = 0, changed = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    double sum = 0.0;
+    const int32_t b = g->rowptr[u], e_end = g->rowptr[u + 1];
+    for (int32_t e = b; e < e_end; ++e) {
+      if (mode[u] == ROW_APPROX && !r->active[e]) continue;
+      sum += ggo_bp_message(r->pr_x[g->col[e]], kappa);
+      ++edges;
+    }
+    if (mode[u] == ROW_SUPER) {
+      double P = 0.0;
+      for (int32_t e = b; e < e_end; ++e) {
+        const double c = (double)(float)ggo_bp_message(r->pr_x[g->col[e]], kappa);
+        P += c;
+        r->infl[e] = fabs(P) > 0.0 ? fabs(c) / fabs(P) : 0.0;
+      }
+    }
+    const double xn = r->app.prior[u] + sum;
     if (xn != r->pr_x[u]) ++changed;
     out[u] = xn;
   }
@@ -726,6 +808,7 @@ static void run_pass(ggo_run* r, const uint8_t* mode, int shadow, int64_t* edges
   switch (r->app.app) {
     case GGO_PR:
     case GGO_PPR: pass_pr(r, mode, r->outdeg, NULL, shadow ? r->pr_sh : r->pr_xn, edges, changed); break;
+    case GGO_BP: pass_bp(r, mode, shadow ? r->pr_sh : r->pr_xn, edges, changed); break;
     case GGO_SSSP: pass_sssp(r, mode, shadow ? r->d_sh : r->d_xn, edges, changed); break;
     case GGO_CC: pass_cc(r, mode, shadow ? r->l_sh : r->l_xn, edges, changed); break;
   }
@@ -862,7 +945,8 @@ int ggo_step(ggo_run* r, ggo_step_info* info) {
   }
   switch (r->app.app) {
     case GGO_PR:
-    case GGO_PPR: {
+    case GGO_PPR:
+    case GGO_BP: {
       double* t = r->pr_x;
       r->pr_x = r->pr_xn;
       r->pr_xn = t;
@@ -896,7 +980,7 @@ int ggo_step(ggo_run* r, ggo_step_info* info) {
 
   /* Termination. */
   const int app = r->app.app;
-  if (app == GGO_PR || app == GGO_PPR) {
+  if (app == GGO_PR || app == GGO_PPR || app == GGO_BP) {
     if (i >= r->app.iters) r->done = 1;
   } else if (p->kind == GGO_EXACT) {
     if (changed == 0 || i >= r->app.max_iters) r->done = 1;
@@ -920,7 +1004,8 @@ void ggo_get_values(const ggo_run* r, void* out) {
   const size_t n = (size_t)r->g.n;
   switch (r->app.app) {
     case GGO_PR:
-    case GGO_PPR: memcpy(out, r->pr_x, n * sizeof(double)); break;
+    case GGO_PPR:
+    case GGO_BP: memcpy(out, r->pr_x, n * sizeof(double)); break;
     case GGO_SSSP: memcpy(out, r->d_x, n * sizeof(uint32_t)); break;
     case GGO_CC: memcpy(out, r->l_x, n * sizeof(int32_t)); break;
   }

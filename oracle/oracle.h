@@ -23,7 +23,17 @@
 extern "C" {
 #endif
 
-enum { GGO_PR = 0, GGO_SSSP = 1, GGO_CC = 2, GGO_PPR = 3 };
+enum { GGO_PR = 0, GGO_SSSP = 1, GGO_CC = 2, GGO_PPR = 3, GGO_BP = 4 };
+/* BP (belief propagation, Sec. 4.1, whose model the paper does not give):
+   a pairwise binary Markov random field on the graph. Vertex u has prior
+   log-odds prior[u]; every edge v -> u couples the two endpoints with the
+   potential psi(x, y) = (1 + coupling) / 2 if x == y, (1 - coupling) / 2
+   otherwise, 0 <= coupling < 1. Each iteration, in the vertex-centric pull
+   model, v sends u the message m(x) = sum_y psi(x, y) b_v(y) built from its
+   current belief b_v (no exclusion of u's own message), and u's new belief
+   is its prior times the product of its incoming messages. The value of a
+   vertex is the log-odds of its belief; the gather sums the log-ratios
+   log(m(1) / m(0)) over the row's edge set. */
 /* Correction schemes: EXACT = accurate mode every iteration (the baseline of
    Sec. 5); SP = sparsified only; SMS = static mode switch; GG = adaptive
    correction with periodic supersteps (Sec. 3.4, Sec. 5.2). */
@@ -77,6 +87,8 @@ typedef struct {
   int32_t source;     /* SSSP/PPR source */
   int32_t dangling;   /* GGO_DANGLING_* */
   int32_t pr_degree;  /* GGO_DEGREE_* (PR/PPR) */
+  double coupling;    /* BP: edge coupling in [0, 1) */
+  const double* prior;/* BP: n prior log-odds */
 } ggo_app_params;
 
 typedef struct {
@@ -132,11 +144,15 @@ int ggo_step(ggo_run* r, ggo_step_info* info);
 int ggo_done(const ggo_run* r);
 int32_t ggo_iterations(const ggo_run* r);
 int64_t ggo_edges_total(const ggo_run* r);
-/* PR/PPR: double[n]; SSSP: uint32[n]; CC: int32[n]. */
+/* PR/PPR: double[n]; BP: double[n] log-odds; SSSP: uint32[n]; CC: int32[n]. */
 void ggo_get_values(const ggo_run* r, void* out);
 /* One byte per edge: current active flag. */
 void ggo_get_mask(const ggo_run* r, uint8_t* out);
-/* Per-edge influence computed at the last superstep (PR: the ratio; SSSP:
+/* BP message of a sender with belief log-odds L: log(m(1) / m(0)), from
+   the definition m(x) = sum_y psi(x, y) b(y); exposed for the pins. */
+double ggo_bp_message(double L, double coupling);
+/* Per-edge influence computed at the last superstep (PR: the ratio; BP: the
+   same on magnitudes, |message| / |running sum|; SSSP:
    relative improvement, 1 for the first finite candidate, -1 when not
    assessable; CC: 1/0). */
 void ggo_get_influence(const ggo_run* r, double* out);

@@ -70,6 +70,15 @@ MUTANTS = {
     # CC influence relative to the row's first label only (running minimum never updated)
     "cc_influence_no_running_min": ("        r->infl[e] = xv < run ? 1.0 : 0.0;\n        if (xv < run) run = xv;",
                                     "        r->infl[e] = xv < run ? 1.0 : 0.0;"),
+    # BP message without the factor of the log-ratio (half the log-ratio)
+    "bp_message_half": ("  return log(m1) - log(m0);", "  return 0.5 * (log(m1) - log(m0));"),
+    # BP message with the potential's two entries swapped (anti-ferromagnetic)
+    "bp_psi_swapped": ("const double m1 = same * b1 + diff * b0;", "const double m1 = diff * b1 + same * b0;"),
+    # BP update without the vertex's own prior
+    "bp_prior_dropped": ("const double xn = r->app.prior[u] + sum;", "const double xn = sum;"),
+    # BP influence on signed values instead of magnitudes
+    "bp_influence_signed": ("r->infl[e] = fabs(P) > 0.0 ? fabs(c) / fabs(P) : 0.0;",
+                            "r->infl[e] = P > 0.0 ? c / P : 0.0;"),
 }
 
 

@@ -6,6 +6,7 @@ to a textbook algorithm, invariants, and hand-worked examples in
 tests/golden/. None of these tests needs a GPU.
 """
 import json
+import math
 import os
 from fractions import Fraction
 
@@ -740,3 +741,127 @@ def test_set_mask_replays_flags():
     want = np.full(g.n, 0.15 / g.n) + 0.85 * (np.bincount(g.dst(), weights=x[g.col] / outdeg[g.col],
                                                           minlength=g.n) + dang / g.n)
     assert np.max(np.abs(b.values() - want)) <= 1e-15
+
+
+# --------------------------------------------------------------------------
+# Belief propagation (the reading: binary pairwise MRF, messages from the
+# sender's belief, value = belief log-odds)
+# --------------------------------------------------------------------------
+
+def _ev(expr):
+    """Value of a closed-form expression of the golden files (ln, products, quotients)."""
+    return float(eval(expr, {"__builtins__": {}}, {"ln": math.log}))
+
+
+@pytest.mark.parametrize("case", ["pos", "neg"])
+def test_golden_bp_superstep(case):
+    """Hand-worked GG run on 3 vertices: values after every iteration, the
+    influences and flags of the superstep (closed forms, tests/golden)."""
+    fx = json.load(open(os.path.join(GOLDEN, "bp_superstep_3v.json")))
+    g, p = _golden_graph(fx), fx["params"]
+    c = fx["cases"][case]
+    prior = np.array([_ev(x) for x in c["prior"]])
+    r = oracle.Run(g, "bp", p["policy"], sigma=p["sigma"], alpha=p["alpha"], theta=p["theta"], seed=1,
+                   iters=p["iters"], coupling=p["coupling"], prior=prior)
+    for it in range(1, p["iters"] + 1):
+        info = r.step()
+        want = np.array([_ev(x) for x in c["values_after"][str(it)]])
+        assert np.allclose(r.values(), want, rtol=1e-12, atol=1e-12), (it, r.values(), want)
+        if info.superstep:
+            infl = r.influence()
+            want_i = np.array([_ev(x) for x in c["influence_at_superstep_2"]])
+            assert np.allclose(infl, want_i, rtol=1e-6), (infl, want_i)  # binary32-rounded messages
+            assert r.mask().tolist() == c["mask_after_superstep_2"]
+    r.close()
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.1, 0.6, 0.95])
+def test_bp_message_closed_form(kappa):
+    """The message from the definition (sum over the sender's states of the
+    potential times its belief) equals the closed form 2 atanh(kappa tanh(L/2)),
+    is odd in L, zero at L = 0 and bounded by 2 atanh(kappa)."""
+    for L in (-40.0, -5.0, -1.0, -0.3, 0.0, 1e-9, 0.7, 3.0, 12.0, 700.0):
+        m = oracle.bp_message(L, kappa)
+        want = 2.0 * math.atanh(kappa * math.tanh(L / 2.0))
+        assert abs(m - want) <= 1e-12 * max(1.0, abs(want)), (L, m, want)
+        assert oracle.bp_message(-L, kappa) == -m
+        assert abs(m) <= 2.0 * math.atanh(kappa) + 1e-15
+    assert oracle.bp_message(0.0, kappa) == 0.0
+
+
+def _bp_graph_and_prior(scale=9, seed=31):
+    g = gg.rmat(scale, 8, seed=seed, symmetrize=True)
+    return g, gg.bp_prior(g.n, seed).astype(np.float64)
+
+
+def test_bp_zero_coupling_keeps_the_prior():
+    g, h = _bp_graph_and_prior()
+    r = oracle.run(g, "bp", "exact", iters=7, coupling=0.0, prior=h)
+    assert np.array_equal(r.values, h)
+
+
+def test_bp_graph_without_edges_keeps_the_prior():
+    n = 50
+    g = gg.Graph(n=n, rowptr=np.zeros(n + 1, dtype=np.int32), col=np.zeros(0, dtype=np.int32))
+    h = gg.bp_prior(n, 5).astype(np.float64)
+    r = oracle.run(g, "bp", "exact", iters=5, coupling=0.7, prior=h)
+    assert np.array_equal(r.values, h)
+
+
+def test_bp_single_edge():
+    """v -> u: after any number of iterations u holds its prior plus v's
+    message, v (no in-edge) its prior."""
+    g = gg.from_edges(2, [0], [1])
+    h = np.array([1.3, -0.4])
+    for it in (1, 2, 5):
+        r = oracle.run(g, "bp", "exact", iters=it, coupling=0.45, prior=h)
+        assert r.values[0] == 1.3
+        assert abs(r.values[1] - (-0.4 + 2 * math.atanh(0.45 * math.tanh(0.65)))) < 1e-14
+
+
+def test_bp_cycle_converges_to_the_scalar_fixed_point():
+    """On a symmetric cycle (in-degree 2) with one prior h everywhere, every
+    vertex converges to the root of L = h + 2 * 2 atanh(kappa tanh(L/2)),
+    found by scipy's brentq (a contraction for 2 kappa < 1)."""
+    from scipy.optimize import brentq
+    n, h0, kappa = 12, 0.3, 0.35
+    src = list(range(n)) + [(i + 1) % n for i in range(n)]
+    dst = [(i + 1) % n for i in range(n)] + list(range(n))
+    g = gg.from_edges(n, src, dst)
+    r = oracle.run(g, "bp", "exact", iters=300, coupling=kappa, prior=np.full(n, h0))
+    f = lambda L: L - h0 - 4.0 * math.atanh(kappa * math.tanh(L / 2.0))
+    want = brentq(f, -50.0, 50.0, xtol=1e-15)
+    assert np.allclose(r.values, want, rtol=1e-12, atol=1e-12), (r.values[:3], want)
+
+
+def test_bp_sign_symmetry_and_monotonicity():
+    """Negating every prior negates every value (exactly: the message is an
+    odd function); raising one prior lowers no vertex's value."""
+    g, h = _bp_graph_and_prior()
+    a = oracle.run(g, "bp", "exact", iters=6, coupling=0.5, prior=h).values
+    b = oracle.run(g, "bp", "exact", iters=6, coupling=0.5, prior=-h).values
+    assert np.array_equal(a, -b)
+    h2 = h.copy()
+    v = int(np.argmax(np.diff(g.rowptr)))
+    h2[v] += 2.0
+    c = oracle.run(g, "bp", "exact", iters=6, coupling=0.5, prior=h2).values
+    assert np.all(c >= a) and c[v] > a[v]
+
+
+def test_bp_sigma_one_alpha_zero_is_exact():
+    """SP with every edge kept and SMS from iteration 1 equal the exact run."""
+    g, h = _bp_graph_and_prior()
+    ex = oracle.run(g, "bp", "exact", iters=8, coupling=0.4, prior=h).values
+    sp = oracle.run(g, "bp", "sp", sigma=1.0, iters=8, coupling=0.4, prior=h).values
+    sms = oracle.run(g, "bp", "sms", sigma=0.3, alpha=0, iters=8, coupling=0.4, prior=h).values
+    assert np.array_equal(ex, sp) and np.array_equal(ex, sms)
+
+
+def test_bp_rejects_unsupported():
+    g, h = _bp_graph_and_prior()
+    with pytest.raises(ValueError):
+        oracle.Run(g, "bp", "exact", coupling=1.0, prior=h)
+    with pytest.raises(ValueError):
+        oracle.Run(g, "bp", "exact", coupling=0.5)
+    with pytest.raises(ValueError):
+        oracle.Run(g, "bp", "gg", coupling=0.5, prior=h, influence=oracle.INFL_TOTAL)
