@@ -26,6 +26,12 @@ part of `value`):
            1% error (BATCH_SMS_1PCT) against the exact batch, and 64
            independent R-MAT graphs of scale 10..18 and edge factor 8..32 run
            as one block-diagonal union (PR, SSSP, CC);
+  bp       belief propagation (a binary pairwise Markov random field with
+           coupling BP_KAPPA on every edge and a seeded prior per vertex, 20
+           iterations) on the symmetrized graph: exact, GG at every sample
+           ratio of the timed step, and the fastest SMS and GG configurations
+           within 1% top-1000 error for every sampling seed (BP_1PCT), with
+           the gather's and the superstep's device time and HBM rate;
   learned  the correction network trained by the library's kernels on the
            (features, drift label) traces of GG runs on the scale-22 graph at
            every sample ratio, then LEARNED against GG and exact on R-MAT
@@ -116,6 +122,14 @@ LEARNED_1PCT = {"pr": dict(sigma=0.1, alpha=6, theta=0.0, tau=0.0, rho=0.6, stop
 
 SEEDS = (1, 2, 3, 4, 5)
 
+# Belief propagation: coupling of the potential, and the fastest SMS and GG
+# configurations within 1% top-1000 error for every sampling seed 1..5 on the
+# symmetrized R-MAT scale 22 (seed 2), from a sweep over SP/SMS/GG, sigma in
+# {.05, .1, .2, .3, .5}, alpha in {2, 4, 8, 12, 16} (GG: {2, 4, 8}) and theta
+# in {0, .01, .05, .2}, at kappa in {.01, .03, .1, .3}.
+BP_KAPPA = 0.1
+BP_1PCT = {"sms": (0.05, 16, 0.0), "gg": (0.05, 8, 0.0)}
+
 
 def app_error(metrics, np, app, approx_h, exact_h, source):
     """The paper's error metric of one approximate result [Sec. 4.2]."""
@@ -153,6 +167,65 @@ def bench_at_1pct(G, apps, iters, source, exact_out, metrics, np):
                     "gteps_eff": round(G[app].m * iters[app] / st.device_ms / 1e6, 2),
                     "exact_gteps_work": round(sx.edges_processed / sx.device_ms / 1e6, 2)}
         log("at_1pct:", app, out[app])
+    return out
+
+
+def bench_bp(Gs, gs, seed, sigmas, alpha, theta, np, metrics):
+    """Belief propagation on the symmetrized graph (not part of `value`)."""
+    import graphgen as gg
+    prior = gg.bp_prior(gs.n, seed)
+    iters = 20
+    kw = dict(iters=iters, coupling=BP_KAPPA, prior=prior)
+    ex, _ = Gs.exact_run("bp", **kw)  # warm-up
+    exh = ex.cpu().numpy()
+    Gs.set_profiling(True)
+    ex_ms = sorted(Gs.exact_run("bp", **kw)[1].device_ms for _ in range(3))[1]
+    prof = {k: Gs.get_profile(k, "bp") for k in ("gather_exact",)}
+    Gs.set_profiling(False)
+    out = {"kappa": BP_KAPPA, "iters": iters, "m": gs.m, "exact_ms": round(ex_ms, 3),
+           "exact_gteps": round(gs.m * iters / ex_ms / 1e6, 2), "runs": {}, "at_1pct": {}}
+    p = prof["gather_exact"]
+    if p["launches"]:
+        avg = p["total_ms"] / p["launches"]
+        out["gather_exact"] = {"avg_launch_ms": round(avg, 4),
+                               "achieved_gbs": round(p["alg_bytes"] / p["launches"] / (avg * 1e-3) / 1e9, 1)}
+
+    def timed(sg, pol, a, th, seed=1):
+        Gs.approx_run("bp", sg, pol, alpha=a, theta=th, seed=seed, **kw)
+        runs = [Gs.approx_run("bp", sg, pol, alpha=a, theta=th, seed=seed, **kw) for _ in range(3)]
+        return sorted(runs, key=lambda r: r[1].device_ms)[1]
+
+    def errors(sg, pol, a, th, first):
+        errs = [metrics.topk_error(first, exh, 1000)]
+        for sd in SEEDS[1:]:
+            o, _ = Gs.approx_run("bp", sg, pol, alpha=a, theta=th, seed=sd, **kw)
+            errs.append(metrics.topk_error(o.cpu().numpy(), exh, 1000))
+        return errs
+
+    Gs.set_profiling(True)
+    for sg in sigmas:
+        o, st = timed(sg, "gg", alpha, theta)
+        errs = errors(sg, "gg", alpha, theta, o.cpu().numpy())
+        out["runs"]["gg%.1f" % sg] = {"ms": round(st.device_ms, 3), "speedup": round(ex_ms / st.device_ms, 3),
+                                      "accuracy": round(metrics.accuracy(float(np.mean(errs))), 3),
+                                      "accuracy_min": round(metrics.accuracy(float(np.max(errs))), 3),
+                                      "gteps_work": round(st.edges_processed / st.device_ms / 1e6, 2)}
+    sp = Gs.get_profile("superstep", "bp")
+    Gs.set_profiling(False)
+    if sp["launches"]:
+        avg = sp["total_ms"] / sp["launches"]
+        out["superstep"] = {"avg_launch_ms": round(avg, 4),
+                            "achieved_gbs": round(sp["alg_bytes"] / sp["launches"] / (avg * 1e-3) / 1e9, 1)}
+    for pol, (sg, a, th) in BP_1PCT.items():
+        o, st = timed(sg, pol, a, th)
+        errs = errors(sg, pol, a, th, o.cpu().numpy())
+        out["at_1pct"][pol] = {"sigma": sg, "alpha": a, "theta": th, "ms": round(st.device_ms, 3),
+                               "speedup": round(ex_ms / st.device_ms, 3),
+                               "accuracy": round(metrics.accuracy(float(np.mean(errs))), 3),
+                               "accuracy_min": round(metrics.accuracy(float(np.max(errs))), 3),
+                               "within_1pct": bool(max(errs) <= 0.01),
+                               "edges_vs_exact": round(st.edges_gathered / (gs.m * iters), 4)}
+    log("bp:", out)
     return out
 
 
@@ -374,6 +447,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-query section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction section")
+    ap.add_argument("--no-bp", action="store_true", help="skip the belief-propagation section")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain copy kernel of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -536,6 +610,10 @@ def main():
 
     at1 = bench_at_1pct(G, apps, iters, source, {a: outs[(a, "exact")].cpu().numpy() for a in apps}, metrics, np)
 
+    bp = None
+    if not args.no_bp and "cc" in apps:
+        bp = bench_bp(G["cc"], graphs["cc"], args.seed, sigmas, args.alpha, args.theta, np, metrics)
+
     batch = None
     if not args.no_batch:
         batch = bench_batch(P, gg, torch, args.seed, np, metrics)
@@ -570,6 +648,7 @@ def main():
         "cpu_baseline": cpu,
         "runs": summary,
         "at_1pct": at1,
+        "bp": bp,
         "batch": batch,
         "learned": learned,
     }

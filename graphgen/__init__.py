@@ -204,20 +204,16 @@ def pick_sources(g: Graph, count: int, seed: int) -> np.ndarray:
     return out[:count].copy()
 
 
-def bp_prior(n: int, seed: int, labeled: float = 0.1) -> np.ndarray:
-    """Prior log-odds of a belief-propagation workload, float32 [n]: a
-    fraction `labeled` of the vertices carries evidence (probability 0.9 or
-    0.1 of state 1, equally likely), the others a nearly uninformative
-    probability in [0.45, 0.55]. Uses the generator's own counter-based
-    draws: vertex u takes draw(seed, u, 0) and draw(seed, u, 1)."""
-    u1 = np.empty(max(n, 1), dtype=np.uint64)
-    u2 = np.empty(max(n, 1), dtype=np.uint64)
-    _lib().graphgen_draws(seed, 0, n, u1.ctypes.data)
-    _lib().graphgen_draws(seed, 1, n, u2.ctypes.data)
-    u1, u2 = u1[:n], u2[:n]
-    a = (u1 >> np.uint64(11)).astype(np.float64) / float(1 << 53)
-    b = (u2 >> np.uint64(11)).astype(np.float64) / float(1 << 53)
-    p = np.where(a < labeled, np.where(b < 0.5, 0.9, 0.1), 0.45 + 0.1 * b)
+def bp_prior(n: int, seed: int) -> np.ndarray:
+    """Prior log-odds of a belief-propagation workload, float32 [n]: every
+    vertex carries evidence of its own strength, a probability p of state 1
+    uniform in [0.05, 0.95] (log-odds within +-2.944, no two vertices tied).
+    Uses the generator's own counter-based draws: vertex u takes
+    draw(seed, u, 0)."""
+    u = np.empty(max(n, 1), dtype=np.uint64)
+    _lib().graphgen_draws(seed, 0, n, u.ctypes.data)
+    a = (u[:n] >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    p = 0.05 + 0.9 * a
     return (np.log(p) - np.log1p(-p)).astype(np.float32)
 
 

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GG_VERSION 7
+#define GG_VERSION 8
 
 typedef enum {
   GG_OK = 0,
@@ -54,8 +54,19 @@ typedef enum {
 /* Vertex programs [Sec. 4.1]. PR = PageRank (Alg. 2); PPR = personalized
    PageRank from a source; SSSP = single-source shortest paths; CC = weakly
    connected components by minimum-label propagation (load the symmetrized
-   graph). */
-typedef enum { GG_APP_PR = 0, GG_APP_SSSP = 1, GG_APP_CC = 2, GG_APP_PPR = 3 } gg_app;
+   graph); BP = belief propagation on a binary pairwise Markov random field
+   (the paper names BP among its applications without giving the model; the
+   reading taken here: one potential psi(x, y) = (1 + kappa)/2 if x == y,
+   (1 - kappa)/2 otherwise, on every edge, a prior log-odds h_u per vertex;
+   the value of u is its belief log-odds L_u = h_u + sum over the in-edges
+   (v, u) of the edge set of c_v, with c_v = log(m_v(1) / m_v(0)) =
+   2 atanh(kappa tanh(L_v / 2)) the message of v computed from its whole
+   belief; load the symmetrized graph for an undirected model). BP runs
+   gg_app_params.iters iterations; its edge influence at a superstep is
+   |c_v| / |P| with P the running sum of the row's contributions up to and
+   including the edge (PREFIX on magnitudes, since messages have both
+   signs). */
+typedef enum { GG_APP_PR = 0, GG_APP_SSSP = 1, GG_APP_CC = 2, GG_APP_PPR = 3, GG_APP_BP = 4 } gg_app;
 
 /* Correction schemes: EXACT = accurate mode in every iteration (the baseline
    of Sec. 5); SP = sparsified for the whole run; SMS = approximate for alpha
@@ -139,11 +150,15 @@ typedef struct {
 typedef struct {
   int32_t app;       /* gg_app */
   double damping;    /* PR/PPR damping factor d in [0,1) (Alg. 2, GG-Apply) */
-  int32_t iters;     /* PR/PPR: iterations T; SSSP/CC FIXED_ITERS: iterations */
+  int32_t iters;     /* PR/PPR/BP: iterations T; SSSP/CC FIXED_ITERS: iterations */
   int32_t max_iters; /* SSSP/CC fixed-point runs: cap on iterations (> 0) */
   int32_t source;    /* SSSP/PPR source vertex */
   int32_t dangling;  /* gg_dangling */
   int32_t pr_degree; /* gg_pr_degree (PR/PPR) */
+  double coupling;    /* BP: kappa in [0, 1) */
+  const float* prior; /* BP: device pointer, float32[n] prior log-odds (finite); copied by
+                         gg_run_begin / gg_approx_run / gg_exact_run, so it need not outlive
+                         the call */
 } gg_app_params;
 
 typedef struct gg_mlp gg_mlp;

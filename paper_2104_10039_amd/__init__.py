@@ -23,7 +23,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgg.so")
 
-APP = {"pr": 0, "sssp": 1, "cc": 2, "ppr": 3}
+APP = {"pr": 0, "sssp": 1, "cc": 2, "ppr": 3, "bp": 4}
 POLICY = {"exact": 0, "sp": 1, "sms": 2, "gg": 3, "learned": 4}
 STEP_KIND = {0: "approx", 1: "accurate", 2: "full", 3: "partial"}
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 8, 64, 4801
@@ -54,7 +54,7 @@ class CsrDesc(ctypes.Structure):
 class AppParams(ctypes.Structure):
     _fields_ = [("app", ctypes.c_int32), ("damping", ctypes.c_double), ("iters", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("source", ctypes.c_int32), ("dangling", ctypes.c_int32),
-                ("pr_degree", ctypes.c_int32)]
+                ("pr_degree", ctypes.c_int32), ("coupling", ctypes.c_double), ("prior", ctypes.c_void_p)]
 
 
 class Policy(ctypes.Structure):
@@ -255,7 +255,8 @@ def _ptr(x):
 
 
 def _value_dtype(app: str):
-    return {"pr": torch.float32, "ppr": torch.float32, "sssp": torch.int32, "cc": torch.int32}[app]
+    return {"pr": torch.float32, "ppr": torch.float32, "bp": torch.float32, "sssp": torch.int32,
+            "cc": torch.int32}[app]
 
 
 @dataclass
@@ -283,8 +284,23 @@ def _stats(s: RunStats) -> Stats:
 PR_DEGREE = {"full": 0, "active": 1}
 
 
-def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full"):
-    return AppParams(APP[app], damping, iters, max_iters, source, DANGLING[dangling], PR_DEGREE[pr_degree])
+def _app_params(app, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full",
+                coupling=0.0, prior=None):
+    """prior: None or a float32 device tensor (see _prior_dev), read during the call."""
+    return AppParams(APP[app], damping, iters, max_iters, source, DANGLING[dangling], PR_DEGREE[pr_degree],
+                     float(coupling), None if prior is None else prior.data_ptr())
+
+
+def _prior_dev(prior, n):
+    """BP prior log-odds as a contiguous float32 device tensor of n values
+    (numpy arrays and host tensors are copied to the device)."""
+    if prior is None:
+        return None
+    t = prior if isinstance(prior, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(prior, dtype=np.float32))
+    t = t.to(device="cuda", dtype=torch.float32).contiguous()
+    if t.numel() != n:
+        raise ValueError("prior must hold %d values, got %d" % (n, t.numel()))
+    return t
 
 
 def _policy(policy="gg", alpha=4, theta=0.05, seed=1, influence="prefix", mask_update="replace",
@@ -418,10 +434,13 @@ class Graph:
             out = torch.empty(self.n, dtype=_value_dtype(app), device="cuda")
         return out
 
-    def exact_run(self, app, out=None, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform"):
-        """gg_exact_run: returns (values tensor on the device, Stats)."""
+    def exact_run(self, app, out=None, damping=0.85, iters=20, max_iters=1 << 20, source=0, dangling="uniform",
+                  coupling=0.0, prior=None):
+        """gg_exact_run: returns (values tensor on the device, Stats). BP takes
+        coupling and prior (n float32 log-odds)."""
         out = self._out(app, out)
-        p = _app_params(app, damping, iters, max_iters, source, dangling)
+        pri = _prior_dev(prior, self.n)
+        p = _app_params(app, damping, iters, max_iters, source, dangling, coupling=coupling, prior=pri)
         st = RunStats()
         _check(lib().gg_exact_run(self._h, ctypes.byref(p), out.data_ptr(), 0, ctypes.byref(st)))
         return out, _stats(st)
@@ -438,16 +457,18 @@ class Graph:
 
     def approx_run(self, app, sample_ratio, policy="gg", out=None, alpha=4, theta=0.05, seed=1,
                    influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
-                   max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full", **learned):
+                   max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full", coupling=0.0, prior=None,
+                   **learned):
         """gg_approx_run: returns (values tensor on the device, Stats). Learned-policy
         and trace arguments: mlp, tau, rho, fallback_k, audit, trace, label_eps;
         decoupled first superstep: alpha0, theta0; vertex status: vstatus, eps;
-        pr_degree "full" or "active"."""
+        pr_degree "full" or "active"; BP: coupling, prior."""
         bad = set(learned) - set(POLICY_KW)
         if bad:
             raise TypeError("unknown arguments %s" % sorted(bad))
         out = self._out(app, out)
-        p = _app_params(app, damping, iters, max_iters, source, dangling, pr_degree)
+        pri = _prior_dev(prior, self.n)
+        p = _app_params(app, damping, iters, max_iters, source, dangling, pr_degree, coupling, pri)
         pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop, **learned)
         st = RunStats()
         _check(lib().gg_approx_run(self._h, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
@@ -469,11 +490,12 @@ class Graph:
         return out, _stats(st)
 
     def autotune(self, app, sample_ratio=1.0, policy="exact", sources=None, reps=2, damping=0.85, iters=20,
-                 max_iters=1 << 20, source=0, dangling="uniform", **pol):
+                 max_iters=1 << 20, source=0, dangling="uniform", coupling=0.0, prior=None, **pol):
         """gg_graph_autotune: times the workload (a single run, or a batch over
         `sources`) under candidate tunings and keeps the fastest on the graph.
         Returns (tuning dict, median ms of the chosen tuning)."""
-        p = _app_params(app, damping, iters, max_iters, source, dangling)
+        pri = _prior_dev(prior, self.n)
+        p = _app_params(app, damping, iters, max_iters, source, dangling, coupling=coupling, prior=pri)
         pc = _policy(policy, **pol)
         src = None if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
         t = Tuning()
@@ -494,14 +516,16 @@ class Run:
 
     def __init__(self, graph: Graph, app, sample_ratio=1.0, policy="exact", alpha=4, theta=0.05, seed=1,
                  influence="prefix", mask_update="replace", stop="fixed_iters", damping=0.85, iters=20,
-                 max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full", **learned):
+                 max_iters=1 << 20, source=0, dangling="uniform", pr_degree="full", coupling=0.0, prior=None,
+                 **learned):
         bad = set(learned) - set(POLICY_KW)
         if bad:
             raise TypeError("unknown arguments %s" % sorted(bad))
         self.graph = graph
         self.app = app
         self._keep = (learned.get("mlp"), learned.get("trace"))  # the run reads them until it ends
-        p = _app_params(app, damping, iters, max_iters, source, dangling, pr_degree)
+        pri = _prior_dev(prior, graph.n)  # copied by gg_run_begin
+        p = _app_params(app, damping, iters, max_iters, source, dangling, pr_degree, coupling, pri)
         pol = _policy(policy, alpha, theta, seed, influence, mask_update, stop, **learned)
         h = ctypes.c_void_p()
         _check(lib().gg_run_begin(graph.handle, ctypes.byref(p), float(sample_ratio), ctypes.byref(pol),
@@ -545,7 +569,7 @@ class Run:
         return out[: self.graph.n]
 
     def values(self, host=True):
-        dt = {"pr": np.float32, "ppr": np.float32, "sssp": np.uint32, "cc": np.int32}[self.app]
+        dt = {"pr": np.float32, "ppr": np.float32, "bp": np.float32, "sssp": np.uint32, "cc": np.int32}[self.app]
         if host:
             out = np.empty(max(self.graph.n, 1), dtype=dt)
             _check(lib().gg_run_values(self._h, out.ctypes.data, OUT_HOST))

@@ -15,7 +15,7 @@ constexpr int kSegWin = 2048;  // edges gathered per window of a segmented gathe
 constexpr int kPartDangBlocks = 32;  // blocks per part of the per-part dangling sums
 constexpr int kHubSpinLimit = 1 << 20;  // default polls before a single-pass hub chunk gives up waiting
 
-enum App : int { kPR = 0, kSSSP = 1, kCC = 2, kPPR = 3 };
+enum App : int { kPR = 0, kSSSP = 1, kCC = 2, kPPR = 3, kBP = 4 };
 
 // Counts of one degree binning, on the device (filled by the rebin kernels)
 // and mirrored on the host after a rebin.
@@ -109,6 +109,10 @@ struct Sweep {
   float* x_prev;
   double vs_eps;
   int32_t vs_rel;
+  // BP: prior log-odds per vertex and the coupling kappa of the potential;
+  // c_in / c_out hold the message log-ratios, x_out the belief log-odds
+  const float* bp_prior;
+  double bp_kappa;
 };
 
 // Segmented gather constants.
@@ -167,6 +171,8 @@ hipError_t launch_rebin(const int32_t* rowptr, const int32_t* cnt, int32_t n, in
                         int32_t wave_max, int32_t hub_chunk, Bins& bins, void* blk_scratch, hipStream_t st, const uint8_t* rowsel = nullptr,
                         int selwant = 0, const uint32_t* hub_err = nullptr);
 
+// BP initial messages c[u] = message of the prior log-odds prior[u].
+hipError_t launch_bp_init(const float* prior, int32_t n, double kappa, float* c, hipStream_t st);
 // PR/PPR initial contributions.
 // part_of / part_start nullable (PR: 1/N per part when set).
 hipError_t launch_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t source, const int32_t* part_of,

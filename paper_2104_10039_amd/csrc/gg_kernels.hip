@@ -66,6 +66,11 @@ __device__ __forceinline__ uint32_t team_scan_min(uint32_t x, int lt) {
   return x;
 }
 
+// Apps whose gather is a sum of binary32 per-vertex contributions (PR, PPR:
+// rank over out-degree; BP: message log-ratio).
+template <int APP>
+constexpr bool kSumApp = APP == kPR || APP == kPPR || APP == kBP;
+
 // Per-app gather element, identity and combine.
 template <int APP>
 struct Tr;
@@ -79,6 +84,8 @@ struct Tr<kPR> {
 };
 template <>
 struct Tr<kPPR> : Tr<kPR> {};
+template <>
+struct Tr<kBP> : Tr<kPR> {};
 template <>
 struct Tr<kSSSP> {
   using T = uint32_t;
@@ -172,7 +179,15 @@ __device__ __forceinline__ int find_hub(const int32_t* hub_start, int n_hub, int
 template <int APP>
 __device__ __forceinline__ uint32_t apply_word(const Sweep& s, int u) {
   if constexpr (APP == kPR || APP == kPPR) return (uint32_t)s.outdeg[u];
+  else if constexpr (APP == kBP) return __float_as_uint(s.bp_prior[u]);
   else return s.x_in[u];
+}
+
+// BP message log-ratio of a vertex with belief log-odds L under the coupling
+// kappa: log(m(1) / m(0)) = 2 atanh(kappa tanh(L / 2)) (the sum over the
+// sender's states of the potential times its belief, in closed form).
+__device__ __forceinline__ double bp_message(double L, double kappa) {
+  return 2.0 * atanh(kappa * tanh(0.5 * L));
 }
 
 template <int APP>
@@ -205,6 +220,12 @@ __device__ __forceinline__ void apply_with(const Sweep& s, int u, typename Tr<AP
       s.vact[u] = (uint8_t)(fabs(x - xo) > bound);
       s.x_prev[u] = (float)x;
     }
+  } else if constexpr (APP == kBP) {
+    // belief log-odds: prior plus the gathered messages; the new message is
+    // what the next iteration gathers
+    const double L = (double)__uint_as_float(word) + acc;
+    s.c_out[u] = (float)bp_message(L, s.bp_kappa);
+    if (s.x_out) s.x_out[u] = (float)L;
   } else {
     const uint32_t old = word;
     const uint32_t nv = min(old, acc);
@@ -280,7 +301,7 @@ __device__ __forceinline__ void gather_hub_chunk(const Sweep& s, int ch, bool al
     if (nch == 1 && !always_partial) {
       apply<APP>(s, u, acc, nchanged);
     } else {
-      if constexpr (APP == kPR || APP == kPPR) s.part_f[ch] = acc;
+      if constexpr (kSumApp<APP>) s.part_f[ch] = acc;
       else s.part_u[ch] = acc;
     }
   }
@@ -325,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_combine(Sweep s) {
     if (nch > 1) {
       typename R::T acc = R::id();
       for (int j = 0; j < nch; ++j) {
-        if constexpr (APP == kPR || APP == kPPR) acc = R::op(acc, s.part_f[c0 + j]);
+        if constexpr (kSumApp<APP>) acc = R::op(acc, s.part_f[c0 + j]);
         else acc = R::op(acc, s.part_u[c0 + j]);
       }
       apply<APP>(s, s.list[s.n_small + s.n_wave + h], acc, nchanged);
@@ -340,12 +361,10 @@ __global__ __launch_bounds__(kBlock) void k_hub_combine(Sweep s) {
 
 __device__ __forceinline__ uint32_t edge_bit(const uint32_t* bits, int e) { return (bits[e >> 5] >> (e & 31)) & 1u; }
 
-// Flag of one edge given the exclusive prefix (running value before it).
-// PR: influence = c / P with P the inclusive running sum. SSSP: relative
+// Flag of one edge given the running value of its row. PR/PPR: influence =
+// c / P with P the inclusive running sum; BP: |c| / |P|. SSSP: relative
 // improvement of the running minimum; unreached sources keep their flag.
 // CC: the source label lowers the running minimum.
-template <int APP>
-struct Decide;
 
 // c / P > theta for c, P >= 0, identical to comparing the rounded quotient:
 // away from the threshold (relative margin 1e-12, far above the rounding of
@@ -358,13 +377,16 @@ __device__ __forceinline__ bool infl_above(double c, double P, double theta) {
   return c / P > theta;
 }
 
-template <>
-struct Decide<kPR> {
-  static __device__ __forceinline__ bool f(const Sweep& s, bool valid, double c, double P, uint32_t oldf) {
-    bool flag = valid && infl_above(c, P, s.theta);
-    return flag || (s.mask_union && oldf);
+// Sum-type apps: influence c / P (BP on magnitudes, its messages having
+// both signs).
+template <int APP>
+__device__ __forceinline__ bool sum_flag(const Sweep& s, bool valid, double c, double P, uint32_t oldf) {
+  if constexpr (APP == kBP) {
+    c = fabs(c);
+    P = fabs(P);
   }
-};
+  return (valid && infl_above(c, P, s.theta)) || (s.mask_union && oldf);
+}
 
 // Set the new flag bits of TEAM consecutive edges (edge e at team lane lt).
 template <int TEAM>
@@ -393,7 +415,7 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
     const int b = s.rowptr[u];
     const int len = s.rowptr[u + 1] - b;
     // TOTAL influence compares with the row sum, PREFIX with the running sum
-    const double rtot = ((APP == kPR || APP == kPPR) && s.row_total) ? s.row_total[u] : -1.0;
+    const double rtot = (kSumApp<APP> && s.row_total) ? s.row_total[u] : -1.0;
     T carry = R::id();
     int carry_cnt = 0;
     // edge words and values of kPreT consecutive team-wide steps are loaded
@@ -425,11 +447,11 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
           (valid && s.old_bits && (APP == kSSSP || s.mask_union)) ? edge_bit(s.old_bits, e) : 0u;
       bool flag;
       T chunk_total;
-      if constexpr (APP == kPR || APP == kPPR) {
+      if constexpr (kSumApp<APP>) {
         const double c = vq[q];
         const double incl = team_scan_add<TEAM>(c, lt);
         const double P = carry + incl;
-        flag = Decide<kPR>::f(s, valid, c, rtot >= 0.0 ? rtot : P, oldf);
+        flag = sum_flag<APP>(s, valid, c, rtot >= 0.0 ? rtot : P, oldf);
         chunk_total = __shfl(incl, TEAM - 1, TEAM);
       } else if constexpr (APP == kSSSP) {
         const uint32_t cand = vq[q];  // INF exactly when the source is unreached
@@ -485,7 +507,7 @@ __device__ __forceinline__ bool hub_step(const Sweep& s, int b, int sub, int e1,
   const uint32_t oldf = (valid && s.old_bits && (APP == kSSSP || s.mask_union)) ? edge_bit(s.old_bits, e) : 0u;
   bool flag;
   T sub_total;
-  if constexpr (APP == kPR || APP == kPPR) {
+  if constexpr (kSumApp<APP>) {
     const double c = v;
     const double incl_w = team_scan_add<64>(c, lane);
     if (lane == 63) lds[wid] = incl_w;
@@ -495,7 +517,7 @@ __device__ __forceinline__ bool hub_step(const Sweep& s, int b, int sub, int e1,
     sub_total = (lds[0] + lds[1]) + (lds[2] + lds[3]);
     __syncthreads();
     const double P = carry + (before + incl_w);
-    flag = Decide<kPR>::f(s, valid, c, rtot >= 0.0 ? rtot : P, oldf);
+    flag = sum_flag<APP>(s, valid, c, rtot >= 0.0 ? rtot : P, oldf);
   } else {
     const uint32_t val = v;  // SSSP: INF exactly when the source is unreached
     const uint32_t incl_w = team_scan_min<64>(val, lane);
@@ -541,10 +563,10 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
   const int len = s.rowptr[u + 1] - b;
   const int e0 = j * s.hub_chunk;
   const int e1 = min(len, e0 + s.hub_chunk);
-  const double rtot = ((APP == kPR || APP == kPPR) && s.row_total) ? s.row_total[u] : -1.0;
+  const double rtot = (kSumApp<APP> && s.row_total) ? s.row_total[u] : -1.0;
 
   auto part = [&](int i) -> T {
-    if constexpr (APP == kPR || APP == kPPR) return s.part_f[i];
+    if constexpr (kSumApp<APP>) return s.part_f[i];
     else return s.part_u[i];
   };
   T carry = R::id();
@@ -587,7 +609,7 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
 }
 
 // Chunk totals of the single-pass hub path travel in one 64-bit word that is
-// zero until written: PR/PPR the complemented bits of the binary64 total (a
+// zero until written: PR/PPR/BP the complemented bits of the binary64 total (a
 // finite total never complements to zero), SSSP/CC (1 << 32) | minimum.
 // Counts travel as count + 1 in a 32-bit word. Both are written and polled
 // with relaxed device-scope atomics, which stay coherent across the dies
@@ -595,12 +617,12 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
 // ordering would cost on every poll.
 template <int APP>
 __device__ __forceinline__ uint64_t pack_total(typename Tr<APP>::T v) {
-  if constexpr (APP == kPR || APP == kPPR) return ~(uint64_t)__double_as_longlong(v);
+  if constexpr (kSumApp<APP>) return ~(uint64_t)__double_as_longlong(v);
   else return (1ull << 32) | (uint64_t)v;
 }
 template <int APP>
 __device__ __forceinline__ typename Tr<APP>::T unpack_total(uint64_t w) {
-  if constexpr (APP == kPR || APP == kPPR) return __longlong_as_double((long long)~w);
+  if constexpr (kSumApp<APP>) return __longlong_as_double((long long)~w);
   else return (uint32_t)w;
 }
 
@@ -668,7 +690,7 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
   const int len = s.rowptr[u + 1] - b;
   const int e0 = j * s.hub_chunk;
   const int e1 = min(len, e0 + s.hub_chunk);
-  const double rtot = ((APP == kPR || APP == kPPR) && s.row_total) ? s.row_total[u] : -1.0;
+  const double rtot = (kSumApp<APP> && s.row_total) ? s.row_total[u] : -1.0;
   // gather: every edge of the chunk, all loads in flight together, values
   // held in their stored width (binary32 contributions for PR)
   using V = typename GV<APP>::V;
@@ -1237,6 +1259,12 @@ __global__ void k_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t sou
   }
 }
 
+// BP before iteration 1: every belief is its prior; c[u] is its message.
+__global__ void k_bp_init(const float* prior, int32_t n, double kappa, float* c) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = (float)bp_message((double)prior[i], kappa);
+}
+
 __global__ void k_min_init(int app, int32_t n, int32_t source, uint32_t* x) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     if (app == kSSSP) x[i] = (i == source) ? 0u : kInf;
@@ -1392,6 +1420,12 @@ hipError_t launch_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t sou
   return hipGetLastError();
 }
 
+hipError_t launch_bp_init(const float* prior, int32_t n, double kappa, float* c, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bp_init, dim3(grid_for(n, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, prior, n, kappa, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_min_init(int app, int32_t n, int32_t source, uint32_t* x, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_min_init, dim3(grid_for(n, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, app, n, source, x);
@@ -1466,6 +1500,7 @@ hipError_t launch_gather(int app, int team, const Sweep& s, hipStream_t st, hipE
   switch (app) {
     case kPR: return gather_app<kPR>(team, s, nchunks, st, ev0, ev1);
     case kPPR: return gather_app<kPPR>(team, s, nchunks, st, ev0, ev1);
+    case kBP: return gather_app<kBP>(team, s, nchunks, st, ev0, ev1);
     case kSSSP: return gather_app<kSSSP>(team, s, nchunks, st, ev0, ev1);
     case kCC: return gather_app<kCC>(team, s, nchunks, st, ev0, ev1);
   }
@@ -1477,6 +1512,7 @@ hipError_t launch_superstep(int app, int team, const Sweep& s, hipStream_t st, h
   switch (app) {
     case kPR: return super_app<kPR>(team, s, nchunks, st, ev0, ev1);
     case kPPR: return super_app<kPPR>(team, s, nchunks, st, ev0, ev1);
+    case kBP: return super_app<kBP>(team, s, nchunks, st, ev0, ev1);
     case kSSSP: return super_app<kSSSP>(team, s, nchunks, st, ev0, ev1);
     case kCC: return super_app<kCC>(team, s, nchunks, st, ev0, ev1);
   }
@@ -1598,7 +1634,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_offsets(Sweep s, uint32_t src_ma
 
 template <int APP>
 __device__ __forceinline__ void seg_store(const Sweep& s, int64_t idx, typename Tr<APP>::T v) {
-  if constexpr (APP == kPR || APP == kPPR) s.seg_part_f[idx] = v;
+  if constexpr (kSumApp<APP>) s.seg_part_f[idx] = v;
   else s.seg_part_u[idx] = v;
 }
 
@@ -1617,6 +1653,8 @@ struct GV<kPR> {
 };
 template <>
 struct GV<kPPR> : GV<kPR> {};
+template <>
+struct GV<kBP> : GV<kPR> {};
 
 
 
@@ -1765,7 +1803,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_combine(Sweep s) {
   if (i < nl) {
     typename R::T acc = R::id();
     for (int sg = 0; sg < s.seg_s; ++sg) {
-      if constexpr (APP == kPR || APP == kPPR) acc = R::op(acc, s.seg_part_f[(int64_t)sg * nl + i]);
+      if constexpr (kSumApp<APP>) acc = R::op(acc, s.seg_part_f[(int64_t)sg * nl + i]);
       else acc = R::op(acc, s.seg_part_u[(int64_t)sg * nl + i]);
     }
     apply<APP>(s, s.list[s.n_small + i], acc, nchanged);
@@ -1810,6 +1848,7 @@ hipError_t launch_gather_seg(int app, int team, const Sweep& s, hipStream_t st, 
   switch (app) {
     case kPR: return gather_seg_app<kPR>(team, s, st, ev0, ev1);
     case kPPR: return gather_seg_app<kPPR>(team, s, st, ev0, ev1);
+    case kBP: return gather_seg_app<kBP>(team, s, st, ev0, ev1);
     case kSSSP: return gather_seg_app<kSSSP>(team, s, st, ev0, ev1);
     case kCC: return gather_seg_app<kCC>(team, s, st, ev0, ev1);
   }
@@ -2421,7 +2460,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
     word = apply_word<APP>(s, u);
     mine = len <= s.small_max;
     if (!mine) len = 0;
-    if ((APP == kPR || APP == kPPR) && s.row_total && mine) rtot = s.row_total[u];
+    if (kSumApp<APP> && s.row_total && mine) rtot = s.row_total[u];
   }
   // exclusive scan of the row lengths
   int x = len;
@@ -2481,10 +2520,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
         oldf = (oword >> (e & 31)) & 1u;
       }
       bool flag;
-      if constexpr (APP == kPR || APP == kPPR) {
+      if constexpr (kSumApp<APP>) {
         const double c = (double)val;
         Psum += c;
-        flag = infl_above(c, rtot >= 0.0 ? rtot : Psum, s.theta) || (s.mask_union && oldf);
+        flag = sum_flag<APP>(s, true, c, rtot >= 0.0 ? rtot : Psum, oldf);
       } else if constexpr (APP == kSSSP) {
         const uint32_t cand = val;  // INF iff the source is unreached
         if (cand == kInf) {
@@ -2515,7 +2554,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
   if (mine) {
     if (bacc) atomicOr(&s.new_bits[bw], bacc);
     T acc;
-    if constexpr (APP == kPR || APP == kPPR) acc = Psum;
+    if constexpr (kSumApp<APP>) acc = Psum;
     else acc = run;
     apply_with<APP>(s, u, acc, word, nchanged);
     s.act_cnt[u] = cnt;
@@ -2575,6 +2614,7 @@ hipError_t launch_superstep_flat(int app, const Sweep& s, hipStream_t st, hipEve
   switch (app) {
     case kPR: return super_flat_t<kPR>(s, nchunks, st, ev0, ev1);
     case kPPR: return super_flat_t<kPPR>(s, nchunks, st, ev0, ev1);
+    case kBP: return super_flat_t<kBP>(s, nchunks, st, ev0, ev1);
     case kSSSP: return super_flat_t<kSSSP>(s, nchunks, st, ev0, ev1);
     case kCC: return super_flat_t<kCC>(s, nchunks, st, ev0, ev1);
   }

@@ -226,6 +226,7 @@ struct gg_graph {
   int32_t* odeg_act = nullptr;
   int32_t* dang_act = nullptr;
   int32_t n_dang_act = 0;
+  float* bp_prior = nullptr;  // n: BP prior log-odds of the current run (first use)
   int32_t* changed = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   gg_run* active_run = nullptr;
@@ -602,6 +603,7 @@ void free_graph(gg_graph* g) {
   dfree(g->x_prev);
   dfree(g->odeg_act);
   dfree(g->dang_act);
+  dfree(g->bp_prior);
   dfree(g->changed);
   dfree(g->seg_off_full);
   dfree(g->seg_off_act);
@@ -684,10 +686,19 @@ int step_kind(const gg_correction_policy& p, int32_t i) {
 }
 
 bool is_pr(int app) { return app == GG_APP_PR || app == GG_APP_PPR; }
+// Apps whose values are binary32 and whose gather sums binary32 per-vertex
+// contributions (PR, PPR, BP); they run a fixed number of iterations.
+bool is_float(int app) { return is_pr(app) || app == GG_APP_BP; }
 
 int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol) {
   if (!p || !pol) return fail(GG_E_INVAL, "null params or policy");
-  if (p->app < GG_APP_PR || p->app > GG_APP_PPR) return fail(GG_E_INVAL, "unknown app");
+  if (p->app < GG_APP_PR || p->app > GG_APP_BP) return fail(GG_E_INVAL, "unknown app");
+  if (p->app == GG_APP_BP) {
+    if (!(p->coupling >= 0.0 && p->coupling < 1.0)) return fail(GG_E_INVAL, "coupling outside [0, 1)");
+    if (!p->prior && g->n > 0) return fail(GG_E_INVAL, "BP needs a prior");
+    if (pol->kind == GG_POLICY_LEARNED || pol->trace) return fail(GG_E_UNSUPPORTED, "BP with LEARNED or traces");
+    if (g->n_parts > 0) return fail(GG_E_UNSUPPORTED, "BP on a graph with parts");
+  }
   if (pol->kind < GG_POLICY_EXACT || pol->kind > GG_POLICY_LEARNED) return fail(GG_E_INVAL, "unknown policy kind");
   if (pol->kind == GG_POLICY_LEARNED) {
     if (!pol->mlp) return fail(GG_E_INVAL, "LEARNED needs a network");
@@ -739,7 +750,7 @@ int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const 
     return fail(GG_E_INVAL, "source out of range");
   }
   if (p->app == GG_APP_SSSP && !g->wedges) return fail(GG_E_INVAL, "SSSP needs edge weights");
-  const bool fixed_iters = is_pr(p->app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
+  const bool fixed_iters = is_float(p->app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
   if (fixed_iters && p->iters < 0) return fail(GG_E_INVAL, "iters < 0");
   if (!fixed_iters && p->max_iters <= 0) return fail(GG_E_INVAL, "max_iters must be > 0");
   return GG_OK;
@@ -769,6 +780,10 @@ Sweep base_sweep(const gg_graph* g, const gg_run* r, int32_t i) {
   s.mask_union = r->pol.mask_update == GG_MASK_UNION;
   s.act_edges = g->act_edges;
   s.act_cnt = g->act_cnt;
+  if (r->p.app == GG_APP_BP) {
+    s.bp_prior = g->bp_prior;
+    s.bp_kappa = r->p.coupling;
+  }
   if (r->pol.vstatus != GG_VSTATUS_NONE) {
     s.vact = g->vact;
     s.x_prev = g->x_prev;
@@ -893,6 +908,13 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
       GG_HIP(launch_fill_u32((uint32_t*)(g->dpartial + 256), 2, 0u, g->stream));
       if (parts) GG_HIP(launch_fill_u32((uint32_t*)g->part_dang, 2 * (int64_t)g->n_parts, 0u, g->stream));
     }
+  } else if (app == GG_APP_BP) {
+    // the run keeps its own copy of the prior
+    if (g->n > 0) {
+      if (!g->bp_prior) GG_TRY(dalloc(&g->bp_prior, (size_t)g->n));
+      GG_HIP(hipMemcpyAsync(g->bp_prior, p->prior, sizeof(float) * (size_t)g->n, hipMemcpyDeviceToDevice, g->stream));
+      GG_HIP(launch_bp_init(g->bp_prior, g->n, p->coupling, g->c[0], g->stream));
+    }
   } else {
     const int32_t src0 = parts ? -1 : p->source;
     GG_HIP(launch_min_init(app, g->n, src0, g->xu[0], g->stream));
@@ -959,7 +981,7 @@ int run_begin(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
     GG_HIP(launch_fill_u32((uint32_t*)g->feat, (int64_t)g->n * 4, 0u, g->stream));
     GG_HIP(launch_fill_u32((uint32_t*)g->audit, 4, 0u, g->stream));
   }
-  const bool fixed_iters = is_pr(app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
+  const bool fixed_iters = is_float(app) || (pol->kind != GG_POLICY_EXACT && pol->stop == GG_STOP_FIXED_ITERS);
   if (fixed_iters && p->iters == 0) r->done = true;
   g->active_run = owner.release();
   *out = r;
@@ -1001,7 +1023,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   if (r->done) return 0;
   const int32_t i = r->iter + 1;
   const int app = r->p.app;
-  const bool pr = is_pr(app);
+  const bool pr = is_float(app);  // binary32 values (PR, PPR, BP)
   const bool learned = r->pol.kind == GG_POLICY_LEARNED;
   int kind = step_kind(r->pol, i);
   int64_t selected = -1;
@@ -1033,7 +1055,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   Sweep s = base_sweep(g, r, i);
   const bool act_deg = active_degree_run(r);
   if (pr) {
-    if (r->p.dangling == GG_DANGLING_UNIFORM) {
+    if (is_pr(app) && r->p.dangling == GG_DANGLING_UNIFORM) {
       // with the ACTIVE out-degree an approximate iteration's dangling set is
       // the vertices without an active out-edge
       const bool ad = act_deg && kind == GG_STEP_APPROX;
@@ -1410,7 +1432,9 @@ int run_values(gg_run* r, void* out, uint32_t flags) {
   if (!out) return fail(GG_E_INVAL, "null output");
   // only a superstep can raise the hub error word
   if (r->supersteps > 0) GG_TRY(check_hub_sync(g));
-  if (is_pr(r->p.app)) {
+  if (r->p.app == GG_APP_BP && r->iter == 0)
+    return copy_out(g, g->bp_prior, out, sizeof(float) * (size_t)g->n, flags);  // the beliefs start at the prior
+  if (is_float(r->p.app)) {
     if (r->iter == 0) GG_TRY(pr_initial_x(r));
     if (!r->x_valid) return fail(GG_E_STATE, "PR values of this iteration were not materialized");
     return copy_out(g, g->xout, out, sizeof(float) * (size_t)g->n, flags);
@@ -1465,6 +1489,7 @@ int state_check_kind(const gg_run* r) {
   if (r->pol.vstatus != GG_VSTATUS_NONE)
     return fail(GG_E_UNSUPPORTED, "run state of runs with vertex status (it spans two iterations)");
   if (active_degree_run(r)) return fail(GG_E_UNSUPPORTED, "run state of runs with the ACTIVE out-degree");
+  if (r->p.app == GG_APP_BP) return fail(GG_E_UNSUPPORTED, "run state of BP runs");
   return GG_OK;
 }
 
@@ -1703,6 +1728,7 @@ NoAllocLayout noalloc_layout(const gg_graph* g) {
 int exact_noalloc(gg_graph* g, const gg_app_params* p, void* out, gg_run_stats* st) {
   if (!g || !p || !out) return fail(GG_E_INVAL, "null argument");
   const int app = p->app;
+  if (app == GG_APP_BP) return fail(GG_E_UNSUPPORTED, "BP runs");
   if (app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "unknown app");
   if (p->iters < 1) return fail(GG_E_INVAL, "iters must be >= 1");
   const bool pr = is_pr(app);
@@ -2260,7 +2286,7 @@ int gg_graph_set_profiling(gg_graph* g, int enable) {
 int gg_graph_get_profile(gg_graph* g, int kind, int app, gg_kernel_profile* out) {
   return guard([&]() -> int {
     if (!g || !out) return fail(GG_E_INVAL, "null argument");
-    if (kind < 0 || kind > 4 || app < GG_APP_PR || app > GG_APP_PPR) return fail(GG_E_INVAL, "bad kind or app");
+    if (kind < 0 || kind > 4 || app < GG_APP_PR || app > GG_APP_BP) return fail(GG_E_INVAL, "bad kind or app");
     GG_HIP(hipStreamSynchronize(g->stream));
     gg_kernel_profile p{0, 0.0, 0.0, 0};
     for (const auto& r : g->recs) {

@@ -21,6 +21,35 @@ REPLAY_BAND = 1e-4
 VSTATUS_BAND = 1e-6
 
 
+def bp_flip_justified(g, flips, lo_prev, lg_prev, kappa, theta):
+    """Replay check of BP edge flags that differ after a superstep.
+
+    Both sides decide |c_e| > theta |P_e| (c_e the binary32 message of the
+    edge's source, P_e the running sum of its row up to and including e) on
+    their own beliefs of the previous iteration. A flag may differ only where
+    the oracle's decision margin |c_e| - theta |P_e| is within four times the
+    change of that margin between the two sides' beliefs (the GPU's given as
+    its binary32 output), plus a relative 1e-4 theta |P_e| and a rounding
+    term 1e-6 (|c_e| + theta S_e), S_e the running sum of |c|. Returns the
+    edges that fail the check."""
+    bad = []
+    rowptr, col = np.asarray(g.rowptr), np.asarray(g.col)
+    msg = lambda L: (2.0 * np.arctanh(kappa * np.tanh(0.5 * np.asarray(L, dtype=np.float64)))).astype(np.float32)
+    for e in np.asarray(flips).tolist():
+        u = int(np.searchsorted(rowptr, e, side="right") - 1)
+        src = col[rowptr[u]:e + 1]
+        margins = []
+        for L in (lo_prev, lg_prev):
+            c = msg(L[src]).astype(np.float64)
+            P = c.sum()
+            margins.append((abs(c[-1]) - theta * abs(P), abs(c[-1]), abs(P), np.abs(c).sum()))
+        (mo, co, po, so), (mg, _, _, _) = margins
+        allow = 4.0 * abs(mo - mg) + REPLAY_BAND * theta * po + 1e-6 * (co + theta * so)
+        if abs(mo) > allow:
+            bad.append((e, mo, mg, allow))
+    return bad
+
+
 def log(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -51,7 +80,7 @@ def device_values(t, app):
 
 
 def compare_values(app, got, want, ctx=""):
-    if app in ("pr", "ppr"):
+    if app in ("pr", "ppr", "bp"):
         err = rel_l1(got, want)
         assert err <= PR_TOL, "%s rel L1 %.3e > %.0e" % (ctx, err, PR_TOL)
         return err
@@ -162,6 +191,7 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
     vflips_total = 0
     vs = kw.get("vstatus", "none")
     ov_prev = O.values() if vs != "none" else None
+    bp_prev = (O.values(), R.values().astype(np.float64)) if app == "bp" else None
     while True:
         a = R.step()
         b = O.step()
@@ -189,17 +219,24 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
                 theta = kw.get("theta0", kw.get("theta")) if b.iter == kw.get("alpha0", -2) + 1 else kw.get("theta")
                 log("flips at iter", b.iter, ":", flips.size, "edges, first", flips[:5].tolist(), "oracle influence",
                     infl[flips[:5]].tolist(), "theta", theta)
-                assert app in ("pr", "ppr"), "%d SSSP/CC edge flags differ after superstep %d" % (flips.size, b.iter)
-                dist = np.abs(infl[flips] - theta)
-                assert np.all(dist <= REPLAY_BAND * theta), \
-                    "flag differs away from theta: influence %r" % infl[flips[dist > REPLAY_BAND * theta][:5]].tolist()
+                assert app in ("pr", "ppr", "bp"), "%d SSSP/CC edge flags differ after superstep %d" % (flips.size,
+                                                                                                    b.iter)
+                if app == "bp":
+                    bad = bp_flip_justified(g, flips, bp_prev[0], bp_prev[1], kw.get("coupling", 0.0), theta)
+                    assert not bad, "BP flag differs away from its decision band: %r" % bad[:5]
+                else:
+                    dist = np.abs(infl[flips] - theta)
+                    assert np.all(dist <= REPLAY_BAND * theta), \
+                        "flag differs away from theta: influence %r" % infl[flips[dist > REPLAY_BAND * theta][:5]].tolist()
                 O.set_mask(gm)
                 flips_total += int(flips.size)
             assert a["active_edges"] == int(gm.sum())
         gv = R.values()
         ov = O.values()
-        if app in ("pr", "ppr"):
+        if app in ("pr", "ppr", "bp"):
             worst = max(worst, rel_l1(gv, ov))
+        if app == "bp":
+            bp_prev = (ov, gv.astype(np.float64))
         compare_values(app, gv, ov, ctx="iter %d" % b.iter)
         if vs != "none":
             # vertex status: equal except within the band of its bound, where
@@ -217,7 +254,7 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
                 O.set_vactive(ga)
                 vflips_total += int(diff.size)
             ov_prev = ov
-    log("replay: %d PageRank flags adopted from the GPU over the run" % flips_total)
+    log("replay: %d edge flags adopted from the GPU over the run" % flips_total)
     if vs != "none":
         log("replay: %d vertex statuses adopted from the GPU over the run" % vflips_total)
     if stats is not None:

@@ -1,6 +1,7 @@
 """CPU-side checks of the C-ABI library: it loads, it exports every entry
 point that include/gg.h declares, and the binding declares a signature for
 each. No compute call is made (there is no GPU here)."""
+import ctypes
 import os
 import re
 import subprocess
@@ -62,3 +63,30 @@ def test_product_does_not_touch_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.lower().replace("oracle-", ""), f
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the header's struct (gcc on the host)."""
+    import paper_2104_10039_amd as P
+    pairs = {"gg_csr_desc": P.CsrDesc, "gg_app_params": P.AppParams, "gg_correction_policy": P.Policy,
+             "gg_run_stats": P.RunStats, "gg_step_info": P.StepInfo, "gg_kernel_profile": P.KernelProfile,
+             "gg_tuning": P.Tuning}
+    lines = ['#include <stdio.h>', '#include "gg.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in cls._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = str(tmp_path / "layout")
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", exe, str(src)])
+    got = {}
+    for line in subprocess.check_output([exe]).decode().splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
