@@ -118,6 +118,10 @@ def _lib():
     lib.ggo_bf16_array.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
     lib.ggo_bf16_value.restype = ctypes.c_float
     lib.ggo_bf16_value.argtypes = [ctypes.c_uint16]
+    lib.ggo_run_update.restype = ctypes.c_int
+    lib.ggo_run_update.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Csr), ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int32]
+    lib.ggo_get_reset.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.ggo_bp_message.restype = ctypes.c_double
     lib.ggo_bp_message.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.ggo_lg_feature.restype = ctypes.c_float
@@ -234,6 +238,31 @@ class Run:
         out = np.empty(max(self.m, 1), dtype=np.uint8)
         self._lib.ggo_get_mask(self._h, out.ctypes.data)
         return out[: self.m]
+
+    def update(self, upd: "Update", more_iters: int = 0):
+        """Continue this run on the graph after an update batch (ggo_run_update)."""
+        if upd.graph.n != self.n:
+            raise ValueError("the vertex set of an update is fixed")
+        g = upd.graph
+        rp = np.ascontiguousarray(g.rowptr, dtype=np.int32)
+        col = np.ascontiguousarray(g.col, dtype=np.int32)
+        w = None if g.weight is None else np.ascontiguousarray(g.weight, dtype=np.int32)
+        oon = np.ascontiguousarray(upd.old_of_new, dtype=np.int64)
+        dele = np.ascontiguousarray(upd.deleted_old, dtype=np.uint8)
+        m = int(rp[-1])
+        csr = _Csr(self.n, m, rp.ctypes.data, col.ctypes.data, None if w is None else w.ctypes.data)
+        if self._lib.ggo_run_update(self._h, ctypes.byref(csr), oon.ctypes.data if m else None,
+                                    dele.ctypes.data if self.m else None, int(more_iters)) != 0:
+            raise ValueError("oracle: " + self._lib.ggo_last_error().decode())
+        # the run reads the new arrays until it ends
+        self._rowptr, self._col, self._w = rp, col, w
+        self.m = m
+
+    def reset_vertices(self) -> np.ndarray:
+        """Vertices whose value the last update reset (one byte per vertex)."""
+        out = np.empty(max(self.n, 1), dtype=np.uint8)
+        self._lib.ggo_get_reset(self._h, out.ctypes.data)
+        return out[: self.n]
 
     def set_mask(self, mask):
         """Adopt another side's edge flags (one value per edge, nonzero = active)."""
@@ -372,3 +401,80 @@ def adam_step(params, m, v, grad, lr, t):
 def bp_message(L, coupling):
     """The oracle's BP message log-ratio of a sender with log-odds L."""
     return float(_lib().ggo_bp_message(float(L), float(coupling)))
+
+
+# ---------------------------------------------------------------------------
+# Dynamic graphs: the graph after an update batch (plain definition)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class UpdatedCsr:
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    weight: Optional[np.ndarray] = None
+
+    @property
+    def m(self) -> int:
+        return int(self.rowptr[-1])
+
+
+@dataclass
+class Update:
+    graph: UpdatedCsr
+    old_of_new: np.ndarray   # int64[m_new]: the old edge each new edge continues, -1 if inserted
+    deleted_old: np.ndarray  # uint8[m_old]: 1 for every old edge the batch removed
+
+
+def apply_update(g, del_src, del_dst, ins_src, ins_dst, ins_weight=None) -> Update:
+    """The in-CSR after an update batch. Deletions remove every arc s -> d of
+    the graph that matches a listed pair (s, d); insertions then add one arc
+    per listed triple. Each row stays sorted by source; among arcs with the
+    same source, the surviving ones come first in their old order, then the
+    inserted ones in batch order. The vertex set is fixed. The rows of g
+    must be sorted by source (the canonical in-CSR)."""
+    n = int(g.n)
+    rowptr = np.asarray(g.rowptr, dtype=np.int64)
+    col = np.asarray(g.col, dtype=np.int64)
+    m = int(rowptr[-1])
+    dst = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    if m > 1 and np.any((dst[1:] == dst[:-1]) & (col[1:] < col[:-1])):
+        raise ValueError("a row is not sorted by source")
+    del_src = np.asarray(del_src, dtype=np.int64)
+    del_dst = np.asarray(del_dst, dtype=np.int64)
+    ins_src = np.asarray(ins_src, dtype=np.int64)
+    ins_dst = np.asarray(ins_dst, dtype=np.int64)
+    for a in (del_src, del_dst, ins_src, ins_dst):
+        if a.size and (a.min() < 0 or a.max() >= n):
+            raise ValueError("vertex id out of range")
+    if ins_src.size != ins_dst.size or del_src.size != del_dst.size:
+        raise ValueError("source and destination lists differ in length")
+    if g.weight is None and ins_weight is not None:
+        raise ValueError("weights inserted into a graph without weights")
+    if g.weight is not None:
+        if ins_weight is None:
+            ins_weight = np.zeros(0, dtype=np.int64) if ins_src.size == 0 else None
+        if ins_weight is None or np.asarray(ins_weight).size != ins_src.size:
+            raise ValueError("a weighted graph needs one weight per inserted arc")
+        if np.asarray(ins_weight).size and (np.min(ins_weight) < 0 or np.max(ins_weight) > 255):
+            raise ValueError("weight outside [0, 255]")
+    deleted = np.isin(col * n + dst, del_src * n + del_dst)
+    keep = np.nonzero(~deleted)[0]
+    k_ins = ins_src.size
+    # every arc of the new graph: (destination, source, group 0 = old / 1 = inserted, order within group)
+    d_all = np.concatenate([dst[keep], ins_dst])
+    s_all = np.concatenate([col[keep], ins_src])
+    grp = np.concatenate([np.zeros(keep.size, dtype=np.int64), np.ones(k_ins, dtype=np.int64)])
+    within = np.concatenate([keep, np.arange(k_ins, dtype=np.int64)])
+    order = np.lexsort((within, grp, s_all, d_all))
+    new_rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(new_rowptr, d_all + 1, 1)
+    new_rowptr = np.cumsum(new_rowptr)
+    old_of_new = np.where(grp[order] == 0, within[order], -1)
+    weight = None
+    if g.weight is not None:
+        w_all = np.concatenate([np.asarray(g.weight, dtype=np.int64)[keep],
+                                np.asarray(ins_weight, dtype=np.int64).reshape(-1)])
+        weight = w_all[order].astype(np.int32)
+    out = UpdatedCsr(n, new_rowptr.astype(np.int32), s_all[order].astype(np.int32), weight)
+    return Update(out, old_of_new.astype(np.int64), deleted.astype(np.uint8))

@@ -18,6 +18,8 @@
  *    with threshold theta, deactivating all others; supersteps recur with the
  *    same alpha [Sec. 3.4].
  *  - SP and SMS schemes [Sec. 5.2].
+ *  - Dynamic graphs: a run continues on the graph after an update batch
+ *    (ggo_run_update; Sec. 1 states the method applies to changing graphs).
  *
  * Readings where the paper is silent (each is a flag where a variant exists):
  *  - Iteration i (1-based) is accurate for GG iff i mod (alpha+1) == 0; for
@@ -368,6 +370,9 @@ struct ggo_run {
   uint8_t* vact;     /* vertex status after the last iteration (GG-VStatus) */
   uint8_t* skip;     /* rows not recomputed in this iteration (GG-VStatus) */
   double theta_now;  /* threshold of this iteration's superstep */
+  /* dynamic graphs */
+  int32_t converged; /* an exact SSSP/CC run that ended on a no-change iteration */
+  uint8_t* reset;    /* vertices reset by the last update */
 };
 
 /* Superstep (correction step) of GG and LEARNED at iteration i, 1-based:
@@ -487,6 +492,7 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
   r->vact = (uint8_t*)malloc((size_t)n + 1);
   memset(r->vact, 1, (size_t)n + 1); /* every vertex starts active */
   r->skip = (uint8_t*)calloc((size_t)n + 1, 1);
+  r->reset = (uint8_t*)calloc((size_t)n + 1, 1);
   r->theta_now = pol->theta;
 
   /* Initial sparsification [Sec. 3.4]: each edge kept iff its draw falls
@@ -983,6 +989,7 @@ int ggo_step(ggo_run* r, ggo_step_info* info) {
   if (app == GGO_PR || app == GGO_PPR || app == GGO_BP) {
     if (i >= r->app.iters) r->done = 1;
   } else if (p->kind == GGO_EXACT) {
+    if (changed == 0) r->converged = 1;
     if (changed == 0 || i >= r->app.max_iters) r->done = 1;
   } else if (p->stop == GGO_STOP_FIXED_ITERS) {
     if (i >= r->app.iters) r->done = 1;
@@ -997,6 +1004,103 @@ int ggo_step(ggo_run* r, ggo_step_info* info) {
 }
 
 int ggo_done(const ggo_run* r) { return r->done; }
+
+/* ---------------------------------------------------------------------------
+ * Dynamic graphs. An SSSP/CC value at a converged exact run is the length of
+ * a shortest path (the smallest label that reaches the vertex). Edge s -> d
+ * "supports" d when it realises d's value: x_s + w = x_d for SSSP (d not the
+ * source, both finite), l_s = l_d for CC (l_d not d's own id). After
+ * deletions a value can only be wrong if every path realising it used a
+ * deleted edge; walking such a path back from the vertex meets a deleted
+ * supporting edge, so the closure below (seeded at the targets of deleted
+ * supporting edges, grown along supporting edges of the new graph) contains
+ * every vertex whose value may have become too small. Those restart from
+ * their initial values; every other value is still exact.
+ * ------------------------------------------------------------------------- */
+static int supports(const ggo_run* r, int32_t s, int32_t d, int32_t w) {
+  if (r->app.app == GGO_SSSP) {
+    if (d == r->app.source || r->d_x[s] == GGO_INF_U32 || r->d_x[d] == GGO_INF_U32) return 0;
+    return (uint64_t)r->d_x[s] + (uint64_t)w == (uint64_t)r->d_x[d];
+  }
+  return r->l_x[s] == r->l_x[d] && r->l_x[d] != d;
+}
+
+int ggo_run_update(ggo_run* r, const ggo_csr* gn, const int64_t* old_of_new, const uint8_t* deleted_old,
+                   int32_t more_iters) {
+  if (!r || !gn || (gn->m > 0 && !old_of_new) || (r->g.m > 0 && !deleted_old)) { set_err("null argument"); return -1; }
+  if (gn->n != r->g.n) { set_err("the vertex set of an update is fixed"); return -1; }
+  if (more_iters < 0) { set_err("more_iters < 0"); return -1; }
+  if (r->pol.kind == GGO_LEARNED || r->pol.trace || r->pol.vstatus != GGO_VSTATUS_NONE ||
+      r->app.pr_degree != GGO_DEGREE_FULL) {
+    set_err("updates of LEARNED, traced, vertex-status or ACTIVE-degree runs");
+    return -1;
+  }
+  if ((r->g.weight != NULL) != (gn->weight != NULL)) { set_err("weights on one side only"); return -1; }
+  const int32_t n = gn->n;
+  const int64_t m0 = r->g.m, m1 = gn->m;
+  for (int64_t e = 0; e < m1; ++e)
+    if (old_of_new[e] < -1 || old_of_new[e] >= m0) { set_err("old_of_new out of range"); return -1; }
+  const int app = r->app.app;
+  int any_deleted = 0;
+  for (int64_t e = 0; e < m0; ++e) any_deleted |= deleted_old[e] != 0;
+  memset(r->reset, 0, (size_t)n + 1);
+  if ((app == GGO_SSSP || app == GGO_CC) && any_deleted) {
+    if (r->pol.kind == GGO_EXACT && r->converged) {
+      /* seeds: targets of deleted supporting edges (old graph) */
+      for (int32_t u = 0; u < n; ++u)
+        for (int32_t e = r->g.rowptr[u]; e < r->g.rowptr[u + 1]; ++e)
+          if (deleted_old[e] && supports(r, r->g.col[e], u, r->g.weight ? r->g.weight[e] : 0)) r->reset[u] = 1;
+      /* closure along supporting edges of the new graph */
+      int grew = 1;
+      while (grew) {
+        grew = 0;
+        for (int32_t v = 0; v < n; ++v) {
+          if (r->reset[v]) continue;
+          for (int32_t e = gn->rowptr[v]; e < gn->rowptr[v + 1]; ++e) {
+            const int32_t p = gn->col[e];
+            if (r->reset[p] && supports(r, p, v, gn->weight ? gn->weight[e] : 0)) {
+              r->reset[v] = 1;
+              grew = 1;
+              break;
+            }
+          }
+        }
+      }
+    } else {
+      memset(r->reset, 1, (size_t)n);
+    }
+    for (int32_t v = 0; v < n; ++v) {
+      if (!r->reset[v]) continue;
+      if (app == GGO_SSSP) r->d_x[v] = v == r->app.source ? 0u : GGO_INF_U32;
+      else r->l_x[v] = v;
+    }
+  }
+  /* edge flags: a surviving edge keeps its flag, an inserted edge is active */
+  uint8_t* act = (uint8_t*)calloc((size_t)m1 + 1, 1);
+  for (int64_t e = 0; e < m1; ++e) act[e] = old_of_new[e] >= 0 ? r->active[old_of_new[e]] : 1;
+  free(r->active);
+  r->active = act;
+  free(r->infl);
+  r->infl = (double*)calloc((size_t)m1 + 1, sizeof(double));
+  r->g = *gn;
+  memset(r->outdeg, 0, sizeof(int32_t) * ((size_t)n + 1));
+  for (int64_t e = 0; e < m1; ++e) r->outdeg[gn->col[e]]++;
+  for (int32_t u = 0; u < n; ++u) r->indeg[u] = gn->rowptr[u + 1] - gn->rowptr[u];
+  r->converged = 0;
+  const int fixed_iters = app == GGO_PR || app == GGO_PPR || app == GGO_BP || r->pol.stop == GGO_STOP_FIXED_ITERS;
+  if (fixed_iters) {
+    if (r->app.iters < r->iter) r->app.iters = r->iter;
+    r->app.iters += more_iters;
+    r->done = r->iter >= r->app.iters;
+  } else {
+    if (r->app.max_iters < r->iter) r->app.max_iters = r->iter;
+    r->app.max_iters += more_iters;
+    r->done = r->iter >= r->app.max_iters;
+  }
+  return 0;
+}
+
+void ggo_get_reset(const ggo_run* r, uint8_t* out) { memcpy(out, r->reset, (size_t)r->g.n); }
 int32_t ggo_iterations(const ggo_run* r) { return r->iter; }
 int64_t ggo_edges_total(const ggo_run* r) { return r->edges_total; }
 
@@ -1059,6 +1163,7 @@ void ggo_end(ggo_run* r) {
   free(r->odeg_act);
   free(r->vact);
   free(r->skip);
+  free(r->reset);
   free(r->pr_x);
   free(r->pr_xn);
   free(r->pr_sh);

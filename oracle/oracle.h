@@ -171,6 +171,24 @@ void ggo_get_features(const ggo_run* r, uint16_t* out);
 int ggo_get_selection(const ggo_run* r, uint8_t* sel, double* logits);
 /* Drift labels of this step (traced full supersteps); 0 if none. */
 int ggo_get_labels(const ggo_run* r, uint8_t* out);
+/* Dynamic graphs (the paper states GraphGuess applies to changing graphs
+   and evaluates none; the reading is the oracle's): the run continues on
+   g_new, the graph after an update batch, with the same vertex set.
+   old_of_new[e] is the old edge that new edge e continues, or -1 for an
+   inserted edge; deleted_old[e] is 1 for every old edge the batch removed.
+   Surviving edges keep their flags and inserted edges are active.
+   PR/PPR/BP values continue (the next iteration divides by the new
+   out-degrees). SSSP/CC after a deletion: a converged exact run resets the
+   vertices whose value may rest on a deleted edge (a taint closure over
+   supporting edges), any other run restarts from the initial values.
+   more_iters (>= 0) extends the run: fixed-count runs raise their
+   iteration count, fixed-point runs their cap, and the run resumes.
+   LEARNED, traced, vertex-status and ACTIVE-degree runs are refused.
+   g_new's arrays must outlive the run. Returns 0, or -1 with a message. */
+int ggo_run_update(ggo_run* r, const ggo_csr* g_new, const int64_t* old_of_new, const uint8_t* deleted_old,
+                   int32_t more_iters);
+/* Vertices reset by the last update (one byte per vertex). */
+void ggo_get_reset(const ggo_run* r, uint8_t* out);
 void ggo_end(ggo_run* r);
 
 /* bfloat16: round to nearest even from binary32 (NaN -> 0x7FC0), and back. */

@@ -3,7 +3,8 @@
 Each case plants one mistake in a temporary copy of oracle/oracle.c (a
 dropped term, a wrong index or operand, an off-by-one, a non-strict
 comparison), builds that copy,
-and runs the pin suite (tests/test_oracle_pins.py) against it in a child
+and runs the pin suites (tests/test_oracle_pins.py, tests/test_oracle_dynamic.py)
+against it in a child
 process; at least one pin must fail. The oracle itself is never modified.
 """
 import os
@@ -79,6 +80,17 @@ MUTANTS = {
     # BP influence on signed values instead of magnitudes
     "bp_influence_signed": ("r->infl[e] = fabs(P) > 0.0 ? fabs(c) / fabs(P) : 0.0;",
                             "r->infl[e] = P > 0.0 ? c / P : 0.0;"),
+    # dynamic update: the taint closure never grows beyond its seeds
+    "update_no_closure": ("      int grew = 1;\n      while (grew) {", "      int grew = 0;\n      while (grew) {"),
+    # dynamic update: every deleted arc seeds, supporting or not
+    "update_seed_ignores_support": ("if (deleted_old[e] && supports(r, r->g.col[e], u, r->g.weight ? r->g.weight[e] : 0))",
+                                    "if (deleted_old[e])"),
+    # dynamic update: inserted arcs start inactive
+    "update_inserted_inactive": ("act[e] = old_of_new[e] >= 0 ? r->active[old_of_new[e]] : 1;",
+                                 "act[e] = old_of_new[e] >= 0 ? r->active[old_of_new[e]] : 0;"),
+    # dynamic update: out-degrees of the old graph kept
+    "update_stale_outdeg": ("  memset(r->outdeg, 0, sizeof(int32_t) * ((size_t)n + 1));\n"
+                            "  for (int64_t e = 0; e < m1; ++e) r->outdeg[gn->col[e]]++;", ""),
 }
 
 
@@ -92,7 +104,8 @@ def run_pins_against(tmp_path, src):
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", lib, str(tmp_path / "oracle.c"), "-lm"])
     env = dict(os.environ, GGO_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_dynamic.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode, r.stdout
 
