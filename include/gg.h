@@ -423,6 +423,74 @@ int gg_run_import_state(gg_run* run, const void* state_host, int64_t bytes);
 void gg_run_end(gg_run* run);
 
 /*
+ * Dynamic graphs. The paper states that the method applies to graphs that
+ * change [Sec. 1] and evaluates static ones only; the update rules below are
+ * this library's reading.
+ *
+ * An update batch first deletes every arc s -> d of the graph that matches a
+ * listed pair (del_src[i], del_dst[i]) (pairs that match nothing are
+ * ignored), then inserts one arc ins_src[j] -> ins_dst[j] per entry, with
+ * weight ins_weight[j] in [0, 255] (given exactly when the graph has
+ * weights). The vertex set is fixed. Each row stays sorted by source; among
+ * arcs with the same source the surviving ones come first in their old
+ * order, then the inserted ones in batch order. The graph must have rows
+ * sorted by source (the canonical in-CSR; GG_E_UNSUPPORTED otherwise) and
+ * no parts. After an update the graph owns its CSR arrays (a borrowed device
+ * CSR is no longer read), and the result is as if the new CSR had been
+ * loaded with the graph's tuning.
+ *   del_src/del_dst  int32[n_delete]; ins_src/ins_dst/ins_weight int32[n_insert]
+ *   flags            GG_UPDATE_DEVICE_PTRS: the arrays are device pointers
+ *                    (default: host), read during the call only
+ * Errors: GG_E_INVAL (null arrays, negative counts, weights given or missing
+ * against the graph), GG_E_RANGE (a vertex id outside [0, n), a weight
+ * outside [0, 255], more than 2^31 - 1 arcs after the update), GG_E_NOMEM.
+ * On an error the graph and any run on it are unchanged.
+ */
+#define GG_UPDATE_DEVICE_PTRS 0x1u
+typedef struct {
+  int64_t n_delete;
+  const int32_t* del_src;
+  const int32_t* del_dst;
+  int64_t n_insert;
+  const int32_t* ins_src;
+  const int32_t* ins_dst;
+  const int32_t* ins_weight;
+  uint32_t flags;
+} gg_update_batch;
+
+/* Applies a batch to a graph with no active run (GG_E_STATE otherwise). */
+int gg_graph_update(gg_graph* g, const gg_update_batch* batch);
+
+/* Applies a batch to the graph of an active run, which then continues on the
+ * new graph:
+ *  - edge flags: a surviving arc keeps its flag, an inserted arc is active
+ *    (no superstep has assessed it); the next superstep re-selects it;
+ *  - PR/PPR/BP values continue from the current ones; the next iteration
+ *    divides by the new out-degrees;
+ *  - SSSP/CC: insertions keep every value. After a deletion, a converged
+ *    exact run (one that ended on an iteration that changed nothing) resets
+ *    only the vertices whose value may rest on a deleted arc: the closure,
+ *    along arcs of the new graph that realise their destination's value
+ *    (x_s + w = x_d; CC l_s = l_d != d), of the destinations of deleted arcs
+ *    that did; every other value is still exact. Any other SSSP/CC run
+ *    restarts from its initial values. A converged exact run with the
+ *    frontier enabled resumes with a push from the in-neighbours of the
+ *    reset vertices and the sources of the inserted arcs; others resume
+ *    with a dense iteration;
+ *  - the run continues its iteration numbering and schedule for more_iters
+ *    (>= 0) further iterations: fixed-count runs raise their count,
+ *    fixed-point runs their cap, and the run is no longer done.
+ * reset_host (nullable, n bytes) receives 1 for every vertex whose value was
+ * reset. LEARNED, traced, vertex-status and ACTIVE-degree runs:
+ * GG_E_UNSUPPORTED. */
+int gg_run_update(gg_run* run, const gg_update_batch* batch, int32_t more_iters, uint8_t* reset_host);
+
+/* Host copies of the graph's in-CSR: rowptr_host int32[n+1] (required),
+ * col_host int32[m] (nullable), weight_host int32[m] (nullable; GG_E_INVAL
+ * when requested from a graph without weights). */
+int gg_graph_get_csr(gg_graph* g, int32_t* rowptr_host, int32_t* col_host, int32_t* weight_host);
+
+/*
  * Tuning knobs of the degree-binned sweep (set directly or by gg_graph_autotune):
  * rows of degree <= small_max are processed by teams of small_team lanes
  * (4, 8, 16 or 32); rows of degree <= wave_max by one 64-lane wavefront;

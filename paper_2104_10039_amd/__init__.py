@@ -57,6 +57,37 @@ class AppParams(ctypes.Structure):
                 ("pr_degree", ctypes.c_int32), ("coupling", ctypes.c_double), ("prior", ctypes.c_void_p)]
 
 
+class UpdateBatch(ctypes.Structure):
+    _fields_ = [("n_delete", ctypes.c_int64), ("del_src", ctypes.c_void_p), ("del_dst", ctypes.c_void_p),
+                ("n_insert", ctypes.c_int64), ("ins_src", ctypes.c_void_p), ("ins_dst", ctypes.c_void_p),
+                ("ins_weight", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+UPDATE_DEVICE_PTRS = 0x1
+
+
+def _batch(del_src=(), del_dst=(), ins_src=(), ins_dst=(), ins_weight=None):
+    """gg_update_batch over host int32 copies (returned with the struct, which
+    points into them). Device tensors (int32, contiguous) are passed as
+    device pointers."""
+    arrs = [del_src, del_dst, ins_src, ins_dst]
+    dev = any(isinstance(a, torch.Tensor) and a.is_cuda for a in arrs + [ins_weight])
+    if dev:
+        keep = [None if a is None else a.to(device="cuda", dtype=torch.int32).contiguous() for a in arrs + [ins_weight]]
+        ptr = lambda a: None if a is None or a.numel() == 0 else a.data_ptr()
+        cnt = lambda a: 0 if a is None else int(a.numel())
+    else:
+        keep = [None if a is None else np.ascontiguousarray(np.asarray(a), dtype=np.int32) for a in arrs + [ins_weight]]
+        ptr = lambda a: None if a is None or a.size == 0 else a.ctypes.data
+        cnt = lambda a: 0 if a is None else int(a.size)
+    ds, dd, is_, id_, iw = keep
+    if cnt(ds) != cnt(dd) or cnt(is_) != cnt(id_) or (iw is not None and cnt(iw) != cnt(is_)):
+        raise ValueError("source, destination and weight lists must have equal lengths")
+    b = UpdateBatch(cnt(ds), ptr(ds), ptr(dd), cnt(is_), ptr(is_), ptr(id_), ptr(iw),
+                    UPDATE_DEVICE_PTRS if dev else 0)
+    return b, keep
+
+
 class Policy(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("alpha", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("influence", ctypes.c_int32), ("mask_update", ctypes.c_int32),
@@ -116,6 +147,9 @@ SIGNATURES = {
     "gg_run_vstatus": (ctypes.c_int, [_VP, _VP]),
     "gg_run_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(RunStats)]),
     "gg_run_end": (None, [_VP]),
+    "gg_graph_update": (ctypes.c_int, [_VP, _VP]),
+    "gg_run_update": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP]),
+    "gg_graph_get_csr": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "gg_graph_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "gg_graph_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "gg_batch_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_int32, _VP, ctypes.c_double,
@@ -509,6 +543,30 @@ class Graph:
     def begin(self, app, sample_ratio=1.0, policy="exact", **kw) -> "Run":
         return Run(self, app, sample_ratio, policy, **kw)
 
+    def update(self, del_src=(), del_dst=(), ins_src=(), ins_dst=(), ins_weight=None):
+        """gg_graph_update: delete every arc matching (del_src[i], del_dst[i]),
+        then insert ins_src[j] -> ins_dst[j] (weight ins_weight[j] on weighted
+        graphs). No run may be active."""
+        b, keep = _batch(del_src, del_dst, ins_src, ins_dst, ins_weight)
+        _check(lib().gg_graph_update(self._h, ctypes.byref(b)))
+        self.m = self._csr_m()
+        self._keep = None  # the graph owns its CSR now
+
+    def _csr_m(self) -> int:
+        rp = np.empty(self.n + 1, dtype=np.int32)
+        _check(lib().gg_graph_get_csr(self._h, rp.ctypes.data, None, None))
+        return int(rp[-1])
+
+    def csr(self, weights=False):
+        """Host copies (rowptr, col, weight or None) of the graph's in-CSR."""
+        rp = np.empty(self.n + 1, dtype=np.int32)
+        _check(lib().gg_graph_get_csr(self._h, rp.ctypes.data, None, None))
+        m = int(rp[-1])
+        col = np.empty(max(m, 1), dtype=np.int32)
+        w = np.empty(max(m, 1), dtype=np.int32) if weights else None
+        _check(lib().gg_graph_get_csr(self._h, rp.ctypes.data, col.ctypes.data, None if w is None else w.ctypes.data))
+        return rp, col[:m], None if w is None else w[:m]
+
 
 class Run:
     """Step API (gg_run_begin / gg_run_step / gg_run_values / gg_run_mask /
@@ -577,6 +635,16 @@ class Run:
         out = torch.empty(self.graph.n, dtype=_value_dtype(self.app), device="cuda")
         _check(lib().gg_run_values(self._h, out.data_ptr(), 0))
         return out
+
+    def update(self, del_src=(), del_dst=(), ins_src=(), ins_dst=(), ins_weight=None, more_iters=0):
+        """gg_run_update: apply an update batch to the run's graph and continue
+        for more_iters further iterations. Returns the reset vertices (uint8[n])."""
+        b, keep = _batch(del_src, del_dst, ins_src, ins_dst, ins_weight)
+        reset = np.zeros(max(self.graph.n, 1), dtype=np.uint8)
+        _check(lib().gg_run_update(self._h, ctypes.byref(b), int(more_iters), reset.ctypes.data))
+        self.graph.m = self.graph._csr_m()
+        self.graph._keep = None
+        return reset[: self.graph.n]
 
     def mask_bits(self) -> np.ndarray:
         nw = (self.graph.m + 31) // 32

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgg.so")
-SOURCES = ["gg_kernels.hip", "gg_batch.hip", "gg_mlp.hip", "gg_runtime.hip"]
+SOURCES = ["gg_kernels.hip", "gg_batch.hip", "gg_mlp.hip", "gg_update.hip", "gg_runtime.hip"]
 ARCH = os.environ.get("GG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

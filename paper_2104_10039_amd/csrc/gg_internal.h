@@ -334,4 +334,57 @@ hipError_t launch_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_
 hipError_t launch_clear_rows(const int32_t* list, int32_t n_short, int32_t count, const int32_t* rowptr,
                              uint32_t* bits, hipStream_t st);
 
+// ---- dynamic graphs (gg_update.hip) -----------------------------------------
+// flags |= 1 for a vertex id outside [0, n), |= 2 for a weight outside [0, 255].
+hipError_t launch_batch_check(const int32_t* src, const int32_t* dst, const int32_t* w, int64_t k, int32_t n,
+                              int32_t* flags, hipStream_t st);
+// keys[j] = (dst[j] << 32) | src[j]; idx[j] = j when idx is non-null.
+hipError_t launch_arc_keys(const int32_t* src, const int32_t* dst, int64_t k, uint64_t* keys, int32_t* idx,
+                           hipStream_t st);
+// Temporary storage of the stable 64-bit radix sorts below.
+hipError_t sort_keys_bytes(int64_t k, size_t* bytes);
+hipError_t sort_pairs_bytes(int64_t k, size_t* bytes);
+hipError_t launch_sort_keys(const uint64_t* in, uint64_t* out, int64_t k, void* temp, size_t bytes, hipStream_t st);
+hipError_t launch_sort_pairs(const uint64_t* kin, uint64_t* kout, const int32_t* vin, int32_t* vout, int64_t k,
+                             void* temp, size_t bytes, hipStream_t st);
+// keep[e] = 0 iff edge e's arc is in the sorted deletion keys. With x
+// non-null, destinations of deleted edges that support their value are
+// appended to list (count) once each (taint[v] set).
+hipError_t launch_mark_kept(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
+                            const uint64_t* dkeys, int64_t nd, int32_t* keep, int app, const uint32_t* x,
+                            int32_t source, int32_t* taint, int32_t* list, int32_t* count, hipStream_t st);
+// ins_rp[u] (u in [0, n]) = first sorted insertion with destination >= u.
+hipError_t launch_ins_rows(const uint64_t* ikeys, int64_t ni, int32_t n, int32_t* ins_rp, hipStream_t st);
+// New row lengths: survivors (keep_ex: exclusive scan of keep, m+1 entries) plus insertions.
+hipError_t launch_new_len(const int32_t* rowptr, const int32_t* keep_ex, const int32_t* ins_rp, int32_t n,
+                          int32_t* len, hipStream_t st);
+// Merge of survivors and insertions into the new CSR (rows sorted by source,
+// old edges first on equal sources); old_of_new[e'] = old edge or -1.
+hipError_t launch_scatter_old(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
+                              const int32_t* keep, const int32_t* keep_ex, const uint64_t* ikeys,
+                              const int32_t* ins_rp, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
+                              int32_t* old_of_new, hipStream_t st);
+hipError_t launch_scatter_ins(const int32_t* rowptr, const int32_t* col, const int32_t* keep_ex,
+                              const uint64_t* ikeys, const int32_t* iidx, int64_t ni, const int32_t* ins_rp,
+                              const int32_t* ins_w, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
+                              int32_t* old_of_new, hipStream_t st);
+// New flag bitmap: continued edges keep their flag, inserted ones are set.
+hipError_t launch_remap_bits(const uint32_t* old_bits, const int32_t* old_of_new, int64_t m, uint32_t* new_bits,
+                             hipStream_t st);
+// PR contributions c = x / outdeg recomputed where the out-degree changed.
+hipError_t launch_rescale_contrib(float* c, const int32_t* od_old, const int32_t* od_new, int32_t n, hipStream_t st);
+// One round of the taint closure: out-edges of list[lo, hi) that support
+// their destination taint it (appended to out_list at count).
+hipError_t launch_taint_push(const int32_t* list, int32_t lo, int32_t hi, const int32_t* orow, const int32_t* oedge,
+                             const int32_t* odst, const int32_t* weight, int app, const uint32_t* x, int32_t source,
+                             int32_t* taint, int32_t* out_list, int32_t* count, hipStream_t st);
+// Initial values (SSSP: INF, 0 at the source; CC: own id) for the listed vertices, in both buffers.
+hipError_t launch_taint_reset(const int32_t* list, int32_t count, int app, int32_t source, uint32_t* x0,
+                              uint32_t* x1, hipStream_t st);
+// chg[s] = 1 for every in-edge s -> v of the listed vertices.
+hipError_t launch_mark_in_neighbors(const int32_t* list, int32_t count, const int32_t* rowptr, const int32_t* col,
+                                    uint8_t* chg, hipStream_t st);
+// chg[s] = 1 for the source of every (sorted) inserted arc.
+hipError_t launch_mark_sources(const uint64_t* ikeys, int64_t ni, uint8_t* chg, hipStream_t st);
+
 }  // namespace ggk

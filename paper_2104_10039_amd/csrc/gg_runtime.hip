@@ -270,6 +270,8 @@ struct gg_run {
   int64_t selected_total = 0;
   int64_t audit_selected = 0;
   bool have_feat = false, have_sel = false, have_labels = false;
+  // an exact SSSP/CC run that ended on an iteration that changed nothing
+  bool converged = false;
 };
 
 struct gg_mlp {
@@ -510,7 +512,7 @@ int ensure_out(gg_graph* g) {
   GG_TRY(dalloc(&g->orow, n + 1));
   GG_TRY(dalloc(&g->oedge, m));
   GG_TRY(dalloc(&g->odst, m));
-  GG_TRY(dalloc(&g->chg, n));
+  GG_TRY(dalloc(&g->chg, (n + 3) / 4 * 4));  // whole words, so that 32-bit fills clear it
   GG_TRY(dalloc(&g->stamp, n));
   GG_TRY(dalloc(&g->flist[0], n));
   GG_TRY(dalloc(&g->flist[1], n));
@@ -692,6 +694,7 @@ bool is_float(int app) { return is_pr(app) || app == GG_APP_BP; }
 
 int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol) {
   if (!p || !pol) return fail(GG_E_INVAL, "null params or policy");
+  if (!g->full_valid) return fail(GG_E_STATE, "the graph was left unusable by a failed update");
   if (p->app < GG_APP_PR || p->app > GG_APP_BP) return fail(GG_E_INVAL, "unknown app");
   if (p->app == GG_APP_BP) {
     if (!(p->coupling >= 0.0 && p->coupling < 1.0)) return fail(GG_E_INVAL, "coupling outside [0, 1)");
@@ -1353,6 +1356,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   if (pr) {
     if (i >= r->p.iters) r->done = true;
   } else if (r->pol.kind == GG_POLICY_EXACT) {
+    if (changed == 0) r->converged = true;
     if (changed == 0 || i >= r->p.max_iters) r->done = true;
   } else if (r->pol.stop == GG_STOP_FIXED_ITERS) {
     if (i >= r->p.iters) r->done = true;
@@ -2031,6 +2035,295 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
   return GG_OK;
 }
 
+
+// ---- dynamic graphs ---------------------------------------------------------
+
+// Device buffers that live for one call.
+struct TempBufs {
+  std::vector<void*> ptrs;
+  template <typename T>
+  int get(T** p, size_t count) {
+    *p = nullptr;
+    GG_TRY(dalloc(p, count));
+    ptrs.push_back((void*)*p);
+    return GG_OK;
+  }
+  ~TempBufs() {
+    for (void* q : ptrs) dev_free(q);
+  }
+};
+
+// Device copy of a batch array (or the caller's device pointer).
+int batch_array(gg_graph* g, TempBufs& T, const int32_t* a, int64_t k, bool device, const int32_t** out) {
+  *out = nullptr;
+  if (k == 0 || !a) return GG_OK;
+  if (device) {
+    *out = a;
+    return GG_OK;
+  }
+  int32_t* d = nullptr;
+  GG_TRY(T.get(&d, (size_t)k));
+  GG_HIP(hipMemcpyAsync(d, a, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice, g->stream));
+  *out = d;
+  return GG_OK;
+}
+
+// Frontier of a converged exact SSSP/CC run after an update: the vertices
+// flagged in g->chg, compacted into flist[r->fcur].
+int seed_frontier(gg_graph* g, gg_run* r) {
+  GG_HIP(launch_compact_changed(g->chg, g->outdeg, g->n, g->flist[r->fcur], g->fc, (int32_t*)g->blk_scratch, g->psum,
+                                g->stream));
+  FrontCounters h = {0, 0, 0};
+  GG_TRY(readback(g, &h, g->fc, sizeof(h)));
+  r->front_count = h.count;
+  r->front_outdeg = h.outdeg_sum;
+  return GG_OK;
+}
+
+// Applies an update batch to g (and to the active run r, when given). Every
+// check that can fail on the caller's input runs before anything changes.
+int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more, uint8_t* reset_host) {
+  if (!b) return fail(GG_E_INVAL, "null batch");
+  if (b->n_delete < 0 || b->n_insert < 0) return fail(GG_E_INVAL, "negative batch size");
+  if (b->n_delete >= ((int64_t)1 << 31) || b->n_insert >= ((int64_t)1 << 31))
+    return fail(GG_E_RANGE, "a batch list holds 2^31 entries or more");
+  if (b->n_delete > 0 && (!b->del_src || !b->del_dst)) return fail(GG_E_INVAL, "null deletion arrays");
+  if (b->n_insert > 0 && (!b->ins_src || !b->ins_dst)) return fail(GG_E_INVAL, "null insertion arrays");
+  const bool weighted = g->weight != nullptr;
+  if (b->n_insert > 0 && weighted != (b->ins_weight != nullptr))
+    return fail(GG_E_INVAL, weighted ? "the graph has weights: ins_weight is required" : "the graph has no weights");
+  if (!weighted && b->ins_weight) return fail(GG_E_INVAL, "the graph has no weights");
+  if (!g->rows_sorted) return fail(GG_E_UNSUPPORTED, "updates need rows sorted by source");
+  if (g->n_parts > 0) return fail(GG_E_UNSUPPORTED, "updates of a graph with parts");
+  if (!g->full_valid) return fail(GG_E_STATE, "the graph was left unusable by a failed update");
+  const int app = r ? r->p.app : -1;
+  if (r) {
+    if (more < 0) return fail(GG_E_INVAL, "more_iters < 0");
+    if (r->pol.kind == GG_POLICY_LEARNED || r->pol.trace || r->pol.vstatus != GG_VSTATUS_NONE ||
+        active_degree_run(r))
+      return fail(GG_E_UNSUPPORTED, "updates of LEARNED, traced, vertex-status or ACTIVE-degree runs");
+    if (r->supersteps > 0) GG_TRY(check_hub_sync(g));
+  }
+  const int32_t n = g->n;
+  const int64_t m0 = g->m, nd = b->n_delete, ni = b->n_insert;
+  const bool dev = (b->flags & GG_UPDATE_DEVICE_PTRS) != 0;
+  TempBufs T;
+  const int32_t *ds, *dd, *is, *id, *iw;
+  GG_TRY(batch_array(g, T, b->del_src, nd, dev, &ds));
+  GG_TRY(batch_array(g, T, b->del_dst, nd, dev, &dd));
+  GG_TRY(batch_array(g, T, b->ins_src, ni, dev, &is));
+  GG_TRY(batch_array(g, T, b->ins_dst, ni, dev, &id));
+  GG_TRY(batch_array(g, T, weighted ? b->ins_weight : nullptr, ni, dev, &iw));
+  int32_t* flags = nullptr;
+  GG_TRY(T.get(&flags, 1));
+  GG_HIP(launch_fill_u32((uint32_t*)flags, 1, 0u, g->stream));
+  GG_HIP(launch_batch_check(ds, dd, nullptr, nd, n, flags, g->stream));
+  GG_HIP(launch_batch_check(is, id, iw, ni, n, flags, g->stream));
+  int32_t hf = 0;
+  GG_TRY(readback(g, &hf, flags, sizeof(hf)));
+  if (hf & 1) return fail(GG_E_RANGE, "a batch vertex id is outside [0, n)");
+  if (hf & 2) return fail(GG_E_RANGE, "an inserted weight is outside [0, 255]");
+
+  // sorted arc keys of both lists
+  uint64_t *dk, *dks, *ik, *iks;
+  int32_t *ix, *ixs;
+  GG_TRY(T.get(&dk, (size_t)nd));
+  GG_TRY(T.get(&dks, (size_t)nd));
+  GG_TRY(T.get(&ik, (size_t)ni));
+  GG_TRY(T.get(&iks, (size_t)ni));
+  GG_TRY(T.get(&ix, (size_t)ni));
+  GG_TRY(T.get(&ixs, (size_t)ni));
+  GG_HIP(launch_arc_keys(ds, dd, nd, dk, nullptr, g->stream));
+  GG_HIP(launch_arc_keys(is, id, ni, ik, ix, g->stream));
+  size_t sb1 = 0, sb2 = 0;
+  GG_HIP(sort_keys_bytes(nd, &sb1));
+  GG_HIP(sort_pairs_bytes(ni, &sb2));
+  unsigned char* stemp = nullptr;
+  GG_TRY(T.get(&stemp, std::max(sb1, sb2)));
+  GG_HIP(launch_sort_keys(dk, dks, nd, stemp, sb1, g->stream));
+  GG_HIP(launch_sort_pairs(ik, iks, ix, ixs, ni, stemp, sb2, g->stream));
+
+  // survivors (and, for a converged exact SSSP/CC run, the taint seeds)
+  const bool min_app = r && (app == GG_APP_SSSP || app == GG_APP_CC);
+  const bool taint_mode = min_app && r->pol.kind == GG_POLICY_EXACT && r->converged && nd > 0;
+  int32_t *taint = nullptr, *tlist = nullptr, *tcount = nullptr;
+  if (taint_mode) {
+    GG_TRY(T.get(&taint, (size_t)n));
+    GG_TRY(T.get(&tlist, (size_t)n));
+    GG_TRY(T.get(&tcount, 1));
+    GG_HIP(launch_fill_u32((uint32_t*)taint, n, 0u, g->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)tcount, 1, 0u, g->stream));
+  }
+  int32_t *keep, *keep_ex, *scr;
+  GG_TRY(T.get(&keep, (size_t)m0));
+  GG_TRY(T.get(&keep_ex, (size_t)m0 + 1));
+  const int64_t big = std::max<int64_t>(m0, n);
+  GG_TRY(T.get(&scr, (size_t)(big / 1024 + 2)));
+  GG_HIP(launch_mark_kept(g->rowptr, g->col, g->weight, n, m0, dks, nd, keep, app,
+                          taint_mode ? g->xu[r->cur] : nullptr, r ? r->p.source : 0, taint, tlist, tcount, g->stream));
+  if (m0 > 0) GG_HIP(launch_scan(keep, keep_ex, (int32_t)m0, keep_ex + m0, scr, g->stream));
+  else GG_HIP(launch_fill_u32((uint32_t*)keep_ex, 1, 0u, g->stream));
+  int32_t kept = 0;
+  GG_TRY(readback(g, &kept, keep_ex + m0, sizeof(kept)));
+  const int64_t m1 = (int64_t)kept + ni;
+  if (m1 >= ((int64_t)1 << 31)) return fail(GG_E_RANGE, "the updated graph would hold 2^31 arcs or more");
+  const bool deleted_any = kept < m0;
+
+  // every array the new graph needs, before anything is replaced
+  int32_t *ins_rp, *len;
+  GG_TRY(T.get(&ins_rp, (size_t)n + 1));
+  GG_TRY(T.get(&len, (size_t)n + 1));
+  int32_t* oon = nullptr;
+  GG_TRY(T.get(&oon, (size_t)m1));
+  struct Owned {
+    int32_t *rowptr = nullptr, *col = nullptr, *weight = nullptr;
+    uint32_t *wedges = nullptr, *bits0 = nullptr, *bits1 = nullptr, *act_edges = nullptr;
+    ~Owned() {
+      dfree(rowptr);
+      dfree(col);
+      dfree(weight);
+      dfree(wedges);
+      dfree(bits0);
+      dfree(bits1);
+      dfree(act_edges);
+    }
+  } nw;
+  GG_TRY(dalloc(&nw.rowptr, (size_t)n + 1));
+  GG_TRY(dalloc(&nw.col, (size_t)m1));
+  if (weighted) {
+    GG_TRY(dalloc(&nw.weight, (size_t)m1));
+    GG_TRY(dalloc(&nw.wedges, (size_t)m1));
+  }
+  const size_t nwords = (size_t)((m1 + 31) / 32);
+  if (g->ws) {
+    GG_TRY(dalloc(&nw.bits0, nwords));
+    GG_TRY(dalloc(&nw.bits1, nwords));
+    GG_TRY(dalloc(&nw.act_edges, (size_t)m1));
+  }
+  int32_t* od_old = nullptr;
+  if (r && is_pr(app)) {
+    GG_TRY(T.get(&od_old, (size_t)n));
+    GG_HIP(launch_copy_u32((const uint32_t*)g->outdeg, (uint32_t*)od_old, n, g->stream));
+  }
+
+  // the new CSR
+  GG_HIP(launch_ins_rows(iks, ni, n, ins_rp, g->stream));
+  GG_HIP(launch_new_len(g->rowptr, keep_ex, ins_rp, n, len, g->stream));
+  if (n > 0) GG_HIP(launch_scan(len, nw.rowptr, n, nw.rowptr + n, scr, g->stream));
+  else GG_HIP(launch_fill_u32((uint32_t*)nw.rowptr, 1, 0u, g->stream));
+  GG_HIP(launch_scatter_old(g->rowptr, g->col, g->weight, n, m0, keep, keep_ex, iks, ins_rp, nw.rowptr, nw.col,
+                            nw.weight, oon, g->stream));
+  GG_HIP(launch_scatter_ins(g->rowptr, g->col, keep_ex, iks, ixs, ni, ins_rp, iw, nw.rowptr, nw.col, nw.weight, oon,
+                            g->stream));
+  const bool flags_run = r && r->pol.kind != GG_POLICY_EXACT;
+  if (flags_run) GG_HIP(launch_remap_bits(g->bits[r->bcur], oon, m1, nw.bits0, g->stream));
+  GG_HIP(hipStreamSynchronize(g->stream));
+
+  // replace the CSR and everything derived from it; a failure from here on
+  // leaves the graph unusable (full_valid stays false)
+  g->full_valid = false;
+  if (g->owns_csr) {
+    dfree(g->rowptr);
+    dfree(g->col);
+    dfree(g->weight);
+  }
+  g->owns_csr = true;
+  g->rowptr = nw.rowptr;
+  g->col = nw.col;
+  g->weight = nw.weight;
+  nw.rowptr = nw.col = nw.weight = nullptr;
+  g->m = m1;
+  if (weighted) {
+    dfree(g->wedges);
+    g->wedges = nw.wedges;
+    nw.wedges = nullptr;
+    GG_HIP(launch_pack_weights(g->col, g->weight, g->m, g->wedges, g->stream));
+  }
+  if (g->ws) {
+    for (int k = 0; k < 2; ++k) dfree(g->bits[k]);
+    dfree(g->act_edges);
+    g->bits[0] = nw.bits0;
+    g->bits[1] = nw.bits1;
+    g->act_edges = nw.act_edges;
+    nw.bits0 = nw.bits1 = nw.act_edges = nullptr;
+  }
+  GG_HIP(launch_outdeg(g->col, g->m, g->outdeg, g->n, g->stream));
+  GG_HIP(launch_dangling_list(g->outdeg, g->n, g->dang, g->i32_scratch, (int32_t*)g->blk_scratch, g->stream));
+  GG_TRY(readback(g, &g->n_dang, g->i32_scratch, sizeof(int32_t)));
+  if (g->out_built) {
+    g->out_built = false;
+    GG_TRY(ensure_out(g));
+  }
+  GG_TRY(rebin_full(g));
+  if (g->ws) GG_TRY(ensure_parts(g));
+  g->full_valid = true;
+  if (!r) return GG_OK;
+
+  // the run continues on the new graph
+  if (flags_run) {
+    r->bcur = 0;
+    GG_TRY(pack_from_bits0(g, app));
+  }
+  if (is_pr(app)) GG_HIP(launch_rescale_contrib(g->c[r->cur], od_old, g->outdeg, n, g->stream));
+  std::vector<uint8_t> reset_v;
+  if (reset_host) reset_v.assign((size_t)n, 0);
+  if (min_app) {
+    const bool frontier = g->tune.frontier_enable != 0;
+    r->front_count = -1;
+    r->front_outdeg = 0;
+    if (deleted_any && taint_mode) {
+      // closure of the seeds along supporting out-edges of the new graph
+      GG_TRY(ensure_out(g));
+      int32_t lo = 0, hi = 0;
+      GG_TRY(readback(g, &hi, tcount, sizeof(hi)));
+      while (lo < hi) {
+        GG_HIP(launch_taint_push(tlist, lo, hi, g->orow, g->oedge, g->odst, g->weight, app, g->xu[r->cur],
+                                 r->p.source, taint, tlist, tcount, g->stream));
+        lo = hi;
+        GG_TRY(readback(g, &hi, tcount, sizeof(hi)));
+      }
+      GG_HIP(launch_taint_reset(tlist, hi, app, r->p.source, g->xu[0], g->xu[1], g->stream));
+      if (frontier) {
+        GG_HIP(launch_fill_u32((uint32_t*)g->chg, ((int64_t)n + 3) / 4, 0u, g->stream));
+        GG_HIP(launch_mark_in_neighbors(tlist, hi, g->rowptr, g->col, g->chg, g->stream));
+        GG_HIP(launch_mark_sources(iks, ni, g->chg, g->stream));
+        GG_TRY(seed_frontier(g, r));
+      }
+      if (reset_host && hi > 0) {
+        std::vector<int32_t> t((size_t)hi);
+        GG_HIP(hipMemcpyAsync(t.data(), tlist, sizeof(int32_t) * (size_t)hi, hipMemcpyDeviceToHost, g->stream));
+        GG_HIP(hipStreamSynchronize(g->stream));
+        for (int32_t v : t) reset_v[(size_t)v] = 1;
+      }
+    } else if (deleted_any) {
+      // any other run restarts from its initial values
+      GG_HIP(launch_min_init(app, n, r->p.source, g->xu[0], g->stream));
+      GG_HIP(launch_min_init(app, n, r->p.source, g->xu[1], g->stream));
+      if (reset_host) reset_v.assign((size_t)n, 1);
+    } else if (r->pol.kind == GG_POLICY_EXACT && r->converged && frontier) {
+      // insertions only: a push from their sources
+      GG_TRY(ensure_out(g));
+      GG_HIP(launch_fill_u32((uint32_t*)g->chg, ((int64_t)n + 3) / 4, 0u, g->stream));
+      GG_HIP(launch_mark_sources(iks, ni, g->chg, g->stream));
+      GG_TRY(seed_frontier(g, r));
+    }
+  }
+  r->converged = false;
+  const bool fixed_iters = is_float(app) || (r->pol.kind != GG_POLICY_EXACT && r->pol.stop == GG_STOP_FIXED_ITERS);
+  if (fixed_iters) {
+    if (r->p.iters < r->iter) r->p.iters = r->iter;
+    r->p.iters += more;
+    r->done = r->iter >= r->p.iters;
+  } else {
+    if (r->p.max_iters < r->iter) r->p.max_iters = r->iter;
+    r->p.max_iters = (int32_t)std::min<int64_t>((int64_t)r->p.max_iters + more, INT32_MAX);
+    r->done = r->iter >= r->p.max_iters;
+  }
+  GG_HIP(hipStreamSynchronize(g->stream));
+  if (reset_host) std::memcpy(reset_host, reset_v.data(), (size_t)n);
+  return GG_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2554,6 +2847,39 @@ void gg_run_end(gg_run* run) {
     end_run(run);
   } catch (...) {
   }
+}
+
+int gg_graph_update(gg_graph* g, const gg_update_batch* batch) {
+  return guard([&]() -> int {
+    if (!g) return fail(GG_E_INVAL, "null graph");
+    if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph: use gg_run_update");
+    return update_graph(g, batch, nullptr, 0, nullptr);
+  });
+}
+
+int gg_run_update(gg_run* run, const gg_update_batch* batch, int32_t more_iters, uint8_t* reset_host) {
+  return guard([&]() -> int {
+    if (!run) return fail(GG_E_INVAL, "null run");
+    return update_graph(run->g, batch, run, more_iters, reset_host);
+  });
+}
+
+int gg_graph_get_csr(gg_graph* g, int32_t* rowptr_host, int32_t* col_host, int32_t* weight_host) {
+  return guard([&]() -> int {
+    if (!g || !rowptr_host) return fail(GG_E_INVAL, "null argument");
+    if (weight_host && !g->weight) return fail(GG_E_INVAL, "the graph has no weights");
+    GG_HIP(hipMemcpyAsync(rowptr_host, g->rowptr, sizeof(int32_t) * ((size_t)g->n + 1), hipMemcpyDeviceToHost,
+                          g->stream));
+    if (g->m > 0) {
+      if (col_host)
+        GG_HIP(hipMemcpyAsync(col_host, g->col, sizeof(int32_t) * (size_t)g->m, hipMemcpyDeviceToHost, g->stream));
+      if (weight_host)
+        GG_HIP(hipMemcpyAsync(weight_host, g->weight, sizeof(int32_t) * (size_t)g->m, hipMemcpyDeviceToHost,
+                              g->stream));
+    }
+    GG_HIP(hipStreamSynchronize(g->stream));
+    return GG_OK;
+  });
 }
 
 // ---- learned correction network and traces ---------------------------------

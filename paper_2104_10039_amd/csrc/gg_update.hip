@@ -1,0 +1,355 @@
+// Dynamic graphs: device side of an update batch (deletions, then
+// insertions) applied to the in-CSR, the remapping of the edge flags, and
+// the repair of min-type values after deletions. The method is stated to
+// apply to changing graphs [Sec. 1]; the paper evaluates none, so the
+// update rules are this library's reading (see include/gg.h).
+//
+// Arcs of a batch are keyed (destination << 32) | source and radix-sorted
+// (stable, so equal arcs keep their batch order). Every old edge looks its
+// key up in the sorted deletions; the surviving edges and the sorted
+// insertions of a row are merged by source with two binary searches per
+// arc, old edges first on equal sources, so rows stay sorted by source.
+#include <hipcub/hipcub.hpp>
+
+#include "gg_internal.h"
+
+namespace ggk {
+
+namespace {
+
+constexpr int kUpdBlock = 256;
+
+int grid_of(int64_t work) {
+  int64_t b = (work + kUpdBlock - 1) / kUpdBlock;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (int)b;
+}
+
+__device__ __forceinline__ uint64_t arc_key(int32_t src, int32_t dst) {
+  return ((uint64_t)(uint32_t)dst << 32) | (uint32_t)src;
+}
+
+// Row holding edge e: the last u with rowptr[u] <= e (rows may be empty).
+__device__ __forceinline__ int row_of(const int32_t* rowptr, int32_t n, int64_t e) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rowptr[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// First index in sorted keys[lo, hi) whose key is >= k.
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t* keys, int64_t lo, int64_t hi, uint64_t k) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Whether edge s -> d (weight w) realises d's value: SSSP x_s + w == x_d
+// (d not the source, both finite); CC l_s == l_d with l_d not d's own id.
+__device__ __forceinline__ bool supports(int app, const uint32_t* x, int32_t source, int32_t s, int32_t d,
+                                         uint32_t w) {
+  const uint32_t xs = x[s], xd = x[d];
+  if (app == kSSSP) {
+    if (d == source || xs == kInf || xd == kInf) return false;
+    return (uint64_t)xs + (uint64_t)w == (uint64_t)xd;
+  }
+  return xs == xd && xd != (uint32_t)d;
+}
+
+__global__ void k_batch_check(const int32_t* src, const int32_t* dst, const int32_t* w, int64_t k, int32_t n,
+                              int32_t* flags) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < k; j += (int64_t)gridDim.x * blockDim.x) {
+    if (src[j] < 0 || src[j] >= n || dst[j] < 0 || dst[j] >= n) atomicOr(flags, 1);
+    if (w && (w[j] < 0 || w[j] > 255)) atomicOr(flags, 2);
+  }
+}
+
+__global__ void k_arc_keys(const int32_t* src, const int32_t* dst, int64_t k, uint64_t* keys, int32_t* idx) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < k; j += (int64_t)gridDim.x * blockDim.x) {
+    keys[j] = arc_key(src[j], dst[j]);
+    if (idx) idx[j] = (int32_t)j;
+  }
+}
+
+// keep[e] = 0 for the edges whose arc is listed for deletion. With x set,
+// the destinations of deleted supporting edges are appended to the taint
+// list (taint[v] guards against duplicates).
+__global__ void k_mark_kept(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
+                            const uint64_t* dkeys, int64_t nd, int32_t* keep, int app, const uint32_t* x,
+                            int32_t source, int32_t* taint, int32_t* list, int32_t* count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int u = row_of(rowptr, n, e);
+    const int32_t s = col[e];
+    const uint64_t key = arc_key(s, u);
+    const int64_t p = lower_bound_u64(dkeys, 0, nd, key);
+    const bool del = p < nd && dkeys[p] == key;
+    keep[e] = del ? 0 : 1;
+    if (del && x && supports(app, x, source, s, u, weight ? (uint32_t)weight[e] : 0u)) {
+      if (atomicExch(&taint[u], 1) == 0) list[atomicAdd(count, 1)] = u;
+    }
+  }
+}
+
+// ins_rp[u] = first sorted insertion whose destination is >= u, for u in [0, n].
+__global__ void k_ins_rows(const uint64_t* ikeys, int64_t ni, int32_t n, int32_t* ins_rp) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= n; u += (int64_t)gridDim.x * blockDim.x)
+    ins_rp[u] = (int32_t)lower_bound_u64(ikeys, 0, ni, (uint64_t)u << 32);
+}
+
+__global__ void k_new_len(const int32_t* rowptr, const int32_t* keep_ex, const int32_t* ins_rp, int32_t n,
+                          int32_t* len) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+    len[u] = (keep_ex[rowptr[u + 1]] - keep_ex[rowptr[u]]) + (ins_rp[u + 1] - ins_rp[u]);
+}
+
+// A surviving old edge goes after the survivors before it in its row and
+// after the row's insertions with a smaller source.
+__global__ void k_scatter_old(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
+                              const int32_t* keep, const int32_t* keep_ex, const uint64_t* ikeys, const int32_t* ins_rp,
+                              const int32_t* new_rp, int32_t* ncol, int32_t* nweight, int32_t* old_of_new) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    if (!keep[e]) continue;
+    const int u = row_of(rowptr, n, e);
+    const int32_t s = col[e];
+    const int64_t rank = keep_ex[e] - keep_ex[rowptr[u]];
+    const int64_t before = lower_bound_u64(ikeys, ins_rp[u], ins_rp[u + 1], arc_key(s, u)) - ins_rp[u];
+    const int64_t pos = new_rp[u] + rank + before;
+    ncol[pos] = s;
+    if (nweight) nweight[pos] = weight[e];
+    old_of_new[pos] = (int32_t)e;
+  }
+}
+
+// An inserted arc goes after the row's earlier insertions and after every
+// surviving old edge whose source is not larger.
+__global__ void k_scatter_ins(const int32_t* rowptr, const int32_t* col, const int32_t* keep_ex, const uint64_t* ikeys,
+                              const int32_t* iidx, int64_t ni, const int32_t* ins_rp, const int32_t* ins_w,
+                              const int32_t* new_rp, int32_t* ncol, int32_t* nweight, int32_t* old_of_new) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ni; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = ikeys[j];
+    const int u = (int)(key >> 32);
+    const int32_t s = (int32_t)(uint32_t)key;
+    int lo = rowptr[u], hi = rowptr[u + 1];  // first old edge of the row with a larger source
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (col[mid] <= s) lo = mid + 1;
+      else hi = mid;
+    }
+    const int64_t kept = keep_ex[lo] - keep_ex[rowptr[u]];
+    const int64_t pos = new_rp[u] + (j - ins_rp[u]) + kept;
+    ncol[pos] = s;
+    if (nweight) nweight[pos] = ins_w[iidx[j]];
+    old_of_new[pos] = -1;
+  }
+}
+
+// One new flag word per thread: a continued edge keeps its old flag, an
+// inserted one is set.
+__global__ void k_remap_bits(const uint32_t* old_bits, const int32_t* old_of_new, int64_t m, uint32_t* new_bits) {
+  const int64_t nw = (m + 31) / 32;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t word = 0;
+    const int64_t e0 = w * 32;
+    const int cnt = (int)min((int64_t)32, m - e0);
+    for (int b = 0; b < cnt; ++b) {
+      const int32_t o = old_of_new[e0 + b];
+      const uint32_t bit = o < 0 ? 1u : (old_bits[o >> 5] >> (o & 31)) & 1u;
+      word |= bit << b;
+    }
+    new_bits[w] = word;
+  }
+}
+
+// c = x / outdeg under the new out-degrees, from c = x / outdeg_old (x
+// itself for vertices without out-edges).
+__global__ void k_rescale_contrib(float* c, const int32_t* od_old, const int32_t* od_new, int32_t n) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    const int a = od_old[u], b = od_new[u];
+    if (a == b) continue;
+    const double x = a > 0 ? (double)c[u] * (double)a : (double)c[u];
+    c[u] = b > 0 ? (float)(x / (double)b) : (float)x;
+  }
+}
+
+// One wavefront per listed vertex p: every out-edge p -> v that supports v
+// taints v (appended once to the list).
+__global__ __launch_bounds__(kUpdBlock) void k_taint_push(const int32_t* list, int32_t lo, int32_t hi,
+                                                          const int32_t* orow, const int32_t* oedge,
+                                                          const int32_t* odst, const int32_t* weight, int app,
+                                                          const uint32_t* x, int32_t source, int32_t* taint,
+                                                          int32_t* out_list, int32_t* count) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = lo + wave; i < hi; i += nwaves) {
+    const int32_t p = list[i];
+    for (int32_t k = orow[p] + lane; k < orow[p + 1]; k += 64) {
+      const int32_t v = odst[k];
+      const uint32_t w = weight ? (uint32_t)weight[oedge[k]] : 0u;
+      if (taint[v] == 0 && supports(app, x, source, p, v, w)) {
+        if (atomicExch(&taint[v], 1) == 0) out_list[atomicAdd(count, 1)] = v;
+      }
+    }
+  }
+}
+
+__global__ void k_taint_reset(const int32_t* list, int32_t count, int app, int32_t source, uint32_t* x0,
+                              uint32_t* x1) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = list[i];
+    const uint32_t init = app == kSSSP ? (v == source ? 0u : kInf) : (uint32_t)v;
+    x0[v] = init;
+    x1[v] = init;
+  }
+}
+
+// chg[src] = 1 for every in-edge src -> v of the listed vertices (one
+// wavefront per vertex).
+__global__ __launch_bounds__(kUpdBlock) void k_mark_in_neighbors(const int32_t* list, int32_t count,
+                                                                 const int32_t* rowptr, const int32_t* col,
+                                                                 uint8_t* chg) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = wave; i < count; i += nwaves) {
+    const int32_t v = list[i];
+    for (int32_t e = rowptr[v] + lane; e < rowptr[v + 1]; e += 64) chg[col[e]] = 1;
+  }
+}
+
+__global__ void k_mark_sources(const uint64_t* ikeys, int64_t ni, uint8_t* chg) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ni; j += (int64_t)gridDim.x * blockDim.x)
+    chg[(int32_t)(uint32_t)ikeys[j]] = 1;
+}
+
+}  // namespace
+
+hipError_t launch_batch_check(const int32_t* src, const int32_t* dst, const int32_t* w, int64_t k, int32_t n,
+                              int32_t* flags, hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_check, dim3(grid_of(k)), dim3(kUpdBlock), 0, st, src, dst, w, k, n, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_arc_keys(const int32_t* src, const int32_t* dst, int64_t k, uint64_t* keys, int32_t* idx,
+                           hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_arc_keys, dim3(grid_of(k)), dim3(kUpdBlock), 0, st, src, dst, k, keys, idx);
+  return hipGetLastError();
+}
+
+hipError_t sort_keys_bytes(int64_t k, size_t* bytes) {
+  *bytes = 0;
+  return hipcub::DeviceRadixSort::SortKeys(nullptr, *bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr, (int)k);
+}
+
+hipError_t sort_pairs_bytes(int64_t k, size_t* bytes) {
+  *bytes = 0;
+  return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                            (const int32_t*)nullptr, (int32_t*)nullptr, (int)k);
+}
+
+hipError_t launch_sort_keys(const uint64_t* in, uint64_t* out, int64_t k, void* temp, size_t bytes, hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  return hipcub::DeviceRadixSort::SortKeys(temp, bytes, in, out, (int)k, 0, 64, st);
+}
+
+hipError_t launch_sort_pairs(const uint64_t* kin, uint64_t* kout, const int32_t* vin, int32_t* vout, int64_t k,
+                             void* temp, size_t bytes, hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  return hipcub::DeviceRadixSort::SortPairs(temp, bytes, kin, kout, vin, vout, (int)k, 0, 64, st);
+}
+
+hipError_t launch_mark_kept(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
+                            const uint64_t* dkeys, int64_t nd, int32_t* keep, int app, const uint32_t* x,
+                            int32_t source, int32_t* taint, int32_t* list, int32_t* count, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_kept, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, rowptr, col, weight, n, m, dkeys, nd,
+                     keep, app, x, source, taint, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_ins_rows(const uint64_t* ikeys, int64_t ni, int32_t n, int32_t* ins_rp, hipStream_t st) {
+  hipLaunchKernelGGL(k_ins_rows, dim3(grid_of((int64_t)n + 1)), dim3(kUpdBlock), 0, st, ikeys, ni, n, ins_rp);
+  return hipGetLastError();
+}
+
+hipError_t launch_new_len(const int32_t* rowptr, const int32_t* keep_ex, const int32_t* ins_rp, int32_t n,
+                          int32_t* len, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_new_len, dim3(grid_of(n)), dim3(kUpdBlock), 0, st, rowptr, keep_ex, ins_rp, n, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_old(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
+                              const int32_t* keep, const int32_t* keep_ex, const uint64_t* ikeys,
+                              const int32_t* ins_rp, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
+                              int32_t* old_of_new, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_old, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, rowptr, col, weight, n, m, keep,
+                     keep_ex, ikeys, ins_rp, new_rp, ncol, nweight, old_of_new);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_ins(const int32_t* rowptr, const int32_t* col, const int32_t* keep_ex,
+                              const uint64_t* ikeys, const int32_t* iidx, int64_t ni, const int32_t* ins_rp,
+                              const int32_t* ins_w, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
+                              int32_t* old_of_new, hipStream_t st) {
+  if (ni == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_ins, dim3(grid_of(ni)), dim3(kUpdBlock), 0, st, rowptr, col, keep_ex, ikeys, iidx, ni,
+                     ins_rp, ins_w, new_rp, ncol, nweight, old_of_new);
+  return hipGetLastError();
+}
+
+hipError_t launch_remap_bits(const uint32_t* old_bits, const int32_t* old_of_new, int64_t m, uint32_t* new_bits,
+                             hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_remap_bits, dim3(grid_of((m + 31) / 32)), dim3(kUpdBlock), 0, st, old_bits, old_of_new, m,
+                     new_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescale_contrib(float* c, const int32_t* od_old, const int32_t* od_new, int32_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rescale_contrib, dim3(grid_of(n)), dim3(kUpdBlock), 0, st, c, od_old, od_new, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_taint_push(const int32_t* list, int32_t lo, int32_t hi, const int32_t* orow, const int32_t* oedge,
+                             const int32_t* odst, const int32_t* weight, int app, const uint32_t* x, int32_t source,
+                             int32_t* taint, int32_t* out_list, int32_t* count, hipStream_t st) {
+  if (hi <= lo) return hipSuccess;
+  hipLaunchKernelGGL(k_taint_push, dim3(grid_of((int64_t)(hi - lo) * 64)), dim3(kUpdBlock), 0, st, list, lo, hi,
+                     orow, oedge, odst, weight, app, x, source, taint, out_list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_taint_reset(const int32_t* list, int32_t count, int app, int32_t source, uint32_t* x0,
+                              uint32_t* x1, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_taint_reset, dim3(grid_of(count)), dim3(kUpdBlock), 0, st, list, count, app, source, x0, x1);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_in_neighbors(const int32_t* list, int32_t count, const int32_t* rowptr, const int32_t* col,
+                                    uint8_t* chg, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_in_neighbors, dim3(grid_of((int64_t)count * 64)), dim3(kUpdBlock), 0, st, list, count,
+                     rowptr, col, chg);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_sources(const uint64_t* ikeys, int64_t ni, uint8_t* chg, hipStream_t st) {
+  if (ni == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_sources, dim3(grid_of(ni)), dim3(kUpdBlock), 0, st, ikeys, ni, chg);
+  return hipGetLastError();
+}
+
+}  // namespace ggk

@@ -170,7 +170,7 @@ def load(P, g, tuning=None):
     return G
 
 
-def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
+def step_compare(P, g, app, policy, tuning=None, stats=None, update=None, graph_obj=None, **kw):
     """Run both sides one iteration at a time; compare values every iteration
     and the edge flags after every superstep. Returns the worst PR error.
 
@@ -179,8 +179,16 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
     within REPLAY_BAND * theta of theta; the oracle then adopts the GPU's
     flags and both continue from the same edge set. `stats` (a dict), when
     given, receives the number of such flips ("flips"), of idle iterations (a
-    push from an empty frontier) and of supersteps that followed one."""
-    G = load(P, g, tuning)
+    push from an empty frontier) and of supersteps that followed one.
+
+    `update` (a dict: "at" = iteration after which to apply it, or None for
+    when the run has ended; "batch" = (del_src, del_dst, ins_src, ins_dst,
+    ins_weight); "more" = further iterations) applies one update batch to
+    both sides (gg_run_update / ggo_run_update), then checks the reset
+    vertices, values and flags right away and continues the comparison.
+    `graph_obj`: run on this loaded graph (whose CSR must equal g's) instead
+    of loading g; it is left open."""
+    G = graph_obj if graph_obj is not None else load(P, g, tuning)
     sr = kw.pop("sample_ratio", 1.0)
     R = G.begin(app, sr, policy, **kw)
     okw = oracle_kw(kw)
@@ -192,11 +200,42 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
     vs = kw.get("vstatus", "none")
     ov_prev = O.values() if vs != "none" else None
     bp_prev = (O.values(), R.values().astype(np.float64)) if app == "bp" else None
+    gcur = g
+    pending = dict(update) if update else None
+
+    def apply_update():
+        nonlocal gcur, bp_prev, ov_prev
+        ds, dd, is_, id_, iw = pending["batch"]
+        upd = oracle.apply_update(gcur, ds, dd, is_, id_, iw)
+        greset = R.update(ds, dd, is_, id_, iw, more_iters=pending["more"])
+        O.update(upd, more_iters=pending["more"])
+        gcur = upd.graph
+        oreset = O.reset_vertices()
+        log("update: %d deletions, %d insertions, m %d -> %d, %d vertices reset" % (
+            len(ds), len(is_), upd.deleted_old.size, gcur.m, int(oreset.sum())))
+        assert np.array_equal(greset, oreset), "reset vertices differ: %d on the GPU, %d in the oracle" % (
+            int(greset.sum()), int(oreset.sum()))
+        if policy != "exact":
+            assert np.array_equal(R.mask(), O.mask()), "edge flags differ after the update"
+        gv, ov = R.values(), O.values()
+        compare_values(app, gv, ov, ctx="after the update")
+        if app == "bp":
+            bp_prev = (ov, gv.astype(np.float64))
+        if vs != "none":
+            ov_prev = ov
+
     while True:
+        if pending is not None and pending["at"] is not None and O.iterations == pending["at"]:
+            apply_update()
+            pending = None
         a = R.step()
         b = O.step()
         if a is None or b is None:
             assert a is None and b is None, (a, b)
+            if pending is not None:
+                apply_update()
+                pending = None
+                continue
             break
         assert a["iter"] == b.iter and a["accurate"] == b.accurate and a["superstep"] == b.superstep
         assert a["edges"] == b.edges, (a, b)
@@ -222,7 +261,7 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
                 assert app in ("pr", "ppr", "bp"), "%d SSSP/CC edge flags differ after superstep %d" % (flips.size,
                                                                                                     b.iter)
                 if app == "bp":
-                    bad = bp_flip_justified(g, flips, bp_prev[0], bp_prev[1], kw.get("coupling", 0.0), theta)
+                    bad = bp_flip_justified(gcur, flips, bp_prev[0], bp_prev[1], kw.get("coupling", 0.0), theta)
                     assert not bad, "BP flag differs away from its decision band: %r" % bad[:5]
                 else:
                     dist = np.abs(infl[flips] - theta)
@@ -262,5 +301,6 @@ def step_compare(P, g, app, policy, tuning=None, stats=None, **kw):
         stats["vflips"] = vflips_total
     R.close()
     O.close()
-    G.close()
+    if graph_obj is None:
+        G.close()
     return worst
