@@ -32,6 +32,13 @@ part of `value`):
            ratio of the timed step, and the fastest SMS and GG configurations
            within 1% top-1000 error for every sampling seed (BP_1PCT), with
            the gather's and the superstep's device time and HBM rate;
+  dynamic  update batches (half deletions of existing arcs, half insertions
+           of arcs with uniform endpoints) of 0.01%, 0.1% and 1% of the arcs
+           applied to a converged exact SSSP run and to a PageRank run on a
+           copy of the weighted graph: the update's wall time, the repair
+           (taint closure, frontier continuation) against an exact run from
+           scratch on the updated graph, whose distances it must equal, and
+           PageRank continued for 5 iterations against 20 from scratch;
   learned  the correction network trained by the library's kernels on the
            (features, drift label) traces of GG runs on the scale-22 graph at
            every sample ratio, then LEARNED against GG and exact on R-MAT
@@ -226,6 +233,86 @@ def bench_bp(Gs, gs, seed, sigmas, alpha, theta, np, metrics):
                                "within_1pct": bool(max(errs) <= 0.01),
                                "edges_vs_exact": round(st.edges_gathered / (gs.m * iters), 4)}
     log("bp:", out)
+    return out
+
+
+def bench_dynamic(P, gg, torch, np, metrics, gw, source, seed):
+    """Update batches on a copy of the weighted graph (not part of `value`)."""
+    G = P.Graph.from_host(gw)
+    rng = np.random.default_rng(seed + 100)
+    out = {"batches": [], "endpoints": "deletions: uniform over existing arcs; insertions: uniform endpoints, "
+                                      "no self-loops, weights uniform in [1, 255]"}
+
+    def wall(f):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t) * 1e3
+
+    def run_to_end(R):
+        while R.step() is not None:
+            pass
+
+    def make_batch(frac):
+        """Device arrays: half deletions of existing arcs, half insertions."""
+        rp, col, _ = G.csr()
+        m = int(rp[-1])
+        k = max(1, int(m * frac / 2))
+        dst = np.repeat(np.arange(G.n, dtype=np.int32), np.diff(rp))
+        pick = rng.choice(m, size=k, replace=False)
+        a = rng.integers(0, G.n, k)
+        b = rng.integers(0, G.n, k)
+        ok = a != b
+        dev = lambda x: torch.as_tensor(np.asarray(x, dtype=np.int32), device="cuda")
+        return (dev(col[pick]), dev(dst[pick]), dev(a[ok]), dev(b[ok]), dev(rng.integers(1, 256, int(ok.sum()))))
+
+    for frac in (1e-4, 1e-3, 1e-2):
+        # SSSP: a converged exact run, updated, repaired, against a run from
+        # scratch on the updated graph
+        batch = make_batch(frac)
+        R = G.begin("sssp", 1.0, "exact", source=source, max_iters=1 << 20)
+        run_to_end(R)
+        st0 = R.stats()
+        reset, upd_ms = wall(lambda: R.update(*batch, more_iters=1 << 20))
+        _, rep_ms = wall(lambda: run_to_end(R))
+        st = R.stats()
+        rep_vals = R.values()
+        R.close()
+
+        def scratch():
+            R2 = G.begin("sssp", 1.0, "exact", source=source, max_iters=1 << 20)
+            run_to_end(R2)
+            return R2
+        R2, scratch_ms = wall(scratch)
+        scratch_vals = R2.values()
+        scratch_iters = R2.stats().iterations
+        R2.close()
+        # PageRank: 20 exact iterations, another batch, 5 more iterations
+        # against 20 from scratch on the updated graph
+        pbatch = make_batch(frac)
+        R = G.begin("pr", 1.0, "exact", iters=20)
+        run_to_end(R)
+        _, pupd_ms = wall(lambda: R.update(*pbatch, more_iters=5))
+        _, pcont_ms = wall(lambda: run_to_end(R))
+        pr_cont = R.values()
+        R.close()
+        ex, _ = G.exact_run("pr", iters=20)
+        _, pscratch_ms = wall(lambda: G.exact_run("pr", iters=20))
+        d = {"fraction": frac, "deleted": int(len(batch[0])), "inserted": int(len(batch[2])), "m_after": G.m,
+             "sssp": {"update_ms": round(upd_ms, 3), "reset_vertices": int(reset.sum()),
+                      "repair_ms": round(rep_ms, 3), "repair_iters": st.iterations - st0.iterations,
+                      "repair_edges_processed": int(st.edges_processed - st0.edges_processed),
+                      "scratch_ms": round(scratch_ms, 3), "scratch_iters": scratch_iters,
+                      "speedup_vs_scratch": round(scratch_ms / (upd_ms + rep_ms), 3),
+                      "equal_to_scratch": bool(np.array_equal(rep_vals, scratch_vals))},
+             "pr": {"update_ms": round(pupd_ms, 3), "continue5_ms": round(pcont_ms, 3),
+                    "scratch20_ms": round(pscratch_ms, 3),
+                    "accuracy_vs_scratch20": round(metrics.accuracy(
+                        metrics.topk_error(pr_cont, ex.cpu().numpy(), 1000)), 3)}}
+        out["batches"].append(d)
+        log("dynamic:", d)
+    G.close()
     return out
 
 
@@ -448,6 +535,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-query section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction section")
     ap.add_argument("--no-bp", action="store_true", help="skip the belief-propagation section")
+    ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic-graph section")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain copy kernel of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -614,6 +702,10 @@ def main():
     if not args.no_bp and "cc" in apps:
         bp = bench_bp(G["cc"], graphs["cc"], args.seed, sigmas, args.alpha, args.theta, np, metrics)
 
+    dynamic = None
+    if not args.no_dynamic and "sssp" in apps:
+        dynamic = bench_dynamic(P, gg, torch, np, metrics, gw, source, args.seed)
+
     batch = None
     if not args.no_batch:
         batch = bench_batch(P, gg, torch, args.seed, np, metrics)
@@ -649,6 +741,7 @@ def main():
         "runs": summary,
         "at_1pct": at1,
         "bp": bp,
+        "dynamic": dynamic,
         "batch": batch,
         "learned": learned,
     }

@@ -347,27 +347,44 @@ hipError_t sort_pairs_bytes(int64_t k, size_t* bytes);
 hipError_t launch_sort_keys(const uint64_t* in, uint64_t* out, int64_t k, void* temp, size_t bytes, hipStream_t st);
 hipError_t launch_sort_pairs(const uint64_t* kin, uint64_t* kout, const int32_t* vin, int32_t* vout, int64_t k,
                              void* temp, size_t bytes, hipStream_t st);
-// keep[e] = 0 iff edge e's arc is in the sorted deletion keys. With x
+// Row of every edge: dst[e] = u for e in [rowptr[u], rowptr[u+1]).
+hipError_t launch_row_ids(const int32_t* rowptr, int32_t n, int32_t* dst, hipStream_t st);
+// For every distinct sorted deletion key: keep[e] = 0 for the matching edges
+// (rows sorted by source), od_new[s] decreased by their count. With x
 // non-null, destinations of deleted edges that support their value are
 // appended to list (count) once each (taint[v] set).
-hipError_t launch_mark_kept(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
-                            const uint64_t* dkeys, int64_t nd, int32_t* keep, int app, const uint32_t* x,
-                            int32_t source, int32_t* taint, int32_t* list, int32_t* count, hipStream_t st);
+hipError_t launch_mark_deleted(const int32_t* rowptr, const int32_t* col, const int32_t* weight,
+                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, int app,
+                               const uint32_t* x, int32_t source, int32_t* taint, int32_t* list, int32_t* count,
+                               hipStream_t st);
+// od_new[s] and ins_cnt[s] (nullable) increased for every inserted arc s -> d.
+hipError_t launch_ins_outdeg(const uint64_t* ikeys, int64_t ni, int32_t* od_new, int32_t* ins_cnt, hipStream_t st);
 // ins_rp[u] (u in [0, n]) = first sorted insertion with destination >= u.
 hipError_t launch_ins_rows(const uint64_t* ikeys, int64_t ni, int32_t n, int32_t* ins_rp, hipStream_t st);
 // New row lengths: survivors (keep_ex: exclusive scan of keep, m+1 entries) plus insertions.
 hipError_t launch_new_len(const int32_t* rowptr, const int32_t* keep_ex, const int32_t* ins_rp, int32_t n,
                           int32_t* len, hipStream_t st);
 // Merge of survivors and insertions into the new CSR (rows sorted by source,
-// old edges first on equal sources); old_of_new[e'] = old edge or -1.
-hipError_t launch_scatter_old(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
-                              const int32_t* keep, const int32_t* keep_ex, const uint64_t* ikeys,
-                              const int32_t* ins_rp, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
-                              int32_t* old_of_new, hipStream_t st);
+// old edges first on equal sources); old_of_new[e'] = old edge or -1,
+// new_of_old[e] = new position or -1. With noedge non-null, scatter_ins also
+// places each inserted arc in the new out-CSR (after its source's surviving
+// entries: orow_new[s+1] - ins_cnt[s] + its turn from icur[s], zeroed).
+hipError_t launch_scatter_old(const int32_t* rowptr, const int32_t* row_of_edge, const int32_t* col,
+                              const int32_t* weight, int64_t m, const int32_t* keep, const int32_t* keep_ex,
+                              const uint64_t* ikeys, const int32_t* ins_rp, const int32_t* new_rp, int32_t* ncol,
+                              int32_t* nweight, int32_t* old_of_new, int32_t* new_of_old, hipStream_t st);
 hipError_t launch_scatter_ins(const int32_t* rowptr, const int32_t* col, const int32_t* keep_ex,
                               const uint64_t* ikeys, const int32_t* iidx, int64_t ni, const int32_t* ins_rp,
                               const int32_t* ins_w, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
-                              int32_t* old_of_new, hipStream_t st);
+                              int32_t* old_of_new, const int32_t* orow_new, const int32_t* ins_cnt, int32_t* icur,
+                              int32_t* noedge, int32_t* nodst, hipStream_t st);
+// Surviving out-CSR entries (kout[k] = 1), then their compaction into the new
+// out-CSR (kout_ex: exclusive scan of kout, m+1 entries).
+hipError_t launch_out_keep(const int32_t* oedge, int64_t m, const int32_t* new_of_old, int32_t* kout, hipStream_t st);
+hipError_t launch_out_compact(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* col_old,
+                              const int32_t* orow_old, const int32_t* kout, const int32_t* kout_ex,
+                              const int32_t* new_of_old, const int32_t* orow_new, int32_t* noedge, int32_t* nodst,
+                              hipStream_t st);
 // New flag bitmap: continued edges keep their flag, inserted ones are set.
 hipError_t launch_remap_bits(const uint32_t* old_bits, const int32_t* old_of_new, int64_t m, uint32_t* new_bits,
                              hipStream_t st);

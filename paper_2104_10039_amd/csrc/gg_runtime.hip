@@ -2154,13 +2154,27 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
     GG_HIP(launch_fill_u32((uint32_t*)taint, n, 0u, g->stream));
     GG_HIP(launch_fill_u32((uint32_t*)tcount, 1, 0u, g->stream));
   }
-  int32_t *keep, *keep_ex, *scr;
+  int32_t *keep, *keep_ex, *scr, *od_new;
   GG_TRY(T.get(&keep, (size_t)m0));
   GG_TRY(T.get(&keep_ex, (size_t)m0 + 1));
+  GG_TRY(T.get(&od_new, (size_t)n));
   const int64_t big = std::max<int64_t>(m0, n);
   GG_TRY(T.get(&scr, (size_t)(big / 1024 + 2)));
-  GG_HIP(launch_mark_kept(g->rowptr, g->col, g->weight, n, m0, dks, nd, keep, app,
-                          taint_mode ? g->xu[r->cur] : nullptr, r ? r->p.source : 0, taint, tlist, tcount, g->stream));
+  GG_HIP(launch_fill_u32((uint32_t*)keep, m0, 1u, g->stream));
+  GG_HIP(launch_copy_u32((const uint32_t*)g->outdeg, (uint32_t*)od_new, n, g->stream));
+  GG_HIP(launch_mark_deleted(g->rowptr, g->col, g->weight, dks, nd, keep, od_new, app,
+                             taint_mode ? g->xu[r->cur] : nullptr, r ? r->p.source : 0, taint, tlist, tcount,
+                             g->stream));
+  // the out-CSR, when built, is carried over rather than rebuilt
+  const bool out = g->out_built;
+  int32_t *ins_cnt = nullptr, *icur = nullptr;
+  if (out) {
+    GG_TRY(T.get(&ins_cnt, (size_t)n));
+    GG_TRY(T.get(&icur, (size_t)n));
+    GG_HIP(launch_fill_u32((uint32_t*)ins_cnt, n, 0u, g->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)icur, n, 0u, g->stream));
+  }
+  GG_HIP(launch_ins_outdeg(iks, ni, od_new, ins_cnt, g->stream));
   if (m0 > 0) GG_HIP(launch_scan(keep, keep_ex, (int32_t)m0, keep_ex + m0, scr, g->stream));
   else GG_HIP(launch_fill_u32((uint32_t*)keep_ex, 1, 0u, g->stream));
   int32_t kept = 0;
@@ -2173,15 +2187,20 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   int32_t *ins_rp, *len;
   GG_TRY(T.get(&ins_rp, (size_t)n + 1));
   GG_TRY(T.get(&len, (size_t)n + 1));
-  int32_t* oon = nullptr;
+  int32_t *oon = nullptr, *rowid = nullptr, *new_of_old = nullptr;
   GG_TRY(T.get(&oon, (size_t)m1));
+  GG_TRY(T.get(&rowid, (size_t)m0));
+  GG_TRY(T.get(&new_of_old, (size_t)m0));
   struct Owned {
-    int32_t *rowptr = nullptr, *col = nullptr, *weight = nullptr;
+    int32_t *rowptr = nullptr, *col = nullptr, *weight = nullptr, *orow = nullptr, *oedge = nullptr, *odst = nullptr;
     uint32_t *wedges = nullptr, *bits0 = nullptr, *bits1 = nullptr, *act_edges = nullptr;
     ~Owned() {
       dfree(rowptr);
       dfree(col);
       dfree(weight);
+      dfree(orow);
+      dfree(oedge);
+      dfree(odst);
       dfree(wedges);
       dfree(bits0);
       dfree(bits1);
@@ -2200,6 +2219,14 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
     GG_TRY(dalloc(&nw.bits1, nwords));
     GG_TRY(dalloc(&nw.act_edges, (size_t)m1));
   }
+  int32_t *kout = nullptr, *kout_ex = nullptr;
+  if (out) {
+    GG_TRY(dalloc(&nw.orow, (size_t)n + 1));
+    GG_TRY(dalloc(&nw.oedge, (size_t)m1));
+    GG_TRY(dalloc(&nw.odst, (size_t)m1));
+    GG_TRY(T.get(&kout, (size_t)m0));
+    GG_TRY(T.get(&kout_ex, (size_t)m0 + 1));
+  }
   int32_t* od_old = nullptr;
   if (r && is_pr(app)) {
     GG_TRY(T.get(&od_old, (size_t)n));
@@ -2211,10 +2238,21 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   GG_HIP(launch_new_len(g->rowptr, keep_ex, ins_rp, n, len, g->stream));
   if (n > 0) GG_HIP(launch_scan(len, nw.rowptr, n, nw.rowptr + n, scr, g->stream));
   else GG_HIP(launch_fill_u32((uint32_t*)nw.rowptr, 1, 0u, g->stream));
-  GG_HIP(launch_scatter_old(g->rowptr, g->col, g->weight, n, m0, keep, keep_ex, iks, ins_rp, nw.rowptr, nw.col,
-                            nw.weight, oon, g->stream));
+  GG_HIP(launch_row_ids(g->rowptr, n, rowid, g->stream));
+  if (out) {
+    if (n > 0) GG_HIP(launch_scan(od_new, nw.orow, n, nw.orow + n, scr, g->stream));
+    else GG_HIP(launch_fill_u32((uint32_t*)nw.orow, 1, 0u, g->stream));
+  }
+  GG_HIP(launch_scatter_old(g->rowptr, rowid, g->col, g->weight, m0, keep, keep_ex, iks, ins_rp, nw.rowptr, nw.col,
+                            nw.weight, oon, new_of_old, g->stream));
   GG_HIP(launch_scatter_ins(g->rowptr, g->col, keep_ex, iks, ixs, ni, ins_rp, iw, nw.rowptr, nw.col, nw.weight, oon,
-                            g->stream));
+                            nw.orow, ins_cnt, icur, out ? nw.oedge : nullptr, nw.odst, g->stream));
+  if (out) {
+    GG_HIP(launch_out_keep(g->oedge, m0, new_of_old, kout, g->stream));
+    if (m0 > 0) GG_HIP(launch_scan(kout, kout_ex, (int32_t)m0, kout_ex + m0, scr, g->stream));
+    GG_HIP(launch_out_compact(g->oedge, g->odst, m0, g->col, g->orow, kout, kout_ex, new_of_old, nw.orow, nw.oedge,
+                              nw.odst, g->stream));
+  }
   const bool flags_run = r && r->pol.kind != GG_POLICY_EXACT;
   if (flags_run) GG_HIP(launch_remap_bits(g->bits[r->bcur], oon, m1, nw.bits0, g->stream));
   GG_HIP(hipStreamSynchronize(g->stream));
@@ -2247,12 +2285,17 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
     g->act_edges = nw.act_edges;
     nw.bits0 = nw.bits1 = nw.act_edges = nullptr;
   }
-  GG_HIP(launch_outdeg(g->col, g->m, g->outdeg, g->n, g->stream));
+  GG_HIP(launch_copy_u32((const uint32_t*)od_new, (uint32_t*)g->outdeg, n, g->stream));
   GG_HIP(launch_dangling_list(g->outdeg, g->n, g->dang, g->i32_scratch, (int32_t*)g->blk_scratch, g->stream));
   GG_TRY(readback(g, &g->n_dang, g->i32_scratch, sizeof(int32_t)));
-  if (g->out_built) {
-    g->out_built = false;
-    GG_TRY(ensure_out(g));
+  if (out) {
+    dfree(g->orow);
+    dfree(g->oedge);
+    dfree(g->odst);
+    g->orow = nw.orow;
+    g->oedge = nw.oedge;
+    g->odst = nw.odst;
+    nw.orow = nw.oedge = nw.odst = nullptr;
   }
   GG_TRY(rebin_full(g));
   if (g->ws) GG_TRY(ensure_parts(g));

@@ -5,10 +5,12 @@
 // update rules are this library's reading (see include/gg.h).
 //
 // Arcs of a batch are keyed (destination << 32) | source and radix-sorted
-// (stable, so equal arcs keep their batch order). Every old edge looks its
-// key up in the sorted deletions; the surviving edges and the sorted
-// insertions of a row are merged by source with two binary searches per
-// arc, old edges first on equal sources, so rows stay sorted by source.
+// (stable, so equal arcs keep their batch order). Each distinct deletion
+// finds its run of matching edges in the sorted row; the surviving edges and
+// the sorted insertions of a row are merged by source, old edges first on
+// equal sources, so rows stay sorted by source. Out-degrees and the out-CSR
+// of the frontier are carried over (survivors compacted, insertions
+// appended) instead of being recounted with one atomic per edge.
 #include <hipcub/hipcub.hpp>
 
 #include "gg_internal.h"
@@ -28,17 +30,6 @@ int grid_of(int64_t work) {
 
 __device__ __forceinline__ uint64_t arc_key(int32_t src, int32_t dst) {
   return ((uint64_t)(uint32_t)dst << 32) | (uint32_t)src;
-}
-
-// Row holding edge e: the last u with rowptr[u] <= e (rows may be empty).
-__device__ __forceinline__ int row_of(const int32_t* rowptr, int32_t n, int64_t e) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (rowptr[mid] <= e) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
 }
 
 // First index in sorted keys[lo, hi) whose key is >= k.
@@ -78,22 +69,51 @@ __global__ void k_arc_keys(const int32_t* src, const int32_t* dst, int64_t k, ui
   }
 }
 
-// keep[e] = 0 for the edges whose arc is listed for deletion. With x set,
-// the destinations of deleted supporting edges are appended to the taint
-// list (taint[v] guards against duplicates).
-__global__ void k_mark_kept(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
-                            const uint64_t* dkeys, int64_t nd, int32_t* keep, int app, const uint32_t* x,
-                            int32_t source, int32_t* taint, int32_t* list, int32_t* count) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-    const int u = row_of(rowptr, n, e);
-    const int32_t s = col[e];
-    const uint64_t key = arc_key(s, u);
-    const int64_t p = lower_bound_u64(dkeys, 0, nd, key);
-    const bool del = p < nd && dkeys[p] == key;
-    keep[e] = del ? 0 : 1;
-    if (del && x && supports(app, x, source, s, u, weight ? (uint32_t)weight[e] : 0u)) {
-      if (atomicExch(&taint[u], 1) == 0) list[atomicAdd(count, 1)] = u;
+// Row of every edge (one wavefront per row).
+__global__ __launch_bounds__(kUpdBlock) void k_row_ids(const int32_t* rowptr, int32_t n, int32_t* dst) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t u = wave; u < n; u += nwaves)
+    for (int32_t e = rowptr[u] + lane; e < rowptr[u + 1]; e += 64) dst[e] = (int32_t)u;
+}
+
+// One thread per distinct deletion key (s, d): the matching edges, a run of
+// equal sources in the sorted row d, get keep[e] = 0 and leave s's
+// out-degree. With x set, a deleted edge that supports d's value appends d
+// to the taint list (taint[d] guards against duplicates).
+__global__ void k_mark_deleted(const int32_t* rowptr, const int32_t* col, const int32_t* weight,
+                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, int app,
+                               const uint32_t* x, int32_t source, int32_t* taint, int32_t* list, int32_t* count) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nd; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = dkeys[j];
+    if (j > 0 && dkeys[j - 1] == key) continue;
+    const int32_t d = (int32_t)(key >> 32);
+    const int32_t s = (int32_t)(uint32_t)key;
+    int lo = rowptr[d], hi = rowptr[d + 1];  // first edge of the row with source >= s
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (col[mid] < s) lo = mid + 1;
+      else hi = mid;
     }
+    int cnt = 0;
+    bool seed = false;
+    for (int e = lo; e < rowptr[d + 1] && col[e] == s; ++e) {
+      keep[e] = 0;
+      ++cnt;
+      if (x && supports(app, x, source, s, d, weight ? (uint32_t)weight[e] : 0u)) seed = true;
+    }
+    if (cnt) atomicSub(&od_new[s], cnt);
+    if (seed && atomicExch(&taint[d], 1) == 0) list[atomicAdd(count, 1)] = d;
+  }
+}
+
+// Out-degree and per-source insertion count of the inserted arcs.
+__global__ void k_ins_outdeg(const uint64_t* ikeys, int64_t ni, int32_t* od_new, int32_t* ins_cnt) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ni; j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = (int32_t)(uint32_t)ikeys[j];
+    atomicAdd(&od_new[s], 1);
+    if (ins_cnt) atomicAdd(&ins_cnt[s], 1);
   }
 }
 
@@ -110,20 +130,27 @@ __global__ void k_new_len(const int32_t* rowptr, const int32_t* keep_ex, const i
 }
 
 // A surviving old edge goes after the survivors before it in its row and
-// after the row's insertions with a smaller source.
-__global__ void k_scatter_old(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
-                              const int32_t* keep, const int32_t* keep_ex, const uint64_t* ikeys, const int32_t* ins_rp,
-                              const int32_t* new_rp, int32_t* ncol, int32_t* nweight, int32_t* old_of_new) {
+// after the row's insertions with a smaller source. new_of_old[e] receives
+// its new position (-1 when deleted).
+__global__ void k_scatter_old(const int32_t* rowptr, const int32_t* row_of_edge, const int32_t* col,
+                              const int32_t* weight, int64_t m, const int32_t* keep, const int32_t* keep_ex,
+                              const uint64_t* ikeys, const int32_t* ins_rp, const int32_t* new_rp, int32_t* ncol,
+                              int32_t* nweight, int32_t* old_of_new, int32_t* new_of_old) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-    if (!keep[e]) continue;
-    const int u = row_of(rowptr, n, e);
+    if (!keep[e]) {
+      new_of_old[e] = -1;
+      continue;
+    }
+    const int u = row_of_edge[e];
     const int32_t s = col[e];
     const int64_t rank = keep_ex[e] - keep_ex[rowptr[u]];
-    const int64_t before = lower_bound_u64(ikeys, ins_rp[u], ins_rp[u + 1], arc_key(s, u)) - ins_rp[u];
+    const int32_t i0 = ins_rp[u], i1 = ins_rp[u + 1];
+    const int64_t before = i0 == i1 ? 0 : lower_bound_u64(ikeys, i0, i1, arc_key(s, u)) - i0;
     const int64_t pos = new_rp[u] + rank + before;
     ncol[pos] = s;
     if (nweight) nweight[pos] = weight[e];
     old_of_new[pos] = (int32_t)e;
+    new_of_old[e] = (int32_t)pos;
   }
 }
 
@@ -131,7 +158,9 @@ __global__ void k_scatter_old(const int32_t* rowptr, const int32_t* col, const i
 // surviving old edge whose source is not larger.
 __global__ void k_scatter_ins(const int32_t* rowptr, const int32_t* col, const int32_t* keep_ex, const uint64_t* ikeys,
                               const int32_t* iidx, int64_t ni, const int32_t* ins_rp, const int32_t* ins_w,
-                              const int32_t* new_rp, int32_t* ncol, int32_t* nweight, int32_t* old_of_new) {
+                              const int32_t* new_rp, int32_t* ncol, int32_t* nweight, int32_t* old_of_new,
+                              const int32_t* orow_new, const int32_t* ins_cnt, int32_t* icur, int32_t* noedge,
+                              int32_t* nodst) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ni; j += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = ikeys[j];
     const int u = (int)(key >> 32);
@@ -147,6 +176,34 @@ __global__ void k_scatter_ins(const int32_t* rowptr, const int32_t* col, const i
     ncol[pos] = s;
     if (nweight) nweight[pos] = ins_w[iidx[j]];
     old_of_new[pos] = -1;
+    if (noedge) {
+      // the inserted arcs of a source follow its surviving out-arcs
+      const int32_t q = orow_new[s + 1] - ins_cnt[s] + atomicAdd(&icur[s], 1);
+      noedge[q] = (int32_t)pos;
+      nodst[q] = u;
+    }
+  }
+}
+
+// Out-CSR after an update, surviving entries: kout[k] = 1 when out-entry k
+// (in-edge oedge[k]) survives.
+__global__ void k_out_keep(const int32_t* oedge, int64_t m, const int32_t* new_of_old, int32_t* kout) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+    kout[k] = new_of_old[oedge[k]] >= 0 ? 1 : 0;
+}
+
+// A surviving out-entry keeps its rank among its source's survivors, now
+// pointing at the edge's new position.
+__global__ void k_out_compact(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* col_old,
+                              const int32_t* orow_old, const int32_t* kout, const int32_t* kout_ex,
+                              const int32_t* new_of_old, const int32_t* orow_new, int32_t* noedge, int32_t* nodst) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    if (!kout[k]) continue;
+    const int32_t e = oedge[k];
+    const int32_t v = col_old[e];
+    const int64_t q = orow_new[v] + (kout_ex[k] - kout_ex[orow_old[v]]);
+    noedge[q] = new_of_old[e];
+    nodst[q] = odst[k];
   }
 }
 
@@ -267,12 +324,25 @@ hipError_t launch_sort_pairs(const uint64_t* kin, uint64_t* kout, const int32_t*
   return hipcub::DeviceRadixSort::SortPairs(temp, bytes, kin, kout, vin, vout, (int)k, 0, 64, st);
 }
 
-hipError_t launch_mark_kept(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
-                            const uint64_t* dkeys, int64_t nd, int32_t* keep, int app, const uint32_t* x,
-                            int32_t source, int32_t* taint, int32_t* list, int32_t* count, hipStream_t st) {
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark_kept, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, rowptr, col, weight, n, m, dkeys, nd,
-                     keep, app, x, source, taint, list, count);
+hipError_t launch_row_ids(const int32_t* rowptr, int32_t n, int32_t* dst, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_ids, dim3(grid_of((int64_t)n * 64)), dim3(kUpdBlock), 0, st, rowptr, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_deleted(const int32_t* rowptr, const int32_t* col, const int32_t* weight,
+                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, int app,
+                               const uint32_t* x, int32_t source, int32_t* taint, int32_t* list, int32_t* count,
+                               hipStream_t st) {
+  if (nd == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_deleted, dim3(grid_of(nd)), dim3(kUpdBlock), 0, st, rowptr, col, weight, dkeys, nd, keep,
+                     od_new, app, x, source, taint, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_ins_outdeg(const uint64_t* ikeys, int64_t ni, int32_t* od_new, int32_t* ins_cnt, hipStream_t st) {
+  if (ni == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ins_outdeg, dim3(grid_of(ni)), dim3(kUpdBlock), 0, st, ikeys, ni, od_new, ins_cnt);
   return hipGetLastError();
 }
 
@@ -288,23 +358,40 @@ hipError_t launch_new_len(const int32_t* rowptr, const int32_t* keep_ex, const i
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_old(const int32_t* rowptr, const int32_t* col, const int32_t* weight, int32_t n, int64_t m,
-                              const int32_t* keep, const int32_t* keep_ex, const uint64_t* ikeys,
-                              const int32_t* ins_rp, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
-                              int32_t* old_of_new, hipStream_t st) {
+hipError_t launch_scatter_old(const int32_t* rowptr, const int32_t* row_of_edge, const int32_t* col,
+                              const int32_t* weight, int64_t m, const int32_t* keep, const int32_t* keep_ex,
+                              const uint64_t* ikeys, const int32_t* ins_rp, const int32_t* new_rp, int32_t* ncol,
+                              int32_t* nweight, int32_t* old_of_new, int32_t* new_of_old, hipStream_t st) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_old, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, rowptr, col, weight, n, m, keep,
-                     keep_ex, ikeys, ins_rp, new_rp, ncol, nweight, old_of_new);
+  hipLaunchKernelGGL(k_scatter_old, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, rowptr, row_of_edge, col, weight, m,
+                     keep, keep_ex, ikeys, ins_rp, new_rp, ncol, nweight, old_of_new, new_of_old);
   return hipGetLastError();
 }
 
 hipError_t launch_scatter_ins(const int32_t* rowptr, const int32_t* col, const int32_t* keep_ex,
                               const uint64_t* ikeys, const int32_t* iidx, int64_t ni, const int32_t* ins_rp,
                               const int32_t* ins_w, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
-                              int32_t* old_of_new, hipStream_t st) {
+                              int32_t* old_of_new, const int32_t* orow_new, const int32_t* ins_cnt, int32_t* icur,
+                              int32_t* noedge, int32_t* nodst, hipStream_t st) {
   if (ni == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_ins, dim3(grid_of(ni)), dim3(kUpdBlock), 0, st, rowptr, col, keep_ex, ikeys, iidx, ni,
-                     ins_rp, ins_w, new_rp, ncol, nweight, old_of_new);
+                     ins_rp, ins_w, new_rp, ncol, nweight, old_of_new, orow_new, ins_cnt, icur, noedge, nodst);
+  return hipGetLastError();
+}
+
+hipError_t launch_out_keep(const int32_t* oedge, int64_t m, const int32_t* new_of_old, int32_t* kout, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_out_keep, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, oedge, m, new_of_old, kout);
+  return hipGetLastError();
+}
+
+hipError_t launch_out_compact(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* col_old,
+                              const int32_t* orow_old, const int32_t* kout, const int32_t* kout_ex,
+                              const int32_t* new_of_old, const int32_t* orow_new, int32_t* noedge, int32_t* nodst,
+                              hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_out_compact, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, oedge, odst, m, col_old, orow_old, kout,
+                     kout_ex, new_of_old, orow_new, noedge, nodst);
   return hipGetLastError();
 }
 
