@@ -36,7 +36,7 @@ P_B2 = P_W2 + MLP_HIDDEN * MLP_HIDDEN
 P_W3 = P_B2 + MLP_HIDDEN
 P_B3 = P_W3 + MLP_HIDDEN
 FIXED_ITERS, FIXED_POINT = 0, 1
-INFL_PREFIX, INFL_TOTAL = 0, 1
+INFL_PREFIX, INFL_TOTAL, INFL_PUSH = 0, 1, 2
 MASK_REPLACE, MASK_UNION = 0, 1
 DANGLING_UNIFORM, DANGLING_NONE = 0, 1
 DEGREE_FULL, DEGREE_ACTIVE = 0, 1

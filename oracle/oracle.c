@@ -457,6 +457,11 @@ ggo_run* ggo_begin(const ggo_csr* g, const ggo_app_params* app, const ggo_policy
     set_err("TOTAL influence is defined for PR/PPR only");
     return NULL;
   }
+  if (pol->influence == GGO_INFL_PUSH && app->app != GGO_SSSP && app->app != GGO_CC) {
+    set_err("PUSH influence is defined for SSSP/CC only");
+    return NULL;
+  }
+  if (pol->influence < GGO_INFL_PREFIX || pol->influence > GGO_INFL_PUSH) { set_err("bad influence"); return NULL; }
   const int pr_app = app->app == GGO_PR || app->app == GGO_PPR;
   if (app->pr_degree != GGO_DEGREE_FULL && app->pr_degree != GGO_DEGREE_ACTIVE) { set_err("bad pr_degree"); return NULL; }
   if (app->pr_degree == GGO_DEGREE_ACTIVE && (!pr_app || pol->kind == GGO_LEARNED || pol->trace)) {
@@ -677,7 +682,9 @@ static void pass_sssp(ggo_run* r, const uint8_t* mode, uint32_t* out, int64_t* e
       if (cand < best) best = (uint32_t)cand;
     }
     if (mode[u] == ROW_SUPER) {
-      uint64_t run = GGO_INF_U32; /* running minimum, starts at INF */
+      /* running minimum: starts at INF, or (push order) at the vertex's own
+         value, which the pushes then lower in source order */
+      uint64_t run = r->pol.influence == GGO_INFL_PUSH ? r->d_x[u] : GGO_INF_U32;
       for (int32_t e = b; e < e_end; ++e) {
         const uint32_t xv = r->d_x[g->col[e]];
         if (xv == GGO_INF_U32) { r->infl[e] = -1.0; continue; } /* not assessable */
@@ -717,7 +724,7 @@ static void pass_cc(ggo_run* r, const uint8_t* mode, int32_t* out, int64_t* edge
       if (xv < best) best = xv;
     }
     if (mode[u] == ROW_SUPER) {
-      int64_t run = INT64_MAX;
+      int64_t run = r->pol.influence == GGO_INFL_PUSH ? (int64_t)r->l_x[u] : INT64_MAX;
       for (int32_t e = b; e < e_end; ++e) {
         const int32_t xv = r->l_x[g->col[e]];
         r->infl[e] = xv < run ? 1.0 : 0.0;
@@ -755,7 +762,7 @@ static void estatus_sssp(ggo_run* r) {
   const uint64_t theta_q = (uint64_t)floor(r->theta_now * 65536.0 + 0.5);
   for (int32_t u = 0; u < g->n; ++u) {
     if (r->mode[u] != ROW_SUPER) continue;
-    uint64_t run = GGO_INF_U32;
+    uint64_t run = r->pol.influence == GGO_INFL_PUSH ? r->d_x[u] : GGO_INF_U32;
     for (int32_t e = g->rowptr[u]; e < g->rowptr[u + 1]; ++e) {
       const uint32_t xv = r->d_x[g->col[e]];
       if (xv == GGO_INF_U32) continue; /* not assessable: keeps its flag */

@@ -52,7 +52,9 @@ enum { GGO_KIND_APPROX = 0, GGO_KIND_ACCURATE = 1, GGO_KIND_FULL = 2, GGO_KIND_P
 #define GGO_MLP_PARAMS \
   (GGO_MLP_IN * GGO_MLP_HIDDEN + GGO_MLP_HIDDEN + GGO_MLP_HIDDEN * GGO_MLP_HIDDEN + GGO_MLP_HIDDEN + GGO_MLP_HIDDEN + 1)
 enum { GGO_STOP_FIXED_ITERS = 0, GGO_STOP_FIXED_POINT = 1 };
-enum { GGO_INFL_PREFIX = 0, GGO_INFL_TOTAL = 1 };
+/* PUSH (SSSP/CC): influence in push order, the destination's running value
+   starting at its own value before the superstep instead of at INF. */
+enum { GGO_INFL_PREFIX = 0, GGO_INFL_TOTAL = 1, GGO_INFL_PUSH = 2 };
 enum { GGO_MASK_REPLACE = 0, GGO_MASK_UNION = 1 };
 enum { GGO_DANGLING_UNIFORM = 0, GGO_DANGLING_NONE = 1 };
 /* PR/PPR out-degree in approximate iterations: the full graph's (FULL) or

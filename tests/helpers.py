@@ -103,7 +103,8 @@ def oracle_kw(kw):
     o["mask_update"] = oracle.MASK_UNION if mu == "union" else oracle.MASK_REPLACE
     dg = o.pop("dangling", "uniform")
     o["dangling"] = oracle.DANGLING_NONE if dg == "none" else oracle.DANGLING_UNIFORM
-    o["influence"] = oracle.INFL_TOTAL if o.pop("influence", "prefix") == "total" else oracle.INFL_PREFIX
+    o["influence"] = {"prefix": oracle.INFL_PREFIX, "total": oracle.INFL_TOTAL,
+                      "push": oracle.INFL_PUSH}[o.pop("influence", "prefix")]
     o["pr_degree"] = oracle.DEGREE_ACTIVE if o.pop("pr_degree", "full") == "active" else oracle.DEGREE_FULL
     o["vstatus"] = {"none": oracle.VSTATUS_NONE, "abs": oracle.VSTATUS_ABS,
                     "rel": oracle.VSTATUS_REL}[o.pop("vstatus", "none")]

@@ -80,6 +80,13 @@ MUTANTS = {
     # BP influence on signed values instead of magnitudes
     "bp_influence_signed": ("r->infl[e] = fabs(P) > 0.0 ? fabs(c) / fabs(P) : 0.0;",
                             "r->infl[e] = P > 0.0 ? c / P : 0.0;"),
+    # SSSP push-order influence starting at INF (the PREFIX reading) in EStatus
+    "push_sssp_starts_at_inf": ("    if (r->mode[u] != ROW_SUPER) continue;\n"
+                                "    uint64_t run = r->pol.influence == GGO_INFL_PUSH ? r->d_x[u] : GGO_INF_U32;",
+                                "    if (r->mode[u] != ROW_SUPER) continue;\n    uint64_t run = GGO_INF_U32;"),
+    # CC push-order influence starting at INF
+    "push_cc_starts_at_inf": ("int64_t run = r->pol.influence == GGO_INFL_PUSH ? (int64_t)r->l_x[u] : INT64_MAX;",
+                              "int64_t run = INT64_MAX;"),
     # dynamic update: the taint closure never grows beyond its seeds
     "update_no_closure": ("      int grew = 1;\n      while (grew) {", "      int grew = 0;\n      while (grew) {"),
     # dynamic update: every deleted arc seeds, supporting or not

@@ -865,3 +865,75 @@ def test_bp_rejects_unsupported():
         oracle.Run(g, "bp", "exact", coupling=0.5)
     with pytest.raises(ValueError):
         oracle.Run(g, "bp", "gg", coupling=0.5, prior=h, influence=oracle.INFL_TOTAL)
+
+
+# --------------------------------------------------------------------------
+# Influence in push order (SSSP/CC): the running value starts at the
+# destination's own value
+# --------------------------------------------------------------------------
+
+def _inf_list(v):
+    return [0xFFFFFFFF if x == "INF" else x for x in v]
+
+
+def test_golden_sssp_push_influence():
+    fx = _load("sssp_push_influence_4v.json")
+    e = fx["graph"]["edges"]
+    g = gg.from_edges(4, [x[0] for x in e], [x[1] for x in e], [x[2] for x in e])
+    p = fx["params"]
+    r = oracle.Run(g, "sssp", "gg", sigma=p["sigma"], alpha=p["alpha"], theta=p["theta"], source=p["source"],
+                   iters=p["iters"], influence=oracle.INFL_PUSH)
+    gathered = []
+    for it in range(1, p["iters"] + 1):
+        st = r.step()
+        gathered.append(st.edges)
+        assert r.values().tolist() == _inf_list(fx["expected"]["values_after"][str(it)]), it
+        if str(it) in fx["expected"]["mask_after"]:
+            assert r.mask().tolist() == fx["expected"]["mask_after"][str(it)], it
+    assert gathered == fx["expected"]["edges_gathered"]
+    r.close()
+
+
+def test_golden_cc_push_influence():
+    fx = _load("cc_push_influence_path3.json")
+    e = fx["graph"]["edges"]
+    g = gg.from_edges(3, [x[0] for x in e], [x[1] for x in e])
+    p = fx["params"]
+    for infl, key in ((oracle.INFL_PUSH, "mask_after_superstep_2"), (oracle.INFL_PREFIX, "prefix_mask_after_superstep_2")):
+        r = oracle.Run(g, "cc", "gg", sigma=p["sigma"], alpha=p["alpha"], theta=p["theta"], iters=p["iters"],
+                       influence=infl)
+        for it in range(1, p["iters"] + 1):
+            r.step()
+            assert r.values().tolist() == fx["expected"]["values_after"][str(it)], it
+            if it == 2:
+                assert r.mask().tolist() == fx["expected"][key]
+        r.close()
+
+
+@pytest.mark.parametrize("app", ["sssp", "cc"])
+def test_push_flags_are_a_subset_of_prefix_flags(app):
+    """From the same state (identical runs up to the first superstep), an
+    edge active in push order is active under PREFIX too: its running value
+    is never above PREFIX's, so it improves it less. The subset is strict on
+    R-MAT, and values are unaffected by the flags of that superstep."""
+    g = gg.rmat(10, 8, seed=12, weights=(app == "sssp"), symmetrize=(app == "cc"))
+    cand = gg.pick_sources(g, 8, 12)
+    s = int(cand[np.argmax(g.outdeg()[cand])])
+    runs = {}
+    for infl in (oracle.INFL_PREFIX, oracle.INFL_PUSH):
+        r = oracle.Run(g, app, "gg", sigma=0.5, alpha=7, theta=0.05, seed=2, source=s, iters=8, influence=infl)
+        for _ in range(8):
+            r.step()
+        runs[infl] = (r.mask(), r.values())
+        r.close()
+    mp, vp = runs[oracle.INFL_PREFIX]
+    mu, vu = runs[oracle.INFL_PUSH]
+    assert np.all(mu <= mp) and mu.sum() < mp.sum()
+    assert np.array_equal(vp, vu)
+
+
+def test_push_influence_rejected_for_sum_apps():
+    g = gg.rmat(6, 4, seed=1)
+    for app in ("pr", "ppr"):
+        with pytest.raises(ValueError):
+            oracle.Run(g, app, "gg", influence=oracle.INFL_PUSH)
