@@ -98,11 +98,17 @@ typedef enum { GG_STEP_APPROX = 0, GG_STEP_ACCURATE = 1, GG_STEP_FULL = 2, GG_ST
    runs always stop at their first no-change iteration. */
 typedef enum { GG_STOP_FIXED_ITERS = 0, GG_STOP_FIXED_POINT = 1 } gg_stop;
 
-/* PageRank edge influence [Alg. 2, GG-Gather]: PREFIX = contribution over the
-   running sum of the row in CSR order; TOTAL = contribution over the row sum
-   (PR/PPR; its supersteps gather every edge twice, once for the row sums;
-   not with LEARNED: GG_E_UNSUPPORTED). */
-typedef enum { GG_INFL_PREFIX = 0, GG_INFL_TOTAL = 1 } gg_influence;
+/* Edge influence at a superstep [Alg. 2, GG-Gather]. PREFIX: over the
+   running value of the row in CSR order, starting from the gather's identity
+   (PR/PPR/BP: contribution over the running sum; SSSP: relative improvement
+   of the running minimum; CC: lowers the running minimum). TOTAL (PR/PPR):
+   contribution over the row sum (its supersteps gather every edge twice,
+   once for the row sums; not with LEARNED: GG_E_UNSUPPORTED). PUSH
+   (SSSP/CC): push order [Sec. 3.1: the method is not tied to the pull
+   model], the running minimum starting at the destination's own value
+   before the superstep, so that an edge stays active only while it improves
+   its destination; values are those of PREFIX. */
+typedef enum { GG_INFL_PREFIX = 0, GG_INFL_TOTAL = 1, GG_INFL_PUSH = 2 } gg_influence;
 
 /* Flag update at a superstep: REPLACE deactivates every edge that does not
    qualify [Sec. 3.4]; UNION keeps previously active edges. */

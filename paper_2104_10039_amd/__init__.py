@@ -28,7 +28,7 @@ POLICY = {"exact": 0, "sp": 1, "sms": 2, "gg": 3, "learned": 4}
 STEP_KIND = {0: "approx", 1: "accurate", 2: "full", 3: "partial"}
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 8, 64, 4801
 STOP = {"fixed_iters": 0, "fixed_point": 1}
-INFLUENCE = {"prefix": 0, "total": 1}
+INFLUENCE = {"prefix": 0, "total": 1, "push": 2}
 MASK = {"replace": 0, "union": 1}
 DANGLING = {"uniform": 0, "none": 1}
 CSR_DEVICE_PTRS = 0x1

@@ -113,6 +113,9 @@ struct Sweep {
   // c_in / c_out hold the message log-ratios, x_out the belief log-odds
   const float* bp_prior;
   double bp_kappa;
+  // SSSP/CC influence in push order: a superstep row's running minimum
+  // starts at the row's own value x_in[u] instead of the identity
+  int32_t push_infl;
 };
 
 // Segmented gather constants.

@@ -388,6 +388,14 @@ __device__ __forceinline__ bool sum_flag(const Sweep& s, bool valid, double c, d
   return (valid && infl_above(c, P, s.theta)) || (s.mask_union && oldf);
 }
 
+// Start of a superstep row's running value: the gather identity, or for
+// SSSP/CC in push order the row's own value.
+template <int APP>
+__device__ __forceinline__ typename Tr<APP>::T run_init(const Sweep& s, int u) {
+  if constexpr (kSumApp<APP>) return Tr<APP>::id();
+  else return s.push_infl ? s.x_in[u] : Tr<APP>::id();
+}
+
 // Set the new flag bits of TEAM consecutive edges (edge e at team lane lt).
 template <int TEAM>
 __device__ __forceinline__ void write_bits(uint32_t* bits, uint64_t tm, int lt, int e, int remaining, bool valid) {
@@ -416,7 +424,7 @@ __device__ __forceinline__ void super_team_rows(const Sweep& s, const int32_t* l
     const int len = s.rowptr[u + 1] - b;
     // TOTAL influence compares with the row sum, PREFIX with the running sum
     const double rtot = (kSumApp<APP> && s.row_total) ? s.row_total[u] : -1.0;
-    T carry = R::id();
+    T carry = run_init<APP>(s, u);
     int carry_cnt = 0;
     // edge words and values of kPreT consecutive team-wide steps are loaded
     // before the first step's scan
@@ -569,7 +577,7 @@ __device__ __forceinline__ void super_hub_chunk(const Sweep& s, int ch, int& nch
     if constexpr (kSumApp<APP>) return s.part_f[i];
     else return s.part_u[i];
   };
-  T carry = R::id();
+  T carry = run_init<APP>(s, u);
   for (int i = 0; i < j; ++i) carry = R::op(carry, part(c0 + i));
   int cnt = 0;
   // The edge words and gathered values of kHubPre consecutive 256-edge steps
@@ -721,7 +729,7 @@ __device__ void super_hub_chunk_1p(const Sweep& s, int nchunks, int& nchanged, t
     if (lane == 0) s_carry = p;
   }
   __syncthreads();
-  const T carry0 = s_carry;
+  const T carry0 = R::op(s_carry, run_init<APP>(s, u));
   T carry = carry0;
   bool fq[kHubPre];
 #pragma unroll
@@ -2482,6 +2490,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
   const int mine0 = s_scan[tid], mine1 = s_scan[tid] + len;
   double Psum = 0.0;            // PR: running sum of the row's contributions
   uint32_t run = kInf;          // SSSP/CC: running minimum
+  if constexpr (!kSumApp<APP>) {
+    if (s.push_infl && mine) run = s.x_in[u];  // push order: from the row's own value
+  }
   int cnt = 0;                  // active edges written
   int bw = -1;                  // current flag word
   uint32_t bacc = 0;            // new bits of that word

@@ -726,7 +726,9 @@ int check_params(const gg_graph* g, const gg_app_params* p, double sigma, const 
   if (pol->mask_update != GG_MASK_REPLACE && pol->mask_update != GG_MASK_UNION)
     return fail(GG_E_INVAL, "unknown mask_update");
   if (pol->stop != GG_STOP_FIXED_ITERS && pol->stop != GG_STOP_FIXED_POINT) return fail(GG_E_INVAL, "unknown stop");
-  if (pol->influence != GG_INFL_PREFIX && pol->influence != GG_INFL_TOTAL) return fail(GG_E_INVAL, "unknown influence");
+  if (pol->influence < GG_INFL_PREFIX || pol->influence > GG_INFL_PUSH) return fail(GG_E_INVAL, "unknown influence");
+  if (pol->influence == GG_INFL_PUSH && p->app != GG_APP_SSSP && p->app != GG_APP_CC)
+    return fail(GG_E_INVAL, "PUSH influence is defined for SSSP and CC (push order is PREFIX for sum-type apps)");
   if (p->pr_degree != GG_DEGREE_FULL && p->pr_degree != GG_DEGREE_ACTIVE) return fail(GG_E_INVAL, "unknown pr_degree");
   if (p->pr_degree == GG_DEGREE_ACTIVE) {
     if (!is_pr(p->app)) return fail(GG_E_INVAL, "the ACTIVE out-degree is defined for PR and PPR");
@@ -781,6 +783,7 @@ Sweep base_sweep(const gg_graph* g, const gg_run* r, int32_t i) {
   s.theta = theta_at(r->pol, i);
   s.theta_q = (uint64_t)std::floor(s.theta * 65536.0 + 0.5);
   s.mask_union = r->pol.mask_update == GG_MASK_UNION;
+  s.push_infl = r->pol.influence == GG_INFL_PUSH;
   s.act_edges = g->act_edges;
   s.act_cnt = g->act_cnt;
   if (r->p.app == GG_APP_BP) {
