@@ -73,12 +73,23 @@ def test_learned_gain_over_gg(P, app, eps, tau):
                              ("sp", "sp", dict(alpha=4)),
                              # rho = 1: the network's selection alone, no edge-share fallback
                              ("learned", "learned", dict(alpha=4, mlp=net, tau=tau, rho=1.0, fallback_k=0))):
-        out, st = G.approx_run(app, 0.3, pol, **kw, **extra)
-        res[name] = (st.edges_gathered / sx.edges_gathered, _err(app, out, exact), st.device_ms)
-        log(app, name, "edges %.3f of exact, error %.4f, %.3f ms" % res[name])
-    e_l, err_l, _ = res["learned"]
-    e_g4, err_g4, _ = res["gg4"]
-    e_g8, err_g8, _ = res["gg8"]
+        G.approx_run(app, 0.3, pol, **kw, **extra)  # warm-up of this configuration
+        runs = [G.approx_run(app, 0.3, pol, **kw, **extra) for _ in range(3)]
+        out, st = sorted(runs, key=lambda r: r[1].device_ms)[1]
+        res[name] = (st.edges_gathered / sx.edges_gathered, _err(app, out, exact), st.device_ms,
+                     st.edges_processed)
+        log(app, name, "edges %.3f of exact, error %.4f, %.3f ms, %d edges processed" % res[name])
+    e_l, err_l, ms_l, p_l = res["learned"]
+    e_g4, err_g4, ms_g4, p_g4 = res["gg4"]
+    e_g8, err_g8, _, _ = res["gg8"]
+    # the edges the learned run actually read (features, network and partial
+    # supersteps included) stay below GG's
+    assert p_l < p_g4
+    # time: the fixed costs of a correction step (features, network, the
+    # selection's binning, the rebinning of every active row) outweigh the
+    # edges saved at this size; the bound guards against their growth
+    log(app, "learned / gg4 device time %.2f" % (ms_l / ms_g4))
+    assert ms_l <= 3.0 * ms_g4
     # fewer edges than GG at the same alpha, at no worse accuracy
     assert e_l <= 0.93 * e_g4
     assert err_l <= err_g4 + 0.005
