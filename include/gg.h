@@ -544,6 +544,25 @@ int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t);
 int gg_graph_set_wait_limit(gg_graph* g, int32_t polls);
 
 /*
+ * Captured schedules (project addition). A whole run (gg_exact_run,
+ * gg_approx_run) of PR, PPR or BP under EXACT, SP or SMS has a static
+ * iteration schedule: once the run has begun, no host decision depends on
+ * device data. Its iterations are captured into a HIP graph on the graph's
+ * private stream the first time and replayed by later runs with the same
+ * parameters, scheme, sample ratio, seed and tuning, as long as the graph's
+ * buffers and binning are unchanged (an update, a new tuning or a grown
+ * workspace captures again). Results are identical either way; the launch
+ * is ordered after the work already on the graph's stream and before what
+ * follows. Not while profiling, nor with parts, vertex status, the ACTIVE
+ * degree or traces. enable = 1 turns capture on; it is off by default,
+ * because on gfx950 a replayed schedule was measured no faster than the
+ * same kernels launched one by one (the gaps between dependent kernels are
+ * the device's, and the graph launch adds its own). GG_E_STATE while a run
+ * is active on the graph.
+ */
+int gg_graph_set_capture(gg_graph* g, int enable);
+
+/*
  * Autotuner (project addition): picks the tuning knobs for one workload on
  * this graph by timing that workload. With n_queries = 0 the workload is a
  * single run (gg_exact_run when policy is NULL or EXACT, else gg_approx_run

@@ -148,6 +148,7 @@ SIGNATURES = {
     "gg_run_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(RunStats)]),
     "gg_run_end": (None, [_VP]),
     "gg_graph_update": (ctypes.c_int, [_VP, _VP]),
+    "gg_graph_set_capture": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_run_update": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP]),
     "gg_graph_get_csr": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "gg_graph_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
@@ -454,6 +455,10 @@ class Graph:
         self._parts = (ps, src)
         _check(lib().gg_graph_set_parts(self._h, int(ps.shape[0]) - 1, ps.ctypes.data,
                                         None if src is None else src.ctypes.data))
+
+    def set_capture(self, enable=True):
+        """gg_graph_set_capture: capture and replay static whole-run schedules."""
+        _check(lib().gg_graph_set_capture(self._h, 1 if enable else 0))
 
     def set_profiling(self, enable=True):
         _check(lib().gg_graph_set_profiling(self._h, 1 if enable else 0))

@@ -230,6 +230,25 @@ struct gg_graph {
   int32_t* changed = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   gg_run* active_run = nullptr;
+  // The captured iteration schedule of the last static whole run (EXACT, SP
+  // or SMS of PR/PPR/BP: no host decision depends on device data once the
+  // run has begun), replayed while its key and the graph's generation match.
+  // gen changes whenever a buffer or binning that the schedule refers to is
+  // rebuilt or moved.
+  uint64_t gen = 1;
+  struct RunGraph {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cs = nullptr;  // private stream (default priority)
+    hipEvent_t ea = nullptr, eb = nullptr;
+    uint64_t gen = 0;
+    std::vector<unsigned char> key;
+    // host state of the run after the schedule
+    int32_t iter = 0;
+    int cur = 0;
+    bool x_valid = false;
+    int64_t edges_total = 0, edges_processed = 0;
+  } rg;
+  bool capture = false;  // gg_graph_set_capture
   // kernel profiling (gg_graph_set_profiling)
   struct ProfRec {
     int kind, app;
@@ -390,6 +409,7 @@ int ensure_seg(gg_graph* g) {
   const int64_t need_off = ((int64_t)g->seg_s + 1) * rows;
   const int64_t need_part = (int64_t)g->seg_s * rows;
   if (g->seg_off_full && g->seg_cap_off >= need_off && g->seg_cap_part >= need_part) return GG_OK;
+  g->gen++;
   dfree(g->seg_off_full);
   dfree(g->seg_off_act);
   dfree(g->seg_part);
@@ -448,6 +468,7 @@ int seg_offsets(gg_graph* g, const Bins& b, const uint32_t* edges, const int32_t
 void set_bins(Sweep& s, const Bins& b);
 
 int rebin_full(gg_graph* g) {
+  g->gen++;
   GG_TRY(rebin(g, g->full, nullptr));
   g->chunk_order_n = 0;
   if (!g->tune.seg_enable) return GG_OK;
@@ -534,6 +555,7 @@ int ensure_out(gg_graph* g) {
 int ensure_parts(gg_graph* g) {
   const int64_t need = max_chunks(g);
   if (g->part_cap >= need) return GG_OK;
+  g->gen++;
   dfree(g->part_f);
   dfree(g->part_u);
   dfree(g->part_cnt);
@@ -550,6 +572,7 @@ int ensure_parts(gg_graph* g) {
 
 int ensure_workspace(gg_graph* g) {
   if (g->ws) return ensure_parts(g);
+  g->gen++;
   const size_t n = (size_t)g->n, m = (size_t)g->m, nw = (m + 31) / 32;
   GG_TRY(dalloc(&g->c[0], n));
   GG_TRY(dalloc(&g->c[1], n));
@@ -634,6 +657,10 @@ void free_graph(gg_graph* g) {
   dfree(g->batch.src);
   dfree(g->batch.ctr);
   if (g->batch.cs) (void)hipStreamDestroy(g->batch.cs);
+  if (g->rg.exec) (void)hipGraphExecDestroy(g->rg.exec);
+  if (g->rg.cs) (void)hipStreamDestroy(g->rg.cs);
+  for (hipEvent_t e : {g->rg.ea, g->rg.eb})
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : {g->batch.ea, g->batch.eb, g->batch.t0, g->batch.t1})
     if (e) (void)hipEventDestroy(e);
   dfree(g->seg_part);
@@ -1632,6 +1659,108 @@ void end_run(gg_run* r) {
   delete r;
 }
 
+// Whether a whole run's iterations form a static schedule: after run_begin
+// no host decision of run_step depends on device data (no superstep, no
+// frontier, no readback), so the iterations can be captured once and
+// replayed.
+bool static_schedule(const gg_graph* g, const gg_app_params* p, const gg_correction_policy* pol) {
+  return g->capture && !g->prof && is_float(p->app) && g->n_parts == 0 &&
+         (pol->kind == GG_POLICY_EXACT || pol->kind == GG_POLICY_SP || pol->kind == GG_POLICY_SMS) &&
+         pol->vstatus == GG_VSTATUS_NONE && p->pr_degree == GG_DEGREE_FULL && !pol->trace;
+}
+
+template <typename T>
+void key_add(std::vector<unsigned char>& k, const T& v) {
+  const unsigned char* b = (const unsigned char*)&v;
+  k.insert(k.end(), b, b + sizeof(T));
+}
+
+// Everything the captured kernels' arguments and grids depend on besides
+// the graph's buffers (covered by gen): the run's parameters, the scheme,
+// the sample (sigma, seed) and the tuning.
+std::vector<unsigned char> schedule_key(const gg_graph* g, const gg_app_params* p, double sigma,
+                                        const gg_correction_policy* pol) {
+  std::vector<unsigned char> k;
+  key_add(k, p->app);
+  key_add(k, p->damping);
+  key_add(k, p->iters);
+  key_add(k, p->source);
+  key_add(k, p->dangling);
+  key_add(k, p->coupling);
+  key_add(k, pol->kind);
+  key_add(k, pol->alpha);
+  key_add(k, pol->seed);
+  key_add(k, sigma);
+  key_add(k, g->tune);
+  return k;
+}
+
+// Runs the iterations of a begun static-schedule run: replays the captured
+// schedule when it matches, else captures the iterations on the graph's
+// private stream, instantiates and launches them. The launch is ordered
+// after the work already on the graph's stream and before what follows.
+int run_static(gg_graph* g, gg_run* r, const gg_app_params* p, double sigma, const gg_correction_policy* pol) {
+  auto& G = g->rg;
+  if (!G.cs) GG_HIP(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
+  if (!G.ea) GG_HIP(hipEventCreateWithFlags(&G.ea, hipEventDisableTiming));
+  if (!G.eb) GG_HIP(hipEventCreateWithFlags(&G.eb, hipEventDisableTiming));
+  std::vector<unsigned char> key = schedule_key(g, p, sigma, pol);
+  if (!(G.exec && G.gen == g->gen && G.key == key)) {
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+    hipStream_t saved = g->stream;
+    g->stream = G.cs;
+    int rc = GG_OK;
+    hipError_t e = hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      g->stream = saved;
+      return fail(GG_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    while (!r->done) {
+      const int s = run_step(r, nullptr, false);
+      if (s < 0) {
+        rc = s;
+        break;
+      }
+      if (s == 0) break;
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(G.cs, &graph);
+    g->stream = saved;
+    if (rc != GG_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(GG_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      G.exec = nullptr;
+      return fail(GG_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    G.gen = g->gen;
+    G.key = key;
+    G.iter = r->iter;
+    G.cur = r->cur;
+    G.x_valid = r->x_valid;
+    G.edges_total = r->edges_total;
+    G.edges_processed = r->edges_processed;
+  } else {
+    r->iter = G.iter;
+    r->cur = G.cur;
+    r->x_valid = G.x_valid;
+    r->edges_total = G.edges_total;
+    r->edges_processed = G.edges_processed;
+    r->done = true;
+  }
+  GG_HIP(hipEventRecord(G.ea, g->stream));
+  GG_HIP(hipStreamWaitEvent(G.cs, G.ea, 0));
+  GG_HIP(hipGraphLaunch(G.exec, G.cs));
+  GG_HIP(hipEventRecord(G.eb, G.cs));
+  GG_HIP(hipStreamWaitEvent(g->stream, G.eb, 0));
+  return GG_OK;
+}
+
 int whole_run(gg_graph* g, const gg_app_params* p, double sigma, const gg_correction_policy* pol, void* out,
               uint32_t flags, gg_run_stats* st) {
   if (!g) return fail(GG_E_INVAL, "null graph");
@@ -1640,15 +1769,19 @@ int whole_run(gg_graph* g, const gg_app_params* p, double sigma, const gg_correc
   GG_TRY(ensure_workspace(g));
   GG_HIP(hipEventRecord(g->ev0, g->stream));
   GG_TRY(run_begin(g, p, sigma, pol, &r));
-  const bool need_changed = !is_pr(p->app) && (pol->kind == GG_POLICY_EXACT || pol->stop == GG_STOP_FIXED_POINT);
+  const bool need_changed = !is_float(p->app) && (pol->kind == GG_POLICY_EXACT || pol->stop == GG_STOP_FIXED_POINT);
   int rc = GG_OK;
-  while (!r->done) {
-    int s = run_step(r, nullptr, need_changed);
-    if (s < 0) {
-      rc = s;
-      break;
+  if (static_schedule(g, p, pol) && !r->done) {
+    rc = run_static(g, r, p, sigma, pol);
+  } else {
+    while (!r->done) {
+      int s = run_step(r, nullptr, need_changed);
+      if (s < 0) {
+        rc = s;
+        break;
+      }
+      if (s == 0) break;
     }
-    if (s == 0) break;
   }
   if (rc == GG_OK) {
     hipError_t e = hipEventRecord(g->ev1, g->stream);
@@ -2263,6 +2396,7 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   // replace the CSR and everything derived from it; a failure from here on
   // leaves the graph unusable (full_valid stays false)
   g->full_valid = false;
+  g->gen++;
   if (g->owns_csr) {
     dfree(g->rowptr);
     dfree(g->col);
@@ -2598,6 +2732,15 @@ int gg_graph_set_tuning(gg_graph* g, const gg_tuning* t) {
     if (!g->rows_sorted) g->tune.seg_enable = 0;
     GG_TRY(rebin_full(g));
     if (g->ws) GG_TRY(ensure_parts(g));
+    return GG_OK;
+  });
+}
+
+int gg_graph_set_capture(gg_graph* g, int enable) {
+  return guard([&]() -> int {
+    if (!g) return fail(GG_E_INVAL, "null graph");
+    if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+    g->capture = enable != 0;
     return GG_OK;
   });
 }
