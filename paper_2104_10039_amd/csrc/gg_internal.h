@@ -407,4 +407,9 @@ hipError_t launch_mark_in_neighbors(const int32_t* list, int32_t count, const in
 // chg[s] = 1 for the source of every (sorted) inserted arc.
 hipError_t launch_mark_sources(const uint64_t* ikeys, int64_t ni, uint8_t* chg, hipStream_t st);
 
+// Small readback through mapped coherent host memory: copies `words` 32-bit
+// words of src to host[1..] and then publishes seq in host[0] (system-scope
+// release), after all earlier work on the stream. words <= 63.
+hipError_t launch_post(const uint32_t* src, int32_t words, uint32_t* host, uint32_t seq, hipStream_t st);
+
 }  // namespace ggk

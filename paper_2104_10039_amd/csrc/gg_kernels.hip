@@ -1428,6 +1428,21 @@ hipError_t launch_pr_init(int app, const int32_t* outdeg, int32_t n, int32_t sou
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(64) void k_post(const uint32_t* src, int32_t words, uint32_t* host, uint32_t seq) {
+  const int t = threadIdx.x;
+  if (t < words) __hip_atomic_store(host + 1 + t, src[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __syncthreads();
+  if (t == 0) {
+    __threadfence_system();
+    __hip_atomic_store(host, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+hipError_t launch_post(const uint32_t* src, int32_t words, uint32_t* host, uint32_t seq, hipStream_t st) {
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, st, src, words, host, seq);
+  return hipGetLastError();
+}
+
 hipError_t launch_bp_init(const float* prior, int32_t n, double kappa, float* c, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bp_init, dim3(grid_for(n, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, prior, n, kappa, c);

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -129,6 +130,8 @@ struct gg_graph {
   int64_t m = 0;
   hipStream_t stream = nullptr;
   void* pin = nullptr;  // kPinBytes of pinned host memory for small readbacks
+  uint32_t* pin_dev = nullptr;  // its device address when mapped and coherent (posted readbacks)
+  uint32_t pin_seq = 0;
   bool owns_csr = false;
   int32_t* rowptr = nullptr;
   int32_t* col = nullptr;
@@ -323,10 +326,37 @@ int64_t max_chunks(const gg_graph* g) {
 // Small device-to-host readback that the host waits for: through the graph's
 // pinned buffer when it fits (a direct DMA, no staging copy).
 constexpr size_t kPinBytes = 256;
-static_assert(sizeof(BinCounts) <= kPinBytes && sizeof(FrontCounters) <= kPinBytes,
-              "the per-iteration readbacks fit the pinned buffer");
+static_assert(sizeof(BinCounts) <= kPinBytes - 4 && sizeof(FrontCounters) <= kPinBytes - 4,
+              "the per-iteration readbacks fit the pinned buffer behind its sequence word");
+
+// A posted readback: a one-wavefront kernel, queued after the work it must
+// follow, writes the words and then a sequence number into mapped coherent
+// host memory, and the host polls that number. This wakes the host as soon
+// as the data lands instead of after a copy engine transfer and a stream
+// synchronization. A poll that has not seen the number after 20 ms
+// synchronizes the stream (which reports any earlier device error) before
+// trusting the data.
+int readback_posted(gg_graph* g, void* dst, const void* src, size_t bytes) {
+  uint32_t seq = ++g->pin_seq;
+  if (seq == 0) seq = ++g->pin_seq;
+  GG_HIP(launch_post((const uint32_t*)src, (int32_t)(bytes / 4), g->pin_dev, seq, g->stream));
+  volatile uint32_t* flag = (volatile uint32_t*)g->pin;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t spins = 1; *flag != seq; ++spins) {
+    if ((spins & 4095) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+      GG_HIP(hipStreamSynchronize(g->stream));
+      if (*flag != seq) return fail(GG_E_DEVICE, "posted readback not seen after its stream completed");
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  std::memcpy(dst, (const char*)g->pin + 4, bytes);
+  return GG_OK;
+}
 
 int readback(gg_graph* g, void* dst, const void* src, size_t bytes) {
+  if (g->pin_dev && bytes <= kPinBytes - 4 && bytes % 4 == 0 && ((uintptr_t)src & 3) == 0)
+    return readback_posted(g, dst, src, bytes);
   if (g->pin && bytes <= kPinBytes) {
     GG_HIP(hipMemcpyAsync(g->pin, src, bytes, hipMemcpyDeviceToHost, g->stream));
     GG_HIP(hipStreamSynchronize(g->stream));
@@ -2575,10 +2605,22 @@ int gg_graph_load_csr(const gg_csr_desc* d, void* hip_stream, gg_graph** out) {
       free_graph(g);
       return code;
     };
-    if (hipHostMalloc(&g->pin, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&g->pin, kPinBytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+      void* dp = nullptr;
+      if (hipHostGetDevicePointer(&dp, g->pin, 0) == hipSuccess) {
+        g->pin_dev = (uint32_t*)dp;
+        std::memset(g->pin, 0, kPinBytes);
+      } else {
+        (void)hipGetLastError();
+      }
+    } else {
       (void)hipGetLastError();
       g->pin = nullptr;
-      return bail(fail(GG_E_NOMEM, "pinned readback buffer"));
+      if (hipHostMalloc(&g->pin, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        g->pin = nullptr;
+        return bail(fail(GG_E_NOMEM, "pinned readback buffer"));
+      }
     }
     if (d->flags & GG_CSR_DEVICE_PTRS) {
       g->owns_csr = false;
