@@ -553,8 +553,8 @@ int gg_graph_set_wait_limit(gg_graph* g, int32_t polls);
  * buffers and binning are unchanged (an update, a new tuning or a grown
  * workspace captures again). Results are identical either way; the launch
  * is ordered after the work already on the graph's stream and before what
- * follows. Not while profiling, nor with parts, vertex status, the ACTIVE
- * degree or traces. enable = 1 turns capture on; it is off by default,
+ * follows (a union of parts included: one launch for the whole union). Not
+ * while profiling, nor with vertex status, the ACTIVE degree or traces. enable = 1 turns capture on; it is off by default,
  * because on gfx950 a replayed schedule was measured no faster than the
  * same kernels launched one by one (the gaps between dependent kernels are
  * the device's, and the graph launch adds its own). GG_E_STATE while a run

@@ -515,13 +515,14 @@ class Graph:
         return out, _stats(st)
 
     def batch_run(self, app, sources, sample_ratio=1.0, policy="exact", out=None, seed=1, damping=0.85, iters=20,
-                  max_iters=1 << 20, dangling="uniform", alpha=0):
-        """gg_batch_run: returns (values [n, Q] on the device, Stats)."""
+                  max_iters=1 << 20, dangling="uniform", alpha=0, pr_degree="full"):
+        """gg_batch_run: returns (values [n, Q] on the device, Stats). pr_degree
+        "active": PPR's approximate iterations divide by the sample's out-degree."""
         src = np.ascontiguousarray(sources, dtype=np.int32)
         q = int(src.shape[0])
         if out is None:
             out = torch.empty((self.n, q), dtype=_value_dtype(app), device="cuda")
-        p = _app_params(app, damping, iters, max_iters, 0, dangling)
+        p = _app_params(app, damping, iters, max_iters, 0, dangling, pr_degree)
         pol = _policy(policy, alpha, 0.0, seed)
         st = RunStats()
         _check(lib().gg_batch_run(self._h, ctypes.byref(p), q, src.ctypes.data, float(sample_ratio),

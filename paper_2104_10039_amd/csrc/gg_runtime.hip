@@ -1694,7 +1694,7 @@ void end_run(gg_run* r) {
 // frontier, no readback), so the iterations can be captured once and
 // replayed.
 bool static_schedule(const gg_graph* g, const gg_app_params* p, const gg_correction_policy* pol) {
-  return g->capture && !g->prof && is_float(p->app) && g->n_parts == 0 &&
+  return g->capture && !g->prof && is_float(p->app) &&
          (pol->kind == GG_POLICY_EXACT || pol->kind == GG_POLICY_SP || pol->kind == GG_POLICY_SMS) &&
          pol->vstatus == GG_VSTATUS_NONE && p->pr_degree == GG_DEGREE_FULL && !pol->trace;
 }
@@ -2056,6 +2056,9 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
   if (!(sigma >= 0.0 && sigma <= 1.0)) return fail(GG_E_INVAL, "sample_ratio outside [0, 1]");
   if (p->app == GG_APP_SSSP && !g->wedges) return fail(GG_E_INVAL, "SSSP needs edge weights");
   if (p->app == GG_APP_PPR && !(p->damping >= 0.0 && p->damping < 1.0)) return fail(GG_E_INVAL, "bad damping");
+  if (p->pr_degree != GG_DEGREE_FULL && p->pr_degree != GG_DEGREE_ACTIVE) return fail(GG_E_INVAL, "unknown pr_degree");
+  if (p->pr_degree == GG_DEGREE_ACTIVE && p->app != GG_APP_PPR)
+    return fail(GG_E_INVAL, "the ACTIVE out-degree is defined for PPR batches");
   for (int32_t q = 0; q < nq; ++q)
     if (sources[q] < 0 || sources[q] >= g->n) return fail(GG_E_INVAL, "source out of range");
   const bool ppr = p->app == GG_APP_PPR;
@@ -2078,15 +2081,21 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
   const int app = p->app;
   // shared edge set: all edges, or the sample of ratio sigma (one mask for all queries)
   const bool approx = pol->kind != GG_POLICY_EXACT;
+  // PPR with the ACTIVE out-degree: approximate iterations divide by the
+  // sample's out-degree and spread the mass of the vertices without a
+  // sampled out-edge, as single runs do
+  const bool act_deg = ppr && approx && p->pr_degree == GG_DEGREE_ACTIVE;
   if (approx) {
     hipStream_t keep = g->stream;
     g->stream = B.cs;
     int rc = sample_and_pack(g, app, sigma, pol->seed);
+    if (rc == GG_OK && act_deg) rc = active_degree(g, 0);
     g->stream = keep;
     GG_TRY(rc);
   }
   // SMS: approximate iterations 1..alpha over the sample, accurate ones after
   const bool sms = pol->kind == GG_POLICY_SMS;
+  auto approx_iter = [&](int32_t i) { return approx && !(sms && i >= pol->alpha + 1); };
   const Bins& bins = approx ? g->act : g->full;
   if ((int64_t)bins.h.chunks * qp > B.part_cap || (int64_t)g->full.h.chunks * qp > B.part_cap)
     return fail(GG_E_STATE, "batch partial array too small");
@@ -2126,7 +2135,8 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
   float* C[2] = {(float*)B.buf[0], (float*)B.buf[1]};
   float* X = (float*)B.buf[2];
   uint32_t* U[2] = {(uint32_t*)B.buf[0], (uint32_t*)B.buf[1]};
-  GG_HIP(launch_batch_init(app, g->n, qp, B.src, g->outdeg, C[0], U[0], U[1], B.cs));
+  GG_HIP(launch_batch_init(app, g->n, qp, B.src, (act_deg && approx_iter(1)) ? g->odeg_act : g->outdeg, C[0], U[0],
+                           U[1], B.cs));
   GG_HIP(launch_fill_u32((uint32_t*)B.ctr, 4, 0u, B.cs));
   if (ppr && p->dangling == GG_DANGLING_NONE) GG_HIP(launch_fill_u32((uint32_t*)B.dang, 2 * (int64_t)qp, 0u, B.cs));
   int32_t iters = 0;
@@ -2138,8 +2148,12 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
         t.c_in = C[(i - 1) & 1];
         t.c_out = C[i & 1];
         t.x_out = i == T ? X : nullptr;
+        // contributions for iteration i + 1 divide by its out-degree
+        if (act_deg && approx_iter(i + 1)) t.outdeg = g->odeg_act;
+        const bool ad = act_deg && approx_iter(i);
         if (p->dangling == GG_DANGLING_UNIFORM)
-          GG_HIP(launch_batch_dangling(t, g->dang, g->n_dang, B.dpart, B.dang, cs));
+          GG_HIP(launch_batch_dangling(t, ad ? g->dang_act : g->dang, ad ? g->n_dang_act : g->n_dang, B.dpart, B.dang,
+                                       cs));
         GG_HIP(launch_batch_gather(app, t, cs));
       }
       return GG_OK;
@@ -2708,6 +2722,7 @@ int gg_graph_set_parts(gg_graph* g, int32_t n_parts, const int32_t* part_start_h
   return guard([&]() -> int {
     if (!g) return fail(GG_E_INVAL, "null graph");
     if (g->active_run) return fail(GG_E_STATE, "a run is active on this graph");
+    g->gen++;
     dfree(g->part_start);
     dfree(g->part_of);
     dfree(g->part_e0);

@@ -38,6 +38,10 @@ def check_batch(P, g, app, nq, policy="exact", sigma=1.0, tuning=None, n_check=6
             okw.update(sigma=sigma, seed=5)
         if "alpha" in kw:
             okw["alpha"] = kw["alpha"]
+        if kw.get("pr_degree") == "active":
+            okw["pr_degree"] = oracle.DEGREE_ACTIVE
+        if kw.get("dangling") == "none":
+            okw["dangling"] = oracle.DANGLING_NONE
         ref = oracle.run(g, app, policy, **okw)
         compare_values(app, got[:, q], ref.values, ctx="query %d" % q)
         iters.append(ref.iterations)
@@ -93,6 +97,18 @@ def test_batch_sms(P, app, alpha):
         assert st.edges_gathered == 80 * 12 * st.active_edges < 80 * 12 * m
     else:
         assert 80 * (12 - alpha) * m < st.edges_gathered < 80 * 12 * m
+
+
+@pytest.mark.parametrize("policy,alpha", [("sms", 0), ("sms", 4), ("sms", 20), ("sp", 0)])
+def test_batch_ppr_active_degree(P, policy, alpha):
+    """Batched PPR with the ACTIVE out-degree: approximate iterations divide
+    by the shared sample's out-degree and spread the mass of the vertices
+    without a sampled out-edge; every query equals its single oracle run."""
+    g = gg.rmat(13, 16, seed=19)
+    check_batch(P, g, "ppr", 80, policy=policy, sigma=0.3, alpha=alpha, iters=12, pr_degree="active",
+                tuning=dict(small_max=8, wave_max=64, hub_chunk=512))
+    check_batch(P, g, "ppr", 80, policy=policy, sigma=0.3, alpha=alpha, iters=12, pr_degree="active",
+                dangling="none")
 
 
 @pytest.mark.parametrize("app", ["ppr", "sssp"])

@@ -108,4 +108,12 @@ def test_union64_full_size(P, app):
         iters.append(ref.iterations)
     if app != "pr":
         assert st.iterations == max(iters)
+    else:
+        # the whole union's static PR schedule as one captured launch, replayed:
+        # bit for bit the kernel-by-kernel result
+        G.set_capture(True)
+        for _ in range(2):
+            outc, stc = G.exact_run(app, iters=20, max_iters=1000)
+            assert np.array_equal(device_values(outc, app), got) and stc.edges_gathered == st.edges_gathered
+        G.set_capture(False)
     G.close()
