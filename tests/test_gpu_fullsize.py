@@ -231,3 +231,55 @@ def test_full_cc_24(P, kind):
     g = gg.rmat(24, 16, seed=3, symmetrize=True) if kind == "rmat" else gg.erdos_renyi(1 << 24, 16, seed=4,
                                                                                        symmetrize=True)
     _check_app(P, g, "cc", 0)
+
+
+def test_full_bp_rmat22(P, rmat22_sym):
+    """Belief propagation as the benchmark runs it (symmetrized R-MAT 22,
+    coupling 0.1, seeded priors): exact and SMS (sigma 0.05, alpha 16 of 20
+    iterations, here 8 iterations with alpha 6 to bound the oracle's time)
+    against the oracle, 1e-6 relative L1."""
+    g = rmat22_sym
+    prior = gg.bp_prior(g.n, 2)
+    G = P.Graph.from_host(g)
+    it = 8
+    out, st = G.exact_run("bp", iters=it, coupling=0.1, prior=prior)
+    ref = _oracle(g, "bp", "exact", iters=it, coupling=0.1, prior=prior)
+    compare_values("bp", out.cpu().numpy().astype(np.float64), ref.values, ctx="exact bp")
+    assert st.edges_gathered == ref.edges
+    out, st = G.approx_run("bp", 0.05, "sms", alpha=6, seed=1, iters=it, coupling=0.1, prior=prior)
+    ref = _oracle(g, "bp", "sms", sigma=0.05, alpha=6, seed=1, iters=it, coupling=0.1, prior=prior)
+    compare_values("bp", out.cpu().numpy().astype(np.float64), ref.values, ctx="sms bp")
+    assert st.edges_gathered == ref.edges
+    G.close()
+
+
+def test_full_dynamic_sssp_rmat22(P, rmat22):
+    """A converged exact SSSP run on R-MAT 22 updated by 0.1% of its arcs
+    (half deletions, half insertions): the repaired distances equal an exact
+    run from scratch on the updated graph, whose distances satisfy the
+    shortest-path optimality conditions on the updated CSR."""
+    g, s = rmat22
+    G = P.Graph.from_host(g)
+    rng = np.random.default_rng(61)
+    k = g.m // 2000
+    dst = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.rowptr))
+    pick = rng.choice(g.m, size=k, replace=False)
+    a, b = rng.integers(0, g.n, k), rng.integers(0, g.n, k)
+    ok = a != b
+    batch = (g.col[pick], dst[pick], a[ok], b[ok], rng.integers(1, 256, int(ok.sum())))
+    R = G.begin("sssp", 1.0, "exact", source=s, max_iters=1 << 20)
+    while R.step() is not None:
+        pass
+    reset = R.update(*batch, more_iters=1 << 20)
+    while R.step() is not None:
+        pass
+    rep = R.values()
+    R.close()
+    log("dynamic rmat22: %d arcs deleted, %d inserted, %d vertices reset" % (k, int(ok.sum()), int(reset.sum())))
+    ex, _ = G.exact_run("sssp", source=s)
+    exh = _host(ex, "sssp")
+    assert np.array_equal(rep, exh)
+    rp, col, w = G.csr(weights=True)
+    upd = gg.Graph(n=g.n, rowptr=rp, col=col, weight=w)
+    certify_sssp(upd, s, exh)
+    G.close()
