@@ -200,8 +200,9 @@ def bench_bp(Gs, gs, seed, sigmas, alpha, theta, np, metrics):
     p = prof["gather_exact"]
     if p["launches"]:
         avg = p["total_ms"] / p["launches"]
-        out["gather_exact"] = {"avg_launch_ms": round(avg, 4),
-                               "achieved_gbs": round(p["alg_bytes"] / p["launches"] / (avg * 1e-3) / 1e9, 1)}
+        ach = p["alg_bytes"] / p["launches"] / (avg * 1e-3) / 1e9
+        out["gather_exact"] = {"kernel": "k_gather_seg<BP>", "avg_launch_ms": round(avg, 4),
+                               "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)}
 
     def timed(sg, pol, a, th, seed=1):
         Gs.approx_run("bp", sg, pol, alpha=a, theta=th, seed=seed, **kw)
@@ -227,8 +228,9 @@ def bench_bp(Gs, gs, seed, sigmas, alpha, theta, np, metrics):
     Gs.set_profiling(False)
     if sp["launches"]:
         avg = sp["total_ms"] / sp["launches"]
-        out["superstep"] = {"avg_launch_ms": round(avg, 4),
-                            "achieved_gbs": round(sp["alg_bytes"] / sp["launches"] / (avg * 1e-3) / 1e9, 1)}
+        ach = sp["alg_bytes"] / sp["launches"] / (avg * 1e-3) / 1e9
+        out["superstep"] = {"kernel": "k_super_flat<BP>", "avg_launch_ms": round(avg, 4),
+                            "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)}
     for pol, (sg, a, th) in BP_1PCT.items():
         o, st = timed(sg, pol, a, th)
         errs = errors(sg, pol, a, th, o.cpu().numpy())
