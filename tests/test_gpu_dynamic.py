@@ -185,3 +185,32 @@ def test_update_to_and_from_an_empty_graph(P):
     rp, col, _ = G.csr()
     assert rp.tolist() == [0, 0, 0, 0, 1, 2, 2] and col.tolist() == [4, 5]
     G.close()
+
+
+def test_update_refusals_for_parts_and_policies(P):
+    """Updates of a graph with parts, and of LEARNED, vertex-status and
+    ACTIVE-degree runs, are refused (GG_E_UNSUPPORTED) and change nothing."""
+    gs = [gg.rmat(6, 4, seed=70 + k) for k in range(3)]
+    U, ps = gg.union(gs)
+    G = P.Graph.from_host(U)
+    G.set_parts(ps)
+    with pytest.raises(P.GGError) as ei:
+        G.update([], [], [0], [1])
+    assert ei.value.code == -5
+    G.close()
+    g = gg.rmat(9, 8, seed=71)
+    G = load(P, g)
+    rp0, col0, _ = G.csr()
+    net = P.Mlp(seed=1)
+    for kw in (dict(policy="learned", mlp=net, tau=0.0), dict(policy="gg", vstatus="rel", eps=1e-3)):
+        pol = kw.pop("policy")
+        R = G.begin("pr", 0.5, pol, iters=6, **kw)
+        R.step()
+        with pytest.raises(P.GGError) as ei:
+            R.update([], [], [0], [1])
+        assert ei.value.code == -5
+        R.close()
+    rp1, col1, _ = G.csr()
+    assert np.array_equal(rp0, rp1) and np.array_equal(col0, col1)
+    net.close()
+    G.close()
