@@ -184,7 +184,7 @@ SIGNATURES = {
     "gg_trace_export": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP]),
 }
 
-PROFILE_KIND = {"gather_exact": 0, "gather_approx": 1, "superstep": 2, "push": 3}
+PROFILE_KIND = {"gather_exact": 0, "gather_approx": 1, "superstep": 2, "push": 3, "partial": 4}
 
 _lib = None
 

@@ -116,6 +116,9 @@ struct Sweep {
   // SSSP/CC influence in push order: a superstep row's running minimum
   // starts at the row's own value x_in[u] instead of the identity
   int32_t push_infl;
+  // gathers (nullable): rows u with skip[u] != 0 are neither gathered nor
+  // applied; another launch of the same iteration computes them
+  const uint8_t* skip;
 };
 
 // Segmented gather constants.
@@ -332,8 +335,8 @@ hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
                          uint8_t* label_u8, float* label_f, int32_t nf, unsigned long long* audit,
                          unsigned long long* trace_pos, hipStream_t st);
 hipError_t launch_add_f32(const float* src, float* dst, hipStream_t st);
-hipError_t launch_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,
-                          const int32_t* act_cnt, int32_t* changed, unsigned long long* act_sum, hipStream_t st);
+hipError_t launch_sel_active(const int32_t* list, int32_t count, const int32_t* act_cnt, unsigned long long* act_sum,
+                             hipStream_t st);
 hipError_t launch_clear_rows(const int32_t* list, int32_t n_short, int32_t count, const int32_t* rowptr,
                              uint32_t* bits, hipStream_t st);
 

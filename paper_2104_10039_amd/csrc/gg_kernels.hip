@@ -254,6 +254,7 @@ __device__ __forceinline__ void gather_team_rows(const Sweep& s, const int32_t* 
   const int stride = nblk * TPB;
   for (int t = blk * TPB + (int)threadIdx.x / TEAM; t < count; t += stride) {
     const int u = list[t];
+    if (s.skip && s.skip[u]) continue;  // the whole team skips the row
     const int b = s.rowptr[u];
     const int len = row_len(s, u, b);
     const uint32_t* ed = s.edges + b;
@@ -280,6 +281,7 @@ __device__ __forceinline__ void gather_hub_chunk(const Sweep& s, int ch, bool al
   using T = typename R::T;
   const int h = find_hub(s.hub_start, s.n_hub, ch);
   const int u = s.list[s.n_small + s.n_wave + h];
+  if (s.skip && s.skip[u]) return;  // uniform over the block
   const int j = ch - s.hub_start[h];
   const int nch = s.hub_start[h + 1] - s.hub_start[h];
   const int b = s.rowptr[u];
@@ -343,13 +345,14 @@ __global__ __launch_bounds__(kBlock) void k_hub_combine(Sweep s) {
   const int h = blockIdx.x * kBlock + threadIdx.x;
   if (h < s.n_hub) {
     const int c0 = s.hub_start[h], nch = s.hub_start[h + 1] - c0;
-    if (nch > 1) {
+    const int u = s.list[s.n_small + s.n_wave + h];
+    if (nch > 1 && !(s.skip && s.skip[u])) {
       typename R::T acc = R::id();
       for (int j = 0; j < nch; ++j) {
         if constexpr (kSumApp<APP>) acc = R::op(acc, s.part_f[c0 + j]);
         else acc = R::op(acc, s.part_u[c0 + j]);
       }
-      apply<APP>(s, s.list[s.n_small + s.n_wave + h], acc, nchanged);
+      apply<APP>(s, u, acc, nchanged);
     }
   }
   flush_changed<APP>(s, nchanged, ilds);
@@ -1766,7 +1769,9 @@ __global__ __launch_bounds__(kBlock) void k_gather_seg(Sweep s, int gh, int gw, 
     int sg, h;
     seg_map(bid, s.seg_s, s.n_hub, sg, h);
     const int i = s.n_wave + h;
-    const int lo = s.seg_off[(int64_t)sg * nl + i], hi = s.seg_off[(int64_t)(sg + 1) * nl + i];
+    const bool skipped = s.skip && s.skip[s.list[s.n_small + i]];  // uniform over the block
+    const int lo = s.seg_off[(int64_t)sg * nl + i];
+    const int hi = skipped ? lo : s.seg_off[(int64_t)(sg + 1) * nl + i];
     T acc = R::id();
     int k = lo + (int)threadIdx.x;
     for (; k + 3 * kBlock < hi; k += 4 * kBlock) {
@@ -1789,6 +1794,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_seg(Sweep s, int gh, int gw, 
       const int i = i0 + threadIdx.x;
       lo = s.seg_off[(int64_t)sg * nl + i];
       len = s.seg_off[(int64_t)(sg + 1) * nl + i] - lo;
+      if (s.skip && s.skip[s.list[s.n_small + i]]) len = 0;
     }
     const T acc = flat_batch<APP>(s, P, lo, len, s_val, s_lo, s_scan, ilds);
     if ((int)threadIdx.x < P) seg_store<APP>(s, (int64_t)sg * nl + i0 + threadIdx.x, acc);
@@ -1806,7 +1812,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_seg(Sweep s, int gh, int gw, 
       lo = s.rowptr[u];
       len = row_len(s, u, lo);
       word = apply_word<APP>(s, u);
-      mine = len <= s.small_max;
+      mine = len <= s.small_max && !(s.skip && s.skip[u]);
       if (!mine) len = 0;
     }
     const T acc = flat_batch<APP>(s, P, lo, len, s_val, s_lo, s_scan, ilds);
@@ -1823,13 +1829,14 @@ __global__ __launch_bounds__(kBlock) void k_seg_combine(Sweep s) {
   int nchanged = 0;
   const int nl = s.n_wave + s.n_hub;
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < nl) {
+  const int u = i < nl ? s.list[s.n_small + i] : 0;
+  if (i < nl && !(s.skip && s.skip[u])) {
     typename R::T acc = R::id();
     for (int sg = 0; sg < s.seg_s; ++sg) {
       if constexpr (kSumApp<APP>) acc = R::op(acc, s.seg_part_f[(int64_t)sg * nl + i]);
       else acc = R::op(acc, s.seg_part_u[(int64_t)sg * nl + i]);
     }
-    apply<APP>(s, s.list[s.n_small + i], acc, nchanged);
+    apply<APP>(s, u, acc, nchanged);
   }
   flush_changed<APP>(s, nchanged, ilds);
 }

@@ -695,35 +695,21 @@ __global__ void k_clear_rows(const int32_t* list, int32_t n_short, int32_t count
   }
 }
 
-// Before the selected rows of a partial superstep are recomputed over all
-// in-edges: withdraw the change the approximate gather counted for them
-// (SSSP/CC, changed may be null) and add up their active edges.
-__global__ void k_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,
-                          const int32_t* act_cnt, int32_t* changed, unsigned long long* act_sum) {
-  int withdrawn = 0;
+// Active edges of the selected rows of a partial superstep (the
+// approximate gather skips those rows; the superstep reads all their
+// in-edges), added to act_sum.
+__global__ void k_sel_active(const int32_t* list, int32_t count, const int32_t* act_cnt,
+                             unsigned long long* act_sum) {
   unsigned long long a = 0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
-    const int u = list[t];
-    if (changed) withdrawn += x_next[u] != x_in[u];
-    a += (unsigned long long)act_cnt[u];
-  }
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+    a += (unsigned long long)act_cnt[list[t]];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    withdrawn += __shfl_xor(withdrawn, o, 64);
-    a += __shfl_xor(a, o, 64);
-  }
-  __shared__ int wsw[4];
+  for (int o = 1; o < 64; o <<= 1) a += __shfl_xor(a, o, 64);
   __shared__ unsigned long long wsa[4];
-  const int wv = threadIdx.x >> 6;
-  if (__lane_id() == 0) {
-    wsw[wv] = withdrawn;
-    wsa[wv] = a;
-  }
+  if (__lane_id() == 0) wsa[threadIdx.x >> 6] = a;
   __syncthreads();
   if (threadIdx.x == 0) {
-    withdrawn = wsw[0] + wsw[1] + wsw[2] + wsw[3];
     a = wsa[0] + wsa[1] + wsa[2] + wsa[3];
-    if (changed && withdrawn) atomicSub(changed, withdrawn);
     if (a) atomicAdd(act_sum, a);
   }
 }
@@ -758,11 +744,10 @@ hipError_t launch_labels(int app, int32_t n, const uint32_t* acc, const uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_sel_fix(const int32_t* list, int32_t count, const uint32_t* x_in, const uint32_t* x_next,
-                          const int32_t* act_cnt, int32_t* changed, unsigned long long* act_sum, hipStream_t st) {
+hipError_t launch_sel_active(const int32_t* list, int32_t count, const int32_t* act_cnt, unsigned long long* act_sum,
+                             hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sel_fix, dim3(grid1d(count, 4096)), dim3(256), 0, st, list, count, x_in, x_next, act_cnt,
-                     changed, act_sum);
+  hipLaunchKernelGGL(k_sel_active, dim3(grid1d(count, 4096)), dim3(256), 0, st, list, count, act_cnt, act_sum);
   return hipGetLastError();
 }
 

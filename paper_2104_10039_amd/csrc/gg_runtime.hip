@@ -1188,9 +1188,9 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
   } else if (kind == GG_STEP_PARTIAL) {
     // Partial superstep: the selected rows S gather over all in-edges and
     // re-select their flags; the other rows take an approximate iteration and
-    // keep theirs. The approximate gather runs over every row (the fast
-    // path); the superstep over S then overwrites S's results, after S's
-    // approximate change counts are withdrawn.
+    // keep theirs. The approximate gather skips the rows of S (selection
+    // bytes as its skip mask), so its work scales with the rows outside S;
+    // the superstep then computes S from its list.
     pkind = 4;
     GG_TRY(rebin(g, g->selb, nullptr, g->sel, 1));
     const int32_t ns = g->selb.h.small + g->selb.h.wave + g->selb.h.hub;
@@ -1201,6 +1201,7 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     set_bins(sa, g->act);
     sa.edges = g->act_edges;
     sa.cnt = g->act_cnt;
+    sa.skip = g->sel;
     GG_TRY(check_part_capacity(g, g->act));
     if (g->tune.seg_enable) {
       GG_TRY(check_seg_capacity(g, g->act));
@@ -1209,8 +1210,8 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     } else {
       GG_HIP(launch_gather(app, g->tune.small_team, sa, g->stream, pe0, nullptr));
     }
-    GG_HIP(launch_sel_fix(g->selb.list, ns, pr ? nullptr : s.x_in, pr ? nullptr : s.x_next, g->act_cnt,
-                          (pr || frontier) ? nullptr : g->changed, g->audit + 2, g->stream));
+    // active edges of S, for the edge count
+    GG_HIP(launch_sel_active(g->selb.list, ns, g->act_cnt, g->audit + 2, g->stream));
     const int64_t act_all = g->act.h.edges;
     Sweep sc = s;
     set_bins(sc, g->selb);
@@ -1231,9 +1232,9 @@ int run_step(gg_run* r, gg_step_info* info, bool sync_changed) {
     GG_TRY(rebin_act(g, app, true));  // synchronizes the stream, reads the hub error word
     r->supersteps++;
     r->partials++;
-    // algorithmic edges: S over all in-edges, the other rows over active ones
+    // S over all in-edges, the other rows over their active ones
     edges = act_all - (int64_t)act_s + g->selb.h.edges;
-    processed = act_all + g->selb.h.edges;
+    processed = edges;
   } else if (superstep) {
     pkind = 2;
     if (traced || audited) {

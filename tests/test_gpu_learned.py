@@ -227,12 +227,14 @@ def test_trace_capacity_drops(P):
 # LEARNED runs
 # --------------------------------------------------------------------------
 
-def learned_step_compare(P, g, app, params, tau, rho=1.0, fallback_k=0, audit=False, **kw):
+def learned_step_compare(P, g, app, params, tau, rho=1.0, fallback_k=0, audit=False, tuning=None, **kw):
     """Both sides step by step; selections, step kinds, edges, values and
     (after every correction) the flags must agree."""
     net = P.Mlp()
     net.set_weights(params.astype(np.float32))
     G = P.Graph.from_host(g)
+    if tuning:
+        G.set_tuning(**tuning)
     sr = kw.pop("sample_ratio")
     R = G.begin(app, sr, "learned", mlp=net, tau=tau, rho=rho, fallback_k=fallback_k, audit=audit, **kw)
     O = oracle.Run(g, app, "learned", sigma=sr, mlp=params, tau=tau, rho=rho, fallback_k=fallback_k,
@@ -248,6 +250,9 @@ def learned_step_compare(P, g, app, params, tau, rho=1.0, fallback_k=0, audit=Fa
         assert a["kind"] == P.STEP_KIND[b.kind], (a, b)
         assert a["selected"] == b.selected, (a, b)
         assert a["edges"] == b.edges, (a, b)
+        if a["kind"] == "partial":
+            # the selected rows are read once, by the superstep
+            assert a["edges_processed"] == a["edges"], a
         if app in ("sssp", "cc"):
             assert a["changed"] == b.changed, (a, b)
         if a["selected"] >= 0:
@@ -281,6 +286,29 @@ def test_learned_selector_indegree(P, app):
         assert "partial" in kinds
         assert ("full" in kinds) == (fk > 0)
         log(app, "fallback", fk, "kinds", "".join(k[0] for k in kinds), "partials", st.partial_supersteps)
+
+
+PARTIAL_TUNINGS = [
+    # unsegmented gathers: team rows, wavefront rows, multi-chunk hub rows
+    dict(small_max=4, small_team=4, wave_max=32, hub_chunk=256, seg_enable=0, seg_vertices=0, frontier_enable=1,
+         frontier_div=16),
+    # segmented gathers with many segments: hub pieces, wave-row batches
+    dict(small_max=4, small_team=4, wave_max=32, hub_chunk=256, seg_enable=1, seg_vertices=64, frontier_enable=1,
+         frontier_div=1),
+]
+
+
+@pytest.mark.parametrize("ti", range(len(PARTIAL_TUNINGS)))
+@pytest.mark.parametrize("app", ["pr", "sssp", "cc"])
+def test_learned_partial_tunings(P, app, ti):
+    """Partial supersteps over every bin of both gather paths: the
+    approximate pass skips the selected rows, the superstep computes them."""
+    g = graph_for(app, 12, seed=6)
+    s = int(gg.pick_sources(g, 1, 7)[0])
+    log("case: partial supersteps", app, PARTIAL_TUNINGS[ti])
+    kinds, st = learned_step_compare(P, g, app, mlp_selector_params(1), tau=3.0, tuning=PARTIAL_TUNINGS[ti],
+                                     sample_ratio=0.3, alpha=2, theta=0.05, seed=8, source=s, iters=15)
+    assert "partial" in kinds and st.partial_supersteps > 0
 
 
 @pytest.mark.parametrize("app", ["sssp", "cc"])
