@@ -92,6 +92,21 @@ def test_exact_rmat14(P, app, ti):
     check_run(P, g, app, "exact", tuning=TUNINGS[ti], ctx="rmat14", source=s)
 
 
+@pytest.mark.parametrize("seg_vertices", [1500, 700, 520, 400])
+def test_segment_geometries(P, seg_vertices):
+    """Source-segment counts S of 16, 24, 32 and 48 on R-MAT 14: exact runs
+    and GG steps, whose active rows get fresh segment offsets after every
+    superstep."""
+    tuning = dict(TUNINGS[0], seg_vertices=seg_vertices)
+    for app in ("pr", "sssp", "cc"):
+        g = graph_for(app, 14, seed=1)
+        s = int(gg.pick_sources(g, 1, 1)[0])
+        log("case: segments", seg_vertices, app)
+        check_run(P, g, app, "exact", tuning=tuning, ctx="rmat14 seg %d" % seg_vertices, source=s)
+        step_compare(P, g, app, "gg", tuning=tuning, sample_ratio=0.5, alpha=2, theta=0.05, seed=2, source=s,
+                     iters=9)
+
+
 # ---------------------------------------------------------------------------
 # Approximate runs: whole-run outputs
 # ---------------------------------------------------------------------------
