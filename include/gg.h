@@ -443,7 +443,10 @@ void gg_run_end(gg_run* run);
  * sorted by source (the canonical in-CSR; GG_E_UNSUPPORTED otherwise) and
  * no parts. After an update the graph owns its CSR arrays (a borrowed device
  * CSR is no longer read), and the result is as if the new CSR had been
- * loaded with the graph's tuning.
+ * loaded with the graph's tuning. The arrays an update replaces (the CSR,
+ * the packed weights, the flag and active-edge arrays and the frontier's
+ * out-CSR: about one more copy of each) are kept as the next update's
+ * destinations and released with the graph.
  *   del_src/del_dst  int32[n_delete]; ins_src/ins_dst/ins_weight int32[n_insert]
  *   flags            GG_UPDATE_DEVICE_PTRS: the arrays are device pointers
  *                    (default: host), read during the call only
@@ -495,6 +498,10 @@ int gg_run_update(gg_run* run, const gg_update_batch* batch, int32_t more_iters,
  * col_host int32[m] (nullable), weight_host int32[m] (nullable; GG_E_INVAL
  * when requested from a graph without weights). */
 int gg_graph_get_csr(gg_graph* g, int32_t* rowptr_host, int32_t* col_host, int32_t* weight_host);
+
+/* Arc count m of the graph's current in-CSR (it changes with updates);
+ * -1 for a null graph. Host-side, no device work. */
+int64_t gg_graph_num_arcs(const gg_graph* g);
 
 /*
  * Tuning knobs of the degree-binned sweep (set directly or by gg_graph_autotune):

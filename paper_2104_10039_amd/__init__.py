@@ -151,6 +151,7 @@ SIGNATURES = {
     "gg_graph_set_capture": (ctypes.c_int, [_VP, ctypes.c_int]),
     "gg_run_update": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP]),
     "gg_graph_get_csr": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "gg_graph_num_arcs": (ctypes.c_int64, [_VP]),
     "gg_graph_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "gg_graph_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "gg_batch_run": (ctypes.c_int, [_VP, ctypes.POINTER(AppParams), ctypes.c_int32, _VP, ctypes.c_double,
@@ -559,9 +560,7 @@ class Graph:
         self._keep = None  # the graph owns its CSR now
 
     def _csr_m(self) -> int:
-        rp = np.empty(self.n + 1, dtype=np.int32)
-        _check(lib().gg_graph_get_csr(self._h, rp.ctypes.data, None, None))
-        return int(rp[-1])
+        return int(lib().gg_graph_num_arcs(self._h))
 
     def csr(self, weights=False):
         """Host copies (rowptr, col, weight or None) of the graph's in-CSR."""

@@ -222,9 +222,9 @@ struct FrontCounters {
 hipError_t launch_scan(const int32_t* in, int32_t* out, int32_t n, int32_t* total, int32_t* scratch,
                        hipStream_t st);
 // Out-CSR structure of an in-CSR: orow[n+1] (from outdeg), oedge[m] = in-edge
-// id, odst[m] = destination row. cursor: n int32 of scratch.
+// id, odst[m] = destination row, osrc[m] = source. cursor: n int32 of scratch.
 hipError_t launch_build_out(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, const int32_t* orow,
-                            int32_t* cursor, int32_t* oedge, int32_t* odst, hipStream_t st);
+                            int32_t* cursor, int32_t* oedge, int32_t* odst, int32_t* osrc, hipStream_t st);
 // List of vertices whose chg flag is set (vertex order) with out-degree sum.
 // psum: int64 scratch of max(ceil(n / kBlock), 1024) entries.
 hipError_t launch_compact_changed(const uint8_t* chg, const int32_t* outdeg, int32_t n, int32_t* list,
@@ -356,20 +356,22 @@ hipError_t launch_sort_pairs(const uint64_t* kin, uint64_t* kout, const int32_t*
 // Row of every edge: dst[e] = u for e in [rowptr[u], rowptr[u+1]).
 hipError_t launch_row_ids(const int32_t* rowptr, int32_t n, int32_t* dst, hipStream_t st);
 // For every distinct sorted deletion key: keep[e] = 0 for the matching edges
-// (rows sorted by source), od_new[s] decreased by their count. With x
-// non-null, destinations of deleted edges that support their value are
-// appended to list (count) once each (taint[v] set).
+// (rows sorted by source), od_new[s] decreased by their count, rowflag[d] = 1
+// for a row that lost edges (rowflag: n bytes, zeroed). With x non-null,
+// destinations of deleted edges that support their value are appended to
+// list (count) once each (taint[v] set).
 hipError_t launch_mark_deleted(const int32_t* rowptr, const int32_t* col, const int32_t* weight,
-                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, int app,
-                               const uint32_t* x, int32_t source, int32_t* taint, int32_t* list, int32_t* count,
-                               hipStream_t st);
+                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, uint8_t* rowflag,
+                               int app, const uint32_t* x, int32_t source, int32_t* taint, int32_t* list,
+                               int32_t* count, hipStream_t st);
 // od_new[s] and ins_cnt[s] (nullable) increased for every inserted arc s -> d.
 hipError_t launch_ins_outdeg(const uint64_t* ikeys, int64_t ni, int32_t* od_new, int32_t* ins_cnt, hipStream_t st);
 // ins_rp[u] (u in [0, n]) = first sorted insertion with destination >= u.
 hipError_t launch_ins_rows(const uint64_t* ikeys, int64_t ni, int32_t n, int32_t* ins_rp, hipStream_t st);
-// New row lengths: survivors (keep_ex: exclusive scan of keep, m+1 entries) plus insertions.
+// New row lengths: survivors (keep_ex: exclusive scan of keep, m+1 entries)
+// plus insertions; rowflag[u] gains 2 for a row with insertions.
 hipError_t launch_new_len(const int32_t* rowptr, const int32_t* keep_ex, const int32_t* ins_rp, int32_t n,
-                          int32_t* len, hipStream_t st);
+                          int32_t* len, uint8_t* rowflag, hipStream_t st);
 // Merge of survivors and insertions into the new CSR (rows sorted by source,
 // old edges first on equal sources); old_of_new[e'] = old edge or -1,
 // new_of_old[e] = new position or -1. With noedge non-null, scatter_ins also
@@ -383,14 +385,22 @@ hipError_t launch_scatter_ins(const int32_t* rowptr, const int32_t* col, const i
                               const uint64_t* ikeys, const int32_t* iidx, int64_t ni, const int32_t* ins_rp,
                               const int32_t* ins_w, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
                               int32_t* old_of_new, const int32_t* orow_new, const int32_t* ins_cnt, int32_t* icur,
-                              int32_t* noedge, int32_t* nodst, hipStream_t st);
-// Surviving out-CSR entries (kout[k] = 1), then their compaction into the new
-// out-CSR (kout_ex: exclusive scan of kout, m+1 entries).
-hipError_t launch_out_keep(const int32_t* oedge, int64_t m, const int32_t* new_of_old, int32_t* kout, hipStream_t st);
-hipError_t launch_out_compact(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* col_old,
-                              const int32_t* orow_old, const int32_t* kout, const int32_t* kout_ex,
-                              const int32_t* new_of_old, const int32_t* orow_new, int32_t* noedge, int32_t* nodst,
-                              hipStream_t st);
+                              int32_t* noedge, int32_t* nodst, int32_t* nosrc, hipStream_t st);
+// Out-CSR carried over an update. move[u]: how row u's old edges move (the
+// row shift when rowflag[u] is 0, else a marker to look edges up in
+// new_of_old). Then per out-entry its new in-edge id ne[k] (-1: deleted) and
+// kout[k] = 1 for a survivor; the offset of every source's survivors
+// (obase[v] = orow_new[v] - kout_ex[orow_old[v]]); and their compaction into
+// the new out-CSR (kout_ex: exclusive scan of kout, m+1 entries).
+hipError_t launch_row_move(const int32_t* rp_old, const int32_t* rp_new, const uint8_t* rowflag, int32_t n,
+                           int32_t* move, hipStream_t st);
+hipError_t launch_out_keep(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* move,
+                           const int32_t* new_of_old, int32_t* ne, int32_t* kout, hipStream_t st);
+hipError_t launch_out_base(const int32_t* orow_old, const int32_t* orow_new, const int32_t* kout_ex, int32_t n,
+                           int32_t* obase, hipStream_t st);
+hipError_t launch_out_compact(const int32_t* ne, const int32_t* odst, const int32_t* osrc, int64_t m,
+                              const int32_t* kout, const int32_t* kout_ex, const int32_t* obase, int32_t* noedge,
+                              int32_t* nodst, int32_t* nosrc, hipStream_t st);
 // New flag bitmap: continued edges keep their flag, inserted ones are set.
 hipError_t launch_remap_bits(const uint32_t* old_bits, const int32_t* old_of_new, int64_t m, uint32_t* new_bits,
                              hipStream_t st);

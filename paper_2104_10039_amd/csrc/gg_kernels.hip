@@ -1942,8 +1942,11 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int32_t n, int32_t* tota
 }
 
 // ---- out-CSR structure -------------------------------------------------------
+// Entry pos of source v: in-edge id oedge, destination odst and the source
+// itself in osrc (what an update needs to carry an entry over without
+// looking up its in-edge).
 __global__ void k_out_scatter(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, const int32_t* orow,
-                              int32_t* cursor, int32_t* oedge, int32_t* odst) {
+                              int32_t* cursor, int32_t* oedge, int32_t* odst, int32_t* osrc) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
     int lo = 0, hi = n - 1;  // the row holding edge e: last u with rowptr[u] <= e
     while (lo < hi) {
@@ -1955,15 +1958,16 @@ __global__ void k_out_scatter(const int32_t* rowptr, const int32_t* col, int32_t
     const int pos = orow[v] + atomicAdd(&cursor[v], 1);
     oedge[pos] = (int32_t)e;
     odst[pos] = lo;
+    osrc[pos] = v;
   }
 }
 
 hipError_t launch_build_out(const int32_t* rowptr, const int32_t* col, int32_t n, int64_t m, const int32_t* orow,
-                            int32_t* cursor, int32_t* oedge, int32_t* odst, hipStream_t st) {
+                            int32_t* cursor, int32_t* oedge, int32_t* odst, int32_t* osrc, hipStream_t st) {
   hipError_t e = launch_fill_u32((uint32_t*)cursor, n, 0u, st);
   if (e != hipSuccess || m == 0 || n == 0) return e;
   hipLaunchKernelGGL(k_out_scatter, dim3(grid_for(m, kBlock * 4, 1 << 16)), dim3(kBlock), 0, st, rowptr, col, n, m,
-                     orow, cursor, oedge, odst);
+                     orow, cursor, oedge, odst, osrc);
   return hipGetLastError();
 }
 

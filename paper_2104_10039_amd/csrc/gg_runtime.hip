@@ -151,6 +151,14 @@ struct gg_graph {
   int32_t* orow = nullptr;
   int32_t* oedge = nullptr;
   int32_t* odst = nullptr;
+  int32_t* osrc = nullptr;  // source of every out-CSR entry (for updates)
+  // buffers of the arrays an update replaced, reused as the next update's
+  // destinations when large enough; bytes is what the replaced graph needed
+  // (a lower bound of the allocation)
+  struct Spare {
+    void* p = nullptr;
+    size_t bytes = 0;
+  } spare[11];
   uint8_t* chg = nullptr;
   uint32_t* stamp = nullptr;
   uint32_t epoch = 0;
@@ -554,8 +562,8 @@ int rebin_act(gg_graph* g, int app, bool after_superstep = false) {
 // Out-CSR structure and frontier lists (first SSSP/CC run with the frontier on).
 int ensure_out(gg_graph* g) {
   if (g->out_built) {
-    if (!g->orow || !g->oedge || !g->odst || !g->chg || !g->stamp || !g->flist[0] || !g->flist[1] || !g->touched ||
-        !g->fc || !g->fdeg || !g->fscan || !g->psum)
+    if (!g->orow || !g->oedge || !g->odst || !g->osrc || !g->chg || !g->stamp || !g->flist[0] || !g->flist[1] ||
+        !g->touched || !g->fc || !g->fdeg || !g->fscan || !g->psum)
       return fail(GG_E_STATE, "frontier arrays missing");
     return GG_OK;
   }
@@ -563,6 +571,7 @@ int ensure_out(gg_graph* g) {
   GG_TRY(dalloc(&g->orow, n + 1));
   GG_TRY(dalloc(&g->oedge, m));
   GG_TRY(dalloc(&g->odst, m));
+  GG_TRY(dalloc(&g->osrc, m));
   GG_TRY(dalloc(&g->chg, (n + 3) / 4 * 4));  // whole words, so that 32-bit fills clear it
   GG_TRY(dalloc(&g->stamp, n));
   GG_TRY(dalloc(&g->flist[0], n));
@@ -576,7 +585,8 @@ int ensure_out(gg_graph* g) {
   GG_HIP(launch_fill_u32(g->stamp, g->n, 0u, g->stream));
   GG_HIP(launch_scan(g->outdeg, g->orow, g->n, g->orow + g->n, (int32_t*)g->blk_scratch, g->stream));
   // cursor scratch: the touched list is free at this point
-  GG_HIP(launch_build_out(g->rowptr, g->col, g->n, g->m, g->orow, g->touched, g->oedge, g->odst, g->stream));
+  GG_HIP(launch_build_out(g->rowptr, g->col, g->n, g->m, g->orow, g->touched, g->oedge, g->odst, g->osrc,
+                          g->stream));
   GG_HIP(hipStreamSynchronize(g->stream));
   g->out_built = true;
   return GG_OK;
@@ -625,6 +635,11 @@ int ensure_workspace(gg_graph* g) {
 void free_graph(gg_graph* g) {
   if (!g) return;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
+  for (auto& s : g->spare) {
+    dev_free(s.p);
+    s.p = nullptr;
+    s.bytes = 0;
+  }
   if (g->owns_csr) {
     dfree(g->rowptr);
     dfree(g->col);
@@ -665,6 +680,7 @@ void free_graph(gg_graph* g) {
   dfree(g->orow);
   dfree(g->oedge);
   dfree(g->odst);
+  dfree(g->osrc);
   dfree(g->chg);
   dfree(g->stamp);
   dfree(g->flist[0]);
@@ -2220,10 +2236,27 @@ int batch_run(gg_graph* g, const gg_app_params* p, int32_t nq, const int32_t* so
 // ---- dynamic graphs ---------------------------------------------------------
 
 // Device buffers that live for one call.
+// Temporaries of one update, carved from one block reserved up front (one
+// allocator call instead of one per array); requests beyond the reserve get
+// blocks of their own. All are freed when the object goes.
 struct TempBufs {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
   std::vector<void*> ptrs;
+  int reserve(size_t bytes) {
+    GG_TRY(dalloc(&base, bytes));
+    ptrs.push_back((void*)base);
+    cap = bytes;
+    return GG_OK;
+  }
   template <typename T>
   int get(T** p, size_t count) {
+    const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    if (base && bytes <= cap - used) {
+      *p = (T*)(base + used);
+      used += bytes;
+      return GG_OK;
+    }
     *p = nullptr;
     GG_TRY(dalloc(p, count));
     ptrs.push_back((void*)*p);
@@ -2233,6 +2266,33 @@ struct TempBufs {
     for (void* q : ptrs) dev_free(q);
   }
 };
+
+// Update destinations: the spare of the slot when it holds at least count
+// elements, else a new block.
+enum SpareSlot { kSpRowptr, kSpCol, kSpWeight, kSpWedges, kSpBits0, kSpBits1, kSpAct, kSpOrow, kSpOedge, kSpOdst,
+                 kSpOsrc };
+
+template <typename T>
+int take_spare(gg_graph* g, int slot, T** p, size_t count) {
+  auto& s = g->spare[slot];
+  if (*p) dev_free((void*)*p);
+  *p = nullptr;
+  if (s.p && s.bytes >= (count ? count : 1) * sizeof(T)) {
+    *p = (T*)s.p;
+    s.p = nullptr;
+    s.bytes = 0;
+    return GG_OK;
+  }
+  return dalloc(p, count);
+}
+
+// A replaced array becomes the slot's spare (bytes: what it held).
+void retire(gg_graph* g, int slot, void* p, size_t bytes) {
+  auto& s = g->spare[slot];
+  dev_free(s.p);
+  s.p = p;
+  s.bytes = p ? bytes : 0;
+}
 
 // Device copy of a batch array (or the caller's device pointer).
 int batch_array(gg_graph* g, TempBufs& T, const int32_t* a, int64_t k, bool device, const int32_t** out) {
@@ -2288,7 +2348,63 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   const int32_t n = g->n;
   const int64_t m0 = g->m, nd = b->n_delete, ni = b->n_insert;
   const bool dev = (b->flags & GG_UPDATE_DEVICE_PTRS) != 0;
+  size_t sb1 = 0, sb2 = 0;  // radix sort scratch of both key lists
+  GG_HIP(sort_keys_bytes(nd, &sb1));
+  GG_HIP(sort_pairs_bytes(ni, &sb2));
   TempBufs T;
+  {
+    // one reserve covering every temporary below, in 4-byte words plus each
+    // request's alignment (m0 + ni bounds the new arc count)
+    const bool out0 = g->out_built;
+    const bool taint0 = r && (app == GG_APP_SSSP || app == GG_APP_CC) && r->pol.kind == GG_POLICY_EXACT &&
+                        r->converged && nd > 0;
+    const size_t N = (size_t)n, M = (size_t)m0, I = (size_t)ni, D = (size_t)nd;
+    size_t w = 0;
+    auto add = [&](size_t words) { w += words + 64; };
+    if (!dev) {
+      add(D);
+      add(D);
+      add(I);
+      add(I);
+      add(I);
+    }
+    add(1);
+    add(2 * D);
+    add(2 * D);
+    add(2 * I);
+    add(2 * I);
+    add(I);
+    add(I);
+    add((std::max(sb1, sb2) + 3) / 4);
+    if (taint0) {
+      add(N);
+      add(N);
+      add(1);
+    }
+    add((N + 3) / 4);
+    add(M);
+    add(M + 1);
+    add(N);
+    add(std::max(M, N) / 1024 + 2);
+    if (out0) {
+      add(N);
+      add(N);
+    }
+    add(N + 1);
+    add(N + 1);
+    add(M + I);
+    add(M);
+    add(M);
+    if (out0) {
+      add(M);
+      add(M + 1);
+      add(N);
+      add(N);
+      add(M);
+    }
+    if (r && is_pr(app)) add(N);
+    GG_TRY(T.reserve(w * 4));
+  }
   const int32_t *ds, *dd, *is, *id, *iw;
   GG_TRY(batch_array(g, T, b->del_src, nd, dev, &ds));
   GG_TRY(batch_array(g, T, b->del_dst, nd, dev, &dd));
@@ -2316,9 +2432,6 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   GG_TRY(T.get(&ixs, (size_t)ni));
   GG_HIP(launch_arc_keys(ds, dd, nd, dk, nullptr, g->stream));
   GG_HIP(launch_arc_keys(is, id, ni, ik, ix, g->stream));
-  size_t sb1 = 0, sb2 = 0;
-  GG_HIP(sort_keys_bytes(nd, &sb1));
-  GG_HIP(sort_pairs_bytes(ni, &sb2));
   unsigned char* stemp = nullptr;
   GG_TRY(T.get(&stemp, std::max(sb1, sb2)));
   GG_HIP(launch_sort_keys(dk, dks, nd, stemp, sb1, g->stream));
@@ -2336,6 +2449,9 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
     GG_HIP(launch_fill_u32((uint32_t*)tcount, 1, 0u, g->stream));
   }
   int32_t *keep, *keep_ex, *scr, *od_new;
+  uint8_t* rowflag = nullptr;  // per row: 1 lost edges, 2 gained edges
+  GG_TRY(T.get(&rowflag, ((size_t)n + 3) / 4 * 4));
+  GG_HIP(launch_fill_u32((uint32_t*)rowflag, ((int64_t)n + 3) / 4, 0u, g->stream));
   GG_TRY(T.get(&keep, (size_t)m0));
   GG_TRY(T.get(&keep_ex, (size_t)m0 + 1));
   GG_TRY(T.get(&od_new, (size_t)n));
@@ -2343,7 +2459,7 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   GG_TRY(T.get(&scr, (size_t)(big / 1024 + 2)));
   GG_HIP(launch_fill_u32((uint32_t*)keep, m0, 1u, g->stream));
   GG_HIP(launch_copy_u32((const uint32_t*)g->outdeg, (uint32_t*)od_new, n, g->stream));
-  GG_HIP(launch_mark_deleted(g->rowptr, g->col, g->weight, dks, nd, keep, od_new, app,
+  GG_HIP(launch_mark_deleted(g->rowptr, g->col, g->weight, dks, nd, keep, od_new, rowflag, app,
                              taint_mode ? g->xu[r->cur] : nullptr, r ? r->p.source : 0, taint, tlist, tcount,
                              g->stream));
   // the out-CSR, when built, is carried over rather than rebuilt
@@ -2373,7 +2489,8 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   GG_TRY(T.get(&rowid, (size_t)m0));
   GG_TRY(T.get(&new_of_old, (size_t)m0));
   struct Owned {
-    int32_t *rowptr = nullptr, *col = nullptr, *weight = nullptr, *orow = nullptr, *oedge = nullptr, *odst = nullptr;
+    int32_t *rowptr = nullptr, *col = nullptr, *weight = nullptr, *orow = nullptr, *oedge = nullptr, *odst = nullptr,
+            *osrc = nullptr;
     uint32_t *wedges = nullptr, *bits0 = nullptr, *bits1 = nullptr, *act_edges = nullptr;
     ~Owned() {
       dfree(rowptr);
@@ -2382,31 +2499,36 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
       dfree(orow);
       dfree(oedge);
       dfree(odst);
+      dfree(osrc);
       dfree(wedges);
       dfree(bits0);
       dfree(bits1);
       dfree(act_edges);
     }
   } nw;
-  GG_TRY(dalloc(&nw.rowptr, (size_t)n + 1));
-  GG_TRY(dalloc(&nw.col, (size_t)m1));
+  GG_TRY(take_spare(g, kSpRowptr, &nw.rowptr, (size_t)n + 1));
+  GG_TRY(take_spare(g, kSpCol, &nw.col, (size_t)m1));
   if (weighted) {
-    GG_TRY(dalloc(&nw.weight, (size_t)m1));
-    GG_TRY(dalloc(&nw.wedges, (size_t)m1));
+    GG_TRY(take_spare(g, kSpWeight, &nw.weight, (size_t)m1));
+    GG_TRY(take_spare(g, kSpWedges, &nw.wedges, (size_t)m1));
   }
   const size_t nwords = (size_t)((m1 + 31) / 32);
   if (g->ws) {
-    GG_TRY(dalloc(&nw.bits0, nwords));
-    GG_TRY(dalloc(&nw.bits1, nwords));
-    GG_TRY(dalloc(&nw.act_edges, (size_t)m1));
+    GG_TRY(take_spare(g, kSpBits0, &nw.bits0, nwords));
+    GG_TRY(take_spare(g, kSpBits1, &nw.bits1, nwords));
+    GG_TRY(take_spare(g, kSpAct, &nw.act_edges, (size_t)m1));
   }
-  int32_t *kout = nullptr, *kout_ex = nullptr;
+  int32_t *kout = nullptr, *kout_ex = nullptr, *obase = nullptr, *omove = nullptr, *one = nullptr;
   if (out) {
-    GG_TRY(dalloc(&nw.orow, (size_t)n + 1));
-    GG_TRY(dalloc(&nw.oedge, (size_t)m1));
-    GG_TRY(dalloc(&nw.odst, (size_t)m1));
+    GG_TRY(take_spare(g, kSpOrow, &nw.orow, (size_t)n + 1));
+    GG_TRY(take_spare(g, kSpOedge, &nw.oedge, (size_t)m1));
+    GG_TRY(take_spare(g, kSpOdst, &nw.odst, (size_t)m1));
+    GG_TRY(take_spare(g, kSpOsrc, &nw.osrc, (size_t)m1));
     GG_TRY(T.get(&kout, (size_t)m0));
     GG_TRY(T.get(&kout_ex, (size_t)m0 + 1));
+    GG_TRY(T.get(&obase, (size_t)n));
+    GG_TRY(T.get(&omove, (size_t)n));
+    GG_TRY(T.get(&one, (size_t)m0));
   }
   int32_t* od_old = nullptr;
   if (r && is_pr(app)) {
@@ -2416,7 +2538,7 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
 
   // the new CSR
   GG_HIP(launch_ins_rows(iks, ni, n, ins_rp, g->stream));
-  GG_HIP(launch_new_len(g->rowptr, keep_ex, ins_rp, n, len, g->stream));
+  GG_HIP(launch_new_len(g->rowptr, keep_ex, ins_rp, n, len, rowflag, g->stream));
   if (n > 0) GG_HIP(launch_scan(len, nw.rowptr, n, nw.rowptr + n, scr, g->stream));
   else GG_HIP(launch_fill_u32((uint32_t*)nw.rowptr, 1, 0u, g->stream));
   GG_HIP(launch_row_ids(g->rowptr, n, rowid, g->stream));
@@ -2427,12 +2549,14 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   GG_HIP(launch_scatter_old(g->rowptr, rowid, g->col, g->weight, m0, keep, keep_ex, iks, ins_rp, nw.rowptr, nw.col,
                             nw.weight, oon, new_of_old, g->stream));
   GG_HIP(launch_scatter_ins(g->rowptr, g->col, keep_ex, iks, ixs, ni, ins_rp, iw, nw.rowptr, nw.col, nw.weight, oon,
-                            nw.orow, ins_cnt, icur, out ? nw.oedge : nullptr, nw.odst, g->stream));
-  if (out) {
-    GG_HIP(launch_out_keep(g->oedge, m0, new_of_old, kout, g->stream));
-    if (m0 > 0) GG_HIP(launch_scan(kout, kout_ex, (int32_t)m0, kout_ex + m0, scr, g->stream));
-    GG_HIP(launch_out_compact(g->oedge, g->odst, m0, g->col, g->orow, kout, kout_ex, new_of_old, nw.orow, nw.oedge,
-                              nw.odst, g->stream));
+                            nw.orow, ins_cnt, icur, out ? nw.oedge : nullptr, nw.odst, nw.osrc, g->stream));
+  if (out && m0 > 0) {
+    GG_HIP(launch_row_move(g->rowptr, nw.rowptr, rowflag, n, omove, g->stream));
+    GG_HIP(launch_out_keep(g->oedge, g->odst, m0, omove, new_of_old, one, kout, g->stream));
+    GG_HIP(launch_scan(kout, kout_ex, (int32_t)m0, kout_ex + m0, scr, g->stream));
+    GG_HIP(launch_out_base(g->orow, nw.orow, kout_ex, n, obase, g->stream));
+    GG_HIP(launch_out_compact(one, g->odst, g->osrc, m0, kout, kout_ex, obase, nw.oedge, nw.odst, nw.osrc,
+                              g->stream));
   }
   const bool flags_run = r && r->pol.kind != GG_POLICY_EXACT;
   if (flags_run) GG_HIP(launch_remap_bits(g->bits[r->bcur], oon, m1, nw.bits0, g->stream));
@@ -2442,11 +2566,16 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   // leaves the graph unusable (full_valid stays false)
   g->full_valid = false;
   g->gen++;
+  // the replaced arrays become the next update's spares (a borrowed CSR
+  // stays the caller's)
+  const size_t ob = sizeof(int32_t) * (size_t)m0, rb = sizeof(int32_t) * ((size_t)n + 1);
+  const size_t bb = sizeof(uint32_t) * (size_t)((m0 + 31) / 32);
   if (g->owns_csr) {
-    dfree(g->rowptr);
-    dfree(g->col);
-    dfree(g->weight);
+    retire(g, kSpRowptr, g->rowptr, rb);
+    retire(g, kSpCol, g->col, ob);
+    retire(g, kSpWeight, g->weight, ob);
   }
+  g->rowptr = g->col = g->weight = nullptr;
   g->owns_csr = true;
   g->rowptr = nw.rowptr;
   g->col = nw.col;
@@ -2454,14 +2583,15 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   nw.rowptr = nw.col = nw.weight = nullptr;
   g->m = m1;
   if (weighted) {
-    dfree(g->wedges);
+    retire(g, kSpWedges, g->wedges, ob);
     g->wedges = nw.wedges;
     nw.wedges = nullptr;
     GG_HIP(launch_pack_weights(g->col, g->weight, g->m, g->wedges, g->stream));
   }
   if (g->ws) {
-    for (int k = 0; k < 2; ++k) dfree(g->bits[k]);
-    dfree(g->act_edges);
+    retire(g, kSpBits0, g->bits[0], bb);
+    retire(g, kSpBits1, g->bits[1], bb);
+    retire(g, kSpAct, g->act_edges, ob);
     g->bits[0] = nw.bits0;
     g->bits[1] = nw.bits1;
     g->act_edges = nw.act_edges;
@@ -2471,13 +2601,15 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   GG_HIP(launch_dangling_list(g->outdeg, g->n, g->dang, g->i32_scratch, (int32_t*)g->blk_scratch, g->stream));
   GG_TRY(readback(g, &g->n_dang, g->i32_scratch, sizeof(int32_t)));
   if (out) {
-    dfree(g->orow);
-    dfree(g->oedge);
-    dfree(g->odst);
+    retire(g, kSpOrow, g->orow, rb);
+    retire(g, kSpOedge, g->oedge, ob);
+    retire(g, kSpOdst, g->odst, ob);
+    retire(g, kSpOsrc, g->osrc, ob);
     g->orow = nw.orow;
     g->oedge = nw.oedge;
     g->odst = nw.odst;
-    nw.orow = nw.oedge = nw.odst = nullptr;
+    g->osrc = nw.osrc;
+    nw.orow = nw.oedge = nw.odst = nw.osrc = nullptr;
   }
   GG_TRY(rebin_full(g));
   if (g->ws) GG_TRY(ensure_parts(g));
@@ -3110,6 +3242,8 @@ int gg_run_update(gg_run* run, const gg_update_batch* batch, int32_t more_iters,
     return update_graph(run->g, batch, run, more_iters, reset_host);
   });
 }
+
+int64_t gg_graph_num_arcs(const gg_graph* g) { return g ? g->m : -1; }
 
 int gg_graph_get_csr(gg_graph* g, int32_t* rowptr_host, int32_t* col_host, int32_t* weight_host) {
   return guard([&]() -> int {

@@ -83,8 +83,9 @@ __global__ __launch_bounds__(kUpdBlock) void k_row_ids(const int32_t* rowptr, in
 // out-degree. With x set, a deleted edge that supports d's value appends d
 // to the taint list (taint[d] guards against duplicates).
 __global__ void k_mark_deleted(const int32_t* rowptr, const int32_t* col, const int32_t* weight,
-                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, int app,
-                               const uint32_t* x, int32_t source, int32_t* taint, int32_t* list, int32_t* count) {
+                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, uint8_t* rowflag,
+                               int app, const uint32_t* x, int32_t source, int32_t* taint, int32_t* list,
+                               int32_t* count) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nd; j += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = dkeys[j];
     if (j > 0 && dkeys[j - 1] == key) continue;
@@ -103,7 +104,10 @@ __global__ void k_mark_deleted(const int32_t* rowptr, const int32_t* col, const 
       ++cnt;
       if (x && supports(app, x, source, s, d, weight ? (uint32_t)weight[e] : 0u)) seed = true;
     }
-    if (cnt) atomicSub(&od_new[s], cnt);
+    if (cnt) {
+      atomicSub(&od_new[s], cnt);
+      rowflag[d] = 1;  // every writer stores the same byte
+    }
     if (seed && atomicExch(&taint[d], 1) == 0) list[atomicAdd(count, 1)] = d;
   }
 }
@@ -124,9 +128,12 @@ __global__ void k_ins_rows(const uint64_t* ikeys, int64_t ni, int32_t n, int32_t
 }
 
 __global__ void k_new_len(const int32_t* rowptr, const int32_t* keep_ex, const int32_t* ins_rp, int32_t n,
-                          int32_t* len) {
-  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
-    len[u] = (keep_ex[rowptr[u + 1]] - keep_ex[rowptr[u]]) + (ins_rp[u + 1] - ins_rp[u]);
+                          int32_t* len, uint8_t* rowflag) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t ins = ins_rp[u + 1] - ins_rp[u];
+    len[u] = (keep_ex[rowptr[u + 1]] - keep_ex[rowptr[u]]) + ins;
+    if (ins > 0) rowflag[u] |= 2;
+  }
 }
 
 // A surviving old edge goes after the survivors before it in its row and
@@ -160,7 +167,7 @@ __global__ void k_scatter_ins(const int32_t* rowptr, const int32_t* col, const i
                               const int32_t* iidx, int64_t ni, const int32_t* ins_rp, const int32_t* ins_w,
                               const int32_t* new_rp, int32_t* ncol, int32_t* nweight, int32_t* old_of_new,
                               const int32_t* orow_new, const int32_t* ins_cnt, int32_t* icur, int32_t* noedge,
-                              int32_t* nodst) {
+                              int32_t* nodst, int32_t* nosrc) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ni; j += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = ikeys[j];
     const int u = (int)(key >> 32);
@@ -181,29 +188,57 @@ __global__ void k_scatter_ins(const int32_t* rowptr, const int32_t* col, const i
       const int32_t q = orow_new[s + 1] - ins_cnt[s] + atomicAdd(&icur[s], 1);
       noedge[q] = (int32_t)pos;
       nodst[q] = u;
+      nosrc[q] = s;
     }
   }
 }
 
-// Out-CSR after an update, surviving entries: kout[k] = 1 when out-entry k
-// (in-edge oedge[k]) survives.
-__global__ void k_out_keep(const int32_t* oedge, int64_t m, const int32_t* new_of_old, int32_t* kout) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
-    kout[k] = new_of_old[oedge[k]] >= 0 ? 1 : 0;
+// Per row: how its old edges move. A row that neither lost nor gained edges
+// moves as a whole (new row start minus old); the others are marked
+// kMoveByMap and look every edge up in new_of_old.
+constexpr int32_t kMoveByMap = INT32_MIN;
+
+__global__ void k_row_move(const int32_t* rp_old, const int32_t* rp_new, const uint8_t* rowflag, int32_t n,
+                           int32_t* move) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+    move[u] = rowflag[u] ? kMoveByMap : rp_new[u] - rp_old[u];
+}
+
+// Out-CSR after an update: the new in-edge id of out-entry k (in-edge
+// oedge[k] of row odst[k]), -1 when deleted, in ne[k], and kout[k] = 1 for
+// a survivor. The out-CSR is read in order; the one gather per entry is
+// the destination row's move (n entries).
+__global__ void k_out_keep(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* move,
+                           const int32_t* new_of_old, int32_t* ne, int32_t* kout) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e = oedge[k];
+    const int32_t mv = move[odst[k]];
+    const int32_t x = mv == kMoveByMap ? new_of_old[e] : e + mv;
+    ne[k] = x;
+    kout[k] = x >= 0 ? 1 : 0;
+  }
+}
+
+// Per source: the new position of its first survivor minus the survivors
+// before it.
+__global__ void k_out_base(const int32_t* orow_old, const int32_t* orow_new, const int32_t* kout_ex, int32_t n,
+                           int32_t* obase) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    obase[v] = orow_new[v] - kout_ex[orow_old[v]];
 }
 
 // A surviving out-entry keeps its rank among its source's survivors, now
-// pointing at the edge's new position.
-__global__ void k_out_compact(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* col_old,
-                              const int32_t* orow_old, const int32_t* kout, const int32_t* kout_ex,
-                              const int32_t* new_of_old, const int32_t* orow_new, int32_t* noedge, int32_t* nodst) {
+// pointing at the edge's new position (ne). Streams the out-CSR in order.
+__global__ void k_out_compact(const int32_t* ne, const int32_t* odst, const int32_t* osrc, int64_t m,
+                              const int32_t* kout, const int32_t* kout_ex, const int32_t* obase, int32_t* noedge,
+                              int32_t* nodst, int32_t* nosrc) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
     if (!kout[k]) continue;
-    const int32_t e = oedge[k];
-    const int32_t v = col_old[e];
-    const int64_t q = orow_new[v] + (kout_ex[k] - kout_ex[orow_old[v]]);
-    noedge[q] = new_of_old[e];
+    const int32_t v = osrc[k];
+    const int64_t q = (int64_t)kout_ex[k] + obase[v];
+    noedge[q] = ne[k];
     nodst[q] = odst[k];
+    nosrc[q] = v;
   }
 }
 
@@ -236,7 +271,8 @@ __global__ void k_rescale_contrib(float* c, const int32_t* od_old, const int32_t
 }
 
 // One wavefront per listed vertex p: every out-edge p -> v that supports v
-// taints v (appended once to the list).
+// taints v (appended once to the list). The test is that of supports(),
+// with the SSSP weight read only when x_v - x_p can be a weight.
 __global__ __launch_bounds__(kUpdBlock) void k_taint_push(const int32_t* list, int32_t lo, int32_t hi,
                                                           const int32_t* orow, const int32_t* oedge,
                                                           const int32_t* odst, const int32_t* weight, int app,
@@ -247,12 +283,20 @@ __global__ __launch_bounds__(kUpdBlock) void k_taint_push(const int32_t* list, i
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t i = lo + wave; i < hi; i += nwaves) {
     const int32_t p = list[i];
+    const uint32_t xs = x[p];
     for (int32_t k = orow[p] + lane; k < orow[p + 1]; k += 64) {
       const int32_t v = odst[k];
-      const uint32_t w = weight ? (uint32_t)weight[oedge[k]] : 0u;
-      if (taint[v] == 0 && supports(app, x, source, p, v, w)) {
-        if (atomicExch(&taint[v], 1) == 0) out_list[atomicAdd(count, 1)] = v;
+      const int32_t tv = taint[v];
+      const uint32_t xd = x[v];  // loaded with taint[v], before the test
+      if (tv != 0) continue;
+      bool sup;
+      if (app == kSSSP) {
+        sup = v != source && xs != kInf && xd != kInf && xd >= xs && xd - xs <= 255u &&
+              (uint32_t)weight[oedge[k]] == xd - xs;
+      } else {
+        sup = xs == xd && xd != (uint32_t)v;
       }
+      if (sup && atomicExch(&taint[v], 1) == 0) out_list[atomicAdd(count, 1)] = v;
     }
   }
 }
@@ -331,12 +375,12 @@ hipError_t launch_row_ids(const int32_t* rowptr, int32_t n, int32_t* dst, hipStr
 }
 
 hipError_t launch_mark_deleted(const int32_t* rowptr, const int32_t* col, const int32_t* weight,
-                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, int app,
-                               const uint32_t* x, int32_t source, int32_t* taint, int32_t* list, int32_t* count,
-                               hipStream_t st) {
+                               const uint64_t* dkeys, int64_t nd, int32_t* keep, int32_t* od_new, uint8_t* rowflag,
+                               int app, const uint32_t* x, int32_t source, int32_t* taint, int32_t* list,
+                               int32_t* count, hipStream_t st) {
   if (nd == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mark_deleted, dim3(grid_of(nd)), dim3(kUpdBlock), 0, st, rowptr, col, weight, dkeys, nd, keep,
-                     od_new, app, x, source, taint, list, count);
+                     od_new, rowflag, app, x, source, taint, list, count);
   return hipGetLastError();
 }
 
@@ -352,9 +396,9 @@ hipError_t launch_ins_rows(const uint64_t* ikeys, int64_t ni, int32_t n, int32_t
 }
 
 hipError_t launch_new_len(const int32_t* rowptr, const int32_t* keep_ex, const int32_t* ins_rp, int32_t n,
-                          int32_t* len, hipStream_t st) {
+                          int32_t* len, uint8_t* rowflag, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_new_len, dim3(grid_of(n)), dim3(kUpdBlock), 0, st, rowptr, keep_ex, ins_rp, n, len);
+  hipLaunchKernelGGL(k_new_len, dim3(grid_of(n)), dim3(kUpdBlock), 0, st, rowptr, keep_ex, ins_rp, n, len, rowflag);
   return hipGetLastError();
 }
 
@@ -372,26 +416,41 @@ hipError_t launch_scatter_ins(const int32_t* rowptr, const int32_t* col, const i
                               const uint64_t* ikeys, const int32_t* iidx, int64_t ni, const int32_t* ins_rp,
                               const int32_t* ins_w, const int32_t* new_rp, int32_t* ncol, int32_t* nweight,
                               int32_t* old_of_new, const int32_t* orow_new, const int32_t* ins_cnt, int32_t* icur,
-                              int32_t* noedge, int32_t* nodst, hipStream_t st) {
+                              int32_t* noedge, int32_t* nodst, int32_t* nosrc, hipStream_t st) {
   if (ni == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_ins, dim3(grid_of(ni)), dim3(kUpdBlock), 0, st, rowptr, col, keep_ex, ikeys, iidx, ni,
-                     ins_rp, ins_w, new_rp, ncol, nweight, old_of_new, orow_new, ins_cnt, icur, noedge, nodst);
+                     ins_rp, ins_w, new_rp, ncol, nweight, old_of_new, orow_new, ins_cnt, icur, noedge, nodst, nosrc);
   return hipGetLastError();
 }
 
-hipError_t launch_out_keep(const int32_t* oedge, int64_t m, const int32_t* new_of_old, int32_t* kout, hipStream_t st) {
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_out_keep, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, oedge, m, new_of_old, kout);
+hipError_t launch_row_move(const int32_t* rp_old, const int32_t* rp_new, const uint8_t* rowflag, int32_t n,
+                           int32_t* move, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_move, dim3(grid_of(n)), dim3(kUpdBlock), 0, st, rp_old, rp_new, rowflag, n, move);
   return hipGetLastError();
 }
 
-hipError_t launch_out_compact(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* col_old,
-                              const int32_t* orow_old, const int32_t* kout, const int32_t* kout_ex,
-                              const int32_t* new_of_old, const int32_t* orow_new, int32_t* noedge, int32_t* nodst,
-                              hipStream_t st) {
+hipError_t launch_out_keep(const int32_t* oedge, const int32_t* odst, int64_t m, const int32_t* move,
+                           const int32_t* new_of_old, int32_t* ne, int32_t* kout, hipStream_t st) {
   if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_out_compact, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, oedge, odst, m, col_old, orow_old, kout,
-                     kout_ex, new_of_old, orow_new, noedge, nodst);
+  hipLaunchKernelGGL(k_out_keep, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, oedge, odst, m, move, new_of_old, ne,
+                     kout);
+  return hipGetLastError();
+}
+
+hipError_t launch_out_base(const int32_t* orow_old, const int32_t* orow_new, const int32_t* kout_ex, int32_t n,
+                           int32_t* obase, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_out_base, dim3(grid_of(n)), dim3(kUpdBlock), 0, st, orow_old, orow_new, kout_ex, n, obase);
+  return hipGetLastError();
+}
+
+hipError_t launch_out_compact(const int32_t* ne, const int32_t* odst, const int32_t* osrc, int64_t m,
+                              const int32_t* kout, const int32_t* kout_ex, const int32_t* obase, int32_t* noedge,
+                              int32_t* nodst, int32_t* nosrc, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_out_compact, dim3(grid_of(m)), dim3(kUpdBlock), 0, st, ne, odst, osrc, m, kout, kout_ex, obase,
+                     noedge, nodst, nosrc);
   return hipGetLastError();
 }
 
