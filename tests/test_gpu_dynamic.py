@@ -214,3 +214,26 @@ def test_update_refusals_for_parts_and_policies(P):
     assert np.array_equal(rp0, rp1) and np.array_equal(col0, col1)
     net.close()
     G.close()
+
+
+def test_updates_that_grow_and_shrink_the_graph(P):
+    """Consecutive updates that add and remove many arcs: the arrays an update
+    replaces serve the next update only when large enough. The CSR after each
+    update and an exact SSSP run on the result match the oracle."""
+    g = gg.rmat(12, 8, seed=26, weights=True)
+    G = load(P, g)
+    s = int(gg.pick_sources(g, 1, 26)[0])
+    G.exact_run("sssp", source=s)  # builds the out-CSR, carried over by every update
+    cur = g
+    for k, (nd, ni) in enumerate([(100, 20000), (15000, 100), (50, 30000), (30000, 0)]):
+        b = random_batch(cur, 40 + k, nd, ni, True)
+        G.update(*b)
+        cur = oracle.apply_update(cur, *b).graph
+        rp, col, w = G.csr(weights=True)
+        assert np.array_equal(rp, cur.rowptr) and np.array_equal(col, cur.col) and np.array_equal(w, cur.weight)
+        assert G.m == cur.m
+        log("case: grow/shrink update", k, "m", cur.m)
+        out, _ = G.exact_run("sssp", source=s)
+        ref = oracle.run(cur, "sssp", "exact", source=s)
+        assert np.array_equal(device_values(out, "sssp"), ref.values)
+    G.close()
