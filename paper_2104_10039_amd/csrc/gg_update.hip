@@ -69,13 +69,31 @@ __global__ void k_arc_keys(const int32_t* src, const int32_t* dst, int64_t k, ui
   }
 }
 
-// Row of every edge (one wavefront per row).
+// Row of every edge. A block takes kUpdBlock consecutive rows, whose edges
+// are one contiguous range: it stages their starts in LDS, and each thread
+// writes the row ids of every kUpdBlock-th edge of the range (coalesced),
+// finding the row by binary search over the staged starts (the last row
+// starting at or before the edge; empty rows share their successor's start).
 __global__ __launch_bounds__(kUpdBlock) void k_row_ids(const int32_t* rowptr, int32_t n, int32_t* dst) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t u = wave; u < n; u += nwaves)
-    for (int32_t e = rowptr[u] + lane; e < rowptr[u + 1]; e += 64) dst[e] = (int32_t)u;
+  __shared__ int32_t s_rp[kUpdBlock + 1];
+  for (int64_t u0 = (int64_t)blockIdx.x * kUpdBlock; u0 < n; u0 += (int64_t)gridDim.x * kUpdBlock) {
+    const int cnt = (int)min((int64_t)kUpdBlock, (int64_t)n - u0);
+    __syncthreads();  // the previous round's searches are done with s_rp
+    if ((int)threadIdx.x < cnt) s_rp[threadIdx.x] = rowptr[u0 + threadIdx.x];
+    if (threadIdx.x == 0) s_rp[cnt] = rowptr[u0 + cnt];
+    __syncthreads();
+    const int32_t base = s_rp[0];
+    const int32_t total = s_rp[cnt] - base;
+    for (int32_t k = threadIdx.x; k < total; k += kUpdBlock) {
+      int lo = 0, hi = cnt - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rp[mid] - base <= k) lo = mid;
+        else hi = mid - 1;
+      }
+      dst[base + k] = (int32_t)(u0 + lo);
+    }
+  }
 }
 
 // One thread per distinct deletion key (s, d): the matching edges, a run of
@@ -370,7 +388,7 @@ hipError_t launch_sort_pairs(const uint64_t* kin, uint64_t* kout, const int32_t*
 
 hipError_t launch_row_ids(const int32_t* rowptr, int32_t n, int32_t* dst, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_ids, dim3(grid_of((int64_t)n * 64)), dim3(kUpdBlock), 0, st, rowptr, n, dst);
+  hipLaunchKernelGGL(k_row_ids, dim3(grid_of(n)), dim3(kUpdBlock), 0, st, rowptr, n, dst);
   return hipGetLastError();
 }
 
@@ -472,8 +490,9 @@ hipError_t launch_taint_push(const int32_t* list, int32_t lo, int32_t hi, const 
                              const int32_t* odst, const int32_t* weight, int app, const uint32_t* x, int32_t source,
                              int32_t* taint, int32_t* out_list, int32_t* count, hipStream_t st) {
   if (hi <= lo) return hipSuccess;
-  hipLaunchKernelGGL(k_taint_push, dim3(grid_of((int64_t)(hi - lo) * 64)), dim3(kUpdBlock), 0, st, list, lo, hi,
-                     orow, oedge, odst, weight, app, x, source, taint, out_list, count);
+  const dim3 grid(grid_of((int64_t)(hi - lo) * 64));
+  hipLaunchKernelGGL(k_taint_push, grid, dim3(kUpdBlock), 0, st, list, lo, hi, orow, oedge, odst, weight, app, x,
+                     source, taint, out_list, count);
   return hipGetLastError();
 }
 
