@@ -406,17 +406,26 @@ hipError_t launch_remap_bits(const uint32_t* old_bits, const int32_t* old_of_new
                              hipStream_t st);
 // PR contributions c = x / outdeg recomputed where the out-degree changed.
 hipError_t launch_rescale_contrib(float* c, const int32_t* od_old, const int32_t* od_new, int32_t n, hipStream_t st);
-// One round of the taint closure: out-edges of list[lo, hi) that support
-// their destination taint it (appended to out_list at count).
-hipError_t launch_taint_push(const int32_t* list, int32_t lo, int32_t hi, const int32_t* orow, const int32_t* oedge,
-                             const int32_t* odst, const int32_t* weight, int app, const uint32_t* x, int32_t source,
-                             int32_t* taint, int32_t* out_list, int32_t* count, hipStream_t st);
+// Taint closure over a work list of row chunks (wv[i], wc[i]): vertex and
+// chunk of kTaintChunk edges of its row. row_chunks appends the chunks of the
+// rows (in offsets: orow or rowptr) of list[0, count) at wcount. One round
+// of the closure: the out-edges of the work entries [lo, hi) that support
+// their destination taint it (appended to tlist at counts[0], its out-row
+// chunks to the work list at counts[1]). Work lists hold at most
+// n + m / kTaintChunk entries.
+constexpr int32_t kTaintChunk = 2048;
+hipError_t launch_row_chunks(const int32_t* list, int32_t count, const int32_t* offsets, int32_t* wv, int32_t* wc,
+                             int32_t* wcount, hipStream_t st);
+hipError_t launch_taint_push(int32_t* wv, int32_t* wc, int32_t lo, int32_t hi, const int32_t* orow,
+                             const int32_t* oedge, const int32_t* odst, const int32_t* weight, int app,
+                             const uint32_t* x, int32_t source, int32_t* taint, int32_t* tlist, int32_t* counts,
+                             hipStream_t st);
 // Initial values (SSSP: INF, 0 at the source; CC: own id) for the listed vertices, in both buffers.
 hipError_t launch_taint_reset(const int32_t* list, int32_t count, int app, int32_t source, uint32_t* x0,
                               uint32_t* x1, hipStream_t st);
-// chg[s] = 1 for every in-edge s -> v of the listed vertices.
-hipError_t launch_mark_in_neighbors(const int32_t* list, int32_t count, const int32_t* rowptr, const int32_t* col,
-                                    uint8_t* chg, hipStream_t st);
+// chg[s] = 1 for every in-edge s -> v of the work entries (v, chunk) [0, count).
+hipError_t launch_mark_in_neighbors(const int32_t* wv, const int32_t* wc, int32_t count, const int32_t* rowptr,
+                                    const int32_t* col, uint8_t* chg, hipStream_t st);
 // chg[s] = 1 for the source of every (sorted) inserted arc.
 hipError_t launch_mark_sources(const uint64_t* ikeys, int64_t ni, uint8_t* chg, hipStream_t st);
 

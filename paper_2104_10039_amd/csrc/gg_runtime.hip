@@ -2379,7 +2379,9 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
     if (taint0) {
       add(N);
       add(N);
-      add(1);
+      add(2);
+      add(N + (M + I) / kTaintChunk + 2);
+      add(N + (M + I) / kTaintChunk + 2);
     }
     add((N + 3) / 4);
     add(M);
@@ -2440,13 +2442,18 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   // survivors (and, for a converged exact SSSP/CC run, the taint seeds)
   const bool min_app = r && (app == GG_APP_SSSP || app == GG_APP_CC);
   const bool taint_mode = min_app && r->pol.kind == GG_POLICY_EXACT && r->converged && nd > 0;
-  int32_t *taint = nullptr, *tlist = nullptr, *tcount = nullptr;
+  // taint closure: tainted vertices (tlist, tcounts[0]) and a work list of
+  // row chunks (wv, wc, tcounts[1]) of at most n + m1 / kTaintChunk entries
+  int32_t *taint = nullptr, *tlist = nullptr, *tcounts = nullptr, *wv = nullptr, *wc = nullptr;
   if (taint_mode) {
     GG_TRY(T.get(&taint, (size_t)n));
     GG_TRY(T.get(&tlist, (size_t)n));
-    GG_TRY(T.get(&tcount, 1));
+    GG_TRY(T.get(&tcounts, 2));
+    const size_t wcap = (size_t)n + (size_t)(m0 + ni) / kTaintChunk + 2;
+    GG_TRY(T.get(&wv, wcap));
+    GG_TRY(T.get(&wc, wcap));
     GG_HIP(launch_fill_u32((uint32_t*)taint, n, 0u, g->stream));
-    GG_HIP(launch_fill_u32((uint32_t*)tcount, 1, 0u, g->stream));
+    GG_HIP(launch_fill_u32((uint32_t*)tcounts, 2, 0u, g->stream));
   }
   int32_t *keep, *keep_ex, *scr, *od_new;
   uint8_t* rowflag = nullptr;  // per row: 1 lost edges, 2 gained edges
@@ -2460,7 +2467,7 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
   GG_HIP(launch_fill_u32((uint32_t*)keep, m0, 1u, g->stream));
   GG_HIP(launch_copy_u32((const uint32_t*)g->outdeg, (uint32_t*)od_new, n, g->stream));
   GG_HIP(launch_mark_deleted(g->rowptr, g->col, g->weight, dks, nd, keep, od_new, rowflag, app,
-                             taint_mode ? g->xu[r->cur] : nullptr, r ? r->p.source : 0, taint, tlist, tcount,
+                             taint_mode ? g->xu[r->cur] : nullptr, r ? r->p.source : 0, taint, tlist, tcounts,
                              g->stream));
   // the out-CSR, when built, is carried over rather than rebuilt
   const bool out = g->out_built;
@@ -2629,20 +2636,30 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
     r->front_count = -1;
     r->front_outdeg = 0;
     if (deleted_any && taint_mode) {
-      // closure of the seeds along supporting out-edges of the new graph
+      // closure of the seeds along supporting out-edges of the new graph,
+      // level by level over chunks of the out-rows
       GG_TRY(ensure_out(g));
-      int32_t lo = 0, hi = 0;
-      GG_TRY(readback(g, &hi, tcount, sizeof(hi)));
-      while (lo < hi) {
-        GG_HIP(launch_taint_push(tlist, lo, hi, g->orow, g->oedge, g->odst, g->weight, app, g->xu[r->cur],
-                                 r->p.source, taint, tlist, tcount, g->stream));
+      int32_t c2[2] = {0, 0};
+      GG_TRY(readback(g, c2, tcounts, sizeof(c2)));
+      GG_HIP(launch_row_chunks(tlist, c2[0], g->orow, wv, wc, tcounts + 1, g->stream));
+      int32_t lo = 0;
+      GG_TRY(readback(g, c2, tcounts, sizeof(c2)));
+      while (lo < c2[1]) {
+        const int32_t hi = c2[1];
+        GG_HIP(launch_taint_push(wv, wc, lo, hi, g->orow, g->oedge, g->odst, g->weight, app, g->xu[r->cur],
+                                 r->p.source, taint, tlist, tcounts, g->stream));
         lo = hi;
-        GG_TRY(readback(g, &hi, tcount, sizeof(hi)));
+        GG_TRY(readback(g, c2, tcounts, sizeof(c2)));
       }
+      const int32_t hi = c2[0];  // tainted vertices
       GG_HIP(launch_taint_reset(tlist, hi, app, r->p.source, g->xu[0], g->xu[1], g->stream));
       if (frontier) {
         GG_HIP(launch_fill_u32((uint32_t*)g->chg, ((int64_t)n + 3) / 4, 0u, g->stream));
-        GG_HIP(launch_mark_in_neighbors(tlist, hi, g->rowptr, g->col, g->chg, g->stream));
+        // the in-rows of the reset vertices, again as chunks
+        GG_HIP(launch_fill_u32((uint32_t*)(tcounts + 1), 1, 0u, g->stream));
+        GG_HIP(launch_row_chunks(tlist, hi, g->rowptr, wv, wc, tcounts + 1, g->stream));
+        GG_TRY(readback(g, c2, tcounts, sizeof(c2)));
+        GG_HIP(launch_mark_in_neighbors(wv, wc, c2[1], g->rowptr, g->col, g->chg, g->stream));
         GG_HIP(launch_mark_sources(iks, ni, g->chg, g->stream));
         GG_TRY(seed_frontier(g, r));
       }

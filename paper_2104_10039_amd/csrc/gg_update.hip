@@ -288,21 +288,46 @@ __global__ void k_rescale_contrib(float* c, const int32_t* od_old, const int32_t
   }
 }
 
-// One wavefront per listed vertex p: every out-edge p -> v that supports v
-// taints v (appended once to the list). The test is that of supports(),
-// with the SSSP weight read only when x_v - x_p can be a weight.
-__global__ __launch_bounds__(kUpdBlock) void k_taint_push(const int32_t* list, int32_t lo, int32_t hi,
+// Work list of row chunks: for each vertex of list[lo, hi), one entry
+// (vertex, chunk) per kTaintChunk edges of its row in offsets (none for an
+// empty row), appended at wcount. A wavefront takes one entry, so a hub row
+// is spread over many wavefronts.
+__device__ __forceinline__ void append_chunks(int32_t v, const int32_t* offsets, int32_t* wv, int32_t* wc,
+                                              int32_t* wcount) {
+  const int32_t nch = (offsets[v + 1] - offsets[v] + kTaintChunk - 1) / kTaintChunk;
+  if (nch == 0) return;
+  const int32_t base = atomicAdd(wcount, nch);
+  for (int32_t c = 0; c < nch; ++c) {
+    wv[base + c] = v;
+    wc[base + c] = c;
+  }
+}
+
+__global__ void k_row_chunks(const int32_t* list, int32_t count, const int32_t* offsets, int32_t* wv, int32_t* wc,
+                             int32_t* wcount) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    append_chunks(list[i], offsets, wv, wc, wcount);
+}
+
+// One wavefront per work entry (p, chunk) of [lo, hi): every out-edge
+// p -> v of the chunk that supports v taints v, which is appended once to
+// tlist (tcount) and its out-row's chunks to the work list. The test is that
+// of supports(), with the SSSP weight read only when x_v - x_p can be a
+// weight.
+__global__ __launch_bounds__(kUpdBlock) void k_taint_push(int32_t* wv, int32_t* wc, int32_t lo, int32_t hi,
                                                           const int32_t* orow, const int32_t* oedge,
                                                           const int32_t* odst, const int32_t* weight, int app,
                                                           const uint32_t* x, int32_t source, int32_t* taint,
-                                                          int32_t* out_list, int32_t* count) {
+                                                          int32_t* tlist, int32_t* counts) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t i = lo + wave; i < hi; i += nwaves) {
-    const int32_t p = list[i];
+    const int32_t p = wv[i];
     const uint32_t xs = x[p];
-    for (int32_t k = orow[p] + lane; k < orow[p + 1]; k += 64) {
+    const int32_t k0 = orow[p] + wc[i] * kTaintChunk;
+    const int32_t k1 = min(orow[p + 1], k0 + kTaintChunk);
+    for (int32_t k = k0 + lane; k < k1; k += 64) {
       const int32_t v = odst[k];
       const int32_t tv = taint[v];
       const uint32_t xd = x[v];  // loaded with taint[v], before the test
@@ -314,7 +339,10 @@ __global__ __launch_bounds__(kUpdBlock) void k_taint_push(const int32_t* list, i
       } else {
         sup = xs == xd && xd != (uint32_t)v;
       }
-      if (sup && atomicExch(&taint[v], 1) == 0) out_list[atomicAdd(count, 1)] = v;
+      if (sup && atomicExch(&taint[v], 1) == 0) {
+        tlist[atomicAdd(&counts[0], 1)] = v;
+        append_chunks(v, orow, wv, wc, &counts[1]);
+      }
     }
   }
 }
@@ -329,17 +357,19 @@ __global__ void k_taint_reset(const int32_t* list, int32_t count, int app, int32
   }
 }
 
-// chg[src] = 1 for every in-edge src -> v of the listed vertices (one
-// wavefront per vertex).
-__global__ __launch_bounds__(kUpdBlock) void k_mark_in_neighbors(const int32_t* list, int32_t count,
+// chg[src] = 1 for every in-edge src -> v of the work entries (v, chunk)
+// (one wavefront per entry).
+__global__ __launch_bounds__(kUpdBlock) void k_mark_in_neighbors(const int32_t* wv, const int32_t* wc, int32_t count,
                                                                  const int32_t* rowptr, const int32_t* col,
                                                                  uint8_t* chg) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t i = wave; i < count; i += nwaves) {
-    const int32_t v = list[i];
-    for (int32_t e = rowptr[v] + lane; e < rowptr[v + 1]; e += 64) chg[col[e]] = 1;
+    const int32_t v = wv[i];
+    const int32_t e0 = rowptr[v] + wc[i] * kTaintChunk;
+    const int32_t e1 = min(rowptr[v + 1], e0 + kTaintChunk);
+    for (int32_t e = e0 + lane; e < e1; e += 64) chg[col[e]] = 1;
   }
 }
 
@@ -486,13 +516,21 @@ hipError_t launch_rescale_contrib(float* c, const int32_t* od_old, const int32_t
   return hipGetLastError();
 }
 
-hipError_t launch_taint_push(const int32_t* list, int32_t lo, int32_t hi, const int32_t* orow, const int32_t* oedge,
-                             const int32_t* odst, const int32_t* weight, int app, const uint32_t* x, int32_t source,
-                             int32_t* taint, int32_t* out_list, int32_t* count, hipStream_t st) {
+hipError_t launch_row_chunks(const int32_t* list, int32_t count, const int32_t* offsets, int32_t* wv, int32_t* wc,
+                             int32_t* wcount, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_chunks, dim3(grid_of(count)), dim3(kUpdBlock), 0, st, list, count, offsets, wv, wc, wcount);
+  return hipGetLastError();
+}
+
+hipError_t launch_taint_push(int32_t* wv, int32_t* wc, int32_t lo, int32_t hi, const int32_t* orow,
+                             const int32_t* oedge, const int32_t* odst, const int32_t* weight, int app,
+                             const uint32_t* x, int32_t source, int32_t* taint, int32_t* tlist, int32_t* counts,
+                             hipStream_t st) {
   if (hi <= lo) return hipSuccess;
   const dim3 grid(grid_of((int64_t)(hi - lo) * 64));
-  hipLaunchKernelGGL(k_taint_push, grid, dim3(kUpdBlock), 0, st, list, lo, hi, orow, oedge, odst, weight, app, x,
-                     source, taint, out_list, count);
+  hipLaunchKernelGGL(k_taint_push, grid, dim3(kUpdBlock), 0, st, wv, wc, lo, hi, orow, oedge, odst, weight, app, x,
+                     source, taint, tlist, counts);
   return hipGetLastError();
 }
 
@@ -503,10 +541,10 @@ hipError_t launch_taint_reset(const int32_t* list, int32_t count, int app, int32
   return hipGetLastError();
 }
 
-hipError_t launch_mark_in_neighbors(const int32_t* list, int32_t count, const int32_t* rowptr, const int32_t* col,
-                                    uint8_t* chg, hipStream_t st) {
-  if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark_in_neighbors, dim3(grid_of((int64_t)count * 64)), dim3(kUpdBlock), 0, st, list, count,
+hipError_t launch_mark_in_neighbors(const int32_t* wv, const int32_t* wc, int32_t count, const int32_t* rowptr,
+                                    const int32_t* col, uint8_t* chg, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_in_neighbors, dim3(grid_of((int64_t)count * 64)), dim3(kUpdBlock), 0, st, wv, wc, count,
                      rowptr, col, chg);
   return hipGetLastError();
 }
