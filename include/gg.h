@@ -490,7 +490,8 @@ int gg_graph_update(gg_graph* g, const gg_update_batch* batch);
  *    (>= 0) further iterations: fixed-count runs raise their count,
  *    fixed-point runs their cap, and the run is no longer done.
  * reset_host (nullable, n bytes) receives 1 for every vertex whose value was
- * reset. LEARNED, traced, vertex-status and ACTIVE-degree runs:
+ * reset and 0 for the others, written only on success. LEARNED, traced,
+ * vertex-status and ACTIVE-degree runs:
  * GG_E_UNSUPPORTED. */
 int gg_run_update(gg_run* run, const gg_update_batch* batch, int32_t more_iters, uint8_t* reset_host);
 

@@ -645,7 +645,7 @@ class Run:
         """gg_run_update: apply an update batch to the run's graph and continue
         for more_iters further iterations. Returns the reset vertices (uint8[n])."""
         b, keep = _batch(del_src, del_dst, ins_src, ins_dst, ins_weight)
-        reset = np.zeros(max(self.graph.n, 1), dtype=np.uint8)
+        reset = np.empty(max(self.graph.n, 1), dtype=np.uint8)  # every byte written on success
         _check(lib().gg_run_update(self._h, ctypes.byref(b), int(more_iters), reset.ctypes.data))
         self.graph.m = self.graph._csr_m()
         self.graph._keep = None

@@ -2629,8 +2629,10 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
     GG_TRY(pack_from_bits0(g, app));
   }
   if (is_pr(app)) GG_HIP(launch_rescale_contrib(g->c[r->cur], od_old, g->outdeg, n, g->stream));
-  std::vector<uint8_t> reset_v;
-  if (reset_host) reset_v.assign((size_t)n, 0);
+  // reset vertices for reset_host, written only once the update has
+  // succeeded: the tainted list, or every vertex after a restart
+  std::vector<int32_t> reset_list;
+  bool reset_all = false;
   if (min_app) {
     const bool frontier = g->tune.frontier_enable != 0;
     r->front_count = -1;
@@ -2664,16 +2666,16 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
         GG_TRY(seed_frontier(g, r));
       }
       if (reset_host && hi > 0) {
-        std::vector<int32_t> t((size_t)hi);
-        GG_HIP(hipMemcpyAsync(t.data(), tlist, sizeof(int32_t) * (size_t)hi, hipMemcpyDeviceToHost, g->stream));
+        reset_list.resize((size_t)hi);
+        GG_HIP(hipMemcpyAsync(reset_list.data(), tlist, sizeof(int32_t) * (size_t)hi, hipMemcpyDeviceToHost,
+                              g->stream));
         GG_HIP(hipStreamSynchronize(g->stream));
-        for (int32_t v : t) reset_v[(size_t)v] = 1;
       }
     } else if (deleted_any) {
       // any other run restarts from its initial values
       GG_HIP(launch_min_init(app, n, r->p.source, g->xu[0], g->stream));
       GG_HIP(launch_min_init(app, n, r->p.source, g->xu[1], g->stream));
-      if (reset_host) reset_v.assign((size_t)n, 1);
+      reset_all = true;
     } else if (r->pol.kind == GG_POLICY_EXACT && r->converged && frontier) {
       // insertions only: a push from their sources
       GG_TRY(ensure_out(g));
@@ -2694,7 +2696,10 @@ int update_graph(gg_graph* g, const gg_update_batch* b, gg_run* r, int32_t more,
     r->done = r->iter >= r->p.max_iters;
   }
   GG_HIP(hipStreamSynchronize(g->stream));
-  if (reset_host) std::memcpy(reset_host, reset_v.data(), (size_t)n);
+  if (reset_host) {
+    std::memset(reset_host, reset_all ? 1 : 0, (size_t)n);
+    for (int32_t v : reset_list) reset_host[(size_t)v] = 1;
+  }
   return GG_OK;
 }
 
